@@ -1,0 +1,877 @@
+/*
+ * Plain FP64 CPU oracle of the volumetric sonar echo model.
+ *
+ * TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
+ * baseline load this library; the product path never does. It shares no code,
+ * header, table or helper with the HIP library.
+ *
+ * What it follows in the paper:
+ *   Sec. III, Eq. (1)-(3)  sampling-grid counts N_range, N_H, N_V, and the
+ *                          LiDAR firing grid N_L = N_V + 1, N_R = N_H + 1.
+ *   Sec. II-A              the sensor is volumetric: the aperture is split in
+ *                          azimuth and elevation and the output is an
+ *                          azimuth x elevation x range distribution of
+ *                          backscatter; rays bend by Snell's law in a
+ *                          sound-speed field.
+ *   Sec. II-B              each intersection scatters according to incidence
+ *                          angle and material coefficients; a bounded number
+ *                          of secondary reflections with a tunable depth;
+ *                          complex returns whose phase follows the propagation
+ *                          delay, with attenuation; beams and cells formed by
+ *                          coherent summation within each ray bundle.
+ * Readings where the paper is silent (jitter law, spreading, absorption, the
+ * multipath path model, the tie rule, CFAR constants) are stated next to the
+ * code that applies them.
+ *
+ * Everything is brute force: every ray is tested against every triangle, so
+ * the result is the definition itself. Intersection uses the plane equation
+ * and signed distances to the three edges (not the Moller-Trumbore form).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_MAXK 8
+
+/* ------------------------------------------------------------------------ */
+/* small vector algebra                                                      */
+
+typedef struct { double x, y, z; } v3;
+
+static v3 mk(double x, double y, double z) { v3 r; r.x = x; r.y = y; r.z = z; return r; }
+static v3 add(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static v3 sub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 scl(v3 a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static v3 cross(v3 a, v3 b) { return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+static double len(v3 a) { return sqrt(dot(a, a)); }
+static v3 unit(v3 a) { return scl(a, 1.0 / len(a)); }
+
+/* ------------------------------------------------------------------------ */
+/* inputs                                                                    */
+
+typedef struct {
+    double hfov, vfov;           /* radians */
+    int32_t n_h, n_v, n_r;       /* beams in azimuth / elevation, rays per beam */
+    int32_t grid_mode;           /* 0 cell-centred beams, 1 LiDAR firing grid */
+    int32_t jitter;              /* 1: stratified jitter, 0: stratum centres */
+    int32_t n_bins;
+    double r_min, r_max;
+    double f0, c0, g;            /* centre frequency, c(z) = c0 + g z */
+    double alpha_db;             /* absorption in dB per metre of total path */
+    int32_t max_bounces;
+    int32_t pad0;
+    double k_d, k_s, phong_n;
+    uint64_t seed;
+    uint32_t ping;
+    uint32_t pad1;
+} orc_params;
+
+typedef struct { double pos[3]; double rot[9]; } orc_pose;   /* sensor->world, row-major */
+
+/* Thresholds of the ambiguity flags. A ray is flagged when any of its events
+ * is within these margins of a discrete decision; flagged rays are excluded
+ * from index comparisons and from the masked volume. */
+typedef struct {
+    double graze;      /* cos(incidence) or cos(departure) below this */
+    double edge_abs;   /* hit within edge_abs + edge_rel * s of a triangle edge */
+    double edge_rel;
+    double tie_rel;    /* a second candidate within s * (1 + tie_rel) + tie_abs */
+    double tie_abs;
+    double bin_frac;   /* range position within this fraction of a bin edge */
+    double fov;        /* arrival direction within this angle (rad) of the FOV edge */
+    double lim_rel;    /* a hit or a stop test within this relative margin of its bound */
+    double self_lo, self_hi;  /* hit distances in [self_lo, self_hi] are flagged */
+} orc_tol;
+
+enum {
+    F_GRAZE = 1u << 0, F_EDGE = 1u << 1, F_TIE = 1u << 2, F_LIMIT = 1u << 3,
+    F_SELF = 1u << 4, F_BIN = 1u << 5, F_FOV = 1u << 6, F_OCCLUDER = 1u << 7,
+    F_STOP = 1u << 8, F_DEPART = 1u << 9
+};
+
+typedef struct {
+    int64_t nt;
+    double *p;          /* [nt][9] FP32 vertices promoted exactly */
+    double *nrm;        /* [nt][3] (p1 - p0) x (p2 - p0) */
+    double *rho, *phi;
+    uint8_t *mat;
+    double zabs_max;    /* max |z| over all vertices */
+} oscene;
+
+static const double EPS_SELF = 1e-4;   /* minimum hit distance, metres */
+
+/* ------------------------------------------------------------------------ */
+/* scene                                                                     */
+
+void *orc_scene_new(const float *v, int64_t nv, const int32_t *idx, int64_t nt,
+                    const float *rho, const float *phi, const uint8_t *mat)
+{
+    (void)nv;
+    oscene *s = (oscene *)calloc(1, sizeof(oscene));
+    s->nt = nt;
+    s->p = (double *)malloc(sizeof(double) * 9 * (size_t)nt);
+    s->nrm = (double *)malloc(sizeof(double) * 3 * (size_t)nt);
+    s->rho = (double *)malloc(sizeof(double) * (size_t)nt);
+    s->phi = (double *)malloc(sizeof(double) * (size_t)nt);
+    s->mat = (uint8_t *)malloc((size_t)nt);
+    double zmax = 0.0;
+    for (int64_t i = 0; i < nt; ++i) {
+        for (int c = 0; c < 3; ++c)
+            for (int a = 0; a < 3; ++a) {
+                double w = (double)v[3 * (int64_t)idx[3 * i + c] + a];
+                s->p[9 * i + 3 * c + a] = w;
+                if (a == 2 && fabs(w) > zmax) zmax = fabs(w);
+            }
+        v3 p0 = mk(s->p[9 * i], s->p[9 * i + 1], s->p[9 * i + 2]);
+        v3 p1 = mk(s->p[9 * i + 3], s->p[9 * i + 4], s->p[9 * i + 5]);
+        v3 p2 = mk(s->p[9 * i + 6], s->p[9 * i + 7], s->p[9 * i + 8]);
+        v3 n = cross(sub(p1, p0), sub(p2, p0));
+        s->nrm[3 * i] = n.x; s->nrm[3 * i + 1] = n.y; s->nrm[3 * i + 2] = n.z;
+        s->rho[i] = rho[i];
+        s->phi[i] = phi[i];
+        s->mat[i] = mat[i];
+    }
+    s->zabs_max = zmax;
+    return s;
+}
+
+void orc_scene_free(void *h)
+{
+    oscene *s = (oscene *)h;
+    if (!s) return;
+    free(s->p); free(s->nrm); free(s->rho); free(s->phi); free(s->mat); free(s);
+}
+
+static v3 tri_vertex(const oscene *s, int64_t i, int c)
+{
+    const double *q = s->p + 9 * i + 3 * c;
+    return mk(q[0], q[1], q[2]);
+}
+
+static v3 tri_normal(const oscene *s, int64_t i)
+{
+    return mk(s->nrm[3 * i], s->nrm[3 * i + 1], s->nrm[3 * i + 2]);
+}
+
+/* Signed distance (metres) from a point of the triangle's plane to the nearest
+ * edge line: positive inside, negative outside. */
+static double edge_distance(const oscene *s, int64_t i, v3 P)
+{
+    v3 n = tri_normal(s, i);
+    double nl = len(n);
+    double best = 1e300;
+    for (int e = 0; e < 3; ++e) {
+        v3 a = tri_vertex(s, i, e), b = tri_vertex(s, i, (e + 1) % 3);
+        v3 ed = sub(b, a);
+        double el = len(ed);
+        double d = dot(cross(n, ed), sub(P, a)) / (nl * el);
+        if (d < best) best = d;
+    }
+    return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. III, Eq. (1)-(3): grid counts. floor() of a quotient that is an       */
+/* integer in exact arithmetic is taken with a 1e-9 guard against rounding.  */
+
+void orc_grid_counts(double hfov, double vfov, double dth_h, double dth_v, double r_min,
+                     double r_max, double dr, int32_t out[6])
+{
+    out[0] = (int32_t)floor((r_max - r_min) / dr + 1e-9);    /* N_range */
+    out[1] = (int32_t)floor(hfov / dth_h + 1e-9);            /* N_H */
+    out[2] = (int32_t)floor(vfov / dth_v + 1e-9);            /* N_V */
+    out[3] = out[2] + 1;                                     /* N_L: elevation rows */
+    out[4] = out[1] + 1;                                     /* N_R: rays per row */
+    out[5] = out[3] * out[4];                                /* N_E: emitters */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ray generation. Jitter uniforms are the (counter + 1)-th output of the     */
+/* SplitMix64 generator (Steele, Lea and Flood, OOPSLA 2014) seeded with      */
+/* `seed`; the counter packs (ping, beam, ray).                              */
+
+static uint64_t splitmix_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_splitmix64_nth(uint64_t seed, uint64_t n)
+{
+    return splitmix_mix(seed + n * 0x9E3779B97F4A7C15ULL);
+}
+
+void orc_jitter(uint64_t seed, uint32_t ping, uint32_t beam, uint32_t ray, double out[2])
+{
+    uint64_t ctr = ((uint64_t)ping << 40) ^ ((uint64_t)beam << 8) ^ (uint64_t)ray;
+    uint64_t z = orc_splitmix64_nth(seed, ctr + 1);
+    out[0] = (double)(z >> 40) * (1.0 / 16777216.0);
+    out[1] = (double)((z >> 16) & 0xFFFFFFu) * (1.0 / 16777216.0);
+}
+
+static void strata(int n_r, int *na, int *ne)
+{
+    int lg = 0;
+    while ((1 << (lg + 1)) <= n_r) ++lg;
+    *ne = 1 << (lg / 2);
+    *na = n_r / *ne;
+}
+
+static int beams_h(const orc_params *P) { return P->grid_mode == 1 ? P->n_h + 1 : P->n_h; }
+
+
+static v3 sensor_to_world(const orc_pose *Q, v3 a)
+{
+    const double *R = Q->rot;
+    return mk(R[0] * a.x + R[1] * a.y + R[2] * a.z,
+              R[3] * a.x + R[4] * a.y + R[5] * a.z,
+              R[6] * a.x + R[7] * a.y + R[8] * a.z);
+}
+
+static v3 world_to_sensor(const orc_pose *Q, v3 a)
+{
+    const double *R = Q->rot;
+    return mk(R[0] * a.x + R[3] * a.y + R[6] * a.z,
+              R[1] * a.x + R[4] * a.y + R[7] * a.z,
+              R[2] * a.x + R[5] * a.y + R[8] * a.z);
+}
+
+/* Azimuth/elevation of ray j of beam b. Sensor frame: x forward, y left, z up;
+ * azimuth from +x toward +y, elevation toward +z; the beam index is
+ * b = v * (beams per row) + h with h, v increasing with azimuth, elevation. */
+static void ray_angles(const orc_params *P, int b, int j, double *az, double *el)
+{
+    int nh = beams_h(P);
+    int h = b % nh, v = b / nh;
+    double dh = P->hfov / P->n_h, dv = P->vfov / P->n_v;
+    if (P->grid_mode == 1) {
+        *az = -0.5 * P->hfov + h * dh;
+        *el = -0.5 * P->vfov + v * dv;
+        return;
+    }
+    int na, ne;
+    strata(P->n_r, &na, &ne);
+    int ja = j % na, je = j / na;
+    double u[2] = {0.5, 0.5};
+    if (P->jitter) orc_jitter(P->seed, P->ping, (uint32_t)b, (uint32_t)j, u);
+    *az = -0.5 * P->hfov + (h + (ja + u[0]) / na) * dh;
+    *el = -0.5 * P->vfov + (v + (je + u[1]) / ne) * dv;
+}
+
+static v3 dir_from_angles(double az, double el)
+{
+    return mk(cos(el) * cos(az), cos(el) * sin(az), sin(el));
+}
+
+void orc_ray(const orc_params *P, const orc_pose *Q, int32_t b, int32_t j, double out[6])
+{
+    double az, el;
+    ray_angles(P, b, j, &az, &el);
+    v3 d = sensor_to_world(Q, dir_from_angles(az, el));
+    out[0] = Q->pos[0]; out[1] = Q->pos[1]; out[2] = Q->pos[2];
+    out[3] = d.x; out[4] = d.y; out[5] = d.z;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Propagation paths. In c(z) = c0 + g z the Snell invariant cos(theta)/c is  */
+/* constant, so a ray is a circle of curvature kappa = g cos(theta) / c(z)    */
+/* whose centre lies on the plane c = 0 (Sec. II-A asks for ray bending by    */
+/* Snell's law; the circle is its exact solution for a linear profile).      */
+/* x(s) = o + d sin(ks)/k + nc (1 - cos(ks))/k, nc the in-plane unit normal.  */
+
+typedef struct {
+    int arc;            /* 0: straight line */
+    v3 o, d, nc;
+    double kappa;
+} opath;
+
+static opath make_path(const orc_params *P, v3 o, v3 d)
+{
+    opath r;
+    r.o = o; r.d = d; r.arc = 0; r.kappa = 0.0; r.nc = mk(0, 0, 0);
+    double dh = hypot(d.x, d.y);
+    if (P->g == 0.0 || dh == 0.0) return r;
+    double c = P->c0 + P->g * o.z;
+    r.arc = 1;
+    r.kappa = P->g * dh / c;
+    r.nc = mk(d.z * d.x / dh, d.z * d.y / dh, -dh);
+    return r;
+}
+
+static v3 path_point(const opath *p, double s)
+{
+    if (!p->arc) return add(p->o, scl(p->d, s));
+    double u = p->kappa * s;
+    double sh = sin(0.5 * u);
+    return add(p->o, add(scl(p->d, sin(u) / p->kappa), scl(p->nc, 2.0 * sh * sh / p->kappa)));
+}
+
+static v3 path_tangent(const opath *p, double s)
+{
+    if (!p->arc) return p->d;
+    double u = p->kappa * s;
+    return add(scl(p->d, cos(u)), scl(p->nc, sin(u)));
+}
+
+/* One-way travel time along the path from s = 0 to s. For the arc, the
+ * integral of ds / c along a circle of a linear profile is
+ * (atanh(sin th0) - atanh(sin th1)) / g (Jensen et al., Computational Ocean
+ * Acoustics, ch. 3), written with log1p so that no large terms cancel. */
+static double path_time(const orc_params *P, const opath *p, double s)
+{
+    if (!p->arc) {
+        if (P->g == 0.0) return s / P->c0;
+        /* vertical ray: dt = dz / c(z) */
+        double z0 = p->o.z, dz = p->d.z * s;
+        return fabs(log1p(P->g * dz / (P->c0 + P->g * z0)) / P->g);
+    }
+    double u = p->kappa * s;
+    double sh = sin(0.5 * u);
+    double omc = 2.0 * sh * sh;                       /* 1 - cos u */
+    double dh = hypot(p->d.x, p->d.y);
+    double s0 = p->d.z;
+    double ds = p->d.z * omc + dh * sin(u);           /* sin th0 - sin th1 */
+    double s1 = s0 - ds;
+    double dz = (p->d.z * sin(u) + p->nc.z * omc) / p->kappa;
+    double lc = log1p(P->g * dz / (P->c0 + P->g * p->o.z));   /* ln(c1 / c0) */
+    double t;
+    if (s0 >= 0.0) t = log1p(ds / (1.0 + s1)) + lc;
+    else t = log1p(ds / (1.0 - s0)) - lc;
+    return t / P->g;
+}
+
+/* Roots s in (0, hi] of the path meeting the plane of triangle i. */
+static int plane_roots(const oscene *S, int64_t i, const opath *p, double hi, double r[2])
+{
+    v3 n = tri_normal(S, i);
+    v3 p0 = tri_vertex(S, i, 0);
+    double a = dot(n, sub(p->o, p0));
+    double b = dot(n, p->d);
+    if (!p->arc) {
+        if (b == 0.0) return 0;
+        double s = -a / b;
+        if (s > 0.0 && s <= hi) { r[0] = s; return 1; }
+        return 0;
+    }
+    /* a + (b sin u + c (1 - cos u)) / k = 0 with u = k s. The half-angle
+     * substitution w = tan(u / 2) (sin u = 2w / (1 + w^2), 1 - cos u =
+     * 2w^2 / (1 + w^2)) turns it exactly into the quadratic
+     * (2c + a k) w^2 + 2b w + a k = 0, solved in the cancellation-free form;
+     * then u = 2 atan(w). As k -> 0 the small root tends to s = -a / b. */
+    double c = dot(n, p->nc);
+    double k = p->kappa;
+    double qa = 2.0 * c + a * k, qb = 2.0 * b, qc = a * k;
+    double disc = qb * qb - 4.0 * qa * qc;
+    if (disc < 0.0) return 0;
+    double sq = sqrt(disc);
+    double q = -0.5 * (qb + (qb >= 0.0 ? sq : -sq));
+    double wr[2];
+    int nw = 0;
+    if (qa != 0.0) wr[nw++] = q / qa;
+    if (q != 0.0) wr[nw++] = qc / q;
+    int m = 0;
+    for (int t = 0; t < nw; ++t) {
+        double s = 2.0 * atan(wr[t]) / k;
+        if (s > 0.0 && s <= hi) r[m++] = s;
+    }
+    if (m == 2 && r[1] < r[0]) { double w = r[0]; r[0] = r[1]; r[1] = w; }
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nearest hit by brute force. Valid: triangle != prev, eps < s <= s_lim and  */
+/* the point lies inside the closed triangle. Tie rule: smallest s, then the */
+/* lowest triangle index. Flags mark candidates that a finite-precision      */
+/* search could resolve differently.                                         */
+
+typedef struct {
+    int64_t tri;
+    double s;
+    uint32_t flags;
+} ohit;
+
+static ohit nearest_hit(const oscene *S, const opath *p, int64_t prev, double s_lim, const orc_tol *T)
+{
+    ohit h;
+    h.tri = -1; h.s = 0.0; h.flags = 0;
+    double hi = s_lim * (1.0 + T->lim_rel) + 1e-9;
+    double best = 1e300;
+    double near1 = 1e300, near2 = 1e300;   /* the two nearest near-candidates */
+    int64_t near1_i = -1;
+    for (int64_t i = 0; i < S->nt; ++i) {
+        if (i == prev) continue;
+        double r[2];
+        int m = plane_roots(S, i, p, hi, r);
+        for (int t = 0; t < m; ++t) {
+            double s = r[t];
+            v3 X = path_point(p, s);
+            double de = edge_distance(S, i, X);
+            if (s > EPS_SELF && s <= s_lim && de >= 0.0 && s < best) {
+                best = s;
+                h.tri = i;
+            }
+            double dl = T->edge_abs + T->edge_rel * s;
+            if (de > -dl && s >= T->self_lo) {
+                if (s < near1) { near2 = near1; near1 = s; near1_i = i; }
+                else if (s < near2) near2 = s;
+            }
+        }
+    }
+    if (h.tri >= 0) {
+        h.s = best;
+        v3 X = path_point(p, best);
+        double de = edge_distance(S, h.tri, X);
+        if (de < T->edge_abs + T->edge_rel * best) h.flags |= F_EDGE;
+        double other = (near1_i == h.tri) ? near2 : near1;
+        if (other <= best * (1.0 + T->tie_rel) + T->tie_abs) h.flags |= F_TIE;
+        if (best >= s_lim * (1.0 - T->lim_rel)) h.flags |= F_LIMIT;
+        if (best <= T->self_hi) h.flags |= F_SELF;
+    } else {
+        if (near1 <= hi) h.flags |= F_TIE;
+    }
+    return h;
+}
+
+/* Any hit on (eps, L - eps) other than `skip`; flags occluders near an edge or
+ * near either end of the segment. Returns 1 when the path is blocked. */
+static int blocked(const oscene *S, const opath *p, int64_t skip, double L, const orc_tol *T, uint32_t *flags)
+{
+    int hit = 0;
+    double hi = L;
+    for (int64_t i = 0; i < S->nt; ++i) {
+        if (i == skip) continue;
+        double r[2];
+        int m = plane_roots(S, i, p, hi, r);
+        for (int t = 0; t < m; ++t) {
+            double s = r[t];
+            v3 X = path_point(p, s);
+            double de = edge_distance(S, i, X);
+            double dl = T->edge_abs + T->edge_rel * s;
+            int inside_range = (s > EPS_SELF && s < L - EPS_SELF);
+            if (inside_range && de >= 0.0) hit = 1;
+            if (de > -dl) {
+                if (inside_range && de < dl) *flags |= F_OCCLUDER;
+                if (s >= T->self_lo && s <= T->self_hi) *flags |= F_OCCLUDER;
+                if (s >= L - T->self_hi && s <= L - T->self_lo) *flags |= F_OCCLUDER;
+            }
+        }
+    }
+    return hit;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Connection from a scattering point P back to the sensor at Sp. Straight    */
+/* segment when g = 0; otherwise the eigenray: the circle through both points */
+/* with its centre on the plane c = 0, in their vertical plane.              */
+
+typedef struct {
+    double L, T;        /* arc length and one-way time P -> S */
+    v3 w_out;           /* unit departure direction at P */
+    v3 arrive;          /* unit direction of travel at S */
+    opath path;         /* the path from P */
+} oconn;
+
+static oconn connection(const orc_params *P, v3 Pp, v3 Sp)
+{
+    oconn c;
+    v3 dv = sub(Sp, Pp);
+    double D = hypot(dv.x, dv.y);
+    if (P->g == 0.0 || D == 0.0) {
+        c.L = len(dv);
+        c.w_out = scl(dv, 1.0 / c.L);
+        c.arrive = c.w_out;
+        if (P->g == 0.0) c.T = c.L / P->c0;
+        else c.T = fabs(log1p(P->g * dv.z / (P->c0 + P->g * Pp.z)) / P->g);
+        c.path = make_path(P, Pp, c.w_out);
+        return c;
+    }
+    /* Work in a frame where g > 0: z' = sg z. The centre plane is z' = -c0/|g|. */
+    double sg = P->g > 0 ? 1.0 : -1.0;
+    double ag = fabs(P->g);
+    double zs = -P->c0 / ag;
+    double h1 = sg * Pp.z - zs, h2 = sg * Sp.z - zs;
+    double xc = (D * D + (h2 - h1) * (h2 + h1)) / (2.0 * D);
+    double R = hypot(xc, h1);
+    v3 uh = mk(dv.x / D, dv.y / D, 0.0);
+    double sin0 = xc / R, cos0 = h1 / R;
+    double sin1 = (xc - D) / R, cos1 = h2 / R;
+    c.w_out = mk(cos0 * uh.x, cos0 * uh.y, sg * sin0);
+    c.arrive = mk(cos1 * uh.x, cos1 * uh.y, sg * sin1);
+    /* angle subtended at the centre between the radii to P and to S */
+    double cr = xc * (h1 - h2) - h1 * D;     /* (-xc, h1) x (D - xc, h2) */
+    double dt = -xc * (D - xc) + h1 * h2;
+    double ang = atan2(fabs(cr), dt);
+    c.L = R * ang;
+    /* time: (atanh sin0 - atanh sin1) / |g| with sin0 - sin1 = D / R */
+    double lc = log1p(ag * (h2 - h1) / (ag * h1));   /* ln(c_S / c_P) */
+    double t;
+    if (sin0 >= 0.0) t = log1p((D / R) / (1.0 + sin1)) + lc;
+    else t = log1p((D / R) / (1.0 - sin0)) - lc;
+    c.T = t / ag;
+    c.path = make_path(P, Pp, c.w_out);
+    return c;
+}
+
+/* Exposed for closed-form checks: eigenray P -> S. out = {L, T, w_out xyz, arrive xyz}. */
+void orc_connection(const orc_params *P, const double p[3], const double s[3], double out[8])
+{
+    oconn c = connection(P, mk(p[0], p[1], p[2]), mk(s[0], s[1], s[2]));
+    out[0] = c.L; out[1] = c.T;
+    out[2] = c.w_out.x; out[3] = c.w_out.y; out[4] = c.w_out.z;
+    out[5] = c.arrive.x; out[6] = c.arrive.y; out[7] = c.arrive.z;
+}
+
+/* Exposed: point, tangent and time after arc length s from (o, d). out = {x3, t3, time}. */
+void orc_path_eval(const orc_params *P, const double o[3], const double d[3], double s, double out[7])
+{
+    opath p = make_path(P, mk(o[0], o[1], o[2]), mk(d[0], d[1], d[2]));
+    v3 x = path_point(&p, s), t = path_tangent(&p, s);
+    out[0] = x.x; out[1] = x.y; out[2] = x.z;
+    out[3] = t.x; out[4] = t.y; out[5] = t.z;
+    out[6] = path_time(P, &p, s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The per-ray model.                                                        */
+
+typedef struct {
+    int32_t tri[ORC_MAXK], bin[ORC_MAXK], vis[ORC_MAXK];
+    double re[ORC_MAXK], im[ORC_MAXK], inc[ORC_MAXK];
+    uint32_t flags;
+    int g_valid;
+    double g_r, g_cos, g_rho;
+    v3 g_n;
+} oray;
+
+static double upper_speed(const orc_params *P, const oscene *S, const orc_pose *Q)
+{
+    /* an upper bound of c(z) over the scene and the sensor, with 1 m margin */
+    double z = S->zabs_max;
+    if (fabs(Q->pos[2]) > z) z = fabs(Q->pos[2]);
+    return P->c0 + fabs(P->g) * (z + 1.0);
+}
+
+static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, const orc_tol *T,
+                      v3 o, v3 d, oray *out)
+{
+    memset(out, 0, sizeof(*out));
+    for (int k = 0; k < ORC_MAXK; ++k) { out->tri[k] = -1; out->bin[k] = -1; }
+    const int K = P->max_bounces;
+    const v3 Sp = mk(Q->pos[0], Q->pos[1], Q->pos[2]);
+    const double c_ref = P->c0 + P->g * Sp.z;              /* time-to-range speed */
+    const double c_hi = upper_speed(P, S, Q);
+    const double dr = (P->r_max - P->r_min) / P->n_bins;
+    double L_out = 0.0, T_out = 0.0, W = 1.0;
+    int64_t prev = -1;
+    for (int k = 0; k < K; ++k) {
+        opath path = make_path(P, o, d);
+        double s_lim, T_lim = 0.0;
+        if (P->g == 0.0) {
+            s_lim = (K == 1) ? P->r_max : 2.0 * P->r_max - L_out;
+        } else {
+            T_lim = (K == 1) ? P->r_max / c_ref : 2.0 * P->r_max / c_ref - T_out;
+            s_lim = c_hi * T_lim;
+        }
+        if (s_lim <= EPS_SELF) break;
+        ohit h = nearest_hit(S, &path, prev, s_lim, T);
+        out->flags |= h.flags;
+        if (h.tri < 0) break;
+        double tau = path_time(P, &path, h.s);
+        if (P->g != 0.0) {
+            if (fabs(tau - T_lim) <= T->lim_rel * T_lim) out->flags |= F_LIMIT;
+            if (tau > T_lim) break;
+        }
+        v3 X = path_point(&path, h.s);
+        v3 din = path_tangent(&path, h.s);
+        L_out += h.s;
+        T_out += tau;
+        int64_t f = h.tri;
+        out->tri[k] = (int32_t)f;
+
+        /* two-sided facet: n' faces the incoming ray */
+        v3 nh = unit(tri_normal(S, f));
+        double dn = dot(nh, din);
+        v3 np = dn > 0.0 ? scl(nh, -1.0) : nh;
+        double cos_i = -dot(np, din);
+        if (cos_i < T->graze) out->flags |= F_GRAZE;
+        v3 rh = sub(din, scl(np, 2.0 * dot(np, din)));      /* mirror direction */
+
+        /* material: pressure-release facets have rho = 1, no diffuse part, a
+         * unit specular part, phase 0 and reflection sign -1 */
+        int pr = S->mat[f] == 1;
+        double rho = pr ? 1.0 : S->rho[f];
+        double kd = pr ? 0.0 : P->k_d;
+        double ks = pr ? 1.0 : P->k_s;
+        double phi = pr ? 0.0 : S->phi[f];
+        double sgn = pr ? -1.0 : 1.0;
+
+        /* return path */
+        double L_back, T_back;
+        v3 w;
+        int vis = 1;
+        if (k == 0) {
+            L_back = L_out; T_back = T_out; w = scl(din, -1.0);
+        } else {
+            oconn c = connection(P, X, Sp);
+            L_back = c.L; T_back = c.T; w = c.w_out;
+            uint32_t fl = 0;
+            if (blocked(S, &c.path, f, c.L, T, &fl)) vis = 0;
+            out->flags |= fl;
+            /* arrival direction must lie in the field of view */
+            v3 a = world_to_sensor(Q, scl(c.arrive, -1.0));
+            double az = atan2(a.y, a.x), el = atan2(a.z, hypot(a.x, a.y));
+            double mh = 0.5 * P->hfov - fabs(az), mv = 0.5 * P->vfov - fabs(el);
+            if (fabs(mh) <= T->fov || fabs(mv) <= T->fov) out->flags |= F_FOV;
+            if (mh < 0.0 || mv < 0.0) vis = 0;
+        }
+        out->vis[k] = vis;
+        if (vis) {
+            double cos_o = dot(np, w);
+            if (k > 0 && fabs(cos_o) < T->graze) out->flags |= F_DEPART;
+            if (cos_o > 0.0) {
+                double Tt = T_out + T_back;
+                double reff = c_ref * Tt / 2.0;
+                double x = (reff - P->r_min) / dr;
+                double fb = floor(x);
+                double fr = x - fb;
+                if (x > -1.0 && x < P->n_bins + 1.0 && (fr < T->bin_frac || fr > 1.0 - T->bin_frac))
+                    out->flags |= F_BIN;
+                if (fb >= 0.0 && fb < P->n_bins) {
+                    int bin = (int)fb;
+                    double lobe = dot(rh, w);
+                    if (lobe < 0.0) lobe = 0.0;
+                    double fsc = rho * (kd * cos_i * cos_o + ks * pow(lobe, P->phong_n));
+                    double amp = W * sgn * sqrt(fsc) * pow(10.0, -P->alpha_db * (L_out + L_back) / 20.0) /
+                                 (L_out * L_back * P->n_r);
+                    double cyc = P->f0 * Tt;
+                    double ph = 2.0 * ORC_PI * (cyc - floor(cyc)) + phi;
+                    out->bin[k] = bin;
+                    out->re[k] = amp * cos(ph);
+                    out->im[k] = amp * sin(ph);
+                    out->inc[k] = amp * amp;
+                    if (k == 0) {
+                        out->g_valid = 1;
+                        out->g_r = reff;
+                        out->g_cos = cos_i;
+                        out->g_rho = rho;
+                        out->g_n = np;
+                    }
+                }
+            }
+        }
+        /* continuation along the mirror direction */
+        if (k + 1 >= K) break;
+        W *= sqrt(rho * ks) * sgn;
+        if (W == 0.0) break;
+        double dS = len(sub(X, Sp));
+        double lb, bound;
+        if (P->g == 0.0) { lb = (L_out + dS) / 2.0; bound = P->r_max; }
+        else { lb = c_ref * (T_out + dS / c_hi) / 2.0; bound = P->r_max; }
+        if (fabs(lb - bound) <= T->lim_rel * bound) out->flags |= F_STOP;
+        if (lb >= bound) break;
+        o = X; d = rh; prev = f;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Beams: all rays of each listed beam, their records, and the beam's range   */
+/* column. Every ray of a bundle is weighted 1/N_r and contributes to its    */
+/* launch beam (coherent summation within each ray bundle).                 */
+
+int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_tol *T,
+                    const int32_t *beams, int64_t n_beams,
+                    double *col,        /* [n_beams][n_bins][2], flagged rays excluded */
+                    double *col_all,    /* [n_beams][n_bins][2], every ray, or NULL */
+                    double *incoh,      /* [n_beams][2][n_bins] (bounce 1, bounces >= 2), or NULL */
+                    double *gbuf,       /* [n_beams][8], or NULL */
+                    int32_t *rec_tri, int32_t *rec_bin, int32_t *rec_vis,  /* [n_beams*n_r][K] */
+                    double *rec_amp,    /* [n_beams*n_r][K][2] */
+                    uint32_t *ray_flags,/* [n_beams*n_r] */
+                    int n_threads)
+{
+    const oscene *S = (const oscene *)hs;
+    if (P->max_bounces < 1 || P->max_bounces > ORC_MAXK) return -1;
+    const int K = P->max_bounces, NB = P->n_bins, NR = P->n_r;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t q = 0; q < n_beams; ++q) {
+        int b = beams[q];
+        double *cc = col + (size_t)q * NB * 2;
+        double *ca = col_all ? col_all + (size_t)q * NB * 2 : NULL;
+        double *ic = incoh ? incoh + (size_t)q * 2 * NB : NULL;
+        memset(cc, 0, sizeof(double) * NB * 2);
+        if (ca) memset(ca, 0, sizeof(double) * NB * 2);
+        if (ic) memset(ic, 0, sizeof(double) * NB * 2);
+        double gs[8] = {0};
+        int gcount = 0;
+        for (int j = 0; j < NR; ++j) {
+            double od[6];
+            orc_ray(P, Q, b, j, od);
+            oray r;
+            trace_ray(S, P, Q, T, mk(od[0], od[1], od[2]), mk(od[3], od[4], od[5]), &r);
+            size_t ri = (size_t)q * NR + j;
+            ray_flags[ri] = r.flags;
+            for (int k = 0; k < K; ++k) {
+                rec_tri[ri * K + k] = r.tri[k];
+                rec_bin[ri * K + k] = r.bin[k];
+                rec_vis[ri * K + k] = r.vis[k];
+                rec_amp[(ri * K + k) * 2] = r.re[k];
+                rec_amp[(ri * K + k) * 2 + 1] = r.im[k];
+                if (r.bin[k] < 0) continue;
+                if (ca) { ca[2 * r.bin[k]] += r.re[k]; ca[2 * r.bin[k] + 1] += r.im[k]; }
+                if (r.flags == 0) {
+                    cc[2 * r.bin[k]] += r.re[k];
+                    cc[2 * r.bin[k] + 1] += r.im[k];
+                    if (ic) ic[(k == 0 ? 0 : NB) + r.bin[k]] += r.inc[k];
+                }
+            }
+            if (r.flags == 0 && r.g_valid) {
+                gs[0] += r.g_r / P->r_max;
+                gs[1] += r.g_cos;
+                gs[2] += r.g_rho;
+                gs[3] += r.g_n.x; gs[4] += r.g_n.y; gs[5] += r.g_n.z;
+                ++gcount;
+            }
+        }
+        if (gbuf) {
+            double *g = gbuf + (size_t)q * 8;
+            for (int t = 0; t < 8; ++t) g[t] = 0.0;
+            if (gcount > 0) for (int t = 0; t < 6; ++t) g[t] = gs[t] / gcount;
+            g[6] = (double)gcount / NR;
+        }
+    }
+    return 0;
+}
+
+/* A single ray from an arbitrary origin and direction (closed-form checks). */
+int orc_trace_one(void *hs, const orc_params *P, const orc_pose *Q, const orc_tol *T,
+                  const double o[3], const double d[3],
+                  int32_t *tri, int32_t *bin, int32_t *vis, double *amp, uint32_t *flags)
+{
+    const oscene *S = (const oscene *)hs;
+    if (P->max_bounces < 1 || P->max_bounces > ORC_MAXK) return -1;
+    oray r;
+    trace_ray(S, P, Q, T, mk(o[0], o[1], o[2]), unit(mk(d[0], d[1], d[2])), &r);
+    for (int k = 0; k < P->max_bounces; ++k) {
+        tri[k] = r.tri[k]; bin[k] = r.bin[k]; vis[k] = r.vis[k];
+        amp[2 * k] = r.re[k]; amp[2 * k + 1] = r.im[k];
+    }
+    *flags = r.flags;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Detection: cell-averaging CFAR (Finn and Johnson 1968) on |E|^2 + N0 per    */
+/* beam, a local-peak test, at most `max_per_beam` strongest cells per beam, */
+/* and points at the beam centre along a straight line at the bin-centre     */
+/* range. Flags mark decisions within a relative margin of their threshold.  */
+
+typedef struct {
+    int32_t train, guard, max_per_beam, pad;
+    double pfa, noise_floor;
+} orc_cfar;
+
+int orc_detect(const float *vol, const orc_params *P, const orc_pose *Q, const orc_cfar *C,
+               const int32_t *beams, int64_t n_beams,
+               int32_t *out_bin,      /* [n_beams][max_per_beam], -1 padded, in range order */
+               double *out_pts,       /* [n_beams][max_per_beam][4]: x, y, z, dB */
+               int32_t *out_count,    /* [n_beams] */
+               uint8_t *flag_bins,    /* [n_beams][n_bins]: 1 = decision near its threshold */
+               int32_t *beam_flag,    /* [n_beams]: 1 = top-k choice ambiguous */
+               double rel_thr, double rel_peak)
+{
+    const int NB = P->n_bins, M = C->max_per_beam;
+    const double dr = (P->r_max - P->r_min) / NB;
+    double *Pw = (double *)malloc(sizeof(double) * NB);
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * NB);
+    for (int64_t q = 0; q < n_beams; ++q) {
+        int b = beams[q];
+        const float *col = vol + (size_t)b * NB * 2;
+        for (int r = 0; r < NB; ++r) {
+            double re = col[2 * r], im = col[2 * r + 1];
+            Pw[r] = re * re + im * im + C->noise_floor;
+        }
+        uint8_t *fb = flag_bins + (size_t)q * NB;
+        int nc = 0;
+        for (int r = 0; r < NB; ++r) {
+            fb[r] = 0;
+            double sum = 0.0;
+            int N = 0;
+            for (int t = r - C->guard - C->train; t <= r + C->guard + C->train; ++t) {
+                if (t < 0 || t >= NB) continue;
+                if (t >= r - C->guard && t <= r + C->guard) continue;
+                sum += Pw[t];
+                ++N;
+            }
+            if (N == 0) continue;
+            double alpha = N * (pow(C->pfa, -1.0 / N) - 1.0);
+            double thr = alpha * sum / N;
+            int det = Pw[r] > thr;
+            if (fabs(Pw[r] - thr) <= rel_thr * thr) fb[r] = 1;
+            if (r > 0) {
+                if (!(Pw[r] > Pw[r - 1])) det = 0;
+                if (fabs(Pw[r] - Pw[r - 1]) <= rel_peak * Pw[r]) fb[r] = 1;
+            }
+            if (r + 1 < NB) {
+                if (!(Pw[r] >= Pw[r + 1])) det = 0;
+                if (fabs(Pw[r] - Pw[r + 1]) <= rel_peak * Pw[r]) fb[r] = 1;
+            }
+            if (det) cand[nc++] = r;
+        }
+        /* keep the M strongest: power descending, then lower range */
+        for (int a = 1; a < nc; ++a) {
+            int x = cand[a], t = a - 1;
+            while (t >= 0 && (Pw[cand[t]] < Pw[x] || (Pw[cand[t]] == Pw[x] && cand[t] > x))) {
+                cand[t + 1] = cand[t];
+                --t;
+            }
+            cand[t + 1] = x;
+        }
+        beam_flag[q] = 0;
+        if (nc > M && fabs(Pw[cand[M - 1]] - Pw[cand[M]]) <= rel_peak * Pw[cand[M - 1]]) beam_flag[q] = 1;
+        int kept = nc < M ? nc : M;
+        /* output in range order */
+        for (int a = 1; a < kept; ++a) {
+            int x = cand[a], t = a - 1;
+            while (t >= 0 && cand[t] > x) { cand[t + 1] = cand[t]; --t; }
+            cand[t + 1] = x;
+        }
+        int nh = beams_h(P);
+        int h = b % nh, v = b / nh;
+        double az, el;
+        if (P->grid_mode == 1) {
+            az = -0.5 * P->hfov + h * (P->hfov / P->n_h);
+            el = -0.5 * P->vfov + v * (P->vfov / P->n_v);
+        } else {
+            az = -0.5 * P->hfov + (h + 0.5) * (P->hfov / P->n_h);
+            el = -0.5 * P->vfov + (v + 0.5) * (P->vfov / P->n_v);
+        }
+        v3 dw = sensor_to_world(Q, dir_from_angles(az, el));
+        out_count[q] = kept;
+        for (int a = 0; a < M; ++a) {
+            out_bin[q * M + a] = a < kept ? cand[a] : -1;
+            double *pt = out_pts + ((size_t)q * M + a) * 4;
+            if (a < kept) {
+                double rr = P->r_min + (cand[a] + 0.5) * dr;
+                pt[0] = Q->pos[0] + dw.x * rr;
+                pt[1] = Q->pos[1] + dw.y * rr;
+                pt[2] = Q->pos[2] + dw.z * rr;
+                pt[3] = 10.0 * log10(Pw[cand[a]]);
+            } else {
+                pt[0] = pt[1] = pt[2] = pt[3] = 0.0;
+            }
+        }
+    }
+    free(Pw);
+    free(cand);
+    return 0;
+}
