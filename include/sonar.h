@@ -1,0 +1,229 @@
+/*
+ * sonar.h -- C-ABI of the MI355X volumetric sonar echo-synthesis library
+ * (libsonar.so, hand-written HIP for gfx950).
+ *
+ * The method (arXiv 2606.06130, "Towards Realistic 3D Sonar Simulation"):
+ *   - Sec. II-A: the sensor is volumetric; its aperture is discretised in
+ *     azimuth and elevation and each ping yields an azimuth x elevation x
+ *     range distribution of backscatter. Rays are cast in parallel through
+ *     the scene and bend by Snell's law in a sound-speed field.
+ *   - Sec. II-B: every intersection scatters according to its incidence angle
+ *     and material coefficients; a bounded, tunable number of secondary
+ *     reflections; complex returns carry phase from the propagation delay and
+ *     are attenuated; beams and cells are formed by coherent summation within
+ *     each ray bundle.
+ *   - Sec. III, Eq. (1)-(3): the sampling grid N_range, N_H, N_V from the
+ *     fields of view, range limits and resolutions; the LiDAR firing grid has
+ *     (N_V + 1) x (N_H + 1) emitters.
+ *
+ * Conventions shared by every entry point:
+ *   - World frame: metres, z up. Sensor frame: x forward, y left, z up.
+ *     Azimuth is measured from +x toward +y, elevation toward +z. Beam index
+ *     b = v * beams_per_row + h, with h and v increasing with azimuth and
+ *     elevation.
+ *   - Volumes are complex64 [beams_v][beams_h][n_range], interleaved FP32
+ *     (re, im), elevation-major: layout-compatible with torch.complex64.
+ *   - Ownership: the caller owns every buffer passed in; the library owns only
+ *     the scene it builds. Inputs of sonar_build_scene may be freed when it
+ *     returns.
+ *   - Streams: a sonar_stream is a hipStream_t (NULL = the null stream).
+ *     Every call is stream-ordered and asynchronous except sonar_build_scene
+ *     and sonar_device_status, which synchronise.
+ *   - Errors: host-side validation runs before any launch; a failing call
+ *     returns a negative status, launches nothing and leaves a message for
+ *     sonar_last_error() (per thread). Nothing aborts and no C++ exception
+ *     crosses this boundary. sonar_ping, sonar_ping_batch and sonar_detect
+ *     allocate nothing.
+ */
+#ifndef SONAR_H
+#define SONAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SONAR_OK = 0,
+    SONAR_W_TRUNCATED = 1,      /* more detections than `capacity`; the count holds the total */
+    SONAR_E_INVALID = -1,       /* an argument failed validation */
+    SONAR_E_NOMEM = -2,         /* device allocation failed (build only) */
+    SONAR_E_DEVICE = -3,        /* a HIP call failed */
+    SONAR_E_STACK = -4,         /* traversal stack too shallow for the scene's hierarchy */
+    SONAR_E_UNSUPPORTED = -5    /* a valid request outside what this build implements */
+} sonar_status;
+
+/* Opaque, library-owned, immutable after build. Usable from several streams
+ * at once. */
+typedef struct sonar_scene sonar_scene;
+
+/* Triangle mesh with per-facet material metadata (Sec. II-B: reflection and
+ * scattering coefficients per material; the engine provides geometry and
+ * material data, the acoustic layer the rest).
+ *   vertices     float32 [n_vertices][3], metres
+ *   indices      int32 [n_triangles][3], each in [0, n_vertices)
+ *   reflectivity float32 [n_triangles], intensity coefficient rho >= 0
+ *   phase        float32 [n_triangles], per-facet phase (rad)
+ *   material     uint8 [n_triangles]: 0 rough facet, 1 pressure-release
+ *                surface (rho 1, no diffuse part, unit specular part,
+ *                phase 0, reflection sign -1)
+ *   on_device    0: host pointers, 1: device pointers
+ *   leaf_size    most triangles per hierarchy leaf, 1..8 (0 = 4) */
+typedef struct {
+    const float *vertices;
+    const int32_t *indices;
+    const float *reflectivity;
+    const float *phase;
+    const uint8_t *material;
+    int64_t n_vertices;
+    int64_t n_triangles;
+    int32_t on_device;
+    int32_t leaf_size;
+} sonar_mesh;
+
+/* Sensor pose: position (metres) and sensor->world rotation, row-major, whose
+ * columns are the sensor's x, y, z axes in world coordinates. `ping` is the
+ * ping counter that keys the jitter sequence. */
+typedef struct {
+    double position[3];
+    double rot[9];
+    uint32_t ping;
+    uint32_t pad;
+} sonar_pose;
+
+/* Sensor, medium and scattering parameters.
+ *   hfov, vfov        fields of view (rad), Sec. III
+ *   n_h, n_v          angular samples N_H, N_V (Eq. 2-3)
+ *   rays_per_beam     rays per beam: a power of two in [1, 64]
+ *   grid_mode         0: N_H x N_V cell-centred beams, rays stratified inside
+ *                     each cell; 1: LiDAR firing grid of (N_V+1) x (N_H+1)
+ *                     emitters at -FOV/2 + i * FOV/N (rays_per_beam must be 1)
+ *   jitter            1: one uniform sample per stratum, 0: stratum centres
+ *   n_range           range bins N_range (Eq. 1), 1..4096
+ *   r_min, r_max      range limits (m); bin = floor((r - r_min) / dr),
+ *                     dr = (r_max - r_min) / n_range
+ *   freq_hz           centre frequency f0 (phase 2 pi f0 T)
+ *   c0, c_grad        sound speed c(z) = c0 + c_grad * z (m/s)
+ *   abs_db_per_m      absorption per metre of total (out + back) path
+ *   max_bounces       path depth K, 1..4 (Sec. II-B: tunable)
+ *   k_d, k_s, phong_n diffuse weight, specular weight, specular exponent
+ *   seed              jitter seed (SplitMix64)
+ *   flags             reserved, 0 */
+typedef struct {
+    double hfov, vfov;
+    int32_t n_h, n_v, rays_per_beam, grid_mode, jitter, n_range;
+    double r_min, r_max, freq_hz, c0, c_grad, abs_db_per_m;
+    int32_t max_bounces, pad0;
+    double k_d, k_s, phong_n;
+    uint64_t seed;
+    uint32_t flags, pad1;
+} sonar_params;
+
+/* CFAR detection settings (cell averaging): `train` training and `guard`
+ * guard cells per side, probability of false alarm `pfa`, `noise_floor` added
+ * to |E|^2, at most `max_per_beam` points per beam (1..16). */
+typedef struct {
+    int32_t train, guard, max_per_beam, pad;
+    double pfa, noise_floor;
+} sonar_cfar;
+
+typedef struct { float x, y, z, db; int32_t beam, bin; } sonar_point;
+typedef struct { float re, im; } sonar_cf32;
+typedef void *sonar_stream;
+
+/* Optional per-ray record, device arrays of [n_rays][max_bounces] with
+ * n_rays = beams * rays_per_beam in (beam, ray) order: hit triangle (-1 none),
+ * range bin (-1 none), connection visibility (1 visible), and contribution. */
+typedef struct {
+    int32_t *tri;
+    int32_t *bin;
+    int32_t *vis;
+    sonar_cf32 *amp;
+} sonar_ray_record;
+
+typedef struct {
+    int64_t n_triangles;
+    int64_t n_nodes;        /* internal nodes of the binary hierarchy */
+    int32_t depth;          /* longest root-to-leaf path */
+    int32_t leaf_size;
+    float lo[3], hi[3];     /* scene bounding box */
+    int64_t node_bytes;     /* bytes of the node array */
+    int64_t tri_bytes;      /* bytes of the triangle array */
+} sonar_scene_info;
+
+/* Builds the ray-traversal hierarchy of a mesh (linear BVH: Morton codes of
+ * triangle centroids, radix sort, binary radix tree, bottom-up bounds).
+ * Synchronous on `stream`. Returns SONAR_E_INVALID for null pointers,
+ * n_triangles < 1, indices out of range or non-finite vertices (checked on
+ * the device, reported after the build's synchronisation). */
+sonar_status sonar_build_scene(const sonar_mesh *mesh, sonar_stream stream, sonar_scene **out);
+
+/* Frees a scene (NULL is ignored). The caller guarantees no call using it is
+ * still in flight. */
+void sonar_free_scene(sonar_scene *scene);
+
+sonar_status sonar_get_scene_info(const sonar_scene *scene, sonar_scene_info *info);
+
+/* One ping (Sec. II-A/II-B): ray generation, nearest-hit traversal, bounce
+ * continuation with connection rays, scattering, spreading, absorption and
+ * phase, and coherent per-beam range accumulation.
+ *   volume   device complex64 [beams_v][beams_h][n_range], fully overwritten
+ *   gbuffer  optional device float32 [beams_v][beams_h][8]: over the beam's
+ *            first-bounce hits in range, mean range / r_max, mean cos
+ *            incidence, mean rho, mean facet normal (xyz, facing the ray),
+ *            hit count / rays_per_beam, 0
+ *   incoh    optional device float32 [2][beams_v][beams_h][n_range]:
+ *            sum |A|^2 of first-bounce (0) and later-bounce (1) returns
+ *   record   optional per-ray record (testing)
+ *   ray_mask optional device bit mask over rays (bit r of word r / 32): set
+ *            rays are traced and recorded but add nothing to the outputs
+ * Asynchronous on `stream`. No workspace. */
+sonar_status sonar_ping(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
+                        sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *record,
+                        const uint32_t *ray_mask, sonar_stream stream);
+
+/* Bytes of device workspace sonar_detect needs for these parameters. */
+size_t sonar_detect_workspace_size(const sonar_params *params);
+
+/* Per-beam CA-CFAR detection of a volume into a point cloud (Sec. II-A: an
+ * azimuth-elevation-range point cloud). Power P = |E|^2 + noise_floor;
+ * a cell is detected when P exceeds alpha(N) times the mean of its N training
+ * cells (alpha(N) = N (pfa^(-1/N) - 1)), exceeds its lower neighbour and is
+ * not below its upper one. The `max_per_beam` strongest per beam (ties: lower
+ * range) are emitted in (beam, range) order at the beam centre along a
+ * straight line at the bin-centre range, with 10 log10 P in dB.
+ *   points     device sonar_point [capacity]
+ *   dev_count  device int32[1]: total number of detections (may exceed
+ *              capacity; only `capacity` are written)
+ *   workspace  device buffer of sonar_detect_workspace_size() bytes
+ * Asynchronous on `stream`. */
+sonar_status sonar_detect(const sonar_cf32 *volume, const sonar_params *params, const sonar_pose *pose,
+                          const sonar_cfar *cfar, sonar_point *points, int32_t capacity, int32_t *dev_count,
+                          void *workspace, size_t workspace_bytes, sonar_stream stream);
+
+/* Synchronises `stream` and reports device-side errors recorded by calls
+ * that used `scene` (SONAR_E_STACK if a traversal ran out of stack). Clears
+ * the record. */
+sonar_status sonar_device_status(const sonar_scene *scene, sonar_stream stream);
+
+/* Static description of a status code. */
+const char *sonar_status_string(sonar_status status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *sonar_last_error(void);
+
+/* Sec. III, Eq. (1)-(3): fills n_range, n_h, n_v (and hfov, vfov, r_min,
+ * r_max) of `params` from fields of view (rad), angular resolutions (rad),
+ * range limits and range resolution (m), as floor() of each quotient (with a
+ * 1e-9 guard for quotients that are integers in exact arithmetic). Other
+ * fields are left unchanged. */
+sonar_status sonar_params_from_resolution(double hfov, double vfov, double dth_h, double dth_v, double r_min,
+                                          double r_max, double dr, sonar_params *params);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SONAR_H */

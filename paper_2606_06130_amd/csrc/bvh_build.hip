@@ -1,0 +1,558 @@
+// Linear BVH construction on the GPU: triangle bounds -> 63-bit Morton codes
+// of the centroids -> stable key/value radix sort -> binary radix tree
+// (Karras, "Maximizing parallelism in the construction of BVHs, octrees and
+// k-d trees", HPG 2012) -> bottom-up bounds with per-node arrival counters ->
+// 64-byte nodes with child boxes and leaf collapse.
+//
+// The hierarchy is only an accelerator for the nearest-hit and any-hit
+// queries of Sec. II-A (rays cast in parallel through a triangle scene): any
+// valid hierarchy gives the same hits. Every step is deterministic: min/max of
+// FP32 values are exact and the sort is stable.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.hpp"
+
+namespace sonar {
+
+namespace {
+
+constexpr int BT = 256;                 // threads per block of the simple kernels
+constexpr int RS_THREADS = 256;         // radix sort: threads per block
+constexpr int RS_ITEMS = 8;             // radix sort: keys per thread per block
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int MAX_WALK = 4096;          // bound on parent-chain walks (a valid tree is far shallower)
+
+// Order-preserving map of a float to a uint32 for atomic min/max.
+__device__ __forceinline__ uint32_t f2ord(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+// K1: bounds and centroids of every triangle; scene centroid box and vertex
+// box via block reductions and ordered-int atomics. Validates indices and
+// vertices.
+__global__ void k_tri_prep(const float *__restrict__ V, int64_t nv, const int32_t *__restrict__ I,
+                           const float *__restrict__ rho, const float *__restrict__ phi,
+                           const uint8_t *__restrict__ mat, int64_t nt, float4 *__restrict__ tri_rec,
+                           float4 *__restrict__ cen, float4 *__restrict__ blo, float4 *__restrict__ bhi,
+                           uint32_t *__restrict__ red, int *__restrict__ status)
+{
+    __shared__ float s_min[6][BT / 64], s_max[6][BT / 64];
+    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    float mn[6], mx[6];
+    for (int k = 0; k < 6; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
+    if (i < nt) {
+        int32_t a = I[3 * i], b = I[3 * i + 1], c = I[3 * i + 2];
+        int bad = (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv);
+        if (bad) {
+            atomicOr(status, ST_BAD_INDEX);
+            a = b = c = 0;
+        }
+        float v[9];
+        for (int k = 0; k < 3; ++k) {
+            v[k] = V[3 * (int64_t)a + k];
+            v[3 + k] = V[3 * (int64_t)b + k];
+            v[6 + k] = V[3 * (int64_t)c + k];
+        }
+        int nonfinite = 0;
+        for (int k = 0; k < 9; ++k) nonfinite |= !isfinite(v[k]);
+        float r = rho[i], p = phi[i];
+        uint8_t m = mat[i];
+        if (nonfinite || !isfinite(r) || !isfinite(p) || r < 0.f || m > 1) {
+            atomicOr(status, ST_BAD_VERTEX);
+            for (int k = 0; k < 9; ++k) v[k] = 0.f;
+        }
+        float3 lo = make_float3(fminf(v[0], fminf(v[3], v[6])), fminf(v[1], fminf(v[4], v[7])),
+                                fminf(v[2], fminf(v[5], v[8])));
+        float3 hi = make_float3(fmaxf(v[0], fmaxf(v[3], v[6])), fmaxf(v[1], fmaxf(v[4], v[7])),
+                                fmaxf(v[2], fmaxf(v[5], v[8])));
+        float3 cc = make_float3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z));
+        uint32_t idbits = (uint32_t)i | (m ? MAT_BIT : 0u);
+        tri_rec[3 * i + 0] = make_float4(v[0], v[1], v[2], v[3]);
+        tri_rec[3 * i + 1] = make_float4(v[4], v[5], v[6], v[7]);
+        tri_rec[3 * i + 2] = make_float4(v[8], __uint_as_float(idbits), r, p);
+        cen[i] = make_float4(cc.x, cc.y, cc.z, 0.f);
+        blo[i] = make_float4(lo.x, lo.y, lo.z, 0.f);
+        bhi[i] = make_float4(hi.x, hi.y, hi.z, 0.f);
+        mn[0] = cc.x; mn[1] = cc.y; mn[2] = cc.z; mx[0] = cc.x; mx[1] = cc.y; mx[2] = cc.z;
+        mn[3] = lo.x; mn[4] = lo.y; mn[5] = lo.z; mx[3] = hi.x; mx[4] = hi.y; mx[5] = hi.z;
+    }
+    for (int k = 0; k < 6; ++k) {
+        for (int off = 32; off > 0; off >>= 1) {
+            mn[k] = fminf(mn[k], __shfl_xor(mn[k], off));
+            mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], off));
+        }
+    }
+    int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    if (l == 0)
+        for (int k = 0; k < 6; ++k) { s_min[k][w] = mn[k]; s_max[k][w] = mx[k]; }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        int k = threadIdx.x;
+        float a = INFINITY, b = -INFINITY;
+        for (int q = 0; q < BT / 64; ++q) { a = fminf(a, s_min[k][q]); b = fmaxf(b, s_max[k][q]); }
+        atomicMin(&red[k], f2ord(a));
+        atomicMax(&red[6 + k], f2ord(b));
+    }
+}
+
+__device__ __forceinline__ uint64_t spread3_21(uint32_t x)
+{
+    uint64_t v = x & 0x1FFFFFu;
+    v = (v | (v << 32)) & 0x1F00000000FFFFULL;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFULL;
+    v = (v | (v << 8)) & 0x100F00F00F00F00FULL;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+// K2: 63-bit Morton code (21 bits per axis) of each centroid in the centroid box.
+__global__ void k_morton(const float4 *__restrict__ cen, int64_t nt, const uint32_t *__restrict__ red,
+                         uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= nt) return;
+    float lo[3], ext[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = ord2f(red[k]);
+        ext[k] = ord2f(red[6 + k]) - lo[k];
+    }
+    float4 c = cen[i];
+    float cc[3] = {c.x, c.y, c.z};
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+        float t = ext[k] > 0.f ? (cc[k] - lo[k]) / ext[k] : 0.f;
+        t = fminf(fmaxf(t, 0.f), 1.f);
+        uint32_t v = (uint32_t)(t * 2097152.0f);
+        q[k] = v > 2097151u ? 2097151u : v;
+    }
+    keys[i] = (spread3_21(q[0]) << 2) | (spread3_21(q[1]) << 1) | spread3_21(q[2]);
+    vals[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (uint64 key, uint32 value), 8-bit digits.
+
+__global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t *__restrict__ hist,
+                          int nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = base + r * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `n` uint32 in one block of 1024 threads.
+__global__ void k_scan_single(uint32_t *__restrict__ a, int64_t n)
+{
+    __shared__ uint32_t part[1024];
+    int t = threadIdx.x;
+    int64_t per = (n + 1023) / 1024;
+    int64_t b = t * per, e = b + per < n ? b + per : n;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += a[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t > 0 ? part[t - 1] : 0u;
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
+                             int shift, const uint32_t *__restrict__ hist, int nblocks, uint64_t *__restrict__ kout,
+                             uint32_t *__restrict__ vout)
+{
+    __shared__ uint32_t base[256], running[256], total[256];
+    __shared__ uint32_t cnt[RS_WAVES][256];
+    int t = threadIdx.x, w = t / 64, l = t % 64;
+    base[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+    running[t] = 0;
+    for (int q = 0; q < RS_WAVES; ++q) cnt[q][t] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    int64_t tile = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = tile + r * RS_THREADS + t;
+        bool valid = i < n;
+        uint64_t key = valid ? kin[i] : 0ull;
+        uint32_t val = valid ? vin[i] : 0u;
+        uint32_t dig = (uint32_t)(key >> shift) & 0xFFu;
+        uint64_t match = __ballot(valid);
+        for (int bit = 0; bit < 8; ++bit) {
+            uint64_t bset = __ballot((dig >> bit) & 1u);
+            match &= ((dig >> bit) & 1u) ? bset : ~bset;
+        }
+        uint32_t rank = __popcll(match & lt_mask);
+        if (valid && rank == 0) cnt[w][dig] = __popcll(match);
+        __syncthreads();
+        {   // per-digit prefix over waves
+            uint32_t p = 0;
+            for (int q = 0; q < RS_WAVES; ++q) {
+                uint32_t c = cnt[q][t];
+                cnt[q][t] = p;
+                p += c;
+            }
+            total[t] = p;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t dst = base[dig] + running[dig] + cnt[w][dig] + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+        running[t] += total[t];
+        for (int q = 0; q < RS_WAVES; ++q) cnt[q][t] = 0;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4: binary radix tree over sorted keys. Internal node i covers a contiguous
+// key range; equal keys are told apart by their index.
+
+__device__ __forceinline__ int delta(const uint64_t *__restrict__ k, int64_t n, int64_t i, int64_t j)
+{
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = k[i], b = k[j];
+    if (a != b) return __clzll(a ^ b);
+    return 64 + __clz((uint32_t)(i ^ j));
+}
+
+__global__ void k_karras(const uint64_t *__restrict__ k, int64_t n, int32_t *__restrict__ left,
+                         int32_t *__restrict__ right, int32_t *__restrict__ rlo, int32_t *__restrict__ rhi,
+                         int32_t *__restrict__ parent)
+{
+    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = delta(k, n, i, i - d);
+    int64_t lmax = 2;
+    while (delta(k, n, i, i + lmax * d) > dmin) lmax *= 2;
+    int64_t l = 0;
+    for (int64_t t = lmax / 2; t >= 1; t /= 2)
+        if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
+    int64_t j = i + l * d;
+    int dnode = delta(k, n, i, j);
+    int64_t s = 0;
+    int64_t t = l;
+    do {
+        t = (t + 1) / 2;
+        if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int64_t gamma = i + s * d + (d < 0 ? d : 0);
+    int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    // children: internal nodes 0..n-2, leaves encoded as n-1+leaf
+    int32_t cl = (lo == gamma) ? (int32_t)(n - 1 + gamma) : (int32_t)gamma;
+    int32_t cr = (hi == gamma + 1) ? (int32_t)(n - 1 + gamma + 1) : (int32_t)(gamma + 1);
+    left[i] = cl;
+    right[i] = cr;
+    rlo[i] = (int32_t)lo;
+    rhi[i] = (int32_t)hi;
+    parent[cl] = (int32_t)i;
+    parent[cr] = (int32_t)i;
+}
+
+// K5: bounds bottom-up. The second child to arrive at a node merges both boxes;
+// the first one stops. Each thread also measures its leaf's depth.
+__global__ void k_refit(const uint32_t *__restrict__ order, int64_t n, const float4 *__restrict__ blo_tri,
+                        const float4 *__restrict__ bhi_tri, const int32_t *__restrict__ left,
+                        const int32_t *__restrict__ right, const int32_t *__restrict__ parent,
+                        float4 *__restrict__ blo, float4 *__restrict__ bhi, int32_t *__restrict__ arrive,
+                        int32_t *__restrict__ depth_out)
+{
+    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    int64_t leaf = n - 1 + i;
+    uint32_t tri = order[i];
+    blo[leaf] = blo_tri[tri];
+    bhi[leaf] = bhi_tri[tri];
+    int depth = 0;
+    for (int64_t c = leaf; c != 0 && depth < MAX_WALK;) {
+        c = parent[c];
+        ++depth;
+    }
+    atomicMax(depth_out, depth);
+    if (n == 1) return;
+    __threadfence();
+    int64_t p = parent[leaf];
+    for (int steps = 0; steps < MAX_WALK; ++steps) {
+        int old = atomicAdd(&arrive[p], 1);
+        if (old == 0) return;
+        __threadfence();
+        int32_t a = left[p], b = right[p];
+        // the fence above orders these loads after the sibling's published box
+        float4 la = blo[a], ha = bhi[a];
+        float4 lb = blo[b], hb = bhi[b];
+        blo[p] = make_float4(fminf(la.x, lb.x), fminf(la.y, lb.y), fminf(la.z, lb.z), 0.f);
+        bhi[p] = make_float4(fmaxf(ha.x, hb.x), fmaxf(ha.y, hb.y), fmaxf(ha.z, hb.z), 0.f);
+        __threadfence();
+        if (p == 0) return;
+        p = parent[p];
+    }
+}
+
+// Checks every child link of the packed hierarchy: internal links inside the
+// node array, leaves inside the triangle array. Guards the traversal kernels
+// against any malformed hierarchy.
+__global__ void k_check_links(const float4 *__restrict__ nodes, int64_t n_nodes, int64_t n_tri,
+                              int *__restrict__ status)
+{
+    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n_nodes) return;
+    float4 d = nodes[4 * i + 3];
+    uint32_t l[2] = {__float_as_uint(d.x), __float_as_uint(d.y)};
+    for (int c = 0; c < 2; ++c) {
+        uint32_t x = l[c];
+        bool ok;
+        if (x == EMPTY_LINK) ok = (n_tri == 1 && c == 1);
+        else if (x & LEAF_BIT) ok = (int64_t)((x & 0x7FFFFFFFu) >> 3) + (int64_t)(x & 7u) + 1 <= n_tri;
+        else ok = (int64_t)x < n_nodes && (int64_t)x != i;
+        if (!ok) atomicOr(status, ST_BAD_TREE);
+    }
+}
+
+// K6: pack 64-byte nodes; a child whose range holds at most `leaf_size`
+// triangles becomes a leaf over its consecutive triangle records.
+__device__ __forceinline__ uint32_t child_link(int32_t c, int64_t n, const int32_t *rlo, const int32_t *rhi,
+                                               int leaf_size)
+{
+    if (c >= n - 1) {
+        uint32_t first = (uint32_t)(c - (n - 1));
+        return LEAF_BIT | (first << 3);
+    }
+    int32_t cnt = rhi[c] - rlo[c] + 1;
+    if (cnt <= leaf_size) return LEAF_BIT | ((uint32_t)rlo[c] << 3) | (uint32_t)(cnt - 1);
+    return (uint32_t)c;
+}
+
+__global__ void k_pack(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                       const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi,
+                       const float4 *__restrict__ blo, const float4 *__restrict__ bhi, int leaf_size,
+                       float4 *__restrict__ nodes)
+{
+    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n - 1) return;
+    int32_t a = left[i], b = right[i];
+    float4 la = blo[a], ha = bhi[a], lb = blo[b], hb = bhi[b];
+    nodes[4 * i + 0] = make_float4(la.x, la.y, la.z, ha.x);
+    nodes[4 * i + 1] = make_float4(ha.y, ha.z, lb.x, lb.y);
+    nodes[4 * i + 2] = make_float4(lb.z, hb.x, hb.y, hb.z);
+    uint32_t l0 = child_link(a, n, rlo, rhi, leaf_size), l1 = child_link(b, n, rlo, rhi, leaf_size);
+    nodes[4 * i + 3] = make_float4(__uint_as_float(l0), __uint_as_float(l1), 0.f, 0.f);
+}
+
+// Single-triangle scene: one root whose first child is the leaf and whose
+// second child is empty (inverted box).
+__global__ void k_pack_single(const float4 *__restrict__ blo, const float4 *__restrict__ bhi,
+                              float4 *__restrict__ nodes)
+{
+    float4 l = blo[0], h = bhi[0];
+    nodes[0] = make_float4(l.x, l.y, l.z, h.x);
+    nodes[1] = make_float4(h.y, h.z, INFINITY, INFINITY);
+    nodes[2] = make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
+    nodes[3] = make_float4(__uint_as_float(LEAF_BIT), __uint_as_float(EMPTY_LINK), 0.f, 0.f);
+}
+
+__global__ void k_gather_tris(const uint32_t *__restrict__ order, int64_t n, const float4 *__restrict__ in,
+                              float4 *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    uint32_t t = order[i];
+    out[3 * i + 0] = in[3 * (int64_t)t + 0];
+    out[3 * i + 1] = in[3 * (int64_t)t + 1];
+    out[3 * i + 2] = in[3 * (int64_t)t + 2];
+}
+
+__global__ void k_init_red(uint32_t *red)
+{
+    int t = threadIdx.x;
+    if (t < 6) red[t] = 0xFFFFFFFFu;       // min slots: largest ordered value
+    else if (t < 12) red[t] = 0u;          // max slots
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + BT - 1) / BT); }
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+}  // namespace
+
+#define BCHECK(x)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess) {                                                          \
+            snprintf(err, errlen, "%s: %s", #x, hipGetErrorString(e_));                 \
+            return e_ == hipErrorOutOfMemory ? SONAR_E_NOMEM : SONAR_E_DEVICE;          \
+        }                                                                                \
+    } while (0)
+
+sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, char *err, size_t errlen)
+{
+    const int64_t n = m.n_triangles;
+    const int64_t nv = m.n_vertices;
+    // device copies of the inputs when they are host pointers
+    DevBuf dV, dI, dR, dP, dM;
+    const float *V = m.vertices;
+    const int32_t *I = m.indices;
+    const float *R = m.reflectivity;
+    const float *P = m.phase;
+    const uint8_t *M = m.material;
+    if (!m.on_device) {
+        BCHECK(hipMalloc(&dV.p, sizeof(float) * 3 * nv));
+        BCHECK(hipMalloc(&dI.p, sizeof(int32_t) * 3 * n));
+        BCHECK(hipMalloc(&dR.p, sizeof(float) * n));
+        BCHECK(hipMalloc(&dP.p, sizeof(float) * n));
+        BCHECK(hipMalloc(&dM.p, n));
+        BCHECK(hipMemcpyAsync(dV.p, V, sizeof(float) * 3 * nv, hipMemcpyHostToDevice, s));
+        BCHECK(hipMemcpyAsync(dI.p, I, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice, s));
+        BCHECK(hipMemcpyAsync(dR.p, R, sizeof(float) * n, hipMemcpyHostToDevice, s));
+        BCHECK(hipMemcpyAsync(dP.p, P, sizeof(float) * n, hipMemcpyHostToDevice, s));
+        BCHECK(hipMemcpyAsync(dM.p, M, n, hipMemcpyHostToDevice, s));
+        V = (const float *)dV.p;
+        I = (const int32_t *)dI.p;
+        R = (const float *)dR.p;
+        P = (const float *)dP.p;
+        M = (const uint8_t *)dM.p;
+    }
+    const int64_t n_int = n > 1 ? n - 1 : 1;
+    const int64_t n_all = 2 * n - 1;
+    DevBuf rec, cen, tlo, thi, red, k0, k1, v0, v1, hist, lft, rgt, rlo, rhi, par, blo, bhi, arr, dep;
+    int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+    BCHECK(hipMalloc(&rec.p, sizeof(float4) * 3 * n));
+    BCHECK(hipMalloc(&cen.p, sizeof(float4) * n));
+    BCHECK(hipMalloc(&tlo.p, sizeof(float4) * n));
+    BCHECK(hipMalloc(&thi.p, sizeof(float4) * n));
+    BCHECK(hipMalloc(&red.p, sizeof(uint32_t) * 12 + sizeof(int) * 2));
+    BCHECK(hipMalloc(&k0.p, sizeof(uint64_t) * n));
+    BCHECK(hipMalloc(&k1.p, sizeof(uint64_t) * n));
+    BCHECK(hipMalloc(&v0.p, sizeof(uint32_t) * n));
+    BCHECK(hipMalloc(&v1.p, sizeof(uint32_t) * n));
+    BCHECK(hipMalloc(&hist.p, sizeof(uint32_t) * 256 * nblocks));
+    BCHECK(hipMalloc(&lft.p, sizeof(int32_t) * n_int));
+    BCHECK(hipMalloc(&rgt.p, sizeof(int32_t) * n_int));
+    BCHECK(hipMalloc(&rlo.p, sizeof(int32_t) * n_int));
+    BCHECK(hipMalloc(&rhi.p, sizeof(int32_t) * n_int));
+    BCHECK(hipMalloc(&par.p, sizeof(int32_t) * n_all));
+    BCHECK(hipMalloc(&blo.p, sizeof(float4) * n_all));
+    BCHECK(hipMalloc(&bhi.p, sizeof(float4) * n_all));
+    BCHECK(hipMalloc(&arr.p, sizeof(int32_t) * n_int));
+    BCHECK(hipMalloc(&dep.p, sizeof(int32_t)));
+
+    float4 *nodes = nullptr, *tris = nullptr;
+    int *status = nullptr;
+    BCHECK(hipMalloc(&nodes, sizeof(float4) * 4 * n_int));
+    if (hipMalloc(&tris, sizeof(float4) * 3 * n) != hipSuccess || hipMalloc(&status, sizeof(int)) != hipSuccess) {
+        (void)hipFree(nodes);
+        if (tris) (void)hipFree(tris);
+        snprintf(err, errlen, "out of device memory for the scene");
+        return SONAR_E_NOMEM;
+    }
+    out->nodes = nodes;
+    out->tris = tris;
+    out->status = status;
+
+    uint32_t *redp = (uint32_t *)red.p;
+    int *st_build = (int *)(redp + 12);
+    BCHECK(hipMemsetAsync(status, 0, sizeof(int), s));
+    BCHECK(hipMemsetAsync(st_build, 0, sizeof(int), s));
+    BCHECK(hipMemsetAsync(arr.p, 0, sizeof(int32_t) * n_int, s));
+    BCHECK(hipMemsetAsync(dep.p, 0, sizeof(int32_t), s));
+    BCHECK(hipMemsetAsync(par.p, 0, sizeof(int32_t) * n_all, s));
+    k_init_red<<<1, 64, 0, s>>>(redp);
+    k_tri_prep<<<nblk(n), BT, 0, s>>>(V, nv, I, R, P, M, n, (float4 *)rec.p, (float4 *)cen.p, (float4 *)tlo.p,
+                                      (float4 *)thi.p, redp, st_build);
+    k_morton<<<nblk(n), BT, 0, s>>>((const float4 *)cen.p, n, redp, (uint64_t *)k0.p, (uint32_t *)v0.p);
+    uint64_t *ka = (uint64_t *)k0.p, *kb = (uint64_t *)k1.p;
+    uint32_t *va = (uint32_t *)v0.p, *vb = (uint32_t *)v1.p;
+    for (int shift = 0; shift < 64; shift += 8) {
+        k_rs_hist<<<nblocks, RS_THREADS, 0, s>>>(ka, n, shift, (uint32_t *)hist.p, nblocks);
+        k_scan_single<<<1, 1024, 0, s>>>((uint32_t *)hist.p, (int64_t)256 * nblocks);
+        k_rs_scatter<<<nblocks, RS_THREADS, 0, s>>>(ka, va, n, shift, (const uint32_t *)hist.p, nblocks, kb, vb);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    if (n > 1) {
+        k_karras<<<nblk(n - 1), BT, 0, s>>>(ka, n, (int32_t *)lft.p, (int32_t *)rgt.p, (int32_t *)rlo.p,
+                                            (int32_t *)rhi.p, (int32_t *)par.p);
+    }
+    k_refit<<<nblk(n), BT, 0, s>>>(va, n, (const float4 *)tlo.p, (const float4 *)thi.p, (const int32_t *)lft.p,
+                                   (const int32_t *)rgt.p, (const int32_t *)par.p, (float4 *)blo.p,
+                                   (float4 *)bhi.p, (int32_t *)arr.p, (int32_t *)dep.p);
+    if (n > 1) {
+        k_pack<<<nblk(n - 1), BT, 0, s>>>(n, (const int32_t *)lft.p, (const int32_t *)rgt.p,
+                                          (const int32_t *)rlo.p, (const int32_t *)rhi.p, (const float4 *)blo.p,
+                                          (const float4 *)bhi.p, m.leaf_size, nodes);
+    } else {
+        k_pack_single<<<1, 1, 0, s>>>((const float4 *)blo.p, (const float4 *)bhi.p, nodes);
+    }
+    k_gather_tris<<<nblk(n), BT, 0, s>>>(va, n, (const float4 *)rec.p, tris);
+    k_check_links<<<nblk(n_int), BT, 0, s>>>(nodes, n_int, n, st_build);
+    BCHECK(hipGetLastError());
+    uint32_t hred[12];
+    int hst = 0, hdep = 0;
+    BCHECK(hipMemcpyAsync(hred, redp, sizeof(hred), hipMemcpyDeviceToHost, s));
+    BCHECK(hipMemcpyAsync(&hst, st_build, sizeof(int), hipMemcpyDeviceToHost, s));
+    BCHECK(hipMemcpyAsync(&hdep, dep.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    BCHECK(hipStreamSynchronize(s));
+    if (hst & ST_BAD_INDEX) {
+        snprintf(err, errlen, "triangle index outside [0, n_vertices)");
+        return SONAR_E_INVALID;
+    }
+    if (hst & ST_BAD_TREE) {
+        snprintf(err, errlen, "internal error: malformed hierarchy");
+        return SONAR_E_DEVICE;
+    }
+    if (hst & ST_BAD_VERTEX) {
+        snprintf(err, errlen, "non-finite vertex, reflectivity or phase, negative reflectivity or material > 1");
+        return SONAR_E_INVALID;
+    }
+    auto ordf = [](uint32_t u) {
+        uint32_t v = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+        float f;
+        memcpy(&f, &v, 4);
+        return f;
+    };
+    for (int k = 0; k < 3; ++k) {
+        out->lo[k] = ordf(hred[3 + k]);
+        out->hi[k] = ordf(hred[9 + k]);
+    }
+    out->zabs_max = fmaxf(fabsf(out->lo[2]), fabsf(out->hi[2]));
+    out->n_tri = n;
+    out->n_nodes = n_int;
+    out->depth = hdep;
+    out->leaf_size = m.leaf_size;
+    return SONAR_OK;
+}
+
+}  // namespace sonar

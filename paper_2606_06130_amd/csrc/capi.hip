@@ -1,0 +1,336 @@
+// Host side of the C-ABI: validation, scene ownership and launches.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "internal.hpp"
+
+struct sonar_scene {
+    sonar::Scene s;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+sonar_status fail(sonar_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int x)
+{
+    int l = 0;
+    while ((1 << (l + 1)) <= x) ++l;
+    return l;
+}
+
+void free_scene_mem(sonar::Scene &s)
+{
+    if (s.nodes) (void)hipFree(s.nodes);
+    if (s.tris) (void)hipFree(s.tris);
+    if (s.status) (void)hipFree(s.status);
+    s.nodes = nullptr;
+    s.tris = nullptr;
+    s.status = nullptr;
+}
+
+sonar_status check_params(const sonar_params *p)
+{
+    if (!p) return fail(SONAR_E_INVALID, "params is NULL");
+    if (!(p->hfov > 0 && p->hfov < 2 * M_PI) || !(p->vfov > 0 && p->vfov < M_PI))
+        return fail(SONAR_E_INVALID, "fields of view must satisfy 0 < hfov < 2 pi, 0 < vfov < pi");
+    if (p->n_h < 1 || p->n_v < 1 || p->n_h > 65536 || p->n_v > 65536)
+        return fail(SONAR_E_INVALID, "n_h and n_v must be in [1, 65536]");
+    if (!is_pow2(p->rays_per_beam) || p->rays_per_beam > 64)
+        return fail(SONAR_E_INVALID, "rays_per_beam must be a power of two in [1, 64]");
+    if (p->grid_mode != 0 && p->grid_mode != 1) return fail(SONAR_E_INVALID, "grid_mode must be 0 or 1");
+    if (p->grid_mode == 1 && p->rays_per_beam != 1)
+        return fail(SONAR_E_INVALID, "the LiDAR firing grid takes one ray per emitter");
+    if (p->n_range < 1 || p->n_range > sonar::MAX_BINS)
+        return fail(SONAR_E_INVALID, "n_range must be in [1, %d]", sonar::MAX_BINS);
+    if (!(p->r_min >= 0) || !(p->r_max > p->r_min) || !isfinite(p->r_max))
+        return fail(SONAR_E_INVALID, "need 0 <= r_min < r_max < inf");
+    if (!(p->freq_hz > 0) || !isfinite(p->freq_hz)) return fail(SONAR_E_INVALID, "freq_hz must be positive");
+    if (!(p->c0 > 0) || !isfinite(p->c0) || !isfinite(p->c_grad)) return fail(SONAR_E_INVALID, "bad sound speed");
+    if (!(p->abs_db_per_m >= 0) || !isfinite(p->abs_db_per_m))
+        return fail(SONAR_E_INVALID, "abs_db_per_m must be >= 0");
+    if (p->max_bounces < 1 || p->max_bounces > sonar::MAX_BOUNCES)
+        return fail(SONAR_E_INVALID, "max_bounces must be in [1, %d]", sonar::MAX_BOUNCES);
+    if (!(p->k_d >= 0) || !(p->k_s >= 0) || !(p->phong_n >= 0) || !isfinite(p->k_d) || !isfinite(p->k_s) ||
+        !isfinite(p->phong_n))
+        return fail(SONAR_E_INVALID, "k_d, k_s and phong_n must be finite and >= 0");
+    int64_t beams = (int64_t)(p->n_h + (p->grid_mode == 1)) * (p->n_v + (p->grid_mode == 1));
+    if (beams * p->rays_per_beam > ((int64_t)1 << 31) - 1) return fail(SONAR_E_INVALID, "too many rays");
+    return SONAR_OK;
+}
+
+sonar_status check_pose(const sonar_pose *q)
+{
+    if (!q) return fail(SONAR_E_INVALID, "pose is NULL");
+    for (int i = 0; i < 3; ++i)
+        if (!isfinite(q->position[i])) return fail(SONAR_E_INVALID, "non-finite pose position");
+    // rotation: orthonormal within 1e-6
+    const double *R = q->rot;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double d = R[i] * R[j] + R[3 + i] * R[3 + j] + R[6 + i] * R[6 + j];
+            double want = i == j ? 1.0 : 0.0;
+            if (!(fabs(d - want) <= 1e-6)) return fail(SONAR_E_INVALID, "pose rotation is not orthonormal");
+        }
+    return SONAR_OK;
+}
+
+int beams_h_of(const sonar_params *p) { return p->grid_mode == 1 ? p->n_h + 1 : p->n_h; }
+int beams_v_of(const sonar_params *p) { return p->grid_mode == 1 ? p->n_v + 1 : p->n_v; }
+
+}  // namespace
+
+extern "C" {
+
+const char *sonar_last_error(void) { return g_err; }
+
+const char *sonar_status_string(sonar_status s)
+{
+    switch (s) {
+        case SONAR_OK: return "ok";
+        case SONAR_W_TRUNCATED: return "output truncated to capacity";
+        case SONAR_E_INVALID: return "invalid argument";
+        case SONAR_E_NOMEM: return "out of device memory";
+        case SONAR_E_DEVICE: return "device error";
+        case SONAR_E_STACK: return "traversal stack overflow";
+        case SONAR_E_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+sonar_status sonar_params_from_resolution(double hfov, double vfov, double dth_h, double dth_v, double r_min,
+                                          double r_max, double dr, sonar_params *p)
+{
+    if (!p) return fail(SONAR_E_INVALID, "params is NULL");
+    if (!(hfov > 0) || !(vfov > 0) || !(dth_h > 0) || !(dth_v > 0) || !(dr > 0) || !(r_max > r_min) ||
+        !(r_min >= 0))
+        return fail(SONAR_E_INVALID, "resolutions and fields of view must be positive, r_max > r_min >= 0");
+    double nr = floor((r_max - r_min) / dr + 1e-9);
+    double nh = floor(hfov / dth_h + 1e-9);
+    double nv = floor(vfov / dth_v + 1e-9);
+    if (nr < 1 || nh < 1 || nv < 1 || nr > sonar::MAX_BINS || nh > 65536 || nv > 65536)
+        return fail(SONAR_E_INVALID, "resulting grid out of range");
+    p->hfov = hfov;
+    p->vfov = vfov;
+    p->r_min = r_min;
+    p->r_max = r_max;
+    p->n_range = (int32_t)nr;
+    p->n_h = (int32_t)nh;
+    p->n_v = (int32_t)nv;
+    return SONAR_OK;
+}
+
+sonar_status sonar_build_scene(const sonar_mesh *m, sonar_stream stream, sonar_scene **out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(SONAR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!m) return fail(SONAR_E_INVALID, "mesh is NULL");
+    if (!m->vertices || !m->indices || !m->reflectivity || !m->phase || !m->material)
+        return fail(SONAR_E_INVALID, "mesh arrays must not be NULL");
+    if (m->n_triangles < 1 || m->n_vertices < 3) return fail(SONAR_E_INVALID, "need >= 1 triangle, >= 3 vertices");
+    if (m->n_triangles >= (int64_t)1 << 28) return fail(SONAR_E_INVALID, "at most 2^28 - 1 triangles");
+    if (m->leaf_size < 0 || m->leaf_size > 8) return fail(SONAR_E_INVALID, "leaf_size must be in [0, 8]");
+    sonar_mesh mm = *m;
+    if (mm.leaf_size == 0) mm.leaf_size = 4;
+    sonar_scene *sc = new (std::nothrow) sonar_scene();
+    if (!sc) return fail(SONAR_E_NOMEM, "host allocation failed");
+    if (hipGetDevice(&sc->s.device) != hipSuccess) {
+        delete sc;
+        return fail(SONAR_E_DEVICE, "no HIP device");
+    }
+    char err[256] = "";
+    sonar_status st = sonar::build_hierarchy(mm, (hipStream_t)stream, &sc->s, err, sizeof(err));
+    if (st != SONAR_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        free_scene_mem(sc->s);
+        delete sc;
+        return fail(st, "%s", err);
+    }
+    *out = sc;
+    return SONAR_OK;
+}
+
+void sonar_free_scene(sonar_scene *sc)
+{
+    if (!sc) return;
+    free_scene_mem(sc->s);
+    delete sc;
+}
+
+sonar_status sonar_get_scene_info(const sonar_scene *sc, sonar_scene_info *info)
+{
+    if (!sc || !info) return fail(SONAR_E_INVALID, "scene or info is NULL");
+    info->n_triangles = sc->s.n_tri;
+    info->n_nodes = sc->s.n_nodes;
+    info->depth = sc->s.depth;
+    info->leaf_size = sc->s.leaf_size;
+    for (int k = 0; k < 3; ++k) {
+        info->lo[k] = sc->s.lo[k];
+        info->hi[k] = sc->s.hi[k];
+    }
+    info->node_bytes = sc->s.n_nodes * 64;
+    info->tri_bytes = sc->s.n_tri * 48;
+    return SONAR_OK;
+}
+
+sonar_status sonar_ping(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, sonar_cf32 *volume,
+                        float *gbuffer, float *incoh, const sonar_ray_record *rec, const uint32_t *ray_mask,
+                        sonar_stream stream)
+{
+    g_err[0] = 0;
+    if (!sc) return fail(SONAR_E_INVALID, "scene is NULL");
+    sonar_status st = check_params(p);
+    if (st != SONAR_OK) return st;
+    if ((st = check_pose(q)) != SONAR_OK) return st;
+    if (!volume) return fail(SONAR_E_INVALID, "volume is NULL");
+    if (rec && (!rec->tri || !rec->bin || !rec->vis || !rec->amp))
+        return fail(SONAR_E_INVALID, "record arrays must all be set");
+    if (p->c_grad != 0.0) return fail(SONAR_E_UNSUPPORTED, "curved rays (c_grad != 0) are not in this build");
+    if (sc->s.depth > 64)
+        return fail(SONAR_E_STACK, "hierarchy depth %d exceeds the 64-entry traversal stack", sc->s.depth);
+    sonar::PingArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nodes = sc->s.nodes;
+    a.tris = sc->s.tris;
+    a.status = sc->s.status;
+    for (int i = 0; i < 3; ++i) a.pos[i] = q->position[i];
+    for (int i = 0; i < 9; ++i) a.rot[i] = q->rot[i];
+    a.hfov = p->hfov;
+    a.vfov = p->vfov;
+    a.dth_h = p->hfov / p->n_h;
+    a.dth_v = p->vfov / p->n_v;
+    a.r_min = p->r_min;
+    a.r_max = p->r_max;
+    a.dr = (p->r_max - p->r_min) / p->n_range;
+    a.f0 = p->freq_hz;
+    a.c0 = p->c0;
+    a.g = p->c_grad;
+    a.alpha_db = p->abs_db_per_m;
+    a.k_d = p->k_d;
+    a.k_s = p->k_s;
+    a.phong_n = p->phong_n;
+    a.c_ref = p->c0 + p->c_grad * q->position[2];
+    a.c_hi = p->c0 + fabs(p->c_grad) * (fmax((double)sc->s.zabs_max, fabs(q->position[2])) + 1.0);
+    a.seed = p->seed;
+    a.ping = q->ping;
+    a.beams_h = beams_h_of(p);
+    a.beams_v = beams_v_of(p);
+    a.n_beams = a.beams_h * a.beams_v;
+    a.n_r = p->rays_per_beam;
+    a.log2_nr = ilog2(p->rays_per_beam);
+    a.ne = 1 << (a.log2_nr / 2);
+    a.na = a.n_r / a.ne;
+    a.grid_mode = p->grid_mode;
+    a.jitter = p->jitter;
+    a.n_bins = p->n_range;
+    a.K = p->max_bounces;
+    a.n_rays = (int64_t)a.n_beams * a.n_r;
+    a.volume = reinterpret_cast<float2 *>(volume);
+    a.gbuf = gbuffer;
+    a.incoh = incoh;
+    if (rec) {
+        a.rec_tri = rec->tri;
+        a.rec_bin = rec->bin;
+        a.rec_vis = rec->vis;
+        a.rec_amp = reinterpret_cast<float2 *>(rec->amp);
+    }
+    a.mask = ray_mask;
+    a.max_steps = (uint32_t)(2 * sc->s.n_nodes + 64);
+    hipError_t e = sonar::launch_ping(a, sc->s.depth, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
+size_t sonar_detect_workspace_size(const sonar_params *p)
+{
+    if (check_params(p) != SONAR_OK) return 0;
+    return sonar::detect_workspace_bytes(beams_h_of(p) * beams_v_of(p), 16);
+}
+
+sonar_status sonar_detect(const sonar_cf32 *volume, const sonar_params *p, const sonar_pose *q,
+                          const sonar_cfar *c, sonar_point *points, int32_t capacity, int32_t *dev_count,
+                          void *workspace, size_t ws_bytes, sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar_status st = check_params(p);
+    if (st != SONAR_OK) return st;
+    if ((st = check_pose(q)) != SONAR_OK) return st;
+    if (!volume || !dev_count || !workspace) return fail(SONAR_E_INVALID, "volume, dev_count and workspace are required");
+    if (!c) return fail(SONAR_E_INVALID, "cfar is NULL");
+    if (c->train < 1 || c->guard < 0 || c->train > 64 || c->guard > 64)
+        return fail(SONAR_E_INVALID, "train must be in [1, 64] and guard in [0, 64]");
+    if (c->max_per_beam < 1 || c->max_per_beam > 16) return fail(SONAR_E_INVALID, "max_per_beam must be in [1, 16]");
+    if (!(c->pfa > 0 && c->pfa < 1)) return fail(SONAR_E_INVALID, "pfa must be in (0, 1)");
+    if (!(c->noise_floor >= 0) || !isfinite(c->noise_floor)) return fail(SONAR_E_INVALID, "noise_floor must be >= 0");
+    if (capacity < 0 || (capacity > 0 && !points)) return fail(SONAR_E_INVALID, "points required when capacity > 0");
+    int nb = beams_h_of(p) * beams_v_of(p);
+    if (ws_bytes < sonar::detect_workspace_bytes(nb, 16))
+        return fail(SONAR_E_INVALID, "workspace smaller than sonar_detect_workspace_size()");
+    sonar::DetectArgs a;
+    memset(&a, 0, sizeof(a));
+    a.volume = reinterpret_cast<const float2 *>(volume);
+    a.points = points;
+    a.count = dev_count;
+    char *w = (char *)workspace;
+    a.beam_count = (int32_t *)w;
+    a.block_sums = (int32_t *)(w + sizeof(int32_t) * nb);
+    a.beam_bins = (int32_t *)(w + 2 * sizeof(int32_t) * nb);
+    a.beam_pw = (float *)(w + 2 * sizeof(int32_t) * nb + sizeof(int32_t) * (size_t)nb * 16);
+    a.n_beams = nb;
+    a.n_bins = p->n_range;
+    a.beams_h = beams_h_of(p);
+    a.grid_mode = p->grid_mode;
+    a.train = c->train;
+    a.guard = c->guard;
+    a.max_per_beam = c->max_per_beam;
+    a.capacity = capacity;
+    a.pfa = c->pfa;
+    a.noise_floor = c->noise_floor;
+    a.hfov = p->hfov;
+    a.vfov = p->vfov;
+    a.dth_h = p->hfov / p->n_h;
+    a.dth_v = p->vfov / p->n_v;
+    a.r_min = p->r_min;
+    a.dr = (p->r_max - p->r_min) / p->n_range;
+    for (int i = 0; i < 3; ++i) a.pos[i] = q->position[i];
+    for (int i = 0; i < 9; ++i) a.rot[i] = q->rot[i];
+    hipError_t e = sonar::launch_detect(a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "detect launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
+sonar_status sonar_device_status(const sonar_scene *sc, sonar_stream stream)
+{
+    if (!sc) return fail(SONAR_E_INVALID, "scene is NULL");
+    int h = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&h, sc->s.status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(SONAR_E_DEVICE, "status read failed");
+    if (h) {
+        int zero = 0;
+        (void)hipMemcpyAsync(sc->s.status, &zero, sizeof(int), hipMemcpyHostToDevice, s);
+        (void)hipStreamSynchronize(s);
+    }
+    if (h & sonar::ST_STACK) return fail(SONAR_E_STACK, "a traversal overflowed its stack; those rays were misses");
+    return SONAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Internal types shared by the library's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sonar.h"
+
+namespace sonar {
+
+// ---------------------------------------------------------------------------
+// Scene layout in HBM.
+//
+// Node: 64 bytes, two child boxes and two child links:
+//   float4 a = {lo0.x, lo0.y, lo0.z, hi0.x}
+//   float4 b = {hi0.y, hi0.z, lo1.x, lo1.y}
+//   float4 c = {lo1.z, hi1.x, hi1.y, hi1.z}
+//   int4   d = {link0, link1, 0, 0}
+// Link: >= 0 internal node index; LEAF_BIT | first << 3 | (count - 1) a leaf of
+// `count` consecutive triangle records; EMPTY_LINK no child.
+// Triangle record: 48 bytes, the FP32 input vertices (exact), the original
+// triangle index with the pressure-release bit, reflectivity and phase:
+//   float4 {v0.x, v0.y, v0.z, v1.x}, {v1.y, v1.z, v2.x, v2.y},
+//          {v2.z, bits(id | mat << 31), rho, phi}
+constexpr uint32_t LEAF_BIT = 0x80000000u;
+constexpr uint32_t EMPTY_LINK = 0xFFFFFFFFu;
+constexpr uint32_t MAT_BIT = 0x80000000u;
+constexpr int MAX_BOUNCES = 4;
+constexpr int MAX_BINS = 4096;
+
+struct Scene {
+    float4 *nodes = nullptr;      // [n_nodes * 4]
+    float4 *tris = nullptr;       // [n_tri * 3]
+    int *status = nullptr;        // device error word
+    int64_t n_tri = 0;
+    int64_t n_nodes = 0;
+    int depth = 0;
+    int leaf_size = 4;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    float zabs_max = 0.f;
+    int device = 0;
+};
+
+// Device status bits.
+constexpr int ST_STACK = 1;
+constexpr int ST_BAD_INDEX = 2;
+constexpr int ST_BAD_VERTEX = 4;
+constexpr int ST_BAD_TREE = 8;
+constexpr int ST_LOOP = 16;
+
+// Everything a ping kernel needs, by value.
+struct PingArgs {
+    const float4 *nodes;
+    const float4 *tris;
+    int *status;
+    // sensor
+    double pos[3];
+    double rot[9];
+    double hfov, vfov, dth_h, dth_v;
+    double r_min, r_max, dr;
+    double f0, c0, g, alpha_db;
+    double k_d, k_s, phong_n;
+    double c_ref, c_hi;
+    uint64_t seed;
+    uint32_t ping;
+    int beams_h, beams_v, n_beams, n_r, log2_nr, na, ne;
+    int grid_mode, jitter, n_bins, K;
+    int64_t n_rays;
+    // outputs
+    float2 *volume;
+    float *gbuf;
+    float *incoh;
+    int32_t *rec_tri, *rec_bin, *rec_vis;
+    float2 *rec_amp;
+    const uint32_t *mask;
+    uint32_t max_steps;      // node-visit bound of one traversal (2 * nodes + 64)
+};
+
+// Host-side launchers (one per translation unit).
+hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s);
+
+struct BuildBuffers;
+sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, char *err, size_t errlen);
+
+struct DetectArgs {
+    const float2 *volume;
+    sonar_point *points;
+    int32_t *count;
+    int32_t *beam_count;     // workspace [n_beams]
+    int32_t *beam_bins;      // workspace [n_beams * max_per_beam]
+    float *beam_pw;          // workspace [n_beams * max_per_beam]
+    int32_t *block_sums;     // workspace
+    int n_beams, n_bins, beams_h, grid_mode;
+    int train, guard, max_per_beam, capacity;
+    double pfa, noise_floor;
+    double hfov, vfov, dth_h, dth_v, r_min, dr;
+    double pos[3], rot[9];
+};
+hipError_t launch_detect(const DetectArgs &a, hipStream_t s);
+size_t detect_workspace_bytes(int n_beams, int max_per_beam);
+
+}  // namespace sonar

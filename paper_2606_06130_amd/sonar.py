@@ -1,0 +1,274 @@
+"""Thin Python binding of ``libsonar.so`` (ctypes).
+
+Argument marshalling only: every step of a ping runs in the library's HIP
+kernels. PyTorch provides device memory (tensors) and streams. There is no
+fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsonar.so")
+
+SONAR_OK = 0
+SONAR_W_TRUNCATED = 1
+SONAR_E_INVALID = -1
+SONAR_E_NOMEM = -2
+SONAR_E_DEVICE = -3
+SONAR_E_STACK = -4
+SONAR_E_UNSUPPORTED = -5
+
+# Every symbol include/sonar.h declares.
+EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "sonar_ping",
+           "sonar_detect_workspace_size", "sonar_detect", "sonar_device_status", "sonar_status_string",
+           "sonar_last_error", "sonar_params_from_resolution")
+
+
+class SonarError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class sonar_mesh(C.Structure):
+    _fields_ = [("vertices", C.c_void_p), ("indices", C.c_void_p), ("reflectivity", C.c_void_p),
+                ("phase", C.c_void_p), ("material", C.c_void_p), ("n_vertices", C.c_int64),
+                ("n_triangles", C.c_int64), ("on_device", C.c_int32), ("leaf_size", C.c_int32)]
+
+
+class sonar_pose(C.Structure):
+    _fields_ = [("position", C.c_double * 3), ("rot", C.c_double * 9), ("ping", C.c_uint32), ("pad", C.c_uint32)]
+
+
+class sonar_params(C.Structure):
+    _fields_ = [("hfov", C.c_double), ("vfov", C.c_double),
+                ("n_h", C.c_int32), ("n_v", C.c_int32), ("rays_per_beam", C.c_int32), ("grid_mode", C.c_int32),
+                ("jitter", C.c_int32), ("n_range", C.c_int32),
+                ("r_min", C.c_double), ("r_max", C.c_double), ("freq_hz", C.c_double), ("c0", C.c_double),
+                ("c_grad", C.c_double), ("abs_db_per_m", C.c_double),
+                ("max_bounces", C.c_int32), ("pad0", C.c_int32),
+                ("k_d", C.c_double), ("k_s", C.c_double), ("phong_n", C.c_double),
+                ("seed", C.c_uint64), ("flags", C.c_uint32), ("pad1", C.c_uint32)]
+
+
+class sonar_cfar(C.Structure):
+    _fields_ = [("train", C.c_int32), ("guard", C.c_int32), ("max_per_beam", C.c_int32), ("pad", C.c_int32),
+                ("pfa", C.c_double), ("noise_floor", C.c_double)]
+
+
+class sonar_ray_record(C.Structure):
+    _fields_ = [("tri", C.c_void_p), ("bin", C.c_void_p), ("vis", C.c_void_p), ("amp", C.c_void_p)]
+
+
+class sonar_scene_info(C.Structure):
+    _fields_ = [("n_triangles", C.c_int64), ("n_nodes", C.c_int64), ("depth", C.c_int32),
+                ("leaf_size", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3),
+                ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64)]
+
+
+POINT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("db", "<f4"), ("beam", "<i4"), ("bin", "<i4")])
+
+_lib = None
+
+
+def lib():
+    """Loads libsonar.so (built by ``paper_2606_06130_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2606_06130_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.sonar_build_scene.restype = C.c_int
+        L.sonar_build_scene.argtypes = [P(sonar_mesh), C.c_void_p, P(C.c_void_p)]
+        L.sonar_free_scene.restype = None
+        L.sonar_free_scene.argtypes = [C.c_void_p]
+        L.sonar_get_scene_info.restype = C.c_int
+        L.sonar_get_scene_info.argtypes = [C.c_void_p, P(sonar_scene_info)]
+        L.sonar_ping.restype = C.c_int
+        L.sonar_ping.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), C.c_void_p, C.c_void_p, C.c_void_p,
+                                 P(sonar_ray_record), C.c_void_p, C.c_void_p]
+        L.sonar_detect_workspace_size.restype = C.c_size_t
+        L.sonar_detect_workspace_size.argtypes = [P(sonar_params)]
+        L.sonar_detect.restype = C.c_int
+        L.sonar_detect.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_cfar), C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.sonar_device_status.restype = C.c_int
+        L.sonar_device_status.argtypes = [C.c_void_p, C.c_void_p]
+        L.sonar_status_string.restype = C.c_char_p
+        L.sonar_status_string.argtypes = [C.c_int]
+        L.sonar_last_error.restype = C.c_char_p
+        L.sonar_last_error.argtypes = []
+        L.sonar_params_from_resolution.restype = C.c_int
+        L.sonar_params_from_resolution.argtypes = [C.c_double] * 7 + [P(sonar_params)]
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st < 0:
+        L = lib()
+        raise SonarError(st, f"{L.sonar_status_string(st).decode()}: {L.sonar_last_error().decode()}")
+    return st
+
+
+def params_of(cfg) -> sonar_params:
+    """sonar_params from a ``scenes.SensorConfig``."""
+    return sonar_params(hfov=cfg.hfov, vfov=cfg.vfov, n_h=cfg.n_h, n_v=cfg.n_v, rays_per_beam=cfg.rays_per_beam,
+                        grid_mode=cfg.grid_mode, jitter=cfg.jitter, n_range=cfg.n_range, r_min=cfg.r_min,
+                        r_max=cfg.r_max, freq_hz=cfg.freq_hz, c0=cfg.c0, c_grad=cfg.c_grad,
+                        abs_db_per_m=cfg.abs_db_per_m, max_bounces=cfg.max_bounces, pad0=0, k_d=cfg.k_d,
+                        k_s=cfg.k_s, phong_n=cfg.phong_n, seed=cfg.seed, flags=cfg.flags, pad1=0)
+
+
+def pose_of(pose) -> sonar_pose:
+    q = sonar_pose()
+    for i in range(3):
+        q.position[i] = pose.position[i]
+    for i in range(9):
+        q.rot[i] = pose.rot[i]
+    q.ping = pose.ping
+    return q
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Scene:
+    """A built scene (owns the library handle)."""
+
+    def __init__(self, mesh, leaf_size: int = 4, stream=None, device_inputs: bool = False):
+        import torch
+        self._h = C.c_void_p()
+        keep = []
+        if device_inputs:
+            arrs = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in
+                    (mesh.vertices, mesh.indices, mesh.reflectivity, mesh.phase, mesh.material)]
+            keep = arrs
+            ptrs = [a.data_ptr() for a in arrs]
+        else:
+            arrs = [np.ascontiguousarray(a) for a in
+                    (mesh.vertices.astype(np.float32), mesh.indices.astype(np.int32),
+                     mesh.reflectivity.astype(np.float32), mesh.phase.astype(np.float32),
+                     mesh.material.astype(np.uint8))]
+            keep = arrs
+            ptrs = [a.ctypes.data for a in arrs]
+        m = sonar_mesh(vertices=ptrs[0], indices=ptrs[1], reflectivity=ptrs[2], phase=ptrs[3], material=ptrs[4],
+                       n_vertices=int(mesh.vertices.shape[0]), n_triangles=int(mesh.indices.shape[0]),
+                       on_device=1 if device_inputs else 0, leaf_size=leaf_size)
+        _check(lib().sonar_build_scene(C.byref(m), _stream(stream), C.byref(self._h)))
+        del keep
+
+    def info(self) -> dict:
+        i = sonar_scene_info()
+        _check(lib().sonar_get_scene_info(self._h, C.byref(i)))
+        return dict(n_triangles=i.n_triangles, n_nodes=i.n_nodes, depth=i.depth, leaf_size=i.leaf_size,
+                    lo=list(i.lo), hi=list(i.hi), node_bytes=i.node_bytes, tri_bytes=i.tri_bytes)
+
+    def status(self, stream=None) -> int:
+        return lib().sonar_device_status(self._h, _stream(stream))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sonar_free_scene(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def beams_of(cfg):
+    return (cfg.n_v + 1, cfg.n_h + 1) if cfg.grid_mode == 1 else (cfg.n_v, cfg.n_h)
+
+
+def alloc_outputs(cfg, gbuffer=False, incoh=False, record=False, device="cuda"):
+    import torch
+    bv, bh = beams_of(cfg)
+    out = dict(volume=torch.empty((bv, bh, cfg.n_range), dtype=torch.complex64, device=device))
+    if gbuffer:
+        out["gbuffer"] = torch.empty((bv, bh, 8), dtype=torch.float32, device=device)
+    if incoh:
+        out["incoh"] = torch.empty((2, bv, bh, cfg.n_range), dtype=torch.float32, device=device)
+    if record:
+        n = bv * bh * cfg.rays_per_beam
+        K = cfg.max_bounces
+        out["tri"] = torch.empty((n, K), dtype=torch.int32, device=device)
+        out["bin"] = torch.empty((n, K), dtype=torch.int32, device=device)
+        out["vis"] = torch.empty((n, K), dtype=torch.int32, device=device)
+        out["amp"] = torch.empty((n, K), dtype=torch.complex64, device=device)
+    return out
+
+
+def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=False, ray_mask=None, stream=None,
+         params=None, pose_s=None):
+    """One ping; returns the dict of output tensors (allocated if ``out`` is None)."""
+    if out is None:
+        out = alloc_outputs(cfg, gbuffer, incoh, record)
+    rec = None
+    if "tri" in out:
+        rec = sonar_ray_record(tri=out["tri"].data_ptr(), bin=out["bin"].data_ptr(), vis=out["vis"].data_ptr(),
+                               amp=out["amp"].data_ptr())
+    p = params if params is not None else params_of(cfg)
+    q = pose_s if pose_s is not None else pose_of(pose)
+    _check(lib().sonar_ping(scene.handle, C.byref(p), C.byref(q), _dptr(out["volume"]), _dptr(out.get("gbuffer")),
+                            _dptr(out.get("incoh")), C.byref(rec) if rec is not None else None, _dptr(ray_mask),
+                            _stream(stream)))
+    return out
+
+
+class Detector:
+    """CFAR detection with a preallocated workspace, points buffer and count."""
+
+    def __init__(self, cfg, train=16, guard=4, max_per_beam=4, pfa=1e-4, noise_floor=1e-11, capacity=None):
+        import torch
+        self.cfg = cfg
+        self.params = params_of(cfg)
+        self.cfar = sonar_cfar(train=train, guard=guard, max_per_beam=max_per_beam, pad=0, pfa=pfa,
+                               noise_floor=noise_floor)
+        bv, bh = beams_of(cfg)
+        self.capacity = capacity if capacity is not None else bv * bh * max_per_beam
+        nbytes = lib().sonar_detect_workspace_size(C.byref(self.params))
+        if nbytes == 0:
+            _check(SONAR_E_INVALID)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.points = torch.empty((max(self.capacity, 1), 6), dtype=torch.int32, device="cuda")
+        self.count = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def __call__(self, volume, pose, stream=None, pose_s=None):
+        q = pose_s if pose_s is not None else pose_of(pose)
+        st = lib().sonar_detect(_dptr(volume), C.byref(self.params), C.byref(q), C.byref(self.cfar),
+                                _dptr(self.points), self.capacity, _dptr(self.count), _dptr(self.workspace),
+                                self.workspace.numel(), _stream(stream))
+        _check(st)
+        return self.points, self.count
+
+    def fetch(self):
+        """Host copy of the detections as a structured array (synchronises)."""
+        n = int(self.count.item())
+        n = min(n, self.capacity)
+        raw = self.points[:n].cpu().numpy()
+        return raw.view(POINT_DTYPE).reshape(-1), int(self.count.item())
+
+
+def params_from_resolution(hfov, vfov, dth_h, dth_v, r_min, r_max, dr, base=None) -> sonar_params:
+    p = base if base is not None else sonar_params()
+    _check(lib().sonar_params_from_resolution(hfov, vfov, dth_h, dth_v, r_min, r_max, dr, C.byref(p)))
+    return p

@@ -1,0 +1,56 @@
+"""Helpers that compare the HIP path with the oracle (test infrastructure)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+
+def mask_words(n_rays: int, flagged_rays) -> np.ndarray:
+    """uint32 bit mask over rays with the given ray indices set."""
+    w = np.zeros((n_rays + 31) // 32, np.uint32)
+    fr = np.asarray(flagged_rays, np.int64)
+    np.bitwise_or.at(w, fr >> 5, (np.uint32(1) << (fr & 31).astype(np.uint32)))
+    return w
+
+
+def ray_ids(beams, n_r):
+    beams = np.asarray(beams, np.int64)
+    return (beams[:, None] * n_r + np.arange(n_r)[None, :]).reshape(-1)
+
+
+def flag_summary(flags) -> dict:
+    flags = np.asarray(flags)
+    out = {"rays": int(flags.size), "flagged": int((flags != 0).sum())}
+    for i, nm in enumerate(oracle.FLAG_NAMES):
+        c = int(((flags >> i) & 1).sum())
+        if c:
+            out[nm] = c
+    return out
+
+
+def compare_rays(gpu: dict, orc: dict, rays) -> dict:
+    """Bit-exact comparison of hit triangle, bin and visibility on the
+    oracle's unflagged rays. ``gpu`` arrays are indexed by global ray id,
+    ``orc`` arrays by position in ``rays``."""
+    ok = orc["flags"] == 0
+    res = {}
+    for key in ("tri", "bin", "vis"):
+        g = np.asarray(gpu[key])[rays][ok]
+        o = np.asarray(orc[key])[ok]
+        if key == "vis":
+            # visibility is only defined where there was a hit
+            g = np.where(np.asarray(orc["tri"])[ok] >= 0, g, 0)
+            o = np.where(np.asarray(orc["tri"])[ok] >= 0, o, 0)
+        res[key + "_mismatch"] = int((g != o).any(axis=1).sum())
+    res.update(flag_summary(orc["flags"]))
+    return res
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        return float(np.linalg.norm(a))
+    return float(np.linalg.norm(a - b) / nb)

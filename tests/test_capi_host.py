@@ -1,0 +1,103 @@
+"""The C-ABI library loads, exports every declared symbol and validates its
+arguments on the host (no GPU needed: nothing here launches a kernel)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_2606_06130_amd import scenes as S
+from paper_2606_06130_amd import sonar
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "sonar.h")).read()
+    return sorted(set(re.findall(r"\b(sonar_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(sonar.LIB_PATH):
+        pytest.skip("libsonar.so not built")
+    return sonar.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(sonar.EXPORTS) == names
+
+
+def test_status_strings(L):
+    for st in (0, 1, -1, -2, -3, -4, -5):
+        assert L.sonar_status_string(st)
+    assert L.sonar_status_string(99) == b"unknown status"
+
+
+def test_params_from_resolution_eq1_3(L):
+    p = sonar.params_from_resolution(math.radians(90), math.radians(40), math.radians(1.40625), math.radians(1.25),
+                                     0.3, 15.0, 14.7 / 256)
+    assert (p.n_h, p.n_v, p.n_range) == (64, 32, 256)
+    with pytest.raises(sonar.SonarError):
+        sonar.params_from_resolution(math.radians(90), math.radians(40), 0.0, 1.0, 0.3, 15.0, 0.1)
+
+
+def test_ping_rejects_null_scene(L):
+    p = sonar.params_of(S.sensor_seabed_boxes())
+    q = sonar.pose_of(S.pose_seabed_boxes())
+    st = L.sonar_ping(None, C.byref(p), C.byref(q), C.c_void_p(16), None, None, None, None, None)
+    assert st == sonar.SONAR_E_INVALID
+    assert b"scene" in L.sonar_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("n_h", 0), ("rays_per_beam", 3), ("rays_per_beam", 128),
+                                         ("n_range", 0), ("n_range", 5000), ("max_bounces", 0),
+                                         ("max_bounces", 5), ("r_max", 0.1), ("hfov", 0.0), ("c0", -1.0),
+                                         ("grid_mode", 2), ("k_s", -0.5)])
+def test_detect_validates_params_before_launch(L, field, value):
+    cfg = S.sensor_seabed_boxes()
+    p = sonar.params_of(cfg)
+    setattr(p, field, value)
+    q = sonar.pose_of(S.pose_seabed_boxes())
+    c = sonar.sonar_cfar(train=16, guard=4, max_per_beam=4, pad=0, pfa=1e-4, noise_floor=1e-11)
+    st = L.sonar_detect(C.c_void_p(16), C.byref(p), C.byref(q), C.byref(c), C.c_void_p(16), 10, C.c_void_p(16),
+                        C.c_void_p(16), 1 << 30, None)
+    assert st == sonar.SONAR_E_INVALID
+    assert L.sonar_detect_workspace_size(C.byref(p)) == 0
+
+
+def test_detect_validates_cfar_and_pose(L):
+    cfg = S.sensor_seabed_boxes()
+    p = sonar.params_of(cfg)
+    q = sonar.pose_of(S.pose_seabed_boxes())
+    ws = L.sonar_detect_workspace_size(C.byref(p))
+    assert ws >= cfg.n_beams * 4 * 2
+    for kw in (dict(max_per_beam=0), dict(max_per_beam=17), dict(pfa=0.0), dict(pfa=1.0), dict(train=0)):
+        args = dict(train=16, guard=4, max_per_beam=4, pad=0, pfa=1e-4, noise_floor=1e-11)
+        args.update(kw)
+        c = sonar.sonar_cfar(**args)
+        st = L.sonar_detect(C.c_void_p(16), C.byref(p), C.byref(q), C.byref(c), C.c_void_p(16), 10, C.c_void_p(16),
+                            C.c_void_p(16), ws, None)
+        assert st == sonar.SONAR_E_INVALID, kw
+    c = sonar.sonar_cfar(train=16, guard=4, max_per_beam=4, pad=0, pfa=1e-4, noise_floor=1e-11)
+    st = L.sonar_detect(C.c_void_p(16), C.byref(p), C.byref(q), C.byref(c), C.c_void_p(16), 10, C.c_void_p(16),
+                        C.c_void_p(16), ws - 1, None)
+    assert st == sonar.SONAR_E_INVALID and b"workspace" in L.sonar_last_error()
+    bad = sonar.pose_of(S.pose_seabed_boxes())
+    bad.rot[0] = 2.0
+    st = L.sonar_detect(C.c_void_p(16), C.byref(p), C.byref(bad), C.byref(c), C.c_void_p(16), 10, C.c_void_p(16),
+                        C.c_void_p(16), ws, None)
+    assert st == sonar.SONAR_E_INVALID and b"orthonormal" in L.sonar_last_error()
+
+
+def test_build_rejects_null_mesh(L):
+    out = C.c_void_p()
+    assert L.sonar_build_scene(None, None, C.byref(out)) == sonar.SONAR_E_INVALID
+    m = sonar.sonar_mesh()
+    assert L.sonar_build_scene(C.byref(m), None, C.byref(out)) == sonar.SONAR_E_INVALID
+    assert out.value is None
