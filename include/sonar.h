@@ -203,6 +203,18 @@ sonar_status sonar_detect(const sonar_cf32 *volume, const sonar_params *params, 
                           const sonar_cfar *cfar, sonar_point *points, int32_t capacity, int32_t *dev_count,
                           void *workspace, size_t workspace_bytes, sonar_stream stream);
 
+/* One ping followed by detection, as sonar_ping then sonar_detect, with the
+ * CFAR test evaluated inside the ping kernel while each beam's column is
+ * still indexed on chip, so the volume is written once and never re-read.
+ * Outputs and workspace as for sonar_ping (volume) and sonar_detect (points,
+ * dev_count, workspace). Points are identical to sonar_detect's on the same
+ * volume up to FP64 rounding of the training sums. When some alpha(N) <= 1
+ * (pfa above about 0.37) a bin without a return could be detected; the call
+ * then runs the two stages separately. Asynchronous on `stream`. */
+sonar_status sonar_ping_detect(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
+                               const sonar_cfar *cfar, sonar_cf32 *volume, sonar_point *points, int32_t capacity,
+                               int32_t *dev_count, void *workspace, size_t workspace_bytes, sonar_stream stream);
+
 /* Synchronises `stream` and reports device-side errors recorded by calls
  * that used `scene` (SONAR_E_STACK if a traversal ran out of stack). Clears
  * the record. */

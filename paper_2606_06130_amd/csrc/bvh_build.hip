@@ -280,13 +280,13 @@ __global__ void k_karras(const uint64_t *__restrict__ k, int64_t n, int32_t *__r
     parent[cr] = (int32_t)i;
 }
 
-// K5: bounds bottom-up. The second child to arrive at a node merges both boxes;
-// the first one stops. Each thread also measures its leaf's depth.
+// K5: bounds bottom-up. The second child to arrive at a node merges both boxes
+// and the node height; the first one stops. The root's height is the depth.
 __global__ void k_refit(const uint32_t *__restrict__ order, int64_t n, const float4 *__restrict__ blo_tri,
                         const float4 *__restrict__ bhi_tri, const int32_t *__restrict__ left,
                         const int32_t *__restrict__ right, const int32_t *__restrict__ parent,
                         float4 *__restrict__ blo, float4 *__restrict__ bhi, int32_t *__restrict__ arrive,
-                        int32_t *__restrict__ depth_out)
+                        int32_t *__restrict__ height, int32_t *__restrict__ depth_out)
 {
     int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= n) return;
@@ -294,12 +294,7 @@ __global__ void k_refit(const uint32_t *__restrict__ order, int64_t n, const flo
     uint32_t tri = order[i];
     blo[leaf] = blo_tri[tri];
     bhi[leaf] = bhi_tri[tri];
-    int depth = 0;
-    for (int64_t c = leaf; c != 0 && depth < MAX_WALK;) {
-        c = parent[c];
-        ++depth;
-    }
-    atomicMax(depth_out, depth);
+    height[leaf] = 0;
     if (n == 1) return;
     __threadfence();
     int64_t p = parent[leaf];
@@ -313,8 +308,12 @@ __global__ void k_refit(const uint32_t *__restrict__ order, int64_t n, const flo
         float4 lb = blo[b], hb = bhi[b];
         blo[p] = make_float4(fminf(la.x, lb.x), fminf(la.y, lb.y), fminf(la.z, lb.z), 0.f);
         bhi[p] = make_float4(fmaxf(ha.x, hb.x), fmaxf(ha.y, hb.y), fmaxf(ha.z, hb.z), 0.f);
+        height[p] = max(height[a], height[b]) + 1;
         __threadfence();
-        if (p == 0) return;
+        if (p == 0) {
+            *depth_out = height[0];    // longest root-to-leaf path
+            return;
+        }
         p = parent[p];
     }
 }
@@ -447,7 +446,7 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     }
     const int64_t n_int = n > 1 ? n - 1 : 1;
     const int64_t n_all = 2 * n - 1;
-    DevBuf rec, cen, tlo, thi, red, k0, k1, v0, v1, hist, lft, rgt, rlo, rhi, par, blo, bhi, arr, dep;
+    DevBuf rec, cen, tlo, thi, red, k0, k1, v0, v1, hist, lft, rgt, rlo, rhi, par, blo, bhi, arr, dep, hgt;
     int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
     BCHECK(hipMalloc(&rec.p, sizeof(float4) * 3 * n));
     BCHECK(hipMalloc(&cen.p, sizeof(float4) * n));
@@ -468,6 +467,7 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     BCHECK(hipMalloc(&bhi.p, sizeof(float4) * n_all));
     BCHECK(hipMalloc(&arr.p, sizeof(int32_t) * n_int));
     BCHECK(hipMalloc(&dep.p, sizeof(int32_t)));
+    BCHECK(hipMalloc(&hgt.p, sizeof(int32_t) * n_all));
 
     float4 *nodes = nullptr, *tris = nullptr;
     int *status = nullptr;
@@ -508,7 +508,7 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     }
     k_refit<<<nblk(n), BT, 0, s>>>(va, n, (const float4 *)tlo.p, (const float4 *)thi.p, (const int32_t *)lft.p,
                                    (const int32_t *)rgt.p, (const int32_t *)par.p, (float4 *)blo.p,
-                                   (float4 *)bhi.p, (int32_t *)arr.p, (int32_t *)dep.p);
+                                   (float4 *)bhi.p, (int32_t *)arr.p, (int32_t *)hgt.p, (int32_t *)dep.p);
     if (n > 1) {
         k_pack<<<nblk(n - 1), BT, 0, s>>>(n, (const int32_t *)lft.p, (const int32_t *)rgt.p,
                                           (const int32_t *)rlo.p, (const int32_t *)rhi.p, (const float4 *)blo.p,

@@ -94,6 +94,123 @@ sonar_status check_pose(const sonar_pose *q)
 int beams_h_of(const sonar_params *p) { return p->grid_mode == 1 ? p->n_h + 1 : p->n_h; }
 int beams_v_of(const sonar_params *p) { return p->grid_mode == 1 ? p->n_v + 1 : p->n_v; }
 
+sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, sonar_cf32 *volume,
+                            float *gbuffer, float *incoh, const sonar_ray_record *rec, const uint32_t *ray_mask,
+                            sonar::PingArgs *out)
+{
+    if (!sc) return fail(SONAR_E_INVALID, "scene is NULL");
+    sonar_status st = check_params(p);
+    if (st != SONAR_OK) return st;
+    if ((st = check_pose(q)) != SONAR_OK) return st;
+    if (!volume) return fail(SONAR_E_INVALID, "volume is NULL");
+    if (rec && (!rec->tri || !rec->bin || !rec->vis || !rec->amp))
+        return fail(SONAR_E_INVALID, "record arrays must all be set");
+    if (p->c_grad != 0.0) return fail(SONAR_E_UNSUPPORTED, "curved rays (c_grad != 0) are not in this build");
+    if (sc->s.depth > 64)
+        return fail(SONAR_E_STACK, "hierarchy depth %d exceeds the 64-entry traversal stack", sc->s.depth);
+    sonar::PingArgs &a = *out;
+    memset(&a, 0, sizeof(a));
+    a.nodes = sc->s.nodes;
+    a.tris = sc->s.tris;
+    a.status = sc->s.status;
+    for (int i = 0; i < 3; ++i) a.pos[i] = q->position[i];
+    for (int i = 0; i < 9; ++i) a.rot[i] = q->rot[i];
+    a.hfov = p->hfov;
+    a.vfov = p->vfov;
+    a.dth_h = p->hfov / p->n_h;
+    a.dth_v = p->vfov / p->n_v;
+    a.r_min = p->r_min;
+    a.r_max = p->r_max;
+    a.dr = (p->r_max - p->r_min) / p->n_range;
+    a.f0 = p->freq_hz;
+    a.c0 = p->c0;
+    a.g = p->c_grad;
+    a.alpha_db = p->abs_db_per_m;
+    a.k_d = p->k_d;
+    a.k_s = p->k_s;
+    a.phong_n = p->phong_n;
+    a.c_ref = p->c0 + p->c_grad * q->position[2];
+    a.c_hi = p->c0 + fabs(p->c_grad) * (fmax((double)sc->s.zabs_max, fabs(q->position[2])) + 1.0);
+    a.seed = p->seed;
+    a.ping = q->ping;
+    a.beams_h = beams_h_of(p);
+    a.beams_v = beams_v_of(p);
+    a.n_beams = a.beams_h * a.beams_v;
+    a.n_r = p->rays_per_beam;
+    a.log2_nr = ilog2(p->rays_per_beam);
+    a.ne = 1 << (a.log2_nr / 2);
+    a.na = a.n_r / a.ne;
+    a.grid_mode = p->grid_mode;
+    a.jitter = p->jitter;
+    a.n_bins = p->n_range;
+    a.K = p->max_bounces;
+    a.n_rays = (int64_t)a.n_beams * a.n_r;
+    a.volume = reinterpret_cast<float2 *>(volume);
+    a.gbuf = gbuffer;
+    a.incoh = incoh;
+    if (rec) {
+        a.rec_tri = rec->tri;
+        a.rec_bin = rec->bin;
+        a.rec_vis = rec->vis;
+        a.rec_amp = reinterpret_cast<float2 *>(rec->amp);
+    }
+    a.mask = ray_mask;
+    a.max_steps = (uint32_t)(2 * sc->s.n_nodes + 64);
+    return SONAR_OK;
+}
+
+sonar_status fill_detect_args(const sonar_cf32 *volume, const sonar_params *p, const sonar_pose *q,
+                              const sonar_cfar *c, sonar_point *points, int32_t capacity, int32_t *dev_count,
+                              void *workspace, size_t ws_bytes, sonar::DetectArgs *out)
+{
+    sonar_status st = check_params(p);
+    if (st != SONAR_OK) return st;
+    if ((st = check_pose(q)) != SONAR_OK) return st;
+    if (!volume || !dev_count || !workspace) return fail(SONAR_E_INVALID, "volume, dev_count and workspace are required");
+    if (!c) return fail(SONAR_E_INVALID, "cfar is NULL");
+    if (c->train < 1 || c->guard < 0 || c->train > 64 || c->guard > 64)
+        return fail(SONAR_E_INVALID, "train must be in [1, 64] and guard in [0, 64]");
+    if (c->max_per_beam < 1 || c->max_per_beam > 16) return fail(SONAR_E_INVALID, "max_per_beam must be in [1, 16]");
+    if (!(c->pfa > 0 && c->pfa < 1)) return fail(SONAR_E_INVALID, "pfa must be in (0, 1)");
+    if (!(c->noise_floor >= 0) || !isfinite(c->noise_floor)) return fail(SONAR_E_INVALID, "noise_floor must be >= 0");
+    if (capacity < 0 || (capacity > 0 && !points)) return fail(SONAR_E_INVALID, "points required when capacity > 0");
+    int nb = beams_h_of(p) * beams_v_of(p);
+    if (ws_bytes < sonar::detect_workspace_bytes(nb, 16))
+        return fail(SONAR_E_INVALID, "workspace smaller than sonar_detect_workspace_size()");
+    sonar::DetectArgs &a = *out;
+    memset(&a, 0, sizeof(a));
+    a.volume = reinterpret_cast<const float2 *>(volume);
+    a.points = points;
+    a.count = dev_count;
+    char *w = (char *)workspace;
+    size_t nb4 = ((size_t)nb + 3) & ~(size_t)3;
+    a.beam_count = (int32_t *)w;
+    a.beam_bins = (int32_t *)(w + sizeof(int32_t) * nb4);
+    a.beam_pw = (float *)(w + sizeof(int32_t) * nb4 + sizeof(int32_t) * (size_t)nb * 16);
+    // alpha(N) = N (pfa^(-1/N) - 1): the CA-CFAR scale for N exponential training cells
+    a.alpha[0] = 0.0;
+    for (int n = 1; n <= 2 * 64; ++n) a.alpha[n] = n * (pow(c->pfa, -1.0 / n) - 1.0);
+    a.n_beams = nb;
+    a.n_bins = p->n_range;
+    a.beams_h = beams_h_of(p);
+    a.grid_mode = p->grid_mode;
+    a.train = c->train;
+    a.guard = c->guard;
+    a.max_per_beam = c->max_per_beam;
+    a.capacity = capacity;
+    a.pfa = c->pfa;
+    a.noise_floor = c->noise_floor;
+    a.hfov = p->hfov;
+    a.vfov = p->vfov;
+    a.dth_h = p->hfov / p->n_h;
+    a.dth_v = p->vfov / p->n_v;
+    a.r_min = p->r_min;
+    a.dr = (p->r_max - p->r_min) / p->n_range;
+    for (int i = 0; i < 3; ++i) a.pos[i] = q->position[i];
+    for (int i = 0; i < 9; ++i) a.rot[i] = q->rot[i];
+    return SONAR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -195,64 +312,9 @@ sonar_status sonar_ping(const sonar_scene *sc, const sonar_params *p, const sona
                         sonar_stream stream)
 {
     g_err[0] = 0;
-    if (!sc) return fail(SONAR_E_INVALID, "scene is NULL");
-    sonar_status st = check_params(p);
-    if (st != SONAR_OK) return st;
-    if ((st = check_pose(q)) != SONAR_OK) return st;
-    if (!volume) return fail(SONAR_E_INVALID, "volume is NULL");
-    if (rec && (!rec->tri || !rec->bin || !rec->vis || !rec->amp))
-        return fail(SONAR_E_INVALID, "record arrays must all be set");
-    if (p->c_grad != 0.0) return fail(SONAR_E_UNSUPPORTED, "curved rays (c_grad != 0) are not in this build");
-    if (sc->s.depth > 64)
-        return fail(SONAR_E_STACK, "hierarchy depth %d exceeds the 64-entry traversal stack", sc->s.depth);
     sonar::PingArgs a;
-    memset(&a, 0, sizeof(a));
-    a.nodes = sc->s.nodes;
-    a.tris = sc->s.tris;
-    a.status = sc->s.status;
-    for (int i = 0; i < 3; ++i) a.pos[i] = q->position[i];
-    for (int i = 0; i < 9; ++i) a.rot[i] = q->rot[i];
-    a.hfov = p->hfov;
-    a.vfov = p->vfov;
-    a.dth_h = p->hfov / p->n_h;
-    a.dth_v = p->vfov / p->n_v;
-    a.r_min = p->r_min;
-    a.r_max = p->r_max;
-    a.dr = (p->r_max - p->r_min) / p->n_range;
-    a.f0 = p->freq_hz;
-    a.c0 = p->c0;
-    a.g = p->c_grad;
-    a.alpha_db = p->abs_db_per_m;
-    a.k_d = p->k_d;
-    a.k_s = p->k_s;
-    a.phong_n = p->phong_n;
-    a.c_ref = p->c0 + p->c_grad * q->position[2];
-    a.c_hi = p->c0 + fabs(p->c_grad) * (fmax((double)sc->s.zabs_max, fabs(q->position[2])) + 1.0);
-    a.seed = p->seed;
-    a.ping = q->ping;
-    a.beams_h = beams_h_of(p);
-    a.beams_v = beams_v_of(p);
-    a.n_beams = a.beams_h * a.beams_v;
-    a.n_r = p->rays_per_beam;
-    a.log2_nr = ilog2(p->rays_per_beam);
-    a.ne = 1 << (a.log2_nr / 2);
-    a.na = a.n_r / a.ne;
-    a.grid_mode = p->grid_mode;
-    a.jitter = p->jitter;
-    a.n_bins = p->n_range;
-    a.K = p->max_bounces;
-    a.n_rays = (int64_t)a.n_beams * a.n_r;
-    a.volume = reinterpret_cast<float2 *>(volume);
-    a.gbuf = gbuffer;
-    a.incoh = incoh;
-    if (rec) {
-        a.rec_tri = rec->tri;
-        a.rec_bin = rec->bin;
-        a.rec_vis = rec->vis;
-        a.rec_amp = reinterpret_cast<float2 *>(rec->amp);
-    }
-    a.mask = ray_mask;
-    a.max_steps = (uint32_t)(2 * sc->s.n_nodes + 64);
+    sonar_status st = fill_ping_args(sc, p, q, volume, gbuffer, incoh, rec, ray_mask, &a);
+    if (st != SONAR_OK) return st;
     hipError_t e = sonar::launch_ping(a, sc->s.depth, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping launch: %s", hipGetErrorString(e));
     return SONAR_OK;
@@ -269,50 +331,48 @@ sonar_status sonar_detect(const sonar_cf32 *volume, const sonar_params *p, const
                           void *workspace, size_t ws_bytes, sonar_stream stream)
 {
     g_err[0] = 0;
-    sonar_status st = check_params(p);
-    if (st != SONAR_OK) return st;
-    if ((st = check_pose(q)) != SONAR_OK) return st;
-    if (!volume || !dev_count || !workspace) return fail(SONAR_E_INVALID, "volume, dev_count and workspace are required");
-    if (!c) return fail(SONAR_E_INVALID, "cfar is NULL");
-    if (c->train < 1 || c->guard < 0 || c->train > 64 || c->guard > 64)
-        return fail(SONAR_E_INVALID, "train must be in [1, 64] and guard in [0, 64]");
-    if (c->max_per_beam < 1 || c->max_per_beam > 16) return fail(SONAR_E_INVALID, "max_per_beam must be in [1, 16]");
-    if (!(c->pfa > 0 && c->pfa < 1)) return fail(SONAR_E_INVALID, "pfa must be in (0, 1)");
-    if (!(c->noise_floor >= 0) || !isfinite(c->noise_floor)) return fail(SONAR_E_INVALID, "noise_floor must be >= 0");
-    if (capacity < 0 || (capacity > 0 && !points)) return fail(SONAR_E_INVALID, "points required when capacity > 0");
-    int nb = beams_h_of(p) * beams_v_of(p);
-    if (ws_bytes < sonar::detect_workspace_bytes(nb, 16))
-        return fail(SONAR_E_INVALID, "workspace smaller than sonar_detect_workspace_size()");
     sonar::DetectArgs a;
-    memset(&a, 0, sizeof(a));
-    a.volume = reinterpret_cast<const float2 *>(volume);
-    a.points = points;
-    a.count = dev_count;
-    char *w = (char *)workspace;
-    a.beam_count = (int32_t *)w;
-    a.block_sums = (int32_t *)(w + sizeof(int32_t) * nb);
-    a.beam_bins = (int32_t *)(w + 2 * sizeof(int32_t) * nb);
-    a.beam_pw = (float *)(w + 2 * sizeof(int32_t) * nb + sizeof(int32_t) * (size_t)nb * 16);
-    a.n_beams = nb;
-    a.n_bins = p->n_range;
-    a.beams_h = beams_h_of(p);
-    a.grid_mode = p->grid_mode;
-    a.train = c->train;
-    a.guard = c->guard;
-    a.max_per_beam = c->max_per_beam;
-    a.capacity = capacity;
-    a.pfa = c->pfa;
-    a.noise_floor = c->noise_floor;
-    a.hfov = p->hfov;
-    a.vfov = p->vfov;
-    a.dth_h = p->hfov / p->n_h;
-    a.dth_v = p->vfov / p->n_v;
-    a.r_min = p->r_min;
-    a.dr = (p->r_max - p->r_min) / p->n_range;
-    for (int i = 0; i < 3; ++i) a.pos[i] = q->position[i];
-    for (int i = 0; i < 9; ++i) a.rot[i] = q->rot[i];
+    sonar_status st = fill_detect_args(volume, p, q, c, points, capacity, dev_count, workspace, ws_bytes, &a);
+    if (st != SONAR_OK) return st;
     hipError_t e = sonar::launch_detect(a, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "detect launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
+sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q,
+                               const sonar_cfar *c, sonar_cf32 *volume, sonar_point *points, int32_t capacity,
+                               int32_t *dev_count, void *workspace, size_t ws_bytes, sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar::PingArgs pa;
+    sonar_status st = fill_ping_args(sc, p, q, volume, nullptr, nullptr, nullptr, nullptr, &pa);
+    if (st != SONAR_OK) return st;
+    sonar::DetectArgs da;
+    st = fill_detect_args(volume, p, q, c, points, capacity, dev_count, workspace, ws_bytes, &da);
+    if (st != SONAR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // the fused test needs alpha(N) > 1 for every window size, so that a bin
+    // without a return can never be detected
+    bool fused = true;
+    for (int n = 1; n <= 2 * c->train; ++n)
+        if (!(da.alpha[n] > 1.0)) fused = false;
+    hipError_t e;
+    if (fused) {
+        pa.det_count = da.beam_count;
+        pa.det_bins = da.beam_bins;
+        pa.det_pw = da.beam_pw;
+        pa.det_G = c->guard;
+        pa.det_T = c->train;
+        pa.det_M = c->max_per_beam;
+        pa.det_n0 = (float)c->noise_floor;
+        for (int n = 0; n <= 2 * 64; ++n) pa.det_alpha[n] = da.alpha[n];
+        e = sonar::launch_ping(pa, sc->s.depth, s);
+        if (e == hipSuccess) e = sonar::launch_emit(da, s);
+    } else {
+        e = sonar::launch_ping(pa, sc->s.depth, s);
+        if (e == hipSuccess) e = sonar::launch_detect(da, s);
+    }
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping/detect launch: %s", hipGetErrorString(e));
     return SONAR_OK;
 }
 

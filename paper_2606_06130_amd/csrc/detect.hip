@@ -5,9 +5,13 @@
 // `max_per_beam` cells per beam, then a deterministic (beam, range) ordering
 // through an exclusive scan of the per-beam counts.
 //
-// One wavefront per beam: the column is read once with coalesced loads, the
-// powers live in LDS and the training sums come from an FP64 prefix sum, so
-// no window is re-read from HBM.
+// k_cfar: one 256-thread block per beam. The column is read once with
+// coalesced 16-byte loads, powers go to LDS, an FP64 block prefix sum gives
+// every training window in four LDS reads, and alpha(N) comes from a table
+// built on the host. HBM traffic: the volume, once.
+// k_emit: one thread per beam, 256 beams per block; the block's offset is the
+// sum of all earlier counts (read from L2), then a block scan places its
+// points in (beam, range) order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -17,8 +21,9 @@ namespace sonar {
 
 namespace {
 
-constexpr int WAVE = 64;
-constexpr int SCAN_THREADS = 1024;
+constexpr int CT = 256;                 // k_cfar threads
+constexpr int CW = CT / 64;             // k_cfar waves
+constexpr int ET = 256;                 // k_emit threads = beams per k_emit block
 
 __device__ __forceinline__ uint64_t pack_key(float p, int r)
 {
@@ -26,139 +31,189 @@ __device__ __forceinline__ uint64_t pack_key(float p, int r)
     return ((uint64_t)__float_as_uint(p) << 32) | (uint32_t)(~r);
 }
 
+// Inclusive block scan (FP64) of one value per thread.
+__device__ __forceinline__ double block_scan_incl(double v, double *wsum)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        double o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    double add = 0.0;
+    for (int q = 0; q < w; ++q) add += wsum[q];
+    return v + add;
+}
+
+__device__ __forceinline__ int block_scan_excl_int(int v, int *wsum, int *total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int o = __shfl_up(x, off);
+        if (lane >= off) x += o;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int add = 0, tot = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+        if (q < w) add += wsum[q];
+        tot += wsum[q];
+    }
+    *total = tot;
+    return x - v + add;
+}
+
 }  // namespace
 
-__global__ __launch_bounds__(WAVE) void k_cfar(DetectArgs a)
+__global__ __launch_bounds__(CT) void k_cfar(DetectArgs a)
 {
     extern __shared__ double sh[];
+    __shared__ double wsum[CW];
+    __shared__ uint64_t wtop[CW][16];
     const int nb = a.n_bins;
-    double *pre = sh;                                   // [nb + 1] prefix sums
-    float *pw = reinterpret_cast<float *>(sh + nb + 1); // [nb] powers
-    const int lane = threadIdx.x;
+    double *pre = sh;                                    // [nb + 1]
+    float *pw = reinterpret_cast<float *>(sh + nb + 1);   // [nb]
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int beam = blockIdx.x;
     const float2 *col = a.volume + (size_t)beam * nb;
     const float n0 = (float)a.noise_floor;
 
-    // chunk of contiguous bins per lane for the prefix sum
-    const int chunk = (nb + WAVE - 1) / WAVE;
-    for (int r = lane; r < nb; r += WAVE) {
-        float2 e = col[r];
-        pw[r] = e.x * e.x + e.y * e.y + n0;
+    // coalesced load: 2 bins per 16-byte load when the column is 16-byte aligned
+    if ((nb & 1) == 0) {
+        const float4 *c4 = reinterpret_cast<const float4 *>(col);
+        for (int i = t; i < nb / 2; i += CT) {
+            float4 e = c4[i];
+            pw[2 * i] = e.x * e.x + e.y * e.y + n0;
+            pw[2 * i + 1] = e.z * e.z + e.w * e.w + n0;
+        }
+    } else {
+        for (int r = t; r < nb; r += CT) {
+            float2 e = col[r];
+            pw[r] = e.x * e.x + e.y * e.y + n0;
+        }
     }
     __syncthreads();
-    int c0 = lane * chunk, c1 = min(c0 + chunk, nb);
+    // FP64 prefix sum: thread t owns a contiguous chunk
+    const int chunk = (nb + CT - 1) / CT;
+    const int c0 = min(t * chunk, nb), c1 = min(c0 + chunk, nb);
     double run = 0.0;
     for (int r = c0; r < c1; ++r) run += (double)pw[r];
-    // inclusive scan of chunk totals across the wave
-    double incl = run;
-    for (int off = 1; off < WAVE; off <<= 1) {
-        double v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
-    }
+    double incl = block_scan_incl(run, wsum);
     double acc = incl - run;
     for (int r = c0; r < c1; ++r) {
         pre[r] = acc;
         acc += (double)pw[r];
     }
-    if (lane == WAVE - 1) pre[nb] = incl;
+    if (t == CT - 1) pre[nb] = incl;
     __syncthreads();
 
-    // detections of this lane's bins (r = lane + 64 i), best key per lane kept in order
+    // detections of this thread's bins, its M largest keys kept in order
     const int G = a.guard, T = a.train, M = a.max_per_beam;
-    uint64_t cand[16];
-    int ncand = 0;
-    for (int r = lane; r < nb; r += WAVE) {
-        int l0 = max(r - G - T, 0), l1 = max(r - G, 0);        // [l0, l1)
+    uint64_t mine[16];
+    int have = 0;
+    for (int r = t; r < nb; r += CT) {
+        const float p = pw[r];
+        if (r > 0 && !(p > pw[r - 1])) continue;
+        if (r + 1 < nb && !(p >= pw[r + 1])) continue;
+        int l0 = max(r - G - T, 0), l1 = max(r - G, 0);            // [l0, l1)
         int h0 = min(r + G + 1, nb), h1 = min(r + G + T + 1, nb);  // [h0, h1)
         int N = (l1 - l0) + (h1 - h0);
         if (N <= 0) continue;
         double sum = (pre[l1] - pre[l0]) + (pre[h1] - pre[h0]);
-        double alpha = N * (pow(a.pfa, -1.0 / N) - 1.0);
-        double thr = alpha * sum / N;
-        float p = pw[r];
-        bool det = (double)p > thr;
-        if (r > 0 && !(p > pw[r - 1])) det = false;
-        if (r + 1 < nb && !(p >= pw[r + 1])) det = false;
-        if (!det) continue;
+        double thr = a.alpha[N] * sum / N;
+        if (!((double)p > thr)) continue;
         uint64_t key = pack_key(p, r);
-        // keep this lane's M best in descending order
-        if (ncand < M) {
-            int t = ncand++;
-            while (t > 0 && cand[t - 1] < key) { cand[t] = cand[t - 1]; --t; }
-            cand[t] = key;
-        } else if (key > cand[M - 1]) {
-            int t = M - 1;
-            while (t > 0 && cand[t - 1] < key) { cand[t] = cand[t - 1]; --t; }
-            cand[t] = key;
+        if (have < M) {
+            int q = have++;
+            while (q > 0 && mine[q - 1] < key) { mine[q] = mine[q - 1]; --q; }
+            mine[q] = key;
+        } else if (key > mine[M - 1]) {
+            int q = M - 1;
+            while (q > 0 && mine[q - 1] < key) { mine[q] = mine[q - 1]; --q; }
+            mine[q] = key;
         }
     }
-    // wave-wide selection of the M best keys
+    // per wave: the M largest keys of its lanes (0 = none)
     int head = 0;
-    int kept = 0;
-    int32_t *obin = a.beam_bins + (size_t)beam * M;
-    float *opw = a.beam_pw + (size_t)beam * M;
-    int sel_bins[16];
     for (int m = 0; m < M; ++m) {
-        uint64_t mine = head < ncand ? cand[head] : 0ull;
-        uint64_t best = mine;
+        uint64_t my = head < have ? mine[head] : 0ull;
+        uint64_t best = my;
         for (int off = 32; off > 0; off >>= 1) {
             uint64_t o = __shfl_xor(best, off);
             best = o > best ? o : best;
         }
-        if (best == 0ull) break;
-        if (mine == best) ++head;
-        sel_bins[m] = (int)(~(uint32_t)(best & 0xFFFFFFFFu));
-        ++kept;
+        if (best != 0ull && my == best) ++head;
+        if (lane == 0) wtop[w][m] = best;
     }
-    if (lane == 0) {
-        // range order
-        for (int x = 1; x < kept; ++x) {
-            int v = sel_bins[x], t = x - 1;
-            while (t >= 0 && sel_bins[t] > v) { sel_bins[t + 1] = sel_bins[t]; --t; }
-            sel_bins[t + 1] = v;
-        }
-        for (int x = 0; x < kept; ++x) {
-            obin[x] = sel_bins[x];
-            opw[x] = pw[sel_bins[x]];
-        }
-        a.beam_count[beam] = kept;
-    }
-}
-
-// Exclusive scan of per-beam counts in one block; writes the total.
-__global__ __launch_bounds__(SCAN_THREADS) void k_count_scan(DetectArgs a)
-{
-    __shared__ int part[SCAN_THREADS];
-    const int t = threadIdx.x;
-    const int n = a.n_beams;
-    const int per = (n + SCAN_THREADS - 1) / SCAN_THREADS;
-    int b0 = t * per, b1 = min(b0 + per, n);
-    int s = 0;
-    for (int i = b0; i < b1; ++i) s += a.beam_count[i];
-    part[t] = s;
     __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        int v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    // wave 0 merges the per-wave lists
+    if (w == 0) {
+        uint64_t my = lane < CW * M ? wtop[lane / M][lane % M] : 0ull;
+        int kept = 0;
+        int sel = -1;
+        for (int m = 0; m < M; ++m) {
+            uint64_t best = my;
+            for (int off = 32; off > 0; off >>= 1) {
+                uint64_t o = __shfl_xor(best, off);
+                best = o > best ? o : best;
+            }
+            if (best == 0ull) break;
+            if (lane == m) sel = (int)(~(uint32_t)(best & 0xFFFFFFFFu));
+            if (my == best) my = 0ull;
+            ++kept;
+        }
+        // range order: rank of each selected bin among the kept ones
+        int rank = 0;
+        for (int x = 0; x < kept; ++x) {
+            int other = __shfl(sel, x);
+            if (lane < kept && other < sel) ++rank;
+        }
+        if (lane < kept) {
+            a.beam_bins[(size_t)beam * M + rank] = sel;
+            a.beam_pw[(size_t)beam * M + rank] = pw[sel];
+        }
+        if (lane == 0) a.beam_count[beam] = kept;
     }
-    int run = t > 0 ? part[t - 1] : 0;
-    for (int i = b0; i < b1; ++i) {
-        int c = a.beam_count[i];
-        a.block_sums[i] = run;
-        run += c;
-    }
-    if (t == SCAN_THREADS - 1) *a.count = part[SCAN_THREADS - 1];
 }
 
-__global__ void k_emit(DetectArgs a)
+__global__ __launch_bounds__(ET) void k_emit(DetectArgs a)
 {
-    const int beam = blockIdx.x * blockDim.x + threadIdx.x;
-    if (beam >= a.n_beams) return;
-    const int cnt = a.beam_count[beam];
-    if (cnt == 0) return;
-    const int off = a.block_sums[beam];
+    __shared__ int wsum[ET / 64];
+    __shared__ int wred[ET / 64];
+    const int t = threadIdx.x;
+    const int g = blockIdx.x;
+    // offset of this group: all counts of earlier beams (L2-resident, int4 loads)
+    const int64_t before = (int64_t)g * ET;
+    int part = 0;
+    const int4 *c4 = reinterpret_cast<const int4 *>(a.beam_count);
+    for (int64_t i = t; i < before / 4; i += ET) {
+        int4 v = c4[i];
+        part += v.x + v.y + v.z + v.w;
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((t & 63) == 0) wred[t >> 6] = part;
+    const int beam = (int)before + t;
+    const int c = beam < a.n_beams ? a.beam_count[beam] : 0;
+    int total;
+    const int excl = block_scan_excl_int(c, wsum, &total);
+    int base = 0;
+    for (int q = 0; q < ET / 64; ++q) base += wred[q];
+    if (g == (int)gridDim.x - 1 && t == 0) *a.count = base + total;
+    if (c == 0) return;
+    const int M = a.max_per_beam;
+    // this beam's detections in range order
+    int bins[16];
+    float pws[16];
+    for (int x = 0; x < c; ++x) {
+        int b = a.beam_bins[(size_t)beam * M + x];
+        float p = a.beam_pw[(size_t)beam * M + x];
+        int q = x - 1;
+        while (q >= 0 && bins[q] > b) { bins[q + 1] = bins[q]; pws[q + 1] = pws[q]; --q; }
+        bins[q + 1] = b;
+        pws[q + 1] = p;
+    }
     const int h = beam % a.beams_h, v = beam / a.beams_h;
     double az, el;
     if (a.grid_mode == 1) {
@@ -173,30 +228,29 @@ __global__ void k_emit(DetectArgs a)
     double wx = a.rot[0] * dx + a.rot[1] * dy + a.rot[2] * dz;
     double wy = a.rot[3] * dx + a.rot[4] * dy + a.rot[5] * dz;
     double wz = a.rot[6] * dx + a.rot[7] * dy + a.rot[8] * dz;
-    const int M = a.max_per_beam;
-    for (int x = 0; x < cnt; ++x) {
+    const int off = base + excl;
+    for (int x = 0; x < c; ++x) {
         int dst = off + x;
         if (dst >= a.capacity) break;
-        int bin = a.beam_bins[(size_t)beam * M + x];
-        double rr = a.r_min + (bin + 0.5) * a.dr;
+        double rr = a.r_min + (bins[x] + 0.5) * a.dr;
         sonar_point p;
         p.x = (float)(a.pos[0] + wx * rr);
         p.y = (float)(a.pos[1] + wy * rr);
         p.z = (float)(a.pos[2] + wz * rr);
-        p.db = (float)(10.0 * log10((double)a.beam_pw[(size_t)beam * M + x]));
+        p.db = (float)(10.0 * log10((double)pws[x]));
         p.beam = beam;
-        p.bin = bin;
+        p.bin = bins[x];
         a.points[dst] = p;
     }
 }
 
 size_t detect_workspace_bytes(int n_beams, int max_per_beam)
 {
+    size_t nb4 = ((size_t)n_beams + 3) & ~(size_t)3;            // int4-readable counts
     size_t b = 0;
-    b += sizeof(int32_t) * (size_t)n_beams;                      // beam_count
-    b += sizeof(int32_t) * (size_t)n_beams;                      // offsets
-    b += sizeof(int32_t) * (size_t)n_beams * max_per_beam;       // bins
-    b += sizeof(float) * (size_t)n_beams * max_per_beam;         // powers
+    b += sizeof(int32_t) * nb4;                                   // beam_count
+    b += sizeof(int32_t) * (size_t)n_beams * max_per_beam;        // bins
+    b += sizeof(float) * (size_t)n_beams * max_per_beam;          // powers
     return (b + 255) & ~(size_t)255;
 }
 
@@ -204,9 +258,15 @@ hipError_t launch_detect(const DetectArgs &a, hipStream_t s)
 {
     if (a.n_beams == 0) return hipSuccess;
     size_t shmem = sizeof(double) * (a.n_bins + 1) + sizeof(float) * a.n_bins;
-    hipLaunchKernelGGL(k_cfar, dim3(a.n_beams), dim3(WAVE), shmem, s, a);
-    hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(SCAN_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_emit, dim3((a.n_beams + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_cfar, dim3(a.n_beams), dim3(CT), shmem, s, a);
+    return launch_emit(a, s);
+}
+
+hipError_t launch_emit(const DetectArgs &a, hipStream_t s)
+{
+    if (a.n_beams == 0) return hipSuccess;
+    int groups = (a.n_beams + ET - 1) / ET;
+    hipLaunchKernelGGL(k_emit, dim3(groups), dim3(ET), 0, s, a);
     return hipGetLastError();
 }
 

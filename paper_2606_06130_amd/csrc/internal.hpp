@@ -74,6 +74,13 @@ struct PingArgs {
     float2 *rec_amp;
     const uint32_t *mask;
     uint32_t max_steps;      // node-visit bound of one traversal (2 * nodes + 64)
+    // fused detection (det_count == nullptr: off)
+    int32_t *det_count;      // [n_beams]
+    int32_t *det_bins;       // [n_beams * det_M], strongest first
+    float *det_pw;           // [n_beams * det_M]
+    int det_G, det_T, det_M;
+    float det_n0;
+    double det_alpha[2 * 64 + 1];
 };
 
 // Host-side launchers (one per translation unit).
@@ -89,14 +96,15 @@ struct DetectArgs {
     int32_t *beam_count;     // workspace [n_beams]
     int32_t *beam_bins;      // workspace [n_beams * max_per_beam]
     float *beam_pw;          // workspace [n_beams * max_per_beam]
-    int32_t *block_sums;     // workspace
     int n_beams, n_bins, beams_h, grid_mode;
     int train, guard, max_per_beam, capacity;
     double pfa, noise_floor;
     double hfov, vfov, dth_h, dth_v, r_min, dr;
     double pos[3], rot[9];
+    double alpha[2 * 64 + 1];   // CFAR factor alpha(N) for N training cells
 };
 hipError_t launch_detect(const DetectArgs &a, hipStream_t s);
+hipError_t launch_emit(const DetectArgs &a, hipStream_t s);
 size_t detect_workspace_bytes(int n_beams, int max_per_beam);
 
 }  // namespace sonar

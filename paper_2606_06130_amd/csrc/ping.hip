@@ -240,7 +240,7 @@ struct Slot {
 
 }  // namespace
 
-template <int DEPTH>
+template <int DEPTH, int K>
 __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
 {
     extern __shared__ uint32_t lds[];
@@ -253,7 +253,6 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
     const int64_t beam = gid >> a.log2_nr;
     const int j = (int)(gid & (a.n_r - 1));
     const bool active = beam < a.n_beams;
-    const int K = a.K;
 
     Slot slot[MAX_BOUNCES];
 #pragma unroll
@@ -292,6 +291,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
         const size_t ray = (size_t)gid;
         const bool masked = a.mask && ((a.mask[ray >> 5] >> (ray & 31)) & 1u);
 
+#pragma unroll
         for (int k = 0; k < K; ++k) {
             double s_lim = (K == 1) ? a.r_max : 2.0 * a.r_max - L_out;
             int rec_tri = -1, rec_vis = 0;
@@ -448,6 +448,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
     int *sbin = reinterpret_cast<int *>(W);
     float4 *sval = reinterpret_cast<float4 *>(W + ACC_BIN_WORDS);
     uint16_t *sidx = reinterpret_cast<uint16_t *>(W + ACC_IDX_BASE);
+#pragma unroll
     for (int k = 0; k < K; ++k) {
         sbin[k * WAVE + lane] = slot[k].bin;
         sval[k * WAVE + lane] = k == 0 ? make_float4(slot[k].re, slot[k].im, slot[k].inc, 0.f)
@@ -459,6 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
     const int base_lane = bl << a.log2_nr;
     bool head[MAX_BOUNCES];
     float4 sum[MAX_BOUNCES];
+#pragma unroll
     for (int k = 0; k < K; ++k) {
         head[k] = false;
         sum[k] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -487,6 +489,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
         sum[k] = acc;
     }
     wave_sync();
+#pragma unroll
     for (int k = 0; k < K; ++k)
         if (head[k]) sval[k * WAVE + lane] = sum[k];
 
@@ -501,6 +504,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
         for (int w = lane; w < idx_words; w += WAVE) sidx32[w] = 0u;
         wave_sync();
         if (bl == q) {
+#pragma unroll
             for (int k = 0; k < K; ++k)
                 if (head[k]) sidx[slot[k].bin] = (uint16_t)(k * WAVE + lane + 1);
         }
@@ -531,6 +535,73 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
                 }
             }
         }
+        if (a.det_count) {
+            // CA-CFAR on the column while it is still indexed in LDS. A bin
+            // without a return has power N0 <= the training mean, and alpha(N)
+            // > 1, so only bins holding a return can be detected; the training
+            // sums are N * N0 plus the returns inside each window.
+            const float n0 = a.det_n0;
+            uint64_t key[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                key[k] = 0ull;
+                if (bl != q || !head[k]) continue;
+                const int bin = slot[k].bin;
+                const float4 v = sum[k];
+                const float p = v.x * v.x + v.y * v.y + n0;
+                float pl = n0, pr = n0;
+                if (bin > 0) {
+                    uint32_t sl = sidx[bin - 1];
+                    if (sl) { float4 u = sval[sl - 1]; pl = u.x * u.x + u.y * u.y + n0; }
+                }
+                if (bin + 1 < nb) {
+                    uint32_t sr = sidx[bin + 1];
+                    if (sr) { float4 u = sval[sr - 1]; pr = u.x * u.x + u.y * u.y + n0; }
+                }
+                if ((bin > 0 && !(p > pl)) || (bin + 1 < nb && !(p >= pr))) continue;
+                const int l0 = max(bin - a.det_G - a.det_T, 0), l1 = max(bin - a.det_G, 0);
+                const int h0 = min(bin + a.det_G + 1, nb), h1 = min(bin + a.det_G + a.det_T + 1, nb);
+                const int N = (l1 - l0) + (h1 - h0);
+                if (N <= 0) continue;
+                double wsum = (double)N * (double)n0;
+                for (int side = 0; side < 2; ++side) {
+                    const int p0 = side ? h0 : l0, p1 = side ? h1 : l1;
+                    for (int pos = p0; pos < p1; ++pos) {
+                        uint32_t sz = sidx[pos];
+                        if (sz) {
+                            float4 u = sval[sz - 1];
+                            float pz = u.x * u.x + u.y * u.y + n0;
+                            wsum += (double)pz - (double)n0;
+                        }
+                    }
+                }
+                const double thr = a.det_alpha[N] * wsum / N;
+                if ((double)p > thr) key[k] = ((uint64_t)__float_as_uint(p) << 32) | (uint32_t)(~bin);
+            }
+            // the det_M strongest over the beam's lanes, strongest first
+            unsigned taken = 0u;
+            int cnt = 0;
+            for (int m = 0; m < a.det_M; ++m) {
+                uint64_t my = 0ull;
+                int myk = -1;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (!((taken >> k) & 1u) && key[k] > my) { my = key[k]; myk = k; }
+                uint64_t best = my;
+                for (int off = 1; off < nr; off <<= 1) {
+                    uint64_t o = __shfl_xor(best, off);
+                    best = o > best ? o : best;
+                }
+                if (best == 0ull) break;
+                if (myk >= 0 && my == best) taken |= 1u << myk;
+                if (j == 0) {
+                    a.det_bins[(size_t)gb * a.det_M + m] = (int)(~(uint32_t)(best & 0xFFFFFFFFu));
+                    a.det_pw[(size_t)gb * a.det_M + m] = __uint_as_float((uint32_t)(best >> 32));
+                }
+                cnt = m + 1;
+            }
+            if (bl == q && j == 0) a.det_count[gb] = cnt;
+        }
         wave_sync();
     }
 }
@@ -550,10 +621,23 @@ hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s)
     int depth = stack_depth <= 32 ? 32 : 64;
     int ww = ping_wave_words(depth, a.n_bins);
     size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
-    if (depth == 32)
-        hipLaunchKernelGGL(k_ping<32>, dim3(nblocks), dim3(BLOCK), shmem, s, a, ww);
-    else
-        hipLaunchKernelGGL(k_ping<64>, dim3(nblocks), dim3(BLOCK), shmem, s, a, ww);
+#define SONAR_LAUNCH(D, KK) hipLaunchKernelGGL((k_ping<D, KK>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww)
+    if (depth == 32) {
+        switch (a.K) {
+            case 1: SONAR_LAUNCH(32, 1); break;
+            case 2: SONAR_LAUNCH(32, 2); break;
+            case 3: SONAR_LAUNCH(32, 3); break;
+            default: SONAR_LAUNCH(32, 4); break;
+        }
+    } else {
+        switch (a.K) {
+            case 1: SONAR_LAUNCH(64, 1); break;
+            case 2: SONAR_LAUNCH(64, 2); break;
+            case 3: SONAR_LAUNCH(64, 3); break;
+            default: SONAR_LAUNCH(64, 4); break;
+        }
+    }
+#undef SONAR_LAUNCH
     return hipGetLastError();
 }
 

@@ -24,8 +24,8 @@ SONAR_E_UNSUPPORTED = -5
 
 # Every symbol include/sonar.h declares.
 EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "sonar_ping",
-           "sonar_detect_workspace_size", "sonar_detect", "sonar_device_status", "sonar_status_string",
-           "sonar_last_error", "sonar_params_from_resolution")
+           "sonar_detect_workspace_size", "sonar_detect", "sonar_ping_detect", "sonar_device_status",
+           "sonar_status_string", "sonar_last_error", "sonar_params_from_resolution")
 
 
 class SonarError(RuntimeError):
@@ -97,6 +97,9 @@ def lib():
         L.sonar_detect.restype = C.c_int
         L.sonar_detect.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_cfar), C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.sonar_ping_detect.restype = C.c_int
+        L.sonar_ping_detect.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_cfar), C.c_void_p,
+                                        C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.sonar_device_status.restype = C.c_int
         L.sonar_device_status.argtypes = [C.c_void_p, C.c_void_p]
         L.sonar_status_string.restype = C.c_char_p
@@ -257,6 +260,15 @@ class Detector:
         st = lib().sonar_detect(_dptr(volume), C.byref(self.params), C.byref(q), C.byref(self.cfar),
                                 _dptr(self.points), self.capacity, _dptr(self.count), _dptr(self.workspace),
                                 self.workspace.numel(), _stream(stream))
+        _check(st)
+        return self.points, self.count
+
+    def ping_detect(self, scene: "Scene", volume, pose, stream=None, pose_s=None):
+        """Ping + detection with the CFAR test fused into the ping kernel."""
+        q = pose_s if pose_s is not None else pose_of(pose)
+        st = lib().sonar_ping_detect(scene.handle, C.byref(self.params), C.byref(q), C.byref(self.cfar),
+                                     _dptr(volume), _dptr(self.points), self.capacity, _dptr(self.count),
+                                     _dptr(self.workspace), self.workspace.numel(), _stream(stream))
         _check(st)
         return self.points, self.count
 

@@ -264,3 +264,39 @@ def test_scene_info_and_device_inputs():
     np.testing.assert_allclose(ia["hi"], mesh.vertices.max(0))
     assert 1 <= ia["depth"] <= 64
     _log("harbor hierarchy", ia)
+
+
+@pytest.mark.parametrize("which", ["harbor", "boxes"])
+def test_fused_ping_detect_matches_separate(which):
+    """sonar_ping_detect == sonar_ping + sonar_detect: same volume bits, same
+    points except decisions within 1e-9 relative of their threshold."""
+    torch, sonar = _gpu()
+    if which == "harbor":
+        mesh, cfg, pose = S.scene_harbor(), S.sensor_harbor(), S.pose_harbor()
+    else:
+        mesh, cfg, pose = S.scene_seabed_boxes(), S.sensor_seabed_boxes(), S.pose_seabed_boxes()
+    sc = sonar.Scene(mesh)
+    v1 = sonar.ping(sc, cfg, pose)["volume"]
+    d1 = sonar.Detector(cfg)
+    d1(v1, pose)
+    p1, n1 = d1.fetch()
+    v2 = torch.empty_like(v1)
+    d2 = sonar.Detector(cfg)
+    d2.ping_detect(sc, v2, pose)
+    p2, n2 = d2.fetch()
+    assert torch.equal(v1.view(torch.float32), v2.view(torch.float32))
+    _log(which, "detections", n1, n2)
+    assert n1 > 0
+    assert abs(n1 - n2) <= max(2, n1 // 10000)
+    k1 = set(zip(p1["beam"].tolist(), p1["bin"].tolist()))
+    k2 = set(zip(p2["beam"].tolist(), p2["bin"].tolist()))
+    assert len(k1 ^ k2) <= max(4, n1 // 5000)
+    common = sorted(k1 & k2)
+    i1 = {k: i for i, k in enumerate(zip(p1["beam"].tolist(), p1["bin"].tolist()))}
+    i2 = {k: i for i, k in enumerate(zip(p2["beam"].tolist(), p2["bin"].tolist()))}
+    a = p1[[i1[k] for k in common]]
+    b = p2[[i2[k] for k in common]]
+    for f in ("x", "y", "z"):
+        np.testing.assert_array_equal(a[f], b[f])
+    # the FP32 power may differ in its last bit (fused multiply-add contraction)
+    np.testing.assert_allclose(a["db"], b["db"], rtol=1e-6)
