@@ -105,7 +105,14 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
     if (!volume) return fail(SONAR_E_INVALID, "volume is NULL");
     if (rec && (!rec->tri || !rec->bin || !rec->vis || !rec->amp))
         return fail(SONAR_E_INVALID, "record arrays must all be set");
-    if (p->c_grad != 0.0) return fail(SONAR_E_UNSUPPORTED, "curved rays (c_grad != 0) are not in this build");
+    // a sound speed must stay positive over the scene and the sensor
+    if (p->c_grad != 0.0) {
+        double zmax = fmax((double)sc->s.zabs_max, fabs(q->position[2])) + 1.0;
+        if (!(p->c0 - fabs(p->c_grad) * zmax > 0.0))
+            return fail(SONAR_E_INVALID, "c(z) = c0 + c_grad z must stay positive over the scene");
+        if (fabs(p->c_grad) * 2.0 * p->r_max / (p->c0 - fabs(p->c_grad) * zmax) > 1e-2)
+            return fail(SONAR_E_UNSUPPORTED, "ray curvature too strong for one chord per segment (|g| 2 r_max / c > 1e-2)");
+    }
     if (sc->s.depth > 64)
         return fail(SONAR_E_STACK, "hierarchy depth %d exceeds the 64-entry traversal stack", sc->s.depth);
     sonar::PingArgs &a = *out;

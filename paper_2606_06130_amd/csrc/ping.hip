@@ -2,9 +2,11 @@
 //
 // Per lane (one ray): ray generation in FP64 (Sec. III grid, stratified
 // jitter) -> for each bounce: FP32 nearest-hit traversal of the BVH with an
-// LDS stack -> FP64 re-intersection of the winner -> scattering, spreading,
-// absorption and phase (Sec. II-B) -> for later bounces a connection ray to
-// the sensor with an any-hit visibility query -> mirror continuation.
+// LDS stack, along a straight line or, in a linear sound-speed gradient, along
+// the exact circular arc that Snell's law gives (Sec. II-A) -> FP64
+// re-intersection of the winner -> scattering, spreading, absorption and
+// phase (Sec. II-B) -> for later bounces a connection (eigenray) to the sensor
+// with an any-hit visibility query -> mirror continuation.
 // Per wavefront: the rays of a beam sit in adjacent lanes (64 / N_r beams per
 // wave); their contributions are reduced in a fixed order in LDS and each
 // beam's whole range column is written once with coalesced stores, zeros
@@ -43,6 +45,7 @@ __device__ __forceinline__ d3 cross3(d3 a, d3 b)
 {
     return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
+__device__ __forceinline__ double norm3(d3 a) { return sqrt(dot3(a, a)); }
 
 __device__ __forceinline__ float3 f3(d3 a) { return make_float3((float)a.x, (float)a.y, (float)a.z); }
 __device__ __forceinline__ float3 fsub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
@@ -89,26 +92,120 @@ __device__ __forceinline__ TriF load_tri(const float4 *__restrict__ tris, uint32
     return t;
 }
 
-struct Ray32 {
-    float3 o, d, inv;
+// ---------------------------------------------------------------------------
+// Paths. In c(z) = c0 + g z the Snell invariant cos(theta) / c is constant and
+// a ray is a circle of curvature kappa = g cos(theta) / c(z) centred on the
+// plane c = 0: x(s) = o + d sin(ks)/k + nc (1 - cos ks)/k, with nc the unit
+// normal toward the centre in the ray's vertical plane. With g = 0 or a
+// vertical direction the path is straight.
+struct Path64 {
+    d3 o, d, nc;
+    double kappa;
+    bool arc;
 };
 
-__device__ __forceinline__ Ray32 make_ray32(d3 o, d3 d)
+__device__ __forceinline__ Path64 make_path(d3 o, d3 d, double g, double c0)
 {
-    Ray32 r;
-    r.o = f3(o);
-    r.d = f3(d);
+    Path64 p;
+    p.o = o;
+    p.d = d;
+    p.arc = false;
+    p.kappa = 0.0;
+    p.nc = mk3(0.0, 0.0, 0.0);
+    double dh = sqrt(d.x * d.x + d.y * d.y);
+    if (g != 0.0 && dh > 0.0) {
+        p.arc = true;
+        p.kappa = g * dh / (c0 + g * o.z);
+        p.nc = mk3(d.z * d.x / dh, d.z * d.y / dh, -dh);
+    }
+    return p;
+}
+
+__device__ __forceinline__ d3 path_point(const Path64 &p, double s)
+{
+    if (!p.arc) return p.o + p.d * s;
+    double u = p.kappa * s, h = sin(0.5 * u);
+    return p.o + p.d * (sin(u) / p.kappa) + p.nc * (2.0 * h * h / p.kappa);
+}
+
+__device__ __forceinline__ d3 path_tangent(const Path64 &p, double s)
+{
+    if (!p.arc) return p.d;
+    double u = p.kappa * s;
+    return p.d * cos(u) + p.nc * sin(u);
+}
+
+// One-way time along the path. On the arc, dt = ds / c and the integral from
+// grazing angle th0 to th1 is (atanh sin th0 - atanh sin th1) / g, evaluated
+// here as one atanh of (s0 - s1) / (1 - s0 s1) with s0 - s1 and
+// 1 - s0 s1 = cos^2 th0 + s0 (s0 - s1) formed without cancellation.
+__device__ __forceinline__ double path_time(const Path64 &p, double s, double g, double c0)
+{
+    if (!p.arc) {
+        if (g == 0.0) return s / c0;
+        return fabs(log1p(g * p.d.z * s / (c0 + g * p.o.z)) / g);   // vertical ray
+    }
+    double u = p.kappa * s, h = sin(0.5 * u);
+    double dh = sqrt(p.d.x * p.d.x + p.d.y * p.d.y);
+    double s0 = p.d.z;
+    double ds = p.d.z * 2.0 * h * h + dh * sin(u);                   // sin th0 - sin th1
+    return atanh(ds / (dh * dh + s0 * ds)) / g;
+}
+
+// FP32 traversal segment: a straight ray, or for an arc the chord from o to
+// x(s_lim) with node boxes inflated by the arc's largest distance to it.
+struct Seg32 {
+    float3 o, d, inv;      // the ray or the chord
+    float sigma;           // box inflation (0 for straight rays)
+    float tmin, tmax;      // parameter range on the ray or chord
+    float smin, smax;      // arc-length range of valid hits
+    float3 ad, anc;        // arc tangent and centre normal at o
+    float kappa;
+};
+
+__device__ __forceinline__ float3 safe_inv(float3 d)
+{
     // zero components get a tiny signed value so that slab distances stay finite or infinite, never NaN
-    float dx = fabsf(r.d.x) > 1e-30f ? r.d.x : copysignf(1e-30f, r.d.x);
-    float dy = fabsf(r.d.y) > 1e-30f ? r.d.y : copysignf(1e-30f, r.d.y);
-    float dz = fabsf(r.d.z) > 1e-30f ? r.d.z : copysignf(1e-30f, r.d.z);
-    r.inv = make_float3(1.0f / dx, 1.0f / dy, 1.0f / dz);
-    return r;
+    float dx = fabsf(d.x) > 1e-30f ? d.x : copysignf(1e-30f, d.x);
+    float dy = fabsf(d.y) > 1e-30f ? d.y : copysignf(1e-30f, d.y);
+    float dz = fabsf(d.z) > 1e-30f ? d.z : copysignf(1e-30f, d.z);
+    return make_float3(1.0f / dx, 1.0f / dy, 1.0f / dz);
+}
+
+__device__ __forceinline__ Seg32 make_seg(const Path64 &p, double smin, double smax)
+{
+    Seg32 g;
+    g.o = f3(p.o);
+    g.smin = (float)smin;
+    g.smax = (float)smax;
+    if (!p.arc) {
+        g.d = f3(p.d);
+        g.sigma = 0.f;
+        g.tmin = (float)smin;
+        g.tmax = (float)smax;
+        g.kappa = 0.f;
+        g.ad = g.d;
+        g.anc = make_float3(0.f, 0.f, 0.f);
+    } else {
+        d3 e = path_point(p, smax) - p.o;
+        double lc = norm3(e);
+        g.d = f3(e * (1.0 / lc));
+        // sagitta of the arc over its chord, with margin for FP32 rounding of the chord
+        double sag = fabs(p.kappa) * smax * smax / 8.0;
+        g.sigma = (float)(sag * 1.01 + 2e-6 * (1.0 + smax));
+        g.tmin = 0.f;
+        g.tmax = (float)(lc * (1.0 + 1e-6));
+        g.kappa = (float)p.kappa;
+        g.ad = f3(p.d);
+        g.anc = f3(p.nc);
+    }
+    g.inv = safe_inv(g.d);
+    return g;
 }
 
 // Slab test of one box against [tmin, tmax]; the far distance is widened by
 // 5e-7 relative so that FP32 rounding never rejects a box the exact ray meets.
-__device__ __forceinline__ bool slab(const Ray32 &r, float lx, float ly, float lz, float hx, float hy, float hz,
+__device__ __forceinline__ bool slab(const Seg32 &r, float lx, float ly, float lz, float hx, float hy, float hz,
                                      float tmin, float tmax, float &tnear)
 {
     float x0 = (lx - r.o.x) * r.inv.x, x1 = (hx - r.o.x) * r.inv.x;
@@ -121,7 +218,7 @@ __device__ __forceinline__ bool slab(const Ray32 &r, float lx, float ly, float l
 }
 
 // FP32 Moller-Trumbore (closed triangle). Returns t or -1.
-__device__ __forceinline__ float mt32(const Ray32 &r, const TriF &t)
+__device__ __forceinline__ float mt32(const Seg32 &r, const TriF &t)
 {
     float3 e1 = fsub(t.v1, t.v0), e2 = fsub(t.v2, t.v0);
     float3 p = fcross(r.d, e2);
@@ -137,18 +234,75 @@ __device__ __forceinline__ float mt32(const Ray32 &r, const TriF &t)
     return fdot(e2, q) * inv;
 }
 
+// FP32 arc-triangle test: smallest arc length s in (smin, smax] where the arc
+// meets the triangle's plane inside the closed triangle; -1 if none. The
+// plane equation f(s) = n.(o - v0) + n.d S(s) + n.nc C(s), with S = sin(ks)/k
+// and C = (1 - cos ks)/k, is solved to second order in k s (stable quadratic
+// formula) and then polished by one Newton step with the third-order terms.
+// `tc` returns the hit's parameter along the chord, used for culling.
+__device__ __forceinline__ float arc32(const Seg32 &r, const TriF &t, float &tc)
+{
+    float3 e1 = fsub(t.v1, t.v0), e2 = fsub(t.v2, t.v0);
+    float3 n = fcross(e1, e2);
+    float3 ov = fsub(r.o, t.v0);
+    const float k = r.kappa;
+    float fa = fdot(n, ov), fb = fdot(n, r.ad), fn = fdot(n, r.anc);
+    float fc = 0.5f * fn * k;
+    float s0 = -1.f, s1 = -1.f;
+    if (fc == 0.f) {
+        if (fb != 0.f) s0 = -fa / fb;
+    } else {
+        float disc = fb * fb - 4.f * fc * fa;
+        if (disc < 0.f) return -1.f;
+        float sq = sqrtf(disc);
+        float q = -0.5f * (fb + (fb >= 0.f ? sq : -sq));
+        s0 = q / fc;
+        s1 = q != 0.f ? fa / q : -1.f;
+        if (s1 < s0) { float w = s0; s0 = s1; s1 = w; }
+    }
+    float nn = fdot(n, n);
+    for (int m = 0; m < 2; ++m) {
+        float s = m == 0 ? s0 : s1;
+        if (!(s > 0.f)) continue;
+        {   // Newton step with the cubic terms of S and C
+            float ks = k * s;
+            float Ss = s * (1.f - ks * ks * (1.f / 6.f));
+            float Cs = 0.5f * ks * s * (1.f - ks * ks * (1.f / 12.f));
+            float f = fa + fb * Ss + fn * Cs;
+            float fp = fb * (1.f - 0.5f * ks * ks) + fn * ks * (1.f - ks * ks * (1.f / 6.f));
+            if (fp != 0.f) s -= f / fp;
+        }
+        if (!(s > r.smin && s <= r.smax)) continue;
+        float ks = k * s;
+        float Ss = s * (1.f - ks * ks * (1.f / 6.f));
+        float Cs = 0.5f * ks * s * (1.f - ks * ks * (1.f / 12.f));
+        float3 x = make_float3(ov.x + r.ad.x * Ss + r.anc.x * Cs, ov.y + r.ad.y * Ss + r.anc.y * Cs,
+                               ov.z + r.ad.z * Ss + r.anc.z * Cs);
+        float u = fdot(fcross(x, e2), n), v = fdot(fcross(e1, x), n);
+        if (u >= 0.f && v >= 0.f && u + v <= nn) {
+            float3 xw = make_float3(x.x + t.v0.x - r.o.x, x.y + t.v0.y - r.o.y, x.z + t.v0.z - r.o.z);
+            tc = fdot(xw, r.d);
+            return s;
+        }
+    }
+    return -1.f;
+}
+
 // Stack-based BVH traversal (near child first). ANY = true returns at the
 // first valid hit. `skip` is an original triangle index never reported.
 // Returns the triangle record index, or -1; `overflow` is set when the LDS
-// stack of DEPTH entries would overflow (the ray is then reported as a miss).
-template <int DEPTH, bool ANY>
-__device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restrict__ tris, const Ray32 &r,
-                        float tmin, float tmax, uint32_t skip, uint32_t *__restrict__ stk, int lane, bool &overflow,
-                        float &t_out, uint32_t max_steps)
+// stack of DEPTH entries would overflow or the node-visit bound is reached
+// (the ray is then reported as a miss).
+template <int DEPTH, bool ANY, bool ARC>
+__device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restrict__ tris, const Seg32 &r,
+                        uint32_t skip, uint32_t *__restrict__ stk, int lane, bool &overflow, float &s_out,
+                        uint32_t max_steps)
 {
     int best = -1;
-    float best_t = tmax;
+    float best_t = r.tmax;        // culling bound on the ray / chord parameter
+    float best_s = r.smax;        // best arc length
     uint32_t best_id = 0xFFFFFFFFu;
+    const float sg = r.sigma;
     uint32_t cur = 0;
     int sp = 0;
     for (uint32_t step = 0;; ++step) {
@@ -161,8 +315,14 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
             const float4 *n = nodes + 4 * (size_t)cur;
             float4 a = n[0], b = n[1], c = n[2], d = n[3];
             float t0, t1;
-            bool h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, best_t, t0);
-            bool h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, best_t, t1);
+            bool h0, h1;
+            if (ARC) {
+                h0 = slab(r, a.x - sg, a.y - sg, a.z - sg, a.w + sg, b.x + sg, b.y + sg, r.tmin, best_t, t0);
+                h1 = slab(r, b.z - sg, b.w - sg, c.x - sg, c.y + sg, c.z + sg, c.w + sg, r.tmin, best_t, t1);
+            } else {
+                h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, r.tmin, best_t, t0);
+                h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, r.tmin, best_t, t1);
+            }
             uint32_t l0 = __float_as_uint(d.x), l1 = __float_as_uint(d.y);
             if (h0 && h1) {
                 uint32_t nearc = t0 <= t1 ? l0 : l1;
@@ -190,10 +350,19 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
                 TriF t = load_tri(tris, first + k);
                 uint32_t id = t.idbits & 0x7FFFFFFFu;
                 if (id == skip) continue;
-                float th = mt32(r, t);
-                if (th > tmin && (th < best_t || (th == best_t && id < best_id))) {
+                float sh, th;
+                if (ARC) {
+                    sh = arc32(r, t, th);
+                    if (sh < 0.f) continue;
+                } else {
+                    sh = mt32(r, t);
+                    th = sh;
+                    if (!(sh > r.smin)) continue;
+                }
+                if (sh < best_s || (sh == best_s && id < best_id)) {
                     best = (int)(first + k);
-                    best_t = th;
+                    best_s = sh;
+                    best_t = ARC ? fminf(best_t, th + 2.f * sg) : sh;
                     best_id = id;
                     if (ANY) break;
                 }
@@ -204,23 +373,31 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
         --sp;
         cur = stk[sp * WAVE + lane];
     }
-    t_out = best_t;
+    s_out = best_s;
     return best;
 }
 
-// FP64 re-intersection of a triangle record (Moller-Trumbore in FP64).
-__device__ __forceinline__ double refine64(const TriF &t, d3 o, d3 d, d3 &nrm)
+// FP64 re-intersection of a triangle record along a path: Moller-Trumbore for
+// a straight path, Newton on the plane equation of the exact arc otherwise.
+__device__ __forceinline__ double refine64(const TriF &t, const Path64 &p, double s_guess, d3 &nrm)
 {
     d3 v0 = mk3(t.v0.x, t.v0.y, t.v0.z), v1 = mk3(t.v1.x, t.v1.y, t.v1.z), v2 = mk3(t.v2.x, t.v2.y, t.v2.z);
     d3 e1 = v1 - v0, e2 = v2 - v0;
-    d3 p = cross3(d, e2);
-    double det = dot3(e1, p);
-    d3 tv = o - v0;
-    d3 q = cross3(tv, e1);
-    double th = dot3(e2, q) / det;
     d3 n = cross3(e1, e2);
-    nrm = n * (1.0 / sqrt(dot3(n, n)));
-    return th;
+    nrm = n * (1.0 / norm3(n));
+    if (!p.arc) {
+        d3 q = cross3(p.o - v0, e1);
+        d3 pv = cross3(p.d, e2);
+        return dot3(e2, q) / dot3(e1, pv);
+    }
+    double s = s_guess;
+    for (int it = 0; it < 4; ++it) {
+        double f = dot3(nrm, path_point(p, s) - v0);
+        double fp = dot3(nrm, path_tangent(p, s));
+        if (fp == 0.0) break;
+        s -= f / fp;
+    }
+    return s;
 }
 
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
@@ -238,9 +415,47 @@ struct Slot {
     float re, im, inc;
 };
 
+// Connection from a scattering point P back to the sensor at S: a straight
+// segment when g = 0, else the circle through both points with its centre on
+// the plane c = 0 in their vertical plane (the eigenray).
+struct Conn {
+    double L, T;
+    d3 w;          // departure direction at P
+    d3 arrive;     // direction of travel at S
+};
+
+__device__ __forceinline__ Conn connect(d3 P, d3 S, double g, double c0)
+{
+    Conn c;
+    d3 v = S - P;
+    double D = sqrt(v.x * v.x + v.y * v.y);
+    if (g == 0.0 || D == 0.0) {
+        c.L = norm3(v);
+        c.w = v * (1.0 / c.L);
+        c.arrive = c.w;
+        c.T = g == 0.0 ? c.L / c0 : fabs(log1p(g * v.z / (c0 + g * P.z)) / g);
+        return c;
+    }
+    // heights above the centre plane in a frame where the gradient is positive
+    const double sg = g > 0.0 ? 1.0 : -1.0, ag = fabs(g);
+    const double zc = -c0 / ag;
+    const double h1 = sg * P.z - zc, h2 = sg * S.z - zc;
+    // centre at horizontal distance xc from P toward S on the perpendicular bisector
+    const double xc = 0.5 * D + 0.5 * (h2 - h1) * (h2 + h1) / D;
+    const double R = sqrt(xc * xc + h1 * h1);
+    const d3 uh = mk3(v.x / D, v.y / D, 0.0);
+    const double sin0 = xc / R, cos0 = h1 / R, sin1 = (xc - D) / R, cos1 = h2 / R;
+    c.w = mk3(cos0 * uh.x, cos0 * uh.y, sg * sin0);
+    c.arrive = mk3(cos1 * uh.x, cos1 * uh.y, sg * sin1);
+    c.L = 2.0 * R * asin(0.5 * norm3(v) / R);
+    const double dsn = D / R;                        // sin0 - sin1
+    c.T = atanh(dsn / (cos0 * cos0 + sin0 * dsn)) / ag;
+    return c;
+}
+
 }  // namespace
 
-template <int DEPTH, int K>
+template <int DEPTH, int K, bool ARC>
 __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
 {
     extern __shared__ uint32_t lds[];
@@ -254,9 +469,19 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
     const int j = (int)(gid & (a.n_r - 1));
     const bool active = beam < a.n_beams;
 
-    Slot slot[MAX_BOUNCES];
+    // Contribution slots: registers for a single bounce; for several bounces
+    // an LDS area past the traversal stack, slot (k, lane) at k * 64 + lane.
+    int *sbin = (K == 1) ? reinterpret_cast<int *>(W) : reinterpret_cast<int *>(W + DEPTH * WAVE);
+    float4 *sval = (K == 1) ? reinterpret_cast<float4 *>(W + ACC_BIN_WORDS)
+                            : reinterpret_cast<float4 *>(W + DEPTH * WAVE + K * WAVE);
+    Slot slot0 = Slot{-1, 0.f, 0.f, 0.f};
+    if (K > 1) {
 #pragma unroll
-    for (int k = 0; k < MAX_BOUNCES; ++k) slot[k] = Slot{-1, 0.f, 0.f, 0.f};
+        for (int k = 0; k < K; ++k) {
+            sbin[k * WAVE + lane] = -1;
+            sval[k * WAVE + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
     float gfeat[7] = {0, 0, 0, 0, 0, 0, 0};
     bool overflow = false;
 
@@ -290,114 +515,131 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
         uint32_t prev = 0xFFFFFFFFu;
         const size_t ray = (size_t)gid;
         const bool masked = a.mask && ((a.mask[ray >> 5] >> (ray & 31)) & 1u);
+        bool stop = false;
 
-#pragma unroll
+#pragma unroll 1
         for (int k = 0; k < K; ++k) {
-            double s_lim = (K == 1) ? a.r_max : 2.0 * a.r_max - L_out;
             int rec_tri = -1, rec_vis = 0;
-            if (s_lim > EPS_SELF) {
-                Ray32 r = make_ray32(o, d);
-                float tf;
-                int ti = traverse<DEPTH, false>(a.nodes, a.tris, r, (float)EPS_SELF,
-                                                (float)(s_lim * (1.0 + 1e-6)), prev, W, lane, overflow, tf,
-                                                a.max_steps);
-                if (ti >= 0) {
-                    TriF tr = load_tri(a.tris, (uint32_t)ti);
-                    d3 nh;
-                    double s = refine64(tr, o, d, nh);
-                    if (s > EPS_SELF && s <= s_lim) {
-                        uint32_t id = tr.idbits & 0x7FFFFFFFu;
-                        rec_tri = (int)id;
-                        d3 X = o + d * s;
-                        L_out += s;
-                        T_out += s / a.c0;
-                        double dn = dot3(nh, d);
-                        d3 np = dn > 0.0 ? nh * -1.0 : nh;
-                        double cos_i = -dot3(np, d);
-                        d3 rh = d - np * (2.0 * dot3(np, d));
-                        const bool pr = (tr.idbits & MAT_BIT) != 0;
-                        double rho = pr ? 1.0 : (double)tr.rho;
-                        double kd = pr ? 0.0 : a.k_d;
-                        double ks = pr ? 1.0 : a.k_s;
-                        double phi = pr ? 0.0 : (double)tr.phi;
-                        double sgn = pr ? -1.0 : 1.0;
+            int cbin = -1;
+            float cre = 0.f, cim = 0.f, cinc = 0.f;
+            if (!stop) {
+                // segment limit: arc length for constant c, travel time in a gradient
+                double s_lim, T_lim = 0.0;
+                if (!ARC) {
+                    s_lim = (K == 1) ? a.r_max : 2.0 * a.r_max - L_out;
+                } else {
+                    T_lim = (K == 1) ? a.r_max / a.c_ref : 2.0 * a.r_max / a.c_ref - T_out;
+                    s_lim = a.c_hi * T_lim;
+                }
+                stop = true;
+                if (s_lim > EPS_SELF) {
+                    const Path64 path = ARC ? make_path(o, d, a.g, a.c0) : Path64{o, d, mk3(0, 0, 0), 0.0, false};
+                    const Seg32 seg = make_seg(path, EPS_SELF, s_lim * (1.0 + 1e-6));
+                    float sf;
+                    // in a gradient a vertical ray is a degenerate arc (kappa = 0)
+                    int ti = traverse<DEPTH, false, ARC>(a.nodes, a.tris, seg, prev, W, lane, overflow, sf,
+                                                         a.max_steps);
+                    if (ti >= 0) {
+                        TriF tr = load_tri(a.tris, (uint32_t)ti);
+                        d3 nh;
+                        double s = refine64(tr, path, (double)sf, nh);
+                        double tau = ARC ? path_time(path, s, a.g, a.c0) : s / a.c0;
+                        bool ok = s > EPS_SELF && (ARC ? tau <= T_lim : s <= s_lim);
+                        if (ok) {
+                            stop = false;
+                            uint32_t id = tr.idbits & 0x7FFFFFFFu;
+                            rec_tri = (int)id;
+                            d3 X = ARC ? path_point(path, s) : o + d * s;
+                            d3 din = ARC ? path_tangent(path, s) : d;
+                            L_out += s;
+                            T_out += tau;
+                            double dn = dot3(nh, din);
+                            d3 np = dn > 0.0 ? nh * -1.0 : nh;
+                            double cos_i = -dot3(np, din);
+                            d3 rh = din - np * (2.0 * dot3(np, din));
+                            const bool pr = (tr.idbits & MAT_BIT) != 0;
+                            double rho = pr ? 1.0 : (double)tr.rho;
+                            double kd = pr ? 0.0 : a.k_d;
+                            double ks = pr ? 1.0 : a.k_s;
+                            double phi = pr ? 0.0 : (double)tr.phi;
+                            double sgn = pr ? -1.0 : 1.0;
 
-                        double L_back, T_back;
-                        d3 w;
-                        bool vis = true;
-                        if (k == 0) {
-                            L_back = L_out;
-                            T_back = T_out;
-                            w = d * -1.0;
-                        } else {
-                            d3 toS = S - X;
-                            L_back = sqrt(dot3(toS, toS));
-                            w = toS * (1.0 / L_back);
-                            T_back = L_back / a.c0;
-                            // arrival direction (from S toward P) inside the field of view
-                            d3 av = w * -1.0;
-                            double sx = a.rot[0] * av.x + a.rot[3] * av.y + a.rot[6] * av.z;
-                            double sy = a.rot[1] * av.x + a.rot[4] * av.y + a.rot[7] * av.z;
-                            double sz = a.rot[2] * av.x + a.rot[5] * av.y + a.rot[8] * av.z;
-                            double aza = atan2(sy, sx), ela = atan2(sz, sqrt(sx * sx + sy * sy));
-                            if (fabs(aza) > 0.5 * a.hfov || fabs(ela) > 0.5 * a.vfov) vis = false;
-                            if (vis && L_back > 2.0 * EPS_SELF) {
-                                Ray32 cr = make_ray32(X, w);
-                                float ta;
-                                int hb = traverse<DEPTH, true>(a.nodes, a.tris, cr, (float)EPS_SELF,
-                                                               (float)(L_back - EPS_SELF), id, W, lane, overflow,
-                                                               ta, a.max_steps);
-                                if (hb >= 0) vis = false;
+                            double L_back, T_back;
+                            d3 w;
+                            bool vis = true;
+                            if (k == 0) {
+                                L_back = L_out;
+                                T_back = T_out;
+                                w = din * -1.0;
+                            } else {
+                                const Conn cn = connect(X, S, ARC ? a.g : 0.0, a.c0);
+                                L_back = cn.L;
+                                T_back = cn.T;
+                                w = cn.w;
+                                // arrival direction (from S toward P) inside the field of view
+                                d3 av = cn.arrive * -1.0;
+                                double sx = a.rot[0] * av.x + a.rot[3] * av.y + a.rot[6] * av.z;
+                                double sy = a.rot[1] * av.x + a.rot[4] * av.y + a.rot[7] * av.z;
+                                double sz = a.rot[2] * av.x + a.rot[5] * av.y + a.rot[8] * av.z;
+                                double aza = atan2(sy, sx), ela = atan2(sz, sqrt(sx * sx + sy * sy));
+                                if (fabs(aza) > 0.5 * a.hfov || fabs(ela) > 0.5 * a.vfov) vis = false;
+                                if (vis && L_back > 2.0 * EPS_SELF) {
+                                    const Path64 cp =
+                                        ARC ? make_path(X, w, a.g, a.c0) : Path64{X, w, mk3(0, 0, 0), 0.0, false};
+                                    const Seg32 cs = make_seg(cp, EPS_SELF, L_back - EPS_SELF);
+                                    float sa2;
+                                    int hb = traverse<DEPTH, true, ARC>(a.nodes, a.tris, cs, id, W, lane, overflow,
+                                                                        sa2, a.max_steps);
+                                    if (hb >= 0) vis = false;
+                                }
                             }
-                        }
-                        rec_vis = vis ? 1 : 0;
-                        if (vis) {
-                            double cos_o = dot3(np, w);
-                            if (cos_o > 0.0) {
-                                double Tt = T_out + T_back;
-                                double reff = a.c_ref * Tt / 2.0;
-                                double x = (reff - a.r_min) / a.dr;
-                                double fb = floor(x);
-                                if (fb >= 0.0 && fb < (double)a.n_bins) {
-                                    double lobe = dot3(rh, w);
-                                    lobe = lobe > 0.0 ? lobe : 0.0;
-                                    double spec = ks != 0.0 ? ks * pow(lobe, a.phong_n) : 0.0;
-                                    double fsc = rho * (kd * cos_i * cos_o + spec);
-                                    double amp = Wt * sgn * sqrt(fsc) *
-                                                 exp(-a.alpha_db * (L_out + L_back) * LN10_OVER_20) /
-                                                 (L_out * L_back * a.n_r);
-                                    double cyc = a.f0 * Tt;
-                                    double ph = TWO_PI * (cyc - floor(cyc)) + phi;
-                                    ph -= TWO_PI * rint(ph / TWO_PI);
-                                    float sn, cs;
-                                    sincosf((float)ph, &sn, &cs);
-                                    slot[k].bin = (int)fb;
-                                    slot[k].re = (float)amp * cs;
-                                    slot[k].im = (float)amp * sn;
-                                    slot[k].inc = (float)(amp * amp);
-                                    if (k == 0) {
-                                        gfeat[0] = (float)(reff / a.r_max);
-                                        gfeat[1] = (float)cos_i;
-                                        gfeat[2] = (float)rho;
-                                        gfeat[3] = (float)np.x;
-                                        gfeat[4] = (float)np.y;
-                                        gfeat[5] = (float)np.z;
-                                        gfeat[6] = 1.f;
+                            rec_vis = vis ? 1 : 0;
+                            if (vis) {
+                                double cos_o = dot3(np, w);
+                                if (cos_o > 0.0) {
+                                    double Tt = T_out + T_back;
+                                    double reff = a.c_ref * Tt / 2.0;
+                                    double x = (reff - a.r_min) / a.dr;
+                                    double fb = floor(x);
+                                    if (fb >= 0.0 && fb < (double)a.n_bins) {
+                                        double lobe = dot3(rh, w);
+                                        lobe = lobe > 0.0 ? lobe : 0.0;
+                                        double spec = ks != 0.0 ? ks * pow(lobe, a.phong_n) : 0.0;
+                                        double fsc = rho * (kd * cos_i * cos_o + spec);
+                                        double amp = Wt * sgn * sqrt(fsc) *
+                                                     exp(-a.alpha_db * (L_out + L_back) * LN10_OVER_20) /
+                                                     (L_out * L_back * a.n_r);
+                                        double cyc = a.f0 * Tt;
+                                        double ph = TWO_PI * (cyc - floor(cyc)) + phi;
+                                        ph -= TWO_PI * rint(ph / TWO_PI);
+                                        float sn, cs;
+                                        sincosf((float)ph, &sn, &cs);
+                                        cbin = (int)fb;
+                                        cre = (float)amp * cs;
+                                        cim = (float)amp * sn;
+                                        cinc = (float)(amp * amp);
+                                        if (k == 0) {
+                                            gfeat[0] = (float)(reff / a.r_max);
+                                            gfeat[1] = (float)cos_i;
+                                            gfeat[2] = (float)rho;
+                                            gfeat[3] = (float)np.x;
+                                            gfeat[4] = (float)np.y;
+                                            gfeat[5] = (float)np.z;
+                                            gfeat[6] = 1.f;
+                                        }
                                     }
                                 }
                             }
-                        }
-                        // continuation
-                        if (k + 1 < K) {
-                            Wt *= sqrt(rho * ks) * sgn;
-                            d3 xs = X - S;
-                            double lb = (L_out + sqrt(dot3(xs, xs))) / 2.0;
-                            if (Wt == 0.0 || lb >= a.r_max) {
-                                s_lim = -1.0;   // stop
+                            // continuation along the mirror direction
+                            if (k + 1 < K) {
+                                Wt *= sqrt(rho * ks) * sgn;
+                                const double dS = norm3(X - S);
+                                const double lb = ARC ? a.c_ref * (T_out + dS / a.c_hi) / 2.0 : (L_out + dS) / 2.0;
+                                if (Wt == 0.0 || lb >= a.r_max) stop = true;
+                                o = X;
+                                d = rh;
+                                prev = id;
                             }
-                            o = X;
-                            d = rh;
-                            prev = id;
                         }
                     }
                 }
@@ -405,26 +647,23 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
             if (a.rec_tri) {
                 size_t ri = ray * K + k;
                 a.rec_tri[ri] = rec_tri;
-                a.rec_bin[ri] = slot[k].bin;
+                a.rec_bin[ri] = cbin;
                 a.rec_vis[ri] = rec_vis;
-                a.rec_amp[ri] = make_float2(slot[k].re, slot[k].im);
+                a.rec_amp[ri] = make_float2(cre, cim);
             }
-            if (rec_tri < 0 || s_lim < 0.0) {
-                for (int q = k + 1; q < K; ++q) {
-                    if (a.rec_tri) {
-                        size_t ri = ray * K + q;
-                        a.rec_tri[ri] = -1;
-                        a.rec_bin[ri] = -1;
-                        a.rec_vis[ri] = 0;
-                        a.rec_amp[ri] = make_float2(0.f, 0.f);
-                    }
-                }
-                break;
+            if (K == 1) {
+                slot0 = Slot{cbin, cre, cim, cinc};
+            } else {
+                sbin[k * WAVE + lane] = cbin;
+                sval[k * WAVE + lane] = k == 0 ? make_float4(cre, cim, cinc, 0.f) : make_float4(cre, cim, 0.f, cinc);
             }
         }
         if (masked) {
+            slot0.bin = -1;
+            if (K > 1) {
 #pragma unroll
-            for (int k = 0; k < MAX_BOUNCES; ++k) slot[k].bin = -1;
+                for (int k = 0; k < K; ++k) sbin[k * WAVE + lane] = -1;
+            }
             for (int q = 0; q < 7; ++q) gfeat[q] = 0.f;
         }
     }
@@ -445,16 +684,17 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
 
     // ---- accumulation: fixed-order reduction of equal (beam, bin) slots
     wave_sync();
-    int *sbin = reinterpret_cast<int *>(W);
-    float4 *sval = reinterpret_cast<float4 *>(W + ACC_BIN_WORDS);
-    uint16_t *sidx = reinterpret_cast<uint16_t *>(W + ACC_IDX_BASE);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        sbin[k * WAVE + lane] = slot[k].bin;
-        sval[k * WAVE + lane] = k == 0 ? make_float4(slot[k].re, slot[k].im, slot[k].inc, 0.f)
-                                       : make_float4(slot[k].re, slot[k].im, 0.f, slot[k].inc);
+    // column index: past the slots for one bounce, in the (now free) stack area otherwise
+    uint32_t *sidx32 = (K == 1) ? W + ACC_IDX_BASE : W;
+    uint16_t *sidx = reinterpret_cast<uint16_t *>(sidx32);
+    if (K == 1) {
+        sbin[lane] = slot0.bin;
+        sval[lane] = make_float4(slot0.re, slot0.im, slot0.inc, 0.f);
     }
     wave_sync();
+    int my_bin[MAX_BOUNCES];
+#pragma unroll
+    for (int k = 0; k < K; ++k) my_bin[k] = sbin[k * WAVE + lane];
     const int nr = a.n_r;
     const int bl = lane >> a.log2_nr;          // beam within the wave
     const int base_lane = bl << a.log2_nr;
@@ -464,7 +704,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
     for (int k = 0; k < K; ++k) {
         head[k] = false;
         sum[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        int mb = slot[k].bin;
+        int mb = my_bin[k];
         if (mb < 0) continue;
         int me = j * K + k;
         bool hd = true;
@@ -497,7 +737,6 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
     const int64_t wave_beam0 = (((int64_t)tile * BLOCK) + wave * WAVE) >> a.log2_nr;
     const int nb = a.n_bins;
     const int idx_words = (nb + 1) / 2;
-    uint32_t *sidx32 = W + ACC_IDX_BASE;
     for (int q = 0; q < bpw; ++q) {
         const int64_t gb = wave_beam0 + q;
         if (gb >= a.n_beams) break;
@@ -506,7 +745,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
         if (bl == q) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (head[k]) sidx[slot[k].bin] = (uint16_t)(k * WAVE + lane + 1);
+                if (head[k]) sidx[my_bin[k]] = (uint16_t)(k * WAVE + lane + 1);
         }
         wave_sync();
         float2 *col = a.volume + (size_t)gb * nb;
@@ -546,7 +785,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
             for (int k = 0; k < K; ++k) {
                 key[k] = 0ull;
                 if (bl != q || !head[k]) continue;
-                const int bin = slot[k].bin;
+                const int bin = my_bin[k];
                 const float4 v = sum[k];
                 const float p = v.x * v.x + v.y * v.y + n0;
                 float pl = n0, pr = n0;
@@ -606,10 +845,11 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
     }
 }
 
-int ping_wave_words(int depth, int n_bins)
+int ping_wave_words(int depth, int n_bins, int K)
 {
-    int acc = ACC_IDX_BASE + (n_bins + 1) / 2;
     int stk = depth * WAVE;
+    if (K > 1) return stk + 5 * WAVE * K;      // stack + slots; the column index reuses the stack
+    int acc = ACC_IDX_BASE + (n_bins + 1) / 2;
     return acc > stk ? acc : stk;
 }
 
@@ -619,24 +859,24 @@ hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s)
     int nblocks = (int)((threads + BLOCK - 1) / BLOCK);
     if (nblocks == 0) return hipSuccess;
     int depth = stack_depth <= 32 ? 32 : 64;
-    int ww = ping_wave_words(depth, a.n_bins);
+    int ww = ping_wave_words(depth, a.n_bins, a.K);
     size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
-#define SONAR_LAUNCH(D, KK) hipLaunchKernelGGL((k_ping<D, KK>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww)
-    if (depth == 32) {
-        switch (a.K) {
-            case 1: SONAR_LAUNCH(32, 1); break;
-            case 2: SONAR_LAUNCH(32, 2); break;
-            case 3: SONAR_LAUNCH(32, 3); break;
-            default: SONAR_LAUNCH(32, 4); break;
-        }
-    } else {
-        switch (a.K) {
-            case 1: SONAR_LAUNCH(64, 1); break;
-            case 2: SONAR_LAUNCH(64, 2); break;
-            case 3: SONAR_LAUNCH(64, 3); break;
-            default: SONAR_LAUNCH(64, 4); break;
-        }
+#define SONAR_LAUNCH(D, KK, AR) \
+    hipLaunchKernelGGL((k_ping<D, KK, AR>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww)
+#define SONAR_LAUNCH_K(D, AR)                     \
+    switch (a.K) {                                \
+        case 1: SONAR_LAUNCH(D, 1, AR); break;    \
+        case 2: SONAR_LAUNCH(D, 2, AR); break;    \
+        case 3: SONAR_LAUNCH(D, 3, AR); break;    \
+        default: SONAR_LAUNCH(D, 4, AR); break;   \
     }
+    const bool arc = a.g != 0.0;
+    if (depth == 32) {
+        if (arc) { SONAR_LAUNCH_K(32, true) } else { SONAR_LAUNCH_K(32, false) }
+    } else {
+        if (arc) { SONAR_LAUNCH_K(64, true) } else { SONAR_LAUNCH_K(64, false) }
+    }
+#undef SONAR_LAUNCH_K
 #undef SONAR_LAUNCH
     return hipGetLastError();
 }
