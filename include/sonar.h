@@ -215,6 +215,77 @@ sonar_status sonar_ping_detect(const sonar_scene *scene, const sonar_params *par
                                const sonar_cfar *cfar, sonar_cf32 *volume, sonar_point *points, int32_t capacity,
                                int32_t *dev_count, void *workspace, size_t workspace_bytes, sonar_stream stream);
 
+/* ---------------------------------------------------------------------- */
+/* Batches: hundreds of pings with their own poses, beam layouts and rays per
+ * beam in one persistent launch. Work items are (ping, tile of 256 rays);
+ * persistent workgroups pop them from one device counter. All pings of a
+ * batch share the scene, max_bounces and the medium type (c_grad zero or
+ * not). */
+
+/* Host summary of a prepared batch (filled by sonar_batch_prepare). */
+typedef struct {
+    int32_t n_pings, max_bounces, arc, max_bins;
+    int64_t total_tiles, total_rays;
+} sonar_batch_plan;
+
+/* Launch knobs: persistent workgroups per compute unit (0: the occupancy
+ * limit) and 256-ray tiles taken per queue pop (0: 1). */
+typedef struct {
+    int32_t blocks_per_cu, tiles_per_item;
+} sonar_batch_options;
+
+typedef struct sonar_graph sonar_graph;   /* an instantiated HIP graph of one batch */
+
+/* Bytes of one ping descriptor (device-side argument block). */
+size_t sonar_batch_desc_bytes(void);
+
+/* Bytes of batch workspace for n_pings (queue counter and per-ping device
+ * clock stamps). */
+size_t sonar_batch_workspace_size(int32_t n_pings);
+
+/* Fills n_pings descriptors into the host buffer `host_desc`
+ * (n_pings * sonar_batch_desc_bytes() bytes) from per-ping parameters, poses
+ * and device output volumes (volumes[i]: complex64 of ping i's layout), and
+ * the plan. The caller copies host_desc to device memory; the descriptors may
+ * be rewritten there between launches (new poses) as long as each ping keeps
+ * its layout. SONAR_E_INVALID if pings disagree on max_bounces or medium
+ * type, or any parameter fails sonar_ping's validation. */
+sonar_status sonar_batch_prepare(const sonar_scene *scene, int32_t n_pings, const sonar_params *params,
+                                 const sonar_pose *poses, sonar_cf32 *const *volumes, void *host_desc,
+                                 sonar_batch_plan *plan);
+
+/* Runs a prepared batch: a reset kernel, then the persistent ping kernel.
+ * `dev_desc` are the descriptors in device memory. Allocates nothing, so it
+ * can be captured in a graph. Asynchronous on `stream`. */
+sonar_status sonar_ping_batch(const sonar_scene *scene, const sonar_batch_plan *plan, const void *dev_desc,
+                              const sonar_batch_options *options, void *workspace, size_t workspace_bytes,
+                              sonar_stream stream);
+
+/* Copies the per-ping first-start and last-finish device clock stamps
+ * (100 MHz constant clock, s_memrealtime) of the last batch run on
+ * `workspace` into host arrays; synchronises `stream`. */
+sonar_status sonar_batch_stamps(const void *workspace, int32_t n_pings, uint64_t *start, uint64_t *finish,
+                                sonar_stream stream);
+
+/* Captures one batch launch (reset + persistent kernel) into a HIP graph and
+ * instantiates it; sonar_graph_launch replays it on any stream. The graph
+ * keeps the descriptor and workspace pointers: update descriptors in place. */
+sonar_status sonar_batch_graph_create(const sonar_scene *scene, const sonar_batch_plan *plan, const void *dev_desc,
+                                      const sonar_batch_options *options, void *workspace, size_t workspace_bytes,
+                                      sonar_graph **out);
+sonar_status sonar_graph_launch(sonar_graph *graph, sonar_stream stream);
+void sonar_graph_free(sonar_graph *graph);
+
+/* Measures the batch under every launch-knob candidate (persistent blocks per
+ * compute unit up to the occupancy limit x tiles per pop in {1, 2, 4}) with
+ * device events and returns the fastest in `best` and its time in
+ * `best_ms`. When the environment variable SONAR_AUTOTUNE_CACHE names a file,
+ * a result cached there for the same device, scene size and plan is returned
+ * without measuring, and new results are appended. Synchronous. */
+sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_plan *plan, const void *dev_desc,
+                                  void *workspace, size_t workspace_bytes, sonar_stream stream,
+                                  sonar_batch_options *best, float *best_ms);
+
 /* Synchronises `stream` and reports device-side errors recorded by calls
  * that used `scene` (SONAR_E_STACK if a traversal ran out of stack). Clears
  * the record. */

@@ -9,8 +9,17 @@
 
 #include "internal.hpp"
 
+#include <stdlib.h>
+
+#include <string>
+
 struct sonar_scene {
     sonar::Scene s;
+};
+
+struct sonar_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -380,6 +389,250 @@ sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, con
         if (e == hipSuccess) e = sonar::launch_detect(da, s);
     }
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping/detect launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
+
+size_t sonar_batch_desc_bytes(void) { return sizeof(sonar::PingArgs); }
+
+size_t sonar_batch_workspace_size(int32_t n_pings)
+{
+    if (n_pings < 1) return 0;
+    return 256 + 2 * sizeof(unsigned long long) * (size_t)n_pings;
+}
+
+sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_params *params,
+                                 const sonar_pose *poses, sonar_cf32 *const *volumes, void *host_desc,
+                                 sonar_batch_plan *plan)
+{
+    g_err[0] = 0;
+    if (!sc || !params || !poses || !volumes || !host_desc || !plan)
+        return fail(SONAR_E_INVALID, "scene, params, poses, volumes, host_desc and plan are required");
+    if (n < 1) return fail(SONAR_E_INVALID, "n_pings must be >= 1");
+    sonar::PingArgs *d = reinterpret_cast<sonar::PingArgs *>(host_desc);
+    int64_t tiles = 0, rays = 0;
+    int max_bins = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        sonar_status st = fill_ping_args(sc, &params[i], &poses[i], volumes[i], nullptr, nullptr, nullptr, nullptr,
+                                         &d[i]);
+        if (st != SONAR_OK) {
+            char tmp[512];
+            snprintf(tmp, sizeof(tmp), "ping %d: %s", i, g_err);
+            return fail(st, "%s", tmp);
+        }
+        if (params[i].max_bounces != params[0].max_bounces || (params[i].c_grad != 0.0) != (params[0].c_grad != 0.0))
+            return fail(SONAR_E_INVALID, "ping %d: a batch needs one max_bounces and one medium type", i);
+        int64_t t = (d[i].n_rays + 255) / 256;
+        if (tiles + t > 0x7FFFFFFF) return fail(SONAR_E_INVALID, "batch too large");
+        d[i].tile_offset = (int)tiles;
+        d[i].n_tiles = (int)t;
+        tiles += t;
+        rays += d[i].n_rays;
+        if (d[i].n_bins > max_bins) max_bins = d[i].n_bins;
+    }
+    plan->n_pings = n;
+    plan->max_bounces = params[0].max_bounces;
+    plan->arc = params[0].c_grad != 0.0;
+    plan->max_bins = max_bins;
+    plan->total_tiles = tiles;
+    plan->total_rays = rays;
+    return SONAR_OK;
+}
+
+static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_plan *plan, const void *dev_desc,
+                                      const sonar_batch_options *opt, void *ws, size_t ws_bytes,
+                                      sonar::BatchLaunch *b)
+{
+    if (!sc || !plan || !dev_desc || !ws) return fail(SONAR_E_INVALID, "scene, plan, dev_desc and workspace are required");
+    if (plan->n_pings < 1 || plan->max_bounces < 1 || plan->max_bounces > sonar::MAX_BOUNCES ||
+        plan->max_bins < 1 || plan->max_bins > sonar::MAX_BINS || plan->total_tiles < 1)
+        return fail(SONAR_E_INVALID, "plan is not one filled by sonar_batch_prepare");
+    if (ws_bytes < sonar_batch_workspace_size(plan->n_pings)) return fail(SONAR_E_INVALID, "workspace too small");
+    if (opt && (opt->blocks_per_cu < 0 || opt->blocks_per_cu > 64 || opt->tiles_per_item < 0 || opt->tiles_per_item > 64))
+        return fail(SONAR_E_INVALID, "options out of range");
+    char *w = (char *)ws;
+    b->desc = reinterpret_cast<const sonar::PingArgs *>(dev_desc);
+    b->n_pings = plan->n_pings;
+    b->K = plan->max_bounces;
+    b->arc = plan->arc != 0;
+    b->depth = sc->s.depth;
+    b->max_bins = plan->max_bins;
+    b->total_tiles = plan->total_tiles;
+    b->queue = reinterpret_cast<uint32_t *>(w);
+    b->t0 = reinterpret_cast<unsigned long long *>(w + 256);
+    b->t1 = b->t0 + plan->n_pings;
+    b->blocks_per_cu = opt ? opt->blocks_per_cu : 0;
+    b->tiles_per_item = opt && opt->tiles_per_item > 0 ? opt->tiles_per_item : 1;
+    return SONAR_OK;
+}
+
+sonar_status sonar_ping_batch(const sonar_scene *sc, const sonar_batch_plan *plan, const void *dev_desc,
+                              const sonar_batch_options *opt, void *ws, size_t ws_bytes, sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar::BatchLaunch b;
+    sonar_status st = batch_launch_args(sc, plan, dev_desc, opt, ws, ws_bytes, &b);
+    if (st != SONAR_OK) return st;
+    hipError_t e = sonar::launch_ping_batch(b, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "batch launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
+sonar_status sonar_batch_stamps(const void *ws, int32_t n, uint64_t *start, uint64_t *finish, sonar_stream stream)
+{
+    if (!ws || n < 1 || !start || !finish) return fail(SONAR_E_INVALID, "workspace, n_pings and outputs are required");
+    hipStream_t s = (hipStream_t)stream;
+    const char *w = (const char *)ws;
+    if (hipMemcpyAsync(start, w + 256, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(finish, w + 256 + sizeof(uint64_t) * n, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(SONAR_E_DEVICE, "stamp copy failed");
+    return SONAR_OK;
+}
+
+sonar_status sonar_batch_graph_create(const sonar_scene *sc, const sonar_batch_plan *plan, const void *dev_desc,
+                                      const sonar_batch_options *opt, void *ws, size_t ws_bytes, sonar_graph **out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(SONAR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    sonar::BatchLaunch b;
+    sonar_status st = batch_launch_args(sc, plan, dev_desc, opt, ws, ws_bytes, &b);
+    if (st != SONAR_OK) return st;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return fail(SONAR_E_DEVICE, "capture stream creation failed");
+    sonar_graph *g = new (std::nothrow) sonar_graph();
+    if (!g) {
+        (void)hipStreamDestroy(cs);
+        return fail(SONAR_E_NOMEM, "host allocation failed");
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = sonar::launch_ping_batch(b, cs);
+        e = hipStreamEndCapture(cs, &g->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return fail(SONAR_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return SONAR_OK;
+}
+
+sonar_status sonar_graph_launch(sonar_graph *g, sonar_stream stream)
+{
+    if (!g || !g->exec) return fail(SONAR_E_INVALID, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "graph launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
+void sonar_graph_free(sonar_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+static std::string tune_key(const sonar_scene *sc, const sonar_batch_plan *plan)
+{
+    hipDeviceProp_t prop;
+    char name[128] = "unknown";
+    if (hipGetDeviceProperties(&prop, sc->s.device) == hipSuccess) {
+        snprintf(name, sizeof(name), "%s", prop.gcnArchName);
+        for (char *c = name; *c; ++c)
+            if (*c == ' ' || *c == ':') *c = '_';
+    }
+    char key[320];
+    snprintf(key, sizeof(key), "%s/tri%lld/d%d/p%d/k%d/a%d/b%d/t%lld", name, (long long)sc->s.n_tri, sc->s.depth,
+             plan->n_pings, plan->max_bounces, plan->arc, plan->max_bins, (long long)plan->total_tiles);
+    return key;
+}
+
+sonar_status sonar_batch_autotune(const sonar_scene *sc, const sonar_batch_plan *plan, const void *dev_desc,
+                                  void *ws, size_t ws_bytes, sonar_stream stream, sonar_batch_options *best,
+                                  float *best_ms)
+{
+    g_err[0] = 0;
+    if (!best || !best_ms) return fail(SONAR_E_INVALID, "best and best_ms are required");
+    sonar::BatchLaunch b;
+    sonar_status st = batch_launch_args(sc, plan, dev_desc, nullptr, ws, ws_bytes, &b);
+    if (st != SONAR_OK) return st;
+    const std::string key = tune_key(sc, plan);
+    const char *cache = getenv("SONAR_AUTOTUNE_CACHE");
+    if (cache && *cache) {
+        FILE *f = fopen(cache, "r");
+        if (f) {
+            char k[400];
+            int bpc, tpi;
+            float ms;
+            bool found = false;
+            while (fscanf(f, "%399s %d %d %f", k, &bpc, &tpi, &ms) == 4) {
+                if (key == k) {
+                    best->blocks_per_cu = bpc;
+                    best->tiles_per_item = tpi;
+                    *best_ms = ms;
+                    found = true;
+                }
+            }
+            fclose(f);
+            if (found) return SONAR_OK;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int occ = sonar::batch_max_blocks_per_cu(b);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(SONAR_E_DEVICE, "event creation failed");
+    float bestv = 1e30f;
+    sonar_batch_options bo = {0, 1};
+    const int tpis[3] = {1, 2, 4};
+    for (int bpc = 1; bpc <= occ; ++bpc) {
+        for (int ti = 0; ti < 3; ++ti) {
+            b.blocks_per_cu = bpc;
+            b.tiles_per_item = tpis[ti];
+            hipError_t e = sonar::launch_ping_batch(b, s);   // warm-up
+            float total = 0.f;
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess) e = sonar::launch_ping_batch(b, s);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                total += ms;
+            }
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return fail(SONAR_E_DEVICE, "autotune run: %s", hipGetErrorString(e));
+            }
+            const float ms = total / 3.f;
+            if (ms < bestv) {
+                bestv = ms;
+                bo.blocks_per_cu = bpc;
+                bo.tiles_per_item = tpis[ti];
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *best = bo;
+    *best_ms = bestv;
+    if (cache && *cache) {
+        FILE *f = fopen(cache, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %.6f\n", key.c_str(), bo.blocks_per_cu, bo.tiles_per_item, bestv);
+            fclose(f);
+        }
+    }
     return SONAR_OK;
 }
 

@@ -81,7 +81,27 @@ struct PingArgs {
     int det_G, det_T, det_M;
     float det_n0;
     double det_alpha[2 * 64 + 1];
+    // batch bookkeeping (descriptor of one ping in a batch)
+    int tile_offset;         // first global tile of this ping
+    int n_tiles;             // 256-ray tiles of this ping
 };
+
+// One batch launch: descriptors in device memory, one kernel class.
+struct BatchLaunch {
+    const PingArgs *desc;
+    int n_pings;
+    int K;
+    bool arc;
+    int depth;               // hierarchy depth (selects the stack size)
+    int max_bins;            // largest n_range of the batch (LDS sizing)
+    int64_t total_tiles;
+    uint32_t *queue;
+    unsigned long long *t0, *t1;
+    int blocks_per_cu;       // persistent grid = CUs x this (0: occupancy limit)
+    int tiles_per_item;      // tiles popped per queue operation
+};
+hipError_t launch_ping_batch(const BatchLaunch &b, hipStream_t s);
+int batch_max_blocks_per_cu(const BatchLaunch &b);
 
 // Host-side launchers (one per translation unit).
 hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s);

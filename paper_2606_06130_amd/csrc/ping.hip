@@ -455,15 +455,14 @@ __device__ __forceinline__ Conn connect(d3 P, d3 S, double g, double c0)
 
 }  // namespace
 
+// The ping body for one tile of 256 consecutive rays (4 wavefronts). `a` is
+// the ping's argument block (kernel arguments, or a batch descriptor in
+// device memory); `W` is this wavefront's LDS area.
 template <int DEPTH, int K, bool ARC>
-__global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
+__device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uint32_t *__restrict__ W)
 {
-    extern __shared__ uint32_t lds[];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x / WAVE;
-    uint32_t *W = lds + (size_t)wave * wave_words;
-
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t gid = (int64_t)tile * BLOCK + threadIdx.x;
     const int64_t beam = gid >> a.log2_nr;
     const int j = (int)(gid & (a.n_r - 1));
@@ -845,6 +844,73 @@ __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
     }
 }
 
+template <int DEPTH, int K, bool ARC>
+__global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
+{
+    extern __shared__ uint32_t lds[];
+    uint32_t *W = lds + (size_t)(threadIdx.x / WAVE) * wave_words;
+    ping_tile<DEPTH, K, ARC>(a, xcd_remap(blockIdx.x, gridDim.x), W);
+}
+
+// Persistent batch: every block pops (ping, tile) items from one device
+// counter until the queue is empty; per-ping first-start and last-finish
+// stamps come from the constant-rate device clock. All pings of a batch share
+// the hierarchy depth class, bounce count and medium type (template
+// arguments); layouts, rays per beam, poses and outputs come per ping from
+// its descriptor.
+template <int DEPTH, int K, bool ARC>
+__global__ __launch_bounds__(BLOCK) void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
+                                                      uint32_t *__restrict__ queue, unsigned long long *__restrict__ t0,
+                                                      unsigned long long *__restrict__ t1, int wave_words,
+                                                      int tiles_per_item)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ int s_item;
+    uint32_t *W = lds + (size_t)(threadIdx.x / WAVE) * wave_words;
+    const PingArgs &last = desc[n_pings - 1];
+    const int total_tiles = last.tile_offset + last.n_tiles;
+    const int n_items = (total_tiles + tiles_per_item - 1) / tiles_per_item;
+    while (true) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        for (int q = 0; q < tiles_per_item; ++q) {
+            const int gt = item * tiles_per_item + q;
+            if (gt >= total_tiles) break;
+            // the ping holding global tile gt: last descriptor with tile_offset <= gt
+            int lo = 0, hi = n_pings - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (desc[mid].tile_offset <= gt) lo = mid;
+                else hi = mid - 1;
+            }
+            const PingArgs &a = desc[lo];
+            unsigned long long start = __builtin_amdgcn_s_memrealtime();
+            ping_tile<DEPTH, K, ARC>(a, gt - a.tile_offset, W);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned long long end = __builtin_amdgcn_s_memrealtime();
+                atomicMin(&t0[lo], start);
+                atomicMax(&t1[lo], end);
+            }
+        }
+    }
+}
+
+// Resets the batch queue and the per-ping stamps (a kernel, not a memset, so
+// that graph replays always start from the same state).
+__global__ void k_batch_reset(uint32_t *queue, unsigned long long *t0, unsigned long long *t1, int n_pings)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *queue = 0u;
+    if (i < n_pings) {
+        t0[i] = ~0ull;
+        t1[i] = 0ull;
+    }
+}
+
 int ping_wave_words(int depth, int n_bins, int K)
 {
     int stk = depth * WAVE;
@@ -879,6 +945,69 @@ hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s)
 #undef SONAR_LAUNCH_K
 #undef SONAR_LAUNCH
     return hipGetLastError();
+}
+
+template <int D, int KK, bool AR>
+static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int *occ)
+{
+    const int ww = ping_wave_words(D, b.max_bins, KK);
+    const size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
+    if (query) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR>),
+                                                            BLOCK, shmem);
+    }
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    int per_cu = b.blocks_per_cu;
+    if (per_cu <= 0) {
+        int o = 1;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR>),
+                                                         BLOCK, shmem);
+        if (e != hipSuccess) return e;
+        per_cu = o > 0 ? o : 1;
+    }
+    const int tpi = b.tiles_per_item > 0 ? b.tiles_per_item : 1;
+    const int64_t items = (b.total_tiles + tpi - 1) / tpi;
+    int64_t grid = (int64_t)cus * per_cu;
+    if (grid > items) grid = items;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_batch_reset, dim3((b.n_pings + 255) / 256), dim3(256), 0, s, b.queue, b.t0, b.t1,
+                       b.n_pings);
+    hipLaunchKernelGGL((k_ping_batch<D, KK, AR>), dim3((unsigned)grid), dim3(BLOCK), shmem, s, b.desc, b.n_pings,
+                       b.queue, b.t0, b.t1, ww, tpi);
+    return hipGetLastError();
+}
+
+static hipError_t batch_dispatch(const BatchLaunch &b, hipStream_t s, bool query, int *occ)
+{
+#define SONAR_BK(D, AR)                                           \
+    switch (b.K) {                                                \
+        case 1: return batch_go<D, 1, AR>(b, s, query, occ);      \
+        case 2: return batch_go<D, 2, AR>(b, s, query, occ);      \
+        case 3: return batch_go<D, 3, AR>(b, s, query, occ);      \
+        default: return batch_go<D, 4, AR>(b, s, query, occ);     \
+    }
+    if (b.depth <= 32) {
+        if (b.arc) { SONAR_BK(32, true) } else { SONAR_BK(32, false) }
+    } else {
+        if (b.arc) { SONAR_BK(64, true) } else { SONAR_BK(64, false) }
+    }
+#undef SONAR_BK
+}
+
+hipError_t launch_ping_batch(const BatchLaunch &b, hipStream_t s)
+{
+    if (b.n_pings <= 0 || b.total_tiles <= 0) return hipSuccess;
+    return batch_dispatch(b, s, false, nullptr);
+}
+
+int batch_max_blocks_per_cu(const BatchLaunch &b)
+{
+    int occ = 1;
+    if (batch_dispatch(b, nullptr, true, &occ) != hipSuccess) return 1;
+    return occ > 0 ? occ : 1;
 }
 
 }  // namespace sonar

@@ -25,7 +25,10 @@ SONAR_E_UNSUPPORTED = -5
 # Every symbol include/sonar.h declares.
 EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "sonar_ping",
            "sonar_detect_workspace_size", "sonar_detect", "sonar_ping_detect", "sonar_device_status",
-           "sonar_status_string", "sonar_last_error", "sonar_params_from_resolution")
+           "sonar_status_string", "sonar_last_error", "sonar_params_from_resolution",
+           "sonar_batch_desc_bytes", "sonar_batch_workspace_size", "sonar_batch_prepare", "sonar_ping_batch",
+           "sonar_batch_stamps", "sonar_batch_graph_create", "sonar_graph_launch", "sonar_graph_free",
+           "sonar_batch_autotune")
 
 
 class SonarError(RuntimeError):
@@ -70,6 +73,15 @@ class sonar_scene_info(C.Structure):
                 ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64)]
 
 
+class sonar_batch_plan(C.Structure):
+    _fields_ = [("n_pings", C.c_int32), ("max_bounces", C.c_int32), ("arc", C.c_int32), ("max_bins", C.c_int32),
+                ("total_tiles", C.c_int64), ("total_rays", C.c_int64)]
+
+
+class sonar_batch_options(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("tiles_per_item", C.c_int32)]
+
+
 POINT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("db", "<f4"), ("beam", "<i4"), ("bin", "<i4")])
 
 _lib = None
@@ -106,6 +118,28 @@ def lib():
         L.sonar_status_string.argtypes = [C.c_int]
         L.sonar_last_error.restype = C.c_char_p
         L.sonar_last_error.argtypes = []
+        L.sonar_batch_desc_bytes.restype = C.c_size_t
+        L.sonar_batch_desc_bytes.argtypes = []
+        L.sonar_batch_workspace_size.restype = C.c_size_t
+        L.sonar_batch_workspace_size.argtypes = [C.c_int32]
+        L.sonar_batch_prepare.restype = C.c_int
+        L.sonar_batch_prepare.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          P(sonar_batch_plan)]
+        L.sonar_ping_batch.restype = C.c_int
+        L.sonar_ping_batch.argtypes = [C.c_void_p, P(sonar_batch_plan), C.c_void_p, P(sonar_batch_options),
+                                       C.c_void_p, C.c_size_t, C.c_void_p]
+        L.sonar_batch_stamps.restype = C.c_int
+        L.sonar_batch_stamps.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.sonar_batch_graph_create.restype = C.c_int
+        L.sonar_batch_graph_create.argtypes = [C.c_void_p, P(sonar_batch_plan), C.c_void_p, P(sonar_batch_options),
+                                               C.c_void_p, C.c_size_t, P(C.c_void_p)]
+        L.sonar_graph_launch.restype = C.c_int
+        L.sonar_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+        L.sonar_graph_free.restype = None
+        L.sonar_graph_free.argtypes = [C.c_void_p]
+        L.sonar_batch_autotune.restype = C.c_int
+        L.sonar_batch_autotune.argtypes = [C.c_void_p, P(sonar_batch_plan), C.c_void_p, C.c_void_p, C.c_size_t,
+                                           C.c_void_p, P(sonar_batch_options), P(C.c_float)]
         L.sonar_params_from_resolution.restype = C.c_int
         L.sonar_params_from_resolution.argtypes = [C.c_double] * 7 + [P(sonar_params)]
         _lib = L
@@ -284,3 +318,78 @@ def params_from_resolution(hfov, vfov, dth_h, dth_v, r_min, r_max, dr, base=None
     p = base if base is not None else sonar_params()
     _check(lib().sonar_params_from_resolution(hfov, vfov, dth_h, dth_v, r_min, r_max, dr, C.byref(p)))
     return p
+
+
+class Graph:
+    """An instantiated HIP graph of one batch launch."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self, stream=None):
+        _check(lib().sonar_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sonar_graph_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many pings (own pose, layout, rays per beam) in one persistent launch.
+
+    ``items`` is a list of (SensorConfig, Pose). Output volumes are allocated
+    here, one tensor per ping; descriptors live in device memory."""
+
+    def __init__(self, scene: Scene, items):
+        import torch
+        n = len(items)
+        self.scene = scene
+        self.items = items
+        self.volumes = [alloc_outputs(cfg)["volume"] for cfg, _ in items]
+        P = (sonar_params * n)(*[params_of(cfg) for cfg, _ in items])
+        Q = (sonar_pose * n)(*[pose_of(p) for _, p in items])
+        V = (C.c_void_p * n)(*[v.data_ptr() for v in self.volumes])
+        db = lib().sonar_batch_desc_bytes()
+        host = np.zeros(n * db, np.uint8)
+        self.plan = sonar_batch_plan()
+        _check(lib().sonar_batch_prepare(scene.handle, n, P, Q, V, host.ctypes.data, C.byref(self.plan)))
+        self.desc = torch.from_numpy(host).cuda()
+        self.workspace = torch.empty(lib().sonar_batch_workspace_size(n), dtype=torch.uint8, device="cuda")
+        self.n = n
+
+    def options(self, blocks_per_cu=0, tiles_per_item=0):
+        return sonar_batch_options(blocks_per_cu=blocks_per_cu, tiles_per_item=tiles_per_item)
+
+    def run(self, options=None, stream=None):
+        o = options if options is not None else self.options()
+        _check(lib().sonar_ping_batch(self.scene.handle, C.byref(self.plan), _dptr(self.desc), C.byref(o),
+                                      _dptr(self.workspace), self.workspace.numel(), _stream(stream)))
+
+    def graph(self, options=None) -> Graph:
+        o = options if options is not None else self.options()
+        h = C.c_void_p()
+        _check(lib().sonar_batch_graph_create(self.scene.handle, C.byref(self.plan), _dptr(self.desc), C.byref(o),
+                                              _dptr(self.workspace), self.workspace.numel(), C.byref(h)))
+        return Graph(h)
+
+    def autotune(self, stream=None):
+        best = sonar_batch_options()
+        ms = C.c_float()
+        _check(lib().sonar_batch_autotune(self.scene.handle, C.byref(self.plan), _dptr(self.desc),
+                                          _dptr(self.workspace), self.workspace.numel(), _stream(stream),
+                                          C.byref(best), C.byref(ms)))
+        return best, float(ms.value)
+
+    def stamps(self, stream=None):
+        """(start, finish) device clock stamps per ping, 100 MHz ticks."""
+        a = np.zeros(self.n, np.uint64)
+        b = np.zeros(self.n, np.uint64)
+        _check(lib().sonar_batch_stamps(_dptr(self.workspace), self.n, a.ctypes.data, b.ctypes.data, _stream(stream)))
+        return a, b

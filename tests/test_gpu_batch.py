@@ -1,0 +1,133 @@
+"""Batched pings: one persistent launch over (ping, tile) items, hipGraph
+replay and the launch-knob autotuner (needs an MI355X)."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2606_06130_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_06130_amd import sonar
+    return torch, sonar
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _mixed_items(base, n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    items = []
+    for i in range(n):
+        nh, nv = ((8, 4), (16, 8), (33, 7), (64, 32))[int(rng.integers(0, 4))]
+        nr = (1, 4, 8, 16)[int(rng.integers(0, 4))]
+        cfg = base.replace(n_h=nh, n_v=nv, rays_per_beam=nr)
+        yaw, pitch = rng.normal(0, 0.05), math.radians(55) + rng.normal(0, 0.05)
+        pos = (rng.normal(0, 0.3), rng.normal(0, 0.3), rng.normal(0, 0.2))
+        items.append((cfg, S.pose(pos, yaw, pitch, 0.0, ping=i)))
+    return items
+
+
+@pytest.mark.parametrize("physics", ["single", "multipath_gradient"])
+def test_batch_equals_individual_pings(physics):
+    torch, sonar = _gpu()
+    mesh = S.scene_seabed_boxes()
+    base = S.sensor_seabed_boxes()
+    if physics == "multipath_gradient":
+        base = base.replace(max_bounces=3, k_d=0.7, k_s=0.3, c_grad=0.05, n_range=512)
+    sc = sonar.Scene(mesh)
+    items = _mixed_items(base, 23, 7)
+    batch = sonar.Batch(sc, items)
+    batch.run(batch.options(blocks_per_cu=2, tiles_per_item=2))
+    torch.cuda.synchronize()
+    assert sc.status() == 0
+    nz = 0
+    for i, (cfg, pose) in enumerate(items):
+        ref = sonar.ping(sc, cfg, pose)["volume"]
+        torch.cuda.synchronize()
+        a, b = batch.volumes[i].view(torch.float32), ref.view(torch.float32)
+        assert torch.equal(a, b), (i, cfg.n_h, cfg.n_v, cfg.rays_per_beam)
+        nz += int(torch.count_nonzero(b))
+    assert nz > 0
+    start, finish = batch.stamps()
+    assert (finish > start).all()
+    assert (start != np.uint64(2**64 - 1)).all()
+
+
+def test_batch_graph_replay_matches_direct_launch():
+    torch, sonar = _gpu()
+    mesh = S.scene_seabed_boxes()
+    base = S.sensor_seabed_boxes().replace(max_bounces=2, k_d=0.7, k_s=0.3, c_grad=0.05)
+    sc = sonar.Scene(mesh)
+    items = _mixed_items(base, 12, 11)
+    batch = sonar.Batch(sc, items)
+    batch.run()
+    torch.cuda.synchronize()
+    want = [v.clone() for v in batch.volumes]
+    g = batch.graph(batch.options(blocks_per_cu=1, tiles_per_item=1))
+    for rep in range(3):
+        for v in batch.volumes:
+            v.fill_(complex(float("nan"), 0.0))       # eager work between replays
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, v in enumerate(batch.volumes):
+            assert torch.equal(v.view(torch.float32), want[i].view(torch.float32)), (rep, i)
+    # descriptors updated in place: a replay picks up new poses
+    items2 = [(cfg, S.Pose(tuple(np.asarray(p.position) + [0.0, 0.0, -0.5]), p.rot, p.ping)) for cfg, p in items]
+    other = sonar.Batch(sc, items2)
+    batch.desc.copy_(other.desc)
+    # the copied descriptors point at `other`'s volumes
+    g.launch()
+    torch.cuda.synchronize()
+    for i, (cfg, pose) in enumerate(items2):
+        ref = sonar.ping(sc, cfg, pose)["volume"]
+        torch.cuda.synchronize()
+        assert torch.equal(other.volumes[i].view(torch.float32), ref.view(torch.float32))
+    g.close()
+
+
+def test_autotune_choice_keeps_results(tmp_path):
+    torch, sonar = _gpu()
+    mesh = S.scene_seabed_boxes()
+    sc = sonar.Scene(mesh)
+    items = _mixed_items(S.sensor_seabed_boxes(), 16, 3)
+    batch = sonar.Batch(sc, items)
+    batch.run()
+    torch.cuda.synchronize()
+    want = [v.clone() for v in batch.volumes]
+    os.environ["SONAR_AUTOTUNE_CACHE"] = str(tmp_path / "tune.txt")
+    try:
+        best, ms = batch.autotune()
+        assert best.blocks_per_cu >= 1 and best.tiles_per_item in (1, 2, 4) and ms > 0
+        best2, ms2 = batch.autotune()          # cached
+        assert (best2.blocks_per_cu, best2.tiles_per_item, ms2) == (best.blocks_per_cu, best.tiles_per_item,
+                                                                   pytest.approx(ms, rel=1e-5))
+        assert (tmp_path / "tune.txt").read_text().strip()
+    finally:
+        del os.environ["SONAR_AUTOTUNE_CACHE"]
+    batch.run(best)
+    torch.cuda.synchronize()
+    for v, w in zip(batch.volumes, want):
+        assert torch.equal(v.view(torch.float32), w.view(torch.float32))
+    _log("autotuned", best.blocks_per_cu, best.tiles_per_item, ms)
+
+
+def test_batch_rejects_mixed_physics():
+    torch, sonar = _gpu()
+    sc = sonar.Scene(S.scene_seabed_boxes())
+    items = [(S.sensor_seabed_boxes(), S.pose_seabed_boxes()),
+             (S.sensor_seabed_boxes().replace(max_bounces=2), S.pose_seabed_boxes())]
+    with pytest.raises(sonar.SonarError) as e:
+        sonar.Batch(sc, items)
+    assert e.value.status == sonar.SONAR_E_INVALID
