@@ -147,6 +147,8 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
     a.phong_n = p->phong_n;
     a.c_ref = p->c0 + p->c_grad * q->position[2];
     a.c_hi = p->c0 + fabs(p->c_grad) * (fmax((double)sc->s.zabs_max, fabs(q->position[2])) + 1.0);
+    a.tan_h = p->hfov < M_PI ? tan(0.5 * p->hfov) : 0.0;
+    a.tan_v = tan(0.5 * p->vfov);
     a.seed = p->seed;
     a.ping = q->ping;
     a.beams_h = beams_h_of(p);

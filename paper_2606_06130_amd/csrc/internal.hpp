@@ -61,6 +61,7 @@ struct PingArgs {
     double f0, c0, g, alpha_db;
     double k_d, k_s, phong_n;
     double c_ref, c_hi;
+    double tan_h, tan_v;     // tan(hfov / 2) (when hfov < pi), tan(vfov / 2)
     uint64_t seed;
     uint32_t ping;
     int beams_h, beams_v, n_beams, n_r, log2_nr, na, ne;

@@ -516,7 +516,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         const bool masked = a.mask && ((a.mask[ray >> 5] >> (ray & 31)) & 1u);
         bool stop = false;
 
-#pragma unroll 1
+#pragma unroll
         for (int k = 0; k < K; ++k) {
             int rec_tri = -1, rec_vis = 0;
             int cbin = -1;
@@ -563,6 +563,9 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                             double phi = pr ? 0.0 : (double)tr.phi;
                             double sgn = pr ? -1.0 : 1.0;
 
+                            // Return path and contribution first, visibility last: only the
+                            // contribution and the continuation state stay live across the
+                            // any-hit traversal.
                             double L_back, T_back;
                             d3 w;
                             bool vis = true;
@@ -576,56 +579,49 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                                 T_back = cn.T;
                                 w = cn.w;
                                 // arrival direction (from S toward P) inside the field of view
-                                d3 av = cn.arrive * -1.0;
-                                double sx = a.rot[0] * av.x + a.rot[3] * av.y + a.rot[6] * av.z;
-                                double sy = a.rot[1] * av.x + a.rot[4] * av.y + a.rot[7] * av.z;
-                                double sz = a.rot[2] * av.x + a.rot[5] * av.y + a.rot[8] * av.z;
-                                double aza = atan2(sy, sx), ela = atan2(sz, sqrt(sx * sx + sy * sy));
-                                if (fabs(aza) > 0.5 * a.hfov || fabs(ela) > 0.5 * a.vfov) vis = false;
-                                if (vis && L_back > 2.0 * EPS_SELF) {
-                                    const Path64 cp =
-                                        ARC ? make_path(X, w, a.g, a.c0) : Path64{X, w, mk3(0, 0, 0), 0.0, false};
-                                    const Seg32 cs = make_seg(cp, EPS_SELF, L_back - EPS_SELF);
-                                    float sa2;
-                                    int hb = traverse<DEPTH, true, ARC>(a.nodes, a.tris, cs, id, W, lane, overflow,
-                                                                        sa2, a.max_steps);
-                                    if (hb >= 0) vis = false;
+                                const d3 av = cn.arrive * -1.0;
+                                const double sx = a.rot[0] * av.x + a.rot[3] * av.y + a.rot[6] * av.z;
+                                const double sy = a.rot[1] * av.x + a.rot[4] * av.y + a.rot[7] * av.z;
+                                const double sz = a.rot[2] * av.x + a.rot[5] * av.y + a.rot[8] * av.z;
+                                const double sxy = sqrt(sx * sx + sy * sy);
+                                if (a.hfov < M_PI) {
+                                    // |az| <= hfov / 2 and |el| <= vfov / 2 without inverse trigonometry
+                                    if (!(sx > 0.0 && fabs(sy) <= a.tan_h * sx)) vis = false;
+                                } else if (fabs(atan2(sy, sx)) > 0.5 * a.hfov) {
+                                    vis = false;
                                 }
+                                if (fabs(sz) > a.tan_v * sxy) vis = false;
                             }
-                            rec_vis = vis ? 1 : 0;
-                            if (vis) {
-                                double cos_o = dot3(np, w);
-                                if (cos_o > 0.0) {
-                                    double Tt = T_out + T_back;
-                                    double reff = a.c_ref * Tt / 2.0;
-                                    double x = (reff - a.r_min) / a.dr;
-                                    double fb = floor(x);
-                                    if (fb >= 0.0 && fb < (double)a.n_bins) {
-                                        double lobe = dot3(rh, w);
-                                        lobe = lobe > 0.0 ? lobe : 0.0;
-                                        double spec = ks != 0.0 ? ks * pow(lobe, a.phong_n) : 0.0;
-                                        double fsc = rho * (kd * cos_i * cos_o + spec);
-                                        double amp = Wt * sgn * sqrt(fsc) *
-                                                     exp(-a.alpha_db * (L_out + L_back) * LN10_OVER_20) /
-                                                     (L_out * L_back * a.n_r);
-                                        double cyc = a.f0 * Tt;
-                                        double ph = TWO_PI * (cyc - floor(cyc)) + phi;
-                                        ph -= TWO_PI * rint(ph / TWO_PI);
-                                        float sn, cs;
-                                        sincosf((float)ph, &sn, &cs);
-                                        cbin = (int)fb;
-                                        cre = (float)amp * cs;
-                                        cim = (float)amp * sn;
-                                        cinc = (float)(amp * amp);
-                                        if (k == 0) {
-                                            gfeat[0] = (float)(reff / a.r_max);
-                                            gfeat[1] = (float)cos_i;
-                                            gfeat[2] = (float)rho;
-                                            gfeat[3] = (float)np.x;
-                                            gfeat[4] = (float)np.y;
-                                            gfeat[5] = (float)np.z;
-                                            gfeat[6] = 1.f;
-                                        }
+                            double cos_o = dot3(np, w);
+                            if (vis && cos_o > 0.0) {
+                                const double Tt = T_out + T_back;
+                                const double reff = a.c_ref * Tt / 2.0;
+                                const double fb = floor((reff - a.r_min) / a.dr);
+                                if (fb >= 0.0 && fb < (double)a.n_bins) {
+                                    float lobe = (float)dot3(rh, w);
+                                    lobe = lobe > 0.f ? lobe : 0.f;
+                                    const double spec = ks != 0.0 ? ks * (double)powf(lobe, (float)a.phong_n) : 0.0;
+                                    const double fsc = rho * (kd * cos_i * cos_o + spec);
+                                    const double att =
+                                        (double)expf((float)(-a.alpha_db * (L_out + L_back) * LN10_OVER_20));
+                                    const double amp = Wt * sgn * sqrt(fsc) * att / (L_out * L_back * a.n_r);
+                                    const double cyc = a.f0 * Tt;
+                                    double ph = TWO_PI * (cyc - floor(cyc)) + phi;
+                                    ph -= TWO_PI * rint(ph / TWO_PI);
+                                    float sn, cs;
+                                    sincosf((float)ph, &sn, &cs);
+                                    cbin = (int)fb;
+                                    cre = (float)amp * cs;
+                                    cim = (float)amp * sn;
+                                    cinc = (float)(amp * amp);
+                                    if (k == 0) {
+                                        gfeat[0] = (float)(reff / a.r_max);
+                                        gfeat[1] = (float)cos_i;
+                                        gfeat[2] = (float)rho;
+                                        gfeat[3] = (float)np.x;
+                                        gfeat[4] = (float)np.y;
+                                        gfeat[5] = (float)np.z;
+                                        gfeat[6] = 1.f;
                                     }
                                 }
                             }
@@ -639,6 +635,21 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                                 d = rh;
                                 prev = id;
                             }
+                            // visibility of the connection: any hit other than this facet
+                            if (k > 0 && vis && L_back > 2.0 * EPS_SELF) {
+                                const Path64 cp =
+                                    ARC ? make_path(X, w, a.g, a.c0) : Path64{X, w, mk3(0, 0, 0), 0.0, false};
+                                const Seg32 cs = make_seg(cp, EPS_SELF, L_back - EPS_SELF);
+                                float sa2;
+                                int hb = traverse<DEPTH, true, ARC>(a.nodes, a.tris, cs, id, W, lane, overflow, sa2,
+                                                                    a.max_steps);
+                                if (hb >= 0) {
+                                    vis = false;
+                                    cbin = -1;
+                                    cre = cim = cinc = 0.f;
+                                }
+                            }
+                            rec_vis = vis ? 1 : 0;
                         }
                     }
                 }
