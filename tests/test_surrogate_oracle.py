@@ -1,0 +1,89 @@
+"""Pins of the FP64 surrogate oracle: finite differences, the DCT against the
+library routine and its orthonormality, im2col by brute force."""
+import numpy as np
+import pytest
+from scipy import fft
+
+from oracle import surrogate as SO
+
+
+def test_parameter_count():
+    assert SO.param_count() == 168768
+
+
+def test_im2col_brute_force():
+    rng = np.random.Generator(np.random.PCG64(1))
+    g = rng.normal(size=(2, 5, 6, 8))
+    X = SO.im2col(g)
+    assert X.shape == (60, 63)
+    for n in range(2):
+        for v in range(5):
+            for h in range(6):
+                row = X[n * 30 + v * 6 + h]
+                q = 0
+                for dv in (-1, 0, 1):
+                    for dh in (-1, 0, 1):
+                        vv, hh = v + dv, h + dh
+                        want = g[n, vv, hh, :7] if 0 <= vv < 5 and 0 <= hh < 6 else np.zeros(7)
+                        np.testing.assert_array_equal(row[q:q + 7], want)
+                        q += 7
+
+
+def test_gradients_match_central_differences():
+    rng = np.random.Generator(np.random.PCG64(2))
+    theta = SO.init_params(3).astype(np.float64)
+    theta += rng.normal(0, 0.01, theta.size)                  # nonzero biases
+    g = rng.uniform(-1, 1, size=(1, 4, 5, 8))
+    t = rng.normal(size=(20, 64))
+    loss, grad, _ = SO.loss_and_grad(theta, g, t)
+    idx = rng.choice(theta.size, 60, replace=False)
+    # include entries of every layer's weights and biases
+    offs = np.cumsum([0] + [k * n + n for k, n in SO.LAYERS])
+    for a, b in zip(offs[:-1], offs[1:]):
+        idx = np.concatenate([idx, [a, b - 1]])
+    h = 1e-6
+    for i in idx:
+        tp = theta.copy()
+        tp[i] += h
+        tm = theta.copy()
+        tm[i] -= h
+        lp = SO.loss_and_grad(tp, g, t)[0]
+        lm = SO.loss_and_grad(tm, g, t)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(abs(fd), 1e-3), (i, fd, grad[i])
+
+
+def test_dct_matches_library_and_is_orthonormal():
+    n = 1024
+    C = SO.dct_basis(n, n)
+    x = np.random.Generator(np.random.PCG64(4)).normal(size=(3, n))
+    np.testing.assert_allclose(x @ C.T, fft.dct(x, type=2, norm="ortho", axis=-1), atol=1e-12)
+    np.testing.assert_allclose(C @ C.T, np.eye(n), atol=1e-12)           # orthonormal -> IDCT(DCT(x)) = x
+    np.testing.assert_allclose((x @ C.T) @ C, x, atol=1e-12)
+    c = x @ C.T
+    np.testing.assert_allclose((c ** 2).sum(-1), (x ** 2).sum(-1), rtol=1e-12)   # Parseval
+    e = np.zeros(n)
+    e[5] = 1.0
+    np.testing.assert_allclose(e @ C, C[5])                               # a basis vector maps back
+    np.testing.assert_allclose(C[5] @ C.T, e, atol=1e-12)                  # and to a delta
+
+
+def test_truncated_profile_is_projection():
+    rng = np.random.Generator(np.random.PCG64(5))
+    i1 = rng.exponential(1e-8, (4, 1024))
+    im = rng.exponential(1e-9, (4, 1024)) * (rng.random((4, 1024)) < 0.3)
+    c = SO.residual_coefficients(i1, im)
+    prof = SO.profile_from_coefficients(i1, c)
+    res = SO.residual_db(i1, im)
+    # the truncated reconstruction is the least-squares projection onto 64 basis vectors
+    C = SO.dct_basis(1024)
+    proj = res @ C.T @ C
+    np.testing.assert_allclose(prof - 10 * np.log10(i1 + SO.I_FLOOR), proj, atol=1e-10)
+
+
+def test_zero_residual_gives_single_bounce_profile():
+    i1 = np.full((2, 1024), 1e-8)
+    c = SO.residual_coefficients(i1, np.zeros_like(i1))
+    assert np.abs(c).max() < 1e-12
+    err, n = SO.beam_errors(i1, np.zeros_like(i1), SO.profile_from_coefficients(i1, c))
+    assert np.all(err < 1e-10) and np.all(n == 1024)
