@@ -286,6 +286,90 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
                                   void *workspace, size_t workspace_bytes, sonar_stream stream,
                                   sonar_batch_options *best, float *best_ms);
 
+/* ---------------------------------------------------------------------- */
+/* Learned multipath surrogate (Sec. II-B: scattering functions may be learned
+ * from data). A network maps each beam's single-bounce G-buffer (a 3 x 3 beam
+ * neighbourhood of its 7 features) to 64 standardised orthonormal DCT-II
+ * coefficients of the residual profile that later bounces add:
+ *   res[r] = 10 log10(I1s[r] + Ims[r] + 1e-11) - 10 log10(I1s[r] + 1e-11),
+ * where I1s, Ims are the first-bounce and later-bounce incoherent channels of a
+ * multi-bounce ping box-averaged over `smooth` range bins ([r - smooth/2,
+ * r + smooth/2)), and the profile is shifted so that the beam's first-hit bin
+ * (its G-buffer mean first-bounce range) is bin 0, zero past the end.
+ * Layers: 3 x 3 convolution 7 -> 64 (as an im2col product), then
+ * 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers; 168,768 parameters.
+ * Products use BF16 operands on the matrix cores with FP32 accumulation;
+ * training is MSE on the coefficients with Adam (beta 0.9 / 0.999, eps 1e-8)
+ * on FP32 master weights.
+ *
+ * Parameter vector layout (float, sonar_surrogate_param_count() entries): for
+ * each layer W [fan_in][fan_out] row-major then b [fan_out], with (fan_in,
+ * fan_out) = (63, 64), (64, 256), (256, 256), (256, 256), (256, 64).
+ * G-buffer: float [n_img][H][W][8] as sonar_ping writes it; rows = n_img * H * W
+ * (a multiple of 64 for the network, at most max_rows everywhere).
+ * Standardisation: coefficient j is (c_j - mean_j) / std_j (defaults 0, 1). */
+typedef struct sonar_surrogate sonar_surrogate;
+
+int64_t sonar_surrogate_param_count(void);
+
+/* Allocates weights, Adam state, activations and smoothing buffers for up to
+ * max_rows beams, and the DCT basis for n_bins range bins over [r_min, r_max)
+ * (64 <= n_bins); `smooth` is the range box width in bins. Weights start at
+ * zero: set them. */
+sonar_status sonar_surrogate_create(int64_t max_rows, int32_t n_bins, double r_min, double r_max, int32_t smooth,
+                                    sonar_surrogate **out);
+void sonar_surrogate_free(sonar_surrogate *s);
+
+/* Host copies of the FP32 master weights and Adam moments (any may be NULL)
+ * and the step count: a checkpoint. set_state with m = v = NULL resets Adam.
+ * Both synchronise. */
+sonar_status sonar_surrogate_set_state(sonar_surrogate *s, const float *params, const float *adam_m,
+                                       const float *adam_v, int64_t step);
+sonar_status sonar_surrogate_get_state(const sonar_surrogate *s, float *params, float *adam_m, float *adam_v,
+                                       int64_t *step);
+
+/* Coefficient standardisation (host arrays of 64). */
+sonar_status sonar_surrogate_set_norm(sonar_surrogate *s, const float *mean, const float *std);
+
+/* Inference: standardised coefficients [rows][64] (device) from a G-buffer. */
+sonar_status sonar_surrogate_forward(sonar_surrogate *s, const float *gbuffer, int32_t n_img, int32_t h, int32_t w,
+                                     float *coef, sonar_stream stream);
+
+/* One training step on (G-buffer, standardised target [rows][64]): forward,
+ * MSE, backward, Adam with learning rate lr. The loss before the update goes
+ * to dev_loss (device float). */
+sonar_status sonar_surrogate_train_step(sonar_surrogate *s, const float *gbuffer, int32_t n_img, int32_t h, int32_t w,
+                                        const float *target, float lr, float *dev_loss, sonar_stream stream);
+
+/* Gradient of the MSE w.r.t. the parameter vector (device float
+ * [param_count]) without updating; for checks. */
+sonar_status sonar_surrogate_gradient(sonar_surrogate *s, const float *gbuffer, int32_t n_img, int32_t h, int32_t w,
+                                      const float *target, float *dev_grad, float *dev_loss, sonar_stream stream);
+
+/* Residual target: coefficients [rows][64] from the two incoherent channels
+ * i1, im [rows][n_bins] and the G-buffer of the same beams (device),
+ * standardised when `standardize` is 1. */
+sonar_status sonar_surrogate_residual(const sonar_surrogate *s, const float *i1, const float *im, const float *gbuffer,
+                                      int64_t rows, int32_t standardize, float *coef, sonar_stream stream);
+
+/* Sums of the 64 coefficients and of their squares over rows (host double
+ * arrays of 64), for the standardisation statistics. Synchronises. */
+sonar_status sonar_surrogate_moments(sonar_surrogate *s, const float *coef, int64_t rows, double *sum, double *sum_sq,
+                                     sonar_stream stream);
+
+/* Predicted (range-smoothed) multi-bounce profile and its errors. For
+ * standardised predictions `coef`: profile[r] = 10 log10(I1s[r] + 1e-11),
+ * plus the inverse DCT of the de-standardised coefficients from the first-hit
+ * bin on (written to `profile` [rows][n_bins] if not NULL). If `im` is not
+ * NULL, `err` [rows][4] receives per beam, over bins whose smoothed truth
+ * 10 log10(I1s + Ims + 1e-11) is 3 dB above the floor: mean |error| of the
+ * prediction, of the single-bounce profile alone, of the single-bounce
+ * profile plus the mean residual (inverse DCT of the mean coefficients), and
+ * the number of such bins (NaN errors when none). */
+sonar_status sonar_surrogate_profile(const sonar_surrogate *s, const float *coef, const float *i1, const float *im,
+                                     const float *gbuffer, int64_t rows, float *profile, float *err,
+                                     sonar_stream stream);
+
 /* Synchronises `stream` and reports device-side errors recorded by calls
  * that used `scene` (SONAR_E_STACK if a traversal ran out of stack). Clears
  * the record. */

@@ -49,17 +49,6 @@ def pack(layers):
     return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in layers])
 
 
-def init_params(seed: int) -> np.ndarray:
-    """He-uniform weights, zero biases (the random draws are inputs to both sides)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    parts = []
-    for k, n in LAYERS:
-        lim = np.sqrt(6.0 / k)
-        parts.append(rng.uniform(-lim, lim, k * n))
-        parts.append(np.zeros(n))
-    return np.concatenate(parts).astype(np.float32)
-
-
 def im2col(gbuf):
     """gbuf [n_img, H, W, >= 7] -> [n_img * H * W, 63]: for each beam (v, h)
     the 7 features of (v + dv, h + dh), dv, dh in {-1, 0, 1}, zero outside,
@@ -75,15 +64,18 @@ def im2col(gbuf):
     return np.concatenate(cols, axis=-1).reshape(n * H * W, 9 * N_FEAT)
 
 
-def forward(theta, x0):
-    """Returns (activations [x0 .. x4], y): x_{l+1} = relu(x_l W_l + b_l), y = x4 W4 + b4."""
+def forward(theta, x0, store=None):
+    """Returns (activations [x0 .. x4], y): x_{l+1} = relu(x_l W_l + b_l), y = x4 W4 + b4.
+    `store`, if given, is applied to every stored activation (a test hook that
+    models a lower storage precision; by default values are kept exact)."""
+    st = store if store is not None else (lambda a: a)
     L = unpack(theta)
-    acts = [np.asarray(x0, np.float64)]
+    acts = [st(np.asarray(x0, np.float64))]
     x = acts[0]
     for i, (W, b) in enumerate(L):
         z = x @ W + b
         if i < len(L) - 1:
-            x = np.maximum(z, 0.0)
+            x = st(np.maximum(z, 0.0))
             acts.append(x)
         else:
             return acts, z
@@ -95,25 +87,27 @@ def mse(y, t):
     return float((d * d).mean()), 2.0 * d / d.size
 
 
-def backward(theta, acts, dy):
-    """Gradient of the loss w.r.t. the flat parameter vector, given dL/dy."""
+def backward(theta, acts, dy, store=None):
+    """Gradient of the loss w.r.t. the flat parameter vector, given dL/dy.
+    `store` as in forward(), applied to every stored layer gradient."""
+    st = store if store is not None else (lambda a: a)
     L = unpack(theta)
     grads = [None] * len(L)
-    dz = dy
+    dz = st(dy)
     for i in range(len(L) - 1, -1, -1):
         W, _ = L[i]
         x = acts[i]
         grads[i] = (x.T @ dz, dz.sum(axis=0))
         if i > 0:
             dx = dz @ W.T
-            dz = dx * (acts[i] > 0.0)
+            dz = st(dx * (acts[i] > 0.0))
     return pack(grads)
 
 
-def loss_and_grad(theta, gbuf, target):
-    acts, y = forward(theta, im2col(gbuf))
+def loss_and_grad(theta, gbuf, target, store=None):
+    acts, y = forward(theta, im2col(gbuf), store)
     loss, dy = mse(y, target)
-    return loss, backward(theta, acts, dy), y
+    return loss, backward(theta, acts, dy, store), y
 
 
 def dct_basis(n_bins: int, n_coef: int = N_COEF):
@@ -125,6 +119,59 @@ def dct_basis(n_bins: int, n_coef: int = N_COEF):
     C *= np.sqrt(2.0 / n_bins)
     C[0] *= np.sqrt(0.5)
     return C
+
+
+SMOOTH = 32     # range smoothing of the incoherent intensities (bins)
+
+
+def smooth_range(a, w=SMOOTH):
+    """Box average over bins [r - w/2, r + w/2) along the last axis, zero outside."""
+    a = np.asarray(a, np.float64)
+    n = a.shape[-1]
+    out = np.zeros_like(a)
+    for r in range(n):
+        lo, hi = max(0, r - w // 2), min(n, r + w - w // 2)
+        out[..., r] = a[..., lo:hi].sum(axis=-1) / w
+    return out
+
+
+def first_hit_bin(gbuf_rows, r_min, r_max, n_bins):
+    """Range bin of each beam's mean first-bounce range (G-buffer feature 0 is
+    range / r_max, feature 6 the hit fraction); 0 for beams without hits."""
+    g = np.asarray(gbuf_rows, np.float32)
+    dr = np.float32((r_max - r_min) / n_bins)
+    R = g[:, 0] * np.float32(r_max)
+    b = np.floor((R - np.float32(r_min)) / dr)
+    b = np.where(g[:, 6] > 0, b, 0)
+    return np.clip(b, 0, n_bins - 1).astype(np.int64)
+
+
+def aligned_residual_coefficients(i1, im, r1, floor=I_FLOOR, w=SMOOTH):
+    """DCT coefficients of the range-smoothed dB residual shifted so that each
+    beam's first-hit bin r1 becomes bin 0 (bins past the end are zero)."""
+    res = residual_db(smooth_range(i1, w), smooth_range(im, w), floor)
+    n = res.shape[-1]
+    al = np.zeros_like(res)
+    for q in range(res.shape[0]):
+        al[q, :n - r1[q]] = res[q, r1[q]:]
+    return al @ dct_basis(n).T
+
+
+def aligned_profile(i1, coef, r1, floor=I_FLOOR, w=SMOOTH):
+    """Predicted range-smoothed multi-bounce dB profile: smoothed single-bounce dB
+    plus the inverse DCT shifted back to start at the first-hit bin."""
+    i1s = smooth_range(i1, w)
+    q = np.asarray(coef, np.float64) @ dct_basis(i1s.shape[-1])
+    n = i1s.shape[-1]
+    out = 10.0 * np.log10(i1s + floor)
+    for k in range(out.shape[0]):
+        out[k, r1[k]:] += q[k, :n - r1[k]]
+    return out
+
+
+def aligned_beam_errors(i1, im, pred_profile, floor=I_FLOOR, occupied_db=3.0, w=SMOOTH):
+    """beam_errors() against the range-smoothed truth."""
+    return beam_errors(smooth_range(i1, w), smooth_range(im, w), pred_profile, floor, occupied_db)
 
 
 def residual_db(i1, im, floor=I_FLOOR):

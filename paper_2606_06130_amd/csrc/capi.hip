@@ -17,6 +17,10 @@ struct sonar_scene {
     sonar::Scene s;
 };
 
+struct sonar_surrogate {
+    sonar::Surrogate *s = nullptr;
+};
+
 struct sonar_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -636,6 +640,144 @@ sonar_status sonar_batch_autotune(const sonar_scene *sc, const sonar_batch_plan 
         }
     }
     return SONAR_OK;
+}
+
+int64_t sonar_surrogate_param_count(void) { return sonar::surrogate_param_count(); }
+
+sonar_status sonar_surrogate_create(int64_t max_rows, int32_t n_bins, double r_min, double r_max, int32_t smooth,
+                                    sonar_surrogate **out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(SONAR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (max_rows < 64 || max_rows % 64 != 0 || max_rows > ((int64_t)1 << 26))
+        return fail(SONAR_E_INVALID, "max_rows must be a positive multiple of 64, at most 2^26");
+    if (n_bins < 64 || n_bins > sonar::MAX_BINS)
+        return fail(SONAR_E_INVALID, "n_bins must be in [64, %d]", sonar::MAX_BINS);
+    if (!(r_min >= 0) || !(r_max > r_min) || !isfinite(r_max)) return fail(SONAR_E_INVALID, "need 0 <= r_min < r_max");
+    if (smooth < 1 || smooth > n_bins) return fail(SONAR_E_INVALID, "smooth must be in [1, n_bins]");
+    sonar_surrogate *h = new (std::nothrow) sonar_surrogate();
+    if (!h) return fail(SONAR_E_NOMEM, "host allocation failed");
+    hipError_t e = sonar::surrogate_create(max_rows, n_bins, (float)r_min, (float)r_max, smooth, &h->s);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(e == hipErrorOutOfMemory ? SONAR_E_NOMEM : SONAR_E_DEVICE, "surrogate: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return SONAR_OK;
+}
+
+void sonar_surrogate_free(sonar_surrogate *h)
+{
+    if (!h) return;
+    sonar::surrogate_free(h->s);
+    delete h;
+}
+
+sonar_status sonar_surrogate_set_state(sonar_surrogate *h, const float *params, const float *m, const float *v,
+                                       int64_t step)
+{
+    if (!h || !params) return fail(SONAR_E_INVALID, "surrogate and params are required");
+    if ((m == nullptr) != (v == nullptr)) return fail(SONAR_E_INVALID, "give both Adam moments or neither");
+    if (step < 0) return fail(SONAR_E_INVALID, "step must be >= 0");
+    hipError_t e = sonar::surrogate_set_state(h->s, params, m, v, step);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "set_state: %s", hipGetErrorString(e));
+}
+
+sonar_status sonar_surrogate_get_state(const sonar_surrogate *h, float *params, float *m, float *v, int64_t *step)
+{
+    if (!h) return fail(SONAR_E_INVALID, "surrogate is NULL");
+    hipError_t e = sonar::surrogate_get_state(h->s, params, m, v, step);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "get_state: %s", hipGetErrorString(e));
+}
+
+sonar_status sonar_surrogate_set_norm(sonar_surrogate *h, const float *mean, const float *sd)
+{
+    if (!h || !mean || !sd) return fail(SONAR_E_INVALID, "surrogate, mean and std are required");
+    for (int j = 0; j < 64; ++j)
+        if (!isfinite(mean[j]) || !(sd[j] > 0.f) || !isfinite(sd[j]))
+            return fail(SONAR_E_INVALID, "std must be positive and finite");
+    hipError_t e = sonar::surrogate_set_norm(h->s, mean, sd);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "set_norm: %s", hipGetErrorString(e));
+}
+
+static sonar_status check_gbuf(const sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W)
+{
+    if (!h || !g) return fail(SONAR_E_INVALID, "surrogate and gbuffer are required");
+    if (n < 1 || H < 1 || W < 1) return fail(SONAR_E_INVALID, "n_img, h, w must be >= 1");
+    const int64_t rows = (int64_t)n * H * W;
+    if (rows % 64 != 0) return fail(SONAR_E_INVALID, "n_img * h * w must be a multiple of 64");
+    if (rows > sonar::surrogate_max_rows(h->s)) return fail(SONAR_E_INVALID, "more rows than max_rows");
+    return SONAR_OK;
+}
+
+sonar_status sonar_surrogate_forward(sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W, float *coef,
+                                     sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar_status st = check_gbuf(h, g, n, H, W);
+    if (st != SONAR_OK) return st;
+    if (!coef) return fail(SONAR_E_INVALID, "coef is NULL");
+    hipError_t e = sonar::surrogate_forward(h->s, g, n, H, W, coef, (hipStream_t)stream);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "forward: %s", hipGetErrorString(e));
+}
+
+sonar_status sonar_surrogate_train_step(sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W,
+                                        const float *target, float lr, float *dev_loss, sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar_status st = check_gbuf(h, g, n, H, W);
+    if (st != SONAR_OK) return st;
+    if (!target || !dev_loss) return fail(SONAR_E_INVALID, "target and dev_loss are required");
+    if (!(lr >= 0.f) || !isfinite(lr)) return fail(SONAR_E_INVALID, "lr must be finite and >= 0");
+    hipError_t e = sonar::surrogate_train_step(h->s, g, n, H, W, target, lr, dev_loss, (hipStream_t)stream);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "train_step: %s", hipGetErrorString(e));
+}
+
+sonar_status sonar_surrogate_gradient(sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W,
+                                      const float *target, float *dev_grad, float *dev_loss, sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar_status st = check_gbuf(h, g, n, H, W);
+    if (st != SONAR_OK) return st;
+    if (!target || !dev_grad || !dev_loss) return fail(SONAR_E_INVALID, "target, dev_grad and dev_loss are required");
+    hipError_t e = sonar::surrogate_gradient(h->s, g, n, H, W, target, dev_grad, dev_loss, (hipStream_t)stream);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "gradient: %s", hipGetErrorString(e));
+}
+
+sonar_status sonar_surrogate_residual(const sonar_surrogate *h, const float *i1, const float *im, const float *gbuffer,
+                                      int64_t rows, int32_t standardize, float *coef, sonar_stream stream)
+{
+    g_err[0] = 0;
+    if (!h || !i1 || !im || !gbuffer || !coef)
+        return fail(SONAR_E_INVALID, "surrogate, i1, im, gbuffer and coef are required");
+    if (rows < 1 || rows > sonar::surrogate_max_rows(h->s)) return fail(SONAR_E_INVALID, "rows must be in [1, max_rows]");
+    hipError_t e = sonar::surrogate_residual_coef(h->s, i1, im, gbuffer, rows, standardize ? 1 : 0, coef,
+                                                  (hipStream_t)stream);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "residual: %s", hipGetErrorString(e));
+}
+
+sonar_status sonar_surrogate_moments(sonar_surrogate *h, const float *coef, int64_t rows, double *sum, double *sq,
+                                     sonar_stream stream)
+{
+    g_err[0] = 0;
+    if (!h || !coef || !sum || !sq) return fail(SONAR_E_INVALID, "surrogate, coef, sum and sum_sq are required");
+    if (rows < 1 || rows > sonar::surrogate_max_rows(h->s)) return fail(SONAR_E_INVALID, "rows must be in [1, max_rows]");
+    hipError_t e = sonar::surrogate_coef_moments(h->s, coef, rows, sum, sq, (hipStream_t)stream);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "moments: %s", hipGetErrorString(e));
+}
+
+sonar_status sonar_surrogate_profile(const sonar_surrogate *h, const float *coef, const float *i1, const float *im,
+                                     const float *gbuffer, int64_t rows, float *profile, float *err,
+                                     sonar_stream stream)
+{
+    g_err[0] = 0;
+    if (!h || !coef || !i1 || !gbuffer) return fail(SONAR_E_INVALID, "surrogate, coef, i1 and gbuffer are required");
+    if (rows < 1 || rows > sonar::surrogate_max_rows(h->s)) return fail(SONAR_E_INVALID, "rows must be in [1, max_rows]");
+    if (err && !im) return fail(SONAR_E_INVALID, "errors need the multi-bounce channel im");
+    hipError_t e = sonar::surrogate_profile_errors(h->s, coef, i1, im, gbuffer, rows, err, profile,
+                                                   (hipStream_t)stream);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "profile: %s", hipGetErrorString(e));
 }
 
 sonar_status sonar_device_status(const sonar_scene *sc, sonar_stream stream)

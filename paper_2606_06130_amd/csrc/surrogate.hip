@@ -1,0 +1,747 @@
+// Learned multipath surrogate: kernels and host orchestration.
+//
+// Sec. II-B lets scattering and reverberation effects be learned from data.
+// Here a small network maps each beam's single-bounce G-buffer (3 x 3 beam
+// neighbourhood of 7 features) to the first 64 orthonormal DCT-II
+// coefficients of the dB residual that further bounces add to its range
+// profile. Layers: im2col convolution 63(+1 zero) -> 64, then
+// 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers.
+//
+// Dense products run on the CDNA4 matrix cores: v_mfma_f32_16x16x32_bf16
+// (BF16 operands, FP32 accumulation), 64 x 64 block tiles staged through LDS
+// with k-contiguous fragments, three operand layouts (activations x W^T,
+// dZ x W, X^T x dZ with a split reduction). Weights are FP32 master copies
+// updated by Adam (Kingma and Ba, 2015) and mirrored in BF16 in the two
+// layouts the products read. All reductions are two-stage in a fixed order,
+// so a training step is bit-reproducible.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace sonar {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int NL = 5;                                       // layers
+constexpr int LK[NL] = {63, 64, 256, 256, 256};             // true fan-in
+constexpr int LKP[NL] = {64, 64, 256, 256, 256};            // padded fan-in (multiple of 32)
+constexpr int LN[NL] = {64, 256, 256, 256, 64};             // fan-out
+constexpr int NCOEF = 64;
+constexpr int NFEAT = 7;
+constexpr int GB_STRIDE = 8;                                // floats per beam in the G-buffer
+constexpr int TM = 64, TN = 64, TK = 32, LDT = TK + 8;      // GEMM tiles; LDS row stride in bf16
+constexpr int SPLIT_ROWS = 4096;                            // reduction chunk of the weight gradients
+constexpr float I_FLOOR = 1e-11f;
+
+enum { EPI_BIAS_RELU = 0, EPI_BIAS = 1, EPI_MASK = 2, EPI_PARTIAL = 3 };
+
+constexpr int64_t layer_param_offset(int l)
+{
+    int64_t o = 0;
+    for (int i = 0; i < l; ++i) o += (int64_t)LK[i] * LN[i] + LN[i];
+    return o;
+}
+constexpr int64_t N_PARAMS = layer_param_offset(NL);
+
+// ---------------------------------------------------------------------------
+// GEMM: C[M][N] = sum_k A(m, k) B(k, n), BF16 x BF16 -> FP32 on MFMA.
+//   TA = false: A stored [M][K] (lda); TA = true: A stored [K][M] (lda).
+//   TB = false: B stored [N][K] (ldb); TB = true: B stored [K][N] (ldb).
+// M, N multiples of 64 and K a multiple of 32 (checked by the host). With
+// split > 1, blockIdx.z reduces rows [z * kchunk, (z + 1) * kchunk) of K and
+// writes FP32 partials [z][M][N].
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
+                                              int ldb, int K, int kchunk, const float *__restrict__ bias,
+                                              const __bf16 *__restrict__ mask, int ldm, void *__restrict__ out,
+                                              int ldo, int M, int N)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[TM * LDT];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[TN * LDT];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int kb = blockIdx.z * kchunk;
+    const int ke = min(K, kb + kchunk);
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = kb; k0 < ke; k0 += TK) {
+        // ---- stage A tile (64 rows x 32 k) as [m][k]
+        if (!TA) {
+            const int r = t >> 2, c = (t & 3) * 8;
+            *reinterpret_cast<uint4 *>(&As[r * LDT + c]) =
+                *reinterpret_cast<const uint4 *>(&A[(int64_t)(m0 + r) * lda + k0 + c]);
+        } else {
+            const int kk = t >> 3, c = (t & 7) * 8;
+            uint4 v = *reinterpret_cast<const uint4 *>(&A[(int64_t)(k0 + kk) * lda + m0 + c]);
+            const __bf16 *e = reinterpret_cast<const __bf16 *>(&v);
+            for (int i = 0; i < 8; ++i) As[(c + i) * LDT + kk] = e[i];
+        }
+        // ---- stage B tile (32 k x 64 cols) as [n][k]
+        if (!TB) {
+            const int r = t >> 2, c = (t & 3) * 8;
+            *reinterpret_cast<uint4 *>(&Bs[r * LDT + c]) =
+                *reinterpret_cast<const uint4 *>(&B[(int64_t)(n0 + r) * ldb + k0 + c]);
+        } else {
+            const int kk = t >> 3, c = (t & 7) * 8;
+            uint4 v = *reinterpret_cast<const uint4 *>(&B[(int64_t)(k0 + kk) * ldb + n0 + c]);
+            const __bf16 *e = reinterpret_cast<const __bf16 *>(&v);
+            for (int i = 0; i < 8; ++i) Bs[(c + i) * LDT + kk] = e[i];
+        }
+        __syncthreads();
+        // ---- fragments: lane l holds row/col (l % 16), k = 8 (l / 16) .. + 7
+        bf16x8 a[2], b[2];
+        for (int i = 0; i < 2; ++i)
+            a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm + 16 * i + (lane & 15)) * LDT + 8 * (lane >> 4)]);
+        for (int j = 0; j < 2; ++j)
+            b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn + 16 * j + (lane & 15)) * LDT + 8 * (lane >> 4)]);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // ---- epilogue: lane l holds column (l % 16), rows 4 (l / 16) .. + 3 of each 16 x 16 tile
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
+                const int n = n0 + wn + 16 * j + (lane & 15);
+                float v = acc[i][j][e];
+                if (EPI == EPI_BIAS_RELU) {
+                    v += bias[n];
+                    reinterpret_cast<__bf16 *>(out)[(int64_t)m * ldo + n] = (__bf16)(v > 0.f ? v : 0.f);
+                } else if (EPI == EPI_BIAS) {
+                    reinterpret_cast<float *>(out)[(int64_t)m * ldo + n] = v + bias[n];
+                } else if (EPI == EPI_MASK) {
+                    const float keep = (float)mask[(int64_t)m * ldm + n] > 0.f ? 1.f : 0.f;
+                    reinterpret_cast<__bf16 *>(out)[(int64_t)m * ldo + n] = (__bf16)(v * keep);
+                } else {
+                    reinterpret_cast<float *>(out)[((int64_t)blockIdx.z * M + m) * ldo + n] = v;
+                }
+            }
+}
+
+// im2col of the G-buffer: row (img, v, h) gets the 7 features of the 3 x 3
+// neighbourhood ordered (dv, dh, feature), zero outside the image, then a
+// zero 64th column. One thread per output element pair.
+__global__ void k_im2col(const float *__restrict__ g, int n_img, int H, int W, __bf16 *__restrict__ x)
+{
+    const int64_t rows = (int64_t)n_img * H * W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * 64) return;
+    const int64_t row = i >> 6;
+    const int c = (int)(i & 63);
+    float v = 0.f;
+    if (c < 63) {
+        const int q = c / NFEAT, f = c % NFEAT;
+        const int dv = q / 3 - 1, dh = q % 3 - 1;
+        const int img = (int)(row / ((int64_t)H * W));
+        const int rem = (int)(row % ((int64_t)H * W));
+        const int vv = rem / W + dv, hh = rem % W + dh;
+        if (vv >= 0 && vv < H && hh >= 0 && hh < W)
+            v = g[(((int64_t)img * H + vv) * W + hh) * GB_STRIDE + f];
+    }
+    x[i] = (__bf16)v;
+}
+
+// MSE on the 64 coefficients: dZ = 2 (y - t) / (rows * 64) in BF16 and per
+// block partial sums of (y - t)^2 in FP64.
+__global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, int64_t n, __bf16 *__restrict__ dz,
+                      double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    const int64_t i0 = (int64_t)blockIdx.x * 256 * 16;
+    double s = 0.0;
+    const float sc = (float)(2.0 / (double)n);
+    for (int q = 0; q < 16; ++q) {
+        const int64_t i = i0 + (int64_t)q * 256 + threadIdx.x;
+        if (i < n) {
+            const float d = y[i] - t[i];
+            dz[i] = (__bf16)(sc * d);
+            s += (double)d * d;
+        }
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_loss_final(const double *__restrict__ part, int np, int64_t n, float *__restrict__ loss)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < np; ++i) s += part[i];
+        *loss = (float)(s / (double)n);
+    }
+}
+
+// Column sums of a BF16 [rows][N] matrix over row chunks of SPLIT_ROWS: FP32
+// partials [chunk][N].
+__global__ void k_colsum(const __bf16 *__restrict__ x, int64_t rows, int N, float *__restrict__ part)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r0 = (int64_t)blockIdx.x * SPLIT_ROWS;
+    const int64_t r1 = min(rows, r0 + SPLIT_ROWS);
+    __shared__ float sh[4][64];
+    float s = 0.f;
+    for (int64_t r = r0 + (threadIdx.x >> 6); r < r1; r += 4) s += (float)x[r * N + c];
+    sh[threadIdx.x >> 6][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (threadIdx.x < 64) part[(int64_t)blockIdx.x * N + c] = sh[0][threadIdx.x] + sh[1][threadIdx.x] +
+                                                              sh[2][threadIdx.x] + sh[3][threadIdx.x];
+}
+
+// Sums split partials [S][K][N] (fixed order) into a flat parameter-gradient
+// block: rows k < k_true go to grad[k * N + n] (the padded row is dropped).
+__global__ void k_reduce_partials(const float *__restrict__ part, int S, int K, int N, int k_true,
+                                  float *__restrict__ grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K * N) return;
+    const int k = i / N;
+    if (k >= k_true) return;
+    float s = 0.f;
+    for (int z = 0; z < S; ++z) s += part[(int64_t)z * K * N + i];
+    grad[i] = s;
+}
+
+// Adam on the flat FP32 master parameters (bias-corrected moments).
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 mirrors of layer l: wt [N][Kp] (k contiguous) and wk [Kp][N] (n
+// contiguous), padded rows zero; FP32 bias copy.
+__global__ void k_pack_layer(const float *__restrict__ master, int K, int Kp, int N, __bf16 *__restrict__ wt,
+                             __bf16 *__restrict__ wk, float *__restrict__ bias)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < Kp * N) {
+        const int k = i / N, n = i % N;
+        const float v = k < K ? master[(int64_t)k * N + n] : 0.f;
+        wt[(int64_t)n * Kp + k] = (__bf16)v;
+        wk[(int64_t)k * N + n] = (__bf16)v;
+    }
+    if (i < N) bias[i] = master[(int64_t)K * N + i];
+}
+
+// Range smoothing of both incoherent channels: box average over bins
+// [r - w/2, r + w/2), zero outside. One block per row, the row staged in LDS.
+__global__ __launch_bounds__(256) void k_smooth(const float *__restrict__ i1, const float *__restrict__ im,
+                                                int nb, int w, float *__restrict__ s1, float *__restrict__ sm)
+{
+    extern __shared__ float row[];    // [2][nb]
+    const int64_t o = (int64_t)blockIdx.x * nb;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        row[b] = i1[o + b];
+        row[nb + b] = im[o + b];
+    }
+    __syncthreads();
+    const float inv = 1.f / w;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const int lo = max(0, b - w / 2), hi = min(nb, b + w - w / 2);
+        float a = 0.f, c = 0.f;
+        for (int q = lo; q < hi; ++q) {
+            a += row[q];
+            c += row[nb + q];
+        }
+        s1[o + b] = a * inv;
+        sm[o + b] = c * inv;
+    }
+}
+
+// Bin of a beam's mean first-bounce range from its G-buffer (feature 0 is
+// range / r_max, feature 6 the hit fraction); 0 when it has no hits.
+__device__ __forceinline__ int first_hit_bin(const float *__restrict__ g, int64_t row, float r_min, float r_max,
+                                             float dr, int nb)
+{
+    const float f0 = g[row * GB_STRIDE + 0], cnt = g[row * GB_STRIDE + 6];
+    if (!(cnt > 0.f)) return 0;
+    const float b = floorf((f0 * r_max - r_min) / dr);
+    return (int)fminf(fmaxf(b, 0.f), (float)(nb - 1));
+}
+
+// Residual target: for each row, c_j = sum_r' C[j][r'] res[r' + r1], the
+// range-smoothed dB residual 10 log10(I1 + Im + floor) - 10 log10(I1 + floor)
+// shifted so the beam's first-hit bin r1 is bin 0 (zero past the end),
+// optionally standardised (c - mu_j) / sigma_j. Block: 64 rows x 64
+// coefficients; bins staged 64 at a time in LDS.
+__global__ __launch_bounds__(256) void k_residual_coef(const float *__restrict__ i1, const float *__restrict__ im,
+                                                       const float *__restrict__ gbuf, int64_t rows, int nb,
+                                                       float r_min, float r_max, const float *__restrict__ basis,
+                                                       const float *__restrict__ mu, const float *__restrict__ sg,
+                                                       int standardize, float *__restrict__ coef)
+{
+    __shared__ float R[64][65];
+    __shared__ float Cb[64][65];
+    __shared__ int r1s[64];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const float dr = (r_max - r_min) / nb;
+    if (t < 64) r1s[t] = (r0 + t < rows) ? first_hit_bin(gbuf, r0 + t, r_min, r_max, dr, nb) : 0;
+    __syncthreads();
+    const int rr = t >> 2;           // row within the block handled by this thread
+    const int cq = (t & 3) * 16;     // first of its 16 coefficients
+    float acc[16];
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+        for (int e = t; e < 64 * 64; e += 256) {
+            const int r = e >> 6, b = e & 63;
+            float v = 0.f;
+            const int src = b0 + b + r1s[r];
+            if (r0 + r < rows && src < nb) {
+                const int64_t o = (r0 + r) * nb + src;
+                const float a1 = i1[o], am = im[o];
+                v = 10.f * (log10f(a1 + am + I_FLOOR) - log10f(a1 + I_FLOOR));
+            }
+            R[r][b] = v;
+            Cb[r][b] = (b0 + b < nb) ? basis[(int64_t)r * nb + b0 + b] : 0.f;
+        }
+        __syncthreads();
+        for (int b = 0; b < 64; ++b) {
+            const float x = R[rr][b];
+            for (int q = 0; q < 16; ++q) acc[q] += Cb[cq + q][b] * x;
+        }
+        __syncthreads();
+    }
+    if (r0 + rr < rows) {
+        for (int q = 0; q < 16; ++q) {
+            const int j = cq + q;
+            float v = acc[q];
+            if (standardize) v = (v - mu[j]) / sg[j];
+            coef[(r0 + rr) * NCOEF + j] = v;
+        }
+    }
+}
+
+// Column sums of v and v^2 of an FP32 [rows][64] matrix in FP64 partials.
+__global__ void k_coef_moments(const float *__restrict__ c, int64_t rows, double *__restrict__ part)
+{
+    const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * SPLIT_ROWS, r1 = min(rows, r0 + SPLIT_ROWS);
+    __shared__ double s1[4][64], s2[4][64];
+    double a = 0.0, b = 0.0;
+    for (int64_t r = r0 + q; r < r1; r += 4) {
+        const double v = c[r * NCOEF + j];
+        a += v;
+        b += v * v;
+    }
+    s1[q][j] = a;
+    s2[q][j] = b;
+    __syncthreads();
+    if (q == 0) {
+        part[(int64_t)blockIdx.x * 128 + j] = s1[0][j] + s1[1][j] + s1[2][j] + s1[3][j];
+        part[(int64_t)blockIdx.x * 128 + 64 + j] = s2[0][j] + s2[1][j] + s2[2][j] + s2[3][j];
+    }
+}
+
+// Predicted range-smoothed profile and per-beam dB errors. For row k with
+// first-hit bin r1: profile[b] = 10 log10(I1s[b] + floor) for b < r1 and
+// + sum_j C[j][b - r1] c_j after it, c the de-standardised prediction.
+// Errors over occupied bins (smoothed truth more than 3 dB above the floor):
+// [0] the prediction, [1] the single-bounce profile alone, [2] the single
+// bounce plus the mean residual (the same inverse DCT of the mean
+// coefficients), [3] the number of occupied bins. Block: 16 rows; thread t
+// takes aligned bins t, t + 256, ... so all rows share one basis column.
+__global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict__ pred, const float *__restrict__ i1,
+                                                        const float *__restrict__ im, const float *__restrict__ gbuf,
+                                                        int64_t rows, int nb, float r_min, float r_max,
+                                                        const float *__restrict__ basis, const float *__restrict__ mu,
+                                                        const float *__restrict__ sg, float *__restrict__ err,
+                                                        float *__restrict__ profile)
+{
+    __shared__ float cf[16][64];
+    __shared__ int r1s[16];
+    __shared__ float red[4][4][16];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 16;
+    const float dr = (r_max - r_min) / nb;
+    for (int e = t; e < 16 * 64; e += 256) {
+        const int r = e >> 6, j = e & 63;
+        cf[r][j] = (r0 + r < rows) ? pred[(r0 + r) * NCOEF + j] * sg[j] + mu[j] : 0.f;
+    }
+    if (t < 16) r1s[t] = (r0 + t < rows) ? first_hit_bin(gbuf, r0 + t, r_min, r_max, dr, nb) : 0;
+    __syncthreads();
+    float es[16], e1[16], em[16], no[16];
+    for (int r = 0; r < 16; ++r) es[r] = e1[r] = em[r] = no[r] = 0.f;
+    const float occ_db = 10.f * log10f(I_FLOOR) + 3.f;
+    // bins before the first hit: no residual
+    for (int r = 0; r < 16; ++r) {
+        if (r0 + r >= rows) break;
+        for (int b = t; b < r1s[r]; b += 256) {
+            const int64_t o = (r0 + r) * nb + b;
+            const float p1 = 10.f * log10f(i1[o] + I_FLOOR);
+            if (profile) profile[o] = p1;
+            if (im) {
+                const float tr = 10.f * log10f(i1[o] + im[o] + I_FLOOR);
+                if (tr > occ_db) {
+                    const float d = fabsf(p1 - tr);
+                    es[r] += d;
+                    e1[r] += d;
+                    em[r] += d;
+                    no[r] += 1.f;
+                }
+            }
+        }
+    }
+    for (int q = t; q < nb; q += 256) {
+        float cb[64];
+        float meanres = 0.f;
+        for (int j = 0; j < 64; ++j) {
+            cb[j] = basis[(int64_t)j * nb + q];
+            meanres += cb[j] * mu[j];
+        }
+        for (int r = 0; r < 16; ++r) {
+            if (r0 + r >= rows) break;
+            const int b = q + r1s[r];
+            if (b >= nb) continue;
+            const int64_t o = (r0 + r) * nb + b;
+            const float p1 = 10.f * log10f(i1[o] + I_FLOOR);
+            float res = 0.f;
+            for (int j = 0; j < 64; ++j) res += cb[j] * cf[r][j];
+            const float ph = p1 + res;
+            if (profile) profile[o] = ph;
+            if (im) {
+                const float tr = 10.f * log10f(i1[o] + im[o] + I_FLOOR);
+                if (tr > occ_db) {
+                    es[r] += fabsf(ph - tr);
+                    e1[r] += fabsf(p1 - tr);
+                    em[r] += fabsf(p1 + meanres - tr);
+                    no[r] += 1.f;
+                }
+            }
+        }
+    }
+    if (!err) return;
+    // reduce over the block: wave shuffles then LDS
+    const int lane = t & 63, w = t >> 6;
+    for (int r = 0; r < 16; ++r) {
+        float a = es[r], b = e1[r], c = em[r], d = no[r];
+        for (int off = 32; off > 0; off >>= 1) {
+            a += __shfl_xor(a, off);
+            b += __shfl_xor(b, off);
+            c += __shfl_xor(c, off);
+            d += __shfl_xor(d, off);
+        }
+        if (lane == 0) {
+            red[w][0][r] = a;
+            red[w][1][r] = b;
+            red[w][2][r] = c;
+            red[w][3][r] = d;
+        }
+    }
+    __syncthreads();
+    if (t < 16 && r0 + t < rows) {
+        float sm[4];
+        for (int q = 0; q < 4; ++q) sm[q] = red[0][q][t] + red[1][q][t] + red[2][q][t] + red[3][q][t];
+        const float n = sm[3];
+        float *o = err + (r0 + t) * 4;
+        o[0] = n > 0.f ? sm[0] / n : NAN;
+        o[1] = n > 0.f ? sm[1] / n : NAN;
+        o[2] = n > 0.f ? sm[2] / n : NAN;
+        o[3] = n;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+
+struct Surrogate {
+    int64_t max_rows = 0;
+    int n_bins = 0;
+    float *master = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+    __bf16 *wt[NL] = {}, *wk[NL] = {};
+    float *bias[NL] = {};
+    __bf16 *x[NL] = {};          // layer inputs x0 .. x4
+    __bf16 *dz[2] = {};          // ping-pong gradient buffers [rows][256]
+    float *y = nullptr;          // [rows][64]
+    float *part = nullptr;       // split partials [S][256][256]
+    double *dpart = nullptr;     // loss / moment partials
+    float *basis = nullptr;      // [64][n_bins]
+    float *s1 = nullptr, *sm = nullptr;   // range-smoothed channels [max_rows][n_bins]
+    float r_min = 0.f, r_max = 0.f;
+    int smooth = 32;
+    float *mu = nullptr, *sg = nullptr;
+    int64_t step = 0;
+    std::vector<void *> allocs;
+};
+
+static hipError_t salloc(Surrogate *s, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) s->allocs.push_back(*p);
+    return e;
+}
+
+void surrogate_free(Surrogate *s)
+{
+    if (!s) return;
+    for (void *p : s->allocs) (void)hipFree(p);
+    delete s;
+}
+
+int64_t surrogate_param_count() { return N_PARAMS; }
+
+hipError_t surrogate_create(int64_t max_rows, int n_bins, float r_min, float r_max, int smooth, Surrogate **out)
+{
+    Surrogate *s = new (std::nothrow) Surrogate();
+    if (!s) return hipErrorOutOfMemory;
+    s->max_rows = max_rows;
+    s->n_bins = n_bins;
+    s->r_min = r_min;
+    s->r_max = r_max;
+    s->smooth = smooth;
+    hipError_t e = hipSuccess;
+#define SA(ptr, bytes)                                                        \
+    do {                                                                      \
+        if (e == hipSuccess) e = salloc(s, (void **)&(ptr), (size_t)(bytes)); \
+    } while (0)
+    SA(s->master, N_PARAMS * 4);
+    SA(s->adam_m, N_PARAMS * 4);
+    SA(s->adam_v, N_PARAMS * 4);
+    SA(s->grad, N_PARAMS * 4);
+    for (int l = 0; l < NL; ++l) {
+        SA(s->wt[l], (size_t)LKP[l] * LN[l] * 2);
+        SA(s->wk[l], (size_t)LKP[l] * LN[l] * 2);
+        SA(s->bias[l], (size_t)LN[l] * 4);
+        SA(s->x[l], (size_t)max_rows * LKP[l] * 2);
+    }
+    SA(s->dz[0], (size_t)max_rows * 256 * 2);
+    SA(s->dz[1], (size_t)max_rows * 256 * 2);
+    SA(s->y, (size_t)max_rows * NCOEF * 4);
+    const int64_t S = (max_rows + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    SA(s->part, (size_t)S * 256 * 256 * 4);
+    SA(s->dpart, (size_t)(max_rows / 4096 + S + 2) * 128 * 8);
+    SA(s->basis, (size_t)NCOEF * n_bins * 4);
+    SA(s->s1, (size_t)max_rows * n_bins * 4);
+    SA(s->sm, (size_t)max_rows * n_bins * 4);
+    SA(s->mu, NCOEF * 4);
+    SA(s->sg, NCOEF * 4);
+#undef SA
+    if (e != hipSuccess) {
+        surrogate_free(s);
+        return e;
+    }
+    // orthonormal DCT-II basis, first 64 rows, computed in FP64 on the host
+    std::vector<float> B((size_t)NCOEF * n_bins);
+    for (int j = 0; j < NCOEF; ++j)
+        for (int r = 0; r < n_bins; ++r) {
+            double sc = j == 0 ? sqrt(1.0 / n_bins) : sqrt(2.0 / n_bins);
+            B[(size_t)j * n_bins + r] = (float)(sc * cos(M_PI * (r + 0.5) * j / n_bins));
+        }
+    std::vector<float> mu(NCOEF, 0.f), sg(NCOEF, 1.f), zero(N_PARAMS, 0.f);
+    e = hipMemcpy(s->basis, B.data(), B.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->mu, mu.data(), NCOEF * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->sg, sg.data(), NCOEF * 4, hipMemcpyHostToDevice);
+    for (float **p : {&s->master, &s->adam_m, &s->adam_v, &s->grad})
+        if (e == hipSuccess) e = hipMemcpy(*p, zero.data(), N_PARAMS * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        surrogate_free(s);
+        return e;
+    }
+    *out = s;
+    return hipSuccess;
+}
+
+static hipError_t pack_all(Surrogate *s, hipStream_t st)
+{
+    for (int l = 0; l < NL; ++l) {
+        const int n = LKP[l] * LN[l];
+        hipLaunchKernelGGL(k_pack_layer, dim3((n + 255) / 256), dim3(256), 0, st, s->master + layer_param_offset(l),
+                           LK[l], LKP[l], LN[l], s->wt[l], s->wk[l], s->bias[l]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t surrogate_set_state(Surrogate *s, const float *master, const float *m, const float *v, int64_t step)
+{
+    hipError_t e = hipMemcpy(s->master, master, N_PARAMS * 4, hipMemcpyHostToDevice);
+    std::vector<float> zero;
+    if (!m || !v) zero.assign(N_PARAMS, 0.f);
+    if (e == hipSuccess) e = hipMemcpy(s->adam_m, m ? m : zero.data(), N_PARAMS * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->adam_v, v ? v : zero.data(), N_PARAMS * 4, hipMemcpyHostToDevice);
+    s->step = step;
+    if (e == hipSuccess) e = pack_all(s, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return e;
+}
+
+hipError_t surrogate_get_state(const Surrogate *s, float *master, float *m, float *v, int64_t *step)
+{
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && master) e = hipMemcpy(master, s->master, N_PARAMS * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && m) e = hipMemcpy(m, s->adam_m, N_PARAMS * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && v) e = hipMemcpy(v, s->adam_v, N_PARAMS * 4, hipMemcpyDeviceToHost);
+    if (step) *step = s->step;
+    return e;
+}
+
+hipError_t surrogate_set_norm(Surrogate *s, const float *mu, const float *sg)
+{
+    hipError_t e = hipMemcpy(s->mu, mu, NCOEF * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->sg, sg, NCOEF * 4, hipMemcpyHostToDevice);
+    return e;
+}
+
+template <bool TA, bool TB, int EPI>
+static void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, int K, int kchunk, int split, const float *bias,
+                 const __bf16 *mask, int ldm, void *out, int ldo, int M, int N, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), dim3(N / TN, M / TM, split), dim3(256), 0, st, A, lda, B, ldb, K, kchunk,
+                       bias, mask, ldm, out, ldo, M, N);
+}
+
+static void forward_layers(Surrogate *s, const float *gbuf, int n_img, int H, int W, hipStream_t st)
+{
+    const int64_t rows = (int64_t)n_img * H * W;
+    hipLaunchKernelGGL(k_im2col, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, st, gbuf, n_img, H, W,
+                       s->x[0]);
+    for (int l = 0; l < NL; ++l) {
+        if (l < NL - 1)
+            gemm<false, false, EPI_BIAS_RELU>(s->x[l], LKP[l], s->wt[l], LKP[l], LKP[l], LKP[l], 1, s->bias[l],
+                                              nullptr, 0, s->x[l + 1], LKP[l + 1], (int)rows, LN[l], st);
+        else
+            gemm<false, false, EPI_BIAS>(s->x[l], LKP[l], s->wt[l], LKP[l], LKP[l], LKP[l], 1, s->bias[l], nullptr, 0,
+                                         s->y, NCOEF, (int)rows, LN[l], st);
+    }
+}
+
+hipError_t surrogate_forward(Surrogate *s, const float *gbuf, int n_img, int H, int W, float *coef, hipStream_t st)
+{
+    forward_layers(s, gbuf, n_img, H, W, st);
+    const int64_t rows = (int64_t)n_img * H * W;
+    return hipMemcpyAsync(coef, s->y, (size_t)rows * NCOEF * 4, hipMemcpyDeviceToDevice, st);
+}
+
+// Forward, loss and backward into s->grad; returns the loss on the device.
+static hipError_t gradient(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
+                           float *dev_loss, hipStream_t st)
+{
+    const int64_t rows = (int64_t)n_img * H * W;
+    forward_layers(s, gbuf, n_img, H, W, st);
+    const int64_t n = rows * NCOEF;
+    const int nblk = (int)((n + 4095) / 4096);
+    hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, st, s->y, target, n, s->dz[0], s->dpart);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, s->dpart, nblk, n, dev_loss);
+    const int S = (int)((rows + SPLIT_ROWS - 1) / SPLIT_ROWS);
+    int cur = 0;
+    for (int l = NL - 1; l >= 0; --l) {
+        const int K = LKP[l], N = LN[l];
+        __bf16 *dzl = s->dz[cur];
+        // weight gradient: X_l^T dZ_l, split over row chunks, then a fixed-order sum
+        gemm<true, true, EPI_PARTIAL>(s->x[l], K, dzl, N, (int)rows, SPLIT_ROWS, S, nullptr, nullptr, 0, s->part, N, K,
+                                      N, st);
+        hipLaunchKernelGGL(k_reduce_partials, dim3((K * N + 255) / 256), dim3(256), 0, st, s->part, S, K, N, LK[l],
+                           s->grad + layer_param_offset(l));
+        // bias gradient: column sums of dZ_l
+        hipLaunchKernelGGL(k_colsum, dim3(S, N / 64), dim3(256), 0, st, dzl, rows, N, s->part);
+        hipLaunchKernelGGL(k_reduce_partials, dim3((N + 255) / 256), dim3(256), 0, st, s->part, S, 1, N, 1,
+                           s->grad + layer_param_offset(l) + (int64_t)LK[l] * N);
+        if (l > 0) {
+            // dZ_{l-1} = (dZ_l W_l^T) masked by x_l > 0
+            gemm<false, false, EPI_MASK>(dzl, N, s->wk[l], N, N, N, 1, nullptr, s->x[l], K, s->dz[cur ^ 1], K,
+                                         (int)rows, K, st);
+            cur ^= 1;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t surrogate_gradient(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
+                              float *dev_grad, float *dev_loss, hipStream_t st)
+{
+    hipError_t e = gradient(s, gbuf, n_img, H, W, target, dev_loss, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dev_grad, s->grad, N_PARAMS * 4, hipMemcpyDeviceToDevice, st);
+    return e;
+}
+
+hipError_t surrogate_train_step(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
+                                float lr, float *dev_loss, hipStream_t st)
+{
+    hipError_t e = gradient(s, gbuf, n_img, H, W, target, dev_loss, st);
+    if (e != hipSuccess) return e;
+    s->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - pow(0.9, (double)s->step)), c2 = (float)(1.0 - pow(0.999, (double)s->step));
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((N_PARAMS + 255) / 256)), dim3(256), 0, st, s->master, s->adam_m,
+                       s->adam_v, s->grad, N_PARAMS, lr, b1, b2, 1e-8f, c1, c2);
+    return pack_all(s, st);
+}
+
+static void smooth_channels(const Surrogate *s, const float *i1, const float *im, int64_t rows, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_smooth, dim3((unsigned)rows), dim3(256), (size_t)2 * s->n_bins * 4, st, i1, im, s->n_bins,
+                       s->smooth, s->s1, s->sm);
+}
+
+hipError_t surrogate_residual_coef(const Surrogate *s, const float *i1, const float *im, const float *gbuf,
+                                   int64_t rows, int standardize, float *coef, hipStream_t st)
+{
+    smooth_channels(s, i1, im, rows, st);
+    hipLaunchKernelGGL(k_residual_coef, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, st, s->s1, s->sm, gbuf,
+                       rows, s->n_bins, s->r_min, s->r_max, s->basis, s->mu, s->sg, standardize, coef);
+    return hipGetLastError();
+}
+
+hipError_t surrogate_coef_moments(Surrogate *s, const float *coef, int64_t rows, double *host_sum, double *host_sq,
+                                  hipStream_t st)
+{
+    const int nb = (int)((rows + SPLIT_ROWS - 1) / SPLIT_ROWS);
+    hipLaunchKernelGGL(k_coef_moments, dim3(nb), dim3(256), 0, st, coef, rows, s->dpart);
+    std::vector<double> h((size_t)nb * 128);
+    hipError_t e = hipMemcpyAsync(h.data(), s->dpart, h.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    for (int j = 0; j < 64; ++j) {
+        double a = 0, b = 0;
+        for (int q = 0; q < nb; ++q) {
+            a += h[(size_t)q * 128 + j];
+            b += h[(size_t)q * 128 + 64 + j];
+        }
+        host_sum[j] = a;
+        host_sq[j] = b;
+    }
+    return hipSuccess;
+}
+
+hipError_t surrogate_profile_errors(const Surrogate *s, const float *pred, const float *i1, const float *im,
+                                    const float *gbuf, int64_t rows, float *err, float *profile, hipStream_t st)
+{
+    // smooth i1 and (if given) im into the surrogate's buffers
+    smooth_channels(s, i1, im ? im : i1, rows, st);
+    hipLaunchKernelGGL(k_profile_errors, dim3((unsigned)((rows + 15) / 16)), dim3(256), 0, st, pred, s->s1,
+                       im ? s->sm : nullptr, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->basis, s->mu, s->sg, err,
+                       profile);
+    return hipGetLastError();
+}
+
+int64_t surrogate_max_rows(const Surrogate *s) { return s->max_rows; }
+int surrogate_bins(const Surrogate *s) { return s->n_bins; }
+
+}  // namespace sonar

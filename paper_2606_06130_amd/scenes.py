@@ -417,3 +417,22 @@ def random_poses(seed: int, n: int, pile_seed: int = 3):
             continue
         out.append(pose((x, y, z), yaw, -pitch_up, 0.0, ping=len(out)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# initial weights of the multipath surrogate (random draws shared by the
+# library and its checks)
+
+SURROGATE_LAYERS = ((63, 64), (64, 256), (256, 256), (256, 256), (256, 64))
+
+
+def surrogate_init_params(seed: int) -> np.ndarray:
+    """He-uniform weights U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)) and zero
+    biases, in the parameter-vector layout (per layer W [fan_in][fan_out] then b)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for k, n in SURROGATE_LAYERS:
+        lim = math.sqrt(6.0 / k)
+        parts.append(rng.uniform(-lim, lim, k * n))
+        parts.append(np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)

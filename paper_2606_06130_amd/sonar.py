@@ -28,7 +28,11 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_status_string", "sonar_last_error", "sonar_params_from_resolution",
            "sonar_batch_desc_bytes", "sonar_batch_workspace_size", "sonar_batch_prepare", "sonar_ping_batch",
            "sonar_batch_stamps", "sonar_batch_graph_create", "sonar_graph_launch", "sonar_graph_free",
-           "sonar_batch_autotune")
+           "sonar_batch_autotune", "sonar_surrogate_param_count", "sonar_surrogate_create",
+           "sonar_surrogate_free", "sonar_surrogate_set_state", "sonar_surrogate_get_state",
+           "sonar_surrogate_set_norm", "sonar_surrogate_forward", "sonar_surrogate_train_step",
+           "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
+           "sonar_surrogate_profile")
 
 
 class SonarError(RuntimeError):
@@ -140,6 +144,36 @@ def lib():
         L.sonar_batch_autotune.restype = C.c_int
         L.sonar_batch_autotune.argtypes = [C.c_void_p, P(sonar_batch_plan), C.c_void_p, C.c_void_p, C.c_size_t,
                                            C.c_void_p, P(sonar_batch_options), P(C.c_float)]
+        L.sonar_surrogate_param_count.restype = C.c_int64
+        L.sonar_surrogate_param_count.argtypes = []
+        L.sonar_surrogate_create.restype = C.c_int
+        L.sonar_surrogate_create.argtypes = [C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                             P(C.c_void_p)]
+        L.sonar_surrogate_free.restype = None
+        L.sonar_surrogate_free.argtypes = [C.c_void_p]
+        L.sonar_surrogate_set_state.restype = C.c_int
+        L.sonar_surrogate_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+        L.sonar_surrogate_get_state.restype = C.c_int
+        L.sonar_surrogate_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
+        L.sonar_surrogate_set_norm.restype = C.c_int
+        L.sonar_surrogate_set_norm.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_forward.restype = C.c_int
+        L.sonar_surrogate_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                              C.c_void_p]
+        L.sonar_surrogate_train_step.restype = C.c_int
+        L.sonar_surrogate_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                                 C.c_float, C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_gradient.restype = C.c_int
+        L.sonar_surrogate_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_residual.restype = C.c_int
+        L.sonar_surrogate_residual.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                               C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_moments.restype = C.c_int
+        L.sonar_surrogate_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_profile.restype = C.c_int
+        L.sonar_surrogate_profile.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                              C.c_void_p, C.c_void_p, C.c_void_p]
         L.sonar_params_from_resolution.restype = C.c_int
         L.sonar_params_from_resolution.argtypes = [C.c_double] * 7 + [P(sonar_params)]
         _lib = L
@@ -393,3 +427,90 @@ class Batch:
         b = np.zeros(self.n, np.uint64)
         _check(lib().sonar_batch_stamps(_dptr(self.workspace), self.n, a.ctypes.data, b.ctypes.data, _stream(stream)))
         return a, b
+
+
+class Surrogate:
+    """The learned multipath surrogate (weights, Adam state, activations on the device)."""
+
+    def __init__(self, max_rows: int, n_bins: int, r_min: float = 0.3, r_max: float = 15.0, smooth: int = 32):
+        self._h = C.c_void_p()
+        _check(lib().sonar_surrogate_create(int(max_rows), int(n_bins), float(r_min), float(r_max), int(smooth),
+                                            C.byref(self._h)))
+        self.n_params = int(lib().sonar_surrogate_param_count())
+        self.n_bins = n_bins
+        self.max_rows = max_rows
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sonar_surrogate_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, params, adam_m=None, adam_v=None, step=0):
+        p = np.ascontiguousarray(params, np.float32)
+        m = None if adam_m is None else np.ascontiguousarray(adam_m, np.float32)
+        v = None if adam_v is None else np.ascontiguousarray(adam_v, np.float32)
+        _check(lib().sonar_surrogate_set_state(self._h, p.ctypes.data, m.ctypes.data if m is not None else None,
+                                               v.ctypes.data if v is not None else None, int(step)))
+
+    def get_state(self):
+        n = self.n_params
+        p, m, v = (np.zeros(n, np.float32) for _ in range(3))
+        st = C.c_int64()
+        _check(lib().sonar_surrogate_get_state(self._h, p.ctypes.data, m.ctypes.data, v.ctypes.data, C.byref(st)))
+        return p, m, v, int(st.value)
+
+    def set_norm(self, mean, std):
+        a = np.ascontiguousarray(mean, np.float32)
+        b = np.ascontiguousarray(std, np.float32)
+        _check(lib().sonar_surrogate_set_norm(self._h, a.ctypes.data, b.ctypes.data))
+
+    def forward(self, gbuf, out=None, stream=None):
+        import torch
+        n, H, W = gbuf.shape[0], gbuf.shape[1], gbuf.shape[2]
+        out = out if out is not None else torch.empty((n * H * W, 64), dtype=torch.float32, device="cuda")
+        _check(lib().sonar_surrogate_forward(self._h, _dptr(gbuf), n, H, W, _dptr(out), _stream(stream)))
+        return out
+
+    def train_step(self, gbuf, target, lr, loss_out, stream=None):
+        n, H, W = gbuf.shape[0], gbuf.shape[1], gbuf.shape[2]
+        _check(lib().sonar_surrogate_train_step(self._h, _dptr(gbuf), n, H, W, _dptr(target), float(lr),
+                                                _dptr(loss_out), _stream(stream)))
+
+    def gradient(self, gbuf, target, stream=None):
+        import torch
+        n, H, W = gbuf.shape[0], gbuf.shape[1], gbuf.shape[2]
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().sonar_surrogate_gradient(self._h, _dptr(gbuf), n, H, W, _dptr(target), _dptr(g), _dptr(loss),
+                                              _stream(stream)))
+        return g, loss
+
+    def residual(self, i1, im, gbuf, standardize=True, out=None, stream=None):
+        import torch
+        rows = i1.numel() // self.n_bins
+        out = out if out is not None else torch.empty((rows, 64), dtype=torch.float32, device="cuda")
+        _check(lib().sonar_surrogate_residual(self._h, _dptr(i1), _dptr(im), _dptr(gbuf), rows,
+                                              1 if standardize else 0, _dptr(out), _stream(stream)))
+        return out
+
+    def moments(self, coef, stream=None):
+        s1 = np.zeros(64)
+        s2 = np.zeros(64)
+        _check(lib().sonar_surrogate_moments(self._h, _dptr(coef), coef.shape[0], s1.ctypes.data, s2.ctypes.data,
+                                             _stream(stream)))
+        return s1, s2
+
+    def profile(self, coef, i1, gbuf, im=None, want_profile=True, stream=None):
+        import torch
+        rows = coef.shape[0]
+        prof = torch.empty((rows, self.n_bins), dtype=torch.float32, device="cuda") if want_profile else None
+        err = torch.empty((rows, 4), dtype=torch.float32, device="cuda") if im is not None else None
+        _check(lib().sonar_surrogate_profile(self._h, _dptr(coef), _dptr(i1), _dptr(im), _dptr(gbuf), rows,
+                                             _dptr(prof), _dptr(err), _stream(stream)))
+        return prof, err

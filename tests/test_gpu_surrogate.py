@@ -1,0 +1,187 @@
+"""Surrogate kernels vs the FP64 oracle, training, checkpoints and the gain
+over single-bounce echoes (needs an MI355X)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import surrogate as SO
+from paper_2606_06130_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_06130_amd import sonar
+    return torch, sonar
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def bf16_round(x):
+    """Round to the nearest BF16 value (ties to even), returned as float32."""
+    a = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((a + 0x7FFF + ((a >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def _inputs(seed, n=1, H=8, W=16):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = bf16_round(rng.uniform(-1, 1, (n, H, W, 8)).astype(np.float32))
+    t = rng.normal(0, 1, (n * H * W, 64)).astype(np.float32)
+    theta = S.surrogate_init_params(seed + 1)
+    # BF16 weights so both sides use the same operand values; biases stay FP32
+    off = 0
+    for k, nn in S.SURROGATE_LAYERS:
+        theta[off:off + k * nn] = bf16_round(theta[off:off + k * nn])
+        off += k * nn
+        theta[off:off + nn] = rng.normal(0, 0.05, nn)
+        off += nn
+    return g, t, theta
+
+
+def _split(v):
+    out, o = [], 0
+    for k, n in S.SURROGATE_LAYERS:
+        out.append(v[o:o + k * n])
+        o += k * n
+        out.append(v[o:o + n])
+        o += n
+    return out
+
+
+def test_gradient_matches_oracle():
+    torch, sonar = _gpu()
+    g, t, theta = _inputs(1)
+    sur = sonar.Surrogate(128, 1024)
+    sur.set_state(theta)
+    gd, loss = sur.gradient(torch.from_numpy(g).cuda(), torch.from_numpy(t).cuda())
+    gg = gd.cpu().numpy().astype(np.float64)
+    lo, go, _ = SO.loss_and_grad(theta.astype(np.float64), g, t)
+    # the same FP64 definition with activations and layer gradients stored in
+    # BF16, as the kernels store them
+    lb, gob, _ = SO.loss_and_grad(theta.astype(np.float64), g, t, store=lambda a: bf16_round(a).astype(np.float64))
+    assert abs(float(loss.item()) - lo) <= 2e-2 * lo
+    res = []
+    for i, (a, b, c) in enumerate(zip(_split(gg), _split(go), _split(gob))):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        relb = np.linalg.norm(a - c) / np.linalg.norm(c)
+        _log("tensor", i, "rel", rel, "cos", cos, "rel vs bf16-stored", relb)
+        res.append((i, rel, cos, relb))
+    for i, rel, cos, relb in res:
+        # exact definition: BF16 storage of activations and layer gradients
+        # (unit roundoff 2^-9) through 5 layers, plus ReLU masks that flip
+        # where a pre-activation is within rounding of zero
+        assert rel <= 5e-2 and cos >= 0.999, (i, rel, cos)
+        # same storage precision: only FP32 accumulation order differs
+        assert relb <= 5e-3, (i, relb)
+
+
+def test_forward_matches_oracle():
+    torch, sonar = _gpu()
+    g, _, theta = _inputs(2, n=2)
+    sur = sonar.Surrogate(256, 1024)
+    sur.set_state(theta)
+    y = sur.forward(torch.from_numpy(g).cuda()).cpu().numpy()
+    _, yo = SO.forward(theta.astype(np.float64), SO.im2col(g))
+    rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    _log("forward rel", rel)
+    assert rel <= 1e-2
+
+
+def test_residual_coefficients_and_profile_match_oracle():
+    torch, sonar = _gpu()
+    rng = np.random.Generator(np.random.PCG64(3))
+    rows, nb = 100, 1024
+    i1 = (rng.exponential(1e-8, (rows, nb)) * (rng.random((rows, nb)) < 0.2)).astype(np.float32)
+    im = (rng.exponential(1e-9, (rows, nb)) * (rng.random((rows, nb)) < 0.3)).astype(np.float32)
+    gb = np.zeros((rows, 8), np.float32)
+    gb[:, 0] = rng.uniform(0.0, 1.0, rows)
+    gb[:, 6] = (rng.random(rows) < 0.8) * rng.uniform(0.2, 1.0, rows)
+    r1 = SO.first_hit_bin(gb, 0.3, 15.0, nb)
+    assert (r1 > 0).sum() > 50
+    sur = sonar.Surrogate(128, nb, 0.3, 15.0, 32)
+    mean = rng.normal(0, 1, 64).astype(np.float32)
+    std = rng.uniform(0.5, 2, 64).astype(np.float32)
+    sur.set_norm(mean, std)
+    ti1, tim, tgb = torch.from_numpy(i1).cuda(), torch.from_numpy(im).cuda(), torch.from_numpy(gb).cuda()
+    raw = sur.residual(ti1, tim, tgb, standardize=False).cpu().numpy()
+    want = SO.aligned_residual_coefficients(i1, im, r1)
+    assert np.abs(raw - want).max() <= 1e-4 * np.abs(want).max()
+    stdz = sur.residual(ti1, tim, tgb, standardize=True).cpu().numpy()
+    np.testing.assert_allclose(stdz, (want - mean) / std, atol=1e-4 * np.abs(want).max())
+    # profile and per-beam errors from standardised predictions
+    pred = rng.normal(0, 1, (rows, 64)).astype(np.float32)
+    prof, err = sur.profile(torch.from_numpy(pred).cuda(), ti1, tgb, tim)
+    prof, err = prof.cpu().numpy(), err.cpu().numpy()
+    coef = pred.astype(np.float64) * std + mean
+    want_prof = SO.aligned_profile(i1, coef, r1)
+    assert np.abs(prof - want_prof).max() <= 2e-3
+    e_sur, n = SO.aligned_beam_errors(i1, im, want_prof)
+    e_one, _ = SO.aligned_beam_errors(i1, im, 10 * np.log10(SO.smooth_range(i1) + SO.I_FLOOR))
+    e_mean, _ = SO.aligned_beam_errors(i1, im, SO.aligned_profile(i1, np.broadcast_to(mean, (rows, 64)), r1))
+    np.testing.assert_array_equal(err[:, 3], n)
+    ok = n > 0
+    assert ok.sum() > 50
+    np.testing.assert_allclose(err[ok, 0], e_sur[ok], atol=2e-3)
+    np.testing.assert_allclose(err[ok, 1], e_one[ok], atol=2e-3)
+    np.testing.assert_allclose(err[ok, 2], e_mean[ok], atol=2e-3)
+
+
+def test_training_reduces_loss_and_resumes_bit_exactly():
+    torch, sonar = _gpu()
+    g, t, theta = _inputs(4, n=2)
+    G, T = torch.from_numpy(g).cuda(), torch.from_numpy(t).cuda()
+    loss = torch.zeros(1, device="cuda")
+    a = sonar.Surrogate(256, 1024)
+    a.set_state(theta)
+    a.train_step(G, T, 1e-3, loss)
+    first = float(loss.item())
+    for _ in range(49):
+        a.train_step(G, T, 1e-3, loss)
+    mid = a.get_state()
+    for _ in range(150):
+        a.train_step(G, T, 1e-3, loss)
+    last = float(loss.item())
+    _log("loss", first, last)
+    assert last < first / 5
+    b = sonar.Surrogate(256, 1024)
+    b.set_state(*mid)
+    for _ in range(150):
+        b.train_step(G, T, 1e-3, loss)
+    pa, ma, va, sa = a.get_state()
+    pb, mb, vb, sb = b.get_state()
+    assert sa == sb == 200
+    assert np.array_equal(pa, pb) and np.array_equal(ma, mb) and np.array_equal(va, vb)
+
+
+def test_surrogate_gains_over_single_bounce():
+    """Small layout on the 1.99M-triangle multipath scene: train on 160 poses,
+    evaluate on 24 held-out poses; the network must beat both the
+    single-bounce profile and the single-bounce profile plus the mean residual."""
+    torch, sonar = _gpu()
+    from paper_2606_06130_amd import surrogate as SU
+    mesh = S.scene_harbor_multipath()
+    scene = sonar.Scene(mesh)
+    cfg = S.sensor_harbor_multipath().replace(n_h=64, n_v=32, rays_per_beam=8)
+    src = SU.PingSource(scene, cfg)
+    train_poses = S.random_poses(5, 160)
+    eval_poses = S.random_poses(6, 24)
+    sur = sonar.Surrogate(8 * src.rows, cfg.n_range, cfg.r_min, cfg.r_max)
+    mean, std = SU.coefficient_stats(sur, src, train_poses[:32])
+    sur.set_norm(mean, std)
+    sur.set_state(S.surrogate_init_params(11))
+    SU.train(sur, src, train_poses, epochs=12, batch_pings=8, lr0=1e-3, log=_log)
+    res = SU.evaluate(sur, src, eval_poses)
+    _log("held-out", res)
+    assert res["beams"] > 1000
+    assert res["surrogate"]["mean_db"] < res["single_bounce"]["mean_db"]
+    assert res["surrogate"]["mean_db"] < res["mean_residual"]["mean_db"]

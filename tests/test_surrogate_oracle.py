@@ -5,6 +5,7 @@ import pytest
 from scipy import fft
 
 from oracle import surrogate as SO
+from paper_2606_06130_amd.scenes import surrogate_init_params
 
 
 def test_parameter_count():
@@ -31,7 +32,7 @@ def test_im2col_brute_force():
 
 def test_gradients_match_central_differences():
     rng = np.random.Generator(np.random.PCG64(2))
-    theta = SO.init_params(3).astype(np.float64)
+    theta = surrogate_init_params(3).astype(np.float64)
     theta += rng.normal(0, 0.01, theta.size)                  # nonzero biases
     g = rng.uniform(-1, 1, size=(1, 4, 5, 8))
     t = rng.normal(size=(20, 64))
@@ -87,3 +88,42 @@ def test_zero_residual_gives_single_bounce_profile():
     assert np.abs(c).max() < 1e-12
     err, n = SO.beam_errors(i1, np.zeros_like(i1), SO.profile_from_coefficients(i1, c))
     assert np.all(err < 1e-10) and np.all(n == 1024)
+
+
+def test_smoothing_and_alignment_definitions():
+    rng = np.random.Generator(np.random.PCG64(6))
+    a = rng.random((3, 100))
+    s = SO.smooth_range(a, 8)
+    # interior: plain window mean; total mass preserved away from the edges
+    np.testing.assert_allclose(s[:, 50], a[:, 46:54].mean(axis=1))
+    np.testing.assert_allclose(s[:, 0], a[:, 0:4].sum(axis=1) / 8)
+    # alignment: a residual confined after r1 maps back exactly through the full basis
+    i1 = np.zeros((2, 256))
+    im = np.zeros((2, 256))
+    i1[:, 100:120] = 1e-8
+    im[:, 130:150] = 1e-8
+    r1 = np.array([100, 90])
+    c = SO.aligned_residual_coefficients(i1, im, r1)
+    assert c.shape == (2, 64)
+    prof = SO.aligned_profile(i1, c, r1)
+    # the truncated reconstruction is the projection of the aligned residual
+    res = SO.residual_db(SO.smooth_range(i1), SO.smooth_range(im))
+    C = SO.dct_basis(256)
+    for k in range(2):
+        al = np.zeros(256)
+        al[:256 - r1[k]] = res[k, r1[k]:]
+        proj = al @ C.T @ C
+        want = 10 * np.log10(SO.smooth_range(i1)[k] + SO.I_FLOOR)
+        want[r1[k]:] += proj[:256 - r1[k]]
+        np.testing.assert_allclose(prof[k], want, atol=1e-9)
+
+
+def test_first_hit_bin():
+    g = np.zeros((3, 8), np.float32)
+    g[0, 0], g[0, 6] = 10.0 / 15.0, 1.0
+    g[1, 0], g[1, 6] = 10.0 / 15.0, 0.0          # no hits
+    g[2, 0], g[2, 6] = 0.01, 0.5                 # before r_min
+    b = SO.first_hit_bin(g, 0.3, 15.0, 1024)
+    assert b[0] == int(np.floor((np.float32(10.0 / 15.0) * np.float32(15.0) - np.float32(0.3))
+                                / np.float32(14.7 / 1024)))
+    assert b[1] == 0 and b[2] == 0
