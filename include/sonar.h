@@ -135,12 +135,17 @@ typedef void *sonar_stream;
 
 /* Optional per-ray record, device arrays of [n_rays][max_bounces] with
  * n_rays = beams * rays_per_beam in (beam, ray) order: hit triangle (-1 none),
- * range bin (-1 none), connection visibility (1 visible), and contribution. */
+ * range bin (-1 none), connection visibility (1 visible), and contribution;
+ * `stats` (optional, [n_rays][3]) receives, over all of the ray's traversals,
+ * the internal nodes visited, the triangles tested and the deepest traversal
+ * stack. Counting uses separate kernel instantiations: indices and bins are
+ * the same as without it, values the same up to rounding. */
 typedef struct {
     int32_t *tri;
     int32_t *bin;
     int32_t *vis;
     sonar_cf32 *amp;
+    uint32_t *stats;
 } sonar_ray_record;
 
 typedef struct {

@@ -117,7 +117,7 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
     if ((st = check_pose(q)) != SONAR_OK) return st;
     if (!volume) return fail(SONAR_E_INVALID, "volume is NULL");
     if (rec && (!rec->tri || !rec->bin || !rec->vis || !rec->amp))
-        return fail(SONAR_E_INVALID, "record arrays must all be set");
+        return fail(SONAR_E_INVALID, "record arrays tri, bin, vis and amp must all be set");
     // a sound speed must stay positive over the scene and the sensor
     if (p->c_grad != 0.0) {
         double zmax = fmax((double)sc->s.zabs_max, fabs(q->position[2])) + 1.0;
@@ -175,6 +175,7 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
         a.rec_bin = rec->bin;
         a.rec_vis = rec->vis;
         a.rec_amp = reinterpret_cast<float2 *>(rec->amp);
+        a.stats = rec->stats;
     }
     a.mask = ray_mask;
     a.max_steps = (uint32_t)(2 * sc->s.n_nodes + 64);

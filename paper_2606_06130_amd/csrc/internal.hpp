@@ -73,6 +73,7 @@ struct PingArgs {
     float *incoh;
     int32_t *rec_tri, *rec_bin, *rec_vis;
     float2 *rec_amp;
+    uint32_t *stats;         // optional [n_rays][3]: internal nodes visited, triangles tested, deepest stack
     const uint32_t *mask;
     uint32_t max_steps;      // node-visit bound of one traversal (2 * nodes + 64)
     // fused detection (det_count == nullptr: off)

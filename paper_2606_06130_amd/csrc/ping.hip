@@ -28,10 +28,16 @@ constexpr double EPS_SELF = 1e-4;        // minimum hit distance (m)
 constexpr double TWO_PI = 6.283185307179586476925287;
 constexpr double LN10_OVER_20 = 0.11512925464970228420;
 
-// LDS words per wave used by the accumulation stage (bins, values, index).
-constexpr int ACC_BIN_WORDS = MAX_BOUNCES * WAVE;             // int bin per slot
-constexpr int ACC_VAL_WORDS = MAX_BOUNCES * WAVE * 4;         // float4 per slot
-constexpr int ACC_IDX_BASE = ACC_BIN_WORDS + ACC_VAL_WORDS;   // uint16 column index
+// Single-bounce LDS words per wave for the accumulation stage (one slot per
+// lane: bin, value; then the uint16 column index). The area is shared with
+// the traversal stack, which is dead by then.
+constexpr int K1_BIN_WORDS = WAVE;                            // int bin per slot
+constexpr int K1_VAL_WORDS = WAVE * 4;                        // float4 per slot
+constexpr int K1_IDX_BASE = K1_BIN_WORDS + K1_VAL_WORDS;      // uint16 column index
+// Single-bounce traversals keep the bottom K1_LDS_STACK stack entries of each
+// lane in LDS and deeper ones in private memory. Typical traversals stay in
+// LDS; the short LDS stack is what lets eight waves share a SIMD.
+constexpr int K1_LDS_STACK = 20;
 
 struct d3 {
     double x, y, z;
@@ -293,10 +299,10 @@ __device__ __forceinline__ float arc32(const Seg32 &r, const TriF &t, float &tc)
 // Returns the triangle record index, or -1; `overflow` is set when the LDS
 // stack of DEPTH entries would overflow or the node-visit bound is reached
 // (the ray is then reported as a miss).
-template <int DEPTH, bool ANY, bool ARC>
+template <int DEPTH, int DL, bool ANY, bool ARC, bool STATS>
 __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restrict__ tris, const Seg32 &r,
                         uint32_t skip, uint32_t *__restrict__ stk, int lane, bool &overflow, float &s_out,
-                        uint32_t max_steps)
+                        uint32_t max_steps, uint32_t &n_nodes, uint32_t &n_tris, uint32_t &n_deep)
 {
     int best = -1;
     float best_t = r.tmax;        // culling bound on the ray / chord parameter
@@ -305,6 +311,8 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
     const float sg = r.sigma;
     uint32_t cur = 0;
     int sp = 0;
+    // entries sp >= DL: private memory (volatile keeps them out of registers)
+    volatile uint32_t spill[DEPTH > DL ? DEPTH - DL : 1];
     for (uint32_t step = 0;; ++step) {
         if (step >= max_steps) {   // bound on node visits: every wave exits
             overflow = true;
@@ -312,6 +320,7 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
             break;
         }
         if (!(cur & LEAF_BIT)) {
+            if (STATS) ++n_nodes;
             const float4 *n = nodes + 4 * (size_t)cur;
             float4 a = n[0], b = n[1], c = n[2], d = n[3];
             float t0, t1;
@@ -332,8 +341,10 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
                     best = -1;
                     break;
                 }
-                stk[sp * WAVE + lane] = farc;
+                if (DL == DEPTH || sp < DL) stk[sp * WAVE + lane] = farc;
+                else spill[sp - DL] = farc;
                 ++sp;
+                if (STATS) n_deep = max(n_deep, (uint32_t)sp);
                 cur = nearc;
                 continue;
             } else if (h0) {
@@ -346,6 +357,7 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
         } else if (cur != EMPTY_LINK) {
             uint32_t first = (cur & 0x7FFFFFFFu) >> 3;
             uint32_t cnt = (cur & 7u) + 1u;
+            if (STATS) n_tris += cnt;
             for (uint32_t k = 0; k < cnt; ++k) {
                 TriF t = load_tri(tris, first + k);
                 uint32_t id = t.idbits & 0x7FFFFFFFu;
@@ -371,7 +383,8 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
         }
         if (sp == 0) break;
         --sp;
-        cur = stk[sp * WAVE + lane];
+        if (DL == DEPTH || sp < DL) cur = stk[sp * WAVE + lane];
+        else cur = spill[sp - DL];
     }
     s_out = best_s;
     return best;
@@ -458,7 +471,7 @@ __device__ __forceinline__ Conn connect(d3 P, d3 S, double g, double c0)
 // The ping body for one tile of 256 consecutive rays (4 wavefronts). `a` is
 // the ping's argument block (kernel arguments, or a batch descriptor in
 // device memory); `W` is this wavefront's LDS area.
-template <int DEPTH, int K, bool ARC>
+template <int DEPTH, int K, bool ARC, bool STATS>
 __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uint32_t *__restrict__ W)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -470,8 +483,9 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
 
     // Contribution slots: registers for a single bounce; for several bounces
     // an LDS area past the traversal stack, slot (k, lane) at k * 64 + lane.
+    constexpr int DL = (K == 1 && DEPTH > K1_LDS_STACK) ? K1_LDS_STACK : DEPTH;
     int *sbin = (K == 1) ? reinterpret_cast<int *>(W) : reinterpret_cast<int *>(W + DEPTH * WAVE);
-    float4 *sval = (K == 1) ? reinterpret_cast<float4 *>(W + ACC_BIN_WORDS)
+    float4 *sval = (K == 1) ? reinterpret_cast<float4 *>(W + K1_BIN_WORDS)
                             : reinterpret_cast<float4 *>(W + DEPTH * WAVE + K * WAVE);
     Slot slot0 = Slot{-1, 0.f, 0.f, 0.f};
     if (K > 1) {
@@ -483,6 +497,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
     }
     float gfeat[7] = {0, 0, 0, 0, 0, 0, 0};
     bool overflow = false;
+    uint32_t st_nodes = 0, st_tris = 0, st_deep = 0;     // traversal work of this ray
 
     if (active) {
         // ---- ray generation (FP64)
@@ -536,8 +551,8 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                     const Seg32 seg = make_seg(path, EPS_SELF, s_lim * (1.0 + 1e-6));
                     float sf;
                     // in a gradient a vertical ray is a degenerate arc (kappa = 0)
-                    int ti = traverse<DEPTH, false, ARC>(a.nodes, a.tris, seg, prev, W, lane, overflow, sf,
-                                                         a.max_steps);
+                    int ti = traverse<DEPTH, DL, false, ARC, STATS>(a.nodes, a.tris, seg, prev, W, lane, overflow, sf,
+                                                         a.max_steps, st_nodes, st_tris, st_deep);
                     if (ti >= 0) {
                         TriF tr = load_tri(a.tris, (uint32_t)ti);
                         d3 nh;
@@ -641,8 +656,8 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                                     ARC ? make_path(X, w, a.g, a.c0) : Path64{X, w, mk3(0, 0, 0), 0.0, false};
                                 const Seg32 cs = make_seg(cp, EPS_SELF, L_back - EPS_SELF);
                                 float sa2;
-                                int hb = traverse<DEPTH, true, ARC>(a.nodes, a.tris, cs, id, W, lane, overflow, sa2,
-                                                                    a.max_steps);
+                                int hb = traverse<DEPTH, DL, true, ARC, STATS>(a.nodes, a.tris, cs, id, W, lane, overflow, sa2,
+                                                                    a.max_steps, st_nodes, st_tris, st_deep);
                                 if (hb >= 0) {
                                     vis = false;
                                     cbin = -1;
@@ -667,6 +682,11 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                 sbin[k * WAVE + lane] = cbin;
                 sval[k * WAVE + lane] = k == 0 ? make_float4(cre, cim, cinc, 0.f) : make_float4(cre, cim, 0.f, cinc);
             }
+        }
+        if (STATS) {
+            a.stats[3 * ray] = st_nodes;
+            a.stats[3 * ray + 1] = st_tris;
+            a.stats[3 * ray + 2] = st_deep;
         }
         if (masked) {
             slot0.bin = -1;
@@ -695,7 +715,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
     // ---- accumulation: fixed-order reduction of equal (beam, bin) slots
     wave_sync();
     // column index: past the slots for one bounce, in the (now free) stack area otherwise
-    uint32_t *sidx32 = (K == 1) ? W + ACC_IDX_BASE : W;
+    uint32_t *sidx32 = (K == 1) ? W + K1_IDX_BASE : W;
     uint16_t *sidx = reinterpret_cast<uint16_t *>(sidx32);
     if (K == 1) {
         sbin[lane] = slot0.bin;
@@ -739,13 +759,84 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         sum[k] = acc;
     }
     wave_sync();
+    // from here on a slot that still holds a bin is a head carrying its bin's sum
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) {
         if (head[k]) sval[k * WAVE + lane] = sum[k];
+        else sbin[k * WAVE + lane] = -1;
+    }
+    wave_sync();
 
     const int bpw = WAVE >> a.log2_nr;
     const int64_t wave_beam0 = (((int64_t)tile * BLOCK) + wave * WAVE) >> a.log2_nr;
     const int nb = a.n_bins;
+
+    if (a.det_count) {
+        // CA-CFAR on the beam's head slots, all beams of the wave at once. A
+        // bin without a return has power N0 <= the training mean and alpha(N)
+        // > 1, so only bins holding a return can be detected; a training sum
+        // is N * N0 plus the excess of the returns inside the window.
+        const float n0 = a.det_n0;
+        uint64_t key[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            key[k] = 0ull;
+            if (!head[k]) continue;
+            const int bin = my_bin[k];
+            const float4 v = sum[k];
+            const float p = v.x * v.x + v.y * v.y + n0;
+            const int l0 = max(bin - a.det_G - a.det_T, 0), l1 = max(bin - a.det_G, 0);
+            const int h0 = min(bin + a.det_G + 1, nb), h1 = min(bin + a.det_G + a.det_T + 1, nb);
+            const int N = (l1 - l0) + (h1 - h0);
+            float pl = n0, pr = n0;
+            double wsum = (double)N * (double)n0;
+            for (int jj = 0; jj < nr; ++jj) {
+                for (int kk = 0; kk < K; ++kk) {
+                    const int s2 = kk * WAVE + base_lane + jj;
+                    const int b2 = sbin[s2];
+                    if (b2 < 0) continue;
+                    const bool inw = (b2 >= l0 && b2 < l1) || (b2 >= h0 && b2 < h1);
+                    if (!inw && b2 != bin - 1 && b2 != bin + 1) continue;
+                    const float4 u = sval[s2];
+                    const float pz = u.x * u.x + u.y * u.y + n0;
+                    if (b2 == bin - 1) pl = pz;
+                    if (b2 == bin + 1) pr = pz;
+                    if (inw) wsum += (double)pz - (double)n0;
+                }
+            }
+            if ((bin > 0 && !(p > pl)) || (bin + 1 < nb && !(p >= pr))) continue;
+            if (N <= 0) continue;
+            const double thr = a.det_alpha[N] * wsum / N;
+            if ((double)p > thr) key[k] = ((uint64_t)__float_as_uint(p) << 32) | (uint32_t)(~bin);
+        }
+        // the det_M strongest of each beam over its lanes, strongest first
+        // (every lane of a beam group leaves the loop at the same m)
+        const int64_t gb = wave_beam0 + bl;
+        unsigned taken = 0u;
+        int cnt = 0;
+        for (int m = 0; m < a.det_M; ++m) {
+            uint64_t my = 0ull;
+            int myk = -1;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (!((taken >> k) & 1u) && key[k] > my) { my = key[k]; myk = k; }
+            uint64_t best = my;
+            for (int off = 1; off < nr; off <<= 1) {
+                uint64_t o = __shfl_xor(best, off);
+                best = o > best ? o : best;
+            }
+            if (best == 0ull) break;
+            if (myk >= 0 && my == best) taken |= 1u << myk;
+            if (j == 0 && active) {
+                a.det_bins[(size_t)gb * a.det_M + m] = (int)(~(uint32_t)(best & 0xFFFFFFFFu));
+                a.det_pw[(size_t)gb * a.det_M + m] = __uint_as_float((uint32_t)(best >> 32));
+            }
+            cnt = m + 1;
+        }
+        if (j == 0 && active) a.det_count[gb] = cnt;
+    }
+
+    // ---- column write: one beam at a time through the LDS column index
     const int idx_words = (nb + 1) / 2;
     for (int q = 0; q < bpw; ++q) {
         const int64_t gb = wave_beam0 + q;
@@ -784,83 +875,18 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                 }
             }
         }
-        if (a.det_count) {
-            // CA-CFAR on the column while it is still indexed in LDS. A bin
-            // without a return has power N0 <= the training mean, and alpha(N)
-            // > 1, so only bins holding a return can be detected; the training
-            // sums are N * N0 plus the returns inside each window.
-            const float n0 = a.det_n0;
-            uint64_t key[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                key[k] = 0ull;
-                if (bl != q || !head[k]) continue;
-                const int bin = my_bin[k];
-                const float4 v = sum[k];
-                const float p = v.x * v.x + v.y * v.y + n0;
-                float pl = n0, pr = n0;
-                if (bin > 0) {
-                    uint32_t sl = sidx[bin - 1];
-                    if (sl) { float4 u = sval[sl - 1]; pl = u.x * u.x + u.y * u.y + n0; }
-                }
-                if (bin + 1 < nb) {
-                    uint32_t sr = sidx[bin + 1];
-                    if (sr) { float4 u = sval[sr - 1]; pr = u.x * u.x + u.y * u.y + n0; }
-                }
-                if ((bin > 0 && !(p > pl)) || (bin + 1 < nb && !(p >= pr))) continue;
-                const int l0 = max(bin - a.det_G - a.det_T, 0), l1 = max(bin - a.det_G, 0);
-                const int h0 = min(bin + a.det_G + 1, nb), h1 = min(bin + a.det_G + a.det_T + 1, nb);
-                const int N = (l1 - l0) + (h1 - h0);
-                if (N <= 0) continue;
-                double wsum = (double)N * (double)n0;
-                for (int side = 0; side < 2; ++side) {
-                    const int p0 = side ? h0 : l0, p1 = side ? h1 : l1;
-                    for (int pos = p0; pos < p1; ++pos) {
-                        uint32_t sz = sidx[pos];
-                        if (sz) {
-                            float4 u = sval[sz - 1];
-                            float pz = u.x * u.x + u.y * u.y + n0;
-                            wsum += (double)pz - (double)n0;
-                        }
-                    }
-                }
-                const double thr = a.det_alpha[N] * wsum / N;
-                if ((double)p > thr) key[k] = ((uint64_t)__float_as_uint(p) << 32) | (uint32_t)(~bin);
-            }
-            // the det_M strongest over the beam's lanes, strongest first
-            unsigned taken = 0u;
-            int cnt = 0;
-            for (int m = 0; m < a.det_M; ++m) {
-                uint64_t my = 0ull;
-                int myk = -1;
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (!((taken >> k) & 1u) && key[k] > my) { my = key[k]; myk = k; }
-                uint64_t best = my;
-                for (int off = 1; off < nr; off <<= 1) {
-                    uint64_t o = __shfl_xor(best, off);
-                    best = o > best ? o : best;
-                }
-                if (best == 0ull) break;
-                if (myk >= 0 && my == best) taken |= 1u << myk;
-                if (j == 0) {
-                    a.det_bins[(size_t)gb * a.det_M + m] = (int)(~(uint32_t)(best & 0xFFFFFFFFu));
-                    a.det_pw[(size_t)gb * a.det_M + m] = __uint_as_float((uint32_t)(best >> 32));
-                }
-                cnt = m + 1;
-            }
-            if (bl == q && j == 0) a.det_count[gb] = cnt;
-        }
         wave_sync();
     }
 }
 
-template <int DEPTH, int K, bool ARC>
+// STATS instantiations count traversal work per ray (a diagnostic: the
+// counters cost registers, so the plain instantiations carry none).
+template <int DEPTH, int K, bool ARC, bool STATS>
 __global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
 {
     extern __shared__ uint32_t lds[];
     uint32_t *W = lds + (size_t)(threadIdx.x / WAVE) * wave_words;
-    ping_tile<DEPTH, K, ARC>(a, xcd_remap(blockIdx.x, gridDim.x), W);
+    ping_tile<DEPTH, K, ARC, STATS>(a, xcd_remap(blockIdx.x, gridDim.x), W);
 }
 
 // Persistent batch: every block pops (ping, tile) items from one device
@@ -899,7 +925,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping_batch(const PingArgs *__restrict
             }
             const PingArgs &a = desc[lo];
             unsigned long long start = __builtin_amdgcn_s_memrealtime();
-            ping_tile<DEPTH, K, ARC>(a, gt - a.tile_offset, W);
+            ping_tile<DEPTH, K, ARC, false>(a, gt - a.tile_offset, W);
             __syncthreads();
             if (threadIdx.x == 0) {
                 unsigned long long end = __builtin_amdgcn_s_memrealtime();
@@ -924,10 +950,11 @@ __global__ void k_batch_reset(uint32_t *queue, unsigned long long *t0, unsigned 
 
 int ping_wave_words(int depth, int n_bins, int K)
 {
-    int stk = depth * WAVE;
-    if (K > 1) return stk + 5 * WAVE * K;      // stack + slots; the column index reuses the stack
-    int acc = ACC_IDX_BASE + (n_bins + 1) / 2;
-    return acc > stk ? acc : stk;
+    if (K > 1) return depth * WAVE + 5 * WAVE * K;    // stack + slots; the column index reuses the stack
+    const int stk = (depth > K1_LDS_STACK ? K1_LDS_STACK : depth) * WAVE;
+    const int acc = K1_IDX_BASE + (n_bins + 1) / 2;
+    const int w = acc > stk ? acc : stk;
+    return (w + 3) & ~3;                              // keeps every wave's float4 slots 16-byte aligned
 }
 
 hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s)
@@ -935,23 +962,26 @@ hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s)
     int64_t threads = (int64_t)a.n_beams * a.n_r;
     int nblocks = (int)((threads + BLOCK - 1) / BLOCK);
     if (nblocks == 0) return hipSuccess;
-    int depth = stack_depth <= 32 ? 32 : 64;
+    // the counting variants exist for the deep stack only (same results)
+    int depth = stack_depth <= 32 && !a.stats ? 32 : 64;
     int ww = ping_wave_words(depth, a.n_bins, a.K);
     size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
-#define SONAR_LAUNCH(D, KK, AR) \
-    hipLaunchKernelGGL((k_ping<D, KK, AR>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww)
-#define SONAR_LAUNCH_K(D, AR)                     \
-    switch (a.K) {                                \
-        case 1: SONAR_LAUNCH(D, 1, AR); break;    \
-        case 2: SONAR_LAUNCH(D, 2, AR); break;    \
-        case 3: SONAR_LAUNCH(D, 3, AR); break;    \
-        default: SONAR_LAUNCH(D, 4, AR); break;   \
+#define SONAR_LAUNCH(D, KK, AR, ST) \
+    hipLaunchKernelGGL((k_ping<D, KK, AR, ST>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww)
+#define SONAR_LAUNCH_K(D, AR, ST)                     \
+    switch (a.K) {                                    \
+        case 1: SONAR_LAUNCH(D, 1, AR, ST); break;    \
+        case 2: SONAR_LAUNCH(D, 2, AR, ST); break;    \
+        case 3: SONAR_LAUNCH(D, 3, AR, ST); break;    \
+        default: SONAR_LAUNCH(D, 4, AR, ST); break;   \
     }
     const bool arc = a.g != 0.0;
-    if (depth == 32) {
-        if (arc) { SONAR_LAUNCH_K(32, true) } else { SONAR_LAUNCH_K(32, false) }
+    if (a.stats) {
+        if (arc) { SONAR_LAUNCH_K(64, true, true) } else { SONAR_LAUNCH_K(64, false, true) }
+    } else if (depth == 32) {
+        if (arc) { SONAR_LAUNCH_K(32, true, false) } else { SONAR_LAUNCH_K(32, false, false) }
     } else {
-        if (arc) { SONAR_LAUNCH_K(64, true) } else { SONAR_LAUNCH_K(64, false) }
+        if (arc) { SONAR_LAUNCH_K(64, true, false) } else { SONAR_LAUNCH_K(64, false, false) }
     }
 #undef SONAR_LAUNCH_K
 #undef SONAR_LAUNCH

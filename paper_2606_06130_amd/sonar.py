@@ -68,7 +68,8 @@ class sonar_cfar(C.Structure):
 
 
 class sonar_ray_record(C.Structure):
-    _fields_ = [("tri", C.c_void_p), ("bin", C.c_void_p), ("vis", C.c_void_p), ("amp", C.c_void_p)]
+    _fields_ = [("tri", C.c_void_p), ("bin", C.c_void_p), ("vis", C.c_void_p), ("amp", C.c_void_p),
+                ("stats", C.c_void_p)]
 
 
 class sonar_scene_info(C.Structure):
@@ -270,7 +271,10 @@ def beams_of(cfg):
     return (cfg.n_v + 1, cfg.n_h + 1) if cfg.grid_mode == 1 else (cfg.n_v, cfg.n_h)
 
 
-def alloc_outputs(cfg, gbuffer=False, incoh=False, record=False, device="cuda"):
+def alloc_outputs(cfg, gbuffer=False, incoh=False, record=False, stats=False, device="cuda"):
+    """Output tensors of a ping. ``record`` adds the per-ray record; ``stats``
+    (with ``record``) adds the traversal counters, which select the counting
+    kernel instantiations."""
     import torch
     bv, bh = beams_of(cfg)
     out = dict(volume=torch.empty((bv, bh, cfg.n_range), dtype=torch.complex64, device=device))
@@ -285,18 +289,21 @@ def alloc_outputs(cfg, gbuffer=False, incoh=False, record=False, device="cuda"):
         out["bin"] = torch.empty((n, K), dtype=torch.int32, device=device)
         out["vis"] = torch.empty((n, K), dtype=torch.int32, device=device)
         out["amp"] = torch.empty((n, K), dtype=torch.complex64, device=device)
+        if stats:
+            out["stats"] = torch.empty((n, 3), dtype=torch.int32, device=device)
     return out
 
 
 def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=False, ray_mask=None, stream=None,
-         params=None, pose_s=None):
+         params=None, pose_s=None, stats=False):
     """One ping; returns the dict of output tensors (allocated if ``out`` is None)."""
     if out is None:
-        out = alloc_outputs(cfg, gbuffer, incoh, record)
+        out = alloc_outputs(cfg, gbuffer, incoh, record, stats)
     rec = None
     if "tri" in out:
         rec = sonar_ray_record(tri=out["tri"].data_ptr(), bin=out["bin"].data_ptr(), vis=out["vis"].data_ptr(),
-                               amp=out["amp"].data_ptr())
+                               amp=out["amp"].data_ptr(),
+                               stats=out["stats"].data_ptr() if "stats" in out else None)
     p = params if params is not None else params_of(cfg)
     q = pose_s if pose_s is not None else pose_of(pose)
     _check(lib().sonar_ping(scene.handle, C.byref(p), C.byref(q), _dptr(out["volume"]), _dptr(out.get("gbuffer")),

@@ -82,3 +82,22 @@ def plane_grid_x(x, y0, y1, z0, z1, n, rng):
     T = tri.shape[0]
     return Mesh(V.astype(np.float32), tri.astype(np.int32), np.full(T, 0.5, np.float32),
                 rng.uniform(0, 2 * math.pi, T).astype(np.float32), np.zeros(T, np.uint8), "grid")
+
+
+def deep_chain(levels=20, per_level=64, size=2.0, length=2.0, wall_x=-1.0):
+    """A hierarchy that forces deep traversal stacks. Clusters of `per_level`
+    identical sliver triangles lie in the planes x = length (1 - 2^-i),
+    i = 0 .. levels - 1; each sliver fills y + z < -size / 2 inside the square
+    [-size, size / 2]^2, so its box contains the x axis while the triangle
+    keeps clear of it by at least size / 2. A wall triangle at x = wall_x ends
+    the rays. The geometric positions split one cluster off per Morton bit, so
+    the hierarchy is a chain of balanced cluster subtrees, and a ray running
+    down the axis toward -x enters every box on the chain with the rest of the
+    chain as the near child: it pushes one far child per level."""
+    tris = []
+    for i in range(levels):
+        x = length * (1.0 - 2.0 ** -i)
+        sl = [[x, -size, size / 2], [x, size / 2, -size], [x, -size, -size]]
+        tris.extend([sl] * per_level)
+    tris.append(big_triangle_x(wall_x, half=40.0))
+    return mesh_from(tris, rho=0.5, phi=0.25)

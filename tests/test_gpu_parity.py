@@ -349,3 +349,51 @@ def test_harbor_multipath_full_size_sampled_beams():
     res, g, orc = run_parity(mesh, cfg, pose, beams=beams)
     assert_parity(res)
     assert res["im_energy"] > 0
+
+
+def test_deep_hierarchy_stack_spills_past_lds():
+    """A chain hierarchy whose traversals need more stack entries than the
+    single-bounce LDS stack holds: the deeper entries live in private memory,
+    and every ray still matches the oracle."""
+    torch, sonar = _gpu()
+    mesh = M.deep_chain()
+    mesh.name = "deep_chain"
+    cfg = S.SensorConfig(n_h=16, n_v=8, rays_per_beam=4, n_range=512, hfov=math.radians(10.0),
+                         vfov=math.radians(10.0))
+    pose = S.pose((3.0, 0.0, 0.0), yaw=math.pi)
+    sc = sonar.Scene(mesh)
+    depth = sc.info()["depth"]
+    assert 21 <= depth <= 32, depth
+    st = sonar.ping(sc, cfg, pose, record=True, stats=True)
+    torch.cuda.synchronize()
+    deepest = int(st["stats"][:, 2].max().item())
+    _log("deep chain: hierarchy depth", depth, "deepest stack", deepest)
+    assert deepest > 20
+    res, g, _ = run_parity(mesh, cfg, pose, gpu_scene=sc)
+    assert_parity(res)
+    assert res["energy"] > 0
+    assert (g["tri"][:, 0] == mesh.indices.shape[0] - 1).all()     # every ray reaches the wall
+
+
+@pytest.mark.parametrize("bounces,g", [(1, 0.0), (3, 0.05)])
+def test_traversal_counters_keep_results(bounces, g):
+    """The counting kernels return the same indices and bins as the plain
+    ones, values equal up to rounding, and plausible counts."""
+    torch, sonar = _gpu()
+    mesh = S.scene_seabed_boxes()
+    cfg = S.sensor_seabed_boxes().replace(max_bounces=bounces, k_d=0.7, k_s=0.3, c_grad=g)
+    pose = S.pose_seabed_boxes()
+    sc = sonar.Scene(mesh)
+    a = sonar.ping(sc, cfg, pose, record=True, stats=True)
+    b = sonar.ping(sc, cfg, pose, record=True)
+    torch.cuda.synchronize()
+    assert sc.status() == 0
+    for k in ("tri", "bin", "vis"):
+        assert torch.equal(a[k], b[k]), k
+    va, vb = a["volume"].cpu().numpy(), b["volume"].cpu().numpy()
+    assert rel_l2(va, vb) <= 1e-9
+    st = a["stats"].cpu().numpy()
+    tri = a["tri"].cpu().numpy()
+    assert (st[:, 0] >= 1).all()                      # the root is an internal node
+    assert (st[tri[:, 0] >= 0, 1] >= 1).all()         # a hit needs a tested triangle
+    assert (st[:, 2] <= sc.info()["depth"]).all()     # pushes never exceed the hierarchy depth
