@@ -45,6 +45,41 @@ def _traffic(n_launch_bytes_alg):
     return d.get("hbm_bytes_per_launch")
 
 
+NODE_BYTES, TRI_BYTES = 64, 48      # one hierarchy node, one triangle record
+
+
+def traversal_work(torch, sonar, np, scene, cfg, pose):
+    """Per-ping traversal work from the counting kernel instantiations (run
+    outside any timed region): internal nodes visited and triangles tested
+    over all rays, and the bytes those visits read (the visit stream)."""
+    st = sonar.ping(scene, cfg, pose, record=True, stats=True)["stats"]
+    torch.cuda.synchronize()
+    s = st.cpu().numpy().astype(np.int64)
+    nodes, tris = int(s[:, 0].sum()), int(s[:, 1].sum())
+    return {"nodes_per_ray": nodes / cfg.n_rays, "tris_per_ray": tris / cfg.n_rays,
+            "deepest_stack": int(s[:, 2].max()),
+            "visit_bytes_per_ping": nodes * NODE_BYTES + tris * TRI_BYTES}
+
+
+def copy_bandwidth(torch, reps=5):
+    """Device-to-device copy rate of 1 GiB (read + write bytes per second):
+    the practical HBM ceiling next to the 8 TB/s specification."""
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2.0 * 4 * n / t / 1e9
+
+
 def cpu_baseline(mesh, cfg, pose, budget_s=12.0):
     """The oracle as it stands, brute force, on a bounded sample of beams."""
     import numpy as np
@@ -91,9 +126,13 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     torch.cuda.synchronize()
     assert scene.status() == 0
     mp_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    trav = traversal_work(torch, sonar, np, scene, cfg, pose)
+    trav["visit_gbs"] = trav["visit_bytes_per_ping"] / (mp_ms * 1e-3) / 1e9
+    trav["note"] = "all traversals of a ray (up to 3 nearest-hit and 2 any-hit connection queries)"
     multipath = {"workload": "harbor multipath ping: 1,991,680 triangles, 256x128 beams x 16 rays, 3 bounces, "
                              "Phong-20 + diffuse, c(z) = 1500 + 0.05 z, 1,024 bins",
-                 "ping_ms": mp_ms, "pings_per_s": 1e3 / mp_ms, "mrays_per_s": cfg.n_rays / mp_ms / 1e3}
+                 "ping_ms": mp_ms, "pings_per_s": 1e3 / mp_ms, "mrays_per_s": cfg.n_rays / mp_ms / 1e3,
+                 "traversal": trav}
     del out
 
     # surrogate ping: single-bounce ping with G-buffer and incoherent channel,
@@ -210,7 +249,13 @@ def main():
     t0 = time.perf_counter()
     scene = sonar.Scene(mesh)
     torch.cuda.synchronize()
+    first_build_ms = (time.perf_counter() - t0) * 1e3
+    # the same build again with the runtime and code objects warm (host mesh arrays in, synchronous)
+    t0 = time.perf_counter()
+    again = sonar.Scene(mesh)
+    torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
+    again.close()
     info = scene.info()
 
     out = sonar.alloc_outputs(cfg)
@@ -257,6 +302,8 @@ def main():
 
     pings_s = 1e3 / step_ms
     mrays_s = cfg.n_rays * pings_s / 1e6
+    trav = traversal_work(torch, sonar, np, scene, cfg, pose)
+    copy_gbs = copy_bandwidth(torch)
     vol_bytes = cfg.n_beams * cfg.n_range * 8
     scene_bytes = info["node_bytes"] + info["tri_bytes"]
     alg_bytes = vol_bytes + scene_bytes
@@ -287,13 +334,23 @@ def main():
         "separate_ping_ms_mean": float(sep_ping_ms.mean()),
         "separate_detect_ms_mean": float(sep_det_ms.mean()),
         "scene_build_ms": build_ms,
+        "scene_build_first_ms": first_build_ms,
         "hierarchy": {"nodes": info["n_nodes"], "depth": info["depth"], "leaf_size": info["leaf_size"]},
         "detections": n_det,
-        "roofline": {"bound": "hbm", "kernel": "k_ping (fused CFAR)", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "roofline": {"bound": "hbm", "kernel": "k_ping (fused CFAR) + k_emit", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_note": "volume write (beams x bins x 8 B) + scene node and triangle arrays; "
-                                       "duration from events around the fused call (ping + point emission)"},
+                                       "duration from events around the fused call (the ping kernel and the "
+                                       "point-emission kernel after it)",
+                     "frac_of_copy_bw": achieved / copy_gbs},
+        "copy_bw_gbs": copy_gbs,
+        "traversal": {**trav,
+                      "traversals_per_s": cfg.n_rays * pings_s,
+                      "visit_gbs": trav["visit_bytes_per_ping"] / t_ping / 1e9,
+                      "visit_frac_of_peak": trav["visit_bytes_per_ping"] / t_ping / 1e9 / HBM_PEAK_GBS,
+                      "note": "one nearest-hit traversal per ray; visit stream = nodes x 64 B + triangles x 48 B, "
+                              "served mostly from L1/L2, over the fused call's duration"},
     }
     if not args.no_extras:
         del out, det

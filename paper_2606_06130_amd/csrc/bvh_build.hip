@@ -1,7 +1,7 @@
 // Linear BVH construction on the GPU: triangle bounds -> 63-bit Morton codes
 // of the centroids -> stable key/value radix sort -> binary radix tree
 // (Karras, "Maximizing parallelism in the construction of BVHs, octrees and
-// k-d trees", HPG 2012) -> bottom-up bounds with per-node arrival counters ->
+// k-d trees", HPG 2012) -> bottom-up bounds one tree level per launch ->
 // 64-byte nodes with child boxes and leaf collapse.
 //
 // The hierarchy is only an accelerator for the nearest-hit and any-hit
@@ -160,28 +160,104 @@ __global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shif
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of `n` uint32 in one block of 1024 threads.
-__global__ void k_scan_single(uint32_t *__restrict__ a, int64_t n)
+// Exclusive scan of n uint32 in place, in three launches over tiles of
+// SCAN_TILE: tile sums, a scan of the tile sums, then each tile's scan with
+// its offset. Loads and stores are coalesced; a tile is scanned in LDS.
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }    // LDS index with one pad word per 32
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const uint32_t *__restrict__ a, int64_t n,
+                                                            uint32_t *__restrict__ sums)
 {
-    __shared__ uint32_t part[1024];
-    int t = threadIdx.x;
-    int64_t per = (n + 1023) / 1024;
-    int64_t b = t * per, e = b + per < n ? b + per : n;
+    __shared__ uint32_t ws[SCAN_THREADS / 64];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += a[i];
-    part[t] = s;
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const int64_t i = base + r * SCAN_THREADS + t;
+        s += i < n ? a[i] : 0u;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((t & 63) == 0) ws[t >> 6] = s;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = t >= off ? part[t - off] : 0u;
+    if (t == 0) {
+        uint32_t tot = 0;
+        for (int q = 0; q < SCAN_THREADS / 64; ++q) tot += ws[q];
+        sums[blockIdx.x] = tot;
+    }
+}
+
+// Exclusive scan of the tile sums by one block, 1024 at a time with a carry.
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ sums, int n)
+{
+    __shared__ uint32_t ws[16];
+    __shared__ uint32_t carry;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) carry = 0u;
+    __syncthreads();
+    for (int b0 = 0; b0 < n; b0 += 1024) {
+        const int i = b0 + t;
+        const uint32_t v = i < n ? sums[i] : 0u;
+        uint32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(x, off);
+            if (lane >= off) x += o;
+        }
+        if (lane == 63) ws[w] = x;
         __syncthreads();
-        part[t] += v;
+        uint32_t add = carry;
+        for (int q = 0; q < w; ++q) add += ws[q];
+        if (i < n) sums[i] = add + x - v;
+        __syncthreads();
+        if (t == 1023) carry = add + x;
         __syncthreads();
     }
-    uint32_t run = t > 0 ? part[t - 1] : 0u;
-    for (int64_t i = b; i < e; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(uint32_t *__restrict__ a, int64_t n,
+                                                            const uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t tile[SCAN_TILE + SCAN_TILE / 32];
+    __shared__ uint32_t ws[SCAN_THREADS / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const int j = r * SCAN_THREADS + t;
+        tile[scan_pad(j)] = base + j < n ? a[base + j] : 0u;
+    }
+    __syncthreads();
+    // thread t scans its SCAN_ITEMS consecutive entries
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        v[q] = tile[scan_pad(t * SCAN_ITEMS + q)];
+        s += v[q];
+    }
+    uint32_t x = s;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(x, off);
+        if (lane >= off) x += o;
+    }
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    uint32_t run = sums[blockIdx.x] + x - s;
+    for (int q = 0; q < w; ++q) run += ws[q];
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        tile[scan_pad(t * SCAN_ITEMS + q)] = run;
+        run += v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const int j = r * SCAN_THREADS + t;
+        if (base + j < n) a[base + j] = tile[scan_pad(j)];
     }
 }
 
@@ -280,42 +356,54 @@ __global__ void k_karras(const uint64_t *__restrict__ k, int64_t n, int32_t *__r
     parent[cr] = (int32_t)i;
 }
 
-// K5: bounds bottom-up. The second child to arrive at a node merges both boxes
-// and the node height; the first one stops. The root's height is the depth.
-__global__ void k_refit(const uint32_t *__restrict__ order, int64_t n, const float4 *__restrict__ blo_tri,
-                        const float4 *__restrict__ bhi_tri, const int32_t *__restrict__ left,
-                        const int32_t *__restrict__ right, const int32_t *__restrict__ parent,
-                        float4 *__restrict__ blo, float4 *__restrict__ bhi, int32_t *__restrict__ arrive,
-                        int32_t *__restrict__ height, int32_t *__restrict__ depth_out)
+// K5: bounds bottom-up, one tree level per launch. Every internal node's
+// depth comes from walking its parent links (no dependence between threads);
+// then the levels are merged from the deepest to the root, each launch
+// reading only children finished by an earlier launch. Heights (edges to the
+// deepest triangle) come along; the root's height is the hierarchy depth.
+__global__ void k_depth(const int32_t *__restrict__ parent, int64_t n_int, int32_t *__restrict__ depth,
+                        int32_t *__restrict__ max_depth, int *__restrict__ status)
 {
-    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    int d = 0;
+    if (i < n_int) {
+        int64_t p = i;
+        while (p != 0 && d < MAX_WALK) {
+            p = parent[p];
+            ++d;
+        }
+        if (d >= MAX_WALK) atomicOr(status, ST_BAD_TREE);
+        depth[i] = d;
+    }
+    for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(max_depth, d);
+}
+
+__global__ void k_leaf_boxes(const uint32_t *__restrict__ order, int64_t n, const float4 *__restrict__ blo_tri,
+                             const float4 *__restrict__ bhi_tri, float4 *__restrict__ blo, float4 *__restrict__ bhi,
+                             int32_t *__restrict__ height)
+{
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= n) return;
-    int64_t leaf = n - 1 + i;
-    uint32_t tri = order[i];
+    const int64_t leaf = n - 1 + i;
+    const uint32_t tri = order[i];
     blo[leaf] = blo_tri[tri];
     bhi[leaf] = bhi_tri[tri];
     height[leaf] = 0;
-    if (n == 1) return;
-    __threadfence();
-    int64_t p = parent[leaf];
-    for (int steps = 0; steps < MAX_WALK; ++steps) {
-        int old = atomicAdd(&arrive[p], 1);
-        if (old == 0) return;
-        __threadfence();
-        int32_t a = left[p], b = right[p];
-        // the fence above orders these loads after the sibling's published box
-        float4 la = blo[a], ha = bhi[a];
-        float4 lb = blo[b], hb = bhi[b];
-        blo[p] = make_float4(fminf(la.x, lb.x), fminf(la.y, lb.y), fminf(la.z, lb.z), 0.f);
-        bhi[p] = make_float4(fmaxf(ha.x, hb.x), fmaxf(ha.y, hb.y), fmaxf(ha.z, hb.z), 0.f);
-        height[p] = max(height[a], height[b]) + 1;
-        __threadfence();
-        if (p == 0) {
-            *depth_out = height[0];    // longest root-to-leaf path
-            return;
-        }
-        p = parent[p];
-    }
+}
+
+__global__ void k_refit_level(int level, int64_t n_int, const int32_t *__restrict__ depth,
+                              const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                              float4 *__restrict__ blo, float4 *__restrict__ bhi, int32_t *__restrict__ height)
+{
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n_int || depth[i] != level) return;
+    const int32_t a = left[i], b = right[i];
+    const float4 la = blo[a], ha = bhi[a];
+    const float4 lb = blo[b], hb = bhi[b];
+    blo[i] = make_float4(fminf(la.x, lb.x), fminf(la.y, lb.y), fminf(la.z, lb.z), 0.f);
+    bhi[i] = make_float4(fmaxf(ha.x, hb.x), fmaxf(ha.y, hb.y), fmaxf(ha.z, hb.z), 0.f);
+    height[i] = max(height[a], height[b]) + 1;
 }
 
 // Checks every child link of the packed hierarchy: internal links inside the
@@ -446,7 +534,7 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     }
     const int64_t n_int = n > 1 ? n - 1 : 1;
     const int64_t n_all = 2 * n - 1;
-    DevBuf rec, cen, tlo, thi, red, k0, k1, v0, v1, hist, lft, rgt, rlo, rhi, par, blo, bhi, arr, dep, hgt;
+    DevBuf rec, cen, tlo, thi, red, k0, k1, v0, v1, hist, tsum, lft, rgt, rlo, rhi, par, blo, bhi, ndp, dep, hgt;
     int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
     BCHECK(hipMalloc(&rec.p, sizeof(float4) * 3 * n));
     BCHECK(hipMalloc(&cen.p, sizeof(float4) * n));
@@ -458,6 +546,9 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     BCHECK(hipMalloc(&v0.p, sizeof(uint32_t) * n));
     BCHECK(hipMalloc(&v1.p, sizeof(uint32_t) * n));
     BCHECK(hipMalloc(&hist.p, sizeof(uint32_t) * 256 * nblocks));
+    const int64_t n_hist = (int64_t)256 * nblocks;
+    const int n_scan = (int)((n_hist + SCAN_TILE - 1) / SCAN_TILE);
+    BCHECK(hipMalloc(&tsum.p, sizeof(uint32_t) * n_scan));
     BCHECK(hipMalloc(&lft.p, sizeof(int32_t) * n_int));
     BCHECK(hipMalloc(&rgt.p, sizeof(int32_t) * n_int));
     BCHECK(hipMalloc(&rlo.p, sizeof(int32_t) * n_int));
@@ -465,7 +556,7 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     BCHECK(hipMalloc(&par.p, sizeof(int32_t) * n_all));
     BCHECK(hipMalloc(&blo.p, sizeof(float4) * n_all));
     BCHECK(hipMalloc(&bhi.p, sizeof(float4) * n_all));
-    BCHECK(hipMalloc(&arr.p, sizeof(int32_t) * n_int));
+    BCHECK(hipMalloc(&ndp.p, sizeof(int32_t) * n_int));
     BCHECK(hipMalloc(&dep.p, sizeof(int32_t)));
     BCHECK(hipMalloc(&hgt.p, sizeof(int32_t) * n_all));
 
@@ -486,7 +577,6 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     int *st_build = (int *)(redp + 12);
     BCHECK(hipMemsetAsync(status, 0, sizeof(int), s));
     BCHECK(hipMemsetAsync(st_build, 0, sizeof(int), s));
-    BCHECK(hipMemsetAsync(arr.p, 0, sizeof(int32_t) * n_int, s));
     BCHECK(hipMemsetAsync(dep.p, 0, sizeof(int32_t), s));
     BCHECK(hipMemsetAsync(par.p, 0, sizeof(int32_t) * n_all, s));
     k_init_red<<<1, 64, 0, s>>>(redp);
@@ -497,7 +587,9 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     uint32_t *va = (uint32_t *)v0.p, *vb = (uint32_t *)v1.p;
     for (int shift = 0; shift < 64; shift += 8) {
         k_rs_hist<<<nblocks, RS_THREADS, 0, s>>>(ka, n, shift, (uint32_t *)hist.p, nblocks);
-        k_scan_single<<<1, 1024, 0, s>>>((uint32_t *)hist.p, (int64_t)256 * nblocks);
+        k_scan_tiles<<<n_scan, SCAN_THREADS, 0, s>>>((const uint32_t *)hist.p, n_hist, (uint32_t *)tsum.p);
+        k_scan_sums<<<1, 1024, 0, s>>>((uint32_t *)tsum.p, n_scan);
+        k_scan_apply<<<n_scan, SCAN_THREADS, 0, s>>>((uint32_t *)hist.p, n_hist, (const uint32_t *)tsum.p);
         k_rs_scatter<<<nblocks, RS_THREADS, 0, s>>>(ka, va, n, shift, (const uint32_t *)hist.p, nblocks, kb, vb);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
@@ -506,9 +598,24 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
         k_karras<<<nblk(n - 1), BT, 0, s>>>(ka, n, (int32_t *)lft.p, (int32_t *)rgt.p, (int32_t *)rlo.p,
                                             (int32_t *)rhi.p, (int32_t *)par.p);
     }
-    k_refit<<<nblk(n), BT, 0, s>>>(va, n, (const float4 *)tlo.p, (const float4 *)thi.p, (const int32_t *)lft.p,
-                                   (const int32_t *)rgt.p, (const int32_t *)par.p, (float4 *)blo.p,
-                                   (float4 *)bhi.p, (int32_t *)arr.p, (int32_t *)hgt.p, (int32_t *)dep.p);
+    k_leaf_boxes<<<nblk(n), BT, 0, s>>>(va, n, (const float4 *)tlo.p, (const float4 *)thi.p, (float4 *)blo.p,
+                                        (float4 *)bhi.p, (int32_t *)hgt.p);
+    if (n > 1) {
+        // levels of the tree: one short synchronisation for the deepest level
+        k_depth<<<nblk(n_int), BT, 0, s>>>((const int32_t *)par.p, n_int, (int32_t *)ndp.p, (int32_t *)dep.p,
+                                           st_build);
+        int max_level = 0;
+        BCHECK(hipMemcpyAsync(&max_level, dep.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        BCHECK(hipStreamSynchronize(s));
+        if (max_level >= MAX_WALK) {
+            snprintf(err, errlen, "internal error: malformed hierarchy");
+            return SONAR_E_DEVICE;
+        }
+        for (int level = max_level; level >= 0; --level)
+            k_refit_level<<<nblk(n_int), BT, 0, s>>>(level, n_int, (const int32_t *)ndp.p, (const int32_t *)lft.p,
+                                                     (const int32_t *)rgt.p, (float4 *)blo.p, (float4 *)bhi.p,
+                                                     (int32_t *)hgt.p);
+    }
     if (n > 1) {
         k_pack<<<nblk(n - 1), BT, 0, s>>>(n, (const int32_t *)lft.p, (const int32_t *)rgt.p,
                                           (const int32_t *)rlo.p, (const int32_t *)rhi.p, (const float4 *)blo.p,
@@ -523,7 +630,7 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     int hst = 0, hdep = 0;
     BCHECK(hipMemcpyAsync(hred, redp, sizeof(hred), hipMemcpyDeviceToHost, s));
     BCHECK(hipMemcpyAsync(&hst, st_build, sizeof(int), hipMemcpyDeviceToHost, s));
-    BCHECK(hipMemcpyAsync(&hdep, dep.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    BCHECK(hipMemcpyAsync(&hdep, hgt.p, sizeof(int), hipMemcpyDeviceToHost, s));      // the root's height
     BCHECK(hipStreamSynchronize(s));
     if (hst & ST_BAD_INDEX) {
         snprintf(err, errlen, "triangle index outside [0, n_vertices)");

@@ -177,21 +177,9 @@ def test_harbor_full_size_sampled_beams():
     assert_parity(res)
 
 
-def test_harbor_cfar_points_match_oracle():
-    """Detection on the same FP32 volume: identical point sets except
-    decisions within 1e-4 of their threshold."""
-    torch, sonar = _gpu()
-    mesh = S.scene_harbor()
-    cfg, pose = S.sensor_harbor(), S.pose_harbor()
-    sc = sonar.Scene(mesh)
-    vol = sonar.ping(sc, cfg, pose)["volume"]
-    det = sonar.Detector(cfg)
-    det(vol, pose)
-    pts, total = det.fetch()
-    v = vol.cpu().numpy().reshape(cfg.n_beams, cfg.n_range)
-    rng = np.random.Generator(np.random.PCG64(9))
-    beams = np.sort(rng.choice(cfg.n_beams, 2048, replace=False))
-    o = oracle.detect(v, cfg, pose, beams)
+def _compare_points(pts, total, o, beams):
+    """GPU points vs the oracle's, beam by beam, skipping beams with a
+    threshold- or peak-flagged decision. Returns the number of beams compared."""
     assert total == len(pts)
     by_beam = {}
     for p in pts:
@@ -210,11 +198,64 @@ def test_harbor_cfar_points_match_oracle():
             np.testing.assert_allclose([p["x"], p["y"], p["z"]], want[:3], atol=2e-5)
             assert abs(p["db"] - want[3]) < 1e-3
         compared += 1
-    assert compared > 1900
-    assert total > 0
     # points come out in (beam, range) order
     keys = pts["beam"].astype(np.int64) * 100000 + pts["bin"]
     assert np.all(np.diff(keys) > 0)
+    return compared
+
+
+@pytest.mark.parametrize("n_range,train,guard,M", [
+    (1, 16, 4, 4), (2, 1, 0, 1), (3, 2, 0, 2), (77, 8, 2, 4), (256, 16, 4, 16), (1000, 16, 4, 4),
+    (4096, 64, 8, 16)])
+def test_detect_synthetic_volumes_match_oracle(n_range, train, guard, M):
+    """CFAR on seeded sparse volumes (log-normal returns with random phase,
+    two-bin plateaus, Rayleigh-noise beams) over every per-lane chunk size and
+    both load paths (odd and even bin counts), all beams against the oracle."""
+    torch, sonar = _gpu()
+    cfg = S.SensorConfig(n_h=8, n_v=8, rays_per_beam=1, jitter=0, n_range=n_range)
+    pose = S.pose((1.0, -2.0, -3.0), yaw=0.3, pitch_down=0.4)
+    rng = np.random.Generator(np.random.PCG64(100 + n_range))
+    nb = cfg.n_beams
+    v = np.zeros((nb, n_range), np.complex64)
+    for b in range(nb):
+        if b % 8 == 7:
+            v[b] = (rng.normal(size=n_range) + 1j * rng.normal(size=n_range)) * np.sqrt(5e-11)
+            continue
+        k = int(rng.integers(0, n_range // 8 + 2))
+        bins = rng.choice(n_range, min(k, n_range), replace=False)
+        v[b, bins] = np.exp(rng.normal(-9.0, 3.0, len(bins))) * np.exp(2j * np.pi * rng.random(len(bins)))
+        if n_range >= 4 and b % 8 == 3:
+            r = int(rng.integers(1, n_range - 2))
+            v[b, r] = v[b, r + 1] = 1e-3
+    det = sonar.Detector(cfg, train=train, guard=guard, max_per_beam=M)
+    det(torch.from_numpy(v).cuda(), pose)
+    pts, total = det.fetch()
+    o = oracle.detect(v, cfg, pose, np.arange(nb), train=train, guard=guard, max_per_beam=M)
+    compared = _compare_points(pts, total, o, np.arange(nb))
+    _log("synthetic CFAR", n_range, "points", total, "beams compared", compared)
+    assert compared >= 0.75 * nb
+    if n_range >= 77:
+        assert total > 0
+
+
+def test_harbor_cfar_points_match_oracle():
+    """Detection on the same FP32 volume: identical point sets except
+    decisions within 1e-4 of their threshold."""
+    torch, sonar = _gpu()
+    mesh = S.scene_harbor()
+    cfg, pose = S.sensor_harbor(), S.pose_harbor()
+    sc = sonar.Scene(mesh)
+    vol = sonar.ping(sc, cfg, pose)["volume"]
+    det = sonar.Detector(cfg)
+    det(vol, pose)
+    pts, total = det.fetch()
+    v = vol.cpu().numpy().reshape(cfg.n_beams, cfg.n_range)
+    rng = np.random.Generator(np.random.PCG64(9))
+    beams = np.sort(rng.choice(cfg.n_beams, 2048, replace=False))
+    o = oracle.detect(v, cfg, pose, beams)
+    compared = _compare_points(pts, total, o, beams)
+    assert compared > 1900
+    assert total > 0
 
 
 def test_detect_capacity_truncates():
