@@ -4,7 +4,11 @@ Workload: 601,088-triangle harbor scene (corrugated wall over an fBm seabed),
 256 x 128 beams x 16 jittered rays (524,288 rays), 1,024 range bins, single
 bounce, then CFAR detection into a point cloud. One step = one ping (ray
 generation, traversal, echo model, accumulation, column write) + detection,
-inputs resident in HBM. The scene build is per static scene and timed apart.
+inputs resident in HBM. The job is a sequence of pings along a short sweep of
+poses; independent pings go round-robin to --streams streams (4 by default),
+each with its own outputs, so one ping's tail overlaps the next one's start.
+The latency of a ping on its own is measured separately on one stream. The
+scene build is per static scene and timed apart.
 
 Prints one JSON line (rank 0). ``--gpus`` above 1 is refused: the library runs
 on one GPU.
@@ -14,6 +18,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -45,7 +50,7 @@ def _traffic(n_launch_bytes_alg):
     return d.get("hbm_bytes_per_launch")
 
 
-NODE_BYTES, TRI_BYTES = 64, 48      # one hierarchy node, one triangle record
+NODE_BYTES, TRI_BYTES = 128, 48     # one 4-wide hierarchy node, one triangle record
 
 
 def traversal_work(torch, sonar, np, scene, cfg, pose):
@@ -209,10 +214,13 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the multipath ping and the batch")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="streams the job's pings are issued on round-robin (independent pings overlap)")
+    ap.add_argument("--latency-steps", type=int, default=50, help="single-stream pings timed one by one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for counter calibration) and exit")
     args = ap.parse_args()
@@ -258,33 +266,48 @@ def main():
     again.close()
     info = scene.info()
 
-    out = sonar.alloc_outputs(cfg)
-    det = sonar.Detector(cfg)
     params = sonar.params_of(cfg)
     pose_s = sonar.pose_of(pose)
+    # the job: one ping per step along a short sweep in front of the wall
+    # (lateral and depth offsets of a few decimetres, yaw within 3 degrees),
+    # pings issued round-robin on `streams` streams, each with its own outputs
+    sweep = [sonar.pose_of(S.pose((0.0, 0.25 * math.sin(0.37 * i), -3.0 + 0.1 * math.cos(0.23 * i)),
+                                  yaw=math.radians(3.0 * math.sin(0.11 * i)), pitch_down=math.radians(35.0)))
+             for i in range(64)]
+    ns = args.streams
+    streams = [torch.cuda.Stream() for _ in range(ns)] if ns > 1 else [stream]
+    outs = [sonar.alloc_outputs(cfg) for _ in range(ns)]
+    dets = [sonar.Detector(cfg) for _ in range(ns)]
 
-    def step():
-        det.ping_detect(scene, out["volume"], pose, pose_s=pose_s)
+    def job(n, first=0):
+        for i in range(first, first + n):
+            k = i % ns
+            dets[k].ping_detect(scene, outs[k]["volume"], None, stream=streams[k], pose_s=sweep[i % len(sweep)])
 
-    for _ in range(args.warmup):
-        step()
+    job(args.warmup)
     torch.cuda.synchronize()
     assert scene.status() == 0
-
-    # events bracket each step on the stream both kernels run on (the fused
-    # ping kernel and the small point-emission kernel that follows it)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    job(args.steps, args.warmup)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    assert scene.status() == 0
+    step_ms = wall * 1e3 / args.steps
+
+    # latency of one ping on its own: events bracket each fused call on one
+    # stream (the ping kernel with the CFAR test and the point-emission kernel)
+    out, det = outs[0], dets[0]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.latency_steps)]
+    t1 = time.perf_counter()
     for e in ev:
         e[0].record(stream)
         det.ping_detect(scene, out["volume"], pose, pose_s=pose_s)
         e[1].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
+    single_wall_ms = (time.perf_counter() - t1) * 1e3 / args.latency_steps
     assert scene.status() == 0
     ping_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    step_ms = wall * 1e3 / args.steps
 
     # the separate two-stage path, for reference (ping kernel alone, then CFAR)
     ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
@@ -325,10 +348,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "harbor sheet-pile ping: 601,088 triangles, 256x128 beams x 16 rays, "
-                               "1,024 bins to 15 m, single bounce, CA-CFAR point cloud",
+                               "1,024 bins to 15 m, single bounce, CA-CFAR point cloud; one ping per step along "
+                               "a 64-pose sweep, independent pings issued round-robin on the streams",
                    "triangles": mesh.n_triangles, "beams": cfg.n_beams, "rays_per_beam": cfg.rays_per_beam,
-                   "rays": cfg.n_rays, "bins": cfg.n_range, "bounces": cfg.max_bounces},
+                   "rays": cfg.n_rays, "bins": cfg.n_range, "bounces": cfg.max_bounces, "streams": ns},
         "mrays_per_s": mrays_s,
+        "streams": ns,
+        "single_stream_pings_per_s": 1e3 / single_wall_ms,
         "ping_detect_ms_mean": float(ping_ms.mean()),
         "ping_detect_ms_median": float(np.median(ping_ms)),
         "separate_ping_ms_mean": float(sep_ping_ms.mean()),
@@ -349,7 +375,7 @@ def main():
                       "traversals_per_s": cfg.n_rays * pings_s,
                       "visit_gbs": trav["visit_bytes_per_ping"] / t_ping / 1e9,
                       "visit_frac_of_peak": trav["visit_bytes_per_ping"] / t_ping / 1e9 / HBM_PEAK_GBS,
-                      "note": "one nearest-hit traversal per ray; visit stream = nodes x 64 B + triangles x 48 B, "
+                      "note": "one nearest-hit traversal per ray; visit stream = nodes x 128 B + triangles x 48 B, "
                               "served mostly from L1/L2, over the fused call's duration"},
     }
     if not args.no_extras:

@@ -70,7 +70,7 @@ typedef struct sonar_scene sonar_scene;
  *                surface (rho 1, no diffuse part, unit specular part,
  *                phase 0, reflection sign -1)
  *   on_device    0: host pointers, 1: device pointers
- *   leaf_size    most triangles per hierarchy leaf, 1..8 (0 = 4) */
+ *   leaf_size    most triangles per hierarchy leaf, 1..8 (0 = 3) */
 typedef struct {
     const float *vertices;
     const int32_t *indices;
@@ -150,8 +150,8 @@ typedef struct {
 
 typedef struct {
     int64_t n_triangles;
-    int64_t n_nodes;        /* internal nodes of the binary hierarchy */
-    int32_t depth;          /* longest root-to-leaf path */
+    int64_t n_nodes;        /* 4-wide hierarchy nodes (128 bytes each) */
+    int32_t depth;          /* levels of 4-wide nodes (a traversal stack needs at most 3 per level) */
     int32_t leaf_size;
     float lo[3], hi[3];     /* scene bounding box */
     int64_t node_bytes;     /* bytes of the node array */
@@ -159,7 +159,8 @@ typedef struct {
 } sonar_scene_info;
 
 /* Builds the ray-traversal hierarchy of a mesh (linear BVH: Morton codes of
- * triangle centroids, radix sort, binary radix tree, bottom-up bounds).
+ * triangle centroids, radix sort, binary radix tree, bottom-up bounds, then
+ * 4-wide nodes from every second binary level).
  * Synchronous on `stream`. Returns SONAR_E_INVALID for null pointers,
  * n_triangles < 1, indices out of range or non-finite vertices (checked on
  * the device, reported after the build's synchronisation). */

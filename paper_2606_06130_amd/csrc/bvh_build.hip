@@ -2,7 +2,8 @@
 // of the centroids -> stable key/value radix sort -> binary radix tree
 // (Karras, "Maximizing parallelism in the construction of BVHs, octrees and
 // k-d trees", HPG 2012) -> bottom-up bounds one tree level per launch ->
-// 64-byte nodes with child boxes and leaf collapse.
+// 4-wide nodes (128 bytes: the four children's box planes and links) taken
+// from every second level of the binary tree, with leaf collapse.
 //
 // The hierarchy is only an accelerator for the nearest-hit and any-hit
 // queries of Sec. II-A (rays cast in parallel through a triangle scene): any
@@ -406,66 +407,124 @@ __global__ void k_refit_level(int level, int64_t n_int, const int32_t *__restric
     height[i] = max(height[a], height[b]) + 1;
 }
 
-// Checks every child link of the packed hierarchy: internal links inside the
-// node array, leaves inside the triangle array. Guards the traversal kernels
-// against any malformed hierarchy.
-__global__ void k_check_links(const float4 *__restrict__ nodes, int64_t n_nodes, int64_t n_tri,
-                              int *__restrict__ status)
+// K6: 4-wide nodes. They are the binary nodes of even depth that hold more
+// than leaf_size triangles; each takes as children its binary grandchildren,
+// or a binary child itself when that child is a leaf (at most leaf_size
+// consecutive triangle records). Node layout, 8 float4: lo x, hi x, lo y,
+// hi y, lo z, hi z of children 0..3, then the four child links; an empty
+// child slot has an inverted box and the empty link.
+__device__ __forceinline__ int32_t tri_count(int32_t c, int64_t n, const int32_t *rlo, const int32_t *rhi)
 {
-    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    return c >= n - 1 ? 1 : rhi[c] - rlo[c] + 1;
+}
+
+__global__ void k_mark4(int64_t n, const int32_t *__restrict__ depth, const int32_t *__restrict__ rlo,
+                        const int32_t *__restrict__ rhi, int leaf_size, uint32_t *__restrict__ flag,
+                        uint32_t *__restrict__ id4, int32_t *__restrict__ max_level)
+{
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    int lv = -1;
+    if (i < n - 1) {
+        const bool f = (depth[i] & 1) == 0 && rhi[i] - rlo[i] + 1 > leaf_size;
+        flag[i] = f ? 1u : 0u;
+        id4[i] = flag[i];
+        if (f) lv = depth[i] >> 1;
+    }
+    for (int off = 32; off > 0; off >>= 1) lv = max(lv, __shfl_xor(lv, off));
+    if ((threadIdx.x & 63) == 0 && lv >= 0) atomicMax(max_level, lv);
+}
+
+__global__ void k_pack4(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                        const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi,
+                        const float4 *__restrict__ blo, const float4 *__restrict__ bhi,
+                        const uint32_t *__restrict__ flag, const uint32_t *__restrict__ id4, int leaf_size,
+                        float4 *__restrict__ nodes)
+{
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n - 1 || !flag[i]) return;
+    int32_t ch[4];
+    int nc = 0;
+    const int32_t kids[2] = {left[i], right[i]};
+    for (int q = 0; q < 2; ++q) {
+        const int32_t c = kids[q];
+        if (tri_count(c, n, rlo, rhi) <= leaf_size) {
+            ch[nc++] = c;
+        } else {
+            ch[nc++] = left[c];
+            ch[nc++] = right[c];
+        }
+    }
+    float lo[3][4], hi[3][4];
+    uint32_t link[4];
+    for (int q = 0; q < 4; ++q) {
+        if (q < nc) {
+            const int32_t c = ch[q];
+            const float4 l = blo[c], h = bhi[c];
+            lo[0][q] = l.x; lo[1][q] = l.y; lo[2][q] = l.z;
+            hi[0][q] = h.x; hi[1][q] = h.y; hi[2][q] = h.z;
+            const int32_t cnt = tri_count(c, n, rlo, rhi);
+            if (cnt <= leaf_size) {
+                const uint32_t first = (uint32_t)(c >= n - 1 ? c - (n - 1) : rlo[c]);
+                link[q] = LEAF_BIT | (first << 3) | (uint32_t)(cnt - 1);
+            } else {
+                link[q] = id4[c];
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) {
+                lo[a][q] = INFINITY;
+                hi[a][q] = -INFINITY;
+            }
+            link[q] = EMPTY_LINK;
+        }
+    }
+    float4 *o = nodes + 8 * (size_t)id4[i];
+    for (int a = 0; a < 3; ++a) {
+        o[2 * a] = make_float4(lo[a][0], lo[a][1], lo[a][2], lo[a][3]);
+        o[2 * a + 1] = make_float4(hi[a][0], hi[a][1], hi[a][2], hi[a][3]);
+    }
+    o[6] = make_float4(__uint_as_float(link[0]), __uint_as_float(link[1]), __uint_as_float(link[2]),
+                       __uint_as_float(link[3]));
+    o[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// A scene of at most leaf_size triangles: one node whose only child is a
+// leaf over all of them.
+__global__ void k_pack4_single(int64_t n, const float4 *__restrict__ tlo, const float4 *__restrict__ thi,
+                               float4 *__restrict__ nodes)
+{
+    float l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t t = 0; t < n; ++t) {
+        const float4 a = tlo[t], b = thi[t];
+        l[0] = fminf(l[0], a.x); l[1] = fminf(l[1], a.y); l[2] = fminf(l[2], a.z);
+        h[0] = fmaxf(h[0], b.x); h[1] = fmaxf(h[1], b.y); h[2] = fmaxf(h[2], b.z);
+    }
+    for (int a = 0; a < 3; ++a) {
+        nodes[2 * a] = make_float4(l[a], INFINITY, INFINITY, INFINITY);
+        nodes[2 * a + 1] = make_float4(h[a], -INFINITY, -INFINITY, -INFINITY);
+    }
+    nodes[6] = make_float4(__uint_as_float(LEAF_BIT | (uint32_t)(n - 1)), __uint_as_float(EMPTY_LINK),
+                           __uint_as_float(EMPTY_LINK), __uint_as_float(EMPTY_LINK));
+    nodes[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Checks every child link of the packed hierarchy: internal links inside the
+// node array and not to the node itself, leaves inside the triangle array.
+// Guards the traversal kernels against any malformed hierarchy.
+__global__ void k_check_links4(const float4 *__restrict__ nodes, int64_t n_nodes, int64_t n_tri,
+                               int *__restrict__ status)
+{
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= n_nodes) return;
-    float4 d = nodes[4 * i + 3];
-    uint32_t l[2] = {__float_as_uint(d.x), __float_as_uint(d.y)};
-    for (int c = 0; c < 2; ++c) {
-        uint32_t x = l[c];
+    const float4 d = nodes[8 * i + 6];
+    const uint32_t l[4] = {__float_as_uint(d.x), __float_as_uint(d.y), __float_as_uint(d.z), __float_as_uint(d.w)};
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t x = l[c];
         bool ok;
-        if (x == EMPTY_LINK) ok = (n_tri == 1 && c == 1);
+        if (x == EMPTY_LINK) ok = c > 0;
         else if (x & LEAF_BIT) ok = (int64_t)((x & 0x7FFFFFFFu) >> 3) + (int64_t)(x & 7u) + 1 <= n_tri;
         else ok = (int64_t)x < n_nodes && (int64_t)x != i;
         if (!ok) atomicOr(status, ST_BAD_TREE);
     }
-}
-
-// K6: pack 64-byte nodes; a child whose range holds at most `leaf_size`
-// triangles becomes a leaf over its consecutive triangle records.
-__device__ __forceinline__ uint32_t child_link(int32_t c, int64_t n, const int32_t *rlo, const int32_t *rhi,
-                                               int leaf_size)
-{
-    if (c >= n - 1) {
-        uint32_t first = (uint32_t)(c - (n - 1));
-        return LEAF_BIT | (first << 3);
-    }
-    int32_t cnt = rhi[c] - rlo[c] + 1;
-    if (cnt <= leaf_size) return LEAF_BIT | ((uint32_t)rlo[c] << 3) | (uint32_t)(cnt - 1);
-    return (uint32_t)c;
-}
-
-__global__ void k_pack(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
-                       const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi,
-                       const float4 *__restrict__ blo, const float4 *__restrict__ bhi, int leaf_size,
-                       float4 *__restrict__ nodes)
-{
-    int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    if (i >= n - 1) return;
-    int32_t a = left[i], b = right[i];
-    float4 la = blo[a], ha = bhi[a], lb = blo[b], hb = bhi[b];
-    nodes[4 * i + 0] = make_float4(la.x, la.y, la.z, ha.x);
-    nodes[4 * i + 1] = make_float4(ha.y, ha.z, lb.x, lb.y);
-    nodes[4 * i + 2] = make_float4(lb.z, hb.x, hb.y, hb.z);
-    uint32_t l0 = child_link(a, n, rlo, rhi, leaf_size), l1 = child_link(b, n, rlo, rhi, leaf_size);
-    nodes[4 * i + 3] = make_float4(__uint_as_float(l0), __uint_as_float(l1), 0.f, 0.f);
-}
-
-// Single-triangle scene: one root whose first child is the leaf and whose
-// second child is empty (inverted box).
-__global__ void k_pack_single(const float4 *__restrict__ blo, const float4 *__restrict__ bhi,
-                              float4 *__restrict__ nodes)
-{
-    float4 l = blo[0], h = bhi[0];
-    nodes[0] = make_float4(l.x, l.y, l.z, h.x);
-    nodes[1] = make_float4(h.y, h.z, INFINITY, INFINITY);
-    nodes[2] = make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
-    nodes[3] = make_float4(__uint_as_float(LEAF_BIT), __uint_as_float(EMPTY_LINK), 0.f, 0.f);
 }
 
 __global__ void k_gather_tris(const uint32_t *__restrict__ order, int64_t n, const float4 *__restrict__ in,
@@ -487,6 +546,7 @@ __global__ void k_init_red(uint32_t *red)
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + BT - 1) / BT); }
+inline int64_t leaf_size_of(const sonar_mesh &m) { return m.leaf_size; }
 
 struct DevBuf {
     void *p = nullptr;
@@ -560,17 +620,25 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     BCHECK(hipMalloc(&dep.p, sizeof(int32_t)));
     BCHECK(hipMalloc(&hgt.p, sizeof(int32_t) * n_all));
 
-    float4 *nodes = nullptr, *tris = nullptr;
+    DevBuf flg, id4;
+    BCHECK(hipMalloc(&flg.p, sizeof(uint32_t) * n_int));
+    BCHECK(hipMalloc(&id4.p, sizeof(uint32_t) * n_int));
+    const int n_scan4 = (int)((n_int + SCAN_TILE - 1) / SCAN_TILE);
+    DevBuf tsum4;
+    BCHECK(hipMalloc(&tsum4.p, sizeof(uint32_t) * n_scan4));
+
+    // scene-owned arrays (freed with the scene, also when the build fails)
+    float4 *tris = nullptr;
     int *status = nullptr;
-    BCHECK(hipMalloc(&nodes, sizeof(float4) * 4 * n_int));
-    if (hipMalloc(&tris, sizeof(float4) * 3 * n) != hipSuccess || hipMalloc(&status, sizeof(int)) != hipSuccess) {
-        (void)hipFree(nodes);
-        if (tris) (void)hipFree(tris);
+    if (hipMalloc(&tris, sizeof(float4) * 3 * n) != hipSuccess) {
         snprintf(err, errlen, "out of device memory for the scene");
         return SONAR_E_NOMEM;
     }
-    out->nodes = nodes;
     out->tris = tris;
+    if (hipMalloc(&status, sizeof(int)) != hipSuccess) {
+        snprintf(err, errlen, "out of device memory for the scene");
+        return SONAR_E_NOMEM;
+    }
     out->status = status;
 
     uint32_t *redp = (uint32_t *)red.p;
@@ -616,21 +684,50 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
                                                      (const int32_t *)rgt.p, (float4 *)blo.p, (float4 *)bhi.p,
                                                      (int32_t *)hgt.p);
     }
-    if (n > 1) {
-        k_pack<<<nblk(n - 1), BT, 0, s>>>(n, (const int32_t *)lft.p, (const int32_t *)rgt.p,
-                                          (const int32_t *)rlo.p, (const int32_t *)rhi.p, (const float4 *)blo.p,
-                                          (const float4 *)bhi.p, m.leaf_size, nodes);
+    // 4-wide nodes: mark, number (exclusive scan), count (a short synchronisation), pack
+    int n4 = 0, levels4 = 1;
+    if (n > leaf_size_of(m)) {
+        BCHECK(hipMemsetAsync(dep.p, 0xFF, sizeof(int32_t), s));           // max level: -1
+        k_mark4<<<nblk(n_int), BT, 0, s>>>(n, (const int32_t *)ndp.p, (const int32_t *)rlo.p,
+                                           (const int32_t *)rhi.p, m.leaf_size, (uint32_t *)flg.p,
+                                           (uint32_t *)id4.p, (int32_t *)dep.p);
+        k_scan_tiles<<<n_scan4, SCAN_THREADS, 0, s>>>((const uint32_t *)id4.p, n_int, (uint32_t *)tsum4.p);
+        k_scan_sums<<<1, 1024, 0, s>>>((uint32_t *)tsum4.p, n_scan4);
+        k_scan_apply<<<n_scan4, SCAN_THREADS, 0, s>>>((uint32_t *)id4.p, n_int, (const uint32_t *)tsum4.p);
+        uint32_t last_id = 0, last_flag = 0;
+        int max_lv = -1;
+        BCHECK(hipMemcpyAsync(&last_id, (uint32_t *)id4.p + (n_int - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        BCHECK(hipMemcpyAsync(&last_flag, (uint32_t *)flg.p + (n_int - 1), sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              s));
+        BCHECK(hipMemcpyAsync(&max_lv, dep.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BCHECK(hipStreamSynchronize(s));
+        n4 = (int)(last_id + last_flag);
+        levels4 = max_lv + 1;
+    }
+    const bool single = n4 == 0;
+    if (single) n4 = 1;
+    float4 *nodes = nullptr;
+    if (hipMalloc(&nodes, sizeof(float4) * 8 * (size_t)n4) != hipSuccess) {
+        snprintf(err, errlen, "out of device memory for the scene");
+        return SONAR_E_NOMEM;
+    }
+    out->nodes = nodes;
+    if (single) {
+        k_pack4_single<<<1, 1, 0, s>>>(n, (const float4 *)tlo.p, (const float4 *)thi.p, nodes);
     } else {
-        k_pack_single<<<1, 1, 0, s>>>((const float4 *)blo.p, (const float4 *)bhi.p, nodes);
+        k_pack4<<<nblk(n - 1), BT, 0, s>>>(n, (const int32_t *)lft.p, (const int32_t *)rgt.p,
+                                           (const int32_t *)rlo.p, (const int32_t *)rhi.p, (const float4 *)blo.p,
+                                           (const float4 *)bhi.p, (const uint32_t *)flg.p, (const uint32_t *)id4.p,
+                                           m.leaf_size, nodes);
     }
     k_gather_tris<<<nblk(n), BT, 0, s>>>(va, n, (const float4 *)rec.p, tris);
-    k_check_links<<<nblk(n_int), BT, 0, s>>>(nodes, n_int, n, st_build);
+    k_check_links4<<<nblk(n4), BT, 0, s>>>(nodes, n4, n, st_build);
     BCHECK(hipGetLastError());
     uint32_t hred[12];
     int hst = 0, hdep = 0;
     BCHECK(hipMemcpyAsync(hred, redp, sizeof(hred), hipMemcpyDeviceToHost, s));
     BCHECK(hipMemcpyAsync(&hst, st_build, sizeof(int), hipMemcpyDeviceToHost, s));
-    BCHECK(hipMemcpyAsync(&hdep, hgt.p, sizeof(int), hipMemcpyDeviceToHost, s));      // the root's height
+    BCHECK(hipMemcpyAsync(&hdep, hgt.p, sizeof(int), hipMemcpyDeviceToHost, s));      // the binary root's height
     BCHECK(hipStreamSynchronize(s));
     if (hst & ST_BAD_INDEX) {
         snprintf(err, errlen, "triangle index outside [0, n_vertices)");
@@ -656,8 +753,10 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     }
     out->zabs_max = fmaxf(fabsf(out->lo[2]), fabsf(out->hi[2]));
     out->n_tri = n;
-    out->n_nodes = n_int;
-    out->depth = hdep;
+    out->n_nodes = n4;
+    out->depth = levels4;
+    out->binary_depth = hdep;
+    out->stack = 3 * levels4;     // a traversal pushes at most three children per level
     out->leaf_size = m.leaf_size;
     return SONAR_OK;
 }

@@ -126,8 +126,9 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
         if (fabs(p->c_grad) * 2.0 * p->r_max / (p->c0 - fabs(p->c_grad) * zmax) > 1e-2)
             return fail(SONAR_E_UNSUPPORTED, "ray curvature too strong for one chord per segment (|g| 2 r_max / c > 1e-2)");
     }
-    if (sc->s.depth > 64)
-        return fail(SONAR_E_STACK, "hierarchy depth %d exceeds the 64-entry traversal stack", sc->s.depth);
+    if (sc->s.stack > 64)
+        return fail(SONAR_E_STACK, "hierarchy of %d levels can need %d stack entries, more than 64", sc->s.depth,
+                    sc->s.stack);
     sonar::PingArgs &a = *out;
     memset(&a, 0, sizeof(a));
     a.nodes = sc->s.nodes;
@@ -178,7 +179,8 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
         a.stats = rec->stats;
     }
     a.mask = ray_mask;
-    a.max_steps = (uint32_t)(2 * sc->s.n_nodes + 64);
+    // a traversal of a valid hierarchy visits every node and every leaf at most once
+    a.max_steps = (uint32_t)(sc->s.n_nodes + sc->s.n_tri + 64);
     return SONAR_OK;
 }
 
@@ -288,7 +290,7 @@ sonar_status sonar_build_scene(const sonar_mesh *m, sonar_stream stream, sonar_s
     if (m->n_triangles >= (int64_t)1 << 28) return fail(SONAR_E_INVALID, "at most 2^28 - 1 triangles");
     if (m->leaf_size < 0 || m->leaf_size > 8) return fail(SONAR_E_INVALID, "leaf_size must be in [0, 8]");
     sonar_mesh mm = *m;
-    if (mm.leaf_size == 0) mm.leaf_size = 4;
+    if (mm.leaf_size == 0) mm.leaf_size = 3;
     sonar_scene *sc = new (std::nothrow) sonar_scene();
     if (!sc) return fail(SONAR_E_NOMEM, "host allocation failed");
     if (hipGetDevice(&sc->s.device) != hipSuccess) {
@@ -325,7 +327,7 @@ sonar_status sonar_get_scene_info(const sonar_scene *sc, sonar_scene_info *info)
         info->lo[k] = sc->s.lo[k];
         info->hi[k] = sc->s.hi[k];
     }
-    info->node_bytes = sc->s.n_nodes * 64;
+    info->node_bytes = sc->s.n_nodes * 128;
     info->tri_bytes = sc->s.n_tri * 48;
     return SONAR_OK;
 }
@@ -338,7 +340,7 @@ sonar_status sonar_ping(const sonar_scene *sc, const sonar_params *p, const sona
     sonar::PingArgs a;
     sonar_status st = fill_ping_args(sc, p, q, volume, gbuffer, incoh, rec, ray_mask, &a);
     if (st != SONAR_OK) return st;
-    hipError_t e = sonar::launch_ping(a, sc->s.depth, (hipStream_t)stream);
+    hipError_t e = sonar::launch_ping(a, sc->s.stack, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping launch: %s", hipGetErrorString(e));
     return SONAR_OK;
 }
@@ -389,10 +391,10 @@ sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, con
         pa.det_M = c->max_per_beam;
         pa.det_n0 = (float)c->noise_floor;
         for (int n = 0; n <= 2 * 64; ++n) pa.det_alpha[n] = da.alpha[n];
-        e = sonar::launch_ping(pa, sc->s.depth, s);
+        e = sonar::launch_ping(pa, sc->s.stack, s);
         if (e == hipSuccess) e = sonar::launch_emit(da, s);
     } else {
-        e = sonar::launch_ping(pa, sc->s.depth, s);
+        e = sonar::launch_ping(pa, sc->s.stack, s);
         if (e == hipSuccess) e = sonar::launch_detect(da, s);
     }
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping/detect launch: %s", hipGetErrorString(e));
@@ -462,7 +464,7 @@ static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_p
     b->n_pings = plan->n_pings;
     b->K = plan->max_bounces;
     b->arc = plan->arc != 0;
-    b->depth = sc->s.depth;
+    b->depth = sc->s.stack;
     b->max_bins = plan->max_bins;
     b->total_tiles = plan->total_tiles;
     b->queue = reinterpret_cast<uint32_t *>(w);

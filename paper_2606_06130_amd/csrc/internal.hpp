@@ -29,12 +29,14 @@ constexpr int MAX_BOUNCES = 4;
 constexpr int MAX_BINS = 4096;
 
 struct Scene {
-    float4 *nodes = nullptr;      // [n_nodes * 4]
+    float4 *nodes = nullptr;      // [n_nodes * 8]: 4-wide nodes of 128 bytes
     float4 *tris = nullptr;       // [n_tri * 3]
     int *status = nullptr;        // device error word
     int64_t n_tri = 0;
     int64_t n_nodes = 0;
-    int depth = 0;
+    int depth = 0;                // levels of 4-wide nodes
+    int binary_depth = 0;         // height of the binary tree they come from
+    int stack = 0;                // bound on traversal stack entries (3 per level)
     int leaf_size = 4;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     float zabs_max = 0.f;

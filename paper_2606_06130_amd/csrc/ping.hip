@@ -34,10 +34,12 @@ constexpr double LN10_OVER_20 = 0.11512925464970228420;
 constexpr int K1_BIN_WORDS = WAVE;                            // int bin per slot
 constexpr int K1_VAL_WORDS = WAVE * 4;                        // float4 per slot
 constexpr int K1_IDX_BASE = K1_BIN_WORDS + K1_VAL_WORDS;      // uint16 column index
-// Single-bounce traversals keep the bottom K1_LDS_STACK stack entries of each
-// lane in LDS and deeper ones in private memory. Typical traversals stay in
-// LDS; the short LDS stack is what lets eight waves share a SIMD.
+// Traversals keep the bottom entries of each lane's stack in LDS (20 for a
+// single bounce, 32 with several) and deeper ones in private memory. Typical
+// traversals stay in LDS; the short LDS stack is what lets eight waves share
+// a SIMD.
 constexpr int K1_LDS_STACK = 20;
+constexpr int KN_LDS_STACK = 32;
 
 struct d3 {
     double x, y, z;
@@ -223,21 +225,22 @@ __device__ __forceinline__ bool slab(const Seg32 &r, float lx, float ly, float l
     return tn <= tf * 1.0000005f;
 }
 
-// FP32 Moller-Trumbore (closed triangle). Returns t or -1.
+// FP32 Moller-Trumbore (closed triangle), without a division on the
+// barycentric tests: with U = u det and V = v det the hit is inside when U, V
+// and det - U - V share det's sign. Returns t or -1.
 __device__ __forceinline__ float mt32(const Seg32 &r, const TriF &t)
 {
-    float3 e1 = fsub(t.v1, t.v0), e2 = fsub(t.v2, t.v0);
-    float3 p = fcross(r.d, e2);
-    float det = fdot(e1, p);
-    if (det == 0.f) return -1.f;
-    float inv = 1.0f / det;
-    float3 tv = fsub(r.o, t.v0);
-    float u = fdot(tv, p) * inv;
-    if (!(u >= 0.f && u <= 1.f)) return -1.f;
-    float3 q = fcross(tv, e1);
-    float v = fdot(r.d, q) * inv;
-    if (!(v >= 0.f && u + v <= 1.f)) return -1.f;
-    return fdot(e2, q) * inv;
+    const float3 e1 = fsub(t.v1, t.v0), e2 = fsub(t.v2, t.v0);
+    const float3 p = fcross(r.d, e2);
+    const float det = fdot(e1, p);
+    const float3 tv = fsub(r.o, t.v0);
+    const float U = fdot(tv, p);
+    const float3 q = fcross(tv, e1);
+    const float V = fdot(r.d, q);
+    const float W = U + V;
+    const bool in = det > 0.f ? (U >= 0.f && V >= 0.f && W <= det) : (det < 0.f && U <= 0.f && V <= 0.f && W >= det);
+    if (!in) return -1.f;
+    return fdot(e2, q) / det;
 }
 
 // FP32 arc-triangle test: smallest arc length s in (smin, smax] where the arc
@@ -299,11 +302,28 @@ __device__ __forceinline__ float arc32(const Seg32 &r, const TriF &t, float &tc)
 // Returns the triangle record index, or -1; `overflow` is set when the LDS
 // stack of DEPTH entries would overflow or the node-visit bound is reached
 // (the ray is then reported as a miss).
+// Orders two (distance, link) pairs by distance (ties keep their order).
+__device__ __forceinline__ void order2(float &ta, uint32_t &la, float &tb, uint32_t &lb)
+{
+    const bool sw = tb < ta;
+    const float t = sw ? tb : ta;
+    tb = sw ? ta : tb;
+    ta = t;
+    const uint32_t l = sw ? lb : la;
+    lb = sw ? la : lb;
+    la = l;
+}
+
+// Nearest-hit (or any-hit) traversal of the 4-wide hierarchy. An inner node
+// tests its four child boxes, descends into the nearest one hit and pushes
+// the others farthest first; leaves test their triangles. The stack keeps
+// its bottom DL entries of each lane in LDS, deeper ones in private memory.
 template <int DEPTH, int DL, bool ANY, bool ARC, bool STATS>
 __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restrict__ tris, const Seg32 &r,
                         uint32_t skip, uint32_t *__restrict__ stk, int lane, bool &overflow, float &s_out,
                         uint32_t max_steps, uint32_t &n_nodes, uint32_t &n_tris, uint32_t &n_deep)
 {
+    constexpr float MISS = __builtin_inff();
     int best = -1;
     float best_t = r.tmax;        // culling bound on the ray / chord parameter
     float best_s = r.smax;        // best arc length
@@ -321,37 +341,48 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
         }
         if (!(cur & LEAF_BIT)) {
             if (STATS) ++n_nodes;
-            const float4 *n = nodes + 4 * (size_t)cur;
-            float4 a = n[0], b = n[1], c = n[2], d = n[3];
-            float t0, t1;
-            bool h0, h1;
+            const float4 *n = nodes + 8 * (size_t)cur;
+            const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], lk = n[6];
+            float t0, t1, t2, t3;
+            bool h0, h1, h2, h3;
             if (ARC) {
-                h0 = slab(r, a.x - sg, a.y - sg, a.z - sg, a.w + sg, b.x + sg, b.y + sg, r.tmin, best_t, t0);
-                h1 = slab(r, b.z - sg, b.w - sg, c.x - sg, c.y + sg, c.z + sg, c.w + sg, r.tmin, best_t, t1);
+                h0 = slab(r, lx.x - sg, ly.x - sg, lz.x - sg, hx.x + sg, hy.x + sg, hz.x + sg, r.tmin, best_t, t0);
+                h1 = slab(r, lx.y - sg, ly.y - sg, lz.y - sg, hx.y + sg, hy.y + sg, hz.y + sg, r.tmin, best_t, t1);
+                h2 = slab(r, lx.z - sg, ly.z - sg, lz.z - sg, hx.z + sg, hy.z + sg, hz.z + sg, r.tmin, best_t, t2);
+                h3 = slab(r, lx.w - sg, ly.w - sg, lz.w - sg, hx.w + sg, hy.w + sg, hz.w + sg, r.tmin, best_t, t3);
             } else {
-                h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, r.tmin, best_t, t0);
-                h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, r.tmin, best_t, t1);
+                h0 = slab(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r.tmin, best_t, t0);
+                h1 = slab(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r.tmin, best_t, t1);
+                h2 = slab(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r.tmin, best_t, t2);
+                h3 = slab(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r.tmin, best_t, t3);
             }
-            uint32_t l0 = __float_as_uint(d.x), l1 = __float_as_uint(d.y);
-            if (h0 && h1) {
-                uint32_t nearc = t0 <= t1 ? l0 : l1;
-                uint32_t farc = t0 <= t1 ? l1 : l0;
-                if (sp >= DEPTH) {
+            float ta = h0 ? t0 : MISS, tb = h1 ? t1 : MISS, tc = h2 ? t2 : MISS, td = h3 ? t3 : MISS;
+            uint32_t la = __float_as_uint(lk.x), lb = __float_as_uint(lk.y), lc = __float_as_uint(lk.z),
+                     ld = __float_as_uint(lk.w);
+            order2(ta, la, tb, lb);
+            order2(tc, lc, td, ld);
+            order2(ta, la, tc, lc);
+            order2(tb, lb, td, ld);
+            order2(tb, lb, tc, lc);
+            if (ta != MISS) {
+                const int np = (tb != MISS) + (tc != MISS) + (td != MISS);
+                if (sp + np > DEPTH) {
                     overflow = true;
                     best = -1;
                     break;
                 }
-                if (DL == DEPTH || sp < DL) stk[sp * WAVE + lane] = farc;
-                else spill[sp - DL] = farc;
-                ++sp;
+                const uint32_t lp[3] = {ld, lc, lb};
+                const float tp[3] = {td, tc, tb};
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    if (tp[q] != MISS) {
+                        if (DL == DEPTH || sp < DL) stk[sp * WAVE + lane] = lp[q];
+                        else spill[sp - DL] = lp[q];
+                        ++sp;
+                    }
+                }
                 if (STATS) n_deep = max(n_deep, (uint32_t)sp);
-                cur = nearc;
-                continue;
-            } else if (h0) {
-                cur = l0;
-                continue;
-            } else if (h1) {
-                cur = l1;
+                cur = la;
                 continue;
             }
         } else if (cur != EMPTY_LINK) {
@@ -483,10 +514,11 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
 
     // Contribution slots: registers for a single bounce; for several bounces
     // an LDS area past the traversal stack, slot (k, lane) at k * 64 + lane.
-    constexpr int DL = (K == 1 && DEPTH > K1_LDS_STACK) ? K1_LDS_STACK : DEPTH;
-    int *sbin = (K == 1) ? reinterpret_cast<int *>(W) : reinterpret_cast<int *>(W + DEPTH * WAVE);
+    constexpr int DLS = K == 1 ? K1_LDS_STACK : KN_LDS_STACK;
+    constexpr int DL = DEPTH > DLS ? DLS : DEPTH;
+    int *sbin = (K == 1) ? reinterpret_cast<int *>(W) : reinterpret_cast<int *>(W + DL * WAVE);
     float4 *sval = (K == 1) ? reinterpret_cast<float4 *>(W + K1_BIN_WORDS)
-                            : reinterpret_cast<float4 *>(W + DEPTH * WAVE + K * WAVE);
+                            : reinterpret_cast<float4 *>(W + DL * WAVE + K * WAVE);
     Slot slot0 = Slot{-1, 0.f, 0.f, 0.f};
     if (K > 1) {
 #pragma unroll
@@ -881,8 +913,14 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
 
 // STATS instantiations count traversal work per ray (a diagnostic: the
 // counters cost registers, so the plain instantiations carry none).
+// Occupancy targets: eight waves per SIMD for single-bounce straight rays
+// (64 registers), three with several bounces.
+template <int K, bool ARC>
+constexpr int ping_waves_per_eu() { return K == 1 ? (ARC ? 5 : 8) : 3; }
+
 template <int DEPTH, int K, bool ARC, bool STATS>
-__global__ __launch_bounds__(BLOCK) void k_ping(PingArgs a, int wave_words)
+__global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(ping_waves_per_eu<K, ARC>())))
+void k_ping(PingArgs a, int wave_words)
 {
     extern __shared__ uint32_t lds[];
     uint32_t *W = lds + (size_t)(threadIdx.x / WAVE) * wave_words;
@@ -950,7 +988,8 @@ __global__ void k_batch_reset(uint32_t *queue, unsigned long long *t0, unsigned 
 
 int ping_wave_words(int depth, int n_bins, int K)
 {
-    if (K > 1) return depth * WAVE + 5 * WAVE * K;    // stack + slots; the column index reuses the stack
+    if (K > 1)   // LDS stack + slots; the column index reuses the stack
+        return (depth > KN_LDS_STACK ? KN_LDS_STACK : depth) * WAVE + 5 * WAVE * K;
     const int stk = (depth > K1_LDS_STACK ? K1_LDS_STACK : depth) * WAVE;
     const int acc = K1_IDX_BASE + (n_bins + 1) / 2;
     const int w = acc > stk ? acc : stk;

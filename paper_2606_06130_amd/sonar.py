@@ -220,7 +220,7 @@ def _dptr(t):
 class Scene:
     """A built scene (owns the library handle)."""
 
-    def __init__(self, mesh, leaf_size: int = 4, stream=None, device_inputs: bool = False):
+    def __init__(self, mesh, leaf_size: int = 0, stream=None, device_inputs: bool = False):
         import torch
         self._h = C.c_void_p()
         keep = []

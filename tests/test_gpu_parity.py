@@ -403,8 +403,8 @@ def test_deep_hierarchy_stack_spills_past_lds():
                          vfov=math.radians(10.0))
     pose = S.pose((3.0, 0.0, 0.0), yaw=math.pi)
     sc = sonar.Scene(mesh)
-    depth = sc.info()["depth"]
-    assert 21 <= depth <= 32, depth
+    depth = sc.info()["depth"]          # levels of 4-wide nodes: three pushes each at most
+    assert 3 * depth > 20 and 3 * depth <= 64, depth
     st = sonar.ping(sc, cfg, pose, record=True, stats=True)
     torch.cuda.synchronize()
     deepest = int(st["stats"][:, 2].max().item())
@@ -437,4 +437,4 @@ def test_traversal_counters_keep_results(bounces, g):
     tri = a["tri"].cpu().numpy()
     assert (st[:, 0] >= 1).all()                      # the root is an internal node
     assert (st[tri[:, 0] >= 0, 1] >= 1).all()         # a hit needs a tested triangle
-    assert (st[:, 2] <= sc.info()["depth"]).all()     # pushes never exceed the hierarchy depth
+    assert (st[:, 2] <= 3 * sc.info()["depth"]).all()     # at most three pushes per level of 4-wide nodes
