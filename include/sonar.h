@@ -320,7 +320,7 @@ int64_t sonar_surrogate_param_count(void);
 
 /* Allocates weights, Adam state, activations and smoothing buffers for up to
  * max_rows beams, and the DCT basis for n_bins range bins over [r_min, r_max)
- * (64 <= n_bins); `smooth` is the range box width in bins. Weights start at
+ * (64 <= n_bins <= 2048); `smooth` is the range box width in bins. Weights start at
  * zero: set them. */
 sonar_status sonar_surrogate_create(int64_t max_rows, int32_t n_bins, double r_min, double r_max, int32_t smooth,
                                     sonar_surrogate **out);

@@ -655,8 +655,7 @@ sonar_status sonar_surrogate_create(int64_t max_rows, int32_t n_bins, double r_m
     *out = nullptr;
     if (max_rows < 64 || max_rows % 64 != 0 || max_rows > ((int64_t)1 << 26))
         return fail(SONAR_E_INVALID, "max_rows must be a positive multiple of 64, at most 2^26");
-    if (n_bins < 64 || n_bins > sonar::MAX_BINS)
-        return fail(SONAR_E_INVALID, "n_bins must be in [64, %d]", sonar::MAX_BINS);
+    if (n_bins < 64 || n_bins > 2048) return fail(SONAR_E_INVALID, "n_bins must be in [64, 2048]");
     if (!(r_min >= 0) || !(r_max > r_min) || !isfinite(r_max)) return fail(SONAR_E_INVALID, "need 0 <= r_min < r_max");
     if (smooth < 1 || smooth > n_bins) return fail(SONAR_E_INVALID, "smooth must be in [1, n_bins]");
     sonar_surrogate *h = new (std::nothrow) sonar_surrogate();

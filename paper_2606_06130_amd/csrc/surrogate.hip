@@ -249,28 +249,51 @@ __global__ void k_pack_layer(const float *__restrict__ master, int K, int Kp, in
     if (i < N) bias[i] = master[(int64_t)K * N + i];
 }
 
-// Range smoothing of both incoherent channels: box average over bins
-// [r - w/2, r + w/2), zero outside. One block per row, the row staged in LDS.
-__global__ __launch_bounds__(256) void k_smooth(const float *__restrict__ i1, const float *__restrict__ im,
-                                                int nb, int w, float *__restrict__ s1, float *__restrict__ sm)
+// Range smoothing of an incoherent channel: box average over bins
+// [r - w/2, r + w/2), zero outside. One wave per row: the row is staged in
+// LDS (one pad word per 16 so that the lanes' chunks spread over the banks),
+// each lane slides an FP64 window sum over its consecutive bins, and the
+// results leave through LDS with coalesced stores.
+__device__ __forceinline__ int spad(int b) { return b + (b >> 4); }
+
+__global__ __launch_bounds__(64) void k_smooth(const float *__restrict__ i1, const float *__restrict__ im, int nb,
+                                               int w, float *__restrict__ s1, float *__restrict__ sm)
 {
-    extern __shared__ float row[];    // [2][nb]
+    extern __shared__ float lds[];     // input and output rows, padded
+    const int lane = threadIdx.x;
+    const int pitch = spad(nb) + 1;
+    float *in = lds, *out = lds + pitch;
     const int64_t o = (int64_t)blockIdx.x * nb;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        row[b] = i1[o + b];
-        row[nb + b] = im[o + b];
-    }
-    __syncthreads();
-    const float inv = 1.f / w;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        const int lo = max(0, b - w / 2), hi = min(nb, b + w - w / 2);
-        float a = 0.f, c = 0.f;
-        for (int q = lo; q < hi; ++q) {
-            a += row[q];
-            c += row[nb + q];
+    const int per = (nb + 63) / 64;
+    const int b0 = lane * per, b1 = min(b0 + per, nb);
+    const double inv = 1.0 / w;
+    for (int ch = 0; ch < (im ? 2 : 1); ++ch) {
+        const float *src = (ch ? im : i1) + o;
+        float *dst = (ch ? sm : s1) + o;
+#pragma unroll 8
+        for (int b = lane; b < nb; b += 64) in[spad(b)] = src[b];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (b0 < nb) {
+            double acc = 0.0;
+            for (int q = max(0, b0 - w / 2); q < min(nb, b0 + w - w / 2); ++q) acc += (double)in[spad(q)];
+            out[spad(b0)] = (float)(acc * inv);
+            for (int b = b0 + 1; b < b1; ++b) {
+                const int enter = b + w - w / 2 - 1, leave = b - w / 2 - 1;
+                if (enter < nb) acc += (double)in[spad(enter)];
+                if (leave >= 0) acc -= (double)in[spad(leave)];
+                out[spad(b)] = (float)(acc * inv);
+            }
         }
-        s1[o + b] = a * inv;
-        sm[o + b] = c * inv;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 8
+        for (int b = lane; b < nb; b += 64) dst[b] = out[spad(b)];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -359,105 +382,150 @@ __global__ void k_coef_moments(const float *__restrict__ c, int64_t rows, double
     }
 }
 
+// Single-bounce profile plus the mean residual, per bin: the inverse DCT of
+// the mean coefficients (for the mean-residual baseline error).
+__global__ void k_mean_residual(const float *__restrict__ basis, const float *__restrict__ mu, int nb,
+                                float *__restrict__ mres)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nb) return;
+    float a = 0.f;
+    for (int j = 0; j < NCOEF; ++j) a += basis[(int64_t)j * nb + c] * mu[j];
+    mres[c] = a;
+}
+
 // Predicted range-smoothed profile and per-beam dB errors. For row k with
 // first-hit bin r1: profile[b] = 10 log10(I1s[b] + floor) for b < r1 and
-// + sum_j C[j][b - r1] c_j after it, c the de-standardised prediction.
-// Errors over occupied bins (smoothed truth more than 3 dB above the floor):
-// [0] the prediction, [1] the single-bounce profile alone, [2] the single
-// bounce plus the mean residual (the same inverse DCT of the mean
-// coefficients), [3] the number of occupied bins. Block: 16 rows; thread t
-// takes aligned bins t, t + 256, ... so all rows share one basis column.
+// + Q[k][b - r1] after it, with Q[k][c] = sum_j C[j][c] c_kj the inverse DCT
+// of the de-standardised prediction. Errors over occupied bins (smoothed
+// truth more than 3 dB above the floor): [0] the prediction, [1] the single
+// bounce alone, [2] the single bounce plus the mean residual, [3] the number
+// of occupied bins.
+// Block: 16 rows, 4 waves, in two phases.
+//  1. Q on the matrix cores, wave q taking a quarter of the columns c: 16 x
+//     16 x 4 FP32 MFMA steps, A the 16 rows' coefficients (lane l: row l % 16,
+//     coefficient 4 s + l / 16, in registers), B the basis (lane l:
+//     coefficient 4 s + l / 16, column l % 16); lane l ends with Q of rows
+//     4 (l / 16) + i, column l % 16, stored to LDS.
+//  2. The rows stream out, each thread taking bins t, t + 256, ... (P of
+//     them); the single-bounce values of all 16 rows are loaded before phase
+//     1, so their latency hides behind the matrix work. Error sums: wave
+//     shuffles, then one LDS slot per wave and row.
+constexpr int PR_ROWS = 16;
+
+template <int P>
 __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict__ pred, const float *__restrict__ i1,
                                                         const float *__restrict__ im, const float *__restrict__ gbuf,
                                                         int64_t rows, int nb, float r_min, float r_max,
                                                         const float *__restrict__ basis, const float *__restrict__ mu,
-                                                        const float *__restrict__ sg, float *__restrict__ err,
+                                                        const float *__restrict__ sg,
+                                                        const float *__restrict__ mres, float *__restrict__ err,
                                                         float *__restrict__ profile)
 {
-    __shared__ float cf[16][64];
-    __shared__ int r1s[16];
-    __shared__ float red[4][4][16];
-    const int t = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * 16;
+    extern __shared__ float Q[];              // [PR_ROWS][nb + 1]
+    __shared__ int r1s[PR_ROWS];
+    __shared__ float red[PR_ROWS][4][4];
+    const int t = threadIdx.x, lane = t & 63, wq = t >> 6;
+    const int ar = lane & 15, kq = lane >> 4;
+    const int pitch = nb + 1;
+    const int64_t r0 = (int64_t)blockIdx.x * PR_ROWS;
     const float dr = (r_max - r_min) / nb;
-    for (int e = t; e < 16 * 64; e += 256) {
-        const int r = e >> 6, j = e & 63;
-        cf[r][j] = (r0 + r < rows) ? pred[(r0 + r) * NCOEF + j] * sg[j] + mu[j] : 0.f;
-    }
-    if (t < 16) r1s[t] = (r0 + t < rows) ? first_hit_bin(gbuf, r0 + t, r_min, r_max, dr, nb) : 0;
-    __syncthreads();
-    float es[16], e1[16], em[16], no[16];
-    for (int r = 0; r < 16; ++r) es[r] = e1[r] = em[r] = no[r] = 0.f;
     const float occ_db = 10.f * log10f(I_FLOOR) + 3.f;
-    // bins before the first hit: no residual
-    for (int r = 0; r < 16; ++r) {
-        if (r0 + r >= rows) break;
-        for (int b = t; b < r1s[r]; b += 256) {
-            const int64_t o = (r0 + r) * nb + b;
-            const float p1 = 10.f * log10f(i1[o] + I_FLOOR);
-            if (profile) profile[o] = p1;
-            if (im) {
-                const float tr = 10.f * log10f(i1[o] + im[o] + I_FLOOR);
-                if (tr > occ_db) {
-                    const float d = fabsf(p1 - tr);
-                    es[r] += d;
-                    e1[r] += d;
-                    em[r] += d;
-                    no[r] += 1.f;
-                }
+    if (t < PR_ROWS) r1s[t] = (r0 + t < rows) ? first_hit_bin(gbuf, r0 + t, r_min, r_max, dr, nb) : nb;
+    // the single-bounce channel of the 16 rows, in flight during phase 1
+    float iv[PR_ROWS][P];
+#pragma unroll
+    for (int rl = 0; rl < PR_ROWS; ++rl) {
+        const int64_t rowc = min(r0 + rl, rows - 1);
+#pragma unroll
+        for (int q = 0; q < P; ++q) iv[rl][q] = i1[rowc * nb + min(t + 256 * q, nb - 1)];
+    }
+
+    // phase 1: Q of this wave's column quarter
+    float a[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int j = 4 * s + kq;
+        a[s] = (r0 + ar < rows) ? pred[(r0 + ar) * NCOEF + j] * sg[j] + mu[j] : 0.f;
+    }
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int cq = (nb + 3) / 4;
+    const int c_begin = wq * cq, c_end = min(nb, c_begin + cq);
+    for (int c0 = c_begin; c0 < c_end; c0 += 16) {
+        const int cc = c0 + ar;
+        const int ccl = min(cc, nb - 1);
+        float bv[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) bv[s] = basis[(int64_t)(4 * s + kq) * nb + ccl];
+        f4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv[s], d, 0, 0, 0);
+        if (cc < c_end) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Q[(4 * kq + i) * pitch + cc] = d[i];
+        }
+    }
+    __syncthreads();
+
+    // phase 2: stream the rows out
+#pragma unroll
+    for (int rp = 0; rp < PR_ROWS; rp += 2) {
+        float mv[2][P];
+        if (im) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t rowc = min(r0 + rp + h, rows - 1);
+#pragma unroll
+                for (int q = 0; q < P; ++q) mv[h][q] = im[rowc * nb + min(t + 256 * q, nb - 1)];
             }
         }
-    }
-    for (int q = t; q < nb; q += 256) {
-        float cb[64];
-        float meanres = 0.f;
-        for (int j = 0; j < 64; ++j) {
-            cb[j] = basis[(int64_t)j * nb + q];
-            meanres += cb[j] * mu[j];
-        }
-        for (int r = 0; r < 16; ++r) {
-            if (r0 + r >= rows) break;
-            const int b = q + r1s[r];
-            if (b >= nb) continue;
-            const int64_t o = (r0 + r) * nb + b;
-            const float p1 = 10.f * log10f(i1[o] + I_FLOOR);
-            float res = 0.f;
-            for (int j = 0; j < 64; ++j) res += cb[j] * cf[r][j];
-            const float ph = p1 + res;
-            if (profile) profile[o] = ph;
-            if (im) {
-                const float tr = 10.f * log10f(i1[o] + im[o] + I_FLOOR);
-                if (tr > occ_db) {
-                    es[r] += fabsf(ph - tr);
-                    e1[r] += fabsf(p1 - tr);
-                    em[r] += fabsf(p1 + meanres - tr);
-                    no[r] += 1.f;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int rl = rp + h;
+            const int64_t row = r0 + rl;
+            const bool rok = row < rows;
+            const int r1 = r1s[rl];
+            float es = 0.f, e1 = 0.f, em = 0.f, no = 0.f;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const int b = t + 256 * q;
+                if (!rok || b >= nb) continue;
+                const float p1 = 10.f * log10f(iv[rl][q] + I_FLOOR);
+                const float res = b >= r1 ? Q[rl * pitch + (b - r1)] : 0.f;
+                const float ph = p1 + res;
+                if (profile) profile[row * nb + b] = ph;
+                if (im) {
+                    const float tr = 10.f * log10f(iv[rl][q] + mv[h][q] + I_FLOOR);
+                    if (tr > occ_db) {
+                        const float mr = (b >= r1 && mres) ? mres[b - r1] : 0.f;
+                        es += fabsf(ph - tr);
+                        e1 += fabsf(p1 - tr);
+                        em += fabsf(p1 + mr - tr);
+                        no += 1.f;
+                    }
+                }
+            }
+            if (err) {
+                for (int off = 32; off > 0; off >>= 1) {
+                    es += __shfl_xor(es, off);
+                    e1 += __shfl_xor(e1, off);
+                    em += __shfl_xor(em, off);
+                    no += __shfl_xor(no, off);
+                }
+                if (lane == 0) {
+                    red[rl][wq][0] = es;
+                    red[rl][wq][1] = e1;
+                    red[rl][wq][2] = em;
+                    red[rl][wq][3] = no;
                 }
             }
         }
     }
     if (!err) return;
-    // reduce over the block: wave shuffles then LDS
-    const int lane = t & 63, w = t >> 6;
-    for (int r = 0; r < 16; ++r) {
-        float a = es[r], b = e1[r], c = em[r], d = no[r];
-        for (int off = 32; off > 0; off >>= 1) {
-            a += __shfl_xor(a, off);
-            b += __shfl_xor(b, off);
-            c += __shfl_xor(c, off);
-            d += __shfl_xor(d, off);
-        }
-        if (lane == 0) {
-            red[w][0][r] = a;
-            red[w][1][r] = b;
-            red[w][2][r] = c;
-            red[w][3][r] = d;
-        }
-    }
     __syncthreads();
-    if (t < 16 && r0 + t < rows) {
+    if (t < PR_ROWS && r0 + t < rows) {
         float sm[4];
-        for (int q = 0; q < 4; ++q) sm[q] = red[0][q][t] + red[1][q][t] + red[2][q][t] + red[3][q][t];
+        for (int q = 0; q < 4; ++q) sm[q] = red[t][0][q] + red[t][1][q] + red[t][2][q] + red[t][3][q];
         const float n = sm[3];
         float *o = err + (r0 + t) * 4;
         o[0] = n > 0.f ? sm[0] / n : NAN;
@@ -485,6 +553,7 @@ struct Surrogate {
     double *dpart = nullptr;     // loss / moment partials
     float *basis = nullptr;      // [64][n_bins]
     float *s1 = nullptr, *sm = nullptr;   // range-smoothed channels [max_rows][n_bins]
+    float *mres = nullptr;                // mean-residual profile [n_bins]
     float r_min = 0.f, r_max = 0.f;
     int smooth = 32;
     float *mu = nullptr, *sg = nullptr;
@@ -541,6 +610,7 @@ hipError_t surrogate_create(int64_t max_rows, int n_bins, float r_min, float r_m
     SA(s->basis, (size_t)NCOEF * n_bins * 4);
     SA(s->s1, (size_t)max_rows * n_bins * 4);
     SA(s->sm, (size_t)max_rows * n_bins * 4);
+    SA(s->mres, (size_t)n_bins * 4);
     SA(s->mu, NCOEF * 4);
     SA(s->sg, NCOEF * 4);
 #undef SA
@@ -694,10 +764,11 @@ hipError_t surrogate_train_step(Surrogate *s, const float *gbuf, int n_img, int 
     return pack_all(s, st);
 }
 
+// Smooths i1 into s1 and, when given, im into sm.
 static void smooth_channels(const Surrogate *s, const float *i1, const float *im, int64_t rows, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_smooth, dim3((unsigned)rows), dim3(256), (size_t)2 * s->n_bins * 4, st, i1, im, s->n_bins,
-                       s->smooth, s->s1, s->sm);
+    const size_t lds = (size_t)2 * (s->n_bins + (s->n_bins >> 4) + 1) * sizeof(float);
+    hipLaunchKernelGGL(k_smooth, dim3((unsigned)rows), dim3(64), lds, st, i1, im, s->n_bins, s->smooth, s->s1, s->sm);
 }
 
 hipError_t surrogate_residual_coef(const Surrogate *s, const float *i1, const float *im, const float *gbuf,
@@ -734,10 +805,21 @@ hipError_t surrogate_profile_errors(const Surrogate *s, const float *pred, const
                                     const float *gbuf, int64_t rows, float *err, float *profile, hipStream_t st)
 {
     // smooth i1 and (if given) im into the surrogate's buffers
-    smooth_channels(s, i1, im ? im : i1, rows, st);
-    hipLaunchKernelGGL(k_profile_errors, dim3((unsigned)((rows + 15) / 16)), dim3(256), 0, st, pred, s->s1,
-                       im ? s->sm : nullptr, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->basis, s->mu, s->sg, err,
-                       profile);
+    smooth_channels(s, i1, im, rows, st);
+    if (im && err)
+        hipLaunchKernelGGL(k_mean_residual, dim3((unsigned)((s->n_bins + 255) / 256)), dim3(256), 0, st, s->basis,
+                           s->mu, s->n_bins, s->mres);
+    const size_t lds = (size_t)PR_ROWS * (s->n_bins + 1) * sizeof(float);
+    const int per = (s->n_bins + 255) / 256;
+#define SONAR_PROFILE(PP)                                                                                        \
+    hipLaunchKernelGGL(k_profile_errors<PP>, dim3((unsigned)((rows + PR_ROWS - 1) / PR_ROWS)), dim3(256), lds, st, \
+                       pred, s->s1, im ? s->sm : nullptr, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->basis,     \
+                       s->mu, s->sg, s->mres, err, profile)
+    if (per <= 1) SONAR_PROFILE(1);
+    else if (per <= 2) SONAR_PROFILE(2);
+    else if (per <= 4) SONAR_PROFILE(4);
+    else SONAR_PROFILE(8);
+#undef SONAR_PROFILE
     return hipGetLastError();
 }
 
