@@ -47,7 +47,7 @@ __global__ void k_tri_prep(const float *__restrict__ V, int64_t nv, const int32_
                            const float *__restrict__ rho, const float *__restrict__ phi,
                            const uint8_t *__restrict__ mat, int64_t nt, float4 *__restrict__ tri_rec,
                            float4 *__restrict__ cen, float4 *__restrict__ blo, float4 *__restrict__ bhi,
-                           uint32_t *__restrict__ red, int *__restrict__ status)
+                           uint32_t *__restrict__ part, int *__restrict__ status)
 {
     __shared__ float s_min[6][BT / 64], s_max[6][BT / 64];
     int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
@@ -103,8 +103,67 @@ __global__ void k_tri_prep(const float *__restrict__ V, int64_t nv, const int32_
         int k = threadIdx.x;
         float a = INFINITY, b = -INFINITY;
         for (int q = 0; q < BT / 64; ++q) { a = fminf(a, s_min[k][q]); b = fmaxf(b, s_max[k][q]); }
-        atomicMin(&red[k], f2ord(a));
-        atomicMax(&red[6 + k], f2ord(b));
+        part[(int64_t)blockIdx.x * 12 + k] = f2ord(a);
+        part[(int64_t)blockIdx.x * 12 + 6 + k] = f2ord(b);
+    }
+}
+
+// Reductions of per-block partials by one block (no atomics on one address):
+// twelve order-preserving min (0..5) / max (6..11) words, or one int maximum.
+__global__ __launch_bounds__(1024) void k_reduce_bounds(const uint32_t *__restrict__ part, int nb,
+                                                        uint32_t *__restrict__ red)
+{
+    __shared__ uint32_t s[12][16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t v[12];
+    for (int k = 0; k < 12; ++k) v[k] = k < 6 ? 0xFFFFFFFFu : 0u;
+    for (int b = t; b < nb; b += 1024)
+        for (int k = 0; k < 12; ++k) {
+            const uint32_t x = part[(int64_t)b * 12 + k];
+            v[k] = k < 6 ? min(v[k], x) : max(v[k], x);
+        }
+    for (int k = 0; k < 12; ++k) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t o = __shfl_xor(v[k], off);
+            v[k] = k < 6 ? min(v[k], o) : max(v[k], o);
+        }
+        if (lane == 0) s[k][w] = v[k];
+    }
+    __syncthreads();
+    if (t < 12) {
+        uint32_t r = t < 6 ? 0xFFFFFFFFu : 0u;
+        for (int q = 0; q < 16; ++q) r = t < 6 ? min(r, s[t][q]) : max(r, s[t][q]);
+        red[t] = r;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_max(const int32_t *__restrict__ part, int nb, int32_t *__restrict__ out)
+{
+    __shared__ int32_t s[16];
+    const int t = threadIdx.x;
+    int32_t v = INT32_MIN;
+    for (int b = t; b < nb; b += 1024) v = max(v, part[b]);
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    if ((t & 63) == 0) s[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+        int32_t r = INT32_MIN;
+        for (int q = 0; q < 16; ++q) r = max(r, s[q]);
+        *out = r;
+    }
+}
+
+// Block maximum of one int per thread into part[blockIdx.x].
+__device__ __forceinline__ void block_max_to(int v, int32_t *__restrict__ part)
+{
+    __shared__ int32_t s[BT / 64];
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = s[0];
+        for (int q = 1; q < BT / 64; ++q) r = max(r, s[q]);
+        part[blockIdx.x] = r;
     }
 }
 
@@ -362,8 +421,9 @@ __global__ void k_karras(const uint64_t *__restrict__ k, int64_t n, int32_t *__r
 // then the levels are merged from the deepest to the root, each launch
 // reading only children finished by an earlier launch. Heights (edges to the
 // deepest triangle) come along; the root's height is the hierarchy depth.
-__global__ void k_depth(const int32_t *__restrict__ parent, int64_t n_int, int32_t *__restrict__ depth,
-                        int32_t *__restrict__ max_depth, int *__restrict__ status)
+__global__ __launch_bounds__(BT) void k_depth(const int32_t *__restrict__ parent, int64_t n_int,
+                                             int32_t *__restrict__ depth, int32_t *__restrict__ part,
+                                             int *__restrict__ status)
 {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     int d = 0;
@@ -376,8 +436,7 @@ __global__ void k_depth(const int32_t *__restrict__ parent, int64_t n_int, int32
         if (d >= MAX_WALK) atomicOr(status, ST_BAD_TREE);
         depth[i] = d;
     }
-    for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(max_depth, d);
+    block_max_to(d, part);
 }
 
 __global__ void k_leaf_boxes(const uint32_t *__restrict__ order, int64_t n, const float4 *__restrict__ blo_tri,
@@ -418,9 +477,10 @@ __device__ __forceinline__ int32_t tri_count(int32_t c, int64_t n, const int32_t
     return c >= n - 1 ? 1 : rhi[c] - rlo[c] + 1;
 }
 
-__global__ void k_mark4(int64_t n, const int32_t *__restrict__ depth, const int32_t *__restrict__ rlo,
-                        const int32_t *__restrict__ rhi, int leaf_size, uint32_t *__restrict__ flag,
-                        uint32_t *__restrict__ id4, int32_t *__restrict__ max_level)
+__global__ __launch_bounds__(BT) void k_mark4(int64_t n, const int32_t *__restrict__ depth,
+                                             const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi,
+                                             int leaf_size, uint32_t *__restrict__ flag, uint32_t *__restrict__ id4,
+                                             int32_t *__restrict__ part)
 {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     int lv = -1;
@@ -430,8 +490,7 @@ __global__ void k_mark4(int64_t n, const int32_t *__restrict__ depth, const int3
         id4[i] = flag[i];
         if (f) lv = depth[i] >> 1;
     }
-    for (int off = 32; off > 0; off >>= 1) lv = max(lv, __shfl_xor(lv, off));
-    if ((threadIdx.x & 63) == 0 && lv >= 0) atomicMax(max_level, lv);
+    block_max_to(lv, part);
 }
 
 __global__ void k_pack4(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
@@ -538,13 +597,6 @@ __global__ void k_gather_tris(const uint32_t *__restrict__ order, int64_t n, con
     out[3 * i + 2] = in[3 * (int64_t)t + 2];
 }
 
-__global__ void k_init_red(uint32_t *red)
-{
-    int t = threadIdx.x;
-    if (t < 6) red[t] = 0xFFFFFFFFu;       // min slots: largest ordered value
-    else if (t < 12) red[t] = 0u;          // max slots
-}
-
 inline unsigned nblk(int64_t n) { return (unsigned)((n + BT - 1) / BT); }
 inline int64_t leaf_size_of(const sonar_mesh &m) { return m.leaf_size; }
 
@@ -594,7 +646,7 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     }
     const int64_t n_int = n > 1 ? n - 1 : 1;
     const int64_t n_all = 2 * n - 1;
-    DevBuf rec, cen, tlo, thi, red, k0, k1, v0, v1, hist, tsum, lft, rgt, rlo, rhi, par, blo, bhi, ndp, dep, hgt;
+    DevBuf rec, cen, tlo, thi, red, k0, k1, v0, v1, hist, tsum, lft, rgt, rlo, rhi, par, blo, bhi, ndp, dep, hgt, bpart;
     int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
     BCHECK(hipMalloc(&rec.p, sizeof(float4) * 3 * n));
     BCHECK(hipMalloc(&cen.p, sizeof(float4) * n));
@@ -618,6 +670,7 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     BCHECK(hipMalloc(&bhi.p, sizeof(float4) * n_all));
     BCHECK(hipMalloc(&ndp.p, sizeof(int32_t) * n_int));
     BCHECK(hipMalloc(&dep.p, sizeof(int32_t)));
+    BCHECK(hipMalloc(&bpart.p, sizeof(uint32_t) * 12 * (size_t)nblk(n > n_int ? n : n_int)));
     BCHECK(hipMalloc(&hgt.p, sizeof(int32_t) * n_all));
 
     DevBuf flg, id4;
@@ -645,11 +698,10 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     int *st_build = (int *)(redp + 12);
     BCHECK(hipMemsetAsync(status, 0, sizeof(int), s));
     BCHECK(hipMemsetAsync(st_build, 0, sizeof(int), s));
-    BCHECK(hipMemsetAsync(dep.p, 0, sizeof(int32_t), s));
     BCHECK(hipMemsetAsync(par.p, 0, sizeof(int32_t) * n_all, s));
-    k_init_red<<<1, 64, 0, s>>>(redp);
     k_tri_prep<<<nblk(n), BT, 0, s>>>(V, nv, I, R, P, M, n, (float4 *)rec.p, (float4 *)cen.p, (float4 *)tlo.p,
-                                      (float4 *)thi.p, redp, st_build);
+                                      (float4 *)thi.p, (uint32_t *)bpart.p, st_build);
+    k_reduce_bounds<<<1, 1024, 0, s>>>((const uint32_t *)bpart.p, (int)nblk(n), redp);
     k_morton<<<nblk(n), BT, 0, s>>>((const float4 *)cen.p, n, redp, (uint64_t *)k0.p, (uint32_t *)v0.p);
     uint64_t *ka = (uint64_t *)k0.p, *kb = (uint64_t *)k1.p;
     uint32_t *va = (uint32_t *)v0.p, *vb = (uint32_t *)v1.p;
@@ -670,8 +722,9 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
                                         (float4 *)bhi.p, (int32_t *)hgt.p);
     if (n > 1) {
         // levels of the tree: one short synchronisation for the deepest level
-        k_depth<<<nblk(n_int), BT, 0, s>>>((const int32_t *)par.p, n_int, (int32_t *)ndp.p, (int32_t *)dep.p,
+        k_depth<<<nblk(n_int), BT, 0, s>>>((const int32_t *)par.p, n_int, (int32_t *)ndp.p, (int32_t *)bpart.p,
                                            st_build);
+        k_reduce_max<<<1, 1024, 0, s>>>((const int32_t *)bpart.p, (int)nblk(n_int), (int32_t *)dep.p);
         int max_level = 0;
         BCHECK(hipMemcpyAsync(&max_level, dep.p, sizeof(int), hipMemcpyDeviceToHost, s));
         BCHECK(hipStreamSynchronize(s));
@@ -687,10 +740,10 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     // 4-wide nodes: mark, number (exclusive scan), count (a short synchronisation), pack
     int n4 = 0, levels4 = 1;
     if (n > leaf_size_of(m)) {
-        BCHECK(hipMemsetAsync(dep.p, 0xFF, sizeof(int32_t), s));           // max level: -1
         k_mark4<<<nblk(n_int), BT, 0, s>>>(n, (const int32_t *)ndp.p, (const int32_t *)rlo.p,
                                            (const int32_t *)rhi.p, m.leaf_size, (uint32_t *)flg.p,
-                                           (uint32_t *)id4.p, (int32_t *)dep.p);
+                                           (uint32_t *)id4.p, (int32_t *)bpart.p);
+        k_reduce_max<<<1, 1024, 0, s>>>((const int32_t *)bpart.p, (int)nblk(n_int), (int32_t *)dep.p);
         k_scan_tiles<<<n_scan4, SCAN_THREADS, 0, s>>>((const uint32_t *)id4.p, n_int, (uint32_t *)tsum4.p);
         k_scan_sums<<<1, 1024, 0, s>>>((uint32_t *)tsum4.p, n_scan4);
         k_scan_apply<<<n_scan4, SCAN_THREADS, 0, s>>>((uint32_t *)id4.p, n_int, (const uint32_t *)tsum4.p);

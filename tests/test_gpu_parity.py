@@ -438,3 +438,27 @@ def test_traversal_counters_keep_results(bounces, g):
     assert (st[:, 0] >= 1).all()                      # the root is an internal node
     assert (st[tri[:, 0] >= 0, 1] >= 1).all()         # a hit needs a tested triangle
     assert (st[:, 2] <= 3 * sc.info()["depth"]).all()     # at most three pushes per level of 4-wide nodes
+
+
+@pytest.mark.parametrize("n_tri,leaf", [(2, 0), (3, 0), (4, 0), (5, 0), (5, 1), (9, 2), (17, 8)])
+def test_tiny_scenes(n_tri, leaf):
+    """Scenes of a few triangles: a single 4-wide node with one leaf (at most
+    leaf_size triangles), sparse nodes with empty child slots, leaf sizes 1-8;
+    overlapping triangles at staggered depths so nearer ones occlude."""
+    torch, sonar = _gpu()
+    tris = []
+    for k in range(n_tri):
+        a = 2.0 * math.pi * k / n_tri
+        y0, z0, x = 0.6 * math.cos(a), 0.6 * math.sin(a), 5.0 + 0.35 * k
+        tris.append([[x, y0 - 0.9, z0 - 0.7], [x + 0.2, y0 + 0.9, z0 - 0.6], [x - 0.1, y0 + 0.1, z0 + 0.9]])
+    mesh = M.mesh_from(tris, rho=0.4, phi=0.3)
+    mesh.name = f"tiny{n_tri}"
+    cfg = S.SensorConfig(n_h=16, n_v=8, rays_per_beam=4, n_range=512, hfov=math.radians(40.0),
+                         vfov=math.radians(30.0))
+    sc = sonar.Scene(mesh, leaf_size=leaf)
+    info = sc.info()
+    assert info["n_triangles"] == n_tri and info["n_nodes"] >= 1
+    res, g, _ = run_parity(mesh, cfg, S.pose((0.0, 0.0, 0.0)), gpu_scene=sc)
+    assert_parity(res)
+    assert res["energy"] > 0
+    assert len(set(g["tri"][:, 0].tolist()) - {-1}) >= min(n_tri, 2)     # several triangles are seen
