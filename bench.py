@@ -85,8 +85,20 @@ def copy_bandwidth(torch, reps=5):
     return 2.0 * 4 * n / t / 1e9
 
 
-def cpu_baseline(mesh, cfg, pose, budget_s=12.0):
-    """The oracle as it stands, brute force, on a bounded sample of beams."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(mesh, cfg, pose, budget_s=10.0, single_budget_s=3.0):
+    """The oracle as it stands, brute force, on bounded random samples of
+    beams: with up to 16 host threads, and on one thread."""
     import numpy as np
 
     import oracle
@@ -94,21 +106,29 @@ def cpu_baseline(mesh, cfg, pose, budget_s=12.0):
     sc = oracle.Scene(mesh)
     rng = np.random.Generator(np.random.PCG64(123))
     order = rng.permutation(cfg.n_beams)
-    done, t0 = 0, time.perf_counter()
-    chunk = 16
-    while True:
-        oracle.trace_beams(sc, cfg, pose, order[done:done + chunk], threads=threads, want_all=False)
-        done += chunk
-        el = time.perf_counter() - t0
-        if el >= budget_s or done >= cfg.n_beams:
-            break
-        chunk = min(chunk * 2, 256)
+
+    def sample(n_threads, budget):
+        done, t0 = 0, time.perf_counter()
+        chunk = 4 if n_threads == 1 else 16
+        while True:
+            oracle.trace_beams(sc, cfg, pose, order[done:done + chunk], threads=n_threads, want_all=False)
+            done += chunk
+            el = time.perf_counter() - t0
+            if el >= budget or done >= cfg.n_beams:
+                return done, el
+            chunk = min(chunk * 2, 256)
+
+    done, el = sample(threads, budget_s)
     rays = done * cfg.rays_per_beam
-    pings_s = rays / cfg.n_rays / el
-    return {"value": pings_s, "unit": "pings/s", "cores": threads, "kind": "oracle",
+    done1, el1 = sample(1, single_budget_s)
+    rays1 = done1 * cfg.rays_per_beam
+    return {"value": rays / cfg.n_rays / el, "unit": "pings/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} random beams x {cfg.rays_per_beam} rays ({rays} rays) of the harbor ping, brute force "
-                      f"FP64 in {el:.1f} s, scaled to one {cfg.n_rays}-ray ping",
-            "mrays_per_s": rays / el / 1e6}
+                      f"FP64 in {el:.1f} s on {threads} threads, scaled to one {cfg.n_rays}-ray ping",
+            "mrays_per_s": rays / el / 1e6,
+            "single_thread": {"pings_per_s": rays1 / cfg.n_rays / el1, "mrays_per_s": rays1 / el1 / 1e6,
+                              "sample": f"{done1} beams ({rays1} rays) in {el1:.1f} s"},
+            "cpu_model": _cpu_model()}
 
 
 def multipath_and_batch(torch, sonar, S, np, replays=5):

@@ -225,6 +225,23 @@ __device__ __forceinline__ bool slab(const Seg32 &r, float lx, float ly, float l
     return tn <= tf * 1.0000005f;
 }
 
+// Slab test of a box inflated by the sagitta s on every side, with the
+// inflation folded into two shifted origins: lower planes against o + s,
+// upper planes against o - s (as many operations as the plain test; the
+// rounding of o +- s stays inside the sagitta's own FP32 margin).
+__device__ __forceinline__ bool slab_inflated(const float3 &olo, const float3 &ohi, const float3 &inv, float lx,
+                                              float ly, float lz, float hx, float hy, float hz, float tmin,
+                                              float tmax, float &tnear)
+{
+    float x0 = (lx - olo.x) * inv.x, x1 = (hx - ohi.x) * inv.x;
+    float y0 = (ly - olo.y) * inv.y, y1 = (hy - ohi.y) * inv.y;
+    float z0 = (lz - olo.z) * inv.z, z1 = (hz - ohi.z) * inv.z;
+    float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
+    float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmax));
+    tnear = tn;
+    return tn <= tf * 1.0000005f;
+}
+
 // FP32 Moller-Trumbore (closed triangle), without a division on the
 // barycentric tests: with U = u det and V = v det the hit is inside when U, V
 // and det - U - V share det's sign. Returns t or -1.
@@ -329,6 +346,8 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
     float best_s = r.smax;        // best arc length
     uint32_t best_id = 0xFFFFFFFFu;
     const float sg = r.sigma;
+    const float3 olo = make_float3(r.o.x + sg, r.o.y + sg, r.o.z + sg);    // curved rays: inflated lower planes
+    const float3 ohi = make_float3(r.o.x - sg, r.o.y - sg, r.o.z - sg);    // and upper planes
     uint32_t cur = 0;
     int sp = 0;
     // entries sp >= DL: private memory (volatile keeps them out of registers)
@@ -346,10 +365,10 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
             float t0, t1, t2, t3;
             bool h0, h1, h2, h3;
             if (ARC) {
-                h0 = slab(r, lx.x - sg, ly.x - sg, lz.x - sg, hx.x + sg, hy.x + sg, hz.x + sg, r.tmin, best_t, t0);
-                h1 = slab(r, lx.y - sg, ly.y - sg, lz.y - sg, hx.y + sg, hy.y + sg, hz.y + sg, r.tmin, best_t, t1);
-                h2 = slab(r, lx.z - sg, ly.z - sg, lz.z - sg, hx.z + sg, hy.z + sg, hz.z + sg, r.tmin, best_t, t2);
-                h3 = slab(r, lx.w - sg, ly.w - sg, lz.w - sg, hx.w + sg, hy.w + sg, hz.w + sg, r.tmin, best_t, t3);
+                h0 = slab_inflated(olo, ohi, r.inv, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r.tmin, best_t, t0);
+                h1 = slab_inflated(olo, ohi, r.inv, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r.tmin, best_t, t1);
+                h2 = slab_inflated(olo, ohi, r.inv, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r.tmin, best_t, t2);
+                h3 = slab_inflated(olo, ohi, r.inv, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r.tmin, best_t, t3);
             } else {
                 h0 = slab(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r.tmin, best_t, t0);
                 h1 = slab(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r.tmin, best_t, t1);

@@ -405,20 +405,24 @@ __global__ void k_mean_residual(const float *__restrict__ basis, const float *__
 //  1. Q on the matrix cores, wave q taking a quarter of the columns c: 16 x
 //     16 x 4 FP32 MFMA steps, A the 16 rows' coefficients (lane l: row l % 16,
 //     coefficient 4 s + l / 16, in registers), B the basis (lane l:
-//     coefficient 4 s + l / 16, column l % 16); lane l ends with Q of rows
-//     4 (l / 16) + i, column l % 16, stored to LDS.
+//     coefficient 4 s + l / 16, column l % 16, generated in registers by a
+//     cosine recurrence); lane l ends with Q of rows 4 (l / 16) + i, column
+//     l % 16, stored to LDS.
 //  2. The rows stream out, each thread taking bins t, t + 256, ... (P of
 //     them); the single-bounce values of all 16 rows are loaded before phase
 //     1, so their latency hides behind the matrix work. Error sums: wave
 //     shuffles, then one LDS slot per wave and row.
 constexpr int PR_ROWS = 16;
 
+// 10 log10(x) from the hardware base-2 logarithm (about one ulp for the
+// normal, positive arguments here: x >= the 1e-11 floor).
+__device__ __forceinline__ float db10(float x) { return 3.01029995663981195f * __log2f(x); }
+
 template <int P>
 __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict__ pred, const float *__restrict__ i1,
                                                         const float *__restrict__ im, const float *__restrict__ gbuf,
                                                         int64_t rows, int nb, float r_min, float r_max,
-                                                        const float *__restrict__ basis, const float *__restrict__ mu,
-                                                        const float *__restrict__ sg,
+                                                        const float *__restrict__ mu, const float *__restrict__ sg,
                                                         const float *__restrict__ mres, float *__restrict__ err,
                                                         float *__restrict__ profile)
 {
@@ -430,7 +434,7 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
     const int pitch = nb + 1;
     const int64_t r0 = (int64_t)blockIdx.x * PR_ROWS;
     const float dr = (r_max - r_min) / nb;
-    const float occ_db = 10.f * log10f(I_FLOOR) + 3.f;
+    const float occ_db = db10(I_FLOOR) + 3.f;
     if (t < PR_ROWS) r1s[t] = (r0 + t < rows) ? first_hit_bin(gbuf, r0 + t, r_min, r_max, dr, nb) : nb;
     // the single-bounce channel of the 16 rows, in flight during phase 1
     float iv[PR_ROWS][P];
@@ -451,15 +455,50 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
     typedef float f4 __attribute__((ext_vector_type(4)));
     const int cq = (nb + 3) / 4;
     const int c_begin = wq * cq, c_end = min(nb, c_begin + cq);
+    // Basis values in registers: C[j][c] = s_j cos(j x_c), x_c = pi (c + 1/2) / nb.
+    // This lane needs j = kq + 4 s at column c: seeds cos(kq x) and cos((kq + 4) x),
+    // then cos((m + 1) 4x + kq x) = 2 cos(4x) cos(m 4x + kq x) - cos((m - 1) 4x + kq x).
+    // The seeds and 4x advance by 16 columns per tile through exact rotations.
+    const float dxc = 3.14159265358979323846f / nb;
+    const float xa = (c_begin + ar + 0.5f) * dxc;
+    float ca, sa, cb, sb, c4, s4, rca, rsa, rcb, rsb, rc4, rs4;
+    sincosf(kq * xa, &sa, &ca);
+    sincosf((kq + 4) * xa, &sb, &cb);
+    sincosf(4.f * xa, &s4, &c4);
+    sincosf(16.f * kq * dxc, &rsa, &rca);
+    sincosf(16.f * (kq + 4) * dxc, &rsb, &rcb);
+    sincosf(64.f * dxc, &rs4, &rc4);
+    const float s0 = sqrtf(1.f / nb), s1 = sqrtf(2.f / nb);
     for (int c0 = c_begin; c0 < c_end; c0 += 16) {
         const int cc = c0 + ar;
-        const int ccl = min(cc, nb - 1);
         float bv[16];
+        {
+            const float r = 2.f * c4;
+            float cm2 = ca, cm1 = cb;
+            bv[0] = ca * (kq == 0 ? s0 : s1);
+            bv[1] = cb * s1;
 #pragma unroll
-        for (int s = 0; s < 16; ++s) bv[s] = basis[(int64_t)(4 * s + kq) * nb + ccl];
+            for (int s = 2; s < 16; ++s) {
+                const float cn = r * cm1 - cm2;
+                bv[s] = cn * s1;
+                cm2 = cm1;
+                cm1 = cn;
+            }
+        }
         f4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 16; ++s) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv[s], d, 0, 0, 0);
+        {   // next tile: rotate the seeds by 16 columns
+            float t = ca * rca - sa * rsa;
+            sa = sa * rca + ca * rsa;
+            ca = t;
+            t = cb * rcb - sb * rsb;
+            sb = sb * rcb + cb * rsb;
+            cb = t;
+            t = c4 * rc4 - s4 * rs4;
+            s4 = s4 * rc4 + c4 * rs4;
+            c4 = t;
+        }
         if (cc < c_end) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) Q[(4 * kq + i) * pitch + cc] = d[i];
@@ -490,12 +529,12 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
             for (int q = 0; q < P; ++q) {
                 const int b = t + 256 * q;
                 if (!rok || b >= nb) continue;
-                const float p1 = 10.f * log10f(iv[rl][q] + I_FLOOR);
+                const float p1 = db10(iv[rl][q] + I_FLOOR);
                 const float res = b >= r1 ? Q[rl * pitch + (b - r1)] : 0.f;
                 const float ph = p1 + res;
                 if (profile) profile[row * nb + b] = ph;
                 if (im) {
-                    const float tr = 10.f * log10f(iv[rl][q] + mv[h][q] + I_FLOOR);
+                    const float tr = db10(iv[rl][q] + mv[h][q] + I_FLOOR);
                     if (tr > occ_db) {
                         const float mr = (b >= r1 && mres) ? mres[b - r1] : 0.f;
                         es += fabsf(ph - tr);
@@ -813,8 +852,8 @@ hipError_t surrogate_profile_errors(const Surrogate *s, const float *pred, const
     const int per = (s->n_bins + 255) / 256;
 #define SONAR_PROFILE(PP)                                                                                        \
     hipLaunchKernelGGL(k_profile_errors<PP>, dim3((unsigned)((rows + PR_ROWS - 1) / PR_ROWS)), dim3(256), lds, st, \
-                       pred, s->s1, im ? s->sm : nullptr, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->basis,     \
-                       s->mu, s->sg, s->mres, err, profile)
+                       pred, s->s1, im ? s->sm : nullptr, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->mu, s->sg, \
+                       s->mres, err, profile)
     if (per <= 1) SONAR_PROFILE(1);
     else if (per <= 2) SONAR_PROFILE(2);
     else if (per <= 4) SONAR_PROFILE(4);
