@@ -203,6 +203,7 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
 
     items = S.lawnmower_batch()
     batch = sonar.Batch(scene, items)
+    batch.detect()
     best, tune_ms = batch.autotune()
     g = batch.graph(best)
     g.launch()
@@ -219,12 +220,14 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     assert scene.status() == 0
     rep_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
     lat = np.concatenate(lat)
+    points = int(batch.counts.sum().item())
     g.close()
     res = {"workload": "256 pings on a lawnmower path over the multipath scene, layouts {64x32,128x64,256x128} x "
-                       "{4,8,16} rays, 3 bounces, gradient; one persistent launch in a HIP graph",
+                       "{4,8,16} rays, 3 bounces, gradient; CA-CFAR (16 train, 4 guard, 4 per beam) in the ping "
+                       "kernel; one graph: queue reset, persistent ping launch, batched point emission",
            "pings": batch.n, "rays": int(batch.plan.total_rays), "replay_ms_median": rep_ms,
            "pings_per_s": batch.n / rep_ms * 1e3, "mrays_per_s": batch.plan.total_rays / rep_ms / 1e3,
-           "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+           "points": points, "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
            "autotuned": {"blocks_per_cu": best.blocks_per_cu, "tiles_per_item": best.tiles_per_item,
                          "ms": tune_ms}}
     del batch

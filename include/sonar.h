@@ -230,14 +230,17 @@ sonar_status sonar_ping_detect(const sonar_scene *scene, const sonar_params *par
 
 /* Host summary of a prepared batch (filled by sonar_batch_prepare). */
 typedef struct {
-    int32_t n_pings, max_bounces, arc, max_bins;
+    int32_t n_pings, max_bounces, arc, max_bins, max_beams, reserved;
     int64_t total_tiles, total_rays;
 } sonar_batch_plan;
 
 /* Launch knobs: persistent workgroups per compute unit (0: the occupancy
- * limit) and 256-ray tiles taken per queue pop (0: 1). */
+ * limit) and 256-ray tiles taken per queue pop (0: 1). `emit_desc`: device
+ * copy of the emission descriptors of sonar_batch_prepare_detect, or NULL
+ * for a batch without detection. */
 typedef struct {
     int32_t blocks_per_cu, tiles_per_item;
+    const void *emit_desc;
 } sonar_batch_options;
 
 typedef struct sonar_graph sonar_graph;   /* an instantiated HIP graph of one batch */
@@ -260,7 +263,28 @@ sonar_status sonar_batch_prepare(const sonar_scene *scene, int32_t n_pings, cons
                                  const sonar_pose *poses, sonar_cf32 *const *volumes, void *host_desc,
                                  sonar_batch_plan *plan);
 
-/* Runs a prepared batch: a reset kernel, then the persistent ping kernel.
+/* Detection for a prepared batch (Sec. II-A: each ping's point cloud):
+ * amends the ping descriptors in `host_desc` (as filled by
+ * sonar_batch_prepare) so that every ping's kernel runs the CA-CFAR test of
+ * sonar_ping_detect on its beams, and fills one emission descriptor per ping
+ * (`host_emit`, n_pings * sonar_batch_emit_desc_bytes() bytes) for the
+ * batched point emission that sonar_ping_batch then runs after the pings.
+ * Per ping i: points[i] with room for capacity[i] points, its point count at
+ * dev_counts[i] (device int32, written by the emission), and a detection
+ * workspace slice of `workspace` (device, sonar_batch_detect_workspace_size
+ * bytes in total). Copy both descriptor arrays to the device again and pass
+ * the emission copy as options->emit_desc. SONAR_E_UNSUPPORTED if some
+ * training-window size has alpha(N) <= 1 (the fused test would then miss
+ * detections in bins without a return). */
+size_t sonar_batch_emit_desc_bytes(void);
+size_t sonar_batch_detect_workspace_size(int32_t n_pings, const sonar_params *params);
+sonar_status sonar_batch_prepare_detect(int32_t n_pings, const sonar_params *params, const sonar_pose *poses,
+                                       const sonar_cfar *cfar, sonar_point *const *points,
+                                       const int32_t *capacity, int32_t *dev_counts, void *workspace,
+                                       size_t workspace_bytes, void *host_desc, void *host_emit);
+
+/* Runs a prepared batch: a reset kernel, the persistent ping kernel, and,
+ * when options->emit_desc is set, one point-emission launch for all pings.
  * `dev_desc` are the descriptors in device memory. Allocates nothing, so it
  * can be captured in a graph. Asynchronous on `stream`. */
 sonar_status sonar_ping_batch(const sonar_scene *scene, const sonar_batch_plan *plan, const void *dev_desc,

@@ -404,6 +404,70 @@ sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, con
 
 size_t sonar_batch_desc_bytes(void) { return sizeof(sonar::PingArgs); }
 
+size_t sonar_batch_emit_desc_bytes(void) { return sizeof(sonar::DetectArgs); }
+
+// Detection workspace of one ping, rounded so that every slice stays aligned.
+static size_t det_slice_bytes(const sonar_params *p)
+{
+    size_t b = sonar_detect_workspace_size(p);
+    return (b + 255) & ~(size_t)255;
+}
+
+size_t sonar_batch_detect_workspace_size(int32_t n, const sonar_params *params)
+{
+    if (n < 1 || !params) return 0;
+    size_t total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const size_t b = det_slice_bytes(&params[i]);
+        if (b == 0) return 0;
+        total += b;
+    }
+    return total;
+}
+
+sonar_status sonar_batch_prepare_detect(int32_t n, const sonar_params *params, const sonar_pose *poses,
+                                       const sonar_cfar *cfar, sonar_point *const *points, const int32_t *capacity,
+                                       int32_t *dev_counts, void *workspace, size_t ws_bytes, void *host_desc,
+                                       void *host_emit)
+{
+    g_err[0] = 0;
+    if (n < 1 || !params || !poses || !cfar || !points || !capacity || !dev_counts || !workspace || !host_desc ||
+        !host_emit)
+        return fail(SONAR_E_INVALID, "all arguments are required (n_pings >= 1)");
+    const size_t need = sonar_batch_detect_workspace_size(n, params);
+    if (need == 0 || ws_bytes < need) return fail(SONAR_E_INVALID, "workspace smaller than sonar_batch_detect_workspace_size()");
+    sonar::PingArgs *d = reinterpret_cast<sonar::PingArgs *>(host_desc);
+    sonar::DetectArgs *em = reinterpret_cast<sonar::DetectArgs *>(host_emit);
+    char *w = reinterpret_cast<char *>(workspace);
+    for (int32_t i = 0; i < n; ++i) {
+        const size_t slice = det_slice_bytes(&params[i]);
+        sonar::DetectArgs da;
+        sonar_status st = fill_detect_args(reinterpret_cast<const sonar_cf32 *>(d[i].volume), &params[i], &poses[i],
+                                           cfar, points[i], capacity[i], dev_counts + i, w, slice, &da);
+        if (st != SONAR_OK) {
+            char tmp[512];
+            snprintf(tmp, sizeof(tmp), "ping %d: %s", i, g_err);
+            return fail(st, "%s", tmp);
+        }
+        if (da.n_beams != d[i].n_beams || da.n_bins != d[i].n_bins)
+            return fail(SONAR_E_INVALID, "ping %d: parameters differ from the prepared batch", i);
+        for (int k = 1; k <= 2 * cfar->train; ++k)
+            if (!(da.alpha[k] > 1.0))
+                return fail(SONAR_E_UNSUPPORTED, "alpha(N) <= 1 for N = %d: use sonar_detect per ping", k);
+        d[i].det_count = da.beam_count;
+        d[i].det_bins = da.beam_bins;
+        d[i].det_pw = da.beam_pw;
+        d[i].det_G = cfar->guard;
+        d[i].det_T = cfar->train;
+        d[i].det_M = cfar->max_per_beam;
+        d[i].det_n0 = (float)cfar->noise_floor;
+        for (int k = 0; k <= 2 * 64; ++k) d[i].det_alpha[k] = da.alpha[k];
+        em[i] = da;
+        w += slice;
+    }
+    return SONAR_OK;
+}
+
 size_t sonar_batch_workspace_size(int32_t n_pings)
 {
     if (n_pings < 1) return 0;
@@ -420,7 +484,7 @@ sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_p
     if (n < 1) return fail(SONAR_E_INVALID, "n_pings must be >= 1");
     sonar::PingArgs *d = reinterpret_cast<sonar::PingArgs *>(host_desc);
     int64_t tiles = 0, rays = 0;
-    int max_bins = 0;
+    int max_bins = 0, max_beams = 0;
     for (int32_t i = 0; i < n; ++i) {
         sonar_status st = fill_ping_args(sc, &params[i], &poses[i], volumes[i], nullptr, nullptr, nullptr, nullptr,
                                          &d[i]);
@@ -438,11 +502,14 @@ sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_p
         tiles += t;
         rays += d[i].n_rays;
         if (d[i].n_bins > max_bins) max_bins = d[i].n_bins;
+        if (d[i].n_beams > max_beams) max_beams = (int)d[i].n_beams;
     }
     plan->n_pings = n;
     plan->max_bounces = params[0].max_bounces;
     plan->arc = params[0].c_grad != 0.0;
     plan->max_bins = max_bins;
+    plan->max_beams = max_beams;
+    plan->reserved = 0;
     plan->total_tiles = tiles;
     plan->total_rays = rays;
     return SONAR_OK;
@@ -472,7 +539,18 @@ static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_p
     b->t1 = b->t0 + plan->n_pings;
     b->blocks_per_cu = opt ? opt->blocks_per_cu : 0;
     b->tiles_per_item = opt && opt->tiles_per_item > 0 ? opt->tiles_per_item : 1;
+    b->emit = opt ? reinterpret_cast<const sonar::DetectArgs *>(opt->emit_desc) : nullptr;
+    b->max_beams = plan->max_beams;
+    if (b->emit && plan->max_beams < 1) return fail(SONAR_E_INVALID, "plan has no beam count (prepare it again)");
     return SONAR_OK;
+}
+
+// The pings of a batch, then its batched point emission when it has one.
+static hipError_t batch_launch_all(const sonar::BatchLaunch &b, hipStream_t s)
+{
+    hipError_t e = sonar::launch_ping_batch(b, s);
+    if (e == hipSuccess && b.emit) e = sonar::launch_emit_batch(b.emit, b.n_pings, b.max_beams, s);
+    return e;
 }
 
 sonar_status sonar_ping_batch(const sonar_scene *sc, const sonar_batch_plan *plan, const void *dev_desc,
@@ -482,7 +560,7 @@ sonar_status sonar_ping_batch(const sonar_scene *sc, const sonar_batch_plan *pla
     sonar::BatchLaunch b;
     sonar_status st = batch_launch_args(sc, plan, dev_desc, opt, ws, ws_bytes, &b);
     if (st != SONAR_OK) return st;
-    hipError_t e = sonar::launch_ping_batch(b, (hipStream_t)stream);
+    hipError_t e = batch_launch_all(b, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "batch launch: %s", hipGetErrorString(e));
     return SONAR_OK;
 }
@@ -519,7 +597,7 @@ sonar_status sonar_batch_graph_create(const sonar_scene *sc, const sonar_batch_p
     }
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = sonar::launch_ping_batch(b, cs);
+        hipError_t le = batch_launch_all(b, cs);
         e = hipStreamEndCapture(cs, &g->graph);
         if (le != hipSuccess) e = le;
     }

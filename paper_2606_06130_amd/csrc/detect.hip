@@ -224,12 +224,12 @@ __global__ __launch_bounds__(64) void k_cfar(DetectArgs a)
     if (lane == 0) a.beam_count[beam] = kept;
 }
 
-__global__ __launch_bounds__(ET) void k_emit(DetectArgs a)
+// Point emission of beam group g (EB beams) of one detection.
+__device__ __forceinline__ void emit_group(const DetectArgs &a, const int g)
 {
     __shared__ int wsum[ET / 64];
     __shared__ int wred[ET / 64];
     const int t = threadIdx.x;
-    const int g = blockIdx.x;
     // offset of this group: all counts of earlier beams (L2-resident int4
     // loads, eight independent ones in flight per thread)
     const int64_t before = (int64_t)g * EB;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(ET) void k_emit(DetectArgs a)
     const int excl = block_scan_excl_int(c, wsum, &total);
     int base = 0;
     for (int q = 0; q < ET / 64; ++q) base += wred[q];
-    if (g == (int)gridDim.x - 1 && t == 0) *a.count = base + total;
+    if ((int64_t)(g + 1) * EB >= a.n_beams && t == 0) *a.count = base + total;     // the last group
     if (t >= EB || c == 0) return;
     const int M = a.max_per_beam;
     // this beam's detections in range order
@@ -300,6 +300,16 @@ __global__ __launch_bounds__(ET) void k_emit(DetectArgs a)
     }
 }
 
+__global__ __launch_bounds__(ET) void k_emit(DetectArgs a) { emit_group(a, blockIdx.x); }
+
+// A batch: grid row y is ping y; groups past a ping's beams have nothing to do.
+__global__ __launch_bounds__(ET) void k_emit_batch(const DetectArgs *__restrict__ desc)
+{
+    const DetectArgs &a = desc[blockIdx.y];
+    if ((int64_t)blockIdx.x * EB >= a.n_beams) return;
+    emit_group(a, blockIdx.x);
+}
+
 size_t detect_workspace_bytes(int n_beams, int max_per_beam)
 {
     size_t nb4 = ((size_t)n_beams + 3) & ~(size_t)3;            // int4-readable counts
@@ -325,6 +335,15 @@ hipError_t launch_detect(const DetectArgs &a, hipStream_t s)
     else SONAR_CFAR(64);
 #undef SONAR_CFAR
     return launch_emit(a, s);
+}
+
+hipError_t launch_emit_batch(const DetectArgs *dev_desc, int n_pings, int max_beams, hipStream_t s)
+{
+    if (n_pings <= 0 || max_beams <= 0) return hipSuccess;
+    if (n_pings > 65535) return hipErrorInvalidValue;      // grid rows
+    hipLaunchKernelGGL(k_emit_batch, dim3((unsigned)((max_beams + EB - 1) / EB), (unsigned)n_pings), dim3(ET), 0, s,
+                       dev_desc);
+    return hipGetLastError();
 }
 
 hipError_t launch_emit(const DetectArgs &a, hipStream_t s)

@@ -91,6 +91,7 @@ struct PingArgs {
 };
 
 // One batch launch: descriptors in device memory, one kernel class.
+struct DetectArgs;
 struct BatchLaunch {
     const PingArgs *desc;
     int n_pings;
@@ -103,6 +104,8 @@ struct BatchLaunch {
     unsigned long long *t0, *t1;
     int blocks_per_cu;       // persistent grid = CUs x this (0: occupancy limit)
     int tiles_per_item;      // tiles popped per queue operation
+    const DetectArgs *emit;  // batched point emission after the pings (nullptr: none)
+    int max_beams;           // largest beam count of the batch (emission grid)
 };
 hipError_t launch_ping_batch(const BatchLaunch &b, hipStream_t s);
 int batch_max_blocks_per_cu(const BatchLaunch &b);
@@ -129,6 +132,8 @@ struct DetectArgs {
 };
 hipError_t launch_detect(const DetectArgs &a, hipStream_t s);
 hipError_t launch_emit(const DetectArgs &a, hipStream_t s);
+// Point emission of a batch: descriptors in device memory, one grid row per ping.
+hipError_t launch_emit_batch(const DetectArgs *dev_desc, int n_pings, int max_beams, hipStream_t s);
 size_t detect_workspace_bytes(int n_beams, int max_per_beam);
 
 // Learned multipath surrogate (surrogate.hip).

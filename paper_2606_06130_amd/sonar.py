@@ -28,7 +28,8 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_status_string", "sonar_last_error", "sonar_params_from_resolution",
            "sonar_batch_desc_bytes", "sonar_batch_workspace_size", "sonar_batch_prepare", "sonar_ping_batch",
            "sonar_batch_stamps", "sonar_batch_graph_create", "sonar_graph_launch", "sonar_graph_free",
-           "sonar_batch_autotune", "sonar_surrogate_param_count", "sonar_surrogate_create",
+           "sonar_batch_autotune", "sonar_batch_emit_desc_bytes", "sonar_batch_detect_workspace_size",
+           "sonar_batch_prepare_detect", "sonar_surrogate_param_count", "sonar_surrogate_create",
            "sonar_surrogate_free", "sonar_surrogate_set_state", "sonar_surrogate_get_state",
            "sonar_surrogate_set_norm", "sonar_surrogate_forward", "sonar_surrogate_train_step",
            "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
@@ -80,11 +81,12 @@ class sonar_scene_info(C.Structure):
 
 class sonar_batch_plan(C.Structure):
     _fields_ = [("n_pings", C.c_int32), ("max_bounces", C.c_int32), ("arc", C.c_int32), ("max_bins", C.c_int32),
-                ("total_tiles", C.c_int64), ("total_rays", C.c_int64)]
+                ("max_beams", C.c_int32), ("reserved", C.c_int32), ("total_tiles", C.c_int64),
+                ("total_rays", C.c_int64)]
 
 
 class sonar_batch_options(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int32), ("tiles_per_item", C.c_int32)]
+    _fields_ = [("blocks_per_cu", C.c_int32), ("tiles_per_item", C.c_int32), ("emit_desc", C.c_void_p)]
 
 
 POINT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("db", "<f4"), ("beam", "<i4"), ("bin", "<i4")])
@@ -142,6 +144,14 @@ def lib():
         L.sonar_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
         L.sonar_graph_free.restype = None
         L.sonar_graph_free.argtypes = [C.c_void_p]
+        L.sonar_batch_emit_desc_bytes.restype = C.c_size_t
+        L.sonar_batch_emit_desc_bytes.argtypes = []
+        L.sonar_batch_detect_workspace_size.restype = C.c_size_t
+        L.sonar_batch_detect_workspace_size.argtypes = [C.c_int32, C.c_void_p]
+        L.sonar_batch_prepare_detect.restype = C.c_int
+        L.sonar_batch_prepare_detect.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, P(sonar_cfar), C.c_void_p,
+                                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                                 C.c_void_p]
         L.sonar_batch_autotune.restype = C.c_int
         L.sonar_batch_autotune.argtypes = [C.c_void_p, P(sonar_batch_plan), C.c_void_p, C.c_void_p, C.c_size_t,
                                            C.c_void_p, P(sonar_batch_options), P(C.c_float)]
@@ -401,12 +411,42 @@ class Batch:
         host = np.zeros(n * db, np.uint8)
         self.plan = sonar_batch_plan()
         _check(lib().sonar_batch_prepare(scene.handle, n, P, Q, V, host.ctypes.data, C.byref(self.plan)))
+        self._host, self._P, self._Q = host, P, Q
         self.desc = torch.from_numpy(host).cuda()
         self.workspace = torch.empty(lib().sonar_batch_workspace_size(n), dtype=torch.uint8, device="cuda")
         self.n = n
+        self.emit = None
+
+    def detect(self, train=16, guard=4, max_per_beam=4, pfa=1e-4, noise_floor=1e-11):
+        """Adds the point cloud of every ping: the CA-CFAR test in each ping's
+        kernel and one batched emission after the pings (also in graphs)."""
+        import torch
+        n = self.n
+        cf = sonar_cfar(train=train, guard=guard, max_per_beam=max_per_beam, pad=0, pfa=pfa, noise_floor=noise_floor)
+        caps = [max(1, v.shape[0] * v.shape[1] * max_per_beam) for v in self.volumes]
+        self.points = [torch.empty((c, 6), dtype=torch.int32, device="cuda") for c in caps]
+        self.counts = torch.zeros(n, dtype=torch.int32, device="cuda")
+        nbytes = lib().sonar_batch_detect_workspace_size(n, self._P)
+        if nbytes == 0:
+            _check(SONAR_E_INVALID)
+        self.det_workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        PT = (C.c_void_p * n)(*[p.data_ptr() for p in self.points])
+        CAP = (C.c_int32 * n)(*caps)
+        emit = np.zeros(n * lib().sonar_batch_emit_desc_bytes(), np.uint8)
+        _check(lib().sonar_batch_prepare_detect(n, self._P, self._Q, C.byref(cf), PT, CAP, _dptr(self.counts),
+                                                _dptr(self.det_workspace), self.det_workspace.numel(),
+                                                self._host.ctypes.data, emit.ctypes.data))
+        self.desc = torch.from_numpy(self._host).cuda()
+        self.emit = torch.from_numpy(emit).cuda()
+
+    def point_cloud(self, i):
+        """Points of ping i after a run (synchronises)."""
+        c = int(self.counts[i].item())
+        return self.points[i][:min(c, self.points[i].shape[0])].cpu().numpy().view(POINT_DTYPE).reshape(-1), c
 
     def options(self, blocks_per_cu=0, tiles_per_item=0):
-        return sonar_batch_options(blocks_per_cu=blocks_per_cu, tiles_per_item=tiles_per_item)
+        return sonar_batch_options(blocks_per_cu=blocks_per_cu, tiles_per_item=tiles_per_item,
+                                   emit_desc=self.emit.data_ptr() if self.emit is not None else None)
 
     def run(self, options=None, stream=None):
         o = options if options is not None else self.options()
@@ -421,12 +461,14 @@ class Batch:
         return Graph(h)
 
     def autotune(self, stream=None):
+        """Fastest launch knobs for the pings (timed without the emission);
+        returns options that include this batch's emission if it has one."""
         best = sonar_batch_options()
         ms = C.c_float()
         _check(lib().sonar_batch_autotune(self.scene.handle, C.byref(self.plan), _dptr(self.desc),
                                           _dptr(self.workspace), self.workspace.numel(), _stream(stream),
                                           C.byref(best), C.byref(ms)))
-        return best, float(ms.value)
+        return self.options(best.blocks_per_cu, best.tiles_per_item), float(ms.value)
 
     def stamps(self, stream=None):
         """(start, finish) device clock stamps per ping, 100 MHz ticks."""

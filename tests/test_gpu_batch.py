@@ -131,3 +131,65 @@ def test_batch_rejects_mixed_physics():
     with pytest.raises(sonar.SonarError) as e:
         sonar.Batch(sc, items)
     assert e.value.status == sonar.SONAR_E_INVALID
+
+
+@pytest.mark.parametrize("physics", ["single", "multipath_gradient"])
+def test_batch_detection_equals_individual_ping_detect(physics):
+    """Batched pings with the fused CFAR test and one batched emission give,
+    per ping, the volume and the point cloud of sonar_ping_detect on its own;
+    graph replays repeat them with eager work in between."""
+    torch, sonar = _gpu()
+    mesh = S.scene_seabed_boxes()
+    base = S.sensor_seabed_boxes()
+    if physics == "multipath_gradient":
+        base = base.replace(max_bounces=2, k_d=0.7, k_s=0.3, c_grad=0.05, n_range=512)
+    sc = sonar.Scene(mesh)
+    items = _mixed_items(base, 17, 5)
+    M = 3
+    batch = sonar.Batch(sc, items)
+    batch.detect(train=8, guard=2, max_per_beam=M)
+    want = []
+    for cfg, pose in items:
+        det = sonar.Detector(cfg, train=8, guard=2, max_per_beam=M)
+        vol = sonar.alloc_outputs(cfg)["volume"]
+        det.ping_detect(sc, vol, pose)
+        pts, cnt = det.fetch()
+        want.append((vol.clone(), pts.copy(), cnt))
+    total = sum(w[2] for w in want)
+    assert total > 0
+    _log(physics, "points per ping", [w[2] for w in want])
+
+    def check(tag):
+        for i, (vol, pts, cnt) in enumerate(want):
+            assert torch.equal(batch.volumes[i].view(torch.float32), vol.view(torch.float32)), (tag, i)
+            got, c = batch.point_cloud(i)
+            assert c == cnt, (tag, i, c, cnt)
+            assert np.array_equal(got, pts), (tag, i)
+
+    batch.run(batch.options(blocks_per_cu=2, tiles_per_item=2))
+    torch.cuda.synchronize()
+    assert sc.status() == 0
+    check("direct")
+    g = batch.graph()
+    for rep in range(3):
+        for v in batch.volumes:
+            v.fill_(complex(float("nan"), 0.0))
+        for p in batch.points:
+            p.fill_(-7)
+        batch.counts.fill_(-1)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        check(f"replay {rep}")
+    g.close()
+
+
+def test_batch_detection_rejects_mismatched_parameters():
+    torch, sonar = _gpu()
+    sc = sonar.Scene(S.scene_seabed_boxes())
+    items = _mixed_items(S.sensor_seabed_boxes(), 4, 2)
+    batch = sonar.Batch(sc, items)
+    batch._P[1].n_h += 1          # no longer the layout the descriptors were prepared for
+    with pytest.raises(sonar.SonarError) as e:
+        batch.detect()
+    assert e.value.status == sonar.SONAR_E_INVALID
