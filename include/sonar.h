@@ -162,8 +162,9 @@ typedef struct {
  * triangle centroids, radix sort, binary radix tree, bottom-up bounds, then
  * 4-wide nodes from every second binary level).
  * Synchronous on `stream`. Returns SONAR_E_INVALID for null pointers,
- * n_triangles < 1, indices out of range or non-finite vertices (checked on
- * the device, reported after the build's synchronisation). */
+ * n_triangles < 1 or >= 2^28, indices out of range or non-finite vertices
+ * (checked on the device, reported after the build's synchronisation), and
+ * SONAR_E_UNSUPPORTED for a hierarchy of more than 2^25 4-wide nodes. */
 sonar_status sonar_build_scene(const sonar_mesh *mesh, sonar_stream stream, sonar_scene **out);
 
 /* Frees a scene (NULL is ignored). The caller guarantees no call using it is

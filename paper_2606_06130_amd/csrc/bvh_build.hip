@@ -759,6 +759,10 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     }
     const bool single = n4 == 0;
     if (single) n4 = 1;
+    if (n4 > (1 << 25)) {      // traversal addresses nodes by 32-bit byte offsets
+        snprintf(err, errlen, "hierarchy of %d nodes: at most 2^25 are supported", n4);
+        return SONAR_E_UNSUPPORTED;
+    }
     float4 *nodes = nullptr;
     if (hipMalloc(&nodes, sizeof(float4) * 8 * (size_t)n4) != hipSuccess) {
         snprintf(err, errlen, "out of device memory for the scene");

@@ -81,15 +81,27 @@ __device__ __forceinline__ uint64_t splitmix64_nth(uint64_t seed, uint64_t n)
     return z ^ (z >> 31);
 }
 
+// Scene arrays as global-memory pointers: a pointer read from a batch
+// descriptor is otherwise generic and its loads become flat loads.
+typedef float f4v __attribute__((ext_vector_type(4)));
+using gchar = __attribute__((address_space(1))) const char;
+__device__ __forceinline__ gchar *as_global(const float4 *p) { return (gchar *)p; }
+__device__ __forceinline__ float4 ldg4(gchar *p)
+{
+    const f4v v = *(__attribute__((address_space(1))) const f4v *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Triangle record -> vertices, id bits.
 struct TriF {
     float3 v0, v1, v2;
     uint32_t idbits;
     float rho, phi;
 };
-__device__ __forceinline__ TriF load_tri(const float4 *__restrict__ tris, uint32_t i)
+__device__ __forceinline__ TriF load_tri(gchar *__restrict__ tris, uint32_t i)
 {
-    float4 a = tris[3 * (size_t)i], b = tris[3 * (size_t)i + 1], c = tris[3 * (size_t)i + 2];
+    gchar *r = tris + 48 * (size_t)i;
+    const float4 a = ldg4(r), b = ldg4(r + 16), c = ldg4(r + 32);
     TriF t;
     t.v0 = make_float3(a.x, a.y, a.z);
     t.v1 = make_float3(a.w, b.x, b.y);
@@ -211,33 +223,53 @@ __device__ __forceinline__ Seg32 make_seg(const Path64 &p, double smin, double s
     return g;
 }
 
-// Slab test of one box against [tmin, tmax]; the far distance is widened by
-// 5e-7 relative so that FP32 rounding never rejects a box the exact ray meets.
-__device__ __forceinline__ bool slab(const Seg32 &r, float lx, float ly, float lz, float hx, float hy, float hz,
-                                     float tmin, float tmax, float &tnear)
+// Per-traversal constants of the slab test. For each axis the plane a ray
+// enters first (near) is the lower one when the inverse direction is >= 0,
+// else the upper one; the node stores lower and upper planes of an axis in
+// adjacent 16-byte rows, so the near and far rows are picked by a per-lane
+// byte offset and no min/max per axis is needed. A plane distance is one FMA,
+// t = p * inv + c, with c = -(o * inv) rounded and then widened by 2^-21 |o *
+// inv| (eight roundings of the product): every near distance comes out no
+// later and every far distance no earlier than with exact arithmetic on
+// these operands, which amounts to growing the box by 2^-21 |o| along each
+// axis. Curved rays test the box inflated by the sagitta s: lower planes
+// against o + s, upper planes against o - s.
+struct SlabRay {
+    float3 inv, cn, cf;       // inverse direction, near and far constants
+    uint32_t ox, oy, oz;      // byte offsets of the near rows (far row: offset ^ 16)
+};
+
+__device__ __forceinline__ void slab_axis(float o, float s, float inv, uint32_t base, uint32_t &off, float &cn,
+                                          float &cf)
 {
-    float x0 = (lx - r.o.x) * r.inv.x, x1 = (hx - r.o.x) * r.inv.x;
-    float y0 = (ly - r.o.y) * r.inv.y, y1 = (hy - r.o.y) * r.inv.y;
-    float z0 = (lz - r.o.z) * r.inv.z, z1 = (hz - r.o.z) * r.inv.z;
-    float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
-    float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmax));
-    tnear = tn;
-    return tn <= tf * 1.0000005f;
+    const bool neg = __float_as_uint(inv) >> 31;
+    off = base | (neg ? 16u : 0u);
+    const float on = neg ? o - s : o + s, of = neg ? o + s : o - s;
+    const float an = on * inv, af = of * inv;
+    cn = -an - fabsf(an) * 0x1p-21f;
+    cf = -af + fabsf(af) * 0x1p-21f;
 }
 
-// Slab test of a box inflated by the sagitta s on every side, with the
-// inflation folded into two shifted origins: lower planes against o + s,
-// upper planes against o - s (as many operations as the plain test; the
-// rounding of o +- s stays inside the sagitta's own FP32 margin).
-__device__ __forceinline__ bool slab_inflated(const float3 &olo, const float3 &ohi, const float3 &inv, float lx,
-                                              float ly, float lz, float hx, float hy, float hz, float tmin,
-                                              float tmax, float &tnear)
+__device__ __forceinline__ SlabRay slab_ray(const float3 &o, const float3 &inv, float sigma)
 {
-    float x0 = (lx - olo.x) * inv.x, x1 = (hx - ohi.x) * inv.x;
-    float y0 = (ly - olo.y) * inv.y, y1 = (hy - ohi.y) * inv.y;
-    float z0 = (lz - olo.z) * inv.z, z1 = (hz - ohi.z) * inv.z;
-    float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
-    float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmax));
+    SlabRay q;
+    q.inv = inv;
+    slab_axis(o.x, sigma, inv.x, 0u, q.ox, q.cn.x, q.cf.x);
+    slab_axis(o.y, sigma, inv.y, 32u, q.oy, q.cn.y, q.cf.y);
+    slab_axis(o.z, sigma, inv.z, 64u, q.oz, q.cn.z, q.cf.z);
+    return q;
+}
+
+// One child box against [tmin, tmax] from its near and far planes; the far
+// distance is widened by 5e-7 relative for the rounding of the FMA results
+// and of the inverse direction.
+__device__ __forceinline__ bool slab(const SlabRay &q, float nx, float ny, float nz, float fx, float fy, float fz,
+                                     float tmin, float tmax, float &tnear)
+{
+    const float tn = fmaxf(fmaxf(fmaf(nx, q.inv.x, q.cn.x), fmaf(ny, q.inv.y, q.cn.y)),
+                           fmaxf(fmaf(nz, q.inv.z, q.cn.z), tmin));
+    const float tf = fminf(fminf(fmaf(fx, q.inv.x, q.cf.x), fmaf(fy, q.inv.y, q.cf.y)),
+                           fminf(fmaf(fz, q.inv.z, q.cf.z), tmax));
     tnear = tn;
     return tn <= tf * 1.0000005f;
 }
@@ -336,7 +368,7 @@ __device__ __forceinline__ void order2(float &ta, uint32_t &la, float &tb, uint3
 // the others farthest first; leaves test their triangles. The stack keeps
 // its bottom DL entries of each lane in LDS, deeper ones in private memory.
 template <int DEPTH, int DL, bool ANY, bool ARC, bool STATS>
-__device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restrict__ tris, const Seg32 &r,
+__device__ int traverse(gchar *__restrict__ nodes, gchar *__restrict__ tris, const Seg32 &r,
                         uint32_t skip, uint32_t *__restrict__ stk, int lane, bool &overflow, float &s_out,
                         uint32_t max_steps, uint32_t &n_nodes, uint32_t &n_tris, uint32_t &n_deep)
 {
@@ -346,8 +378,7 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
     float best_s = r.smax;        // best arc length
     uint32_t best_id = 0xFFFFFFFFu;
     const float sg = r.sigma;
-    const float3 olo = make_float3(r.o.x + sg, r.o.y + sg, r.o.z + sg);    // curved rays: inflated lower planes
-    const float3 ohi = make_float3(r.o.x - sg, r.o.y - sg, r.o.z - sg);    // and upper planes
+    const SlabRay q = slab_ray(r.o, r.inv, sg);
     uint32_t cur = 0;
     int sp = 0;
     // entries sp >= DL: private memory (volatile keeps them out of registers)
@@ -360,21 +391,20 @@ __device__ int traverse(const float4 *__restrict__ nodes, const float4 *__restri
         }
         if (!(cur & LEAF_BIT)) {
             if (STATS) ++n_nodes;
-            const float4 *n = nodes + 8 * (size_t)cur;
-            const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], lk = n[6];
+            // 32-bit byte offsets into the node array (at most 2^25 nodes)
+            const uint32_t at = cur << 7, nx_at = at | q.ox, ny_at = at | q.oy, nz_at = at | q.oz;
+            const float4 nx = ldg4(nodes + nx_at);
+            const float4 fx = ldg4(nodes + (nx_at ^ 16u));
+            const float4 ny = ldg4(nodes + ny_at);
+            const float4 fy = ldg4(nodes + (ny_at ^ 16u));
+            const float4 nz = ldg4(nodes + nz_at);
+            const float4 fz = ldg4(nodes + (nz_at ^ 16u));
+            const float4 lk = ldg4(nodes + (at | 96u));
             float t0, t1, t2, t3;
-            bool h0, h1, h2, h3;
-            if (ARC) {
-                h0 = slab_inflated(olo, ohi, r.inv, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r.tmin, best_t, t0);
-                h1 = slab_inflated(olo, ohi, r.inv, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r.tmin, best_t, t1);
-                h2 = slab_inflated(olo, ohi, r.inv, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r.tmin, best_t, t2);
-                h3 = slab_inflated(olo, ohi, r.inv, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r.tmin, best_t, t3);
-            } else {
-                h0 = slab(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r.tmin, best_t, t0);
-                h1 = slab(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r.tmin, best_t, t1);
-                h2 = slab(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r.tmin, best_t, t2);
-                h3 = slab(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r.tmin, best_t, t3);
-            }
+            const bool h0 = slab(q, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, r.tmin, best_t, t0);
+            const bool h1 = slab(q, nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, r.tmin, best_t, t1);
+            const bool h2 = slab(q, nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, r.tmin, best_t, t2);
+            const bool h3 = slab(q, nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, r.tmin, best_t, t3);
             float ta = h0 ? t0 : MISS, tb = h1 ? t1 : MISS, tc = h2 ? t2 : MISS, td = h3 ? t3 : MISS;
             uint32_t la = __float_as_uint(lk.x), lb = __float_as_uint(lk.y), lc = __float_as_uint(lk.z),
                      ld = __float_as_uint(lk.w);
@@ -602,10 +632,10 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                     const Seg32 seg = make_seg(path, EPS_SELF, s_lim * (1.0 + 1e-6));
                     float sf;
                     // in a gradient a vertical ray is a degenerate arc (kappa = 0)
-                    int ti = traverse<DEPTH, DL, false, ARC, STATS>(a.nodes, a.tris, seg, prev, W, lane, overflow, sf,
+                    int ti = traverse<DEPTH, DL, false, ARC, STATS>(as_global(a.nodes), as_global(a.tris), seg, prev, W, lane, overflow, sf,
                                                          a.max_steps, st_nodes, st_tris, st_deep);
                     if (ti >= 0) {
-                        TriF tr = load_tri(a.tris, (uint32_t)ti);
+                        TriF tr = load_tri(as_global(a.tris), (uint32_t)ti);
                         d3 nh;
                         double s = refine64(tr, path, (double)sf, nh);
                         double tau = ARC ? path_time(path, s, a.g, a.c0) : s / a.c0;
@@ -707,7 +737,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                                     ARC ? make_path(X, w, a.g, a.c0) : Path64{X, w, mk3(0, 0, 0), 0.0, false};
                                 const Seg32 cs = make_seg(cp, EPS_SELF, L_back - EPS_SELF);
                                 float sa2;
-                                int hb = traverse<DEPTH, DL, true, ARC, STATS>(a.nodes, a.tris, cs, id, W, lane, overflow, sa2,
+                                int hb = traverse<DEPTH, DL, true, ARC, STATS>(as_global(a.nodes), as_global(a.tris), cs, id, W, lane, overflow, sa2,
                                                                     a.max_steps, st_nodes, st_tris, st_deep);
                                 if (hb >= 0) {
                                     vis = false;
@@ -953,7 +983,8 @@ void k_ping(PingArgs a, int wave_words)
 // arguments); layouts, rays per beam, poses and outputs come per ping from
 // its descriptor.
 template <int DEPTH, int K, bool ARC>
-__global__ __launch_bounds__(BLOCK) void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
+__global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(ping_waves_per_eu<K, ARC>())))
+void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
                                                       uint32_t *__restrict__ queue, unsigned long long *__restrict__ t0,
                                                       unsigned long long *__restrict__ t1, int wave_words,
                                                       int tiles_per_item)
@@ -967,7 +998,7 @@ __global__ __launch_bounds__(BLOCK) void k_ping_batch(const PingArgs *__restrict
     while (true) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);     // uniform: descriptor fields in SGPRs
         __syncthreads();
         if (item >= n_items) break;
         for (int q = 0; q < tiles_per_item; ++q) {
