@@ -420,14 +420,25 @@ __device__ int traverse(gchar *__restrict__ nodes, gchar *__restrict__ tris, con
                     best = -1;
                     break;
                 }
-                const uint32_t lp[3] = {ld, lc, lb};
-                const float tp[3] = {td, tc, tb};
+                // the np links to push, farthest first, are the last np of (ld, lc, lb)
+                const uint32_t p0 = np == 3 ? ld : (np == 2 ? lc : lb);
+                const uint32_t p1 = np == 3 ? lc : lb;
+                if (sp + 3 <= DL) {
+                    // common case: three LDS slots written unconditionally
+                    // (entries past the new top are never read)
+                    stk[sp * WAVE + lane] = p0;
+                    stk[(sp + 1) * WAVE + lane] = p1;
+                    stk[(sp + 2) * WAVE + lane] = lb;
+                    sp += np;
+                } else {
+                    const uint32_t lp[3] = {p0, p1, lb};
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    if (tp[q] != MISS) {
-                        if (DL == DEPTH || sp < DL) stk[sp * WAVE + lane] = lp[q];
-                        else spill[sp - DL] = lp[q];
-                        ++sp;
+                    for (int q = 0; q < 3; ++q) {
+                        if (q < np) {
+                            if (DL == DEPTH || sp < DL) stk[sp * WAVE + lane] = lp[q];
+                            else spill[sp - DL] = lp[q];
+                            ++sp;
+                        }
                     }
                 }
                 if (STATS) n_deep = max(n_deep, (uint32_t)sp);

@@ -462,3 +462,29 @@ def test_tiny_scenes(n_tri, leaf):
     assert_parity(res)
     assert res["energy"] > 0
     assert len(set(g["tri"][:, 0].tolist()) - {-1}) >= min(n_tri, 2)     # several triangles are seen
+
+
+def test_axis_aligned_boxes_along_axes_offset_scene():
+    """Axis-aligned boxes seen with an unrotated sensor on the LiDAR grid, so
+    that the centre row and column of rays have exactly zero direction
+    components (slab distances of +-1e30 on those axes), with scene and sensor
+    moved far from the origin (the slab test's rounding bound grows with the
+    origin's coordinates)."""
+    torch, sonar = _gpu()
+    off = np.array([256.0, -128.0, 64.0])
+    parts = []
+    for k, (cx, cy, z0, ex, ey, ez) in enumerate([(4.0, 0.3, -1.7, 0.5, 1.5, 1.2), (6.0, -1.1, -0.9, 1.0, 1.0, 1.6),
+                                                   (8.5, 0.0, -2.5, 1.0, 4.0, 3.5), (5.0, 2.2, 0.4, 0.6, 0.8, 0.9),
+                                                   (11.0, -3.0, -4.0, 2.0, 6.5, 7.0)]):
+        v, t = S._box(cx + off[0], cy + off[1], z0 + off[2], ex, ey, ez)
+        parts.append(M.mesh_from(v[t], rho=0.3 + 0.1 * k, phi=0.2 * k))
+    mesh = M.concat(*parts)
+    mesh.name = "aabb_offset"
+    cfg = S.SensorConfig(n_h=16, n_v=8, rays_per_beam=1, grid_mode=1, jitter=0, n_range=512,
+                         hfov=math.radians(60.0), vfov=math.radians(30.0))
+    pose = S.pose(tuple(off))
+    assert pose.rot == (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0)
+    res, g, _ = run_parity(mesh, cfg, pose)
+    assert_parity(res)
+    centre = 4 * 17 + 8                      # el = 0, az = 0: direction (1, 0, 0) exactly
+    assert g["tri"][centre, 0] >= 0
