@@ -223,6 +223,43 @@ sonar_status sonar_ping_detect(const sonar_scene *scene, const sonar_params *par
                                int32_t *dev_count, void *workspace, size_t workspace_bytes, sonar_stream stream);
 
 /* ---------------------------------------------------------------------- */
+/* Time series and matched filtering (Sec. II-B: time-series data next to the
+ * intensity volumes, so that matched filtering can be applied). A beam's
+ * complex range column x[n] is read as the scene's impulse response sampled
+ * at the bins' two-way delay spacing dt = 2 dr / c_ref (dr the bin width,
+ * c_ref the sound speed at the sensor); p[0..L-1] is the transmitted baseband
+ * pulse at that spacing. */
+
+#define SONAR_MAX_PULSE_TAPS 64
+#define SONAR_MAX_PULSE_BINS 2048
+
+/* Baseband linear-FM pulse of bandwidth B over `duration`:
+ * L = max(1, round(duration / dt)) samples at t_k = (k + 1/2) dt - L dt / 2,
+ * p[k] = w[k] exp(i pi (B / duration) t_k^2), with w = 1 (window 0) or
+ * w[k] = sin^2(pi (k + 1/2) / L) (window 1, Hann).
+ *   taps  host sonar_cf32 [max_len]; *len receives L
+ * SONAR_E_INVALID for bandwidth < 0, duration <= 0, dt <= 0, another window,
+ * null pointers, or L above max_len or SONAR_MAX_PULSE_TAPS. Host only. */
+sonar_status sonar_lfm_pulse(double bandwidth_hz, double duration_s, double dt_s, int32_t window, sonar_cf32 *taps,
+                             int32_t max_len, int32_t *len);
+
+/* Pulse compression of n_beams complex columns of n_bins samples each:
+ *   series[b][n]  = sum_{k<L} p[k] x[b][n-k]
+ *   matched[b][n] = sum_{k<L} conj(p[k]) series[b][n+k]
+ * with x and series zero outside [0, n_bins) (records of n_bins samples).
+ *   volume   device complex64 [n_beams][n_bins], e.g. a ping's volume
+ *   pulse    host complex64 [pulse_len], 1 <= pulse_len <= SONAR_MAX_PULSE_TAPS;
+ *            copied into the launch, so the call allocates nothing and can be
+ *            captured in a graph
+ *   series   optional device complex64 [n_beams][n_bins]
+ *   matched  optional device complex64 [n_beams][n_bins]
+ * At least one output; the outputs must not overlap the input or each other.
+ * 1 <= n_bins <= SONAR_MAX_PULSE_BINS, 0 <= n_beams < 2^31 (0: nothing).
+ * Asynchronous on `stream`. */
+sonar_status sonar_pulse_compress(const sonar_cf32 *volume, int64_t n_beams, int32_t n_bins, const sonar_cf32 *pulse,
+                                  int32_t pulse_len, sonar_cf32 *series, sonar_cf32 *matched, sonar_stream stream);
+
+/* ---------------------------------------------------------------------- */
 /* Batches: hundreds of pings with their own poses, beam layouts and rays per
  * beam in one persistent launch. Work items are (ping, tile of 256 rays);
  * persistent workgroups pop them from one device counter. All pings of a

@@ -402,6 +402,70 @@ sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, con
 }
 
 
+static_assert(SONAR_MAX_PULSE_TAPS == sonar::MAX_PULSE_TAPS, "pulse tap bound");
+static_assert(SONAR_MAX_PULSE_BINS == sonar::MAX_PULSE_BINS, "pulse bin bound");
+
+sonar_status sonar_lfm_pulse(double bandwidth_hz, double duration_s, double dt_s, int32_t window, sonar_cf32 *taps,
+                             int32_t max_len, int32_t *len)
+{
+    g_err[0] = 0;
+    if (!taps || !len) return fail(SONAR_E_INVALID, "taps and len are required");
+    if (!(bandwidth_hz >= 0.0) || !(duration_s > 0.0) || !(dt_s > 0.0) || (window != 0 && window != 1))
+        return fail(SONAR_E_INVALID, "need bandwidth >= 0, duration > 0, dt > 0, window 0 or 1");
+    const double q = duration_s / dt_s;
+    if (!(q < 1e9)) return fail(SONAR_E_INVALID, "duration / dt too large");
+    int L = (int)llround(q);
+    if (L < 1) L = 1;
+    if (L > SONAR_MAX_PULSE_TAPS || L > max_len)
+        return fail(SONAR_E_INVALID, "pulse of %d taps: at most %d (and max_len %d)", L, SONAR_MAX_PULSE_TAPS, max_len);
+    const double rate = bandwidth_hz / duration_s, pi = 3.14159265358979323846;
+    for (int k = 0; k < L; ++k) {
+        const double t = (k + 0.5) * dt_s - 0.5 * L * dt_s;
+        const double sw = sin(pi * (k + 0.5) / L);
+        const double w = window == 0 ? 1.0 : sw * sw;
+        const double ph = pi * rate * t * t;
+        taps[k].re = (float)(w * cos(ph));
+        taps[k].im = (float)(w * sin(ph));
+    }
+    *len = L;
+    return SONAR_OK;
+}
+
+static bool ranges_overlap(const void *a, const void *b, size_t bytes)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+sonar_status sonar_pulse_compress(const sonar_cf32 *volume, int64_t n_beams, int32_t n_bins, const sonar_cf32 *pulse,
+                                  int32_t pulse_len, sonar_cf32 *series, sonar_cf32 *matched, sonar_stream stream)
+{
+    g_err[0] = 0;
+    if (!volume || !pulse) return fail(SONAR_E_INVALID, "volume and pulse are required");
+    if (!series && !matched) return fail(SONAR_E_INVALID, "at least one of series and matched is required");
+    if (n_beams < 0 || n_beams >= ((int64_t)1 << 31)) return fail(SONAR_E_INVALID, "n_beams must be in [0, 2^31)");
+    if (n_bins < 1 || n_bins > SONAR_MAX_PULSE_BINS)
+        return fail(SONAR_E_INVALID, "n_bins must be in [1, %d]", SONAR_MAX_PULSE_BINS);
+    if (pulse_len < 1 || pulse_len > SONAR_MAX_PULSE_TAPS)
+        return fail(SONAR_E_INVALID, "pulse_len must be in [1, %d]", SONAR_MAX_PULSE_TAPS);
+    const size_t bytes = (size_t)n_beams * (size_t)n_bins * sizeof(sonar_cf32);
+    if ((series && ranges_overlap(series, volume, bytes)) || (matched && ranges_overlap(matched, volume, bytes)) ||
+        (series && matched && ranges_overlap(series, matched, bytes)))
+        return fail(SONAR_E_INVALID, "outputs overlap the input or each other");
+    sonar::PulseArgs a;
+    a.x = reinterpret_cast<const float2 *>(volume);
+    a.s = reinterpret_cast<float2 *>(series);
+    a.y = reinterpret_cast<float2 *>(matched);
+    a.n_beams = n_beams;
+    a.n_bins = n_bins;
+    a.L = pulse_len;
+    for (int k = 0; k < sonar::MAX_PULSE_TAPS; ++k)
+        a.p[k] = k < pulse_len ? make_float2(pulse[k].re, pulse[k].im) : make_float2(0.f, 0.f);
+    hipError_t e = sonar::launch_pulse(a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "pulse compression launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
 size_t sonar_batch_desc_bytes(void) { return sizeof(sonar::PingArgs); }
 
 size_t sonar_batch_emit_desc_bytes(void) { return sizeof(sonar::DetectArgs); }

@@ -136,6 +136,19 @@ hipError_t launch_emit(const DetectArgs &a, hipStream_t s);
 hipError_t launch_emit_batch(const DetectArgs *dev_desc, int n_pings, int max_beams, hipStream_t s);
 size_t detect_workspace_bytes(int n_beams, int max_per_beam);
 
+// Pulse compression (pulse.hip): series and matched output of complex columns.
+constexpr int MAX_PULSE_TAPS = 64;
+constexpr int MAX_PULSE_BINS = 2048;
+struct PulseArgs {
+    const float2 *x;         // [n_beams][n_bins]
+    float2 *s;               // series, or nullptr
+    float2 *y;               // matched output, or nullptr
+    int64_t n_beams;
+    int n_bins, L;
+    float2 p[MAX_PULSE_TAPS];
+};
+hipError_t launch_pulse(const PulseArgs &a, hipStream_t s);
+
 // Learned multipath surrogate (surrogate.hip).
 struct Surrogate;
 hipError_t surrogate_create(int64_t max_rows, int n_bins, float r_min, float r_max, int smooth, Surrogate **out);

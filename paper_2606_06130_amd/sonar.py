@@ -33,7 +33,7 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_free", "sonar_surrogate_set_state", "sonar_surrogate_get_state",
            "sonar_surrogate_set_norm", "sonar_surrogate_forward", "sonar_surrogate_train_step",
            "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
-           "sonar_surrogate_profile")
+           "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress")
 
 
 class SonarError(RuntimeError):
@@ -187,6 +187,12 @@ def lib():
                                               C.c_void_p, C.c_void_p, C.c_void_p]
         L.sonar_params_from_resolution.restype = C.c_int
         L.sonar_params_from_resolution.argtypes = [C.c_double] * 7 + [P(sonar_params)]
+        L.sonar_lfm_pulse.restype = C.c_int
+        L.sonar_lfm_pulse.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32,
+                                      P(C.c_int32)]
+        L.sonar_pulse_compress.restype = C.c_int
+        L.sonar_pulse_compress.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                           C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -369,6 +375,42 @@ def params_from_resolution(hfov, vfov, dth_h, dth_v, r_min, r_max, dr, base=None
     p = base if base is not None else sonar_params()
     _check(lib().sonar_params_from_resolution(hfov, vfov, dth_h, dth_v, r_min, r_max, dr, C.byref(p)))
     return p
+
+
+MAX_PULSE_TAPS = 64
+
+
+def pulse_dt(cfg, pose) -> float:
+    """Two-way delay spacing of the range bins: 2 dr / c(z_sensor)."""
+    dr = (cfg.r_max - cfg.r_min) / cfg.n_range
+    return 2.0 * dr / (cfg.c0 + cfg.c_grad * float(pose.position[2]))
+
+
+def lfm_pulse(bandwidth_hz: float, duration_s: float, dt_s: float, window: int = 0) -> np.ndarray:
+    """Baseband linear-FM pulse sampled at dt (complex64), from the library."""
+    taps = np.zeros(MAX_PULSE_TAPS, np.complex64)
+    n = C.c_int32()
+    _check(lib().sonar_lfm_pulse(float(bandwidth_hz), float(duration_s), float(dt_s), int(window), taps.ctypes.data,
+                                 MAX_PULSE_TAPS, C.byref(n)))
+    return taps[:n.value].copy()
+
+
+def pulse_compress(volume, pulse, series=True, matched=True, out=None, stream=None):
+    """Time series and matched-filter output of every beam column of a
+    complex volume [..., n_bins] for a baseband pulse (complex taps)."""
+    import torch
+    n_bins = int(volume.shape[-1])
+    n_beams = int(volume.numel() // max(n_bins, 1))
+    p = np.ascontiguousarray(np.asarray(pulse, np.complex64))
+    out = dict(out or {})
+    if series and "series" not in out:
+        out["series"] = torch.empty_like(volume)
+    if matched and "matched" not in out:
+        out["matched"] = torch.empty_like(volume)
+    _check(lib().sonar_pulse_compress(_dptr(volume), n_beams, n_bins, p.ctypes.data, int(p.size),
+                                      _dptr(out.get("series") if series else None),
+                                      _dptr(out.get("matched") if matched else None), _stream(stream)))
+    return out
 
 
 class Graph:

@@ -5,6 +5,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2606_06130_amd import scenes as S
@@ -101,3 +102,42 @@ def test_build_rejects_null_mesh(L):
     m = sonar.sonar_mesh()
     assert L.sonar_build_scene(C.byref(m), None, C.byref(out)) == sonar.SONAR_E_INVALID
     assert out.value is None
+
+
+@pytest.mark.parametrize("B,tau,dt,window", [(40e3, 300e-6, 19.14e-6, 0), (40e3, 300e-6, 19.14e-6, 1),
+                                             (0.0, 1e-4, 1e-5, 0), (1e5, 5e-6, 1e-5, 1), (0.4, 64.0, 1.0, 0)])
+def test_lfm_pulse_matches_oracle(L, B, tau, dt, window):
+    from oracle import pulse as OP
+    got = sonar.lfm_pulse(B, tau, dt, window)
+    want = OP.lfm_pulse(B, tau, dt, window)
+    assert got.dtype == np.complex64 and got.shape == want.shape
+    assert np.abs(got - want).max() <= 2e-7          # FP32 rounding of unit-magnitude taps
+
+
+def test_lfm_pulse_rejects(L):
+    for args in [(-1.0, 1e-4, 1e-5, 0), (1e3, 0.0, 1e-5, 0), (1e3, 1e-4, 0.0, 0), (1e3, 1e-4, 1e-5, 2),
+                 (1e3, 65e-5, 1e-5, 0)]:
+        with pytest.raises(sonar.SonarError) as e:
+            sonar.lfm_pulse(*args)
+        assert e.value.status == sonar.SONAR_E_INVALID
+    taps = (C.c_float * 8)()
+    n = C.c_int32()
+    assert L.sonar_lfm_pulse(1e3, 10e-5, 1e-5, 0, taps, 4, C.byref(n)) == sonar.SONAR_E_INVALID   # 10 taps > 4
+
+
+def test_pulse_compress_validates_before_launch(L):
+    p = (C.c_float * 4)(1.0, 0.0, 0.5, 0.5)
+    vol, out1, out2 = C.c_void_p(0x100000), C.c_void_p(0x900000), C.c_void_p(0x1100000)
+    E = sonar.SONAR_E_INVALID
+    assert L.sonar_pulse_compress(None, 4, 16, p, 2, out1, out2, None) == E
+    assert L.sonar_pulse_compress(vol, 4, 16, None, 2, out1, out2, None) == E
+    assert L.sonar_pulse_compress(vol, 4, 16, p, 2, None, None, None) == E          # no output
+    assert L.sonar_pulse_compress(vol, -1, 16, p, 2, out1, None, None) == E
+    assert L.sonar_pulse_compress(vol, 4, 0, p, 2, out1, None, None) == E
+    assert L.sonar_pulse_compress(vol, 4, 2049, p, 2, out1, None, None) == E
+    assert L.sonar_pulse_compress(vol, 4, 16, p, 0, out1, None, None) == E
+    assert L.sonar_pulse_compress(vol, 4, 16, p, 65, out1, None, None) == E
+    assert L.sonar_pulse_compress(vol, 4, 16, p, 2, C.c_void_p(0x100000 + 8), None, None) == E   # overlaps input
+    assert b"overlap" in L.sonar_last_error()
+    assert L.sonar_pulse_compress(vol, 4, 16, p, 2, out1, C.c_void_p(0x900000 + 64), None) == E  # outputs overlap
+    assert L.sonar_pulse_compress(vol, 0, 16, p, 2, out1, None, None) == 0                       # nothing to do
