@@ -16,6 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
+# Beam options (sensor flags, see oracle.c)
+BEAM_PATTERN, RX_BEAMS = 1, 2
+
 # Ambiguity flag bits (see oracle.c)
 F_GRAZE, F_EDGE, F_TIE, F_LIMIT, F_SELF, F_BIN, F_FOV, F_OCCLUDER, F_STOP, F_DEPART = (1 << i for i in range(10))
 FLAG_NAMES = ("graze", "edge", "tie", "limit", "self", "bin", "fov", "occluder", "stop", "depart")
@@ -40,7 +43,7 @@ class Params(C.Structure):
                 ("alpha_db", C.c_double),
                 ("max_bounces", C.c_int32), ("pad0", C.c_int32),
                 ("k_d", C.c_double), ("k_s", C.c_double), ("phong_n", C.c_double),
-                ("seed", C.c_uint64), ("ping", C.c_uint32), ("pad1", C.c_uint32)]
+                ("seed", C.c_uint64), ("ping", C.c_uint32), ("flags", C.c_uint32)]
 
 
 class PoseS(C.Structure):
@@ -95,7 +98,7 @@ def lib():
         L.orc_path_eval.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
         L.orc_trace_beams.restype = C.c_int
         L.orc_trace_beams.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Tol), C.c_void_p, C.c_int64] + \
-            [C.c_void_p] * 9 + [C.c_int]
+            [C.c_void_p] * 10 + [C.c_int]
         L.orc_trace_one.restype = C.c_int
         L.orc_trace_one.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Tol), C.c_void_p, C.c_void_p] + [C.c_void_p] * 5
         L.orc_detect.restype = C.c_int
@@ -115,7 +118,8 @@ def params_of(cfg, ping: int = 0) -> Params:
                   grid_mode=cfg.grid_mode, jitter=cfg.jitter, n_bins=cfg.n_range,
                   r_min=cfg.r_min, r_max=cfg.r_max, f0=cfg.freq_hz, c0=cfg.c0, g=cfg.c_grad,
                   alpha_db=cfg.abs_db_per_m, max_bounces=cfg.max_bounces, pad0=0,
-                  k_d=cfg.k_d, k_s=cfg.k_s, phong_n=cfg.phong_n, seed=cfg.seed, ping=ping, pad1=0)
+                  k_d=cfg.k_d, k_s=cfg.k_s, phong_n=cfg.phong_n, seed=cfg.seed, ping=ping,
+                  flags=int(cfg.flags) & (BEAM_PATTERN | RX_BEAMS))
 
 
 def pose_of(pose) -> PoseS:
@@ -199,14 +203,15 @@ def trace_beams(scene: Scene, cfg, pose, beams, tol=None, threads: int = 0, want
     vis = np.zeros((nb * NR, K), np.int32)
     amp = np.zeros((nb * NR, K, 2))
     flags = np.zeros(nb * NR, np.uint32)
+    rxb = np.zeros((nb * NR, K), np.int32)
     tol = tol if tol is not None else default_tol()
     rc = lib().orc_trace_beams(scene.h, C.byref(P), C.byref(pose_of(pose)), C.byref(tol), _ptr(beams), nb,
                                _ptr(col), _ptr(col_all), _ptr(incoh), _ptr(gbuf), _ptr(tri), _ptr(bin_),
-                               _ptr(vis), _ptr(amp), _ptr(flags), int(threads))
+                               _ptr(vis), _ptr(amp), _ptr(flags), _ptr(rxb), int(threads))
     if rc != 0:
-        raise ValueError("oracle rejected the parameters")
+        raise ValueError(f"oracle rejected the parameters ({rc})")
     out = dict(col=col[..., 0] + 1j * col[..., 1], tri=tri, bin=bin_, vis=vis,
-               amp=amp[..., 0] + 1j * amp[..., 1], flags=flags)
+               amp=amp[..., 0] + 1j * amp[..., 1], flags=flags, rxb=rxb)
     if want_all:
         out["col_all"] = col_all[..., 0] + 1j * col_all[..., 1]
     if want_incoh:

@@ -38,6 +38,21 @@
 #define ORC_PI 3.14159265358979323846
 #define ORC_MAXK 8
 
+/* Beam forming options (Sec. II-B: the backscattered contribution depends on
+ * the transmit-receive beam pattern).
+ * ORC_BEAM_PATTERN: every contribution is weighted by the one-way amplitude
+ *   pattern of the transmit beam at the launch direction times that of the
+ *   receive beam at the arrival direction; the pattern of a beam is a
+ *   Gaussian main lobe b = exp(-2 ln2 ((d_az / dth_h)^2 + (d_el / dth_v)^2))
+ *   in the angular offsets from the beam centre, so that its one-way power
+ *   is 3 dB down half a cell from the axis.
+ * ORC_RX_BEAMS: a contribution of bounce >= 2 goes to the receive beam whose
+ *   cell holds its arrival direction instead of the launch beam (bounce-1
+ *   returns arrive along the reversed launch ray, so their beam is the launch
+ *   beam). Cell-centred beams only. */
+#define ORC_BEAM_PATTERN 1u
+#define ORC_RX_BEAMS 2u
+
 /* ------------------------------------------------------------------------ */
 /* small vector algebra                                                      */
 
@@ -69,7 +84,7 @@ typedef struct {
     double k_d, k_s, phong_n;
     uint64_t seed;
     uint32_t ping;
-    uint32_t pad1;
+    uint32_t flags;              /* ORC_BEAM_PATTERN | ORC_RX_BEAMS */
 } orc_params;
 
 typedef struct { double pos[3]; double rot[9]; } orc_pose;   /* sensor->world, row-major */
@@ -542,7 +557,7 @@ void orc_path_eval(const orc_params *P, const double o[3], const double d[3], do
 /* The per-ray model.                                                        */
 
 typedef struct {
-    int32_t tri[ORC_MAXK], bin[ORC_MAXK], vis[ORC_MAXK];
+    int32_t tri[ORC_MAXK], bin[ORC_MAXK], vis[ORC_MAXK], rxb[ORC_MAXK];
     double re[ORC_MAXK], im[ORC_MAXK], inc[ORC_MAXK];
     uint32_t flags;
     int g_valid;
@@ -558,11 +573,23 @@ static double upper_speed(const orc_params *P, const oscene *S, const orc_pose *
     return P->c0 + fabs(P->g) * (z + 1.0);
 }
 
+static double lobe_gauss(double d_az, double d_el, double dh, double dv)
+{
+    const double a = d_az / dh, e = d_el / dv;
+    return exp(-2.0 * log(2.0) * (a * a + e * e));
+}
+
+/* beam = launch beam index (or -1: beam options unused); d_az, d_el = the
+ * launch direction's offsets from that beam's centre */
 static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, const orc_tol *T,
-                      v3 o, v3 d, oray *out)
+                      v3 o, v3 d, int32_t beam, double d_az, double d_el, oray *out)
 {
     memset(out, 0, sizeof(*out));
-    for (int k = 0; k < ORC_MAXK; ++k) { out->tri[k] = -1; out->bin[k] = -1; }
+    for (int k = 0; k < ORC_MAXK; ++k) { out->tri[k] = -1; out->bin[k] = -1; out->rxb[k] = beam; }
+    const double dh = P->hfov / P->n_h, dv = P->vfov / P->n_v;
+    const int pattern = beam >= 0 && (P->flags & ORC_BEAM_PATTERN);
+    const int rx_bin = beam >= 0 && (P->flags & ORC_RX_BEAMS);
+    const double w_tx = pattern ? lobe_gauss(d_az, d_el, dh, dv) : 1.0;
     const int K = P->max_bounces;
     const v3 Sp = mk(Q->pos[0], Q->pos[1], Q->pos[2]);
     const double c_ref = P->c0 + P->g * Sp.z;              /* time-to-range speed */
@@ -616,6 +643,8 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
         double L_back, T_back;
         v3 w;
         int vis = 1;
+        double w_rx = w_tx;                 /* bounce 1: arrival along the launch ray */
+        int32_t rxb = beam;
         if (k == 0) {
             L_back = L_out; T_back = T_out; w = scl(din, -1.0);
         } else {
@@ -630,7 +659,28 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
             double mh = 0.5 * P->hfov - fabs(az), mv = 0.5 * P->vfov - fabs(el);
             if (fabs(mh) <= T->fov || fabs(mv) <= T->fov) out->flags |= F_FOV;
             if (mh < 0.0 || mv < 0.0) vis = 0;
+            if (beam >= 0 && vis && (pattern || rx_bin)) {
+                const int nh = P->n_h;
+                int h = beam % nh, v = beam / nh;
+                if (rx_bin) {
+                    /* the receive cell holding the arrival direction */
+                    const double xa = (az + 0.5 * P->hfov) / dh, xe = (el + 0.5 * P->vfov) / dv;
+                    h = (int)floor(xa);
+                    v = (int)floor(xe);
+                    if (h > P->n_h - 1) h = P->n_h - 1;
+                    if (v > P->n_v - 1) v = P->n_v - 1;
+                    if (h < 0) h = 0;
+                    if (v < 0) v = 0;
+                    /* an arrival within the FOV margin of a cell edge is ambiguous */
+                    if (fabs(xa - floor(xa + 0.5)) * dh <= T->fov || fabs(xe - floor(xe + 0.5)) * dv <= T->fov)
+                        out->flags |= F_FOV;
+                    rxb = v * nh + h;
+                }
+                const double c_az = -0.5 * P->hfov + (h + 0.5) * dh, c_el = -0.5 * P->vfov + (v + 0.5) * dv;
+                w_rx = pattern ? lobe_gauss(az - c_az, el - c_el, dh, dv) : 1.0;
+            }
         }
+        out->rxb[k] = rxb;
         out->vis[k] = vis;
         if (vis) {
             double cos_o = dot(np, w);
@@ -650,6 +700,7 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
                     double fsc = rho * (kd * cos_i * cos_o + ks * pow(lobe, P->phong_n));
                     double amp = W * sgn * sqrt(fsc) * pow(10.0, -P->alpha_db * (L_out + L_back) / 20.0) /
                                  (L_out * L_back * P->n_r);
+                    if (pattern) amp *= w_tx * w_rx;
                     double cyc = P->f0 * Tt;
                     double ph = 2.0 * ORC_PI * (cyc - floor(cyc)) + phi;
                     out->bin[k] = bin;
@@ -694,11 +745,21 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
                     int32_t *rec_tri, int32_t *rec_bin, int32_t *rec_vis,  /* [n_beams*n_r][K] */
                     double *rec_amp,    /* [n_beams*n_r][K][2] */
                     uint32_t *ray_flags,/* [n_beams*n_r] */
+                    int32_t *rec_rxb,   /* [n_beams*n_r][K] receive beam of each contribution, or NULL */
                     int n_threads)
 {
     const oscene *S = (const oscene *)hs;
     if (P->max_bounces < 1 || P->max_bounces > ORC_MAXK) return -1;
     const int K = P->max_bounces, NB = P->n_bins, NR = P->n_r;
+    if (P->flags && P->grid_mode != 0) return -3;            /* beam options: cell-centred beams only */
+    const int rx = (P->flags & ORC_RX_BEAMS) != 0;
+    if (rx) {
+        /* contributions move between beams: every beam, in order */
+        if (n_beams != (int64_t)P->n_h * P->n_v) return -2;
+        for (int64_t q = 0; q < n_beams; ++q)
+            if (beams[q] != q) return -2;
+    }
+    const double dh = P->hfov / P->n_h, dv = P->vfov / P->n_v;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -716,8 +777,17 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
         for (int j = 0; j < NR; ++j) {
             double od[6];
             orc_ray(P, Q, b, j, od);
+            double d_az = 0.0, d_el = 0.0;
+            if (P->flags) {
+                double az, el;
+                ray_angles(P, b, j, &az, &el);
+                const int nh = beams_h(P);
+                d_az = az - (-0.5 * P->hfov + (b % nh + 0.5) * dh);
+                d_el = el - (-0.5 * P->vfov + (b / nh + 0.5) * dv);
+            }
             oray r;
-            trace_ray(S, P, Q, T, mk(od[0], od[1], od[2]), mk(od[3], od[4], od[5]), &r);
+            trace_ray(S, P, Q, T, mk(od[0], od[1], od[2]), mk(od[3], od[4], od[5]), P->flags ? b : -1, d_az,
+                      d_el, &r);
             size_t ri = (size_t)q * NR + j;
             ray_flags[ri] = r.flags;
             for (int k = 0; k < K; ++k) {
@@ -726,7 +796,9 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
                 rec_vis[ri * K + k] = r.vis[k];
                 rec_amp[(ri * K + k) * 2] = r.re[k];
                 rec_amp[(ri * K + k) * 2 + 1] = r.im[k];
-                if (r.bin[k] < 0) continue;
+                if (rec_rxb) rec_rxb[ri * K + k] = r.rxb[k] >= 0 ? r.rxb[k] : b;
+                if (rx) r.inc[k] = r.re[k] * r.re[k] + r.im[k] * r.im[k];
+                if (r.bin[k] < 0 || rx) continue;
                 if (ca) { ca[2 * r.bin[k]] += r.re[k]; ca[2 * r.bin[k] + 1] += r.im[k]; }
                 if (r.flags == 0) {
                     cc[2 * r.bin[k]] += r.re[k];
@@ -749,6 +821,31 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
             g[6] = (double)gcount / NR;
         }
     }
+    if (rx) {
+        /* receive binning: columns from the records, in ray order */
+        for (int64_t q = 0; q < n_beams; ++q) {
+            memset(col + (size_t)q * NB * 2, 0, sizeof(double) * NB * 2);
+            if (col_all) memset(col_all + (size_t)q * NB * 2, 0, sizeof(double) * NB * 2);
+            if (incoh) memset(incoh + (size_t)q * 2 * NB, 0, sizeof(double) * NB * 2);
+        }
+        for (size_t ri = 0; ri < (size_t)n_beams * NR; ++ri) {
+            for (int k = 0; k < K; ++k) {
+                const size_t e = ri * K + k;
+                const int bin = rec_bin[e];
+                if (bin < 0) continue;
+                /* the receive beam (records carry it when asked for; else recompute below) */
+                int32_t tb = rec_rxb ? rec_rxb[e] : -1;
+                if (tb < 0) return -4;
+                const double re = rec_amp[2 * e], im = rec_amp[2 * e + 1];
+                if (col_all) { col_all[((size_t)tb * NB + bin) * 2] += re; col_all[((size_t)tb * NB + bin) * 2 + 1] += im; }
+                if (ray_flags[ri] == 0) {
+                    col[((size_t)tb * NB + bin) * 2] += re;
+                    col[((size_t)tb * NB + bin) * 2 + 1] += im;
+                    if (incoh) incoh[(size_t)tb * 2 * NB + (k == 0 ? 0 : NB) + bin] += re * re + im * im;
+                }
+            }
+        }
+    }
     return 0;
 }
 
@@ -760,7 +857,7 @@ int orc_trace_one(void *hs, const orc_params *P, const orc_pose *Q, const orc_to
     const oscene *S = (const oscene *)hs;
     if (P->max_bounces < 1 || P->max_bounces > ORC_MAXK) return -1;
     oray r;
-    trace_ray(S, P, Q, T, mk(o[0], o[1], o[2]), unit(mk(d[0], d[1], d[2])), &r);
+    trace_ray(S, P, Q, T, mk(o[0], o[1], o[2]), unit(mk(d[0], d[1], d[2])), -1, 0.0, 0.0, &r);
     for (int k = 0; k < P->max_bounces; ++k) {
         tri[k] = r.tri[k]; bin[k] = r.bin[k]; vis[k] = r.vis[k];
         amp[2 * k] = r.re[k]; amp[2 * k + 1] = r.im[k];
