@@ -154,10 +154,30 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     trav = traversal_work(torch, sonar, np, scene, cfg, pose)
     trav["visit_gbs"] = trav["visit_bytes_per_ping"] / (mp_ms * 1e-3) / 1e9
     trav["note"] = "all traversals of a ray (up to 3 nearest-hit and 2 any-hit connection queries)"
+    # the same ping with the transmit-receive beam pattern and receive binning
+    cfg_rx = cfg.replace(flags=3)
+    out_rx = sonar.alloc_outputs(cfg_rx)
+    for _ in range(3):
+        sonar.ping(scene, cfg_rx, pose, out=out_rx)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for a, b in ev:
+        a.record(stream)
+        sonar.ping(scene, cfg_rx, pose, out=out_rx)
+        b.record(stream)
+    torch.cuda.synchronize()
+    assert scene.status() == 0
+    rx_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    moved = int(out_rx["rx_workspace"][:4].view(torch.int32).item())
+    del out_rx
     multipath = {"workload": "harbor multipath ping: 1,991,680 triangles, 256x128 beams x 16 rays, 3 bounces, "
                              "Phong-20 + diffuse, c(z) = 1500 + 0.05 z, 1,024 bins",
                  "ping_ms": mp_ms, "pings_per_s": 1e3 / mp_ms, "mrays_per_s": cfg.n_rays / mp_ms / 1e3,
-                 "traversal": trav}
+                 "traversal": trav,
+                 "beam_pattern_rx_binning": {"ping_ms": rx_ms, "moved_returns": moved,
+                                             "note": "same ping with the Gaussian transmit-receive pattern and "
+                                                     "later-bounce returns binned by arrival direction (list + "
+                                                     "scatter after the ping kernel)"}}
     del out
 
     # surrogate ping: single-bounce ping with G-buffer and incoherent channel,

@@ -110,7 +110,24 @@ typedef struct {
  *   max_bounces       path depth K, 1..4 (Sec. II-B: tunable)
  *   k_d, k_s, phong_n diffuse weight, specular weight, specular exponent
  *   seed              jitter seed (SplitMix64)
- *   flags             reserved, 0 */
+ *   flags             beam forming options (Sec. II-B: the contribution
+ *                     depends on the transmit-receive beam pattern), 0 or:
+ *     SONAR_FLAG_BEAM_PATTERN  weight every contribution by the one-way
+ *                     amplitude pattern of the transmit beam at the launch
+ *                     direction times that of the receive beam at the
+ *                     arrival direction; a beam's pattern is the Gaussian
+ *                     main lobe exp(-2 ln2 ((d_az/dth_h)^2 + (d_el/dth_v)^2))
+ *                     in the angular offsets from its centre (one-way power
+ *                     3 dB down half a cell off axis)
+ *     SONAR_FLAG_RX_BEAMS  a return of bounce >= 2 goes to the receive beam
+ *                     whose cell holds its arrival direction instead of the
+ *                     launch beam (bounce-1 returns arrive along the reversed
+ *                     launch ray); with max_bounces > 1 it needs the
+ *                     workspace of sonar_ping_rx or sonar_ping_detect, and
+ *                     batches reject it
+ *                     Both options need cell-centred beams (grid_mode 0). */
+#define SONAR_FLAG_BEAM_PATTERN 1u
+#define SONAR_FLAG_RX_BEAMS 2u
 typedef struct {
     double hfov, vfov;
     int32_t n_h, n_v, rays_per_beam, grid_mode, jitter, n_range;
@@ -139,13 +156,16 @@ typedef void *sonar_stream;
  * `stats` (optional, [n_rays][3]) receives, over all of the ray's traversals,
  * the internal nodes visited, the triangles tested and the deepest traversal
  * stack. Counting uses separate kernel instantiations: indices and bins are
- * the same as without it, values the same up to rounding. */
+ * the same as without it, values the same up to rounding. `beam` (optional,
+ * [n_rays][max_bounces]) receives the beam each contribution is added to
+ * (the launch beam unless SONAR_FLAG_RX_BEAMS moves it). */
 typedef struct {
     int32_t *tri;
     int32_t *bin;
     int32_t *vis;
     sonar_cf32 *amp;
     uint32_t *stats;
+    int32_t *beam;
 } sonar_ray_record;
 
 typedef struct {
@@ -186,12 +206,31 @@ sonar_status sonar_get_scene_info(const sonar_scene *scene, sonar_scene_info *in
  *   record   optional per-ray record (testing)
  *   ray_mask optional device bit mask over rays (bit r of word r / 32): set
  *            rays are traced and recorded but add nothing to the outputs
- * Asynchronous on `stream`. No workspace. */
+ * Asynchronous on `stream`. No workspace: SONAR_FLAG_RX_BEAMS with
+ * max_bounces > 1 is rejected (SONAR_E_INVALID; use sonar_ping_rx). */
 sonar_status sonar_ping(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
                         sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *record,
                         const uint32_t *ray_mask, sonar_stream stream);
 
-/* Bytes of device workspace sonar_detect needs for these parameters. */
+/* Bytes of device workspace sonar_ping_rx needs: a list of up to
+ * n_rays * (max_bounces - 1) returns that receive binning moves to another
+ * beam (16 bytes each) and its counter; 0 when the parameters are invalid. */
+size_t sonar_rx_workspace_size(const sonar_params *params);
+
+/* sonar_ping with a workspace, for SONAR_FLAG_RX_BEAMS with several
+ * bounces: returns binned to another beam are listed during the ping and
+ * added into that beam's column (and the bounce >= 2 incoherent channel)
+ * after it, with floating-point atomics, so the order of those additions
+ * and the last bits of the affected cells may vary between runs. Any other
+ * parameters behave as in sonar_ping. Asynchronous on `stream`; no
+ * allocation. */
+sonar_status sonar_ping_rx(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
+                           sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *record,
+                           const uint32_t *ray_mask, void *workspace, size_t workspace_bytes, sonar_stream stream);
+
+/* Bytes of device workspace sonar_detect needs for these parameters (with
+ * SONAR_FLAG_RX_BEAMS and several bounces it includes the receive-binning
+ * list, so that sonar_ping_detect can use it). */
 size_t sonar_detect_workspace_size(const sonar_params *params);
 
 /* Per-beam CA-CFAR detection of a volume into a point cloud (Sec. II-A: an

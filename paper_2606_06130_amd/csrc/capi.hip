@@ -85,6 +85,9 @@ sonar_status check_params(const sonar_params *p)
         return fail(SONAR_E_INVALID, "k_d, k_s and phong_n must be finite and >= 0");
     int64_t beams = (int64_t)(p->n_h + (p->grid_mode == 1)) * (p->n_v + (p->grid_mode == 1));
     if (beams * p->rays_per_beam > ((int64_t)1 << 31) - 1) return fail(SONAR_E_INVALID, "too many rays");
+    if (p->flags & ~(SONAR_FLAG_BEAM_PATTERN | SONAR_FLAG_RX_BEAMS)) return fail(SONAR_E_INVALID, "unknown flags");
+    if (p->flags && p->grid_mode != 0)
+        return fail(SONAR_E_UNSUPPORTED, "beam pattern and receive binning need cell-centred beams (grid_mode 0)");
     return SONAR_OK;
 }
 
@@ -106,6 +109,40 @@ sonar_status check_pose(const sonar_pose *q)
 
 int beams_h_of(const sonar_params *p) { return p->grid_mode == 1 ? p->n_h + 1 : p->n_h; }
 int beams_v_of(const sonar_params *p) { return p->grid_mode == 1 ? p->n_v + 1 : p->n_v; }
+
+static_assert(SONAR_FLAG_BEAM_PATTERN == sonar::FLAG_BEAM_PATTERN && SONAR_FLAG_RX_BEAMS == sonar::FLAG_RX_BEAMS,
+              "beam flags");
+
+// Receive binning with several bounces lists the returns it moves.
+static bool needs_rx_list(const sonar_params *p)
+{
+    return (p->flags & SONAR_FLAG_RX_BEAMS) && p->max_bounces > 1;
+}
+
+// Bytes of the receive-binning area: a 256-byte counter block, then one
+// 16-byte entry per possible moved return (n_rays * (max_bounces - 1)).
+static size_t rx_bytes(const sonar_params *p)
+{
+    const int64_t rays = (int64_t)beams_h_of(p) * beams_v_of(p) * p->rays_per_beam;
+    return 256 + 16 * (size_t)rays * (size_t)(p->max_bounces - 1);
+}
+
+static void set_rx_area(sonar::PingArgs &a, const sonar_params *p, void *area)
+{
+    a.rx_count = reinterpret_cast<uint32_t *>(area);
+    a.rx_list = reinterpret_cast<int4 *>(reinterpret_cast<char *>(area) + 256);
+    a.rx_cap = (uint32_t)(a.n_rays * (p->max_bounces - 1));
+}
+
+// reset -> ping -> scatter of the moved returns (or the plain ping)
+static hipError_t launch_ping_rx(const sonar::PingArgs &a, int stack, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (a.rx_list) e = sonar::launch_rx_reset(a.rx_count, s);
+    if (e == hipSuccess) e = sonar::launch_ping(a, stack, s);
+    if (e == hipSuccess && a.rx_list) e = sonar::launch_rx_scatter(a, s);
+    return e;
+}
 
 sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, sonar_cf32 *volume,
                             float *gbuffer, float *incoh, const sonar_ray_record *rec, const uint32_t *ray_mask,
@@ -165,6 +202,7 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
     a.na = a.n_r / a.ne;
     a.grid_mode = p->grid_mode;
     a.jitter = p->jitter;
+    a.flags = p->flags;
     a.n_bins = p->n_range;
     a.K = p->max_bounces;
     a.n_rays = (int64_t)a.n_beams * a.n_r;
@@ -177,6 +215,7 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
         a.rec_vis = rec->vis;
         a.rec_amp = reinterpret_cast<float2 *>(rec->amp);
         a.stats = rec->stats;
+        a.rec_beam = rec->beam;
     }
     a.mask = ray_mask;
     // a traversal of a valid hierarchy visits every node and every leaf at most once
@@ -340,15 +379,48 @@ sonar_status sonar_ping(const sonar_scene *sc, const sonar_params *p, const sona
     sonar::PingArgs a;
     sonar_status st = fill_ping_args(sc, p, q, volume, gbuffer, incoh, rec, ray_mask, &a);
     if (st != SONAR_OK) return st;
+    if (needs_rx_list(p))
+        return fail(SONAR_E_INVALID, "receive binning with several bounces needs a workspace: use sonar_ping_rx");
     hipError_t e = sonar::launch_ping(a, sc->s.stack, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping launch: %s", hipGetErrorString(e));
     return SONAR_OK;
 }
 
+size_t sonar_rx_workspace_size(const sonar_params *p)
+{
+    if (check_params(p) != SONAR_OK) return 0;
+    return needs_rx_list(p) ? rx_bytes(p) : 256;
+}
+
+sonar_status sonar_ping_rx(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, sonar_cf32 *volume,
+                           float *gbuffer, float *incoh, const sonar_ray_record *rec, const uint32_t *ray_mask,
+                           void *workspace, size_t ws_bytes, sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar::PingArgs a;
+    sonar_status st = fill_ping_args(sc, p, q, volume, gbuffer, incoh, rec, ray_mask, &a);
+    if (st != SONAR_OK) return st;
+    if (needs_rx_list(p)) {
+        if (!workspace || ws_bytes < rx_bytes(p))
+            return fail(SONAR_E_INVALID, "workspace smaller than sonar_rx_workspace_size()");
+        if (((uintptr_t)workspace & 255) != 0) return fail(SONAR_E_INVALID, "workspace must be 256-byte aligned");
+        set_rx_area(a, p, workspace);
+    }
+    hipError_t e = launch_ping_rx(a, sc->s.stack, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
+// detection workspace, then (receive binning with several bounces) the list area
+static size_t det_bytes(const sonar_params *p)
+{
+    return (sonar::detect_workspace_bytes(beams_h_of(p) * beams_v_of(p), 16) + 255) & ~(size_t)255;
+}
+
 size_t sonar_detect_workspace_size(const sonar_params *p)
 {
     if (check_params(p) != SONAR_OK) return 0;
-    return sonar::detect_workspace_bytes(beams_h_of(p) * beams_v_of(p), 16);
+    return det_bytes(p) + (needs_rx_list(p) ? rx_bytes(p) : 0);
 }
 
 sonar_status sonar_detect(const sonar_cf32 *volume, const sonar_params *p, const sonar_pose *q,
@@ -376,6 +448,16 @@ sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, con
     st = fill_detect_args(volume, p, q, c, points, capacity, dev_count, workspace, ws_bytes, &da);
     if (st != SONAR_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    if (needs_rx_list(p)) {
+        // moved returns land after the ping kernel: detection runs after them
+        if (ws_bytes < det_bytes(p) + rx_bytes(p) || ((uintptr_t)workspace & 255) != 0)
+            return fail(SONAR_E_INVALID, "workspace smaller than sonar_detect_workspace_size() or not 256-byte aligned");
+        set_rx_area(pa, p, reinterpret_cast<char *>(workspace) + det_bytes(p));
+        hipError_t e = launch_ping_rx(pa, sc->s.stack, s);
+        if (e == hipSuccess) e = sonar::launch_detect(da, s);
+        if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping/detect launch: %s", hipGetErrorString(e));
+        return SONAR_OK;
+    }
     // the fused test needs alpha(N) > 1 for every window size, so that a bin
     // without a return can never be detected
     bool fused = true;
@@ -550,6 +632,8 @@ sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_p
     int64_t tiles = 0, rays = 0;
     int max_bins = 0, max_beams = 0;
     for (int32_t i = 0; i < n; ++i) {
+        if (needs_rx_list(&params[i]))
+            return fail(SONAR_E_UNSUPPORTED, "ping %d: batches do not take receive binning with several bounces", i);
         sonar_status st = fill_ping_args(sc, &params[i], &poses[i], volumes[i], nullptr, nullptr, nullptr, nullptr,
                                          &d[i]);
         if (st != SONAR_OK) {
@@ -938,6 +1022,7 @@ sonar_status sonar_device_status(const sonar_scene *sc, sonar_stream stream)
         (void)hipStreamSynchronize(s);
     }
     if (h & sonar::ST_STACK) return fail(SONAR_E_STACK, "a traversal overflowed its stack; those rays were misses");
+    if (h & sonar::ST_RX_FULL) return fail(SONAR_E_DEVICE, "receive-binning list full: returns were dropped");
     return SONAR_OK;
 }
 

@@ -49,8 +49,12 @@ constexpr int ST_BAD_INDEX = 2;
 constexpr int ST_BAD_VERTEX = 4;
 constexpr int ST_BAD_TREE = 8;
 constexpr int ST_LOOP = 16;
+constexpr int ST_RX_FULL = 32;
 
 // Everything a ping kernel needs, by value.
+constexpr uint32_t FLAG_BEAM_PATTERN = 1u;
+constexpr uint32_t FLAG_RX_BEAMS = 2u;
+
 struct PingArgs {
     const float4 *nodes;
     const float4 *tris;
@@ -73,7 +77,7 @@ struct PingArgs {
     float2 *volume;
     float *gbuf;
     float *incoh;
-    int32_t *rec_tri, *rec_bin, *rec_vis;
+    int32_t *rec_tri, *rec_bin, *rec_vis, *rec_beam;
     float2 *rec_amp;
     uint32_t *stats;         // optional [n_rays][3]: internal nodes visited, triangles tested, deepest stack
     const uint32_t *mask;
@@ -85,6 +89,12 @@ struct PingArgs {
     int det_G, det_T, det_M;
     float det_n0;
     double det_alpha[2 * 64 + 1];
+    // beam forming: FLAG_BEAM_PATTERN / FLAG_RX_BEAMS; returns binned to
+    // another beam go to rx_list (beam, bin, re, im) through rx_count
+    uint32_t flags;
+    uint32_t rx_cap;
+    int4 *rx_list;
+    uint32_t *rx_count;
     // batch bookkeeping (descriptor of one ping in a batch)
     int tile_offset;         // first global tile of this ping
     int n_tiles;             // 256-ray tiles of this ping
@@ -112,6 +122,10 @@ int batch_max_blocks_per_cu(const BatchLaunch &b);
 
 // Host-side launchers (one per translation unit).
 hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s);
+// Receive binning: clear the list's counter before a ping; add the listed
+// returns into their beams' columns after it.
+hipError_t launch_rx_reset(uint32_t *count, hipStream_t s);
+hipError_t launch_rx_scatter(const PingArgs &a, hipStream_t s);
 
 struct BuildBuffers;
 sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, char *err, size_t errlen);

@@ -559,6 +559,24 @@ __device__ __forceinline__ Conn connect(d3 P, d3 S, double g, double c0)
 
 }  // namespace
 
+// Receive binning: a return added to another beam than the launch beam is
+// appended to a device list, one counter update per wave (ballot, the
+// leader's atomic, per-lane offsets from the lanes below).
+__device__ __forceinline__ void rx_append(const PingArgs &a, const bool want, const int4 e, const int lane)
+{
+    const uint64_t m = __ballot(want);
+    if (m == 0) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(a.rx_count, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader);
+    if (want) {
+        const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (slot < a.rx_cap) a.rx_list[slot] = e;
+        else atomicOr(a.status, ST_RX_FULL);
+    }
+}
+
 // The ping body for one tile of 256 consecutive rays (4 wavefronts). `a` is
 // the ping's argument block (kernel arguments, or a batch descriptor in
 // device memory); `W` is this wavefront's LDS area.
@@ -595,6 +613,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         // ---- ray generation (FP64)
         const int h = (int)(beam % a.beams_h), v = (int)(beam / a.beams_h);
         double az, el;
+        float w_tx = 1.f;            // transmit pattern at the launch direction
         if (a.grid_mode == 1) {
             az = -0.5 * a.hfov + h * a.dth_h;
             el = -0.5 * a.vfov + v * a.dth_v;
@@ -609,6 +628,11 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
             }
             az = -0.5 * a.hfov + (h + (ja + u1) / a.na) * a.dth_h;
             el = -0.5 * a.vfov + (v + (je + u2) / a.ne) * a.dth_v;
+            if (a.flags & FLAG_BEAM_PATTERN) {
+                // offsets from the beam centre in cells: lobe = 2^(-2 (fa^2 + fe^2))
+                const float fa = (float)((ja + u1) / a.na - 0.5), fe = (float)((je + u2) / a.ne - 0.5);
+                w_tx = exp2f(-2.f * (fa * fa + fe * fe));
+            }
         }
         double ce = cos(el), se = sin(el), ca = cos(az), sa = sin(az);
         d3 ds = mk3(ce * ca, ce * sa, se);
@@ -628,6 +652,8 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
             int rec_tri = -1, rec_vis = 0;
             int cbin = -1;
             float cre = 0.f, cim = 0.f, cinc = 0.f;
+            float w_rx = w_tx;       // receive pattern: bounce 1 arrives along the launch ray
+            int rxb = (int)beam;     // the beam the return is added to
             if (!stop) {
                 // segment limit: arc length for constant c, travel time in a gradient
                 double s_lim, T_lim = 0.0;
@@ -698,6 +724,21 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                                     vis = false;
                                 }
                                 if (fabs(sz) > a.tan_v * sxy) vis = false;
+                                if (vis && a.flags) {
+                                    // receive cell and pattern at the arrival direction
+                                    const double xa = (atan2(sy, sx) + 0.5 * a.hfov) / a.dth_h;
+                                    const double xe = (atan2(sz, sxy) + 0.5 * a.vfov) / a.dth_v;
+                                    int hr = h, vr = v;
+                                    if (a.flags & FLAG_RX_BEAMS) {
+                                        hr = min(max((int)floor(xa), 0), a.beams_h - 1);
+                                        vr = min(max((int)floor(xe), 0), a.beams_v - 1);
+                                        rxb = vr * a.beams_h + hr;
+                                    }
+                                    if (a.flags & FLAG_BEAM_PATTERN) {
+                                        const float fa = (float)(xa - (hr + 0.5)), fe = (float)(xe - (vr + 0.5));
+                                        w_rx = exp2f(-2.f * (fa * fa + fe * fe));
+                                    }
+                                }
                             }
                             double cos_o = dot3(np, w);
                             if (vis && cos_o > 0.0) {
@@ -761,17 +802,30 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                     }
                 }
             }
+            if (a.flags & FLAG_BEAM_PATTERN) {
+                const float wgt = w_tx * w_rx;
+                cre *= wgt;
+                cim *= wgt;
+                cinc *= wgt * wgt;
+            }
+            int cbin_here = cbin;    // the bin this lane's launch beam receives
+            if (K > 1 && k > 0 && (a.flags & FLAG_RX_BEAMS)) {
+                const bool away = cbin >= 0 && rxb != (int)beam;
+                if (away) cbin_here = -1;
+                rx_append(a, away && !masked, make_int4(rxb, cbin, __float_as_int(cre), __float_as_int(cim)), lane);
+            }
             if (a.rec_tri) {
                 size_t ri = ray * K + k;
                 a.rec_tri[ri] = rec_tri;
                 a.rec_bin[ri] = cbin;
                 a.rec_vis[ri] = rec_vis;
                 a.rec_amp[ri] = make_float2(cre, cim);
+                if (a.rec_beam) a.rec_beam[ri] = rxb;
             }
             if (K == 1) {
-                slot0 = Slot{cbin, cre, cim, cinc};
+                slot0 = Slot{cbin_here, cre, cim, cinc};
             } else {
-                sbin[k * WAVE + lane] = cbin;
+                sbin[k * WAVE + lane] = cbin_here;
                 sval[k * WAVE + lane] = k == 0 ? make_float4(cre, cim, cinc, 0.f) : make_float4(cre, cim, 0.f, cinc);
             }
         }
@@ -1045,6 +1099,45 @@ __global__ void k_batch_reset(uint32_t *queue, unsigned long long *t0, unsigned 
         t0[i] = ~0ull;
         t1[i] = 0ull;
     }
+}
+
+__global__ void k_rx_reset(uint32_t *count)
+{
+    if (threadIdx.x == 0) *count = 0u;
+}
+
+// Listed returns into their receive beams' columns (and the bounce >= 2
+// incoherent channel); grid-stride over the list.
+__global__ __launch_bounds__(256) void k_rx_scatter(const int4 *__restrict__ list, const uint32_t *__restrict__ count,
+                                                    uint32_t cap, float2 *__restrict__ volume, float *__restrict__ incoh,
+                                                    int n_bins, int64_t n_beams)
+{
+    const uint32_t n = min(*count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int4 e = list[i];
+        const size_t cell = (size_t)e.x * n_bins + e.y;
+        const float re = __int_as_float(e.z), im = __int_as_float(e.w);
+        atomicAdd(&volume[cell].x, re);
+        atomicAdd(&volume[cell].y, im);
+        if (incoh) atomicAdd(&incoh[(size_t)n_beams * n_bins + cell], re * re + im * im);
+    }
+}
+
+hipError_t launch_rx_reset(uint32_t *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rx_reset, dim3(1), dim3(64), 0, s, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_rx_scatter(const PingArgs &a, hipStream_t s)
+{
+    // at most rx_cap entries, grid-stride over up to 2,048 blocks
+    const uint64_t want = ((uint64_t)a.rx_cap + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 2048 ? want : 2048);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rx_scatter, dim3(blocks), dim3(256), 0, s, a.rx_list, a.rx_count, a.rx_cap, a.volume,
+                       a.incoh, a.n_bins, (int64_t)a.n_beams);
+    return hipGetLastError();
 }
 
 int ping_wave_words(int depth, int n_bins, int K)

@@ -21,6 +21,8 @@ SONAR_E_NOMEM = -2
 SONAR_E_DEVICE = -3
 SONAR_E_STACK = -4
 SONAR_E_UNSUPPORTED = -5
+FLAG_BEAM_PATTERN = 1
+FLAG_RX_BEAMS = 2
 
 # Every symbol include/sonar.h declares.
 EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "sonar_ping",
@@ -33,7 +35,8 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_free", "sonar_surrogate_set_state", "sonar_surrogate_get_state",
            "sonar_surrogate_set_norm", "sonar_surrogate_forward", "sonar_surrogate_train_step",
            "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
-           "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress")
+           "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
+           "sonar_rx_workspace_size", "sonar_ping_rx")
 
 
 class SonarError(RuntimeError):
@@ -70,7 +73,7 @@ class sonar_cfar(C.Structure):
 
 class sonar_ray_record(C.Structure):
     _fields_ = [("tri", C.c_void_p), ("bin", C.c_void_p), ("vis", C.c_void_p), ("amp", C.c_void_p),
-                ("stats", C.c_void_p)]
+                ("stats", C.c_void_p), ("beam", C.c_void_p)]
 
 
 class sonar_scene_info(C.Structure):
@@ -187,6 +190,11 @@ def lib():
                                               C.c_void_p, C.c_void_p, C.c_void_p]
         L.sonar_params_from_resolution.restype = C.c_int
         L.sonar_params_from_resolution.argtypes = [C.c_double] * 7 + [P(sonar_params)]
+        L.sonar_rx_workspace_size.restype = C.c_size_t
+        L.sonar_rx_workspace_size.argtypes = [P(sonar_params)]
+        L.sonar_ping_rx.restype = C.c_int
+        L.sonar_ping_rx.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.sonar_lfm_pulse.restype = C.c_int
         L.sonar_lfm_pulse.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32,
                                       P(C.c_int32)]
@@ -305,6 +313,7 @@ def alloc_outputs(cfg, gbuffer=False, incoh=False, record=False, stats=False, de
         out["bin"] = torch.empty((n, K), dtype=torch.int32, device=device)
         out["vis"] = torch.empty((n, K), dtype=torch.int32, device=device)
         out["amp"] = torch.empty((n, K), dtype=torch.complex64, device=device)
+        out["beam"] = torch.empty((n, K), dtype=torch.int32, device=device)
         if stats:
             out["stats"] = torch.empty((n, 3), dtype=torch.int32, device=device)
     return out
@@ -319,9 +328,25 @@ def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=F
     if "tri" in out:
         rec = sonar_ray_record(tri=out["tri"].data_ptr(), bin=out["bin"].data_ptr(), vis=out["vis"].data_ptr(),
                                amp=out["amp"].data_ptr(),
-                               stats=out["stats"].data_ptr() if "stats" in out else None)
+                               stats=out["stats"].data_ptr() if "stats" in out else None,
+                               beam=out["beam"].data_ptr() if "beam" in out else None)
     p = params if params is not None else params_of(cfg)
     q = pose_s if pose_s is not None else pose_of(pose)
+    if (p.flags & FLAG_RX_BEAMS) and p.max_bounces > 1:
+        # receive binning lists the returns it moves: a workspace kept with the outputs
+        import torch
+        need = lib().sonar_rx_workspace_size(C.byref(p))
+        if need == 0:       # invalid parameters: the plain call reports why
+            _check(lib().sonar_ping(scene.handle, C.byref(p), C.byref(q), _dptr(out["volume"]), None, None, None,
+                                    None, _stream(stream)))
+        ws = out.get("rx_workspace")
+        if ws is None or ws.numel() < need:
+            ws = out["rx_workspace"] = torch.empty(need, dtype=torch.uint8, device=out["volume"].device)
+        _check(lib().sonar_ping_rx(scene.handle, C.byref(p), C.byref(q), _dptr(out["volume"]),
+                                   _dptr(out.get("gbuffer")), _dptr(out.get("incoh")),
+                                   C.byref(rec) if rec is not None else None, _dptr(ray_mask), _dptr(ws), ws.numel(),
+                                   _stream(stream)))
+        return out
     _check(lib().sonar_ping(scene.handle, C.byref(p), C.byref(q), _dptr(out["volume"]), _dptr(out.get("gbuffer")),
                             _dptr(out.get("incoh")), C.byref(rec) if rec is not None else None, _dptr(ray_mask),
                             _stream(stream)))

@@ -43,6 +43,12 @@ def compare_rays(gpu: dict, orc: dict, rays) -> dict:
             g = np.where(np.asarray(orc["tri"])[ok] >= 0, g, 0)
             o = np.where(np.asarray(orc["tri"])[ok] >= 0, o, 0)
         res[key + "_mismatch"] = int((g != o).any(axis=1).sum())
+    if "beam" in gpu and "rxb" in orc:
+        # the beam each contribution is added to, where there is one
+        has = np.asarray(orc["bin"])[ok] >= 0
+        g = np.where(has, np.asarray(gpu["beam"])[rays][ok], -1)
+        o = np.where(has, np.asarray(orc["rxb"])[ok], -1)
+        res["beam_mismatch"] = int((g != o).any(axis=1).sum())
     res.update(flag_summary(orc["flags"]))
     return res
 

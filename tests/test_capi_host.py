@@ -141,3 +141,21 @@ def test_pulse_compress_validates_before_launch(L):
     assert b"overlap" in L.sonar_last_error()
     assert L.sonar_pulse_compress(vol, 4, 16, p, 2, out1, C.c_void_p(0x900000 + 64), None) == E  # outputs overlap
     assert L.sonar_pulse_compress(vol, 0, 16, p, 2, out1, None, None) == 0                       # nothing to do
+
+
+def test_rx_workspace_size(L):
+    cfg = S.sensor_seabed_boxes().replace(n_h=16, n_v=8, rays_per_beam=4, max_bounces=3)
+    p = sonar.params_of(cfg)
+    assert L.sonar_rx_workspace_size(C.byref(p)) == 256                      # no receive binning
+    p = sonar.params_of(cfg.replace(flags=sonar.FLAG_RX_BEAMS))
+    assert L.sonar_rx_workspace_size(C.byref(p)) == 256 + 16 * 16 * 8 * 4 * 2
+    p = sonar.params_of(cfg.replace(flags=sonar.FLAG_RX_BEAMS, max_bounces=1))
+    assert L.sonar_rx_workspace_size(C.byref(p)) == 256
+    p = sonar.params_of(cfg.replace(flags=8))
+    assert L.sonar_rx_workspace_size(C.byref(p)) == 0                        # unknown flag
+    p = sonar.params_of(cfg.replace(flags=sonar.FLAG_BEAM_PATTERN, grid_mode=1, rays_per_beam=1))
+    assert L.sonar_rx_workspace_size(C.byref(p)) == 0                        # cell beams only
+    # the detection workspace grows by the list when a ping_detect needs it
+    a = L.sonar_detect_workspace_size(C.byref(sonar.params_of(cfg)))
+    b = L.sonar_detect_workspace_size(C.byref(sonar.params_of(cfg.replace(flags=sonar.FLAG_RX_BEAMS))))
+    assert b >= a + 256 + 16 * 16 * 8 * 4 * 2

@@ -1,0 +1,95 @@
+"""Transmit-receive beam pattern and receive binning of later-bounce returns
+(Sec. II-B) on the GPU against the FP64 oracle, through the C-ABI (needs an
+MI355X)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2606_06130_amd import scenes as S
+from tests.test_gpu_parity import _gpu, _log, assert_parity, run_parity
+
+pytestmark = pytest.mark.gpu
+
+PATTERN, RX = 1, 2
+
+
+def _boxes(K, flags, **kw):
+    cfg = S.sensor_seabed_boxes().replace(n_h=16, n_v=8, rays_per_beam=4, n_range=256, max_bounces=K,
+                                          k_d=0.7, k_s=0.3 if K > 1 else 0.0, flags=flags, **kw)
+    return S.scene_seabed_boxes(), cfg, S.pose_seabed_boxes()
+
+
+@pytest.mark.parametrize("K,flags", [(1, PATTERN), (1, RX | PATTERN), (2, PATTERN), (2, RX), (3, RX | PATTERN)])
+def test_seabed_boxes_beam_options(K, flags):
+    mesh, cfg, pose = _boxes(K, flags)
+    res, g, orc = run_parity(mesh, cfg, pose)
+    assert_parity(res, K)
+    if flags & RX and K > 1:
+        launch = np.repeat(np.arange(cfg.n_beams), cfg.rays_per_beam)[:, None]
+        moved = (orc["rxb"][:, 1:] != launch) & (orc["bin"][:, 1:] >= 0) & (orc["flags"][:, None] == 0)
+        _log("moved returns", int(moved.sum()))
+        assert moved.sum() > 0
+
+
+def test_surface_multipath_receive_binning_gradient():
+    """Curved rays, a pressure-release surface and a wall: receive binning
+    with the pattern, three bounces."""
+    from tests import meshes as M
+    surf = M.mesh_from([M.big_triangle_z(2.0)], rho=1.0, phi=0.0, mat=S.MAT_PRESSURE_RELEASE)
+    wall = M.mesh_from([M.big_triangle_x(8.0)], rho=0.49, phi=0.7)
+    mesh = M.concat(surf, wall)
+    mesh.name = "surface_wall"
+    cfg = S.SensorConfig(hfov=math.radians(90), vfov=math.radians(40), n_h=16, n_v=8, rays_per_beam=4,
+                         n_range=512, max_bounces=3, k_d=0.7, k_s=0.3, c_grad=0.05, flags=RX | PATTERN)
+    res, g, orc = run_parity(mesh, cfg, S.pose((0.0, 0.0, 0.0)))
+    assert_parity(res, 3)
+
+
+def test_ping_detect_with_receive_binning_equals_ping_then_detect():
+    torch, sonar = _gpu()
+    mesh, cfg, pose = _boxes(3, RX | PATTERN)
+    sc = sonar.Scene(mesh)
+    d1 = sonar.Detector(cfg, train=8, guard=2)
+    v1 = sonar.alloc_outputs(cfg)["volume"]
+    d1.ping_detect(sc, v1, pose)
+    p1, n1 = d1.fetch()
+    out = sonar.ping(sc, cfg, pose)
+    d2 = sonar.Detector(cfg, train=8, guard=2)
+    d2(out["volume"], pose)
+    p2, n2 = d2.fetch()
+    torch.cuda.synchronize()
+    assert sc.status() == 0
+    assert n1 == n2 and n1 > 0
+    assert np.array_equal(p1["beam"], p2["beam"]) and np.array_equal(p1["bin"], p2["bin"])
+    assert torch.allclose(v1.view(torch.float32), out["volume"].view(torch.float32), rtol=1e-5, atol=1e-12)
+
+
+def test_receive_binning_rejections():
+    torch, sonar = _gpu()
+    mesh, cfg, pose = _boxes(2, RX)
+    sc = sonar.Scene(mesh)
+    p = sonar.params_of(cfg)
+    q = sonar.pose_of(pose)
+    vol = sonar.alloc_outputs(cfg)["volume"]
+    L = sonar.lib()
+    import ctypes as C
+    st = L.sonar_ping(sc.handle, C.byref(p), C.byref(q), sonar._dptr(vol), None, None, None, None, None)
+    assert st == sonar.SONAR_E_INVALID and b"sonar_ping_rx" in L.sonar_last_error()
+    ws = torch.empty(L.sonar_rx_workspace_size(C.byref(p)) - 16, dtype=torch.uint8, device="cuda")
+    st = L.sonar_ping_rx(sc.handle, C.byref(p), C.byref(q), sonar._dptr(vol), None, None, None, None,
+                         sonar._dptr(ws), ws.numel(), None)
+    assert st == sonar.SONAR_E_INVALID
+    with pytest.raises(sonar.SonarError) as e:
+        sonar.Batch(sc, [(cfg, pose)])
+    assert e.value.status == sonar.SONAR_E_UNSUPPORTED
+    with pytest.raises(sonar.SonarError) as e:
+        sonar.ping(sc, cfg.replace(grid_mode=1, rays_per_beam=1), pose)
+    assert e.value.status == sonar.SONAR_E_UNSUPPORTED
+    # the pattern alone runs in a batch (a weight, no list)
+    b = sonar.Batch(sc, [(cfg.replace(flags=PATTERN), pose)])
+    b.run()
+    torch.cuda.synchronize()
+    ref = sonar.ping(sc, cfg.replace(flags=PATTERN), pose)["volume"]
+    torch.cuda.synchronize()
+    assert torch.equal(b.volumes[0].view(torch.float32), ref.view(torch.float32))

@@ -72,6 +72,7 @@ def assert_parity(res, bounces=1):
     assert res["tri_mismatch"] == 0, res
     assert res["bin_mismatch"] == 0, res
     assert res["vis_mismatch"] == 0, res
+    assert res.get("beam_mismatch", 0) == 0, res
     assert res["vol_err"] <= VOL_TOL, res
     assert res["contrib_err"] <= VOL_TOL, res
     if "i1_err" in res:
