@@ -278,6 +278,25 @@ def pulse_compression(torch, sonar, np, cfg, pose, volume, reps=20):
             "gflop": flops / 1e9, "achieved_tflops": flops / ms / 1e9}
 
 
+def reverb_noise(torch, sonar, np, cfg, pose, volume, reps=20):
+    """Water-column reverberation (S_v = -50 dB) and receiver noise added in
+    place to a harbor ping's volume: one read-modify-write per cell."""
+    stream = torch.cuda.current_stream()
+    sonar.add_reverb(volume, cfg, pose, -50.0, 1e-13, 1)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for i, (a, b) in enumerate(ev):
+        a.record(stream)
+        sonar.add_reverb(volume, cfg, pose, -50.0, 1e-13, 2 + i)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    moved = 2 * volume.numel() * 8
+    return {"workload": f"S_v = -50 dB and noise into the harbor ping volume ({volume.numel() // cfg.n_range} beams x "
+                        f"{cfg.n_range} bins)", "ms": ms, "hbm_bytes": moved, "achieved_gbs": moved / ms / 1e6,
+            "frac_of_peak": moved / ms / 1e6 / 8000.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,6 +466,7 @@ def main():
     }
     if not args.no_extras:
         res["pulse_compression"] = pulse_compression(torch, sonar, np, cfg, pose, out["volume"])
+        res["reverberation"] = reverb_noise(torch, sonar, np, cfg, pose, out["volume"])
         del out, det
         mp, bt = multipath_and_batch(torch, sonar, S, np)
         res["multipath_ping"] = mp

@@ -262,6 +262,33 @@ sonar_status sonar_ping_detect(const sonar_scene *scene, const sonar_params *par
                                int32_t *dev_count, void *workspace, size_t workspace_bytes, sonar_stream stream);
 
 /* ---------------------------------------------------------------------- */
+/* Water-column volume reverberation and receiver noise (Sec. II-B:
+ * volumetric backscatter paths from the water column; speckle). Every range
+ * cell (beam b = v * n_h + h, bin n) of cell-centred beams holds unresolved
+ * scatterers: its echo is a circular complex Gaussian of mean power
+ *   P = s_v V / r^4 10^(-abs_db_per_m 2 r / 10) + noise_power,
+ * r = r_min + (n + 1/2) dr, V = r^2 cos(el_v) dth_h dth_v dr the cell volume
+ * (el_v the row's centre elevation), s_v = 10^(sv_db / 10) in 1/m. The
+ * sample sqrt(P / 2) sqrt(-2 ln u1) exp(2 pi i u2) is added to the cell, with
+ * u1 = ((z >> 40) + 1) / 2^24, u2 = ((z >> 16) mod 2^24) / 2^24 and
+ * z = SplitMix64 output number c + 1 of `seed`, c = (pose->ping << 43) xor
+ * (b << 12) xor n: fixed by the indices, reproducible in any order. The water
+ * behind the first surface is not shadowed. */
+typedef struct {
+    double sv_db;            /* volume scattering strength S_v (dB re 1/m) */
+    double noise_power;      /* receiver noise power per cell, >= 0 */
+    uint64_t seed;
+} sonar_reverb;
+
+/* Adds reverberation and noise to a ping's volume in place.
+ *   volume  device complex64 [beams_v][beams_h][n_range] of these params
+ * SONAR_E_INVALID for bad params, pose or settings (non-finite sv_db,
+ * negative noise); SONAR_E_UNSUPPORTED for grid_mode 1. Asynchronous on
+ * `stream`; no allocation. */
+sonar_status sonar_add_reverb(sonar_cf32 *volume, const sonar_params *params, const sonar_pose *pose,
+                              const sonar_reverb *reverb, sonar_stream stream);
+
+/* ---------------------------------------------------------------------- */
 /* Time series and matched filtering (Sec. II-B: time-series data next to the
  * intensity volumes, so that matched filtering can be applied). A beam's
  * complex range column x[n] is read as the scene's impulse response sampled

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsonar.so")
-SOURCES = ["bvh_build.hip", "ping.hip", "detect.hip", "pulse.hip", "surrogate.hip", "capi.hip"]
+SOURCES = ["bvh_build.hip", "ping.hip", "detect.hip", "pulse.hip", "reverb.hip", "surrogate.hip", "capi.hip"]
 HEADERS = ["internal.hpp", os.path.join("..", "..", "include", "sonar.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

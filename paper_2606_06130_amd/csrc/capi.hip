@@ -484,6 +484,37 @@ sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, con
 }
 
 
+sonar_status sonar_add_reverb(sonar_cf32 *volume, const sonar_params *p, const sonar_pose *q,
+                              const sonar_reverb *rv, sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar_status st = check_params(p);
+    if (st != SONAR_OK) return st;
+    if ((st = check_pose(q)) != SONAR_OK) return st;
+    if (!volume || !rv) return fail(SONAR_E_INVALID, "volume and reverb are required");
+    if (p->grid_mode != 0) return fail(SONAR_E_UNSUPPORTED, "reverberation needs cell-centred beams (grid_mode 0)");
+    if (!isfinite(rv->sv_db) || !(rv->noise_power >= 0) || !isfinite(rv->noise_power))
+        return fail(SONAR_E_INVALID, "sv_db must be finite and noise_power finite and >= 0");
+    sonar::ReverbArgs a;
+    a.volume = reinterpret_cast<float2 *>(volume);
+    a.beams_h = beams_h_of(p);
+    a.n_beams = (int64_t)a.beams_h * beams_v_of(p);
+    a.n_bins = p->n_range;
+    a.r_min = (float)p->r_min;
+    a.dr = (float)((p->r_max - p->r_min) / p->n_range);
+    a.vfov = (float)p->vfov;
+    a.dth_v = (float)(p->vfov / p->n_v);
+    a.cell_solid = (float)((p->hfov / p->n_h) * (p->vfov / p->n_v));
+    a.sv = (float)pow(10.0, rv->sv_db / 10.0);
+    a.alpha_db = (float)p->abs_db_per_m;
+    a.noise = (float)rv->noise_power;
+    a.seed = rv->seed;
+    a.ping = q->ping;
+    hipError_t e = sonar::launch_reverb(a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "reverberation launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
 static_assert(SONAR_MAX_PULSE_TAPS == sonar::MAX_PULSE_TAPS, "pulse tap bound");
 static_assert(SONAR_MAX_PULSE_BINS == sonar::MAX_PULSE_BINS, "pulse bin bound");
 

@@ -43,6 +43,16 @@ struct Scene {
     int device = 0;
 };
 
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output number n of the
+// generator seeded with `seed`.
+__device__ __forceinline__ uint64_t splitmix64_nth(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + n * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // Device status bits.
 constexpr int ST_STACK = 1;
 constexpr int ST_BAD_INDEX = 2;
@@ -162,6 +172,18 @@ struct PulseArgs {
     float2 p[MAX_PULSE_TAPS];
 };
 hipError_t launch_pulse(const PulseArgs &a, hipStream_t s);
+
+// Volume reverberation and receiver noise (reverb.hip).
+struct ReverbArgs {
+    float2 *volume;          // [n_beams][n_bins], updated in place
+    int64_t n_beams;
+    int n_bins, beams_h;
+    float r_min, dr, vfov, dth_v, cell_solid;   // cell_solid = dth_h * dth_v
+    float sv, alpha_db, noise;
+    uint64_t seed;
+    uint32_t ping;
+};
+hipError_t launch_reverb(const ReverbArgs &a, hipStream_t s);
 
 // Learned multipath surrogate (surrogate.hip).
 struct Surrogate;

@@ -71,16 +71,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output number n of the
-// generator seeded with `seed`.
-__device__ __forceinline__ uint64_t splitmix64_nth(uint64_t seed, uint64_t n)
-{
-    uint64_t z = seed + n * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 // Scene arrays as global-memory pointers: a pointer read from a batch
 // descriptor is otherwise generic and its loads become flat loads.
 typedef float f4v __attribute__((ext_vector_type(4)));

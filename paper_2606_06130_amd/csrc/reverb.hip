@@ -1,0 +1,53 @@
+// Water-column volume reverberation and receiver noise (Sec. II-B: volumetric
+// backscatter from the water column; speckle). Every range cell of a
+// cell-centred beam layout receives a circular complex Gaussian sample whose
+// mean power is s_v V / r^4 10^(-alpha 2 r / 10) + N0, V = r^2 cos(el)
+// dth_h dth_v dr the cell's volume at its centre range r and elevation el.
+// The sample is sqrt(P / 2) sqrt(-2 ln u1) e^(2 pi i u2) (Box-Muller) with
+// u1 = (top 24 bits + 1) / 2^24 and u2 = the next 24 bits / 2^24 of
+// SplitMix64(seed, c + 1), c = (ping << 43) ^ (beam << 12) ^ bin, so every
+// cell's sample is fixed by its indices (no state, any launch order).
+//
+// k_reverb: grid x = beams, grid y = chunks of 256 bins; one cell per thread,
+// read-modify-write of the volume (HBM-bound: 16 bytes per cell).
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace sonar {
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_reverb(ReverbArgs a)
+{
+    const int64_t b = blockIdx.x;
+    const int n = blockIdx.y * 256 + threadIdx.x;
+    if (n >= a.n_bins) return;
+    const int v = (int)(b / a.beams_h);
+    const float r = a.r_min + ((float)n + 0.5f) * a.dr;
+    const float el = -0.5f * a.vfov + ((float)v + 0.5f) * a.dth_v;
+    const float P = a.sv * cosf(el) * a.cell_solid * a.dr / (r * r) * exp10f(-0.2f * a.alpha_db * r) + a.noise;
+    const uint64_t c = ((uint64_t)a.ping << 43) ^ ((uint64_t)b << 12) ^ (uint64_t)n;
+    const uint64_t z = splitmix64_nth(a.seed, c + 1);
+    const float u1 = (float)((z >> 40) + 1) * (1.f / 16777216.f);
+    const float u2 = (float)((z >> 16) & 0xFFFFFFull) * (1.f / 16777216.f);
+    float sn, cs;
+    sincospif(2.f * u2, &sn, &cs);
+    const float amp = sqrtf(0.5f * P) * sqrtf(-2.f * logf(u1));
+    float2 &cell = a.volume[b * a.n_bins + n];
+    float2 e = cell;
+    e.x = fmaf(amp, cs, e.x);
+    e.y = fmaf(amp, sn, e.y);
+    cell = e;
+}
+
+}  // namespace
+
+hipError_t launch_reverb(const ReverbArgs &a, hipStream_t s)
+{
+    if (a.n_beams == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reverb, dim3((unsigned)a.n_beams, (unsigned)((a.n_bins + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sonar

@@ -36,7 +36,7 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_set_norm", "sonar_surrogate_forward", "sonar_surrogate_train_step",
            "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
-           "sonar_rx_workspace_size", "sonar_ping_rx")
+           "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb")
 
 
 class SonarError(RuntimeError):
@@ -80,6 +80,10 @@ class sonar_scene_info(C.Structure):
     _fields_ = [("n_triangles", C.c_int64), ("n_nodes", C.c_int64), ("depth", C.c_int32),
                 ("leaf_size", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3),
                 ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64)]
+
+
+class sonar_reverb(C.Structure):
+    _fields_ = [("sv_db", C.c_double), ("noise_power", C.c_double), ("seed", C.c_uint64)]
 
 
 class sonar_batch_plan(C.Structure):
@@ -190,6 +194,8 @@ def lib():
                                               C.c_void_p, C.c_void_p, C.c_void_p]
         L.sonar_params_from_resolution.restype = C.c_int
         L.sonar_params_from_resolution.argtypes = [C.c_double] * 7 + [P(sonar_params)]
+        L.sonar_add_reverb.restype = C.c_int
+        L.sonar_add_reverb.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_reverb), C.c_void_p]
         L.sonar_rx_workspace_size.restype = C.c_size_t
         L.sonar_rx_workspace_size.argtypes = [P(sonar_params)]
         L.sonar_ping_rx.restype = C.c_int
@@ -403,6 +409,14 @@ def params_from_resolution(hfov, vfov, dth_h, dth_v, r_min, r_max, dr, base=None
 
 
 MAX_PULSE_TAPS = 64
+
+
+def add_reverb(volume, cfg, pose, sv_db: float, noise_power: float = 0.0, seed: int = 1, stream=None):
+    """Adds water-column reverberation and receiver noise to a ping's volume in place."""
+    rv = sonar_reverb(sv_db=float(sv_db), noise_power=float(noise_power), seed=int(seed))
+    _check(lib().sonar_add_reverb(_dptr(volume), C.byref(params_of(cfg)), C.byref(pose_of(pose)), C.byref(rv),
+                                  _stream(stream)))
+    return volume
 
 
 def pulse_dt(cfg, pose) -> float:

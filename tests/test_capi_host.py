@@ -159,3 +159,19 @@ def test_rx_workspace_size(L):
     a = L.sonar_detect_workspace_size(C.byref(sonar.params_of(cfg)))
     b = L.sonar_detect_workspace_size(C.byref(sonar.params_of(cfg.replace(flags=sonar.FLAG_RX_BEAMS))))
     assert b >= a + 256 + 16 * 16 * 8 * 4 * 2
+
+
+def test_add_reverb_validates_before_launch(L):
+    cfg = S.sensor_seabed_boxes()
+    p = sonar.params_of(cfg)
+    q = sonar.pose_of(S.pose_seabed_boxes())
+    vol = C.c_void_p(0x100000)
+    good = sonar.sonar_reverb(sv_db=-40.0, noise_power=0.0, seed=1)
+    assert L.sonar_add_reverb(None, C.byref(p), C.byref(q), C.byref(good), None) == sonar.SONAR_E_INVALID
+    assert L.sonar_add_reverb(vol, C.byref(p), C.byref(q), None, None) == sonar.SONAR_E_INVALID
+    for bad in (sonar.sonar_reverb(sv_db=float("inf"), noise_power=0.0, seed=1),
+                sonar.sonar_reverb(sv_db=-40.0, noise_power=-1.0, seed=1),
+                sonar.sonar_reverb(sv_db=float("nan"), noise_power=0.0, seed=1)):
+        assert L.sonar_add_reverb(vol, C.byref(p), C.byref(q), C.byref(bad), None) == sonar.SONAR_E_INVALID
+    p1 = sonar.params_of(cfg.replace(grid_mode=1, rays_per_beam=1))
+    assert L.sonar_add_reverb(vol, C.byref(p1), C.byref(q), C.byref(good), None) == sonar.SONAR_E_UNSUPPORTED
