@@ -43,7 +43,9 @@ class Params(C.Structure):
                 ("alpha_db", C.c_double),
                 ("max_bounces", C.c_int32), ("pad0", C.c_int32),
                 ("k_d", C.c_double), ("k_s", C.c_double), ("phong_n", C.c_double),
-                ("seed", C.c_uint64), ("ping", C.c_uint32), ("flags", C.c_uint32)]
+                ("seed", C.c_uint64), ("ping", C.c_uint32), ("flags", C.c_uint32),
+                ("n_knots", C.c_int32), ("pad2", C.c_int32),
+                ("knot_z", C.c_double * 8), ("knot_c", C.c_double * 8)]
 
 
 class PoseS(C.Structure):
@@ -113,7 +115,18 @@ def _ptr(a):
 
 
 def params_of(cfg, ping: int = 0) -> Params:
-    """Oracle parameters from a ``scenes.SensorConfig``."""
+    """Oracle parameters from a ``scenes.SensorConfig`` (``cfg.ssp``: knots
+    (z, c) of a piecewise-linear sound speed, or empty)."""
+    p = _params(cfg, ping)
+    knots = list(getattr(cfg, "ssp", ()) or ())
+    p.n_knots = len(knots)
+    for i, (z, c) in enumerate(knots[:8]):
+        p.knot_z[i] = z
+        p.knot_c[i] = c
+    return p
+
+
+def _params(cfg, ping: int = 0) -> Params:
     return Params(hfov=cfg.hfov, vfov=cfg.vfov, n_h=cfg.n_h, n_v=cfg.n_v, n_r=cfg.rays_per_beam,
                   grid_mode=cfg.grid_mode, jitter=cfg.jitter, n_bins=cfg.n_range,
                   r_min=cfg.r_min, r_max=cfg.r_max, f0=cfg.freq_hz, c0=cfg.c0, g=cfg.c_grad,

@@ -37,6 +37,7 @@
 
 #define ORC_PI 3.14159265358979323846
 #define ORC_MAXK 8
+#define ORC_MAXKNOTS 8
 
 /* Beam forming options (Sec. II-B: the backscattered contribution depends on
  * the transmit-receive beam pattern).
@@ -85,6 +86,9 @@ typedef struct {
     uint64_t seed;
     uint32_t ping;
     uint32_t flags;              /* ORC_BEAM_PATTERN | ORC_RX_BEAMS */
+    int32_t n_knots;             /* >= 2: piecewise-linear c(z) through the knots (replaces c0, g) */
+    int32_t pad2;
+    double knot_z[ORC_MAXKNOTS], knot_c[ORC_MAXKNOTS];
 } orc_params;
 
 typedef struct { double pos[3]; double rot[9]; } orc_pose;   /* sensor->world, row-major */
@@ -307,18 +311,20 @@ typedef struct {
     double kappa;
 } opath;
 
-static opath make_path(const orc_params *P, v3 o, v3 d)
+static opath make_path_gc(double g, double c0, v3 o, v3 d)
 {
     opath r;
     r.o = o; r.d = d; r.arc = 0; r.kappa = 0.0; r.nc = mk(0, 0, 0);
     double dh = hypot(d.x, d.y);
-    if (P->g == 0.0 || dh == 0.0) return r;
-    double c = P->c0 + P->g * o.z;
+    if (g == 0.0 || dh == 0.0) return r;
+    double c = c0 + g * o.z;
     r.arc = 1;
-    r.kappa = P->g * dh / c;
+    r.kappa = g * dh / c;
     r.nc = mk(d.z * d.x / dh, d.z * d.y / dh, -dh);
     return r;
 }
+
+static opath make_path(const orc_params *P, v3 o, v3 d) { return make_path_gc(P->g, P->c0, o, d); }
 
 static v3 path_point(const opath *p, double s)
 {
@@ -339,13 +345,13 @@ static v3 path_tangent(const opath *p, double s)
  * integral of ds / c along a circle of a linear profile is
  * (atanh(sin th0) - atanh(sin th1)) / g (Jensen et al., Computational Ocean
  * Acoustics, ch. 3), written with log1p so that no large terms cancel. */
-static double path_time(const orc_params *P, const opath *p, double s)
+static double path_time_gc(double g, double c0, const opath *p, double s)
 {
     if (!p->arc) {
-        if (P->g == 0.0) return s / P->c0;
+        if (g == 0.0) return s / c0;
         /* vertical ray: dt = dz / c(z) */
         double z0 = p->o.z, dz = p->d.z * s;
-        return fabs(log1p(P->g * dz / (P->c0 + P->g * z0)) / P->g);
+        return fabs(log1p(g * dz / (c0 + g * z0)) / g);
     }
     double u = p->kappa * s;
     double sh = sin(0.5 * u);
@@ -355,11 +361,73 @@ static double path_time(const orc_params *P, const opath *p, double s)
     double ds = p->d.z * omc + dh * sin(u);           /* sin th0 - sin th1 */
     double s1 = s0 - ds;
     double dz = (p->d.z * sin(u) + p->nc.z * omc) / p->kappa;
-    double lc = log1p(P->g * dz / (P->c0 + P->g * p->o.z));   /* ln(c1 / c0) */
+    double lc = log1p(g * dz / (c0 + g * p->o.z));   /* ln(c1 / c0) */
     double t;
     if (s0 >= 0.0) t = log1p(ds / (1.0 + s1)) + lc;
     else t = log1p(ds / (1.0 - s0)) - lc;
-    return t / P->g;
+    return t / g;
+}
+
+static double path_time(const orc_params *P, const opath *p, double s) { return path_time_gc(P->g, P->c0, p, s); }
+
+/* ------------------------------------------------------------------------ */
+/* Piecewise-linear sound speed (a general depth-dependent profile): layer i */
+/* spans knots i..i+1 with c linear in it (the first and last layers extend  */
+/* to -inf and +inf). Inside a layer the ray is that layer's circle; at a    */
+/* boundary it continues with the same direction (c is continuous, so the    */
+/* Snell invariant cos(theta) / c carries over) and the next curvature.      */
+
+static int layer_count(const orc_params *P) { return P->n_knots - 1; }
+
+static double layer_g(const orc_params *P, int i)
+{
+    return (P->knot_c[i + 1] - P->knot_c[i]) / (P->knot_z[i + 1] - P->knot_z[i]);
+}
+
+static double layer_c0(const orc_params *P, int i) { return P->knot_c[i] - layer_g(P, i) * P->knot_z[i]; }
+
+static int layer_of(const orc_params *P, double z)
+{
+    int i = 0;
+    while (i + 1 < layer_count(P) && z >= P->knot_z[i + 1]) ++i;
+    return i;
+}
+
+static double profile_c(const orc_params *P, double z)
+{
+    int i = layer_of(P, z);
+    return layer_c0(P, i) + layer_g(P, i) * z;
+}
+
+/* Arc length at which path p (in layer i) leaves the layer, and the layer it
+ * enters (-1: never). The grazing angle along a circle of curvature k is
+ * theta(s) = theta0 - k s, and at a boundary z_b Snell gives
+ * cos(theta_b) = cos(theta0) c(z_b) / c(o); the upper boundary is reached
+ * going up (theta_b > 0), the lower one going down. */
+static double layer_exit(const orc_params *P, int i, const opath *p, double g, double c0, int *next,
+                         uint32_t *flags)
+{
+    const int nl = layer_count(P);
+    double best = HUGE_VAL;
+    *next = -1;
+    const double zb[2] = {i + 1 < nl ? P->knot_z[i + 1] : HUGE_VAL, i > 0 ? P->knot_z[i] : -HUGE_VAL};
+    if (!p->arc) {
+        if (p->d.z > 0.0 && zb[0] < HUGE_VAL) { best = (zb[0] - p->o.z) / p->d.z; *next = i + 1; }
+        if (p->d.z < 0.0 && zb[1] > -HUGE_VAL) { best = (zb[1] - p->o.z) / p->d.z; *next = i - 1; }
+        return best;
+    }
+    const double sz = p->d.z > 1.0 ? 1.0 : (p->d.z < -1.0 ? -1.0 : p->d.z);
+    const double th0 = asin(sz), cth = hypot(p->d.x, p->d.y), co = c0 + g * p->o.z;
+    for (int t = 0; t < 2; ++t) {
+        if (!(fabs(zb[t]) < HUGE_VAL)) continue;
+        const double C = cth * (c0 + g * zb[t]) / co;
+        if (fabs(C - 1.0) < 1e-9) *flags |= F_LIMIT;      /* turning point at the boundary */
+        if (C > 1.0) continue;
+        const double thb = t == 0 ? acos(C) : -acos(C);
+        const double s = (th0 - thb) / p->kappa;
+        if (s > 1e-12 && s < best) { best = s; *next = t == 0 ? i + 1 : i - 1; }
+    }
+    return best;
 }
 
 /* Roots s in (0, hi] of the path meeting the plane of triangle i. */
@@ -412,7 +480,16 @@ typedef struct {
     uint32_t flags;
 } ohit;
 
+static ohit nearest_hit_from(const oscene *S, const opath *p, int64_t prev, double s_min, double s_lim,
+                             const orc_tol *T);
+
 static ohit nearest_hit(const oscene *S, const opath *p, int64_t prev, double s_lim, const orc_tol *T)
+{
+    return nearest_hit_from(S, p, prev, EPS_SELF, s_lim, T);
+}
+
+static ohit nearest_hit_from(const oscene *S, const opath *p, int64_t prev, double s_min, double s_lim,
+                             const orc_tol *T)
 {
     ohit h;
     h.tri = -1; h.s = 0.0; h.flags = 0;
@@ -428,7 +505,7 @@ static ohit nearest_hit(const oscene *S, const opath *p, int64_t prev, double s_
             double s = r[t];
             v3 X = path_point(p, s);
             double de = edge_distance(S, i, X);
-            if (s > EPS_SELF && s <= s_lim && de >= 0.0 && s < best) {
+            if (s > s_min && s <= s_lim && de >= 0.0 && s < best) {
                 best = s;
                 h.tri = i;
             }
@@ -570,6 +647,14 @@ static double upper_speed(const orc_params *P, const oscene *S, const orc_pose *
     /* an upper bound of c(z) over the scene and the sensor, with 1 m margin */
     double z = S->zabs_max;
     if (fabs(Q->pos[2]) > z) z = fabs(Q->pos[2]);
+    if (P->n_knots >= 2) {
+        /* c is linear between knots: its largest value over [-z-1, z+1] is at an end or a knot */
+        double c = profile_c(P, z + 1.0), c2 = profile_c(P, -z - 1.0);
+        if (c2 > c) c = c2;
+        for (int i = 0; i < P->n_knots; ++i)
+            if (fabs(P->knot_z[i]) <= z + 1.0 && P->knot_c[i] > c) c = P->knot_c[i];
+        return c;
+    }
     return P->c0 + fabs(P->g) * (z + 1.0);
 }
 
@@ -592,32 +677,75 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
     const double w_tx = pattern ? lobe_gauss(d_az, d_el, dh, dv) : 1.0;
     const int K = P->max_bounces;
     const v3 Sp = mk(Q->pos[0], Q->pos[1], Q->pos[2]);
-    const double c_ref = P->c0 + P->g * Sp.z;              /* time-to-range speed */
+    const int layered = P->n_knots >= 2;
+    const double c_ref = layered ? profile_c(P, Sp.z) : P->c0 + P->g * Sp.z;   /* time-to-range speed */
     const double c_hi = upper_speed(P, S, Q);
     const double dr = (P->r_max - P->r_min) / P->n_bins;
     double L_out = 0.0, T_out = 0.0, W = 1.0;
     int64_t prev = -1;
     for (int k = 0; k < K; ++k) {
-        opath path = make_path(P, o, d);
-        double s_lim, T_lim = 0.0;
-        if (P->g == 0.0) {
-            s_lim = (K == 1) ? P->r_max : 2.0 * P->r_max - L_out;
-        } else {
-            T_lim = (K == 1) ? P->r_max / c_ref : 2.0 * P->r_max / c_ref - T_out;
-            s_lim = c_hi * T_lim;
-        }
-        if (s_lim <= EPS_SELF) break;
-        ohit h = nearest_hit(S, &path, prev, s_lim, T);
-        out->flags |= h.flags;
-        if (h.tri < 0) break;
-        double tau = path_time(P, &path, h.s);
-        if (P->g != 0.0) {
+        ohit h;
+        double tau, s_len;
+        v3 X, din;
+        if (layered) {
+            /* single bounce through the layers: one circle per layer, in order */
+            if (K != 1) return;
+            const double T_lim = P->r_max / c_ref;
+            int layer = layer_of(P, o.z);
+            /* a sensor exactly on a knot, looking down, starts in the layer below */
+            if (layer > 0 && o.z == P->knot_z[layer] && d.z < 0.0) --layer;
+            double t_acc = 0.0, s_acc = 0.0;
+            v3 po = o, pd = d;
+            h.tri = -1;
+            for (int piece = 0; piece < 64; ++piece) {
+                const double g = layer_g(P, layer), c0 = layer_c0(P, layer);
+                opath path = make_path_gc(g, c0, po, pd);
+                int next;
+                const double s_exit = layer_exit(P, layer, &path, g, c0, &next, &out->flags);
+                const double s_cap = c_hi * (T_lim - t_acc);
+                const double s_end = s_exit < s_cap ? s_exit : s_cap;
+                h = nearest_hit_from(S, &path, prev, piece == 0 ? EPS_SELF : 0.0, s_end, T);
+                out->flags |= h.flags;
+                if (h.tri >= 0) {
+                    tau = t_acc + path_time_gc(g, c0, &path, h.s);
+                    s_len = s_acc + h.s;
+                    X = path_point(&path, h.s);
+                    din = path_tangent(&path, h.s);
+                    break;
+                }
+                if (next < 0 || s_exit >= s_cap) break;
+                t_acc += path_time_gc(g, c0, &path, s_exit);
+                s_acc += s_exit;
+                po = path_point(&path, s_exit);
+                pd = unit(path_tangent(&path, s_exit));
+                layer = next;
+            }
+            if (h.tri < 0) break;
             if (fabs(tau - T_lim) <= T->lim_rel * T_lim) out->flags |= F_LIMIT;
             if (tau > T_lim) break;
+        } else {
+            opath path = make_path(P, o, d);
+            double s_lim, T_lim = 0.0;
+            if (P->g == 0.0) {
+                s_lim = (K == 1) ? P->r_max : 2.0 * P->r_max - L_out;
+            } else {
+                T_lim = (K == 1) ? P->r_max / c_ref : 2.0 * P->r_max / c_ref - T_out;
+                s_lim = c_hi * T_lim;
+            }
+            if (s_lim <= EPS_SELF) break;
+            h = nearest_hit(S, &path, prev, s_lim, T);
+            out->flags |= h.flags;
+            if (h.tri < 0) break;
+            tau = path_time(P, &path, h.s);
+            if (P->g != 0.0) {
+                if (fabs(tau - T_lim) <= T->lim_rel * T_lim) out->flags |= F_LIMIT;
+                if (tau > T_lim) break;
+            }
+            X = path_point(&path, h.s);
+            din = path_tangent(&path, h.s);
+            s_len = h.s;
         }
-        v3 X = path_point(&path, h.s);
-        v3 din = path_tangent(&path, h.s);
-        L_out += h.s;
+        L_out += s_len;
         T_out += tau;
         int64_t f = h.tri;
         out->tri[k] = (int32_t)f;
@@ -752,6 +880,14 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
     if (P->max_bounces < 1 || P->max_bounces > ORC_MAXK) return -1;
     const int K = P->max_bounces, NB = P->n_bins, NR = P->n_r;
     if (P->flags && P->grid_mode != 0) return -3;            /* beam options: cell-centred beams only */
+    if (P->n_knots != 0) {
+        /* a layered profile: single bounce, 2..8 knots with increasing depth and positive speed */
+        if (P->max_bounces != 1 || P->n_knots < 2 || P->n_knots > ORC_MAXKNOTS) return -5;
+        for (int i = 0; i < P->n_knots; ++i) {
+            if (!(P->knot_c[i] > 0.0)) return -5;
+            if (i > 0 && !(P->knot_z[i] > P->knot_z[i - 1])) return -5;
+        }
+    }
     const int rx = (P->flags & ORC_RX_BEAMS) != 0;
     if (rx) {
         /* contributions move between beams: every beam, in order */

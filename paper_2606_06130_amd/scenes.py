@@ -77,6 +77,7 @@ class SensorConfig:
     phong_n: float = 20.0
     seed: int = 1000
     flags: int = 0
+    ssp: tuple = ()           # knots (z, c) of a piecewise-linear sound speed (replaces c0, c_grad), or ()
     extra: dict = field(default_factory=dict)
 
     @property
