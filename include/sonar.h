@@ -212,6 +212,30 @@ sonar_status sonar_ping(const sonar_scene *scene, const sonar_params *params, co
                         sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *record,
                         const uint32_t *ray_mask, sonar_stream stream);
 
+/* A general depth-dependent sound speed (Sec. II-A: rays bend by Snell's
+ * law in a spatially varying sound-speed field): c(z) piecewise linear
+ * through n_knots knots (z[k], c[k]), z strictly increasing, c > 0; the
+ * first and last layers extend below z[0] and above z[n-1]. Inside a layer
+ * a ray is that layer's circle; at a knot it continues with the same
+ * direction (c is continuous) and the next curvature. */
+#define SONAR_MAX_SSP_KNOTS 8
+typedef struct {
+    int32_t n_knots, pad;
+    double z[SONAR_MAX_SSP_KNOTS];
+    double c[SONAR_MAX_SSP_KNOTS];
+} sonar_ssp;
+
+/* sonar_ping through a piecewise-linear sound-speed profile (params->c0 and
+ * c_grad are replaced by it; times convert to range with c at the sensor).
+ * Single bounce only (max_bounces 1, else SONAR_E_UNSUPPORTED). Also
+ * SONAR_E_INVALID for 2 > n_knots > SONAR_MAX_SSP_KNOTS, knots not strictly
+ * increasing, c <= 0 at a knot or over the scene, and SONAR_E_UNSUPPORTED for
+ * layers bending more than |g| 2 r_max / c = 1e-2. Asynchronous on
+ * `stream`; no workspace. */
+sonar_status sonar_ping_ssp(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
+                            const sonar_ssp *ssp, sonar_cf32 *volume, float *gbuffer, float *incoh,
+                            const sonar_ray_record *record, const uint32_t *ray_mask, sonar_stream stream);
+
 /* Bytes of device workspace sonar_ping_rx needs: a list of up to
  * n_rays * (max_bounces - 1) returns that receive binning moves to another
  * beam (16 bytes each) and its counter; 0 when the parameters are invalid. */

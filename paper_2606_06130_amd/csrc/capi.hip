@@ -386,6 +386,70 @@ sonar_status sonar_ping(const sonar_scene *sc, const sonar_params *p, const sona
     return SONAR_OK;
 }
 
+static_assert(SONAR_MAX_SSP_KNOTS == sonar::MAX_SSP_KNOTS, "profile knots");
+
+sonar_status sonar_ping_ssp(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, const sonar_ssp *ssp,
+                            sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *rec,
+                            const uint32_t *ray_mask, sonar_stream stream)
+{
+    g_err[0] = 0;
+    if (!ssp) return fail(SONAR_E_INVALID, "ssp is NULL");
+    if (!sc) return fail(SONAR_E_INVALID, "scene is NULL");
+    sonar_status st = check_params(p);
+    if (st != SONAR_OK) return st;
+    if ((st = check_pose(q)) != SONAR_OK) return st;
+    const int n = ssp->n_knots;
+    if (n < 2 || n > SONAR_MAX_SSP_KNOTS)
+        return fail(SONAR_E_INVALID, "n_knots must be in [2, %d]", SONAR_MAX_SSP_KNOTS);
+    for (int k = 0; k < n; ++k) {
+        if (!isfinite(ssp->z[k]) || !(ssp->c[k] > 0) || !isfinite(ssp->c[k]))
+            return fail(SONAR_E_INVALID, "knot %d: z finite and c > 0 required", k);
+        if (k > 0 && !(ssp->z[k] > ssp->z[k - 1])) return fail(SONAR_E_INVALID, "knot depths must increase");
+    }
+    if (p->max_bounces != 1) return fail(SONAR_E_UNSUPPORTED, "layered profiles take single-bounce pings");
+    const int nl = n - 1;
+    double g[SONAR_MAX_SSP_KNOTS], c0[SONAR_MAX_SSP_KNOTS];
+    for (int i = 0; i < nl; ++i) {
+        g[i] = (ssp->c[i + 1] - ssp->c[i]) / (ssp->z[i + 1] - ssp->z[i]);
+        c0[i] = ssp->c[i] - g[i] * ssp->z[i];
+    }
+    auto layer_of = [&](double z) {
+        int i = 0;
+        while (i + 1 < nl && z >= ssp->z[i + 1]) ++i;
+        return i;
+    };
+    auto c_at = [&](double z) { const int i = layer_of(z); return c0[i] + g[i] * z; };
+    // c over the scene and the sensor (1 m margin): its extremes are at the ends or at knots
+    const double zmax = fmax((double)sc->s.zabs_max, fabs(q->position[2])) + 1.0;
+    double c_lo = fmin(c_at(-zmax), c_at(zmax)), c_hi = fmax(c_at(-zmax), c_at(zmax));
+    for (int k = 0; k < n; ++k)
+        if (fabs(ssp->z[k]) <= zmax) {
+            c_lo = fmin(c_lo, ssp->c[k]);
+            c_hi = fmax(c_hi, ssp->c[k]);
+        }
+    if (!(c_lo > 0.0)) return fail(SONAR_E_INVALID, "the profile's sound speed must stay positive over the scene");
+    for (int i = 0; i < nl; ++i)
+        if (fabs(g[i]) * 2.0 * p->r_max / c_lo > 1e-2)
+            return fail(SONAR_E_UNSUPPORTED, "layer %d bends too strongly for one chord per layer", i);
+    sonar_params pp = *p;
+    pp.c_grad = 0.0;
+    pp.c0 = c_at(q->position[2]);
+    sonar::PingArgs a;
+    st = fill_ping_args(sc, &pp, q, volume, gbuffer, incoh, rec, ray_mask, &a);
+    if (st != SONAR_OK) return st;
+    a.n_layers = nl;
+    for (int k = 0; k < n; ++k) a.lay_z[k] = ssp->z[k];
+    for (int i = 0; i < nl; ++i) {
+        a.lay_g[i] = g[i];
+        a.lay_c0[i] = c0[i];
+    }
+    a.c_ref = pp.c0;
+    a.c_hi = c_hi;
+    hipError_t e = sonar::launch_ping_layered(a, sc->s.stack, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
 size_t sonar_rx_workspace_size(const sonar_params *p)
 {
     if (check_params(p) != SONAR_OK) return 0;

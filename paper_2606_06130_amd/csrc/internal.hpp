@@ -63,6 +63,7 @@ constexpr int ST_RX_FULL = 32;
 
 // Everything a ping kernel needs, by value.
 constexpr uint32_t FLAG_BEAM_PATTERN = 1u;
+constexpr int MAX_SSP_KNOTS = 8;
 constexpr uint32_t FLAG_RX_BEAMS = 2u;
 
 struct PingArgs {
@@ -101,6 +102,11 @@ struct PingArgs {
     double det_alpha[2 * 64 + 1];
     // beam forming: FLAG_BEAM_PATTERN / FLAG_RX_BEAMS; returns binned to
     // another beam go to rx_list (beam, bin, re, im) through rx_count
+    // piecewise-linear sound speed (n_layers > 0): knots lay_z[0..n_layers],
+    // layer i spans [lay_z[i], lay_z[i+1]] (the first and last extend to
+    // -inf and +inf) with c = lay_c0[i] + lay_g[i] z
+    int n_layers;
+    double lay_z[MAX_SSP_KNOTS], lay_g[MAX_SSP_KNOTS], lay_c0[MAX_SSP_KNOTS];
     uint32_t flags;
     uint32_t rx_cap;
     int4 *rx_list;
@@ -132,6 +138,8 @@ int batch_max_blocks_per_cu(const BatchLaunch &b);
 
 // Host-side launchers (one per translation unit).
 hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s);
+// Single-bounce ping through a piecewise-linear sound-speed profile.
+hipError_t launch_ping_layered(const PingArgs &a, int stack_depth, hipStream_t s);
 // Receive binning: clear the list's counter before a ping; add the listed
 // returns into their beams' columns after it.
 hipError_t launch_rx_reset(uint32_t *count, hipStream_t s);

@@ -549,6 +549,116 @@ __device__ __forceinline__ Conn connect(d3 P, d3 S, double g, double c0)
 
 }  // namespace
 
+// First hit of a ray: the triangle record, FP64 arc length along the whole
+// path, one-way time, hit point, facet normal and arrival tangent.
+struct Hit64 {
+    bool ok;
+    TriF tr;
+    d3 nh, X, din;
+    double s, tau;
+};
+
+// Piecewise-linear sound speed: the layer holding z (a point on a knot
+// belongs to the layer above it).
+__device__ __forceinline__ int layer_of(const PingArgs &a, double z)
+{
+    int i = 0;
+    while (i + 1 < a.n_layers && z >= a.lay_z[i + 1]) ++i;
+    return i;
+}
+
+// Arc length at which path p leaves layer i and the layer it enters (-1:
+// never). Along a circle of curvature k the grazing angle is th0 - k s; at a
+// boundary z_b Snell's invariant gives cos(th_b) = cos(th0) c(z_b) / c(o),
+// reached going up at the upper boundary and going down at the lower one.
+__device__ double layer_exit(const PingArgs &a, const int i, const Path64 &p, const double g, const double c0, int &next)
+{
+    double best = INFINITY;
+    next = -1;
+    const bool up = i + 1 < a.n_layers, down = i > 0;
+    if (!p.arc) {
+        if (p.d.z > 0.0 && up) {
+            best = (a.lay_z[i + 1] - p.o.z) / p.d.z;
+            next = i + 1;
+        }
+        if (p.d.z < 0.0 && down) {
+            best = (a.lay_z[i] - p.o.z) / p.d.z;
+            next = i - 1;
+        }
+        return best;
+    }
+    const double th0 = asin(fmin(1.0, fmax(-1.0, p.d.z)));
+    const double cth = sqrt(p.d.x * p.d.x + p.d.y * p.d.y), co = c0 + g * p.o.z;
+    for (int t = 0; t < 2; ++t) {
+        if (t == 0 ? !up : !down) continue;
+        const double zb = t == 0 ? a.lay_z[i + 1] : a.lay_z[i];
+        const double C = cth * (c0 + g * zb) / co;
+        if (C > 1.0) continue;
+        const double thb = t == 0 ? acos(C) : -acos(C);
+        const double s = (th0 - thb) / p.kappa;
+        if (s > 1e-12 && s < best) {
+            best = s;
+            next = t == 0 ? i + 1 : i - 1;
+        }
+    }
+    return best;
+}
+
+// Single-bounce first hit through the layers: each layer's circle is
+// traversed as its own chord segment, in path order, until a hit inside the
+// layer, the end of the range window or a layer the ray never leaves.
+template <int DEPTH, int DL, bool STATS>
+__device__ Hit64 first_hit_layered(const PingArgs &a, d3 o, d3 d, const double T_lim, uint32_t *__restrict__ W,
+                                   const int lane, bool &overflow, uint32_t &n_nodes, uint32_t &n_tris,
+                                   uint32_t &n_deep)
+{
+    Hit64 h;
+    h.ok = false;
+    int layer = layer_of(a, o.z);
+    if (layer > 0 && o.z == a.lay_z[layer] && d.z < 0.0) --layer;      // on a knot looking down
+    double t_acc = 0.0, s_acc = 0.0;
+    for (int piece = 0; piece < 64; ++piece) {
+        const double g = a.lay_g[layer], c0 = a.lay_c0[layer];
+        const Path64 path = make_path(o, d, g, c0);
+        int next;
+        const double s_exit = layer_exit(a, layer, path, g, c0, next);
+        const double s_cap = a.c_hi * (T_lim - t_acc);
+        const double s_end = fmin(s_exit, s_cap);
+        const double s_min = piece == 0 ? EPS_SELF : 0.0;
+        if (s_end > s_min) {
+            const Seg32 seg = make_seg(path, s_min, s_end * (1.0 + 1e-6));
+            float sf;
+            const int ti = traverse<DEPTH, DL, false, true, STATS>(as_global(a.nodes), as_global(a.tris), seg,
+                                                                   0xFFFFFFFFu, W, lane, overflow, sf, a.max_steps,
+                                                                   n_nodes, n_tris, n_deep);
+            if (ti >= 0) {
+                const TriF tr = load_tri(as_global(a.tris), (uint32_t)ti);
+                d3 nh;
+                const double s = refine64(tr, path, (double)sf, nh);
+                // a hit past the boundary lies on the next layer's circle
+                if (s > s_min && s <= s_exit) {
+                    h.tau = t_acc + path_time(path, s, g, c0);
+                    h.ok = h.tau <= T_lim;
+                    h.tr = tr;
+                    h.nh = nh;
+                    h.s = s_acc + s;
+                    h.X = path_point(path, s);
+                    h.din = path_tangent(path, s);
+                    return h;
+                }
+            }
+        }
+        if (next < 0 || s_exit >= s_cap) break;
+        t_acc += path_time(path, s_exit, g, c0);
+        s_acc += s_exit;
+        o = path_point(path, s_exit);
+        d = path_tangent(path, s_exit);
+        d = d * (1.0 / norm3(d));
+        layer = next;
+    }
+    return h;
+}
+
 // Receive binning: a return added to another beam than the launch beam is
 // appended to a device list, one counter update per wave (ballot, the
 // leader's atomic, per-lane offsets from the lanes below).
@@ -570,7 +680,7 @@ __device__ __forceinline__ void rx_append(const PingArgs &a, const bool want, co
 // The ping body for one tile of 256 consecutive rays (4 wavefronts). `a` is
 // the ping's argument block (kernel arguments, or a batch descriptor in
 // device memory); `W` is this wavefront's LDS area.
-template <int DEPTH, int K, bool ARC, bool STATS>
+template <int DEPTH, int K, bool ARC, bool STATS, bool LAYERED = false>
 __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uint32_t *__restrict__ W)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -655,24 +765,51 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                 }
                 stop = true;
                 if (s_lim > EPS_SELF) {
-                    const Path64 path = ARC ? make_path(o, d, a.g, a.c0) : Path64{o, d, mk3(0, 0, 0), 0.0, false};
-                    const Seg32 seg = make_seg(path, EPS_SELF, s_lim * (1.0 + 1e-6));
-                    float sf;
-                    // in a gradient a vertical ray is a degenerate arc (kappa = 0)
-                    int ti = traverse<DEPTH, DL, false, ARC, STATS>(as_global(a.nodes), as_global(a.tris), seg, prev, W, lane, overflow, sf,
-                                                         a.max_steps, st_nodes, st_tris, st_deep);
+                    Hit64 hit;
+                    Path64 path;
+                    float sf = 0.f;
+                    int ti;
+                    if constexpr (LAYERED) {
+                        hit = first_hit_layered<DEPTH, DL, STATS>(a, o, d, T_lim, W, lane, overflow, st_nodes, st_tris,
+                                                                  st_deep);
+                        ti = hit.ok ? 0 : -1;
+                    } else {
+                        path = ARC ? make_path(o, d, a.g, a.c0) : Path64{o, d, mk3(0, 0, 0), 0.0, false};
+                        const Seg32 seg = make_seg(path, EPS_SELF, s_lim * (1.0 + 1e-6));
+                        // in a gradient a vertical ray is a degenerate arc (kappa = 0)
+                        ti = traverse<DEPTH, DL, false, ARC, STATS>(as_global(a.nodes), as_global(a.tris), seg, prev, W,
+                                                                    lane, overflow, sf, a.max_steps, st_nodes, st_tris,
+                                                                    st_deep);
+                    }
                     if (ti >= 0) {
-                        TriF tr = load_tri(as_global(a.tris), (uint32_t)ti);
+                        TriF tr;
                         d3 nh;
-                        double s = refine64(tr, path, (double)sf, nh);
-                        double tau = ARC ? path_time(path, s, a.g, a.c0) : s / a.c0;
-                        bool ok = s > EPS_SELF && (ARC ? tau <= T_lim : s <= s_lim);
+                        double s, tau;
+                        bool ok;
+                        if constexpr (LAYERED) {
+                            tr = hit.tr;
+                            nh = hit.nh;
+                            s = hit.s;
+                            tau = hit.tau;
+                            ok = true;
+                        } else {
+                            tr = load_tri(as_global(a.tris), (uint32_t)ti);
+                            s = refine64(tr, path, (double)sf, nh);
+                            tau = ARC ? path_time(path, s, a.g, a.c0) : s / a.c0;
+                            ok = s > EPS_SELF && (ARC ? tau <= T_lim : s <= s_lim);
+                        }
                         if (ok) {
                             stop = false;
                             uint32_t id = tr.idbits & 0x7FFFFFFFu;
                             rec_tri = (int)id;
-                            d3 X = ARC ? path_point(path, s) : o + d * s;
-                            d3 din = ARC ? path_tangent(path, s) : d;
+                            d3 X, din;
+                            if constexpr (LAYERED) {
+                                X = hit.X;
+                                din = hit.din;
+                            } else {
+                                X = ARC ? path_point(path, s) : o + d * s;
+                                din = ARC ? path_tangent(path, s) : d;
+                            }
                             L_out += s;
                             T_out += tau;
                             double dn = dot3(nh, din);
@@ -1022,13 +1159,13 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
 template <int K, bool ARC>
 constexpr int ping_waves_per_eu() { return K == 1 ? (ARC ? 5 : 8) : 3; }
 
-template <int DEPTH, int K, bool ARC, bool STATS>
+template <int DEPTH, int K, bool ARC, bool STATS, bool LAYERED = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(ping_waves_per_eu<K, ARC>())))
 void k_ping(PingArgs a, int wave_words)
 {
     extern __shared__ uint32_t lds[];
     uint32_t *W = lds + (size_t)(threadIdx.x / WAVE) * wave_words;
-    ping_tile<DEPTH, K, ARC, STATS>(a, xcd_remap(blockIdx.x, gridDim.x), W);
+    ping_tile<DEPTH, K, ARC, STATS, LAYERED>(a, xcd_remap(blockIdx.x, gridDim.x), W);
 }
 
 // Persistent batch: every block pops (ping, tile) items from one device
@@ -1168,6 +1305,23 @@ hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s)
     }
 #undef SONAR_LAUNCH_K
 #undef SONAR_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_ping_layered(const PingArgs &a, int stack_depth, hipStream_t s)
+{
+    int64_t threads = (int64_t)a.n_beams * a.n_r;
+    int nblocks = (int)((threads + BLOCK - 1) / BLOCK);
+    if (nblocks == 0) return hipSuccess;
+    int depth = stack_depth <= 32 && !a.stats ? 32 : 64;
+    int ww = ping_wave_words(depth, a.n_bins, 1);
+    size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
+    if (a.stats)
+        hipLaunchKernelGGL((k_ping<64, 1, true, true, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww);
+    else if (depth == 32)
+        hipLaunchKernelGGL((k_ping<32, 1, true, false, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww);
+    else
+        hipLaunchKernelGGL((k_ping<64, 1, true, false, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_set_norm", "sonar_surrogate_forward", "sonar_surrogate_train_step",
            "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
-           "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb")
+           "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb",
+           "sonar_ping_ssp")
 
 
 class SonarError(RuntimeError):
@@ -80,6 +81,19 @@ class sonar_scene_info(C.Structure):
     _fields_ = [("n_triangles", C.c_int64), ("n_nodes", C.c_int64), ("depth", C.c_int32),
                 ("leaf_size", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3),
                 ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64)]
+
+
+class sonar_ssp(C.Structure):
+    _fields_ = [("n_knots", C.c_int32), ("pad", C.c_int32), ("z", C.c_double * 8), ("c", C.c_double * 8)]
+
+
+def ssp_of(knots) -> sonar_ssp:
+    """sonar_ssp from knots [(z, c), ...]."""
+    q = sonar_ssp(n_knots=len(knots))
+    for i, (z, c) in enumerate(knots[:8]):
+        q.z[i] = z
+        q.c[i] = c
+    return q
 
 
 class sonar_reverb(C.Structure):
@@ -194,6 +208,9 @@ def lib():
                                               C.c_void_p, C.c_void_p, C.c_void_p]
         L.sonar_params_from_resolution.restype = C.c_int
         L.sonar_params_from_resolution.argtypes = [C.c_double] * 7 + [P(sonar_params)]
+        L.sonar_ping_ssp.restype = C.c_int
+        L.sonar_ping_ssp.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_ssp), C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.sonar_add_reverb.restype = C.c_int
         L.sonar_add_reverb.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_reverb), C.c_void_p]
         L.sonar_rx_workspace_size.restype = C.c_size_t
@@ -338,6 +355,13 @@ def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=F
                                beam=out["beam"].data_ptr() if "beam" in out else None)
     p = params if params is not None else params_of(cfg)
     q = pose_s if pose_s is not None else pose_of(pose)
+    if getattr(cfg, "ssp", ()):
+        # piecewise-linear sound speed (single bounce)
+        prof = ssp_of(cfg.ssp)
+        _check(lib().sonar_ping_ssp(scene.handle, C.byref(p), C.byref(q), C.byref(prof), _dptr(out["volume"]),
+                                    _dptr(out.get("gbuffer")), _dptr(out.get("incoh")),
+                                    C.byref(rec) if rec is not None else None, _dptr(ray_mask), _stream(stream)))
+        return out
     if (p.flags & FLAG_RX_BEAMS) and p.max_bounces > 1:
         # receive binning lists the returns it moves: a workspace kept with the outputs
         import torch
@@ -387,6 +411,8 @@ class Detector:
 
     def ping_detect(self, scene: "Scene", volume, pose, stream=None, pose_s=None):
         """Ping + detection with the CFAR test fused into the ping kernel."""
+        if getattr(self.cfg, "ssp", ()):
+            raise SonarError(SONAR_E_UNSUPPORTED, "layered profiles: call ping(), then the detector")
         q = pose_s if pose_s is not None else pose_of(pose)
         st = lib().sonar_ping_detect(scene.handle, C.byref(self.params), C.byref(q), C.byref(self.cfar),
                                      _dptr(volume), _dptr(self.points), self.capacity, _dptr(self.count),
@@ -482,6 +508,8 @@ class Batch:
     def __init__(self, scene: Scene, items):
         import torch
         n = len(items)
+        if any(getattr(cfg, "ssp", ()) for cfg, _ in items):
+            raise SonarError(SONAR_E_UNSUPPORTED, "batches take the linear sound-speed profile only")
         self.scene = scene
         self.items = items
         self.volumes = [alloc_outputs(cfg)["volume"] for cfg, _ in items]
