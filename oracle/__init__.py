@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Beam options (sensor flags, see oracle.c)
-BEAM_PATTERN, RX_BEAMS = 1, 2
+BEAM_PATTERN, RX_BEAMS, DIFFUSE_BOUNCE = 1, 2, 4
 
 # Ambiguity flag bits (see oracle.c)
 F_GRAZE, F_EDGE, F_TIE, F_LIMIT, F_SELF, F_BIN, F_FOV, F_OCCLUDER, F_STOP, F_DEPART = (1 << i for i in range(10))
@@ -101,6 +101,8 @@ def lib():
         L.orc_trace_beams.restype = C.c_int
         L.orc_trace_beams.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Tol), C.c_void_p, C.c_int64] + \
             [C.c_void_p] * 10 + [C.c_int]
+        L.orc_draw_continuation.argtypes = [P(Params), C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                            C.c_double, C.c_void_p]
         L.orc_trace_one.restype = C.c_int
         L.orc_trace_one.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Tol), C.c_void_p, C.c_void_p] + [C.c_void_p] * 5
         L.orc_detect.restype = C.c_int
@@ -132,7 +134,7 @@ def _params(cfg, ping: int = 0) -> Params:
                   r_min=cfg.r_min, r_max=cfg.r_max, f0=cfg.freq_hz, c0=cfg.c0, g=cfg.c_grad,
                   alpha_db=cfg.abs_db_per_m, max_bounces=cfg.max_bounces, pad0=0,
                   k_d=cfg.k_d, k_s=cfg.k_s, phong_n=cfg.phong_n, seed=cfg.seed, ping=ping,
-                  flags=int(cfg.flags) & (BEAM_PATTERN | RX_BEAMS))
+                  flags=int(cfg.flags) & (BEAM_PATTERN | RX_BEAMS | DIFFUSE_BOUNCE))
 
 
 def pose_of(pose) -> PoseS:
@@ -232,6 +234,14 @@ def trace_beams(scene: Scene, cfg, pose, beams, tol=None, threads: int = 0, want
     if want_gbuf:
         out["gbuf"] = gbuf
     return out
+
+
+def draw_continuation(cfg, ping, ray, k, rh, np_, kd, ks):
+    out = np.zeros(5)
+    lib().orc_draw_continuation(C.byref(params_of(cfg, ping)), int(ray), int(k),
+                                _ptr(np.asarray(rh, np.float64)), _ptr(np.asarray(np_, np.float64)), float(kd),
+                                float(ks), _ptr(out))
+    return out[:3], float(out[3]), bool(out[4])
 
 
 def trace_one(scene: Scene, cfg, pose, o, d, tol=None):

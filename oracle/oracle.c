@@ -53,6 +53,19 @@
  *   beam). Cell-centred beams only. */
 #define ORC_BEAM_PATTERN 1u
 #define ORC_RX_BEAMS 2u
+/* ORC_DIFFUSE_BOUNCE: the continuation after a rough facet is drawn from the
+ * facet's scattering lobes instead of the mirror direction (Monte Carlo).
+ * With z = SplitMix64 output c + 1 of (seed xor 0xD1B54A32D192ED03) and
+ * c = (ping << 40) xor (ray << 2) xor k, u1 = (z >> 40) / 2^24,
+ * u2 = ((z >> 16) mod 2^24) / 2^24, u3 = (z mod 2^16) / 2^16: the Phong lobe
+ * around the mirror direction when u3 < k_s / (k_d + k_s) (cos a =
+ * (1 - u1)^(1 / (n + 1))), else the cosine lobe around the facet normal
+ * facing the ray (cos a = sqrt(1 - u1)); azimuth 2 pi u2 in the orthonormal
+ * basis of Duff et al. (JCGT 2017) around the lobe axis. A direction that
+ * does not leave the facet's lit side ends the ray. The path's amplitude
+ * weight takes sqrt(rho (k_d + k_s)) (each lobe normalised and drawn with
+ * its own probability). Pressure-release facets stay exact mirrors. */
+#define ORC_DIFFUSE_BOUNCE 4u
 
 /* ------------------------------------------------------------------------ */
 /* small vector algebra                                                      */
@@ -658,6 +671,41 @@ static double upper_speed(const orc_params *P, const oscene *S, const orc_pose *
     return P->c0 + fabs(P->g) * (z + 1.0);
 }
 
+/* orthonormal basis (t1, t2) around the unit vector n (Duff et al., JCGT 2017) */
+static void onb(v3 n, v3 *t1, v3 *t2)
+{
+    const double sg = n.z >= 0.0 ? 1.0 : -1.0;
+    const double a = -1.0 / (sg + n.z), b = n.x * n.y * a;
+    *t1 = mk(1.0 + sg * n.x * n.x * a, sg * b, -sg * n.x);
+    *t2 = mk(b, sg + n.y * n.y * a, -n.y);
+}
+
+/* The drawn continuation (unit) after vertex k of ray `ray`; returns 0 when it
+ * does not leave the lit side (np faces the incoming ray). */
+static int draw_continuation(const orc_params *P, uint64_t ray, int k, v3 rh, v3 np, double kd, double ks,
+                             double *cos_out, v3 *out)
+{
+    const uint64_t c = ((uint64_t)P->ping << 40) ^ (ray << 2) ^ (uint64_t)k;
+    const uint64_t z = orc_splitmix64_nth(P->seed ^ 0xD1B54A32D192ED03ULL, c + 1);
+    const double u1 = (double)(z >> 40) / 16777216.0, u2 = (double)((z >> 16) & 0xFFFFFFu) / 16777216.0;
+    const double u3 = (double)(z & 0xFFFFu) / 65536.0;
+    v3 axis;
+    double ca;
+    if (u3 < ks / (kd + ks)) {
+        axis = rh;
+        ca = pow(1.0 - u1, 1.0 / (P->phong_n + 1.0));
+    } else {
+        axis = np;
+        ca = sqrt(1.0 - u1);
+    }
+    const double sa = sqrt(fmax(0.0, 1.0 - ca * ca)), ph = 2.0 * ORC_PI * u2;
+    v3 t1, t2;
+    onb(axis, &t1, &t2);
+    *out = unit(add(scl(axis, ca), add(scl(t1, sa * cos(ph)), scl(t2, sa * sin(ph)))));
+    *cos_out = dot(*out, np);
+    return *cos_out > 0.0;
+}
+
 static double lobe_gauss(double d_az, double d_el, double dh, double dv)
 {
     const double a = d_az / dh, e = d_el / dv;
@@ -667,7 +715,7 @@ static double lobe_gauss(double d_az, double d_el, double dh, double dv)
 /* beam = launch beam index (or -1: beam options unused); d_az, d_el = the
  * launch direction's offsets from that beam's centre */
 static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, const orc_tol *T,
-                      v3 o, v3 d, int32_t beam, double d_az, double d_el, oray *out)
+                      v3 o, v3 d, int32_t beam, double d_az, double d_el, uint64_t ray_id, oray *out)
 {
     memset(out, 0, sizeof(*out));
     for (int k = 0; k < ORC_MAXK; ++k) { out->tri[k] = -1; out->bin[k] = -1; out->rxb[k] = beam; }
@@ -845,9 +893,20 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
                 }
             }
         }
-        /* continuation along the mirror direction */
+        /* continuation along the mirror direction, or drawn from the lobes */
         if (k + 1 >= K) break;
-        W *= sqrt(rho * ks) * sgn;
+        if ((P->flags & ORC_DIFFUSE_BOUNCE) && !pr) {
+            W *= sqrt(rho * (kd + ks)) * sgn;
+            if (W == 0.0) break;
+            double cd;
+            v3 nd;
+            const int lit = draw_continuation(P, ray_id, k, rh, np, kd, ks, &cd, &nd);
+            if (fabs(cd) < T->graze) out->flags |= F_DEPART;
+            if (!lit) break;
+            rh = nd;
+        } else {
+            W *= sqrt(rho * ks) * sgn;
+        }
         if (W == 0.0) break;
         double dS = len(sub(X, Sp));
         double lb, bound;
@@ -879,7 +938,8 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
     const oscene *S = (const oscene *)hs;
     if (P->max_bounces < 1 || P->max_bounces > ORC_MAXK) return -1;
     const int K = P->max_bounces, NB = P->n_bins, NR = P->n_r;
-    if (P->flags && P->grid_mode != 0) return -3;            /* beam options: cell-centred beams only */
+    if ((P->flags & (ORC_BEAM_PATTERN | ORC_RX_BEAMS)) && P->grid_mode != 0)
+        return -3;                                           /* beam options: cell-centred beams only */
     if (P->n_knots != 0) {
         /* a layered profile: single bounce, 2..8 knots with increasing depth and positive speed */
         if (P->max_bounces != 1 || P->n_knots < 2 || P->n_knots > ORC_MAXKNOTS) return -5;
@@ -914,7 +974,7 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
             double od[6];
             orc_ray(P, Q, b, j, od);
             double d_az = 0.0, d_el = 0.0;
-            if (P->flags) {
+            if (P->flags & (ORC_BEAM_PATTERN | ORC_RX_BEAMS)) {
                 double az, el;
                 ray_angles(P, b, j, &az, &el);
                 const int nh = beams_h(P);
@@ -922,8 +982,9 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
                 d_el = el - (-0.5 * P->vfov + (b / nh + 0.5) * dv);
             }
             oray r;
-            trace_ray(S, P, Q, T, mk(od[0], od[1], od[2]), mk(od[3], od[4], od[5]), P->flags ? b : -1, d_az,
-                      d_el, &r);
+            trace_ray(S, P, Q, T, mk(od[0], od[1], od[2]), mk(od[3], od[4], od[5]),
+                      (P->flags & (ORC_BEAM_PATTERN | ORC_RX_BEAMS)) ? b : -1, d_az,
+                      d_el, (uint64_t)b * NR + j, &r);
             size_t ri = (size_t)q * NR + j;
             ray_flags[ri] = r.flags;
             for (int k = 0; k < K; ++k) {
@@ -985,6 +1046,17 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
     return 0;
 }
 
+/* The drawn continuation of ray `ray` after vertex k (distribution checks):
+ * out = direction xyz, cos with np, lit flag. */
+void orc_draw_continuation(const orc_params *P, uint64_t ray, int32_t k, const double rh[3], const double np[3],
+                           double kd, double ks, double out[5])
+{
+    double c;
+    v3 d;
+    const int lit = draw_continuation(P, ray, k, mk(rh[0], rh[1], rh[2]), mk(np[0], np[1], np[2]), kd, ks, &c, &d);
+    out[0] = d.x; out[1] = d.y; out[2] = d.z; out[3] = c; out[4] = lit;
+}
+
 /* A single ray from an arbitrary origin and direction (closed-form checks). */
 int orc_trace_one(void *hs, const orc_params *P, const orc_pose *Q, const orc_tol *T,
                   const double o[3], const double d[3],
@@ -993,7 +1065,7 @@ int orc_trace_one(void *hs, const orc_params *P, const orc_pose *Q, const orc_to
     const oscene *S = (const oscene *)hs;
     if (P->max_bounces < 1 || P->max_bounces > ORC_MAXK) return -1;
     oray r;
-    trace_ray(S, P, Q, T, mk(o[0], o[1], o[2]), unit(mk(d[0], d[1], d[2])), -1, 0.0, 0.0, &r);
+    trace_ray(S, P, Q, T, mk(o[0], o[1], o[2]), unit(mk(d[0], d[1], d[2])), -1, 0.0, 0.0, 0, &r);
     for (int k = 0; k < P->max_bounces; ++k) {
         tri[k] = r.tri[k]; bin[k] = r.bin[k]; vis[k] = r.vis[k];
         amp[2 * k] = r.re[k]; amp[2 * k + 1] = r.im[k];
