@@ -125,9 +125,23 @@ typedef struct {
  *                     launch ray); with max_bounces > 1 it needs the
  *                     workspace of sonar_ping_rx or sonar_ping_detect, and
  *                     batches reject it
- *                     Both options need cell-centred beams (grid_mode 0). */
+ *                     Both options need cell-centred beams (grid_mode 0).
+ *     SONAR_FLAG_DIFFUSE_BOUNCE  stochastic scattering (Sec. II-B: speckle,
+ *                     reverberation): the continuation after a rough facet is
+ *                     drawn from its lobes instead of the mirror direction,
+ *                     the Phong lobe around the mirror with probability
+ *                     k_s / (k_d + k_s) (cos a = (1 - u1)^(1 / (phong_n + 1)))
+ *                     else the cosine lobe around the facet normal facing the
+ *                     ray (cos a = sqrt(1 - u1)), azimuth 2 pi u2; the uniforms
+ *                     come from SplitMix64 output c + 1 of (seed xor
+ *                     0xD1B54A32D192ED03), c = (ping << 40) xor (ray << 2) xor
+ *                     k (u1 = z >> 40, u2 = (z >> 16) mod 2^24 over 2^24,
+ *                     u3 = z mod 2^16 over 2^16 chooses the lobe); the path
+ *                     weight takes sqrt(rho (k_d + k_s)); a direction into the
+ *                     facet ends the ray. Pressure-release facets stay mirrors. */
 #define SONAR_FLAG_BEAM_PATTERN 1u
 #define SONAR_FLAG_RX_BEAMS 2u
+#define SONAR_FLAG_DIFFUSE_BOUNCE 4u
 typedef struct {
     double hfov, vfov;
     int32_t n_h, n_v, rays_per_beam, grid_mode, jitter, n_range;

@@ -85,8 +85,9 @@ sonar_status check_params(const sonar_params *p)
         return fail(SONAR_E_INVALID, "k_d, k_s and phong_n must be finite and >= 0");
     int64_t beams = (int64_t)(p->n_h + (p->grid_mode == 1)) * (p->n_v + (p->grid_mode == 1));
     if (beams * p->rays_per_beam > ((int64_t)1 << 31) - 1) return fail(SONAR_E_INVALID, "too many rays");
-    if (p->flags & ~(SONAR_FLAG_BEAM_PATTERN | SONAR_FLAG_RX_BEAMS)) return fail(SONAR_E_INVALID, "unknown flags");
-    if (p->flags && p->grid_mode != 0)
+    if (p->flags & ~(SONAR_FLAG_BEAM_PATTERN | SONAR_FLAG_RX_BEAMS | SONAR_FLAG_DIFFUSE_BOUNCE))
+        return fail(SONAR_E_INVALID, "unknown flags");
+    if ((p->flags & (SONAR_FLAG_BEAM_PATTERN | SONAR_FLAG_RX_BEAMS)) && p->grid_mode != 0)
         return fail(SONAR_E_UNSUPPORTED, "beam pattern and receive binning need cell-centred beams (grid_mode 0)");
     return SONAR_OK;
 }
@@ -110,7 +111,8 @@ sonar_status check_pose(const sonar_pose *q)
 int beams_h_of(const sonar_params *p) { return p->grid_mode == 1 ? p->n_h + 1 : p->n_h; }
 int beams_v_of(const sonar_params *p) { return p->grid_mode == 1 ? p->n_v + 1 : p->n_v; }
 
-static_assert(SONAR_FLAG_BEAM_PATTERN == sonar::FLAG_BEAM_PATTERN && SONAR_FLAG_RX_BEAMS == sonar::FLAG_RX_BEAMS,
+static_assert(SONAR_FLAG_BEAM_PATTERN == sonar::FLAG_BEAM_PATTERN && SONAR_FLAG_RX_BEAMS == sonar::FLAG_RX_BEAMS &&
+                  SONAR_FLAG_DIFFUSE_BOUNCE == sonar::FLAG_DIFFUSE_BOUNCE,
               "beam flags");
 
 // Receive binning with several bounces lists the returns it moves.

@@ -65,6 +65,7 @@ constexpr int ST_RX_FULL = 32;
 constexpr uint32_t FLAG_BEAM_PATTERN = 1u;
 constexpr int MAX_SSP_KNOTS = 8;
 constexpr uint32_t FLAG_RX_BEAMS = 2u;
+constexpr uint32_t FLAG_DIFFUSE_BOUNCE = 4u;
 
 struct PingArgs {
     const float4 *nodes;

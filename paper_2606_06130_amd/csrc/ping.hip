@@ -659,6 +659,42 @@ __device__ Hit64 first_hit_layered(const PingArgs &a, d3 o, d3 d, const double T
     return h;
 }
 
+// Monte-Carlo continuation after a rough facet: the Phong lobe around the
+// mirror direction with probability k_s / (k_d + k_s), else the cosine lobe
+// around the facet normal facing the ray; uniforms from SplitMix64 output
+// c + 1 of (seed xor 0xD1B54A32D192ED03), c = (ping << 40) ^ (ray << 2) ^ k,
+// azimuth in the orthonormal basis of Duff et al. (JCGT 2017). `lit` is false
+// when the drawn direction does not leave the lit side. Kept out of line
+// (scalar arguments, result by value) so that the kernels that never draw
+// keep their register allocation.
+struct Drawn {
+    d3 dir;
+    bool lit;
+};
+
+__device__ __attribute__((noinline)) Drawn draw_continuation(const uint64_t seed, const uint32_t ping,
+                                                             const double phong_n, const uint64_t ray, const int k,
+                                                             const d3 rh, const d3 np, const double kd,
+                                                             const double ks)
+{
+    const uint64_t c = ((uint64_t)ping << 40) ^ (ray << 2) ^ (uint64_t)k;
+    const uint64_t z = splitmix64_nth(seed ^ 0xD1B54A32D192ED03ull, c + 1);
+    const double u1 = (double)(z >> 40) * (1.0 / 16777216.0);
+    const double u2 = (double)((z >> 16) & 0xFFFFFFull) * (1.0 / 16777216.0);
+    const double u3 = (double)(z & 0xFFFFull) * (1.0 / 65536.0);
+    const bool spec = u3 < ks / (kd + ks);
+    const d3 ax = spec ? rh : np;
+    const double ca = spec ? pow(1.0 - u1, 1.0 / (phong_n + 1.0)) : sqrt(1.0 - u1);
+    const double sa = sqrt(fmax(0.0, 1.0 - ca * ca)), ph = TWO_PI * u2;
+    const double sg = ax.z >= 0.0 ? 1.0 : -1.0, q = -1.0 / (sg + ax.z), b = ax.x * ax.y * q;
+    const d3 t1 = mk3(1.0 + sg * ax.x * ax.x * q, sg * b, -sg * ax.x), t2 = mk3(b, sg + ax.y * ax.y * q, -ax.y);
+    const d3 v = ax * ca + t1 * (sa * cos(ph)) + t2 * (sa * sin(ph));
+    Drawn r;
+    r.dir = v * (1.0 / norm3(v));
+    r.lit = dot3(r.dir, np) > 0.0;
+    return r;
+}
+
 // Receive binning: a return added to another beam than the launch beam is
 // appended to a device list, one counter update per wave (ballot, the
 // leader's atomic, per-lane offsets from the lanes below).
@@ -900,14 +936,25 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                                     }
                                 }
                             }
-                            // continuation along the mirror direction
+                            // continuation along the mirror direction, or drawn from the lobes
                             if (k + 1 < K) {
-                                Wt *= sqrt(rho * ks) * sgn;
+                                d3 dc = rh;
+                                if ((a.flags & FLAG_DIFFUSE_BOUNCE) && !pr) {
+                                    Wt *= sqrt(rho * (kd + ks)) * sgn;
+                                    if (Wt != 0.0) {
+                                        const Drawn dw = draw_continuation(a.seed, a.ping, a.phong_n, ray, k, rh, np,
+                                                                           kd, ks);
+                                        if (!dw.lit) Wt = 0.0;
+                                        dc = dw.dir;
+                                    }
+                                } else {
+                                    Wt *= sqrt(rho * ks) * sgn;
+                                }
                                 const double dS = norm3(X - S);
                                 const double lb = ARC ? a.c_ref * (T_out + dS / a.c_hi) / 2.0 : (L_out + dS) / 2.0;
                                 if (Wt == 0.0 || lb >= a.r_max) stop = true;
                                 o = X;
-                                d = rh;
+                                d = dc;
                                 prev = id;
                             }
                             // visibility of the connection: any hit other than this facet

@@ -23,6 +23,7 @@ SONAR_E_STACK = -4
 SONAR_E_UNSUPPORTED = -5
 FLAG_BEAM_PATTERN = 1
 FLAG_RX_BEAMS = 2
+FLAG_DIFFUSE_BOUNCE = 4
 
 # Every symbol include/sonar.h declares.
 EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "sonar_ping",
