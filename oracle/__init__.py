@@ -20,8 +20,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 BEAM_PATTERN, RX_BEAMS, DIFFUSE_BOUNCE = 1, 2, 4
 
 # Ambiguity flag bits (see oracle.c)
-F_GRAZE, F_EDGE, F_TIE, F_LIMIT, F_SELF, F_BIN, F_FOV, F_OCCLUDER, F_STOP, F_DEPART = (1 << i for i in range(10))
-FLAG_NAMES = ("graze", "edge", "tie", "limit", "self", "bin", "fov", "occluder", "stop", "depart")
+F_GRAZE, F_EDGE, F_TIE, F_LIMIT, F_SELF, F_BIN, F_FOV, F_OCCLUDER, F_STOP, F_DEPART, F_CAUSTIC = \
+    (1 << i for i in range(11))
+FLAG_NAMES = ("graze", "edge", "tie", "limit", "self", "bin", "fov", "occluder", "stop", "depart", "caustic")
 
 
 def build(force: bool = False) -> str:
@@ -56,7 +57,7 @@ class Tol(C.Structure):
     _fields_ = [("graze", C.c_double), ("edge_abs", C.c_double), ("edge_rel", C.c_double),
                 ("tie_rel", C.c_double), ("tie_abs", C.c_double), ("bin_frac", C.c_double),
                 ("fov", C.c_double), ("lim_rel", C.c_double),
-                ("self_lo", C.c_double), ("self_hi", C.c_double)]
+                ("self_lo", C.c_double), ("self_hi", C.c_double), ("caustic", C.c_double)]
 
 
 class Cfar(C.Structure):
@@ -68,16 +69,18 @@ def default_tol(**kw) -> Tol:
     """Flag margins: grazing below cos 1e-3, hits within 2e-5 m + 2e-6 s of an
     edge, second candidates within 1e-5 relative + 1e-6 m, range positions within
     1e-6 of a bin edge, arrival directions within 1e-9 rad of the FOV edge,
-    bounds within 1e-7 relative, hit distances in [5e-5, 2e-4] m."""
+    bounds within 1e-7 relative, hit distances in [5e-5, 2e-4] m, and in a
+    layered profile two eigenrays turning within 1/64 of the turning-depth
+    window of each other."""
     t = dict(graze=1e-3, edge_abs=2e-5, edge_rel=2e-6, tie_rel=1e-5, tie_abs=1e-6,
-             bin_frac=1e-6, fov=1e-9, lim_rel=1e-7, self_lo=5e-5, self_hi=2e-4)
+             bin_frac=1e-6, fov=1e-9, lim_rel=1e-7, self_lo=5e-5, self_hi=2e-4, caustic=1.0 / 64)
     t.update(kw)
     return Tol(**t)
 
 
 def zero_tol() -> Tol:
     return Tol(graze=0, edge_abs=0, edge_rel=0, tie_rel=0, tie_abs=0, bin_frac=0, fov=0,
-               lim_rel=0, self_lo=1e-4, self_hi=1e-4)
+               lim_rel=0, self_lo=1e-4, self_hi=1e-4, caustic=0)
 
 
 _lib = None
@@ -98,6 +101,7 @@ def lib():
         L.orc_ray.argtypes = [P(Params), P(PoseS), C.c_int32, C.c_int32, C.c_void_p]
         L.orc_connection.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_path_eval.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
+        L.orc_eigenray.argtypes = [P(Params), P(Tol), C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
         L.orc_trace_beams.restype = C.c_int
         L.orc_trace_beams.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Tol), C.c_void_p, C.c_int64] + \
             [C.c_void_p] * 10 + [C.c_int]
@@ -190,6 +194,19 @@ def connection(cfg, p, s):
     lib().orc_connection(C.byref(params_of(cfg)), _ptr(np.asarray(p, np.float64)),
                          _ptr(np.asarray(s, np.float64)), _ptr(out))
     return dict(L=out[0], T=out[1], w_out=out[2:5], arrive=out[5:8])
+
+
+def eigenray(cfg, p, s, H=None, tol=None):
+    """The layered profile's first-arriving eigenray from p to s (turning
+    depths within H of the span, 2 r_max by default): ok, family (0 direct,
+    1 turning above, 2 turning below), number of roots, invariant xi, turning
+    depth, L, T, departure and arrival directions, flags."""
+    out = np.zeros(14)
+    H = 2.0 * cfg.r_max if H is None else H
+    lib().orc_eigenray(C.byref(params_of(cfg)), C.byref(tol or default_tol()), _ptr(np.asarray(p, np.float64)),
+                       _ptr(np.asarray(s, np.float64)), float(H), _ptr(out))
+    return dict(ok=bool(out[0]), fam=int(out[1]), n_roots=int(out[2]), xi=out[3], zt=out[4], L=out[5], T=out[6],
+                w_out=out[7:10], arrive=out[10:13], flags=int(out[13]))
 
 
 def path_eval(cfg, o, d, s):

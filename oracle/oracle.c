@@ -119,12 +119,14 @@ typedef struct {
     double fov;        /* arrival direction within this angle (rad) of the FOV edge */
     double lim_rel;    /* a hit or a stop test within this relative margin of its bound */
     double self_lo, self_hi;  /* hit distances in [self_lo, self_hi] are flagged */
+    double caustic;    /* layered profile: a first-arriving eigenray and another whose turning
+                        * depths differ by less than this in sqrt(rise / window) */
 } orc_tol;
 
 enum {
     F_GRAZE = 1u << 0, F_EDGE = 1u << 1, F_TIE = 1u << 2, F_LIMIT = 1u << 3,
     F_SELF = 1u << 4, F_BIN = 1u << 5, F_FOV = 1u << 6, F_OCCLUDER = 1u << 7,
-    F_STOP = 1u << 8, F_DEPART = 1u << 9
+    F_STOP = 1u << 8, F_DEPART = 1u << 9, F_CAUSTIC = 1u << 10
 };
 
 typedef struct {
@@ -544,19 +546,21 @@ static ohit nearest_hit_from(const oscene *S, const opath *p, int64_t prev, doub
     return h;
 }
 
-/* Any hit on (eps, L - eps) other than `skip`; flags occluders near an edge or
- * near either end of the segment. Returns 1 when the path is blocked. */
-static int blocked(const oscene *S, const opath *p, int64_t skip, double L, const orc_tol *T, uint32_t *flags)
+/* Any hit of piece p of a path of total length L, the piece starting at arc
+ * length s0 and running for len, other than `skip`: a hit at path length s
+ * counts on (eps, L - eps); occluders near an edge or near either end of the
+ * path are flagged. Returns 1 when the piece is blocked. */
+static int blocked_piece(const oscene *S, const opath *p, int64_t skip, double s0, double len, double L,
+                         const orc_tol *T, uint32_t *flags)
 {
     int hit = 0;
-    double hi = L;
     for (int64_t i = 0; i < S->nt; ++i) {
         if (i == skip) continue;
         double r[2];
-        int m = plane_roots(S, i, p, hi, r);
+        int m = plane_roots(S, i, p, len, r);
         for (int t = 0; t < m; ++t) {
-            double s = r[t];
-            v3 X = path_point(p, s);
+            double s = s0 + r[t];
+            v3 X = path_point(p, r[t]);
             double de = edge_distance(S, i, X);
             double dl = T->edge_abs + T->edge_rel * s;
             int inside_range = (s > EPS_SELF && s < L - EPS_SELF);
@@ -569,6 +573,12 @@ static int blocked(const oscene *S, const opath *p, int64_t skip, double L, cons
         }
     }
     return hit;
+}
+
+/* Any hit on (eps, L - eps) of a one-piece path other than `skip`. */
+static int blocked(const oscene *S, const opath *p, int64_t skip, double L, const orc_tol *T, uint32_t *flags)
+{
+    return blocked_piece(S, p, skip, 0.0, L, L, T, flags);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -641,6 +651,346 @@ void orc_path_eval(const orc_params *P, const double o[3], const double d[3], do
     out[0] = x.x; out[1] = x.y; out[2] = x.z;
     out[3] = t.x; out[4] = t.y; out[5] = t.z;
     out[6] = path_time(P, &p, s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eigenrays through a layered profile. Snell's law keeps xi = cos(theta) / c */
+/* fixed along a ray (theta the grazing angle), so crossing one layer between */
+/* depths za and zb without turning, with s = |sin theta| = sqrt(1 - xi^2 c^2), */
+/* the ray advances horizontally by X = integral of cot(theta) dz, travels arc */
+/* length L = integral of dz / s and takes time T = integral of dz / (c s):     */
+/*   X = (sa - sb) / (xi g)  = xi |dz| (ca + cb) / (sa + sb)                  */
+/*   L = |asin sa - asin sb| / (xi |g|),  sin of that difference = xi g dz m,  */
+/*       m = (ca + cb) / (sa cb + sb ca)                                      */
+/*   T = |atanh sa - atanh sb| / |g| = |ln(1 + g dz (1 + m) / ((1 + sb) ca))| / |g| */
+/* (each right-hand form is the left one rearranged without cancellation; the  */
+/* straight-line limits g -> 0 and xi -> 0 follow). A turning point is where   */
+/* s reaches 0. The return path from a vertex P to the sensor S is taken as    */
+/* the eigenray with at most one turning point that arrives first: the direct */
+/* ray (depth monotone between them), or one that turns above the higher of    */
+/* the two depths or below the lower one.                                     */
+
+typedef struct { double X, L, T; } orun;
+
+/* c(zb) - c(za) as the sum of gradient times depth over the layers between
+ * them: accurate relative to the difference itself, however close the two
+ * speeds are (near a turning point 1 - xi c is such a difference). */
+static double dspeed(const orc_params *P, double za, double zb)
+{
+    const int nl = layer_count(P);
+    const double lo = fmin(za, zb), hi = fmax(za, zb);
+    double sum = 0.0;
+    for (int i = 0; i < nl; ++i) {
+        const double a = i > 0 ? fmax(lo, P->knot_z[i]) : lo;
+        const double b = i + 1 < nl ? fmin(hi, P->knot_z[i + 1]) : hi;
+        if (b > a) sum += layer_g(P, i) * (b - a);
+    }
+    return zb >= za ? sum : -sum;
+}
+
+/* A ray family's invariant: xi = (1 - u) / c(zr), with zr the turning depth
+ * (u = 0) or, for the direct family, the depth of the span's largest speed. */
+typedef struct { double zr, u, cr, xi; } oref;
+
+static oref ref_of(const orc_params *P, double zr, double u)
+{
+    oref R;
+    R.zr = zr;
+    R.u = u;
+    R.cr = profile_c(P, zr);
+    R.xi = (1.0 - u) / R.cr;
+    return R;
+}
+
+/* |sin theta| at depth z: from 1 - xi c(z) = (c(zr) - c(z) + u c(z)) / c(zr) */
+static double snell_sin(const orc_params *P, const oref *R, double z)
+{
+    const double a = (dspeed(P, z, R->zr) + R->u * profile_c(P, z)) / R->cr;
+    return a <= 0.0 ? 0.0 : sqrt(a * (2.0 - a));
+}
+
+/* run of a ray of invariant R between depths za and zb of layer i */
+static orun layer_run(const orc_params *P, const oref *R, int i, double za, double zb)
+{
+    orun r = {0.0, 0.0, 0.0};
+    const double dz = zb - za, adz = fabs(dz);
+    if (adz == 0.0) return r;
+    const double g = layer_g(P, i), c0 = layer_c0(P, i), xi = R->xi;
+    const double ca = c0 + g * za, cb = c0 + g * zb;
+    const double sa = snell_sin(P, R, za), sb = snell_sin(P, R, zb);
+    if (sa + sb == 0.0) {
+        /* horizontal at both ends: in a constant layer the ray never leaves its
+         * depth; otherwise the run is a rounding-level sliver at a turning point */
+        if (g == 0.0) { r.X = r.L = r.T = HUGE_VAL; }
+        else { r.L = adz; r.T = adz / ca; }
+        return r;
+    }
+    r.X = xi * adz * (ca + cb) / (sa + sb);
+    const double m = (ca + cb) / (sa * cb + sb * ca);
+    const double y = fmin(1.0, xi * fabs(g) * adz * m);
+    r.L = adz * m * (y > 0.0 ? asin(y) / y : 1.0);
+    const double q = (1.0 + m) / ((1.0 + sb) * ca);
+    r.T = g != 0.0 ? fabs(log1p(g * dz * q) / g) : adz * q;
+    return r;
+}
+
+/* run between depths z0 <= z1, crossing every layer in between once */
+static orun span_run(const orc_params *P, const oref *R, double z0, double z1)
+{
+    orun r = {0.0, 0.0, 0.0};
+    const int nl = layer_count(P);
+    int i = layer_of(P, z0);
+    double za = z0;
+    while (za < z1) {
+        const double top = i + 1 < nl ? P->knot_z[i + 1] : HUGE_VAL;
+        const double zb = top < z1 ? top : z1;
+        const orun q = layer_run(P, R, i, za, zb);
+        r.X += q.X; r.L += q.L; r.T += q.T;
+        za = zb;
+        ++i;
+    }
+    return r;
+}
+
+/* family 0: direct; 1: turning at depth zt above zhi; 2: turning at zt below zlo */
+static orun eig_run(const orc_params *P, int fam, const oref *R, double zlo, double zhi)
+{
+    orun a = span_run(P, R, zlo, zhi);
+    if (fam != 0) {
+        const orun b = fam == 1 ? span_run(P, R, zhi, R->zr) : span_run(P, R, R->zr, zlo);
+        a.X += 2.0 * b.X; a.L += 2.0 * b.L; a.T += 2.0 * b.T;
+    }
+    return a;
+}
+
+/* Turning depths of family 1 (above zhi) or 2 (below zlo) within H of the
+ * span: the depths where c exceeds every speed met on the way there from the
+ * span (cm = the largest speed on the span). At most one interval per layer;
+ * returns their number, each as [nearer end, farther end] along the walk. */
+static int turn_intervals(const orc_params *P, int fam, double zlo, double zhi, double cm, double H,
+                          double iv[][2])
+{
+    const int nl = layer_count(P);
+    int n = 0;
+    double M = cm;
+    if (fam == 1) {
+        const double zend = zhi + H;
+        int i = layer_of(P, zhi);
+        double z = zhi;
+        while (z < zend && i < nl) {
+            const double top = i + 1 < nl ? P->knot_z[i + 1] : HUGE_VAL;
+            const double zb = top < zend ? top : zend;
+            const double g = layer_g(P, i), c0 = layer_c0(P, i);
+            if (g > 0.0) {
+                const double zs = (M - c0) / g;      /* c reaches the record here */
+                const double a = zs > z ? zs : z;
+                if (a < zb) { iv[n][0] = a; iv[n][1] = zb; ++n; }
+                if (c0 + g * zb > M) M = c0 + g * zb;
+            }
+            z = zb;
+            ++i;
+        }
+    } else {
+        const double zend = zlo - H;
+        int i = layer_of(P, zlo);
+        if (i > 0 && zlo == P->knot_z[i]) --i;       /* going down from a knot: the layer below */
+        double z = zlo;
+        while (z > zend && i >= 0) {
+            const double bot = i > 0 ? P->knot_z[i] : -HUGE_VAL;
+            const double zb = bot > zend ? bot : zend;
+            const double g = layer_g(P, i), c0 = layer_c0(P, i);
+            if (g < 0.0) {
+                const double zs = (M - c0) / g;
+                const double a = zs < z ? zs : z;
+                if (a > zb) { iv[n][0] = a; iv[n][1] = zb; ++n; }
+                if (c0 + g * zb > M) M = c0 + g * zb;
+            }
+            z = zb;
+            --i;
+        }
+    }
+    return n;
+}
+
+#define EIG_SCAN 1024      /* scan cells over the turning-depth window (in v, below) */
+#define EIG_MAXROOTS 256
+
+typedef struct {
+    int ok;            /* an eigenray was found */
+    int fam, n_roots;
+    double xi, zt;
+    double L, T;
+    v3 w_out, arrive;
+    uint32_t flags;
+} oeig;
+
+typedef struct { int fam; double zr, u, T; } oroot;
+
+static double eig_f(const orc_params *P, int fam, double zt, double zlo, double zhi, double D)
+{
+    const oref R = ref_of(P, zt, 0.0);
+    return eig_run(P, fam, &R, zlo, zhi).X - D;
+}
+
+/* bisection of f between a (f <= 0 side or not, as classified) and b */
+static double eig_bisect(const orc_params *P, int fam, double a, double b, double zlo, double zhi, double D)
+{
+    const int neg_a = eig_f(P, fam, a, zlo, zhi, D) <= 0.0;
+    for (int it = 0; it < 200; ++it) {
+        const double m = 0.5 * (a + b);
+        if (m == a || m == b) break;
+        if ((eig_f(P, fam, m, zlo, zhi, D) <= 0.0) == neg_a) a = m; else b = m;
+    }
+    return 0.5 * (a + b);
+}
+
+/* The first-arriving eigenray with at most one turning point from P to S.
+ * The direct ray's invariant is found by bisection (its horizontal run grows
+ * with xi up to xi = 1 / c_max of the span). Turning depths zt are searched
+ * within H of the span on a grid uniform in v = sqrt(|zt - z_span| / H) (the
+ * horizontal run of a turning ray grows like the square root of its rise),
+ * EIG_SCAN cells plus the ends of the turning intervals, each sign change
+ * refined by bisection. Flagged: a first arrival with another root of its
+ * family closer than T->caustic in v (near a caustic, where a coarser search
+ * could miss both; roots away from the first arrival do not change the
+ * result), and a second arrival within T->tie_rel of the first in time. */
+static oeig eigenray_layered(const orc_params *P, v3 Pp, v3 Sp, double H, const orc_tol *T)
+{
+    oeig e;
+    memset(&e, 0, sizeof(e));
+    const v3 dv = sub(Sp, Pp);
+    const double D = hypot(dv.x, dv.y);
+    const double zlo = fmin(Pp.z, Sp.z), zhi = fmax(Pp.z, Sp.z);
+    double zm = profile_c(P, zlo) >= profile_c(P, zhi) ? zlo : zhi;     /* depth of the span's largest speed */
+    for (int i = 0; i < P->n_knots; ++i)
+        if (P->knot_z[i] > zlo && P->knot_z[i] < zhi && P->knot_c[i] > profile_c(P, zm)) zm = P->knot_z[i];
+    const double cm = profile_c(P, zm);
+    oroot roots[EIG_MAXROOTS];
+    int nr = 0;
+    /* direct family, xi = (1 - u) / cm: the run shrinks as u grows from 0 to 1 */
+    if (zlo == zhi) {
+        if (layer_g(P, layer_of(P, zlo)) == 0.0 && D > 0.0)
+            roots[nr++] = (oroot){0, zm, 0.0, D / cm};            /* horizontal in a constant layer */
+    } else {
+        double a = 0.0, b = 1.0;
+        const oref R0 = ref_of(P, zm, 0.0);
+        if (D == 0.0) {
+            a = b = 1.0;                                         /* vertical */
+        } else if (span_run(P, &R0, zlo, zhi).X - D > 0.0) {
+            for (int it = 0; it < 200; ++it) {
+                const double m = 0.5 * (a + b);
+                if (m == a || m == b) break;
+                const oref R = ref_of(P, zm, m);
+                if (span_run(P, &R, zlo, zhi).X - D > 0.0) a = m; else b = m;
+            }
+        } else {
+            a = b = -1.0;                                        /* out of the direct family's reach */
+        }
+        if (a >= 0.0) {
+            const double u = 0.5 * (a + b);
+            const oref R = ref_of(P, zm, u);
+            roots[nr++] = (oroot){0, zm, u, span_run(P, &R, zlo, zhi).T};
+        }
+    }
+    /* turning families: scan the turning depth */
+    for (int fam = 1; fam <= 2; ++fam) {
+        double iv[ORC_MAXKNOTS + 1][2];
+        const int ni = turn_intervals(P, fam, zlo, zhi, cm, H, iv);
+        const double z0 = fam == 1 ? zhi : zlo, dir = fam == 1 ? 1.0 : -1.0;
+        for (int q = 0; q < ni; ++q) {
+            const double a = iv[q][0], b = iv[q][1];
+            double zp = a;
+            int negp = eig_f(P, fam, zp, zlo, zhi, D) <= 0.0;
+            int j = (int)floor(sqrt(fabs(a - z0) / H) * EIG_SCAN) + 1;
+            for (;; ++j) {
+                const double v = (double)j / EIG_SCAN;
+                double zq = z0 + dir * (H * (v * v));
+                const int last = dir * (zq - b) >= 0.0;
+                if (last) zq = b;
+                const int negq = eig_f(P, fam, zq, zlo, zhi, D) <= 0.0;
+                if (negq != negp && nr < EIG_MAXROOTS) {
+                    const double zt = eig_bisect(P, fam, zp, zq, zlo, zhi, D);
+                    const oref R = ref_of(P, zt, 0.0);
+                    roots[nr++] = (oroot){fam, zt, 0.0, eig_run(P, fam, &R, zlo, zhi).T};
+                }
+                if (last) break;
+                zp = zq;
+                negp = negq;
+            }
+        }
+    }
+    e.n_roots = nr;
+    if (nr == 0) return e;
+    int best = 0;
+    for (int r = 1; r < nr; ++r)
+        if (roots[r].T < roots[best].T) best = r;
+    for (int r = 0; r < nr; ++r) {
+        if (r == best) continue;
+        if (roots[r].T <= roots[best].T * (1.0 + T->tie_rel)) e.flags |= F_CAUSTIC;
+        if (roots[best].fam != 0 && roots[r].fam == roots[best].fam) {
+            const double z0 = roots[best].fam == 1 ? zhi : zlo;
+            if (fabs(sqrt(fabs(roots[r].zr - z0) / H) - sqrt(fabs(roots[best].zr - z0) / H)) < T->caustic)
+                e.flags |= F_CAUSTIC;
+        }
+    }
+    const oroot *B = &roots[best];
+    const oref R = ref_of(P, B->zr, B->u);
+    orun run = eig_run(P, B->fam, &R, zlo, zhi);
+    if (B->fam == 0 && zlo == zhi) { run.L = D; run.T = D / cm; }
+    e.ok = 1;
+    e.fam = B->fam;
+    e.xi = R.xi;
+    e.zt = B->fam != 0 ? B->zr : 0.0;
+    e.L = run.L;
+    e.T = run.T;
+    /* directions: horizontal part toward S, vertical sign by family and order */
+    const v3 uh = D > 0.0 ? mk(dv.x / D, dv.y / D, 0.0) : mk(0.0, 0.0, 0.0);
+    const double cp = R.xi * profile_c(P, Pp.z), cs = R.xi * profile_c(P, Sp.z);
+    const double sp = snell_sin(P, &R, Pp.z), ss = snell_sin(P, &R, Sp.z);
+    const double up = Sp.z > Pp.z ? 1.0 : (Sp.z < Pp.z ? -1.0 : 0.0);
+    const double vp = B->fam == 0 ? up : (B->fam == 1 ? 1.0 : -1.0);
+    const double vs = B->fam == 0 ? up : (B->fam == 1 ? -1.0 : 1.0);
+    e.w_out = unit(mk(cp * uh.x, cp * uh.y, vp * sp));
+    e.arrive = unit(mk(cs * uh.x, cs * uh.y, vs * ss));
+    return e;
+}
+
+/* Occlusion of the layered eigenray leaving P along w for arc length L: the
+ * path is walked one circle per layer and each piece is tested. */
+static int blocked_layered(const oscene *S, const orc_params *P, v3 Pp, v3 w, double L, int64_t skip,
+                           const orc_tol *T, uint32_t *flags)
+{
+    int layer = layer_of(P, Pp.z);
+    if (layer > 0 && Pp.z == P->knot_z[layer] && w.z < 0.0) --layer;
+    v3 o = Pp, d = w;
+    double s0 = 0.0;
+    for (int piece = 0; piece < 64; ++piece) {
+        const double g = layer_g(P, layer), c0 = layer_c0(P, layer);
+        opath path = make_path_gc(g, c0, o, d);
+        int next;
+        const double s_exit = layer_exit(P, layer, &path, g, c0, &next, flags);
+        const double len = s_exit < L - s0 ? s_exit : L - s0;
+        if (blocked_piece(S, &path, skip, s0, len, L, T, flags)) return 1;
+        if (next < 0 || s0 + s_exit >= L) break;
+        s0 += s_exit;
+        o = path_point(&path, s_exit);
+        d = unit(path_tangent(&path, s_exit));
+        layer = next;
+    }
+    return 0;
+}
+
+/* Exposed for checks: the layered eigenray P -> S with turning depths within
+ * H. out = {ok, family, roots, xi, zt, L, T, w xyz, arrive xyz, flags}. */
+void orc_eigenray(const orc_params *P, const orc_tol *T, const double p[3], const double s[3], double H,
+                  double out[14])
+{
+    const oeig e = eigenray_layered(P, mk(p[0], p[1], p[2]), mk(s[0], s[1], s[2]), H, T);
+    out[0] = e.ok; out[1] = e.fam; out[2] = e.n_roots; out[3] = e.xi; out[4] = e.zt;
+    out[5] = e.L; out[6] = e.T;
+    out[7] = e.w_out.x; out[8] = e.w_out.y; out[9] = e.w_out.z;
+    out[10] = e.arrive.x; out[11] = e.arrive.y; out[12] = e.arrive.z;
+    out[13] = (double)e.flags;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -736,9 +1086,8 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
         double tau, s_len;
         v3 X, din;
         if (layered) {
-            /* single bounce through the layers: one circle per layer, in order */
-            if (K != 1) return;
-            const double T_lim = P->r_max / c_ref;
+            /* through the layers: one circle per layer, in order */
+            const double T_lim = (K == 1) ? P->r_max / c_ref : 2.0 * P->r_max / c_ref - T_out;
             int layer = layer_of(P, o.z);
             /* a sensor exactly on a knot, looking down, starts in the layer below */
             if (layer > 0 && o.z == P->knot_z[layer] && d.z < 0.0) --layer;
@@ -824,13 +1173,28 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
         if (k == 0) {
             L_back = L_out; T_back = T_out; w = scl(din, -1.0);
         } else {
-            oconn c = connection(P, X, Sp);
-            L_back = c.L; T_back = c.T; w = c.w_out;
+            v3 arrive;
             uint32_t fl = 0;
-            if (blocked(S, &c.path, f, c.L, T, &fl)) vis = 0;
+            if (layered) {
+                /* the first-arriving eigenray, turning within 2 r_max of the span */
+                const oeig e = eigenray_layered(P, X, Sp, 2.0 * P->r_max, T);
+                fl |= e.flags;
+                if (!e.ok) {
+                    vis = 0;            /* no eigenray: the vertex lies in a shadow zone */
+                    L_back = T_back = 0.0;
+                    w = arrive = mk(0.0, 0.0, 0.0);
+                } else {
+                    L_back = e.L; T_back = e.T; w = e.w_out; arrive = e.arrive;
+                    if (blocked_layered(S, P, X, w, e.L, f, T, &fl)) vis = 0;
+                }
+            } else {
+                oconn c = connection(P, X, Sp);
+                L_back = c.L; T_back = c.T; w = c.w_out; arrive = c.arrive;
+                if (blocked(S, &c.path, f, c.L, T, &fl)) vis = 0;
+            }
             out->flags |= fl;
             /* arrival direction must lie in the field of view */
-            v3 a = world_to_sensor(Q, scl(c.arrive, -1.0));
+            v3 a = world_to_sensor(Q, scl(arrive, -1.0));
             double az = atan2(a.y, a.x), el = atan2(a.z, hypot(a.x, a.y));
             double mh = 0.5 * P->hfov - fabs(az), mv = 0.5 * P->vfov - fabs(el);
             if (fabs(mh) <= T->fov || fabs(mv) <= T->fov) out->flags |= F_FOV;
@@ -910,7 +1274,7 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
         if (W == 0.0) break;
         double dS = len(sub(X, Sp));
         double lb, bound;
-        if (P->g == 0.0) { lb = (L_out + dS) / 2.0; bound = P->r_max; }
+        if (P->g == 0.0 && !layered) { lb = (L_out + dS) / 2.0; bound = P->r_max; }
         else { lb = c_ref * (T_out + dS / c_hi) / 2.0; bound = P->r_max; }
         if (fabs(lb - bound) <= T->lim_rel * bound) out->flags |= F_STOP;
         if (lb >= bound) break;
@@ -941,8 +1305,8 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
     if ((P->flags & (ORC_BEAM_PATTERN | ORC_RX_BEAMS)) && P->grid_mode != 0)
         return -3;                                           /* beam options: cell-centred beams only */
     if (P->n_knots != 0) {
-        /* a layered profile: single bounce, 2..8 knots with increasing depth and positive speed */
-        if (P->max_bounces != 1 || P->n_knots < 2 || P->n_knots > ORC_MAXKNOTS) return -5;
+        /* a layered profile: 2..8 knots with increasing depth and positive speed */
+        if (P->n_knots < 2 || P->n_knots > ORC_MAXKNOTS) return -5;
         for (int i = 0; i < P->n_knots; ++i) {
             if (!(P->knot_c[i] > 0.0)) return -5;
             if (i > 0 && !(P->knot_z[i] > P->knot_z[i - 1])) return -5;

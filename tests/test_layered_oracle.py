@@ -1,8 +1,10 @@
 """Pins of the oracle's piecewise-linear sound-speed profile (a general
 depth-dependent c(z); Sec. II-A: rays bend by Snell's law in a sound-speed
 field): knots on one line reproduce the single-gradient model, equal speeds
-reproduce straight rays, and single-bounce returns agree with a numerical
-integration of the ray equations layer by layer (CPU only)."""
+reproduce straight rays, single-bounce returns agree with a numerical
+integration of the ray equations layer by layer, and the return eigenrays of
+multi-bounce paths agree with an independent ray shooter: the same set of
+eigenrays, the first arrival chosen, shadow zones without one (CPU only)."""
 import math
 
 import numpy as np
@@ -11,6 +13,7 @@ from scipy.integrate import solve_ivp
 
 import oracle
 from paper_2606_06130_amd import scenes as S
+from tests import layered_rays as LR
 from tests import meshes as M
 
 
@@ -138,11 +141,123 @@ def test_single_bounce_matches_integrated_ray(theta_deg):
     assert abs(r["amp"][0] - want) <= 1e-6 * abs(want)
 
 
-def test_layered_profile_rejects_several_bounces_and_bad_knots():
+def test_layered_profile_rejects_bad_knots():
     sc = oracle.Scene(M.mesh_from([M.big_triangle_z(-5.0)]))
     pose = S.pose((0.0, 0.0, 0.0))
-    for cfg in (_boxes_cfg(ssp=((-5.0, 1490.0), (0.0, 1500.0)), max_bounces=2),
-                _boxes_cfg(ssp=((0.0, 1490.0), (-5.0, 1500.0))),
-                _boxes_cfg(ssp=((-5.0, 1490.0), (0.0, -1.0)))):
+    for cfg in (_boxes_cfg(ssp=((0.0, 1490.0), (-5.0, 1500.0))),
+                _boxes_cfg(ssp=((-5.0, 1490.0), (0.0, -1.0))),
+                _boxes_cfg(ssp=((-5.0, 1490.0),))):
         with pytest.raises(ValueError):
             oracle.trace_beams(sc, cfg, pose, np.arange(4))
+
+
+@pytest.mark.parametrize("g", [0.05, -0.08, 0.5])
+def test_eigenray_knots_on_one_line_equal_the_circle(g):
+    """Knots on one line: the eigenray is the single-gradient circle through
+    both points (direct or turning), in length, time and both directions."""
+    c0 = 1500.0
+    lin = S.SensorConfig(c_grad=g, c0=c0, r_max=30.0)
+    lay = S.SensorConfig(r_max=30.0, ssp=tuple((z, c0 + g * z) for z in (-20.0, -9.0, -3.0, 0.0, 2.0, 5.0)))
+    rng = np.random.default_rng(11)
+    fams = set()
+    for i in range(400):
+        p = rng.uniform((-20, -20, -15), (20, 20, 3))
+        s = rng.uniform((-20, -20, -15), (20, 20, 3))
+        if i % 3 == 0:
+            s[2] = p[2] + rng.uniform(-0.01, 0.01)          # near-level: turning eigenrays
+        a = oracle.connection(lin, p, s)
+        b = oracle.eigenray(lay, p, s)
+        assert b["ok"] and b["flags"] == 0
+        fams.add(b["fam"])
+        assert abs(b["L"] - a["L"]) <= 1e-9 * a["L"] and abs(b["T"] - a["T"]) <= 1e-9 * a["T"]
+        assert np.abs(b["w_out"] - a["w_out"]).max() < 1e-9 and np.abs(b["arrive"] - a["arrive"]).max() < 1e-9
+    assert fams == {0, 1 if g > 0 else 2}
+
+
+def test_eigenray_equal_speeds_is_the_segment():
+    lay = S.SensorConfig(r_max=30.0, ssp=((-8.0, 1500.0), (-4.0, 1500.0), (-1.0, 1500.0)))
+    rng = np.random.default_rng(12)
+    for _ in range(100):
+        p = rng.uniform((-20, -20, -15), (20, 20, 3))
+        s = rng.uniform((-20, -20, -15), (20, 20, 3))
+        e = oracle.eigenray(lay, p, s)
+        d = np.linalg.norm(s - p)
+        assert e["ok"] and e["fam"] == 0 and e["n_roots"] == 1
+        assert abs(e["L"] - d) < 1e-11 * d and abs(e["T"] - d / 1500.0) < 1e-11 * d / 1500.0
+        assert np.abs(e["w_out"] - (s - p) / d).max() < 1e-12 and np.abs(e["arrive"] - e["w_out"]).max() < 1e-12
+
+
+# Profiles for the shooting checks: a weak gradient under a steep one above
+# the span (turning rays form a caustic: three eigenrays, the fast steep one
+# first), a speed maximum inside the span (direct rays only, out to a
+# horizontal tangent), and speed growing downward (rays turning below).
+_CAUSTIC = ((-20.0, 1482.0), (-11.95, 1490.05), (-10.0, 1529.05), (0.0, 1540.0))
+_SHOOT_CASES = [
+    (_CAUSTIC, (0.0, 0.0, -12.0), (10.0, 0.0, -12.01), 3),
+    (_CAUSTIC, (0.0, 0.0, -12.0), (3.0, 21.0, -12.01), 3),
+    (_CAUSTIC, (0.0, 0.0, -12.0), (27.0, 0.0, -12.01), 1),
+    (_CAUSTIC, (0.0, 0.0, -14.0), (12.0, 5.0, -11.0), None),
+    (((-30.0, 1488.0), (-12.0, 1490.0), (-11.0, 1490.02), (-5.0, 1496.0), (5.0, 1497.0)),
+     (0.0, 0.0, -12.3), (28.0, 0.0, -12.1), None),
+    (((-20.0, 1450.0), (-10.0, 1500.0), (0.0, 1450.0)), (0.0, 0.0, -10.5), (30.0, 0.0, -9.5), 1),
+    (((-30.0, 1510.0), (-8.0, 1500.0), (0.0, 1501.0)), (0.0, 0.0, -7.0), (20.0, 0.0, -7.4), None),
+    (((-30.0, 1560.0), (-8.0, 1500.0), (0.0, 1501.0)), (0.0, 0.0, -7.0), (25.0, 4.0, -7.05), None),
+]
+
+
+@pytest.mark.parametrize("case", range(len(_SHOOT_CASES)))
+def test_eigenrays_match_an_independent_shooter(case):
+    knots, p, s, n_expect = _SHOOT_CASES[case]
+    cfg = S.SensorConfig(r_max=30.0, ssp=knots)
+    e = oracle.eigenray(cfg, p, s)
+    rays = LR.eigenrays(knots, p, s, n_fan=2001, max_angle=0.4)
+    assert e["n_roots"] == len(rays) >= 1
+    if n_expect is not None:
+        assert len(rays) == n_expect
+    th_p, T, L, th_s = rays[0]                                  # the first arrival
+    assert e["flags"] == 0
+    assert abs(e["T"] - T) <= 1e-10 * T and abs(e["L"] - L) <= 1e-9 * L
+    assert abs(math.asin(e["w_out"][2]) - th_p) < 1e-9
+    assert abs(math.asin(e["arrive"][2]) - th_s) < 1e-9
+    d = np.asarray(s) - np.asarray(p)
+    uh = d[:2] / np.hypot(*d[:2])
+    assert np.allclose(e["w_out"][:2] / np.hypot(*e["w_out"][:2]), uh, atol=1e-14)
+
+
+def test_shadow_zone_has_no_eigenray():
+    """A speed maximum between the two points bends every ray away from it:
+    past the horizontal tangent at the maximum no ray connects them."""
+    knots = ((-20.0, 1450.0), (-10.0, 1500.0), (0.0, 1450.0))
+    cfg = S.SensorConfig(r_max=30.0, ssp=knots)
+    p, s = (0.0, 0.0, -10.5), (40.0, 0.0, -9.5)
+    assert not oracle.eigenray(cfg, p, s)["ok"]
+    assert LR.eigenrays(knots, p, s, n_fan=2001, max_angle=0.4) == []
+
+
+def _multipath_scene():
+    surface = M.mesh_from([M.big_triangle_z(1.0)], rho=1.0, phi=0.0, mat=S.MAT_PRESSURE_RELEASE)
+    return oracle.Scene(M.concat(S.scene_seabed_boxes(), surface))
+
+
+@pytest.mark.parametrize("g", [0.05, -0.08])
+def test_multibounce_knots_on_one_line_equal_the_linear_profile(g):
+    sc = _multipath_scene()
+    pose = S.pose_seabed_boxes()
+    c0 = 1500.0
+    base = _boxes_cfg(max_bounces=3, k_d=0.7, k_s=0.3, phong_n=20.0)
+    lin = base.replace(c_grad=g, c0=c0)
+    lay = base.replace(ssp=tuple((z, c0 + g * z) for z in (-9.0, -6.5, -3.25, -1.0, 0.5, 4.0)))
+    beams = np.arange(lin.n_beams)
+    a = oracle.trace_beams(sc, lay, pose, beams)
+    b = oracle.trace_beams(sc, lin, pose, beams)
+    assert (a["tri"][:, 1] >= 0).sum() > 100 and (a["bin"][:, 1:] >= 0).sum() > 5
+    _compare(a, b, amp_rel=1e-7)
+
+
+def test_multibounce_equal_speeds_equal_straight_rays():
+    sc = _multipath_scene()
+    pose = S.pose_seabed_boxes()
+    base = _boxes_cfg(max_bounces=3, k_d=0.7, k_s=0.3, phong_n=20.0)
+    lay = base.replace(ssp=((-8.0, 1500.0), (-4.0, 1500.0), (-1.0, 1500.0)))
+    beams = np.arange(lay.n_beams)
+    _compare(oracle.trace_beams(sc, lay, pose, beams), oracle.trace_beams(sc, base, pose, beams), 1e-10)
