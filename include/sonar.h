@@ -241,10 +241,15 @@ typedef struct {
 
 /* sonar_ping through a piecewise-linear sound-speed profile (params->c0 and
  * c_grad are replaced by it; times convert to range with c at the sensor).
- * Single bounce only (max_bounces 1, else SONAR_E_UNSUPPORTED). Also
- * SONAR_E_INVALID for 2 > n_knots > SONAR_MAX_SSP_KNOTS, knots not strictly
- * increasing, c <= 0 at a knot or over the scene, and SONAR_E_UNSUPPORTED for
- * layers bending more than |g| 2 r_max / c = 1e-2. Asynchronous on
+ * With several bounces each later vertex returns to the sensor along its
+ * first-arriving eigenray among those with at most one turning point (the
+ * direct ray, or one turning above or below both ends at a depth where c
+ * exceeds every speed on the way there, the turning depth searched within
+ * 2 r_max); a vertex no such ray reaches (a shadow zone) returns nothing
+ * (record vis 0). SONAR_E_INVALID for 2 > n_knots > SONAR_MAX_SSP_KNOTS,
+ * knots not strictly increasing, c <= 0 at a knot or over the scene;
+ * SONAR_E_UNSUPPORTED for layers bending more than |g| 2 r_max / c = 1e-2
+ * and for SONAR_FLAG_RX_BEAMS with max_bounces > 1. Asynchronous on
  * `stream`; no workspace. */
 sonar_status sonar_ping_ssp(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
                             const sonar_ssp *ssp, sonar_cf32 *volume, float *gbuffer, float *incoh,

@@ -907,6 +907,7 @@ static oeig eigenray_layered(const orc_params *P, v3 Pp, v3 Sp, double H, const 
                 double zq = z0 + dir * (H * (v * v));
                 const int last = dir * (zq - b) >= 0.0;
                 if (last) zq = b;
+                if (dir * (zq - zp) <= 0.0) continue;       /* a grid point not past the interval start */
                 const int negq = eig_f(P, fam, zq, zlo, zhi, D) <= 0.0;
                 if (negq != negp && nr < EIG_MAXROOTS) {
                     const double zt = eig_bisect(P, fam, zp, zq, zlo, zhi, D);

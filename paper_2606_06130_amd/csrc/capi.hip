@@ -408,7 +408,8 @@ sonar_status sonar_ping_ssp(const sonar_scene *sc, const sonar_params *p, const 
             return fail(SONAR_E_INVALID, "knot %d: z finite and c > 0 required", k);
         if (k > 0 && !(ssp->z[k] > ssp->z[k - 1])) return fail(SONAR_E_INVALID, "knot depths must increase");
     }
-    if (p->max_bounces != 1) return fail(SONAR_E_UNSUPPORTED, "layered profiles take single-bounce pings");
+    if (p->max_bounces > 1 && (p->flags & SONAR_FLAG_RX_BEAMS))
+        return fail(SONAR_E_UNSUPPORTED, "layered profiles do not take receive binning with several bounces");
     const int nl = n - 1;
     double g[SONAR_MAX_SSP_KNOTS], c0[SONAR_MAX_SSP_KNOTS];
     for (int i = 0; i < nl; ++i) {

@@ -604,13 +604,14 @@ __device__ double layer_exit(const PingArgs &a, const int i, const Path64 &p, co
     return best;
 }
 
-// Single-bounce first hit through the layers: each layer's circle is
-// traversed as its own chord segment, in path order, until a hit inside the
-// layer, the end of the range window or a layer the ray never leaves.
+// First hit through the layers: each layer's circle is traversed as its own
+// chord segment, in path order, until a hit inside the layer, the end of the
+// time window or a layer the ray never leaves (`skip`: the facet the segment
+// leaves from).
 template <int DEPTH, int DL, bool STATS>
-__device__ Hit64 first_hit_layered(const PingArgs &a, d3 o, d3 d, const double T_lim, uint32_t *__restrict__ W,
-                                   const int lane, bool &overflow, uint32_t &n_nodes, uint32_t &n_tris,
-                                   uint32_t &n_deep)
+__device__ Hit64 first_hit_layered(const PingArgs &a, d3 o, d3 d, const double T_lim, const uint32_t skip,
+                                   uint32_t *__restrict__ W, const int lane, bool &overflow, uint32_t &n_nodes,
+                                   uint32_t &n_tris, uint32_t &n_deep)
 {
     Hit64 h;
     h.ok = false;
@@ -628,9 +629,9 @@ __device__ Hit64 first_hit_layered(const PingArgs &a, d3 o, d3 d, const double T
         if (s_end > s_min) {
             const Seg32 seg = make_seg(path, s_min, s_end * (1.0 + 1e-6));
             float sf;
-            const int ti = traverse<DEPTH, DL, false, true, STATS>(as_global(a.nodes), as_global(a.tris), seg,
-                                                                   0xFFFFFFFFu, W, lane, overflow, sf, a.max_steps,
-                                                                   n_nodes, n_tris, n_deep);
+            const int ti = traverse<DEPTH, DL, false, true, STATS>(as_global(a.nodes), as_global(a.tris), seg, skip,
+                                                                   W, lane, overflow, sf, a.max_steps, n_nodes, n_tris,
+                                                                   n_deep);
             if (ti >= 0) {
                 const TriF tr = load_tri(as_global(a.tris), (uint32_t)ti);
                 d3 nh;
@@ -657,6 +658,279 @@ __device__ Hit64 first_hit_layered(const PingArgs &a, d3 o, d3 d, const double T
         layer = next;
     }
     return h;
+}
+
+// ---------------------------------------------------------------------------
+// Return eigenrays through the layers. Along a ray Snell's invariant
+// xi = cos(theta) / c is fixed; crossing one layer between depths za and zb
+// without turning, with s = |sin theta| = sqrt(1 - xi^2 c^2), a ray advances
+// horizontally by X = xi |dz| (ca + cb) / (sa + sb), travels arc length
+// |asin sa - asin sb| / (xi |g|) and takes |atanh sa - atanh sb| / |g|; both
+// are evaluated in forms free of cancellation (sin of the angle difference
+// = xi g dz (ca + cb) / (sa cb + sb ca); the time as one log1p). The invariant
+// is written xi = (1 - u) / c(zr) for a reference depth zr (the turning depth
+// with u = 0, or the depth of the span's largest speed), so that
+// 1 - xi c(z) = (c(zr) - c(z) + u c(z)) / c(zr) comes from a sum of gradient
+// times depth and stays accurate next to a turning point.
+struct LRef {
+    double zr, u, cr, xi;
+};
+
+struct LRun {
+    double X, L, T;
+};
+
+__device__ __forceinline__ double lay_speed(const PingArgs &a, double z)
+{
+    const int i = layer_of(a, z);
+    return a.lay_c0[i] + a.lay_g[i] * z;
+}
+
+// c(zb) - c(za) as gradient times depth summed over the layers between them
+__device__ __forceinline__ double lay_dspeed(const PingArgs &a, double za, double zb)
+{
+    const double lo = fmin(za, zb), hi = fmax(za, zb);
+    double sum = 0.0;
+    for (int i = 0; i < a.n_layers; ++i) {
+        const double b0 = i > 0 ? fmax(lo, a.lay_z[i]) : lo;
+        const double b1 = i + 1 < a.n_layers ? fmin(hi, a.lay_z[i + 1]) : hi;
+        if (b1 > b0) sum += a.lay_g[i] * (b1 - b0);
+    }
+    return zb >= za ? sum : -sum;
+}
+
+__device__ __forceinline__ LRef lay_ref(const PingArgs &a, double zr, double u)
+{
+    LRef r;
+    r.zr = zr;
+    r.u = u;
+    r.cr = lay_speed(a, zr);
+    r.xi = (1.0 - u) / r.cr;
+    return r;
+}
+
+__device__ __forceinline__ double lay_sin(const PingArgs &a, const LRef &r, double z)
+{
+    const double q = (lay_dspeed(a, z, r.zr) + r.u * lay_speed(a, z)) / r.cr;     // 1 - xi c(z)
+    return q > 0.0 ? sqrt(q * (2.0 - q)) : 0.0;
+}
+
+// the layers crossed once between depths z0 <= z1
+__device__ __forceinline__ LRun lay_span(const PingArgs &a, const LRef &r, double z0, double z1)
+{
+    LRun t{0.0, 0.0, 0.0};
+    int i = layer_of(a, z0);
+    double za = z0;
+    while (za < z1) {
+        const double zb = i + 1 < a.n_layers ? fmin(a.lay_z[i + 1], z1) : z1;
+        const double g = a.lay_g[i], dz = zb - za;
+        const double ca = a.lay_c0[i] + g * za, cb = a.lay_c0[i] + g * zb;
+        const double sa = lay_sin(a, r, za), sb = lay_sin(a, r, zb);
+        if (sa + sb == 0.0) {
+            // level at both ends: endless in a constant layer, else a rounding sliver
+            if (g == 0.0) return LRun{INFINITY, INFINITY, INFINITY};
+            t.L += dz;
+            t.T += dz / ca;
+        } else {
+            t.X += r.xi * dz * (ca + cb) / (sa + sb);
+            const double m = (ca + cb) / (sa * cb + sb * ca);
+            const double y = fmin(1.0, r.xi * fabs(g) * dz * m);
+            t.L += dz * m * (y > 0.0 ? asin(y) / y : 1.0);
+            const double q = (1.0 + m) / ((1.0 + sb) * ca);
+            t.T += g != 0.0 ? fabs(log1p(g * dz * q) / g) : dz * q;
+        }
+        za = zb;
+        ++i;
+    }
+    return t;
+}
+
+// family 0 direct; 1 turning at zr above zhi; 2 turning at zr below zlo
+__device__ __forceinline__ LRun lay_family(const PingArgs &a, int fam, const LRef &r, double zlo, double zhi)
+{
+    LRun t = lay_span(a, r, zlo, zhi);
+    if (fam != 0) {
+        const LRun b = fam == 1 ? lay_span(a, r, zhi, r.zr) : lay_span(a, r, r.zr, zlo);
+        t.X += 2.0 * b.X;
+        t.L += 2.0 * b.L;
+        t.T += 2.0 * b.T;
+    }
+    return t;
+}
+
+__device__ __forceinline__ bool lay_short(const PingArgs &a, int fam, double zt, double zlo, double zhi, double D)
+{
+    return lay_family(a, fam, lay_ref(a, zt, 0.0), zlo, zhi).X - D <= 0.0;
+}
+
+constexpr int EIG_CELLS = 64;      // turning-depth scan cells (uniform in sqrt of the rise)
+
+struct LConn {
+    double L, T;
+    d3 w, arrive;
+    bool ok;
+};
+
+// The first-arriving eigenray with at most one turning point from P to S:
+// the direct ray (its horizontal run grows with xi up to 1 / c_max of the
+// span: bisection), or a ray turning above the span or below it, at a depth
+// where c exceeds every speed met on the way there. Turning depths within
+// H = 2 r_max of the span are scanned at rises H (j / 64)^2 plus the ends of
+// each turning interval, and every sign change of the run's mismatch is
+// bisected. ok = false: no eigenray (an acoustic shadow).
+__device__ __forceinline__ LConn connect_layered(const PingArgs &a, const d3 P, const d3 S)
+{
+    LConn c;
+    c.ok = false;
+    const d3 v = S - P;
+    const double D = sqrt(v.x * v.x + v.y * v.y);
+    const double zlo = fmin(P.z, S.z), zhi = fmax(P.z, S.z);
+    double zm = lay_speed(a, zlo) >= lay_speed(a, zhi) ? zlo : zhi;
+    for (int i = 1; i < a.n_layers; ++i) {
+        const double zk = a.lay_z[i];
+        if (zk > zlo && zk < zhi && a.lay_c0[i] + a.lay_g[i] * zk > lay_speed(a, zm)) zm = zk;
+    }
+    const double cm = lay_speed(a, zm);
+    int best_fam = -1;
+    double best_zr = 0.0, best_u = 0.0, best_T = INFINITY;
+    // direct family: xi = (1 - u) / cm, the run shrinking as u grows
+    if (zlo == zhi) {
+        if (a.lay_g[layer_of(a, zlo)] == 0.0 && D > 0.0) {
+            best_fam = 0;
+            best_zr = zm;
+            best_T = D / cm;
+        }
+    } else if (D == 0.0) {
+        best_fam = 0;
+        best_zr = zm;
+        best_u = 1.0;
+        best_T = lay_span(a, lay_ref(a, zm, 1.0), zlo, zhi).T;
+    } else if (lay_span(a, lay_ref(a, zm, 0.0), zlo, zhi).X > D) {
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid == lo || mid == hi) break;
+            if (lay_span(a, lay_ref(a, zm, mid), zlo, zhi).X > D) lo = mid;
+            else hi = mid;
+        }
+        best_fam = 0;
+        best_zr = zm;
+        best_u = 0.5 * (lo + hi);
+        best_T = lay_span(a, lay_ref(a, zm, best_u), zlo, zhi).T;
+    }
+    // turning families
+    const double H = 2.0 * a.r_max;
+    for (int fam = 1; fam <= 2; ++fam) {
+        const double dir = fam == 1 ? 1.0 : -1.0, z0 = fam == 1 ? zhi : zlo;
+        // walk the layers away from the span; each one where c rises past the
+        // record so far contributes its turning interval [ta, tb] (along the walk)
+        double M = cm, z = z0;
+        int i = layer_of(a, z0);
+        if (fam == 2 && i > 0 && z0 == a.lay_z[i]) --i;
+        for (int step = 0; step < MAX_SSP_KNOTS && i >= 0 && i < a.n_layers; ++step) {
+            const double g = a.lay_g[i], c0 = a.lay_c0[i];
+            const double edge = fam == 1 ? (i + 1 < a.n_layers ? a.lay_z[i + 1] : INFINITY)
+                                         : (i > 0 ? a.lay_z[i] : -INFINITY);
+            const double zend = z0 + dir * H;
+            const double zb = fam == 1 ? fmin(edge, zend) : fmax(edge, zend);
+            if (g * dir > 0.0) {
+                const double zs = (M - c0) / g;
+                const double ta = fam == 1 ? fmax(zs, z) : fmin(zs, z);
+                if (dir * (zb - ta) > 0.0) {
+                    double zp = ta;
+                    bool negp = lay_short(a, fam, zp, zlo, zhi, D);
+                    for (int j = (int)floor(sqrt(fabs(ta - z0) / H) * EIG_CELLS) + 1;; ++j) {
+                        const double vj = (double)j / EIG_CELLS;
+                        double zq = z0 + dir * (H * (vj * vj));
+                        const bool last = dir * (zq - zb) >= 0.0;
+                        if (last) zq = zb;
+                        if (dir * (zq - zp) <= 0.0) continue;      // a grid point not past the interval start
+                        const bool negq = lay_short(a, fam, zq, zlo, zhi, D);
+                        if (negq != negp) {
+                            double ea = zp, eb = zq;
+                            for (int it = 0; it < 200; ++it) {
+                                const double mid = 0.5 * (ea + eb);
+                                if (mid == ea || mid == eb) break;
+                                if (lay_short(a, fam, mid, zlo, zhi, D) == negp) ea = mid;
+                                else eb = mid;
+                            }
+                            const double zt = 0.5 * (ea + eb);
+                            const double T = lay_family(a, fam, lay_ref(a, zt, 0.0), zlo, zhi).T;
+                            if (T < best_T) {
+                                best_T = T;
+                                best_fam = fam;
+                                best_zr = zt;
+                                best_u = 0.0;
+                            }
+                        }
+                        if (last) break;
+                        zp = zq;
+                        negp = negq;
+                    }
+                }
+                M = fmax(M, c0 + g * zb);
+            }
+            if (dir * (zb - zend) >= 0.0) break;
+            z = zb;
+            i += fam == 1 ? 1 : -1;
+        }
+    }
+    if (best_fam < 0) return c;
+    const LRef r = lay_ref(a, best_zr, best_u);
+    LRun run = lay_family(a, best_fam, r, zlo, zhi);
+    if (best_fam == 0 && zlo == zhi) {
+        run.L = D;
+        run.T = D / cm;
+    }
+    c.ok = true;
+    c.L = run.L;
+    c.T = run.T;
+    const double ux = D > 0.0 ? v.x / D : 0.0, uy = D > 0.0 ? v.y / D : 0.0;
+    const double cp = r.xi * lay_speed(a, P.z), cs = r.xi * lay_speed(a, S.z);
+    const double sp = lay_sin(a, r, P.z), ss = lay_sin(a, r, S.z);
+    const double up = S.z > P.z ? 1.0 : (S.z < P.z ? -1.0 : 0.0);
+    const double vp = best_fam == 0 ? up : (best_fam == 1 ? 1.0 : -1.0);
+    const double vs = best_fam == 0 ? up : (best_fam == 1 ? -1.0 : 1.0);
+    const d3 w = mk3(cp * ux, cp * uy, vp * sp), ar = mk3(cs * ux, cs * uy, vs * ss);
+    c.w = w * (1.0 / norm3(w));
+    c.arrive = ar * (1.0 / norm3(ar));
+    return c;
+}
+
+// Occlusion of a layered return path leaving P along w for arc length L:
+// one circle per layer, each piece an any-hit query over its part of
+// (EPS_SELF, L - EPS_SELF), the facet `skip` excluded.
+template <int DEPTH, int DL, bool STATS>
+__device__ __forceinline__ bool occluded_layered(const PingArgs &a, const d3 P, const d3 w, const double L, const uint32_t skip,
+                                 uint32_t *__restrict__ W, const int lane, bool &overflow, uint32_t &n_nodes,
+                                 uint32_t &n_tris, uint32_t &n_deep)
+{
+    int layer = layer_of(a, P.z);
+    if (layer > 0 && P.z == a.lay_z[layer] && w.z < 0.0) --layer;
+    d3 o = P, d = w;
+    double s0 = 0.0;
+    for (int piece = 0; piece < 64; ++piece) {
+        const double g = a.lay_g[layer], c0 = a.lay_c0[layer];
+        const Path64 path = make_path(o, d, g, c0);
+        int next;
+        const double s_exit = layer_exit(a, layer, path, g, c0, next);
+        const double lo = fmax(EPS_SELF - s0, 0.0), hi = fmin(s_exit, L - EPS_SELF - s0);
+        if (hi > lo) {
+            const Seg32 seg = make_seg(path, lo, hi);
+            float sf;
+            const int hb = traverse<DEPTH, DL, true, true, STATS>(as_global(a.nodes), as_global(a.tris), seg, skip, W,
+                                                                  lane, overflow, sf, a.max_steps, n_nodes, n_tris,
+                                                                  n_deep);
+            if (hb >= 0) return true;
+        }
+        if (next < 0 || s0 + s_exit >= L) break;
+        s0 += s_exit;
+        o = path_point(path, s_exit);
+        d = path_tangent(path, s_exit);
+        d = d * (1.0 / norm3(d));
+        layer = next;
+    }
+    return false;
 }
 
 // Monte-Carlo continuation after a rough facet: the Phong lobe around the
@@ -806,8 +1080,8 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                     float sf = 0.f;
                     int ti;
                     if constexpr (LAYERED) {
-                        hit = first_hit_layered<DEPTH, DL, STATS>(a, o, d, T_lim, W, lane, overflow, st_nodes, st_tris,
-                                                                  st_deep);
+                        hit = first_hit_layered<DEPTH, DL, STATS>(a, o, d, T_lim, prev, W, lane, overflow, st_nodes,
+                                                                  st_tris, st_deep);
                         ti = hit.ok ? 0 : -1;
                     } else {
                         path = ARC ? make_path(o, d, a.g, a.c0) : Path64{o, d, mk3(0, 0, 0), 0.0, false};
@@ -870,7 +1144,18 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                                 T_back = T_out;
                                 w = din * -1.0;
                             } else {
-                                const Conn cn = connect(X, S, ARC ? a.g : 0.0, a.c0);
+                                Conn cn;
+                                if constexpr (LAYERED) {
+                                    const LConn lc = connect_layered(a, X, S);
+                                    cn = Conn{lc.L, lc.T, lc.w, lc.arrive};
+                                    if (!lc.ok) {
+                                        // no eigenray reaches the sensor: a shadow zone
+                                        vis = false;
+                                        cn = Conn{0.0, 0.0, mk3(0.0, 0.0, 0.0), mk3(0.0, 0.0, 0.0)};
+                                    }
+                                } else {
+                                    cn = connect(X, S, ARC ? a.g : 0.0, a.c0);
+                                }
                                 L_back = cn.L;
                                 T_back = cn.T;
                                 w = cn.w;
@@ -959,13 +1244,21 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                             }
                             // visibility of the connection: any hit other than this facet
                             if (k > 0 && vis && L_back > 2.0 * EPS_SELF) {
-                                const Path64 cp =
-                                    ARC ? make_path(X, w, a.g, a.c0) : Path64{X, w, mk3(0, 0, 0), 0.0, false};
-                                const Seg32 cs = make_seg(cp, EPS_SELF, L_back - EPS_SELF);
-                                float sa2;
-                                int hb = traverse<DEPTH, DL, true, ARC, STATS>(as_global(a.nodes), as_global(a.tris), cs, id, W, lane, overflow, sa2,
-                                                                    a.max_steps, st_nodes, st_tris, st_deep);
-                                if (hb >= 0) {
+                                bool blocked;
+                                if constexpr (LAYERED) {
+                                    blocked = occluded_layered<DEPTH, DL, STATS>(a, X, w, L_back, id, W, lane, overflow,
+                                                                                 st_nodes, st_tris, st_deep);
+                                } else {
+                                    const Path64 cp =
+                                        ARC ? make_path(X, w, a.g, a.c0) : Path64{X, w, mk3(0, 0, 0), 0.0, false};
+                                    const Seg32 cs = make_seg(cp, EPS_SELF, L_back - EPS_SELF);
+                                    float sa2;
+                                    blocked = traverse<DEPTH, DL, true, ARC, STATS>(as_global(a.nodes), as_global(a.tris),
+                                                                                   cs, id, W, lane, overflow, sa2,
+                                                                                   a.max_steps, st_nodes, st_tris,
+                                                                                   st_deep) >= 0;
+                                }
+                                if (blocked) {
                                     vis = false;
                                     cbin = -1;
                                     cre = cim = cinc = 0.f;
@@ -1361,14 +1654,26 @@ hipError_t launch_ping_layered(const PingArgs &a, int stack_depth, hipStream_t s
     int nblocks = (int)((threads + BLOCK - 1) / BLOCK);
     if (nblocks == 0) return hipSuccess;
     int depth = stack_depth <= 32 && !a.stats ? 32 : 64;
-    int ww = ping_wave_words(depth, a.n_bins, 1);
+    int ww = ping_wave_words(depth, a.n_bins, a.K);
     size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
-    if (a.stats)
-        hipLaunchKernelGGL((k_ping<64, 1, true, true, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww);
-    else if (depth == 32)
-        hipLaunchKernelGGL((k_ping<32, 1, true, false, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww);
-    else
-        hipLaunchKernelGGL((k_ping<64, 1, true, false, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww);
+#define SONAR_LAUNCH(D, KK, ST) \
+    hipLaunchKernelGGL((k_ping<D, KK, true, ST, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww)
+#define SONAR_LAUNCH_K(D, ST)                     \
+    switch (a.K) {                                \
+        case 1: SONAR_LAUNCH(D, 1, ST); break;    \
+        case 2: SONAR_LAUNCH(D, 2, ST); break;    \
+        case 3: SONAR_LAUNCH(D, 3, ST); break;    \
+        default: SONAR_LAUNCH(D, 4, ST); break;   \
+    }
+    if (a.stats) {
+        SONAR_LAUNCH_K(64, true)
+    } else if (depth == 32) {
+        SONAR_LAUNCH_K(32, false)
+    } else {
+        SONAR_LAUNCH_K(64, false)
+    }
+#undef SONAR_LAUNCH_K
+#undef SONAR_LAUNCH
     return hipGetLastError();
 }
 

@@ -357,7 +357,7 @@ def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=F
     p = params if params is not None else params_of(cfg)
     q = pose_s if pose_s is not None else pose_of(pose)
     if getattr(cfg, "ssp", ()):
-        # piecewise-linear sound speed (single bounce)
+        # piecewise-linear sound speed
         prof = ssp_of(cfg.ssp)
         _check(lib().sonar_ping_ssp(scene.handle, C.byref(p), C.byref(q), C.byref(prof), _dptr(out["volume"]),
                                     _dptr(out.get("gbuffer")), _dptr(out.get("incoh")),
