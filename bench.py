@@ -170,6 +170,22 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     rx_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     moved = int(out_rx["rx_workspace"][:4].view(torch.int32).item())
     del out_rx
+    # the same ping through the five-knot layered profile: later legs walked
+    # layer by layer, returns along searched eigenrays
+    cfg_l = cfg.replace(c_grad=0.0, ssp=LAYERED_KNOTS)
+    out_l = sonar.alloc_outputs(cfg_l)
+    for _ in range(2):
+        sonar.ping(scene, cfg_l, pose, out=out_l)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for a, b in ev:
+        a.record(stream)
+        sonar.ping(scene, cfg_l, pose, out=out_l)
+        b.record(stream)
+    torch.cuda.synchronize()
+    assert scene.status() == 0
+    lay_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    del out_l
     multipath = {"workload": "harbor multipath ping: 1,991,680 triangles, 256x128 beams x 16 rays, 3 bounces, "
                              "Phong-20 + diffuse, c(z) = 1500 + 0.05 z, 1,024 bins",
                  "ping_ms": mp_ms, "pings_per_s": 1e3 / mp_ms, "mrays_per_s": cfg.n_rays / mp_ms / 1e3,
@@ -177,7 +193,10 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
                  "beam_pattern_rx_binning": {"ping_ms": rx_ms, "moved_returns": moved,
                                              "note": "same ping with the Gaussian transmit-receive pattern and "
                                                      "later-bounce returns binned by arrival direction (list + "
-                                                     "scatter after the ping kernel)"}}
+                                                     "scatter after the ping kernel)"},
+                 "layered_profile": {"ping_ms": lay_ms,
+                                     "note": "same ping through c(z) piecewise linear in 5 knots from -9 m to 1.5 m: "
+                                             "returns along the first-arriving eigenray of each vertex"}}
     del out
 
     # surrogate ping: single-bounce ping with G-buffer and incoherent channel,

@@ -667,17 +667,15 @@ __device__ Hit64 first_hit_layered(const PingArgs &a, d3 o, d3 d, const double T
 // horizontally by X = xi |dz| (ca + cb) / (sa + sb), travels arc length
 // |asin sa - asin sb| / (xi |g|) and takes |atanh sa - atanh sb| / |g|; both
 // are evaluated in forms free of cancellation (sin of the angle difference
-// = xi g dz (ca + cb) / (sa cb + sb ca); the time as one log1p). The invariant
-// is written xi = (1 - u) / c(zr) for a reference depth zr (the turning depth
-// with u = 0, or the depth of the span's largest speed), so that
-// 1 - xi c(z) = (c(zr) - c(z) + u c(z)) / c(zr) comes from a sum of gradient
-// times depth and stays accurate next to a turning point.
-struct LRef {
-    double zr, u, cr, xi;
-};
-
+// = xi g dz (ca + cb) / (sa cb + sb ca); the time as one log1p). A ray family
+// has a reference depth zr: the turning depth (xi = 1 / c(zr)) or, for the
+// direct ray, the depth of the span's largest speed (xi = (1 - u) / c(zr)).
+// Walking away from zr the speed deficit e = c(zr) - c(z) is accumulated
+// layer by layer from e(zr) = 0, so 1 - xi c(z) = (e + u c(z)) / c(zr) stays
+// accurate next to a turning point.
 struct LRun {
     double X, L, T;
+    double e_lo, e_hi;      // speed deficits at the lower and upper end of the span
 };
 
 __device__ __forceinline__ double lay_speed(const PingArgs &a, double z)
@@ -686,84 +684,118 @@ __device__ __forceinline__ double lay_speed(const PingArgs &a, double z)
     return a.lay_c0[i] + a.lay_g[i] * z;
 }
 
-// c(zb) - c(za) as gradient times depth summed over the layers between them
-__device__ __forceinline__ double lay_dspeed(const PingArgs &a, double za, double zb)
+__device__ __forceinline__ double lay_sine(double e, double u, double c, double inv_cr)
 {
-    const double lo = fmin(za, zb), hi = fmax(za, zb);
-    double sum = 0.0;
-    for (int i = 0; i < a.n_layers; ++i) {
-        const double b0 = i > 0 ? fmax(lo, a.lay_z[i]) : lo;
-        const double b1 = i + 1 < a.n_layers ? fmin(hi, a.lay_z[i + 1]) : hi;
-        if (b1 > b0) sum += a.lay_g[i] * (b1 - b0);
-    }
-    return zb >= za ? sum : -sum;
-}
-
-__device__ __forceinline__ LRef lay_ref(const PingArgs &a, double zr, double u)
-{
-    LRef r;
-    r.zr = zr;
-    r.u = u;
-    r.cr = lay_speed(a, zr);
-    r.xi = (1.0 - u) / r.cr;
-    return r;
-}
-
-__device__ __forceinline__ double lay_sin(const PingArgs &a, const LRef &r, double z)
-{
-    const double q = (lay_dspeed(a, z, r.zr) + r.u * lay_speed(a, z)) / r.cr;     // 1 - xi c(z)
+    const double q = (e + u * c) * inv_cr;      // 1 - xi c
     return q > 0.0 ? sqrt(q * (2.0 - q)) : 0.0;
 }
 
-// the layers crossed once between depths z0 <= z1
-__device__ __forceinline__ LRun lay_span(const PingArgs &a, const LRef &r, double z0, double z1)
+// Walk from z0 to z1 (either direction), each layer crossed once, adding to
+// t; e is the speed deficit at z0 on entry and at z1 on return. FULL adds
+// arc length and time to the horizontal run; `times` counts the walk twice
+// (the two legs of a turning ray).
+template <bool FULL>
+__device__ __forceinline__ void lay_walk(const PingArgs &a, double cr, double u, double z0, double z1, double &e,
+                                         double times, LRun &t)
 {
-    LRun t{0.0, 0.0, 0.0};
+    const double inv = 1.0 / cr, xi = (1.0 - u) * inv;
+    const bool up = z1 >= z0;
     int i = layer_of(a, z0);
-    double za = z0;
-    while (za < z1) {
-        const double zb = i + 1 < a.n_layers ? fmin(a.lay_z[i + 1], z1) : z1;
-        const double g = a.lay_g[i], dz = zb - za;
-        const double ca = a.lay_c0[i] + g * za, cb = a.lay_c0[i] + g * zb;
-        const double sa = lay_sin(a, r, za), sb = lay_sin(a, r, zb);
+    if (!up && i > 0 && z0 == a.lay_z[i]) --i;          // going down from a knot: the layer below
+    double z = z0;
+    double ca = a.lay_c0[i] + a.lay_g[i] * z;
+    double sa = lay_sine(e, u, ca, inv);
+    for (int step = 0; step < MAX_SSP_KNOTS && z != z1; ++step) {
+        const double edge = up ? (i + 1 < a.n_layers ? a.lay_z[i + 1] : INFINITY) : (i > 0 ? a.lay_z[i] : -INFINITY);
+        const double zb = up ? fmin(edge, z1) : fmax(edge, z1);
+        const double g = a.lay_g[i], dzs = zb - z, dz = fabs(dzs);
+        const double cb = a.lay_c0[i] + g * zb;
+        const double eb = e - g * dzs;
+        const double sb = lay_sine(eb, u, cb, inv);
         if (sa + sb == 0.0) {
             // level at both ends: endless in a constant layer, else a rounding sliver
-            if (g == 0.0) return LRun{INFINITY, INFINITY, INFINITY};
-            t.L += dz;
-            t.T += dz / ca;
+            if (g == 0.0) {
+                t.X = t.L = t.T = INFINITY;
+            } else if (FULL) {
+                t.L += times * dz;
+                t.T += times * dz / ca;
+            }
         } else {
-            t.X += r.xi * dz * (ca + cb) / (sa + sb);
-            const double m = (ca + cb) / (sa * cb + sb * ca);
-            const double y = fmin(1.0, r.xi * fabs(g) * dz * m);
-            t.L += dz * m * (y > 0.0 ? asin(y) / y : 1.0);
-            const double q = (1.0 + m) / ((1.0 + sb) * ca);
-            t.T += g != 0.0 ? fabs(log1p(g * dz * q) / g) : dz * q;
+            t.X += times * (xi * dz * (ca + cb) / (sa + sb));
+            if (FULL) {
+                const double m = (ca + cb) / (sa * cb + sb * ca);
+                const double y = fmin(1.0, xi * fabs(g) * dz * m);
+                t.L += times * (dz * m * (y > 0.0 ? asin(y) / y : 1.0));
+                const double q = (1.0 + m) / ((1.0 + sb) * ca);
+                t.T += times * (g != 0.0 ? fabs(log1p(g * dzs * q) / g) : dz * q);
+            }
         }
-        za = zb;
-        ++i;
+        z = zb;
+        e = eb;
+        ca = cb;
+        sa = sb;
+        i += up ? 1 : -1;
+    }
+}
+
+// family 0: direct, reference zr = the span's fastest depth with u; 1 and 2:
+// turning at zr above zhi or below zlo (u = 0)
+template <bool FULL>
+__device__ __forceinline__ LRun lay_family(const PingArgs &a, int fam, double zr, double u, double zlo, double zhi)
+{
+    LRun t{0.0, 0.0, 0.0, 0.0, 0.0};
+    const double cr = lay_speed(a, zr);
+    double e = 0.0;
+    if (fam == 0) {
+        lay_walk<FULL>(a, cr, u, zr, zlo, e, 1.0, t);
+        t.e_lo = e;
+        e = 0.0;
+        lay_walk<FULL>(a, cr, u, zr, zhi, e, 1.0, t);
+        t.e_hi = e;
+    } else if (fam == 1) {
+        lay_walk<FULL>(a, cr, 0.0, zr, zhi, e, 2.0, t);
+        t.e_hi = e;
+        lay_walk<FULL>(a, cr, 0.0, zhi, zlo, e, 1.0, t);
+        t.e_lo = e;
+    } else {
+        lay_walk<FULL>(a, cr, 0.0, zr, zlo, e, 2.0, t);
+        t.e_lo = e;
+        lay_walk<FULL>(a, cr, 0.0, zlo, zhi, e, 1.0, t);
+        t.e_hi = e;
     }
     return t;
 }
 
-// family 0 direct; 1 turning at zr above zhi; 2 turning at zr below zlo
-__device__ __forceinline__ LRun lay_family(const PingArgs &a, int fam, const LRef &r, double zlo, double zhi)
+// Root of f on [pa, pb] (f <= 0 at one end only) by the Illinois variant of
+// regula falsi, to a relative bracket of 1e-15 or |f| <= 1e-15 d.
+template <class F>
+__device__ __forceinline__ double illinois(const F &f, double pa, double fa, double pb, double fb, double d)
 {
-    LRun t = lay_span(a, r, zlo, zhi);
-    if (fam != 0) {
-        const LRun b = fam == 1 ? lay_span(a, r, zhi, r.zr) : lay_span(a, r, r.zr, zlo);
-        t.X += 2.0 * b.X;
-        t.L += 2.0 * b.L;
-        t.T += 2.0 * b.T;
+    int side = 0;
+    double pc = 0.5 * (pa + pb);
+    for (int it = 0; it < 100; ++it) {
+        pc = (pa * fb - pb * fa) / (fb - fa);
+        if (!(pc > fmin(pa, pb) && pc < fmax(pa, pb))) pc = 0.5 * (pa + pb);
+        if (pc == pa || pc == pb) break;
+        const double fc = f(pc);
+        if (fabs(fc) <= 1e-15 * d) break;
+        if ((fc <= 0.0) == (fb <= 0.0)) {
+            pb = pc;
+            fb = fc;
+            if (side == -1) fa *= 0.5;
+            side = -1;
+        } else {
+            pa = pc;
+            fa = fc;
+            if (side == 1) fb *= 0.5;
+            side = 1;
+        }
+        if (fabs(pb - pa) <= 1e-15 * fmax(fabs(pa), fabs(pb))) break;
     }
-    return t;
+    return pc;
 }
 
-__device__ __forceinline__ bool lay_short(const PingArgs &a, int fam, double zt, double zlo, double zhi, double D)
-{
-    return lay_family(a, fam, lay_ref(a, zt, 0.0), zlo, zhi).X - D <= 0.0;
-}
-
-constexpr int EIG_CELLS = 64;      // turning-depth scan cells (uniform in sqrt of the rise)
+constexpr int EIG_CELLS = 64;      // turning-depth scan cells, uniform in sqrt(rise / window)
 
 struct LConn {
     double L, T;
@@ -772,12 +804,14 @@ struct LConn {
 };
 
 // The first-arriving eigenray with at most one turning point from P to S:
-// the direct ray (its horizontal run grows with xi up to 1 / c_max of the
-// span: bisection), or a ray turning above the span or below it, at a depth
+// the direct ray (its horizontal run shrinks as u = 1 - xi c_max grows;
+// root in sqrt(u)), or a ray turning above the span or below it, at a depth
 // where c exceeds every speed met on the way there. Turning depths within
 // H = 2 r_max of the span are scanned at rises H (j / 64)^2 plus the ends of
-// each turning interval, and every sign change of the run's mismatch is
-// bisected. ok = false: no eigenray (an acoustic shadow).
+// each turning interval; every sign change of the run's mismatch is refined
+// in sqrt(rise / H). A family's scan ends once a lower bound of a turning
+// ray's time passes the best arrival found. ok = false: no eigenray (an
+// acoustic shadow).
 __device__ __forceinline__ LConn connect_layered(const PingArgs &a, const d3 P, const d3 S)
 {
     LConn c;
@@ -792,80 +826,92 @@ __device__ __forceinline__ LConn connect_layered(const PingArgs &a, const d3 P, 
     }
     const double cm = lay_speed(a, zm);
     int best_fam = -1;
-    double best_zr = 0.0, best_u = 0.0, best_T = INFINITY;
-    // direct family: xi = (1 - u) / cm, the run shrinking as u grows
+    double best_zr = 0.0, best_u = 0.0;
+    LRun best{0.0, INFINITY, INFINITY, 0.0, 0.0};
+    // direct family
     if (zlo == zhi) {
         if (a.lay_g[layer_of(a, zlo)] == 0.0 && D > 0.0) {
             best_fam = 0;
             best_zr = zm;
-            best_T = D / cm;
+            best = LRun{D, D, D / cm, 0.0, 0.0};          // level in a constant layer
         }
     } else if (D == 0.0) {
         best_fam = 0;
         best_zr = zm;
         best_u = 1.0;
-        best_T = lay_span(a, lay_ref(a, zm, 1.0), zlo, zhi).T;
-    } else if (lay_span(a, lay_ref(a, zm, 0.0), zlo, zhi).X > D) {
-        double lo = 0.0, hi = 1.0;
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (mid == lo || mid == hi) break;
-            if (lay_span(a, lay_ref(a, zm, mid), zlo, zhi).X > D) lo = mid;
-            else hi = mid;
+        best = lay_family<true>(a, 0, zm, 1.0, zlo, zhi);
+    } else {
+        auto f = [&](double w) { return lay_family<false>(a, 0, zm, w * w, zlo, zhi).X - D; };
+        const double f0 = f(0.0);
+        if (f0 > 0.0) {
+            const double w = illinois(f, 0.0, f0, 1.0, -D, D);
+            best_fam = 0;
+            best_zr = zm;
+            best_u = w * w;
+            best = lay_family<true>(a, 0, zm, best_u, zlo, zhi);
         }
-        best_fam = 0;
-        best_zr = zm;
-        best_u = 0.5 * (lo + hi);
-        best_T = lay_span(a, lay_ref(a, zm, best_u), zlo, zhi).T;
     }
     // turning families
-    const double H = 2.0 * a.r_max;
+    const double H = 2.0 * a.r_max, span = zhi - zlo;
     for (int fam = 1; fam <= 2; ++fam) {
-        const double dir = fam == 1 ? 1.0 : -1.0, z0 = fam == 1 ? zhi : zlo;
-        // walk the layers away from the span; each one where c rises past the
-        // record so far contributes its turning interval [ta, tb] (along the walk)
+        const double dir = fam == 1 ? 1.0 : -1.0, z0 = fam == 1 ? zhi : zlo, zend = z0 + dir * H;
+        auto zt_of = [&](double vv) { return z0 + dir * (H * (vv * vv)); };
+        auto f = [&](double vv) { return lay_family<false>(a, fam, zt_of(vv), 0.0, zlo, zhi).X - D; };
+        // A ray turning at rise r travels at least sqrt(D^2 + (2 r + span)^2)
+        // at no more than the window's largest speed: once that bound passes
+        // the best arrival, no later turning depth can arrive first.
+        double c_win = fmax(lay_speed(a, z0), lay_speed(a, zend));
+        for (int k = 1; k < a.n_layers; ++k)
+            if (dir * (a.lay_z[k] - z0) > 0.0 && dir * (zend - a.lay_z[k]) > 0.0)
+                c_win = fmax(c_win, a.lay_c0[k] + a.lay_g[k] * a.lay_z[k]);
+        auto slower = [&](double vv) {
+            const double vert = 2.0 * H * (vv * vv) + span;
+            return sqrt(D * D + vert * vert) >= best.T * c_win;
+        };
         double M = cm, z = z0;
         int i = layer_of(a, z0);
         if (fam == 2 && i > 0 && z0 == a.lay_z[i]) --i;
-        for (int step = 0; step < MAX_SSP_KNOTS && i >= 0 && i < a.n_layers; ++step) {
+        bool done = false;
+        for (int step = 0; step < MAX_SSP_KNOTS && !done && i >= 0 && i < a.n_layers; ++step) {
             const double g = a.lay_g[i], c0 = a.lay_c0[i];
             const double edge = fam == 1 ? (i + 1 < a.n_layers ? a.lay_z[i + 1] : INFINITY)
                                          : (i > 0 ? a.lay_z[i] : -INFINITY);
-            const double zend = z0 + dir * H;
             const double zb = fam == 1 ? fmin(edge, zend) : fmax(edge, zend);
             if (g * dir > 0.0) {
+                // turning interval of this layer: from where c passes the record M to zb
                 const double zs = (M - c0) / g;
                 const double ta = fam == 1 ? fmax(zs, z) : fmin(zs, z);
                 if (dir * (zb - ta) > 0.0) {
-                    double zp = ta;
-                    bool negp = lay_short(a, fam, zp, zlo, zhi, D);
-                    for (int j = (int)floor(sqrt(fabs(ta - z0) / H) * EIG_CELLS) + 1;; ++j) {
-                        const double vj = (double)j / EIG_CELLS;
-                        double zq = z0 + dir * (H * (vj * vj));
-                        const bool last = dir * (zq - zb) >= 0.0;
-                        if (last) zq = zb;
-                        if (dir * (zq - zp) <= 0.0) continue;      // a grid point not past the interval start
-                        const bool negq = lay_short(a, fam, zq, zlo, zhi, D);
-                        if (negq != negp) {
-                            double ea = zp, eb = zq;
-                            for (int it = 0; it < 200; ++it) {
-                                const double mid = 0.5 * (ea + eb);
-                                if (mid == ea || mid == eb) break;
-                                if (lay_short(a, fam, mid, zlo, zhi, D) == negp) ea = mid;
-                                else eb = mid;
-                            }
-                            const double zt = 0.5 * (ea + eb);
-                            const double T = lay_family(a, fam, lay_ref(a, zt, 0.0), zlo, zhi).T;
-                            if (T < best_T) {
-                                best_T = T;
+                    const double va = sqrt(fabs(ta - z0) / H), vb = sqrt(fabs(zb - z0) / H);
+                    if (slower(va)) {
+                        done = true;
+                        break;
+                    }
+                    double vp = va, fp = f(va);
+                    for (int j = (int)floor(va * EIG_CELLS) + 1;; ++j) {
+                        double vq = (double)j / EIG_CELLS;
+                        const bool last = vq >= vb;
+                        if (last) vq = vb;
+                        if (vq <= vp) continue;
+                        if (slower(vp)) {
+                            done = true;
+                            break;
+                        }
+                        const double fq = f(vq);
+                        if ((fq <= 0.0) != (fp <= 0.0)) {
+                            const double vr = illinois(f, vp, fp, vq, fq, D);
+                            const double zr = zt_of(vr);
+                            const LRun r = lay_family<true>(a, fam, zr, 0.0, zlo, zhi);
+                            if (r.T < best.T) {
+                                best = r;
                                 best_fam = fam;
-                                best_zr = zt;
+                                best_zr = zr;
                                 best_u = 0.0;
                             }
                         }
                         if (last) break;
-                        zp = zq;
-                        negp = negq;
+                        vp = vq;
+                        fp = fq;
                     }
                 }
                 M = fmax(M, c0 + g * zb);
@@ -876,22 +922,19 @@ __device__ __forceinline__ LConn connect_layered(const PingArgs &a, const d3 P, 
         }
     }
     if (best_fam < 0) return c;
-    const LRef r = lay_ref(a, best_zr, best_u);
-    LRun run = lay_family(a, best_fam, r, zlo, zhi);
-    if (best_fam == 0 && zlo == zhi) {
-        run.L = D;
-        run.T = D / cm;
-    }
     c.ok = true;
-    c.L = run.L;
-    c.T = run.T;
+    c.L = best.L;
+    c.T = best.T;
+    const double cr = lay_speed(a, best_zr), xi = (1.0 - best_u) / cr;
     const double ux = D > 0.0 ? v.x / D : 0.0, uy = D > 0.0 ? v.y / D : 0.0;
-    const double cp = r.xi * lay_speed(a, P.z), cs = r.xi * lay_speed(a, S.z);
-    const double sp = lay_sin(a, r, P.z), ss = lay_sin(a, r, S.z);
-    const double up = S.z > P.z ? 1.0 : (S.z < P.z ? -1.0 : 0.0);
-    const double vp = best_fam == 0 ? up : (best_fam == 1 ? 1.0 : -1.0);
-    const double vs = best_fam == 0 ? up : (best_fam == 1 ? -1.0 : 1.0);
-    const d3 w = mk3(cp * ux, cp * uy, vp * sp), ar = mk3(cs * ux, cs * uy, vs * ss);
+    const double cP = lay_speed(a, P.z), cS = lay_speed(a, S.z);
+    const bool p_low = P.z <= S.z;
+    const double sp = lay_sine(p_low ? best.e_lo : best.e_hi, best_u, cP, 1.0 / cr);
+    const double ss = lay_sine(p_low ? best.e_hi : best.e_lo, best_u, cS, 1.0 / cr);
+    const double upd = S.z > P.z ? 1.0 : (S.z < P.z ? -1.0 : 0.0);
+    const double vp = best_fam == 0 ? upd : (best_fam == 1 ? 1.0 : -1.0);
+    const double vs = best_fam == 0 ? upd : (best_fam == 1 ? -1.0 : 1.0);
+    const d3 w = mk3(xi * cP * ux, xi * cP * uy, vp * sp), ar = mk3(xi * cS * ux, xi * cS * uy, vs * ss);
     c.w = w * (1.0 / norm3(w));
     c.arrive = ar * (1.0 / norm3(ar));
     return c;
