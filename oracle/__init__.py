@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Beam options (sensor flags, see oracle.c)
-BEAM_PATTERN, RX_BEAMS, DIFFUSE_BOUNCE = 1, 2, 4
+BEAM_PATTERN, RX_BEAMS, DIFFUSE_BOUNCE, RETRO_CHAIN = 1, 2, 4, 8
 
 # Ambiguity flag bits (see oracle.c)
 F_GRAZE, F_EDGE, F_TIE, F_LIMIT, F_SELF, F_BIN, F_FOV, F_OCCLUDER, F_STOP, F_DEPART, F_CAUSTIC = \
@@ -104,11 +104,11 @@ def lib():
         L.orc_eigenray.argtypes = [P(Params), P(Tol), C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
         L.orc_trace_beams.restype = C.c_int
         L.orc_trace_beams.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Tol), C.c_void_p, C.c_int64] + \
-            [C.c_void_p] * 10 + [C.c_int]
+            [C.c_void_p] * 12 + [C.c_int]
         L.orc_draw_continuation.argtypes = [P(Params), C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
                                             C.c_double, C.c_void_p]
         L.orc_trace_one.restype = C.c_int
-        L.orc_trace_one.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Tol), C.c_void_p, C.c_void_p] + [C.c_void_p] * 5
+        L.orc_trace_one.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Tol), C.c_void_p, C.c_void_p] + [C.c_void_p] * 7
         L.orc_detect.restype = C.c_int
         L.orc_detect.argtypes = [C.c_void_p, P(Params), P(PoseS), P(Cfar), C.c_void_p, C.c_int64] + \
             [C.c_void_p] * 5 + [C.c_double, C.c_double]
@@ -138,7 +138,7 @@ def _params(cfg, ping: int = 0) -> Params:
                   r_min=cfg.r_min, r_max=cfg.r_max, f0=cfg.freq_hz, c0=cfg.c0, g=cfg.c_grad,
                   alpha_db=cfg.abs_db_per_m, max_bounces=cfg.max_bounces, pad0=0,
                   k_d=cfg.k_d, k_s=cfg.k_s, phong_n=cfg.phong_n, seed=cfg.seed, ping=ping,
-                  flags=int(cfg.flags) & (BEAM_PATTERN | RX_BEAMS | DIFFUSE_BOUNCE))
+                  flags=int(cfg.flags) & (BEAM_PATTERN | RX_BEAMS | DIFFUSE_BOUNCE | RETRO_CHAIN))
 
 
 def pose_of(pose) -> PoseS:
@@ -236,14 +236,17 @@ def trace_beams(scene: Scene, cfg, pose, beams, tol=None, threads: int = 0, want
     amp = np.zeros((nb * NR, K, 2))
     flags = np.zeros(nb * NR, np.uint32)
     rxb = np.zeros((nb * NR, K), np.int32)
+    rbin = np.zeros((nb * NR, K), np.int32)
+    ramp = np.zeros((nb * NR, K, 2))
     tol = tol if tol is not None else default_tol()
     rc = lib().orc_trace_beams(scene.h, C.byref(P), C.byref(pose_of(pose)), C.byref(tol), _ptr(beams), nb,
                                _ptr(col), _ptr(col_all), _ptr(incoh), _ptr(gbuf), _ptr(tri), _ptr(bin_),
-                               _ptr(vis), _ptr(amp), _ptr(flags), _ptr(rxb), int(threads))
+                               _ptr(vis), _ptr(amp), _ptr(flags), _ptr(rxb), _ptr(rbin), _ptr(ramp), int(threads))
     if rc != 0:
         raise ValueError(f"oracle rejected the parameters ({rc})")
     out = dict(col=col[..., 0] + 1j * col[..., 1], tri=tri, bin=bin_, vis=vis,
-               amp=amp[..., 0] + 1j * amp[..., 1], flags=flags, rxb=rxb)
+               amp=amp[..., 0] + 1j * amp[..., 1], flags=flags, rxb=rxb,
+               rbin=rbin, ramp=ramp[..., 0] + 1j * ramp[..., 1])
     if want_all:
         out["col_all"] = col_all[..., 0] + 1j * col_all[..., 1]
     if want_incoh:
@@ -268,11 +271,14 @@ def trace_one(scene: Scene, cfg, pose, o, d, tol=None):
     vis = np.zeros(K, np.int32)
     amp = np.zeros((K, 2))
     fl = np.zeros(1, np.uint32)
+    rbin = np.zeros(K, np.int32)
+    ramp = np.zeros((K, 2))
     tol = tol if tol is not None else default_tol()
     lib().orc_trace_one(scene.h, C.byref(params_of(cfg, pose.ping)), C.byref(pose_of(pose)), C.byref(tol),
                         _ptr(np.asarray(o, np.float64)), _ptr(np.asarray(d, np.float64)),
-                        _ptr(tri), _ptr(bin_), _ptr(vis), _ptr(amp), _ptr(fl))
-    return dict(tri=tri, bin=bin_, vis=vis, amp=amp[:, 0] + 1j * amp[:, 1], flags=int(fl[0]))
+                        _ptr(tri), _ptr(bin_), _ptr(vis), _ptr(amp), _ptr(fl), _ptr(rbin), _ptr(ramp))
+    return dict(tri=tri, bin=bin_, vis=vis, amp=amp[:, 0] + 1j * amp[:, 1], flags=int(fl[0]),
+                rbin=rbin, ramp=ramp[:, 0] + 1j * ramp[:, 1])
 
 
 def detect(volume, cfg, pose, beams, train=16, guard=4, max_per_beam=4, pfa=1e-4, noise_floor=1e-11,

@@ -66,6 +66,16 @@
  * weight takes sqrt(rho (k_d + k_s)) (each lobe normalised and drawn with
  * its own probability). Pressure-release facets stay exact mirrors. */
 #define ORC_DIFFUSE_BOUNCE 4u
+/* ORC_RETRO_CHAIN: every vertex after the first also returns along its own
+ * outgoing chain reversed (reciprocity: the reversed chain is the same path,
+ * so it is as visible as the way out). The vertex scatters back into the
+ * reversed incoming direction (departure cosine = incidence cosine, Phong
+ * lobe taken toward -incident), the chain's weights apply twice (each
+ * earlier vertex is met again on the way back), the path is the outgoing
+ * one twice (time 2 T_out, spreading 1 / L_out^2, absorption over 2 L_out)
+ * and the echo arrives along the launch ray (launch beam, transmit pattern
+ * twice). */
+#define ORC_RETRO_CHAIN 8u
 
 /* ------------------------------------------------------------------------ */
 /* small vector algebra                                                      */
@@ -1000,6 +1010,8 @@ void orc_eigenray(const orc_params *P, const orc_tol *T, const double p[3], cons
 typedef struct {
     int32_t tri[ORC_MAXK], bin[ORC_MAXK], vis[ORC_MAXK], rxb[ORC_MAXK];
     double re[ORC_MAXK], im[ORC_MAXK], inc[ORC_MAXK];
+    int32_t rbin[ORC_MAXK];                        /* retro-chain return of each vertex */
+    double rre[ORC_MAXK], rim[ORC_MAXK], rinc[ORC_MAXK];
     uint32_t flags;
     int g_valid;
     double g_r, g_cos, g_rho;
@@ -1069,7 +1081,7 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
                       v3 o, v3 d, int32_t beam, double d_az, double d_el, uint64_t ray_id, oray *out)
 {
     memset(out, 0, sizeof(*out));
-    for (int k = 0; k < ORC_MAXK; ++k) { out->tri[k] = -1; out->bin[k] = -1; out->rxb[k] = beam; }
+    for (int k = 0; k < ORC_MAXK; ++k) { out->tri[k] = -1; out->bin[k] = -1; out->rxb[k] = beam; out->rbin[k] = -1; }
     const double dh = P->hfov / P->n_h, dv = P->vfov / P->n_v;
     const int pattern = beam >= 0 && (P->flags & ORC_BEAM_PATTERN);
     const int rx_bin = beam >= 0 && (P->flags & ORC_RX_BEAMS);
@@ -1258,6 +1270,29 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
                 }
             }
         }
+        /* retro-chain return: back into the reversed incident direction and
+         * along the outgoing chain reversed */
+        if (k > 0 && (P->flags & ORC_RETRO_CHAIN)) {
+            double lobe = -dot(rh, din);
+            if (lobe < 0.0) lobe = 0.0;
+            const double fsc = rho * (kd * cos_i * cos_i + ks * pow(lobe, P->phong_n));
+            const double Tt = 2.0 * T_out;
+            const double reff = c_ref * Tt / 2.0;
+            const double x = (reff - P->r_min) / dr, fb = floor(x), fr = x - fb;
+            if (x > -1.0 && x < P->n_bins + 1.0 && (fr < T->bin_frac || fr > 1.0 - T->bin_frac))
+                out->flags |= F_BIN;
+            if (fb >= 0.0 && fb < P->n_bins) {
+                double amp = W * W * sgn * sqrt(fsc) * pow(10.0, -P->alpha_db * 2.0 * L_out / 20.0) /
+                             (L_out * L_out * P->n_r);
+                if (pattern) amp *= w_tx * w_tx;
+                const double cyc = P->f0 * Tt;
+                const double ph = 2.0 * ORC_PI * (cyc - floor(cyc)) + phi;
+                out->rbin[k] = (int)fb;
+                out->rre[k] = amp * cos(ph);
+                out->rim[k] = amp * sin(ph);
+                out->rinc[k] = amp * amp;
+            }
+        }
         /* continuation along the mirror direction, or drawn from the lobes */
         if (k + 1 >= K) break;
         if ((P->flags & ORC_DIFFUSE_BOUNCE) && !pr) {
@@ -1298,6 +1333,8 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
                     double *rec_amp,    /* [n_beams*n_r][K][2] */
                     uint32_t *ray_flags,/* [n_beams*n_r] */
                     int32_t *rec_rxb,   /* [n_beams*n_r][K] receive beam of each contribution, or NULL */
+                    int32_t *rec_rbin,  /* [n_beams*n_r][K] retro-chain bin of each vertex, or NULL */
+                    double *rec_ramp,   /* [n_beams*n_r][K][2] retro-chain contribution, or NULL */
                     int n_threads)
 {
     const oscene *S = (const oscene *)hs;
@@ -1314,6 +1351,7 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
         }
     }
     const int rx = (P->flags & ORC_RX_BEAMS) != 0;
+    if ((P->flags & ORC_RETRO_CHAIN) && rx && (!rec_rbin || !rec_ramp)) return -4;
     if (rx) {
         /* contributions move between beams: every beam, in order */
         if (n_beams != (int64_t)P->n_h * P->n_v) return -2;
@@ -1360,12 +1398,24 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
                 rec_amp[(ri * K + k) * 2 + 1] = r.im[k];
                 if (rec_rxb) rec_rxb[ri * K + k] = r.rxb[k] >= 0 ? r.rxb[k] : b;
                 if (rx) r.inc[k] = r.re[k] * r.re[k] + r.im[k] * r.im[k];
-                if (r.bin[k] < 0 || rx) continue;
-                if (ca) { ca[2 * r.bin[k]] += r.re[k]; ca[2 * r.bin[k] + 1] += r.im[k]; }
-                if (r.flags == 0) {
-                    cc[2 * r.bin[k]] += r.re[k];
-                    cc[2 * r.bin[k] + 1] += r.im[k];
-                    if (ic) ic[(k == 0 ? 0 : NB) + r.bin[k]] += r.inc[k];
+                if (rec_rbin) rec_rbin[ri * K + k] = r.rbin[k];
+                if (rec_ramp) { rec_ramp[(ri * K + k) * 2] = r.rre[k]; rec_ramp[(ri * K + k) * 2 + 1] = r.rim[k]; }
+                if (rx) continue;
+                if (r.bin[k] >= 0) {
+                    if (ca) { ca[2 * r.bin[k]] += r.re[k]; ca[2 * r.bin[k] + 1] += r.im[k]; }
+                    if (r.flags == 0) {
+                        cc[2 * r.bin[k]] += r.re[k];
+                        cc[2 * r.bin[k] + 1] += r.im[k];
+                        if (ic) ic[(k == 0 ? 0 : NB) + r.bin[k]] += r.inc[k];
+                    }
+                }
+                if (r.rbin[k] >= 0) {
+                    if (ca) { ca[2 * r.rbin[k]] += r.rre[k]; ca[2 * r.rbin[k] + 1] += r.rim[k]; }
+                    if (r.flags == 0) {
+                        cc[2 * r.rbin[k]] += r.rre[k];
+                        cc[2 * r.rbin[k] + 1] += r.rim[k];
+                        if (ic) ic[NB + r.rbin[k]] += r.rinc[k];
+                    }
                 }
             }
             if (r.flags == 0 && r.g_valid) {
@@ -1406,6 +1456,20 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
                     if (incoh) incoh[(size_t)tb * 2 * NB + (k == 0 ? 0 : NB) + bin] += re * re + im * im;
                 }
             }
+            /* retro-chain returns arrive along the launch ray: the launch beam */
+            for (int k = 0; rec_rbin && k < K; ++k) {
+                const size_t e = ri * K + k;
+                const int bin = rec_rbin[e];
+                if (bin < 0) continue;
+                const size_t tb = ri / NR;
+                const double re = rec_ramp[2 * e], im = rec_ramp[2 * e + 1];
+                if (col_all) { col_all[(tb * NB + bin) * 2] += re; col_all[(tb * NB + bin) * 2 + 1] += im; }
+                if (ray_flags[ri] == 0) {
+                    col[(tb * NB + bin) * 2] += re;
+                    col[(tb * NB + bin) * 2 + 1] += im;
+                    if (incoh) incoh[tb * 2 * NB + NB + bin] += re * re + im * im;
+                }
+            }
         }
     }
     return 0;
@@ -1425,7 +1489,8 @@ void orc_draw_continuation(const orc_params *P, uint64_t ray, int32_t k, const d
 /* A single ray from an arbitrary origin and direction (closed-form checks). */
 int orc_trace_one(void *hs, const orc_params *P, const orc_pose *Q, const orc_tol *T,
                   const double o[3], const double d[3],
-                  int32_t *tri, int32_t *bin, int32_t *vis, double *amp, uint32_t *flags)
+                  int32_t *tri, int32_t *bin, int32_t *vis, double *amp, uint32_t *flags,
+                  int32_t *rbin, double *ramp)      /* retro-chain returns, or NULL */
 {
     const oscene *S = (const oscene *)hs;
     if (P->max_bounces < 1 || P->max_bounces > ORC_MAXK) return -1;
@@ -1434,6 +1499,8 @@ int orc_trace_one(void *hs, const orc_params *P, const orc_pose *Q, const orc_to
     for (int k = 0; k < P->max_bounces; ++k) {
         tri[k] = r.tri[k]; bin[k] = r.bin[k]; vis[k] = r.vis[k];
         amp[2 * k] = r.re[k]; amp[2 * k + 1] = r.im[k];
+        if (rbin) rbin[k] = r.rbin[k];
+        if (ramp) { ramp[2 * k] = r.rre[k]; ramp[2 * k + 1] = r.rim[k]; }
     }
     *flags = r.flags;
     return 0;
