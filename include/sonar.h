@@ -138,10 +138,23 @@ typedef struct {
  *                     k (u1 = z >> 40, u2 = (z >> 16) mod 2^24 over 2^24,
  *                     u3 = z mod 2^16 over 2^16 chooses the lobe); the path
  *                     weight takes sqrt(rho (k_d + k_s)); a direction into the
- *                     facet ends the ray. Pressure-release facets stay mirrors. */
+ *                     facet ends the ray. Pressure-release facets stay mirrors.
+ *     SONAR_FLAG_RETRO_CHAIN  retro-chain returns (Sec. II-B: secondary
+ *                     reflections): every vertex after the first also
+ *                     scatters back into its reversed incident direction and
+ *                     the echo retraces the outgoing chain (the same path, so
+ *                     no visibility test): time 2 T_out, spreading
+ *                     1 / L_out^2, absorption over 2 L_out, the chain's path
+ *                     weight squared, departure cosine = incidence cosine and
+ *                     the Phong lobe toward the reversed incident direction;
+ *                     it arrives along the launch ray (launch beam, transmit
+ *                     pattern squared) and counts as a later bounce in the
+ *                     incoherent channel. No effect with max_bounces 1;
+ *                     batches reject it. */
 #define SONAR_FLAG_BEAM_PATTERN 1u
 #define SONAR_FLAG_RX_BEAMS 2u
 #define SONAR_FLAG_DIFFUSE_BOUNCE 4u
+#define SONAR_FLAG_RETRO_CHAIN 8u
 typedef struct {
     double hfov, vfov;
     int32_t n_h, n_v, rays_per_beam, grid_mode, jitter, n_range;
@@ -172,7 +185,10 @@ typedef void *sonar_stream;
  * stack. Counting uses separate kernel instantiations: indices and bins are
  * the same as without it, values the same up to rounding. `beam` (optional,
  * [n_rays][max_bounces]) receives the beam each contribution is added to
- * (the launch beam unless SONAR_FLAG_RX_BEAMS moves it). */
+ * (the launch beam unless SONAR_FLAG_RX_BEAMS moves it). `retro_bin` and
+ * `retro_amp` (optional, [n_rays][max_bounces]) receive each vertex's
+ * retro-chain return under SONAR_FLAG_RETRO_CHAIN (bin -1: none; vertex 0
+ * never has one). */
 typedef struct {
     int32_t *tri;
     int32_t *bin;
@@ -180,6 +196,8 @@ typedef struct {
     sonar_cf32 *amp;
     uint32_t *stats;
     int32_t *beam;
+    int32_t *retro_bin;
+    sonar_cf32 *retro_amp;
 } sonar_ray_record;
 
 typedef struct {

@@ -85,7 +85,7 @@ sonar_status check_params(const sonar_params *p)
         return fail(SONAR_E_INVALID, "k_d, k_s and phong_n must be finite and >= 0");
     int64_t beams = (int64_t)(p->n_h + (p->grid_mode == 1)) * (p->n_v + (p->grid_mode == 1));
     if (beams * p->rays_per_beam > ((int64_t)1 << 31) - 1) return fail(SONAR_E_INVALID, "too many rays");
-    if (p->flags & ~(SONAR_FLAG_BEAM_PATTERN | SONAR_FLAG_RX_BEAMS | SONAR_FLAG_DIFFUSE_BOUNCE))
+    if (p->flags & ~(SONAR_FLAG_BEAM_PATTERN | SONAR_FLAG_RX_BEAMS | SONAR_FLAG_DIFFUSE_BOUNCE | SONAR_FLAG_RETRO_CHAIN))
         return fail(SONAR_E_INVALID, "unknown flags");
     if ((p->flags & (SONAR_FLAG_BEAM_PATTERN | SONAR_FLAG_RX_BEAMS)) && p->grid_mode != 0)
         return fail(SONAR_E_UNSUPPORTED, "beam pattern and receive binning need cell-centred beams (grid_mode 0)");
@@ -157,6 +157,14 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
     if (!volume) return fail(SONAR_E_INVALID, "volume is NULL");
     if (rec && (!rec->tri || !rec->bin || !rec->vis || !rec->amp))
         return fail(SONAR_E_INVALID, "record arrays tri, bin, vis and amp must all be set");
+    if (rec && (!rec->retro_bin) != (!rec->retro_amp))
+        return fail(SONAR_E_INVALID, "record arrays retro_bin and retro_amp go together");
+    if ((p->flags & SONAR_FLAG_RETRO_CHAIN) && p->max_bounces > 1) {
+        if (rec && rec->stats)
+            return fail(SONAR_E_UNSUPPORTED, "traversal counters are not kept with retro-chain returns");
+        if (p->max_bounces == 4 && p->n_range > 3584)
+            return fail(SONAR_E_UNSUPPORTED, "retro-chain returns with four bounces take at most 3584 bins");
+    }
     // a sound speed must stay positive over the scene and the sensor
     if (p->c_grad != 0.0) {
         double zmax = fmax((double)sc->s.zabs_max, fabs(q->position[2])) + 1.0;
@@ -218,6 +226,8 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
         a.rec_amp = reinterpret_cast<float2 *>(rec->amp);
         a.stats = rec->stats;
         a.rec_beam = rec->beam;
+        a.rec_rbin = rec->retro_bin;
+        a.rec_ramp = reinterpret_cast<float2 *>(rec->retro_amp);
     }
     a.mask = ray_mask;
     // a traversal of a valid hierarchy visits every node and every leaf at most once
@@ -732,6 +742,8 @@ sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_p
     for (int32_t i = 0; i < n; ++i) {
         if (needs_rx_list(&params[i]))
             return fail(SONAR_E_UNSUPPORTED, "ping %d: batches do not take receive binning with several bounces", i);
+        if ((params[i].flags & SONAR_FLAG_RETRO_CHAIN) && params[i].max_bounces > 1)
+            return fail(SONAR_E_UNSUPPORTED, "ping %d: batches do not take retro-chain returns", i);
         sonar_status st = fill_ping_args(sc, &params[i], &poses[i], volumes[i], nullptr, nullptr, nullptr, nullptr,
                                          &d[i]);
         if (st != SONAR_OK) {

@@ -66,6 +66,7 @@ constexpr uint32_t FLAG_BEAM_PATTERN = 1u;
 constexpr int MAX_SSP_KNOTS = 8;
 constexpr uint32_t FLAG_RX_BEAMS = 2u;
 constexpr uint32_t FLAG_DIFFUSE_BOUNCE = 4u;
+constexpr uint32_t FLAG_RETRO_CHAIN = 8u;
 
 struct PingArgs {
     const float4 *nodes;
@@ -89,8 +90,8 @@ struct PingArgs {
     float2 *volume;
     float *gbuf;
     float *incoh;
-    int32_t *rec_tri, *rec_bin, *rec_vis, *rec_beam;
-    float2 *rec_amp;
+    int32_t *rec_tri, *rec_bin, *rec_vis, *rec_beam, *rec_rbin;
+    float2 *rec_amp, *rec_ramp;
     uint32_t *stats;         // optional [n_rays][3]: internal nodes visited, triangles tested, deepest stack
     const uint32_t *mask;
     uint32_t max_steps;      // node-visit bound of one traversal (2 * nodes + 64)

@@ -40,6 +40,9 @@ constexpr int K1_IDX_BASE = K1_BIN_WORDS + K1_VAL_WORDS;      // uint16 column i
 // a SIMD.
 constexpr int K1_LDS_STACK = 20;
 constexpr int KN_LDS_STACK = 32;
+// four bounces with retro-chain slots: a shorter LDS stack keeps a block
+// within 64 KB (the column index then holds up to 28 * 64 * 2 bins)
+constexpr int KN_LDS_STACK_R4 = 28;
 
 struct d3 {
     double x, y, z;
@@ -1033,7 +1036,7 @@ __device__ __forceinline__ void rx_append(const PingArgs &a, const bool want, co
 // The ping body for one tile of 256 consecutive rays (4 wavefronts). `a` is
 // the ping's argument block (kernel arguments, or a batch descriptor in
 // device memory); `W` is this wavefront's LDS area.
-template <int DEPTH, int K, bool ARC, bool STATS, bool LAYERED = false>
+template <int DEPTH, int K, bool ARC, bool STATS, bool LAYERED = false, bool RETRO = false>
 __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uint32_t *__restrict__ W)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -1044,16 +1047,18 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
     const bool active = beam < a.n_beams;
 
     // Contribution slots: registers for a single bounce; for several bounces
-    // an LDS area past the traversal stack, slot (k, lane) at k * 64 + lane.
-    constexpr int DLS = K == 1 ? K1_LDS_STACK : KN_LDS_STACK;
+    // an LDS area past the traversal stack, slot (k, lane) at k * 64 + lane,
+    // with the retro-chain returns of vertices 1..K-1 in slots K..2K-2.
+    constexpr int KS = RETRO ? 2 * K - 1 : K;
+    constexpr int DLS = K == 1 ? K1_LDS_STACK : ((RETRO && K == 4) ? KN_LDS_STACK_R4 : KN_LDS_STACK);
     constexpr int DL = DEPTH > DLS ? DLS : DEPTH;
     int *sbin = (K == 1) ? reinterpret_cast<int *>(W) : reinterpret_cast<int *>(W + DL * WAVE);
     float4 *sval = (K == 1) ? reinterpret_cast<float4 *>(W + K1_BIN_WORDS)
-                            : reinterpret_cast<float4 *>(W + DL * WAVE + K * WAVE);
+                            : reinterpret_cast<float4 *>(W + DL * WAVE + KS * WAVE);
     Slot slot0 = Slot{-1, 0.f, 0.f, 0.f};
     if (K > 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < KS; ++k) {
             sbin[k * WAVE + lane] = -1;
             sval[k * WAVE + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
@@ -1107,6 +1112,8 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
             float cre = 0.f, cim = 0.f, cinc = 0.f;
             float w_rx = w_tx;       // receive pattern: bounce 1 arrives along the launch ray
             int rxb = (int)beam;     // the beam the return is added to
+            int rbin = -1;           // retro-chain return of this vertex
+            float rre = 0.f, rim = 0.f, rinc = 0.f;
             if (!stop) {
                 // segment limit: arc length for constant c, travel time in a gradient
                 double s_lim, T_lim = 0.0;
@@ -1264,6 +1271,32 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                                     }
                                 }
                             }
+                            if constexpr (RETRO) {
+                                // back into the reversed incident direction and along the
+                                // outgoing chain reversed: twice its time and length, its
+                                // weight squared
+                                if (k > 0) {
+                                    float lobe = (float)(-dot3(rh, din));
+                                    lobe = lobe > 0.f ? lobe : 0.f;
+                                    const double spec = ks != 0.0 ? ks * (double)powf(lobe, (float)a.phong_n) : 0.0;
+                                    const double fsc = rho * (kd * cos_i * cos_i + spec);
+                                    const double fb = floor((a.c_ref * T_out - a.r_min) / a.dr);
+                                    if (fb >= 0.0 && fb < (double)a.n_bins) {
+                                        const double att =
+                                            (double)expf((float)(-a.alpha_db * 2.0 * L_out * LN10_OVER_20));
+                                        const double amp = Wt * Wt * sgn * sqrt(fsc) * att / (L_out * L_out * a.n_r);
+                                        const double cyc = a.f0 * 2.0 * T_out;
+                                        double ph = TWO_PI * (cyc - floor(cyc)) + phi;
+                                        ph -= TWO_PI * rint(ph / TWO_PI);
+                                        float sn, cs;
+                                        sincosf((float)ph, &sn, &cs);
+                                        rbin = (int)fb;
+                                        rre = (float)amp * cs;
+                                        rim = (float)amp * sn;
+                                        rinc = (float)(amp * amp);
+                                    }
+                                }
+                            }
                             // continuation along the mirror direction, or drawn from the lobes
                             if (k + 1 < K) {
                                 d3 dc = rh;
@@ -1317,6 +1350,12 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                 cre *= wgt;
                 cim *= wgt;
                 cinc *= wgt * wgt;
+                if constexpr (RETRO) {
+                    const float wr = w_tx * w_tx;      // out and back along the launch ray
+                    rre *= wr;
+                    rim *= wr;
+                    rinc *= wr * wr;
+                }
             }
             int cbin_here = cbin;    // the bin this lane's launch beam receives
             if (K > 1 && k > 0 && (a.flags & FLAG_RX_BEAMS)) {
@@ -1331,12 +1370,24 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                 a.rec_vis[ri] = rec_vis;
                 a.rec_amp[ri] = make_float2(cre, cim);
                 if (a.rec_beam) a.rec_beam[ri] = rxb;
+                if constexpr (RETRO) {
+                    if (a.rec_rbin) {
+                        a.rec_rbin[ri] = rbin;
+                        a.rec_ramp[ri] = make_float2(rre, rim);
+                    }
+                }
             }
             if (K == 1) {
                 slot0 = Slot{cbin_here, cre, cim, cinc};
             } else {
                 sbin[k * WAVE + lane] = cbin_here;
                 sval[k * WAVE + lane] = k == 0 ? make_float4(cre, cim, cinc, 0.f) : make_float4(cre, cim, 0.f, cinc);
+                if constexpr (RETRO) {
+                    if (k > 0) {
+                        sbin[(K + k - 1) * WAVE + lane] = rbin;
+                        sval[(K + k - 1) * WAVE + lane] = make_float4(rre, rim, 0.f, rinc);
+                    }
+                }
             }
         }
         if (STATS) {
@@ -1348,7 +1399,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
             slot0.bin = -1;
             if (K > 1) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) sbin[k * WAVE + lane] = -1;
+                for (int k = 0; k < KS; ++k) sbin[k * WAVE + lane] = -1;
             }
             for (int q = 0; q < 7; ++q) gfeat[q] = 0.f;
         }
@@ -1378,28 +1429,28 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         sval[lane] = make_float4(slot0.re, slot0.im, slot0.inc, 0.f);
     }
     wave_sync();
-    int my_bin[MAX_BOUNCES];
+    int my_bin[2 * MAX_BOUNCES - 1];
 #pragma unroll
-    for (int k = 0; k < K; ++k) my_bin[k] = sbin[k * WAVE + lane];
+    for (int k = 0; k < KS; ++k) my_bin[k] = sbin[k * WAVE + lane];
     const int nr = a.n_r;
     const int bl = lane >> a.log2_nr;          // beam within the wave
     const int base_lane = bl << a.log2_nr;
-    bool head[MAX_BOUNCES];
-    float4 sum[MAX_BOUNCES];
+    bool head[2 * MAX_BOUNCES - 1];
+    float4 sum[2 * MAX_BOUNCES - 1];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < KS; ++k) {
         head[k] = false;
         sum[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         int mb = my_bin[k];
         if (mb < 0) continue;
-        int me = j * K + k;
+        int me = j * KS + k;
         bool hd = true;
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
         for (int jj = 0; jj < nr; ++jj) {
-            for (int kk = 0; kk < K; ++kk) {
+            for (int kk = 0; kk < KS; ++kk) {
                 int s2 = kk * WAVE + base_lane + jj;
                 if (sbin[s2] != mb) continue;
-                int o2 = jj * K + kk;
+                int o2 = jj * KS + kk;
                 if (o2 < me) {
                     hd = false;
                 } else {
@@ -1417,7 +1468,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
     wave_sync();
     // from here on a slot that still holds a bin is a head carrying its bin's sum
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < KS; ++k) {
         if (head[k]) sval[k * WAVE + lane] = sum[k];
         else sbin[k * WAVE + lane] = -1;
     }
@@ -1433,9 +1484,9 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         // > 1, so only bins holding a return can be detected; a training sum
         // is N * N0 plus the excess of the returns inside the window.
         const float n0 = a.det_n0;
-        uint64_t key[K];
+        uint64_t key[KS];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < KS; ++k) {
             key[k] = 0ull;
             if (!head[k]) continue;
             const int bin = my_bin[k];
@@ -1447,7 +1498,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
             float pl = n0, pr = n0;
             double wsum = (double)N * (double)n0;
             for (int jj = 0; jj < nr; ++jj) {
-                for (int kk = 0; kk < K; ++kk) {
+                for (int kk = 0; kk < KS; ++kk) {
                     const int s2 = kk * WAVE + base_lane + jj;
                     const int b2 = sbin[s2];
                     if (b2 < 0) continue;
@@ -1474,7 +1525,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
             uint64_t my = 0ull;
             int myk = -1;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
+            for (int k = 0; k < KS; ++k)
                 if (!((taken >> k) & 1u) && key[k] > my) { my = key[k]; myk = k; }
             uint64_t best = my;
             for (int off = 1; off < nr; off <<= 1) {
@@ -1501,7 +1552,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         wave_sync();
         if (bl == q) {
 #pragma unroll
-            for (int k = 0; k < K; ++k)
+            for (int k = 0; k < KS; ++k)
                 if (head[k]) sidx[my_bin[k]] = (uint16_t)(k * WAVE + lane + 1);
         }
         wave_sync();
@@ -1542,13 +1593,13 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
 template <int K, bool ARC>
 constexpr int ping_waves_per_eu() { return K == 1 ? (ARC ? 5 : 8) : 3; }
 
-template <int DEPTH, int K, bool ARC, bool STATS, bool LAYERED = false>
+template <int DEPTH, int K, bool ARC, bool STATS, bool LAYERED = false, bool RETRO = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(ping_waves_per_eu<K, ARC>())))
 void k_ping(PingArgs a, int wave_words)
 {
     extern __shared__ uint32_t lds[];
     uint32_t *W = lds + (size_t)(threadIdx.x / WAVE) * wave_words;
-    ping_tile<DEPTH, K, ARC, STATS, LAYERED>(a, xcd_remap(blockIdx.x, gridDim.x), W);
+    ping_tile<DEPTH, K, ARC, STATS, LAYERED, RETRO>(a, xcd_remap(blockIdx.x, gridDim.x), W);
 }
 
 // Persistent batch: every block pops (ping, tile) items from one device
@@ -1650,21 +1701,41 @@ hipError_t launch_rx_scatter(const PingArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-int ping_wave_words(int depth, int n_bins, int K)
+int ping_wave_words(int depth, int n_bins, int K, bool retro = false)
 {
-    if (K > 1)   // LDS stack + slots; the column index reuses the stack
-        return (depth > KN_LDS_STACK ? KN_LDS_STACK : depth) * WAVE + 5 * WAVE * K;
+    if (K > 1) {   // LDS stack + slots; the column index reuses the stack
+        const int dls = (retro && K == 4) ? KN_LDS_STACK_R4 : KN_LDS_STACK;
+        return (depth > dls ? dls : depth) * WAVE + 5 * WAVE * (retro ? 2 * K - 1 : K);
+    }
     const int stk = (depth > K1_LDS_STACK ? K1_LDS_STACK : depth) * WAVE;
     const int acc = K1_IDX_BASE + (n_bins + 1) / 2;
     const int w = acc > stk ? acc : stk;
     return (w + 3) & ~3;                              // keeps every wave's float4 slots 16-byte aligned
 }
 
+// Retro-chain returns take their own instantiations (deep stack, no
+// counters), with 2K - 1 contribution slots per lane.
+static bool retro_of(const PingArgs &a) { return (a.flags & FLAG_RETRO_CHAIN) && a.K > 1; }
+
 hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s)
 {
     int64_t threads = (int64_t)a.n_beams * a.n_r;
     int nblocks = (int)((threads + BLOCK - 1) / BLOCK);
     if (nblocks == 0) return hipSuccess;
+    if (retro_of(a)) {
+        const int ww = ping_wave_words(64, a.n_bins, a.K, true);
+        const size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
+#define SONAR_LAUNCH_R(KK, AR) \
+    hipLaunchKernelGGL((k_ping<64, KK, AR, false, false, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww)
+        const bool arc = a.g != 0.0;
+        switch (a.K) {
+            case 2: if (arc) SONAR_LAUNCH_R(2, true); else SONAR_LAUNCH_R(2, false); break;
+            case 3: if (arc) SONAR_LAUNCH_R(3, true); else SONAR_LAUNCH_R(3, false); break;
+            default: if (arc) SONAR_LAUNCH_R(4, true); else SONAR_LAUNCH_R(4, false); break;
+        }
+#undef SONAR_LAUNCH_R
+        return hipGetLastError();
+    }
     // the counting variants exist for the deep stack only (same results)
     int depth = stack_depth <= 32 && !a.stats ? 32 : 64;
     int ww = ping_wave_words(depth, a.n_bins, a.K);
@@ -1696,6 +1767,16 @@ hipError_t launch_ping_layered(const PingArgs &a, int stack_depth, hipStream_t s
     int64_t threads = (int64_t)a.n_beams * a.n_r;
     int nblocks = (int)((threads + BLOCK - 1) / BLOCK);
     if (nblocks == 0) return hipSuccess;
+    if (retro_of(a)) {
+        const int ww = ping_wave_words(64, a.n_bins, a.K, true);
+        const size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
+        switch (a.K) {
+            case 2: hipLaunchKernelGGL((k_ping<64, 2, true, false, true, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww); break;
+            case 3: hipLaunchKernelGGL((k_ping<64, 3, true, false, true, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww); break;
+            default: hipLaunchKernelGGL((k_ping<64, 4, true, false, true, true>), dim3(nblocks), dim3(BLOCK), shmem, s, a, ww); break;
+        }
+        return hipGetLastError();
+    }
     int depth = stack_depth <= 32 && !a.stats ? 32 : 64;
     int ww = ping_wave_words(depth, a.n_bins, a.K);
     size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;

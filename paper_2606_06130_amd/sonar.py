@@ -24,6 +24,7 @@ SONAR_E_UNSUPPORTED = -5
 FLAG_BEAM_PATTERN = 1
 FLAG_RX_BEAMS = 2
 FLAG_DIFFUSE_BOUNCE = 4
+FLAG_RETRO_CHAIN = 8
 
 # Every symbol include/sonar.h declares.
 EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "sonar_ping",
@@ -75,7 +76,8 @@ class sonar_cfar(C.Structure):
 
 class sonar_ray_record(C.Structure):
     _fields_ = [("tri", C.c_void_p), ("bin", C.c_void_p), ("vis", C.c_void_p), ("amp", C.c_void_p),
-                ("stats", C.c_void_p), ("beam", C.c_void_p)]
+                ("stats", C.c_void_p), ("beam", C.c_void_p), ("retro_bin", C.c_void_p),
+                ("retro_amp", C.c_void_p)]
 
 
 class sonar_scene_info(C.Structure):
@@ -320,9 +322,10 @@ def beams_of(cfg):
 
 
 def alloc_outputs(cfg, gbuffer=False, incoh=False, record=False, stats=False, device="cuda"):
-    """Output tensors of a ping. ``record`` adds the per-ray record; ``stats``
-    (with ``record``) adds the traversal counters, which select the counting
-    kernel instantiations."""
+    """Output tensors of a ping. ``record`` adds the per-ray record (with the
+    retro-chain returns ``rbin`` / ``ramp`` under FLAG_RETRO_CHAIN and several
+    bounces); ``stats`` (with ``record``) adds the traversal counters, which
+    select the counting kernel instantiations."""
     import torch
     bv, bh = beams_of(cfg)
     out = dict(volume=torch.empty((bv, bh, cfg.n_range), dtype=torch.complex64, device=device))
@@ -338,6 +341,9 @@ def alloc_outputs(cfg, gbuffer=False, incoh=False, record=False, stats=False, de
         out["vis"] = torch.empty((n, K), dtype=torch.int32, device=device)
         out["amp"] = torch.empty((n, K), dtype=torch.complex64, device=device)
         out["beam"] = torch.empty((n, K), dtype=torch.int32, device=device)
+        if (int(cfg.flags) & FLAG_RETRO_CHAIN) and K > 1:
+            out["rbin"] = torch.empty((n, K), dtype=torch.int32, device=device)
+            out["ramp"] = torch.empty((n, K), dtype=torch.complex64, device=device)
         if stats:
             out["stats"] = torch.empty((n, 3), dtype=torch.int32, device=device)
     return out
@@ -353,7 +359,9 @@ def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=F
         rec = sonar_ray_record(tri=out["tri"].data_ptr(), bin=out["bin"].data_ptr(), vis=out["vis"].data_ptr(),
                                amp=out["amp"].data_ptr(),
                                stats=out["stats"].data_ptr() if "stats" in out else None,
-                               beam=out["beam"].data_ptr() if "beam" in out else None)
+                               beam=out["beam"].data_ptr() if "beam" in out else None,
+                               retro_bin=out["rbin"].data_ptr() if "rbin" in out else None,
+                               retro_amp=out["ramp"].data_ptr() if "ramp" in out else None)
     p = params if params is not None else params_of(cfg)
     q = pose_s if pose_s is not None else pose_of(pose)
     if getattr(cfg, "ssp", ()):

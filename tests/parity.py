@@ -49,6 +49,11 @@ def compare_rays(gpu: dict, orc: dict, rays) -> dict:
         g = np.where(has, np.asarray(gpu["beam"])[rays][ok], -1)
         o = np.where(has, np.asarray(orc["rxb"])[ok], -1)
         res["beam_mismatch"] = int((g != o).any(axis=1).sum())
+    if "rbin" in gpu and "rbin" in orc:
+        # retro-chain returns: bins exact, values to the volume tolerance
+        res["rbin_mismatch"] = int((np.asarray(gpu["rbin"])[rays][ok] != np.asarray(orc["rbin"])[ok]).any(axis=1).sum())
+        res["retro_err"] = rel_l2(np.asarray(gpu["ramp"])[rays][ok], np.asarray(orc["ramp"])[ok])
+        res["retro_returns"] = int((np.asarray(orc["rbin"])[ok] >= 0).sum())
     res.update(flag_summary(orc["flags"]))
     return res
 

@@ -151,7 +151,9 @@ def test_rx_workspace_size(L):
     assert L.sonar_rx_workspace_size(C.byref(p)) == 256 + 16 * 16 * 8 * 4 * 2
     p = sonar.params_of(cfg.replace(flags=sonar.FLAG_RX_BEAMS, max_bounces=1))
     assert L.sonar_rx_workspace_size(C.byref(p)) == 256
-    p = sonar.params_of(cfg.replace(flags=8))
+    p = sonar.params_of(cfg.replace(flags=sonar.FLAG_RETRO_CHAIN))
+    assert L.sonar_rx_workspace_size(C.byref(p)) == 256                      # retro-chain returns need no list
+    p = sonar.params_of(cfg.replace(flags=16))
     assert L.sonar_rx_workspace_size(C.byref(p)) == 0                        # unknown flag
     p = sonar.params_of(cfg.replace(flags=sonar.FLAG_BEAM_PATTERN, grid_mode=1, rays_per_beam=1))
     assert L.sonar_rx_workspace_size(C.byref(p)) == 0                        # cell beams only

@@ -73,6 +73,8 @@ def assert_parity(res, bounces=1):
     assert res["bin_mismatch"] == 0, res
     assert res["vis_mismatch"] == 0, res
     assert res.get("beam_mismatch", 0) == 0, res
+    assert res.get("rbin_mismatch", 0) == 0, res
+    assert res.get("retro_err", 0.0) <= VOL_TOL, res
     assert res["vol_err"] <= VOL_TOL, res
     assert res["contrib_err"] <= VOL_TOL, res
     if "i1_err" in res:
