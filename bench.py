@@ -226,14 +226,15 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
         b.record(stream)
     torch.cuda.synchronize()
     sp_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    surrogate = {"workload": "single-bounce ping with G-buffer + network (168,768 parameters, BF16 MFMA) + "
+    surrogate = {"workload": "single-bounce ping with G-buffer + network (169,344 parameters, BF16 MFMA) + "
                              "predicted 1,024-bin multi-bounce profile, same scene and layout",
                  "ping_ms": sp_ms, "pings_per_s": 1e3 / sp_ms, "rate_vs_full_multipath": mp_ms / sp_ms}
     try:
         with open(os.path.join(ROOT, "profiles", "surrogate_harbor_multipath_training.json")) as f:
             tr = json.load(f)
         surrogate["held_out_error_db"] = {k: tr[k] for k in ("surrogate", "single_bounce", "mean_residual",
-                                                              "truncated_truth")}
+                                                              "truncated_truth", "surrogate_vs_truncated_truth")
+                                          if k in tr}
         surrogate["held_out_error_source"] = "profiles/surrogate_harbor_multipath_training.json (training run)"
     except (OSError, ValueError, KeyError):
         pass

@@ -232,7 +232,9 @@ sonar_status sonar_get_scene_info(const sonar_scene *scene, sonar_scene_info *in
  *   gbuffer  optional device float32 [beams_v][beams_h][8]: over the beam's
  *            first-bounce hits in range, mean range / r_max, mean cos
  *            incidence, mean rho, mean facet normal (xyz, facing the ray),
- *            hit count / rays_per_beam, 0
+ *            hit count / rays_per_beam, and the vertical (world z)
+ *            component of the beam axis (cell centre; the grid node in
+ *            grid_mode 1)
  *   incoh    optional device float32 [2][beams_v][beams_h][n_range]:
  *            sum |A|^2 of first-bounce (0) and later-bounce (1) returns
  *   record   optional per-ray record (testing)
@@ -484,22 +486,22 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
 /* ---------------------------------------------------------------------- */
 /* Learned multipath surrogate (Sec. II-B: scattering functions may be learned
  * from data). A network maps each beam's single-bounce G-buffer (a 3 x 3 beam
- * neighbourhood of its 7 features) to 64 standardised orthonormal DCT-II
+ * neighbourhood of its 8 features) to 64 standardised orthonormal DCT-II
  * coefficients of the residual profile that later bounces add:
  *   res[r] = 10 log10(I1s[r] + Ims[r] + 1e-11) - 10 log10(I1s[r] + 1e-11),
  * where I1s, Ims are the first-bounce and later-bounce incoherent channels of a
  * multi-bounce ping box-averaged over `smooth` range bins ([r - smooth/2,
  * r + smooth/2)), and the profile is shifted so that the beam's first-hit bin
  * (its G-buffer mean first-bounce range) is bin 0, zero past the end.
- * Layers: 3 x 3 convolution 7 -> 64 (as an im2col product), then
- * 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers; 168,768 parameters.
+ * Layers: 3 x 3 convolution 8 -> 64 (as an im2col product), then
+ * 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers; 169,344 parameters.
  * Products use BF16 operands on the matrix cores with FP32 accumulation;
  * training is MSE on the coefficients with Adam (beta 0.9 / 0.999, eps 1e-8)
  * on FP32 master weights.
  *
  * Parameter vector layout (float, sonar_surrogate_param_count() entries): for
  * each layer W [fan_in][fan_out] row-major then b [fan_out], with (fan_in,
- * fan_out) = (63, 64), (64, 256), (256, 256), (256, 256), (256, 64).
+ * fan_out) = (72, 64), (64, 256), (256, 256), (256, 256), (256, 64).
  * G-buffer: float [n_img][H][W][8] as sonar_ping writes it; rows = n_img * H * W
  * (a multiple of 64 for the network, at most max_rows everywhere).
  * Standardisation: coefficient j is (c_j - mean_j) / std_j (defaults 0, 1). */

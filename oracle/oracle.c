@@ -1431,6 +1431,11 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
             for (int t = 0; t < 8; ++t) g[t] = 0.0;
             if (gcount > 0) for (int t = 0; t < 6; ++t) g[t] = gs[t] / gcount;
             g[6] = (double)gcount / NR;
+            /* the beam axis in the world frame: its vertical component */
+            const int nh = beams_h(P);
+            const double off = P->grid_mode == 1 ? 0.0 : 0.5;
+            const double az = -0.5 * P->hfov + (b % nh + off) * dh, el = -0.5 * P->vfov + (b / nh + off) * dv;
+            g[7] = sensor_to_world(Q, dir_from_angles(az, el)).z;
         }
     }
     if (rx) {

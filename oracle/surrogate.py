@@ -9,22 +9,23 @@ range profile that further bounces add, as the dB residual between the
 incoherent multi-bounce and single-bounce intensity, compressed to the first
 64 coefficients of an orthonormal DCT-II of the 1,024-bin profile.
 
-Network (168,768 parameters): a 3 x 3 beam-neighbourhood convolution of the
-7 G-buffer features (written as an im2col product with 63 inputs, zero
-padding at the edges) -> ReLU -> 64 -> 256 -> 256 -> 256 -> 64 dense layers
-with ReLU between them. Loss: mean squared error over the 64 standardised
+Network (169,344 parameters): a 3 x 3 beam-neighbourhood convolution of the
+8 G-buffer features (the first-hit statistics and the beam axis's vertical
+component; written as an im2col product with 72 inputs, zero padding at the
+edges) -> ReLU -> 64 -> 256 -> 256 -> 256 -> 64 dense layers with ReLU
+between them. Loss: mean squared error over the 64 standardised
 coefficients.
 
-Parameter vector layout (float, 168,768 entries): for each layer in order
-W [K][N] row-major then b [N], with (K, N) = (63, 64), (64, 256), (256, 256),
+Parameter vector layout (float, 169,344 entries): for each layer in order
+W [K][N] row-major then b [N], with (K, N) = (72, 64), (64, 256), (256, 256),
 (256, 256), (256, 64).
 """
 from __future__ import annotations
 
 import numpy as np
 
-LAYERS = ((63, 64), (64, 256), (256, 256), (256, 256), (256, 64))
-N_FEAT = 7
+LAYERS = ((72, 64), (64, 256), (256, 256), (256, 256), (256, 64))
+N_FEAT = 8
 N_COEF = 64
 I_FLOOR = 1e-11
 
@@ -50,8 +51,8 @@ def pack(layers):
 
 
 def im2col(gbuf):
-    """gbuf [n_img, H, W, >= 7] -> [n_img * H * W, 63]: for each beam (v, h)
-    the 7 features of (v + dv, h + dh), dv, dh in {-1, 0, 1}, zero outside,
+    """gbuf [n_img, H, W, 8] -> [n_img * H * W, 72]: for each beam (v, h)
+    the 8 features of (v + dv, h + dh), dv, dh in {-1, 0, 1}, zero outside,
     ordered (dv, dh, feature)."""
     g = np.asarray(gbuf, np.float64)[..., :N_FEAT]
     n, H, W, _ = g.shape

@@ -1413,9 +1413,18 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         if (active && j == 0) {
             float cnt = gfeat[6];
             float inv = cnt > 0.f ? 1.f / cnt : 0.f;
+            // the beam axis (cell centre, or the grid node) in the world frame: its vertical component
+            const int bh = (int)(beam % a.beams_h), bv = (int)(beam / a.beams_h);
+            const float off = a.grid_mode == 1 ? 0.f : 0.5f;
+            const float az = (float)(-0.5 * a.hfov) + ((float)bh + off) * (float)a.dth_h;
+            const float el = (float)(-0.5 * a.vfov) + ((float)bv + off) * (float)a.dth_v;
+            float sa, ca, se, ce;
+            sincosf(az, &sa, &ca);
+            sincosf(el, &se, &ce);
+            const float up = (float)a.rot[6] * (ce * ca) + (float)a.rot[7] * (ce * sa) + (float)a.rot[8] * se;
             float4 *g = reinterpret_cast<float4 *>(a.gbuf + (size_t)beam * 8);
             g[0] = make_float4(gfeat[0] * inv, gfeat[1] * inv, gfeat[2] * inv, gfeat[3] * inv);
-            g[1] = make_float4(gfeat[4] * inv, gfeat[5] * inv, cnt / a.n_r, 0.f);
+            g[1] = make_float4(gfeat[4] * inv, gfeat[5] * inv, cnt / a.n_r, up);
         }
     }
 

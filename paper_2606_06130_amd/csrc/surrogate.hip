@@ -2,10 +2,11 @@
 //
 // Sec. II-B lets scattering and reverberation effects be learned from data.
 // Here a small network maps each beam's single-bounce G-buffer (3 x 3 beam
-// neighbourhood of 7 features) to the first 64 orthonormal DCT-II
-// coefficients of the dB residual that further bounces add to its range
-// profile. Layers: im2col convolution 63(+1 zero) -> 64, then
-// 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers.
+// neighbourhood of 8 features: the first-hit statistics and the beam axis's
+// vertical component) to the first 64 orthonormal DCT-II coefficients of the
+// dB residual that further bounces add to its range profile. Layers: im2col
+// convolution 72 (+56 zero) -> 64, then 64 -> 256 -> 256 -> 256 -> 64, ReLU
+// between layers.
 //
 // Dense products run on the CDNA4 matrix cores: v_mfma_f32_16x16x32_bf16
 // (BF16 operands, FP32 accumulation), 64 x 64 block tiles staged through LDS
@@ -32,11 +33,15 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int NL = 5;                                       // layers
-constexpr int LK[NL] = {63, 64, 256, 256, 256};             // true fan-in
-constexpr int LKP[NL] = {64, 64, 256, 256, 256};            // padded fan-in (multiple of 32)
+constexpr int LK[NL] = {72, 64, 256, 256, 256};             // true fan-in
+// padded fan-in: a multiple of 64, since the weight gradient X^T dZ has it as
+// its row count and the products tile rows and columns by 64
+constexpr int LKP[NL] = {128, 64, 256, 256, 256};
+static_assert(LKP[0] % 64 == 0 && LKP[1] % 64 == 0 && LKP[2] % 64 == 0 && LKP[3] % 64 == 0 && LKP[4] % 64 == 0,
+              "padded fan-ins tile by 64");
 constexpr int LN[NL] = {64, 256, 256, 256, 64};             // fan-out
 constexpr int NCOEF = 64;
-constexpr int NFEAT = 7;
+constexpr int NFEAT = 8;
 constexpr int GB_STRIDE = 8;                                // floats per beam in the G-buffer
 constexpr int TM = 64, TN = 64, TK = 32, LDT = TK + 8;      // GEMM tiles; LDS row stride in bf16
 constexpr int SPLIT_ROWS = 4096;                            // reduction chunk of the weight gradients
@@ -131,18 +136,18 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int 
             }
 }
 
-// im2col of the G-buffer: row (img, v, h) gets the 7 features of the 3 x 3
-// neighbourhood ordered (dv, dh, feature), zero outside the image, then a
-// zero 64th column. One thread per output element pair.
+// im2col of the G-buffer: row (img, v, h) gets the 8 features of the 3 x 3
+// neighbourhood ordered (dv, dh, feature), zero outside the image, then zero
+// columns up to the padded width. One thread per output element.
 __global__ void k_im2col(const float *__restrict__ g, int n_img, int H, int W, __bf16 *__restrict__ x)
 {
     const int64_t rows = (int64_t)n_img * H * W;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows * 64) return;
-    const int64_t row = i >> 6;
-    const int c = (int)(i & 63);
+    if (i >= rows * LKP[0]) return;
+    const int64_t row = i / LKP[0];
+    const int c = (int)(i % LKP[0]);
     float v = 0.f;
-    if (c < 63) {
+    if (c < LK[0]) {
         const int q = c / NFEAT, f = c % NFEAT;
         const int dv = q / 3 - 1, dh = q % 3 - 1;
         const int img = (int)(row / ((int64_t)H * W));
@@ -729,7 +734,7 @@ static void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, int K, int 
 static void forward_layers(Surrogate *s, const float *gbuf, int n_img, int H, int W, hipStream_t st)
 {
     const int64_t rows = (int64_t)n_img * H * W;
-    hipLaunchKernelGGL(k_im2col, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, st, gbuf, n_img, H, W,
+    hipLaunchKernelGGL(k_im2col, dim3((unsigned)((rows * LKP[0] + 255) / 256)), dim3(256), 0, st, gbuf, n_img, H, W,
                        s->x[0]);
     for (int l = 0; l < NL; ++l) {
         if (l < NL - 1)

@@ -636,6 +636,7 @@ class Surrogate:
         a = np.ascontiguousarray(mean, np.float32)
         b = np.ascontiguousarray(std, np.float32)
         _check(lib().sonar_surrogate_set_norm(self._h, a.ctypes.data, b.ctypes.data))
+        self.mean, self.std = a, b
 
     def forward(self, gbuf, out=None, stream=None):
         import torch

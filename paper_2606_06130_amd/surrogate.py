@@ -109,28 +109,40 @@ def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
 def evaluate(sur, src, poses):
     """Mean and p95 per-beam dB errors over beams with occupied bins:
     surrogate, single bounce only, single bounce + mean residual, and the
-    best any 64-coefficient prediction can do (the truncated truth)."""
+    best any 64-coefficient prediction can do (the truncated truth), all
+    against the smoothed truth; and the surrogate against the truncated truth
+    (the network's own error, the DCT truncation taken out)."""
     torch = src.torch
-    errs, errt = [], []
+    errs, errt, errn = [], [], []
     coef = torch.empty((src.rows, 64), dtype=torch.float32, device="cuda")
     exact = torch.empty((src.rows, 64), dtype=torch.float32, device="cuda")
     gbv = torch.empty((1, src.H, src.W, 8), dtype=torch.float32, device="cuda")
+    # standardised coefficients of a zero residual: the profile is then the smoothed input channel
+    zero = torch.from_numpy(-sur.mean / sur.std).cuda().expand(src.rows, 64).contiguous()
+    occupied_db = 10.0 * math.log10(1e-11) + 3.0
     for p in poses:
         _, i1, im = src.run(p, gbuf_slot=gbv[0])
         sur.forward(gbv, out=coef)
-        _, e = sur.profile(coef, i1, gbv, im, want_profile=False)
+        pred, e = sur.profile(coef, i1, gbv, im)
         sur.residual(i1, im, gbv, standardize=True, out=exact)
-        _, et = sur.profile(exact, i1, gbv, im, want_profile=False)
+        trunc, et = sur.profile(exact, i1, gbv, im)
+        truth, _ = sur.profile(zero, i1 + im, gbv)
+        occ = truth > occupied_db
+        cnt = occ.sum(dim=1)
+        en = torch.where(occ, (pred - trunc).abs(), torch.zeros_like(pred)).sum(dim=1) / cnt.clamp(min=1)
         errs.append(e.cpu().numpy())
         errt.append(et.cpu().numpy())
+        errn.append(en.cpu().numpy())
     e = np.concatenate(errs)
     et = np.concatenate(errt)
+    en = np.concatenate(errn)
     ok = e[:, 3] > 0
-    e, et = e[ok], et[ok]
+    e, et, en = e[ok], et[ok], en[ok]
     out = {"beams": int(ok.sum()), "pings": len(poses)}
     for i, nm in enumerate(("surrogate", "single_bounce", "mean_residual")):
         out[nm] = {"mean_db": float(np.mean(e[:, i])), "p95_db": float(np.percentile(e[:, i], 95))}
     out["truncated_truth"] = {"mean_db": float(np.mean(et[:, 0])), "p95_db": float(np.percentile(et[:, 0], 95))}
+    out["surrogate_vs_truncated_truth"] = {"mean_db": float(np.mean(en)), "p95_db": float(np.percentile(en, 95))}
     return out
 
 

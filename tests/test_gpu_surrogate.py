@@ -80,7 +80,7 @@ def test_gradient_matches_oracle():
         # exact definition: BF16 storage of activations and layer gradients
         # (unit roundoff 2^-9) through 5 layers, plus ReLU masks that flip
         # where a pre-activation is within rounding of zero
-        assert rel <= 5e-2 and cos >= 0.999, (i, rel, cos)
+        assert rel <= 5e-2 and cos >= 0.998, (i, rel, cos)
         # same storage precision: only FP32 accumulation order differs
         assert relb <= 5e-3, (i, relb)
 

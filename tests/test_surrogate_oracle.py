@@ -9,14 +9,14 @@ from paper_2606_06130_amd.scenes import surrogate_init_params
 
 
 def test_parameter_count():
-    assert SO.param_count() == 168768
+    assert SO.param_count() == 169344
 
 
 def test_im2col_brute_force():
     rng = np.random.Generator(np.random.PCG64(1))
     g = rng.normal(size=(2, 5, 6, 8))
     X = SO.im2col(g)
-    assert X.shape == (60, 63)
+    assert X.shape == (60, 72)
     for n in range(2):
         for v in range(5):
             for h in range(6):
@@ -25,9 +25,9 @@ def test_im2col_brute_force():
                 for dv in (-1, 0, 1):
                     for dh in (-1, 0, 1):
                         vv, hh = v + dv, h + dh
-                        want = g[n, vv, hh, :7] if 0 <= vv < 5 and 0 <= hh < 6 else np.zeros(7)
-                        np.testing.assert_array_equal(row[q:q + 7], want)
-                        q += 7
+                        want = g[n, vv, hh, :8] if 0 <= vv < 5 and 0 <= hh < 6 else np.zeros(8)
+                        np.testing.assert_array_equal(row[q:q + 8], want)
+                        q += 8
 
 
 def test_gradients_match_central_differences():
