@@ -186,6 +186,21 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     assert scene.status() == 0
     lay_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     del out_l
+    # the same ping with retro-chain returns at every later vertex
+    cfg_r = cfg.replace(flags=8)
+    out_r = sonar.alloc_outputs(cfg_r)
+    for _ in range(2):
+        sonar.ping(scene, cfg_r, pose, out=out_r)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for a, b in ev:
+        a.record(stream)
+        sonar.ping(scene, cfg_r, pose, out=out_r)
+        b.record(stream)
+    torch.cuda.synchronize()
+    assert scene.status() == 0
+    retro_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    del out_r
     multipath = {"workload": "harbor multipath ping: 1,991,680 triangles, 256x128 beams x 16 rays, 3 bounces, "
                              "Phong-20 + diffuse, c(z) = 1500 + 0.05 z, 1,024 bins",
                  "ping_ms": mp_ms, "pings_per_s": 1e3 / mp_ms, "mrays_per_s": cfg.n_rays / mp_ms / 1e3,
@@ -194,6 +209,9 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
                                              "note": "same ping with the Gaussian transmit-receive pattern and "
                                                      "later-bounce returns binned by arrival direction (list + "
                                                      "scatter after the ping kernel)"},
+                 "retro_chain": {"ping_ms": retro_ms,
+                                 "note": "same ping with retro-chain returns (every later vertex also returns along "
+                                         "its outgoing chain reversed; 2K - 1 contribution slots per lane)"},
                  "layered_profile": {"ping_ms": lay_ms,
                                      "note": "same ping through c(z) piecewise linear in 5 knots from -9 m to 1.5 m: "
                                              "returns along the first-arriving eigenray of each vertex"}}
