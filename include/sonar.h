@@ -267,13 +267,22 @@ typedef struct {
  * exceeds every speed on the way there, the turning depth searched within
  * 2 r_max); a vertex no such ray reaches (a shadow zone) returns nothing
  * (record vis 0). SONAR_E_INVALID for 2 > n_knots > SONAR_MAX_SSP_KNOTS,
- * knots not strictly increasing, c <= 0 at a knot or over the scene;
- * SONAR_E_UNSUPPORTED for layers bending more than |g| 2 r_max / c = 1e-2
- * and for SONAR_FLAG_RX_BEAMS with max_bounces > 1. Asynchronous on
- * `stream`; no workspace. */
+ * knots not strictly increasing, c <= 0 at a knot or over the scene, and
+ * for SONAR_FLAG_RX_BEAMS with max_bounces > 1 (that needs the workspace of
+ * sonar_ping_ssp_rx); SONAR_E_UNSUPPORTED for layers bending more than
+ * |g| 2 r_max / c = 1e-2. Asynchronous on `stream`; no workspace. */
 sonar_status sonar_ping_ssp(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
                             const sonar_ssp *ssp, sonar_cf32 *volume, float *gbuffer, float *incoh,
                             const sonar_ray_record *record, const uint32_t *ray_mask, sonar_stream stream);
+
+/* sonar_ping_ssp with a workspace (as sonar_ping_rx: device memory of at
+ * least sonar_rx_workspace_size(params) bytes, 256-byte aligned, owned by the
+ * caller, one ping at a time), for SONAR_FLAG_RX_BEAMS with several bounces
+ * through the layered profile. */
+sonar_status sonar_ping_ssp_rx(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
+                               const sonar_ssp *ssp, sonar_cf32 *volume, float *gbuffer, float *incoh,
+                               const sonar_ray_record *record, const uint32_t *ray_mask, void *workspace,
+                               size_t ws_bytes, sonar_stream stream);
 
 /* Bytes of device workspace sonar_ping_rx needs: a list of up to
  * n_rays * (max_bounces - 1) returns that receive binning moves to another

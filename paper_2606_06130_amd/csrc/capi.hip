@@ -400,11 +400,12 @@ sonar_status sonar_ping(const sonar_scene *sc, const sonar_params *p, const sona
 
 static_assert(SONAR_MAX_SSP_KNOTS == sonar::MAX_SSP_KNOTS, "profile knots");
 
-sonar_status sonar_ping_ssp(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, const sonar_ssp *ssp,
-                            sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *rec,
-                            const uint32_t *ray_mask, sonar_stream stream)
+// A ping through a layered profile; `workspace` (NULL: none) holds the
+// receive-binning list of several bounces.
+static sonar_status ping_ssp(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, const sonar_ssp *ssp,
+                             sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *rec,
+                             const uint32_t *ray_mask, void *workspace, size_t ws_bytes, sonar_stream stream)
 {
-    g_err[0] = 0;
     if (!ssp) return fail(SONAR_E_INVALID, "ssp is NULL");
     if (!sc) return fail(SONAR_E_INVALID, "scene is NULL");
     sonar_status st = check_params(p);
@@ -418,8 +419,12 @@ sonar_status sonar_ping_ssp(const sonar_scene *sc, const sonar_params *p, const 
             return fail(SONAR_E_INVALID, "knot %d: z finite and c > 0 required", k);
         if (k > 0 && !(ssp->z[k] > ssp->z[k - 1])) return fail(SONAR_E_INVALID, "knot depths must increase");
     }
-    if (p->max_bounces > 1 && (p->flags & SONAR_FLAG_RX_BEAMS))
-        return fail(SONAR_E_UNSUPPORTED, "layered profiles do not take receive binning with several bounces");
+    if (needs_rx_list(p)) {
+        if (!workspace)
+            return fail(SONAR_E_INVALID, "receive binning with several bounces needs a workspace: use sonar_ping_ssp_rx");
+        if (ws_bytes < rx_bytes(p)) return fail(SONAR_E_INVALID, "workspace smaller than sonar_rx_workspace_size()");
+        if (((uintptr_t)workspace & 255) != 0) return fail(SONAR_E_INVALID, "workspace must be 256-byte aligned");
+    }
     const int nl = n - 1;
     double g[SONAR_MAX_SSP_KNOTS], c0[SONAR_MAX_SSP_KNOTS];
     for (int i = 0; i < nl; ++i) {
@@ -458,9 +463,33 @@ sonar_status sonar_ping_ssp(const sonar_scene *sc, const sonar_params *p, const 
     }
     a.c_ref = pp.c0;
     a.c_hi = c_hi;
-    hipError_t e = sonar::launch_ping_layered(a, sc->s.stack, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (needs_rx_list(p)) {
+        // reset -> ping -> scatter of the returns binned to other beams
+        set_rx_area(a, p, workspace);
+        e = sonar::launch_rx_reset(a.rx_count, s);
+    }
+    if (e == hipSuccess) e = sonar::launch_ping_layered(a, sc->s.stack, s);
+    if (e == hipSuccess && a.rx_list) e = sonar::launch_rx_scatter(a, s);
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping launch: %s", hipGetErrorString(e));
     return SONAR_OK;
+}
+
+sonar_status sonar_ping_ssp(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, const sonar_ssp *ssp,
+                            sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *rec,
+                            const uint32_t *ray_mask, sonar_stream stream)
+{
+    g_err[0] = 0;
+    return ping_ssp(sc, p, q, ssp, volume, gbuffer, incoh, rec, ray_mask, nullptr, 0, stream);
+}
+
+sonar_status sonar_ping_ssp_rx(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, const sonar_ssp *ssp,
+                               sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *rec,
+                               const uint32_t *ray_mask, void *workspace, size_t ws_bytes, sonar_stream stream)
+{
+    g_err[0] = 0;
+    return ping_ssp(sc, p, q, ssp, volume, gbuffer, incoh, rec, ray_mask, workspace, ws_bytes, stream);
 }
 
 size_t sonar_rx_workspace_size(const sonar_params *p)

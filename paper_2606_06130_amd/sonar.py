@@ -39,7 +39,7 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
            "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb",
-           "sonar_ping_ssp")
+           "sonar_ping_ssp", "sonar_ping_ssp_rx")
 
 
 class SonarError(RuntimeError):
@@ -214,6 +214,10 @@ def lib():
         L.sonar_ping_ssp.restype = C.c_int
         L.sonar_ping_ssp.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_ssp), C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.sonar_ping_ssp_rx.restype = C.c_int
+        L.sonar_ping_ssp_rx.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_ssp), C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                        C.c_void_p]
         L.sonar_add_reverb.restype = C.c_int
         L.sonar_add_reverb.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_reverb), C.c_void_p]
         L.sonar_rx_workspace_size.restype = C.c_size_t
@@ -349,6 +353,18 @@ def alloc_outputs(cfg, gbuffer=False, incoh=False, record=False, stats=False, de
     return out
 
 
+def _rx_workspace(out, p):
+    """The receive-binning workspace, kept with the outputs (grown when too small)."""
+    import torch
+    need = lib().sonar_rx_workspace_size(C.byref(p))
+    if need == 0:           # invalid parameters: the ping call reports why
+        need = 256
+    ws = out.get("rx_workspace")
+    if ws is None or ws.numel() < need:
+        ws = out["rx_workspace"] = torch.empty(need, dtype=torch.uint8, device=out["volume"].device)
+    return ws
+
+
 def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=False, ray_mask=None, stream=None,
          params=None, pose_s=None, stats=False):
     """One ping; returns the dict of output tensors (allocated if ``out`` is None)."""
@@ -367,20 +383,19 @@ def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=F
     if getattr(cfg, "ssp", ()):
         # piecewise-linear sound speed
         prof = ssp_of(cfg.ssp)
+        if (p.flags & FLAG_RX_BEAMS) and p.max_bounces > 1:
+            ws = _rx_workspace(out, p)
+            _check(lib().sonar_ping_ssp_rx(scene.handle, C.byref(p), C.byref(q), C.byref(prof), _dptr(out["volume"]),
+                                           _dptr(out.get("gbuffer")), _dptr(out.get("incoh")),
+                                           C.byref(rec) if rec is not None else None, _dptr(ray_mask), _dptr(ws),
+                                           ws.numel(), _stream(stream)))
+            return out
         _check(lib().sonar_ping_ssp(scene.handle, C.byref(p), C.byref(q), C.byref(prof), _dptr(out["volume"]),
                                     _dptr(out.get("gbuffer")), _dptr(out.get("incoh")),
                                     C.byref(rec) if rec is not None else None, _dptr(ray_mask), _stream(stream)))
         return out
     if (p.flags & FLAG_RX_BEAMS) and p.max_bounces > 1:
-        # receive binning lists the returns it moves: a workspace kept with the outputs
-        import torch
-        need = lib().sonar_rx_workspace_size(C.byref(p))
-        if need == 0:       # invalid parameters: the plain call reports why
-            _check(lib().sonar_ping(scene.handle, C.byref(p), C.byref(q), _dptr(out["volume"]), None, None, None,
-                                    None, _stream(stream)))
-        ws = out.get("rx_workspace")
-        if ws is None or ws.numel() < need:
-            ws = out["rx_workspace"] = torch.empty(need, dtype=torch.uint8, device=out["volume"].device)
+        ws = _rx_workspace(out, p)
         _check(lib().sonar_ping_rx(scene.handle, C.byref(p), C.byref(q), _dptr(out["volume"]),
                                    _dptr(out.get("gbuffer")), _dptr(out.get("incoh")),
                                    C.byref(rec) if rec is not None else None, _dptr(ray_mask), _dptr(ws), ws.numel(),

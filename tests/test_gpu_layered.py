@@ -81,6 +81,17 @@ def test_surface_wall_layered_multipath(knots, K):
     assert res["im_energy"] > 0 and (orc["bin"][:, 1] >= 0).sum() > 500
 
 
+def test_layered_multipath_receive_binning_and_pattern():
+    """Returns of later bounces binned by their arrival direction (the
+    eigenray's arrival at the sensor), through the workspace call."""
+    cfg = S.SensorConfig(n_h=32, n_v=16, rays_per_beam=4, n_range=1024, max_bounces=3, k_d=0.7, k_s=0.3,
+                         vfov=math.radians(60), ssp=KNOTS_CHANNEL, flags=1 | 2)
+    res, g, orc = run_parity(_surface_wall(), cfg, S.pose((0.0, 0.0, 0.0), pitch_down=math.radians(-10)))
+    assert_parity(res, 3)
+    moved = (orc["bin"][:, 1:] >= 0) & (orc["rxb"][:, 1:] != (np.arange(len(orc["rxb"])) // 4)[:, None])
+    assert moved.sum() > 50
+
+
 def test_layered_multipath_drawn_continuations():
     cfg = S.SensorConfig(n_h=32, n_v=16, rays_per_beam=4, n_range=1024, max_bounces=3, k_d=0.7, k_s=0.3,
                          vfov=math.radians(60), ssp=KNOTS_CHANNEL, seed=21, flags=4)
@@ -126,8 +137,15 @@ def test_layered_profile_rejections():
     sc = sonar.Scene(S.scene_seabed_boxes())
     pose = S.pose_seabed_boxes()
     cfg = S.sensor_seabed_boxes().replace(ssp=KNOTS)
-    for bad, status in ((cfg.replace(max_bounces=2, flags=2), sonar.SONAR_E_UNSUPPORTED),
-                        (cfg.replace(ssp=((0.0, 1500.0), (-1.0, 1490.0))), sonar.SONAR_E_INVALID),
+    # receive binning with several bounces needs the workspace call
+    import ctypes as C
+    bad = cfg.replace(max_bounces=2, flags=2)
+    out = sonar.alloc_outputs(bad)
+    st = sonar.lib().sonar_ping_ssp(sc.handle, C.byref(sonar.params_of(bad)), C.byref(sonar.pose_of(pose)),
+                                    C.byref(sonar.ssp_of(bad.ssp)), out["volume"].data_ptr(), None, None, None, None,
+                                    None)
+    assert st == sonar.SONAR_E_INVALID
+    for bad, status in ((cfg.replace(ssp=((0.0, 1500.0), (-1.0, 1490.0))), sonar.SONAR_E_INVALID),
                         (cfg.replace(ssp=((0.0, 1500.0),)), sonar.SONAR_E_INVALID),
                         (cfg.replace(ssp=((-1.0, 1500.0), (0.0, 0.0))), sonar.SONAR_E_INVALID),
                         (cfg.replace(ssp=((-1.0, 1400.0), (0.0, 1500.0))), sonar.SONAR_E_UNSUPPORTED)):
