@@ -150,7 +150,8 @@ typedef struct {
  *                     it arrives along the launch ray (launch beam, transmit
  *                     pattern squared) and counts as a later bounce in the
  *                     incoherent channel. No effect with max_bounces 1;
- *                     batches reject it. */
+ *                     batches reject it, and so does n_range above 3328
+ *                     (3 bounces) or 3584 (4 bounces). */
 #define SONAR_FLAG_BEAM_PATTERN 1u
 #define SONAR_FLAG_RX_BEAMS 2u
 #define SONAR_FLAG_DIFFUSE_BOUNCE 4u

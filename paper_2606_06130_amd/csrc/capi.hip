@@ -162,8 +162,10 @@ sonar_status fill_ping_args(const sonar_scene *sc, const sonar_params *p, const 
     if ((p->flags & SONAR_FLAG_RETRO_CHAIN) && p->max_bounces > 1) {
         if (rec && rec->stats)
             return fail(SONAR_E_UNSUPPORTED, "traversal counters are not kept with retro-chain returns");
-        if (p->max_bounces == 4 && p->n_range > 3584)
-            return fail(SONAR_E_UNSUPPORTED, "retro-chain returns with four bounces take at most 3584 bins");
+        const int max_bins = p->max_bounces == 3 ? 3328 : (p->max_bounces == 4 ? 3584 : 4096);
+        if (p->n_range > max_bins)
+            return fail(SONAR_E_UNSUPPORTED, "retro-chain returns with %d bounces take at most %d bins",
+                        p->max_bounces, max_bins);
     }
     // a sound speed must stay positive over the scene and the sensor
     if (p->c_grad != 0.0) {

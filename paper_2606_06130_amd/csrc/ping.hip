@@ -40,9 +40,10 @@ constexpr int K1_IDX_BASE = K1_BIN_WORDS + K1_VAL_WORDS;      // uint16 column i
 // a SIMD.
 constexpr int K1_LDS_STACK = 20;
 constexpr int KN_LDS_STACK = 32;
-// four bounces with retro-chain slots: a shorter LDS stack keeps a block
-// within 64 KB (the column index then holds up to 28 * 64 * 2 bins)
-constexpr int KN_LDS_STACK_R4 = 28;
+// LDS stack entries with retro-chain slots (2K - 1 per lane): three bounces
+// keep three blocks per CU (160 KB), four bounces keep a block within 64 KB;
+// the column index reuses the stack, so it holds up to entries * 64 * 2 bins
+constexpr int kn_lds_stack_retro(int K) { return K == 3 ? 26 : (K == 4 ? 28 : KN_LDS_STACK); }
 
 struct d3 {
     double x, y, z;
@@ -1050,7 +1051,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
     // an LDS area past the traversal stack, slot (k, lane) at k * 64 + lane,
     // with the retro-chain returns of vertices 1..K-1 in slots K..2K-2.
     constexpr int KS = RETRO ? 2 * K - 1 : K;
-    constexpr int DLS = K == 1 ? K1_LDS_STACK : ((RETRO && K == 4) ? KN_LDS_STACK_R4 : KN_LDS_STACK);
+    constexpr int DLS = K == 1 ? K1_LDS_STACK : (RETRO ? kn_lds_stack_retro(K) : KN_LDS_STACK);
     constexpr int DL = DEPTH > DLS ? DLS : DEPTH;
     int *sbin = (K == 1) ? reinterpret_cast<int *>(W) : reinterpret_cast<int *>(W + DL * WAVE);
     float4 *sval = (K == 1) ? reinterpret_cast<float4 *>(W + K1_BIN_WORDS)
@@ -1713,7 +1714,7 @@ hipError_t launch_rx_scatter(const PingArgs &a, hipStream_t s)
 int ping_wave_words(int depth, int n_bins, int K, bool retro = false)
 {
     if (K > 1) {   // LDS stack + slots; the column index reuses the stack
-        const int dls = (retro && K == 4) ? KN_LDS_STACK_R4 : KN_LDS_STACK;
+        const int dls = retro ? kn_lds_stack_retro(K) : KN_LDS_STACK;
         return (depth > dls ? dls : depth) * WAVE + 5 * WAVE * (retro ? 2 * K - 1 : K);
     }
     const int stk = (depth > K1_LDS_STACK ? K1_LDS_STACK : depth) * WAVE;

@@ -110,10 +110,12 @@ def test_retro_chain_rejections():
     with pytest.raises(sonar.SonarError) as e:
         sonar.ping(sc, _cfg(), POSE, record=True, stats=True)
     assert e.value.status == sonar.SONAR_E_UNSUPPORTED
-    with pytest.raises(sonar.SonarError) as e:
-        sonar.ping(sc, _cfg(max_bounces=4, n_range=4096), POSE)
-    assert e.value.status == sonar.SONAR_E_UNSUPPORTED
-    sonar.ping(sc, _cfg(max_bounces=4, n_range=3584), POSE)
+    for K, most in ((3, 3328), (4, 3584)):
+        with pytest.raises(sonar.SonarError) as e:
+            sonar.ping(sc, _cfg(max_bounces=K, n_range=most + 2), POSE)
+        assert e.value.status == sonar.SONAR_E_UNSUPPORTED
+        sonar.ping(sc, _cfg(max_bounces=K, n_range=most), POSE)
+    sonar.ping(sc, _cfg(max_bounces=2, n_range=4096), POSE)
     sonar.ping(sc, _cfg(max_bounces=1), POSE)                 # one bounce: nothing to retrace
     torch.cuda.synchronize()
     assert sc.status() == 0
