@@ -403,9 +403,10 @@ sonar_status sonar_pulse_compress(const sonar_cf32 *volume, int64_t n_beams, int
  * beam in one persistent launch. Work items are (ping, tile of 256 rays);
  * persistent workgroups pop them from one device counter. All pings of a
  * batch share the scene, max_bounces and the medium type (c_grad zero or
- * not). */
+ * not, or one layered profile). */
 
-/* Host summary of a prepared batch (filled by sonar_batch_prepare). */
+/* Host summary of a prepared batch (filled by sonar_batch_prepare): `arc`
+ * is the medium type, 0 straight rays, 1 one gradient, 2 a layered profile. */
 typedef struct {
     int32_t n_pings, max_bounces, arc, max_bins, max_beams, reserved;
     int64_t total_tiles, total_rays;
@@ -439,6 +440,13 @@ size_t sonar_batch_workspace_size(int32_t n_pings);
 sonar_status sonar_batch_prepare(const sonar_scene *scene, int32_t n_pings, const sonar_params *params,
                                  const sonar_pose *poses, sonar_cf32 *const *volumes, void *host_desc,
                                  sonar_batch_plan *plan);
+
+/* sonar_batch_prepare for pings through one layered sound-speed profile (as
+ * sonar_ping_ssp; each ping's time-to-range speed is c at its own sensor
+ * depth). Validation as sonar_ping_ssp per ping. */
+sonar_status sonar_batch_prepare_ssp(const sonar_scene *scene, int32_t n_pings, const sonar_params *params,
+                                     const sonar_pose *poses, const sonar_ssp *ssp, sonar_cf32 *const *volumes,
+                                     void *host_desc, sonar_batch_plan *plan);
 
 /* Detection for a prepared batch (Sec. II-A: each ping's point cloud):
  * amends the ping descriptors in `host_desc` (as filled by

@@ -402,11 +402,12 @@ sonar_status sonar_ping(const sonar_scene *sc, const sonar_params *p, const sona
 
 static_assert(SONAR_MAX_SSP_KNOTS == sonar::MAX_SSP_KNOTS, "profile knots");
 
-// A ping through a layered profile; `workspace` (NULL: none) holds the
-// receive-binning list of several bounces.
-static sonar_status ping_ssp(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, const sonar_ssp *ssp,
-                             sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *rec,
-                             const uint32_t *ray_mask, void *workspace, size_t ws_bytes, sonar_stream stream)
+// Ping arguments through a layered profile: validation of the knots, the
+// layers' gradients and offsets, the time-to-range speed at the sensor and
+// an upper bound of c over the scene.
+static sonar_status layered_args(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q,
+                                 const sonar_ssp *ssp, sonar_cf32 *volume, float *gbuffer, float *incoh,
+                                 const sonar_ray_record *rec, const uint32_t *ray_mask, sonar::PingArgs *out)
 {
     if (!ssp) return fail(SONAR_E_INVALID, "ssp is NULL");
     if (!sc) return fail(SONAR_E_INVALID, "scene is NULL");
@@ -420,12 +421,6 @@ static sonar_status ping_ssp(const sonar_scene *sc, const sonar_params *p, const
         if (!isfinite(ssp->z[k]) || !(ssp->c[k] > 0) || !isfinite(ssp->c[k]))
             return fail(SONAR_E_INVALID, "knot %d: z finite and c > 0 required", k);
         if (k > 0 && !(ssp->z[k] > ssp->z[k - 1])) return fail(SONAR_E_INVALID, "knot depths must increase");
-    }
-    if (needs_rx_list(p)) {
-        if (!workspace)
-            return fail(SONAR_E_INVALID, "receive binning with several bounces needs a workspace: use sonar_ping_ssp_rx");
-        if (ws_bytes < rx_bytes(p)) return fail(SONAR_E_INVALID, "workspace smaller than sonar_rx_workspace_size()");
-        if (((uintptr_t)workspace & 255) != 0) return fail(SONAR_E_INVALID, "workspace must be 256-byte aligned");
     }
     const int nl = n - 1;
     double g[SONAR_MAX_SSP_KNOTS], c0[SONAR_MAX_SSP_KNOTS];
@@ -454,7 +449,7 @@ static sonar_status ping_ssp(const sonar_scene *sc, const sonar_params *p, const
     sonar_params pp = *p;
     pp.c_grad = 0.0;
     pp.c0 = c_at(q->position[2]);
-    sonar::PingArgs a;
+    sonar::PingArgs &a = *out;
     st = fill_ping_args(sc, &pp, q, volume, gbuffer, incoh, rec, ray_mask, &a);
     if (st != SONAR_OK) return st;
     a.n_layers = nl;
@@ -465,6 +460,24 @@ static sonar_status ping_ssp(const sonar_scene *sc, const sonar_params *p, const
     }
     a.c_ref = pp.c0;
     a.c_hi = c_hi;
+    return SONAR_OK;
+}
+
+// A ping through a layered profile; `workspace` (NULL: none) holds the
+// receive-binning list of several bounces.
+static sonar_status ping_ssp(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, const sonar_ssp *ssp,
+                             sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *rec,
+                             const uint32_t *ray_mask, void *workspace, size_t ws_bytes, sonar_stream stream)
+{
+    sonar::PingArgs a;
+    sonar_status st = layered_args(sc, p, q, ssp, volume, gbuffer, incoh, rec, ray_mask, &a);
+    if (st != SONAR_OK) return st;
+    if (needs_rx_list(p)) {
+        if (!workspace)
+            return fail(SONAR_E_INVALID, "receive binning with several bounces needs a workspace: use sonar_ping_ssp_rx");
+        if (ws_bytes < rx_bytes(p)) return fail(SONAR_E_INVALID, "workspace smaller than sonar_rx_workspace_size()");
+        if (((uintptr_t)workspace & 255) != 0) return fail(SONAR_E_INVALID, "workspace must be 256-byte aligned");
+    }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (needs_rx_list(p)) {
@@ -759,11 +772,12 @@ size_t sonar_batch_workspace_size(int32_t n_pings)
     return 256 + 2 * sizeof(unsigned long long) * (size_t)n_pings;
 }
 
-sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_params *params,
-                                 const sonar_pose *poses, sonar_cf32 *const *volumes, void *host_desc,
-                                 sonar_batch_plan *plan)
+// Descriptors of a batch; `ssp` (NULL: none) is the layered profile every
+// ping goes through.
+static sonar_status batch_prepare(const sonar_scene *sc, int32_t n, const sonar_params *params,
+                                  const sonar_pose *poses, const sonar_ssp *ssp, sonar_cf32 *const *volumes,
+                                  void *host_desc, sonar_batch_plan *plan)
 {
-    g_err[0] = 0;
     if (!sc || !params || !poses || !volumes || !host_desc || !plan)
         return fail(SONAR_E_INVALID, "scene, params, poses, volumes, host_desc and plan are required");
     if (n < 1) return fail(SONAR_E_INVALID, "n_pings must be >= 1");
@@ -775,14 +789,17 @@ sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_p
             return fail(SONAR_E_UNSUPPORTED, "ping %d: batches do not take receive binning with several bounces", i);
         if ((params[i].flags & SONAR_FLAG_RETRO_CHAIN) && params[i].max_bounces > 1)
             return fail(SONAR_E_UNSUPPORTED, "ping %d: batches do not take retro-chain returns", i);
-        sonar_status st = fill_ping_args(sc, &params[i], &poses[i], volumes[i], nullptr, nullptr, nullptr, nullptr,
-                                         &d[i]);
+        sonar_status st = ssp ? layered_args(sc, &params[i], &poses[i], ssp, volumes[i], nullptr, nullptr, nullptr,
+                                             nullptr, &d[i])
+                              : fill_ping_args(sc, &params[i], &poses[i], volumes[i], nullptr, nullptr, nullptr,
+                                               nullptr, &d[i]);
         if (st != SONAR_OK) {
             char tmp[512];
             snprintf(tmp, sizeof(tmp), "ping %d: %s", i, g_err);
             return fail(st, "%s", tmp);
         }
-        if (params[i].max_bounces != params[0].max_bounces || (params[i].c_grad != 0.0) != (params[0].c_grad != 0.0))
+        if (params[i].max_bounces != params[0].max_bounces ||
+            (!ssp && (params[i].c_grad != 0.0) != (params[0].c_grad != 0.0)))
             return fail(SONAR_E_INVALID, "ping %d: a batch needs one max_bounces and one medium type", i);
         int64_t t = (d[i].n_rays + 255) / 256;
         if (tiles + t > 0x7FFFFFFF) return fail(SONAR_E_INVALID, "batch too large");
@@ -795,13 +812,30 @@ sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_p
     }
     plan->n_pings = n;
     plan->max_bounces = params[0].max_bounces;
-    plan->arc = params[0].c_grad != 0.0;
+    plan->arc = ssp ? 2 : (params[0].c_grad != 0.0 ? 1 : 0);
     plan->max_bins = max_bins;
     plan->max_beams = max_beams;
     plan->reserved = 0;
     plan->total_tiles = tiles;
     plan->total_rays = rays;
     return SONAR_OK;
+}
+
+sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_params *params,
+                                 const sonar_pose *poses, sonar_cf32 *const *volumes, void *host_desc,
+                                 sonar_batch_plan *plan)
+{
+    g_err[0] = 0;
+    return batch_prepare(sc, n, params, poses, nullptr, volumes, host_desc, plan);
+}
+
+sonar_status sonar_batch_prepare_ssp(const sonar_scene *sc, int32_t n, const sonar_params *params,
+                                     const sonar_pose *poses, const sonar_ssp *ssp, sonar_cf32 *const *volumes,
+                                     void *host_desc, sonar_batch_plan *plan)
+{
+    g_err[0] = 0;
+    if (!ssp) return fail(SONAR_E_INVALID, "ssp is NULL");
+    return batch_prepare(sc, n, params, poses, ssp, volumes, host_desc, plan);
 }
 
 static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_plan *plan, const void *dev_desc,
@@ -818,8 +852,10 @@ static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_p
     char *w = (char *)ws;
     b->desc = reinterpret_cast<const sonar::PingArgs *>(dev_desc);
     b->n_pings = plan->n_pings;
+    if (plan->arc < 0 || plan->arc > 2) return fail(SONAR_E_INVALID, "plan is not one filled by sonar_batch_prepare");
     b->K = plan->max_bounces;
     b->arc = plan->arc != 0;
+    b->layered = plan->arc == 2;
     b->depth = sc->s.stack;
     b->max_bins = plan->max_bins;
     b->total_tiles = plan->total_tiles;

@@ -125,6 +125,7 @@ struct BatchLaunch {
     int n_pings;
     int K;
     bool arc;
+    bool layered;            // every ping through its layered profile (descriptors carry it)
     int depth;               // hierarchy depth (selects the stack size)
     int max_bins;            // largest n_range of the batch (LDS sizing)
     int64_t total_tiles;

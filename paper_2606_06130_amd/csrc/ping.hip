@@ -1618,7 +1618,7 @@ void k_ping(PingArgs a, int wave_words)
 // the hierarchy depth class, bounce count and medium type (template
 // arguments); layouts, rays per beam, poses and outputs come per ping from
 // its descriptor.
-template <int DEPTH, int K, bool ARC>
+template <int DEPTH, int K, bool ARC, bool LAYERED = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(ping_waves_per_eu<K, ARC>())))
 void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
                                                       uint32_t *__restrict__ queue, unsigned long long *__restrict__ t0,
@@ -1649,7 +1649,7 @@ void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
             }
             const PingArgs &a = desc[lo];
             unsigned long long start = __builtin_amdgcn_s_memrealtime();
-            ping_tile<DEPTH, K, ARC, false>(a, gt - a.tile_offset, W);
+            ping_tile<DEPTH, K, ARC, false, LAYERED>(a, gt - a.tile_offset, W);
             __syncthreads();
             if (threadIdx.x == 0) {
                 unsigned long long end = __builtin_amdgcn_s_memrealtime();
@@ -1811,14 +1811,14 @@ hipError_t launch_ping_layered(const PingArgs &a, int stack_depth, hipStream_t s
     return hipGetLastError();
 }
 
-template <int D, int KK, bool AR>
+template <int D, int KK, bool AR, bool LAY = false>
 static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int *occ)
 {
     const int ww = ping_wave_words(D, b.max_bins, KK);
     const size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
     if (query) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR>),
-                                                            BLOCK, shmem);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            occ, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY>), BLOCK, shmem);
     }
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1827,8 +1827,8 @@ static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int 
     int per_cu = b.blocks_per_cu;
     if (per_cu <= 0) {
         int o = 1;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR>),
-                                                         BLOCK, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &o, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY>), BLOCK, shmem);
         if (e != hipSuccess) return e;
         per_cu = o > 0 ? o : 1;
     }
@@ -1839,7 +1839,7 @@ static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int 
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_batch_reset, dim3((b.n_pings + 255) / 256), dim3(256), 0, s, b.queue, b.t0, b.t1,
                        b.n_pings);
-    hipLaunchKernelGGL((k_ping_batch<D, KK, AR>), dim3((unsigned)grid), dim3(BLOCK), shmem, s, b.desc, b.n_pings,
+    hipLaunchKernelGGL((k_ping_batch<D, KK, AR, LAY>), dim3((unsigned)grid), dim3(BLOCK), shmem, s, b.desc, b.n_pings,
                        b.queue, b.t0, b.t1, ww, tpi);
     return hipGetLastError();
 }
@@ -1852,6 +1852,15 @@ static hipError_t batch_dispatch(const BatchLaunch &b, hipStream_t s, bool query
         case 2: return batch_go<D, 2, AR>(b, s, query, occ);      \
         case 3: return batch_go<D, 3, AR>(b, s, query, occ);      \
         default: return batch_go<D, 4, AR>(b, s, query, occ);     \
+    }
+    if (b.layered) {
+        // a batch through one layered profile: the deep-stack instantiations
+        switch (b.K) {
+            case 1: return batch_go<64, 1, true, true>(b, s, query, occ);
+            case 2: return batch_go<64, 2, true, true>(b, s, query, occ);
+            case 3: return batch_go<64, 3, true, true>(b, s, query, occ);
+            default: return batch_go<64, 4, true, true>(b, s, query, occ);
+        }
     }
     if (b.depth <= 32) {
         if (b.arc) { SONAR_BK(32, true) } else { SONAR_BK(32, false) }

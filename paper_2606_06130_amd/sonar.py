@@ -39,7 +39,7 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
            "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb",
-           "sonar_ping_ssp", "sonar_ping_ssp_rx")
+           "sonar_ping_ssp", "sonar_ping_ssp_rx", "sonar_batch_prepare_ssp")
 
 
 class SonarError(RuntimeError):
@@ -156,6 +156,9 @@ def lib():
         L.sonar_batch_prepare.restype = C.c_int
         L.sonar_batch_prepare.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                           P(sonar_batch_plan)]
+        L.sonar_batch_prepare_ssp.restype = C.c_int
+        L.sonar_batch_prepare_ssp.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, P(sonar_ssp), C.c_void_p,
+                                              C.c_void_p, P(sonar_batch_plan)]
         L.sonar_ping_batch.restype = C.c_int
         L.sonar_ping_batch.argtypes = [C.c_void_p, P(sonar_batch_plan), C.c_void_p, P(sonar_batch_options),
                                        C.c_void_p, C.c_size_t, C.c_void_p]
@@ -532,8 +535,10 @@ class Batch:
     def __init__(self, scene: Scene, items):
         import torch
         n = len(items)
-        if any(getattr(cfg, "ssp", ()) for cfg, _ in items):
-            raise SonarError(SONAR_E_UNSUPPORTED, "batches take the linear sound-speed profile only")
+        profiles = {tuple(getattr(cfg, "ssp", ()) or ()) for cfg, _ in items}
+        if len(profiles) > 1:
+            raise SonarError(SONAR_E_INVALID, "the pings of a batch share one sound-speed profile")
+        knots = profiles.pop()
         self.scene = scene
         self.items = items
         self.volumes = [alloc_outputs(cfg)["volume"] for cfg, _ in items]
@@ -543,7 +548,12 @@ class Batch:
         db = lib().sonar_batch_desc_bytes()
         host = np.zeros(n * db, np.uint8)
         self.plan = sonar_batch_plan()
-        _check(lib().sonar_batch_prepare(scene.handle, n, P, Q, V, host.ctypes.data, C.byref(self.plan)))
+        if knots:
+            prof = ssp_of(knots)
+            _check(lib().sonar_batch_prepare_ssp(scene.handle, n, P, Q, C.byref(prof), V, host.ctypes.data,
+                                                 C.byref(self.plan)))
+        else:
+            _check(lib().sonar_batch_prepare(scene.handle, n, P, Q, V, host.ctypes.data, C.byref(self.plan)))
         self._host, self._P, self._Q = host, P, Q
         self.desc = torch.from_numpy(host).cuda()
         self.workspace = torch.empty(lib().sonar_batch_workspace_size(n), dtype=torch.uint8, device="cuda")

@@ -155,4 +155,26 @@ def test_layered_profile_rejections():
     with pytest.raises(sonar.SonarError):
         sonar.Detector(cfg).ping_detect(sc, sonar.alloc_outputs(cfg)["volume"], pose)
     with pytest.raises(sonar.SonarError):
-        sonar.Batch(sc, [(cfg, pose)])
+        sonar.Batch(sc, [(cfg, pose), (cfg.replace(ssp=KNOTS_MP), pose)])     # one profile per batch
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_layered_batch_equals_single_pings(K):
+    """A batch through one layered profile (mixed layouts and poses, one
+    persistent launch) writes the same volumes, bit for bit, as single pings."""
+    torch, sonar = _gpu()
+    sc = sonar.Scene(_surface_wall())
+    base = S.SensorConfig(n_range=1024, max_bounces=K, k_d=0.7, k_s=0.3, vfov=math.radians(60), ssp=KNOTS_CHANNEL)
+    items = [(base.replace(n_h=nh, n_v=nv, rays_per_beam=nr),
+              S.pose((0.3 * i, -0.2 * i, -0.5 * i), pitch_down=math.radians(-10 + 3 * i), ping=i))
+             for i, (nh, nv, nr) in enumerate([(32, 16, 4), (16, 8, 16), (33, 7, 1), (64, 32, 4)])]
+    b = sonar.Batch(sc, items)
+    assert b.plan.arc == 2
+    b.run()
+    torch.cuda.synchronize()
+    assert sc.status() == 0
+    for i, (cfg, pose) in enumerate(items):
+        ref = sonar.ping(sc, cfg, pose)["volume"]
+        torch.cuda.synchronize()
+        assert torch.equal(b.volumes[i].view(torch.float32), ref.view(torch.float32)), i
+        assert torch.count_nonzero(ref).item() > 0

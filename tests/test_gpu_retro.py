@@ -119,3 +119,16 @@ def test_retro_chain_rejections():
     sonar.ping(sc, _cfg(max_bounces=1), POSE)                 # one bounce: nothing to retrace
     torch.cuda.synchronize()
     assert sc.status() == 0
+
+
+def test_harbor_multipath_retro_chain_full_size_sampled_beams():
+    """The harbor multipath ping (1,991,680 triangles, 3 bounces, 256 x 128
+    beams x 16 rays) with retro-chain returns, as one launch of the
+    benchmark's configuration; 40 beams compared ray by ray."""
+    mesh = S.scene_harbor_multipath()
+    cfg, pose = S.sensor_harbor_multipath().replace(flags=RETRO), S.pose_harbor()
+    rng = np.random.Generator(np.random.PCG64(45))
+    beams = np.sort(rng.choice(cfg.n_beams, 40, replace=False))
+    res, out, orc = run_parity(mesh, cfg, pose, beams=beams)
+    assert_parity(res, 3)
+    assert res["retro_returns"] > 50
