@@ -11,7 +11,7 @@ residual, aligned to each beam's first-hit bin, compressed to 64 DCT
 coefficients and standardised, is the target.
 
     python -m paper_2606_06130_amd.surrogate --train-pings 2000 --epochs 3 \\
-        --eval-pings 200 --out gpurun_out/surrogate
+        --eval-pings 200 --out surrogate_run
 """
 from __future__ import annotations
 
@@ -167,7 +167,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--stats-pings", type=int, default=64)
-    ap.add_argument("--out", default="gpurun_out/surrogate")
+    ap.add_argument("--out", default="surrogate_run")
     ap.add_argument("--resume", default=None)
     args = ap.parse_args(argv)
     import torch
