@@ -1352,12 +1352,12 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
     }
     const int rx = (P->flags & ORC_RX_BEAMS) != 0;
     if ((P->flags & ORC_RETRO_CHAIN) && rx && (!rec_rbin || !rec_ramp)) return -4;
-    if (rx) {
-        /* contributions move between beams: every beam, in order */
-        if (n_beams != (int64_t)P->n_h * P->n_v) return -2;
-        for (int64_t q = 0; q < n_beams; ++q)
-            if (beams[q] != q) return -2;
-    }
+    /* receive binning moves contributions between beams: the columns need
+     * every beam, in order; for a subset of beams only the records are
+     * filled (columns zero) */
+    int rx_all = rx && n_beams == (int64_t)P->n_h * P->n_v;
+    for (int64_t q = 0; rx_all && q < n_beams; ++q)
+        if (beams[q] != q) rx_all = 0;
     const double dh = P->hfov / P->n_h, dv = P->vfov / P->n_v;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -1445,6 +1445,7 @@ int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_
             if (col_all) memset(col_all + (size_t)q * NB * 2, 0, sizeof(double) * NB * 2);
             if (incoh) memset(incoh + (size_t)q * 2 * NB, 0, sizeof(double) * NB * 2);
         }
+        if (!rx_all) return 0;
         for (size_t ri = 0; ri < (size_t)n_beams * NR; ++ri) {
             for (int k = 0; k < K; ++k) {
                 const size_t e = ri * K + k;

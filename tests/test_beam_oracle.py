@@ -135,10 +135,16 @@ def test_receive_binning_only_moves_contributions(K):
     assert moved.sum() > 0
 
 
-def test_beam_options_need_cell_beams_and_all_beams():
+def test_beam_options_need_cell_beams_and_subsets_give_records_only():
     sc = _surface_wall()
     cfg = _cfg(max_bounces=2, k_s=0.3)
-    with pytest.raises(ValueError):
-        oracle.trace_beams(sc, cfg.replace(flags=oracle.RX_BEAMS), LEVEL, np.arange(5))
+    # receive binning over a subset of beams: the records (the same as in a
+    # run over every beam), no columns
+    full = oracle.trace_beams(sc, cfg.replace(flags=oracle.RX_BEAMS), LEVEL, np.arange(cfg.n_beams))
+    sub = oracle.trace_beams(sc, cfg.replace(flags=oracle.RX_BEAMS), LEVEL, np.arange(5, 9))
+    rays = slice(5 * cfg.rays_per_beam, 9 * cfg.rays_per_beam)
+    for key in ("tri", "bin", "vis", "rxb", "amp", "flags"):
+        assert np.array_equal(sub[key], full[key][rays]), key
+    assert not sub["col"].any()
     with pytest.raises(ValueError):
         oracle.trace_beams(sc, cfg.replace(flags=oracle.BEAM_PATTERN, grid_mode=1), LEVEL, np.arange(4))

@@ -93,3 +93,35 @@ def test_receive_binning_rejections():
     ref = sonar.ping(sc, cfg.replace(flags=PATTERN), pose)["volume"]
     torch.cuda.synchronize()
     assert torch.equal(b.volumes[0].view(torch.float32), ref.view(torch.float32))
+
+
+def test_harbor_multipath_pattern_and_receive_binning_full_size_records():
+    """The benchmark's multipath ping with beam pattern and receive binning
+    (1,991,680 triangles, 256 x 128 beams x 16 rays, 3 bounces) as one
+    launch; 40 sampled beams compared ray by ray (hit, bin, visibility,
+    receive beam, weighted contribution). Moved returns land in other beams'
+    columns, so columns are not compared here."""
+    import oracle
+    from tests.parity import compare_rays, ray_ids, rel_l2
+    torch, sonar = _gpu()
+    mesh = S.scene_harbor_multipath()
+    cfg, pose = S.sensor_harbor_multipath().replace(flags=PATTERN | RX), S.pose_harbor()
+    rng = np.random.Generator(np.random.PCG64(46))
+    beams = np.sort(rng.choice(cfg.n_beams, 40, replace=False))
+    orc = oracle.trace_beams(oracle.Scene(mesh), cfg, pose, beams)
+    sc = sonar.Scene(mesh)
+    out = sonar.ping(sc, cfg, pose, record=True)
+    torch.cuda.synchronize()
+    assert sc.status() == 0
+    g = {k: v.cpu().numpy() for k, v in out.items() if k != "rx_workspace"}
+    rays = ray_ids(beams, cfg.rays_per_beam)
+    res = compare_rays(g, orc, rays)
+    ok = orc["flags"] == 0
+    res["contrib_err"] = rel_l2(g["amp"][rays][ok], orc["amp"][ok])
+    _log("harbor multipath pattern+rx", res)
+    for key in ("tri_mismatch", "bin_mismatch", "vis_mismatch", "beam_mismatch"):
+        assert res[key] == 0, res
+    assert res["contrib_err"] <= 1e-4, res
+    assert res["flagged"] <= 0.05 * res["rays"], res
+    launch = np.repeat(beams, cfg.rays_per_beam)[:, None]
+    assert ((orc["rxb"][:, 1:] != launch) & (orc["bin"][:, 1:] >= 0) & ok[:, None]).sum() > 10
