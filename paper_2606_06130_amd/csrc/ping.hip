@@ -78,6 +78,7 @@ __device__ __forceinline__ void wave_sync()
 // Scene arrays as global-memory pointers: a pointer read from a batch
 // descriptor is otherwise generic and its loads become flat loads.
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 using gchar = __attribute__((address_space(1))) const char;
 __device__ __forceinline__ gchar *as_global(const float4 *p) { return (gchar *)p; }
 __device__ __forceinline__ float4 ldg4(gchar *p)
@@ -1553,7 +1554,9 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         if (j == 0 && active) a.det_count[gb] = cnt;
     }
 
-    // ---- column write: one beam at a time through the LDS column index
+    // ---- column write: one beam at a time through the LDS column index, with
+    // non-temporal stores (the volume streams out; caching it would evict the
+    // hierarchy that the other waves are still traversing)
     const int idx_words = (nb + 1) / 2;
     for (int q = 0; q < bpw; ++q) {
         const int64_t gb = wave_beam0 + q;
@@ -1575,20 +1578,20 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
                 uint32_t s0 = pair & 0xFFFFu, s1 = pair >> 16;
                 float4 v0 = s0 ? sval[s0 - 1] : make_float4(0.f, 0.f, 0.f, 0.f);
                 float4 v1 = s1 ? sval[s1 - 1] : make_float4(0.f, 0.f, 0.f, 0.f);
-                reinterpret_cast<float4 *>(col)[w] = make_float4(v0.x, v0.y, v1.x, v1.y);
+                __builtin_nontemporal_store(f4v{v0.x, v0.y, v1.x, v1.y}, reinterpret_cast<f4v *>(col) + w);
                 if (i1) {
-                    reinterpret_cast<float2 *>(i1)[w] = make_float2(v0.z, v1.z);
-                    reinterpret_cast<float2 *>(im)[w] = make_float2(v0.w, v1.w);
+                    __builtin_nontemporal_store(f2v{v0.z, v1.z}, reinterpret_cast<f2v *>(i1) + w);
+                    __builtin_nontemporal_store(f2v{v0.w, v1.w}, reinterpret_cast<f2v *>(im) + w);
                 }
             }
         } else {
             for (int b = lane; b < nb; b += WAVE) {
                 uint32_t s0 = sidx[b];
                 float4 v0 = s0 ? sval[s0 - 1] : make_float4(0.f, 0.f, 0.f, 0.f);
-                col[b] = make_float2(v0.x, v0.y);
+                __builtin_nontemporal_store(f2v{v0.x, v0.y}, reinterpret_cast<f2v *>(col) + b);
                 if (i1) {
-                    i1[b] = v0.z;
-                    im[b] = v0.w;
+                    __builtin_nontemporal_store(v0.z, i1 + b);
+                    __builtin_nontemporal_store(v0.w, im + b);
                 }
             }
         }

@@ -34,11 +34,10 @@ __global__ __launch_bounds__(256) void k_reverb(ReverbArgs a)
     float sn, cs;
     sincospif(2.f * u2, &sn, &cs);
     const float amp = sqrtf(0.5f * P) * sqrtf(-2.f * logf(u1));
-    float2 &cell = a.volume[b * a.n_bins + n];
-    float2 e = cell;
-    e.x = fmaf(amp, cs, e.x);
-    e.y = fmaf(amp, sn, e.y);
-    cell = e;
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    f2v *cell = reinterpret_cast<f2v *>(a.volume) + b * a.n_bins + n;
+    const f2v e = *cell;
+    __builtin_nontemporal_store(f2v{fmaf(amp, cs, e.x), fmaf(amp, sn, e.y)}, cell);     // streamed back out
 }
 
 }  // namespace
