@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
                 const float p1 = db10(iv[rl][q] + I_FLOOR);
                 const float res = b >= r1 ? Q[rl * pitch + (b - r1)] : 0.f;
                 const float ph = p1 + res;
-                if (profile) profile[row * nb + b] = ph;
+                if (profile) __builtin_nontemporal_store(ph, profile + row * nb + b);      // streamed out
                 if (im) {
                     const float tr = db10(iv[rl][q] + mv[h][q] + I_FLOOR);
                     if (tr > occ_db) {
