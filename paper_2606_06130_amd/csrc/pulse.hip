@@ -40,6 +40,25 @@ __device__ __forceinline__ void cmac_conj(float2 &acc, const float2 p, const flo
     acc.y = fmaf(-p.y, v.x, acc.y);
 }
 
+// A staged row from LDS to its output: consecutive lanes take consecutive
+// pairs of samples (one 16-byte store each when the row starts 16-byte
+// aligned), with non-temporal stores, since nothing here reads them again.
+__device__ __forceinline__ void stream_out(const float2 *__restrict__ src, float2 *__restrict__ dst, int N, int t,
+                                           int T)
+{
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        for (int i = t; i < N / 2; i += T)
+            __builtin_nontemporal_store(f4v{src[2 * i].x, src[2 * i].y, src[2 * i + 1].x, src[2 * i + 1].y},
+                                        reinterpret_cast<f4v *>(dst) + i);
+        if ((N & 1) && t == 0) __builtin_nontemporal_store(f2v{src[N - 1].x, src[N - 1].y}, reinterpret_cast<f2v *>(dst) + N - 1);
+    } else {
+        for (int i = t; i < N; i += T)
+            __builtin_nontemporal_store(f2v{src[i].x, src[i].y}, reinterpret_cast<f2v *>(dst) + i);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_pulse(PulseArgs a)
 {
     extern __shared__ float2 lds_c[];
@@ -74,15 +93,12 @@ __global__ __launch_bounds__(256) void k_pulse(PulseArgs a)
         }
         const float2 c[4] = {c0, c1, c2, c3};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (n0 + j < N) {
-                sl[n0 + j] = c[j];
-                if (a.s) a.s[base + n0 + j] = c[j];
-            }
-        }
+        for (int j = 0; j < 4; ++j)
+            if (n0 + j < N) sl[n0 + j] = c[j];
     }
-    if (!a.y) return;
     __syncthreads();
+    if (a.s) stream_out(sl, a.s + base, N, t, T);
+    if (!a.y) return;
 
     for (int n0 = 4 * t; n0 < N; n0 += 4 * T) {
         // window w_j = s[n0 + j + k], starting at k = 0
@@ -102,8 +118,10 @@ __global__ __launch_bounds__(256) void k_pulse(PulseArgs a)
         const float2 c[4] = {c0, c1, c2, c3};
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (n0 + j < N) a.y[base + n0 + j] = c[j];
+            if (n0 + j < N) xl[n0 + j] = c[j];          // the input is no longer needed
     }
+    __syncthreads();
+    stream_out(xl, a.y + base, N, t, T);
 }
 
 }  // namespace
