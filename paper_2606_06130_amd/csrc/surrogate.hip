@@ -295,7 +295,7 @@ __global__ __launch_bounds__(64) void k_smooth(const float *__restrict__ i1, con
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll 8
-        for (int b = lane; b < nb; b += 64) dst[b] = out[spad(b)];
+        for (int b = lane; b < nb; b += 64) __builtin_nontemporal_store(out[spad(b)], dst + b);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
