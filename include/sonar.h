@@ -150,8 +150,8 @@ typedef struct {
  *                     it arrives along the launch ray (launch beam, transmit
  *                     pattern squared) and counts as a later bounce in the
  *                     incoherent channel. No effect with max_bounces 1;
- *                     batches reject it, and so does n_range above 3328
- *                     (3 bounces) or 3584 (4 bounces). */
+ *                     rejected for n_range above 3328 (3 bounces) or 3584
+ *                     (4 bounces); the pings of a batch take it all or none. */
 #define SONAR_FLAG_BEAM_PATTERN 1u
 #define SONAR_FLAG_RX_BEAMS 2u
 #define SONAR_FLAG_DIFFUSE_BOUNCE 4u
@@ -406,9 +406,10 @@ sonar_status sonar_pulse_compress(const sonar_cf32 *volume, int64_t n_beams, int
  * not, or one layered profile). */
 
 /* Host summary of a prepared batch (filled by sonar_batch_prepare): `arc`
- * is the medium type, 0 straight rays, 1 one gradient, 2 a layered profile. */
+ * is the medium type, 0 straight rays, 1 one gradient, 2 a layered profile;
+ * `retro` is 1 when the pings take retro-chain returns. */
 typedef struct {
-    int32_t n_pings, max_bounces, arc, max_bins, max_beams, reserved;
+    int32_t n_pings, max_bounces, arc, max_bins, max_beams, retro;
     int64_t total_tiles, total_rays;
 } sonar_batch_plan;
 

@@ -787,8 +787,8 @@ static sonar_status batch_prepare(const sonar_scene *sc, int32_t n, const sonar_
     for (int32_t i = 0; i < n; ++i) {
         if (needs_rx_list(&params[i]))
             return fail(SONAR_E_UNSUPPORTED, "ping %d: batches do not take receive binning with several bounces", i);
-        if ((params[i].flags & SONAR_FLAG_RETRO_CHAIN) && params[i].max_bounces > 1)
-            return fail(SONAR_E_UNSUPPORTED, "ping %d: batches do not take retro-chain returns", i);
+        if ((params[i].flags & SONAR_FLAG_RETRO_CHAIN) != (params[0].flags & SONAR_FLAG_RETRO_CHAIN))
+            return fail(SONAR_E_INVALID, "ping %d: the pings of a batch all take retro-chain returns or none", i);
         sonar_status st = ssp ? layered_args(sc, &params[i], &poses[i], ssp, volumes[i], nullptr, nullptr, nullptr,
                                              nullptr, &d[i])
                               : fill_ping_args(sc, &params[i], &poses[i], volumes[i], nullptr, nullptr, nullptr,
@@ -815,7 +815,7 @@ static sonar_status batch_prepare(const sonar_scene *sc, int32_t n, const sonar_
     plan->arc = ssp ? 2 : (params[0].c_grad != 0.0 ? 1 : 0);
     plan->max_bins = max_bins;
     plan->max_beams = max_beams;
-    plan->reserved = 0;
+    plan->retro = (params[0].flags & SONAR_FLAG_RETRO_CHAIN) && params[0].max_bounces > 1;
     plan->total_tiles = tiles;
     plan->total_rays = rays;
     return SONAR_OK;
@@ -856,6 +856,7 @@ static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_p
     b->K = plan->max_bounces;
     b->arc = plan->arc != 0;
     b->layered = plan->arc == 2;
+    b->retro = plan->retro != 0;
     b->depth = sc->s.stack;
     b->max_bins = plan->max_bins;
     b->total_tiles = plan->total_tiles;
@@ -963,8 +964,8 @@ static std::string tune_key(const sonar_scene *sc, const sonar_batch_plan *plan)
             if (*c == ' ' || *c == ':') *c = '_';
     }
     char key[320];
-    snprintf(key, sizeof(key), "%s/tri%lld/d%d/p%d/k%d/a%d/b%d/t%lld", name, (long long)sc->s.n_tri, sc->s.depth,
-             plan->n_pings, plan->max_bounces, plan->arc, plan->max_bins, (long long)plan->total_tiles);
+    snprintf(key, sizeof(key), "%s/tri%lld/d%d/p%d/k%d/a%d/r%d/b%d/t%lld", name, (long long)sc->s.n_tri, sc->s.depth,
+             plan->n_pings, plan->max_bounces, plan->arc, plan->retro, plan->max_bins, (long long)plan->total_tiles);
     return key;
 }
 

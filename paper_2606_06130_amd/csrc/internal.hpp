@@ -126,6 +126,7 @@ struct BatchLaunch {
     int K;
     bool arc;
     bool layered;            // every ping through its layered profile (descriptors carry it)
+    bool retro;              // every ping with retro-chain returns
     int depth;               // hierarchy depth (selects the stack size)
     int max_bins;            // largest n_range of the batch (LDS sizing)
     int64_t total_tiles;

@@ -1621,7 +1621,7 @@ void k_ping(PingArgs a, int wave_words)
 // the hierarchy depth class, bounce count and medium type (template
 // arguments); layouts, rays per beam, poses and outputs come per ping from
 // its descriptor.
-template <int DEPTH, int K, bool ARC, bool LAYERED = false>
+template <int DEPTH, int K, bool ARC, bool LAYERED = false, bool RETRO = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(ping_waves_per_eu<K, ARC>())))
 void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
                                                       uint32_t *__restrict__ queue, unsigned long long *__restrict__ t0,
@@ -1652,7 +1652,7 @@ void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
             }
             const PingArgs &a = desc[lo];
             unsigned long long start = __builtin_amdgcn_s_memrealtime();
-            ping_tile<DEPTH, K, ARC, false, LAYERED>(a, gt - a.tile_offset, W);
+            ping_tile<DEPTH, K, ARC, false, LAYERED, RETRO>(a, gt - a.tile_offset, W);
             __syncthreads();
             if (threadIdx.x == 0) {
                 unsigned long long end = __builtin_amdgcn_s_memrealtime();
@@ -1814,14 +1814,14 @@ hipError_t launch_ping_layered(const PingArgs &a, int stack_depth, hipStream_t s
     return hipGetLastError();
 }
 
-template <int D, int KK, bool AR, bool LAY = false>
+template <int D, int KK, bool AR, bool LAY = false, bool RET = false>
 static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int *occ)
 {
-    const int ww = ping_wave_words(D, b.max_bins, KK);
+    const int ww = ping_wave_words(D, b.max_bins, KK, RET);
     const size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
     if (query) {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occ, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY>), BLOCK, shmem);
+            occ, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY, RET>), BLOCK, shmem);
     }
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1831,7 +1831,7 @@ static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int 
     if (per_cu <= 0) {
         int o = 1;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &o, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY>), BLOCK, shmem);
+            &o, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY, RET>), BLOCK, shmem);
         if (e != hipSuccess) return e;
         per_cu = o > 0 ? o : 1;
     }
@@ -1842,7 +1842,7 @@ static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int 
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_batch_reset, dim3((b.n_pings + 255) / 256), dim3(256), 0, s, b.queue, b.t0, b.t1,
                        b.n_pings);
-    hipLaunchKernelGGL((k_ping_batch<D, KK, AR, LAY>), dim3((unsigned)grid), dim3(BLOCK), shmem, s, b.desc, b.n_pings,
+    hipLaunchKernelGGL((k_ping_batch<D, KK, AR, LAY, RET>), dim3((unsigned)grid), dim3(BLOCK), shmem, s, b.desc, b.n_pings,
                        b.queue, b.t0, b.t1, ww, tpi);
     return hipGetLastError();
 }
@@ -1855,6 +1855,24 @@ static hipError_t batch_dispatch(const BatchLaunch &b, hipStream_t s, bool query
         case 2: return batch_go<D, 2, AR>(b, s, query, occ);      \
         case 3: return batch_go<D, 3, AR>(b, s, query, occ);      \
         default: return batch_go<D, 4, AR>(b, s, query, occ);     \
+    }
+    if (b.retro && b.K > 1) {
+        // retro-chain returns: their own instantiations (deep stack, 2K - 1 slots)
+        if (b.layered) {
+            switch (b.K) {
+                case 2: return batch_go<64, 2, true, true, true>(b, s, query, occ);
+                case 3: return batch_go<64, 3, true, true, true>(b, s, query, occ);
+                default: return batch_go<64, 4, true, true, true>(b, s, query, occ);
+            }
+        }
+        switch (b.K) {
+            case 2: return b.arc ? batch_go<64, 2, true, false, true>(b, s, query, occ)
+                                 : batch_go<64, 2, false, false, true>(b, s, query, occ);
+            case 3: return b.arc ? batch_go<64, 3, true, false, true>(b, s, query, occ)
+                                 : batch_go<64, 3, false, false, true>(b, s, query, occ);
+            default: return b.arc ? batch_go<64, 4, true, false, true>(b, s, query, occ)
+                                  : batch_go<64, 4, false, false, true>(b, s, query, occ);
+        }
     }
     if (b.layered) {
         // a batch through one layered profile: the deep-stack instantiations

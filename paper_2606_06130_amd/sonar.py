@@ -105,7 +105,7 @@ class sonar_reverb(C.Structure):
 
 class sonar_batch_plan(C.Structure):
     _fields_ = [("n_pings", C.c_int32), ("max_bounces", C.c_int32), ("arc", C.c_int32), ("max_bins", C.c_int32),
-                ("max_beams", C.c_int32), ("reserved", C.c_int32), ("total_tiles", C.c_int64),
+                ("max_beams", C.c_int32), ("retro", C.c_int32), ("total_tiles", C.c_int64),
                 ("total_rays", C.c_int64)]
 
 

@@ -105,8 +105,8 @@ def test_retro_chain_rejections():
     torch, sonar = _gpu()
     sc = sonar.Scene(_surface_wall())
     with pytest.raises(sonar.SonarError) as e:
-        sonar.Batch(sc, [(_cfg(), POSE)])
-    assert e.value.status == sonar.SONAR_E_UNSUPPORTED
+        sonar.Batch(sc, [(_cfg(), POSE), (_cfg(flags=0), POSE)])          # all pings or none
+    assert e.value.status == sonar.SONAR_E_INVALID
     with pytest.raises(sonar.SonarError) as e:
         sonar.ping(sc, _cfg(), POSE, record=True, stats=True)
     assert e.value.status == sonar.SONAR_E_UNSUPPORTED
@@ -132,3 +132,24 @@ def test_harbor_multipath_retro_chain_full_size_sampled_beams():
     res, out, orc = run_parity(mesh, cfg, pose, beams=beams)
     assert_parity(res, 3)
     assert res["retro_returns"] > 50
+
+
+@pytest.mark.parametrize("K,g,layered", [(2, 0.0, False), (3, 0.05, False), (4, 0.0, False), (3, 0.0, True)])
+def test_retro_chain_batch_equals_single_pings(K, g, layered):
+    """A batch with retro-chain returns (mixed layouts and poses, one
+    persistent launch) writes the same volumes, bit for bit, as single pings."""
+    torch, sonar = _gpu()
+    sc = sonar.Scene(_surface_wall())
+    base = _cfg(max_bounces=K, c_grad=g, ssp=KNOTS if layered else ())
+    items = [(base.replace(n_h=nh, n_v=nv, rays_per_beam=nr),
+              S.pose((0.3 * i, -0.2 * i, -0.5 * i), pitch_down=math.radians(-10 + 3 * i), ping=i))
+             for i, (nh, nv, nr) in enumerate([(32, 16, 4), (16, 8, 16), (33, 7, 1), (64, 32, 4)])]
+    b = sonar.Batch(sc, items)
+    assert b.plan.retro == 1
+    b.run()
+    torch.cuda.synchronize()
+    assert sc.status() == 0
+    for i, (cfg, pose) in enumerate(items):
+        ref = sonar.ping(sc, cfg, pose)["volume"]
+        torch.cuda.synchronize()
+        assert torch.equal(b.volumes[i].view(torch.float32), ref.view(torch.float32)), i
