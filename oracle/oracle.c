@@ -919,10 +919,14 @@ static oeig eigenray_layered(const orc_params *P, v3 Pp, v3 Sp, double H, const 
                 if (last) zq = b;
                 if (dir * (zq - zp) <= 0.0) continue;       /* a grid point not past the interval start */
                 const int negq = eig_f(P, fam, zq, zlo, zhi, D) <= 0.0;
-                if (negq != negp && nr < EIG_MAXROOTS) {
-                    const double zt = eig_bisect(P, fam, zp, zq, zlo, zhi, D);
-                    const oref R = ref_of(P, zt, 0.0);
-                    roots[nr++] = (oroot){fam, zt, 0.0, eig_run(P, fam, &R, zlo, zhi).T};
+                if (negq != negp) {
+                    if (nr == EIG_MAXROOTS) {
+                        e.flags |= F_CAUSTIC;       /* more roots than kept: not compared */
+                    } else {
+                        const double zt = eig_bisect(P, fam, zp, zq, zlo, zhi, D);
+                        const oref R = ref_of(P, zt, 0.0);
+                        roots[nr++] = (oroot){fam, zt, 0.0, eig_run(P, fam, &R, zlo, zhi).T};
+                    }
                 }
                 if (last) break;
                 zp = zq;
