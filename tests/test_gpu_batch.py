@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 def _gpu():
     import torch
     if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+        pytest.fail("a GPU test ran without a visible GPU (it must not pass by skipping)")
     from paper_2606_06130_amd import sonar
     return torch, sonar
 

@@ -18,7 +18,7 @@ VOL_TOL = 1e-4          # relative L2 of the echo volume, flagged rays masked on
 def _gpu():
     import torch
     if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+        pytest.fail("a GPU test ran without a visible GPU (it must not pass by skipping)")
     from paper_2606_06130_amd import sonar
     return torch, sonar
 

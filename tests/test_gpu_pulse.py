@@ -17,7 +17,7 @@ TOL = 1e-5          # relative L2 per output: FP32 sums of at most 2 x 64 produc
 def _gpu():
     import torch
     if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+        pytest.fail("a GPU test ran without a visible GPU (it must not pass by skipping)")
     from paper_2606_06130_amd import sonar
     return torch, sonar
 

@@ -17,7 +17,7 @@ TOL = 1e-5          # relative L2: FP32 power law and Box-Muller against FP64
 def _gpu():
     import torch
     if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+        pytest.fail("a GPU test ran without a visible GPU (it must not pass by skipping)")
     from paper_2606_06130_amd import sonar
     return torch, sonar
 
