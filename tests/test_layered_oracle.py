@@ -261,3 +261,26 @@ def test_multibounce_equal_speeds_equal_straight_rays():
     lay = base.replace(ssp=((-8.0, 1500.0), (-4.0, 1500.0), (-1.0, 1500.0)))
     beams = np.arange(lay.n_beams)
     _compare(oracle.trace_beams(sc, lay, pose, beams), oracle.trace_beams(sc, base, pose, beams), 1e-10)
+
+
+def test_eigenray_degenerate_geometries():
+    """Closed forms: a vertical connection (no horizontal offset) takes the
+    time integral of dz / c through each layer; two points at one depth in a
+    constant-speed layer are joined by the level segment; a vertical pair
+    across a speed maximum is still joined (a vertical ray never turns)."""
+    knots = ((-10.0, 1490.0), (-4.0, 1496.0), (-2.0, 1496.0), (1.0, 1499.0))
+    cfg = S.SensorConfig(r_max=30.0, ssp=knots)
+    p, s = np.array([1.0, 2.0, -8.0]), np.array([1.0, 2.0, 0.5])
+    e = oracle.eigenray(cfg, p, s)
+    # layers: g = 1 on [-10, -4], constant 1496 on [-4, -2], g = 1 on [-2, 1]
+    want_T = math.log(1496.0 / 1492.0) + 2.0 / 1496.0 + math.log(1498.5 / 1496.0)
+    assert e["ok"] and e["fam"] == 0 and abs(e["L"] - 8.5) < 1e-12 and abs(e["T"] - want_T) < 1e-15
+    assert np.allclose(e["w_out"], (0, 0, 1), atol=1e-15) and np.allclose(e["arrive"], (0, 0, 1), atol=1e-15)
+    p, s = np.array([0.0, 0.0, -3.0]), np.array([12.0, 5.0, -3.0])
+    e = oracle.eigenray(cfg, p, s)
+    assert e["ok"] and abs(e["L"] - 13.0) < 1e-12 and abs(e["T"] - 13.0 / 1496.0) < 1e-15
+    assert np.allclose(e["w_out"], (12 / 13, 5 / 13, 0), atol=1e-15)
+    peak = ((-20.0, 1450.0), (-10.0, 1500.0), (0.0, 1450.0))
+    e = oracle.eigenray(S.SensorConfig(r_max=30.0, ssp=peak), (0.0, 0.0, -15.0), (0.0, 0.0, -5.0))
+    assert e["ok"] and abs(e["L"] - 10.0) < 1e-12
+    assert abs(e["T"] - 2.0 * math.log(1500.0 / 1475.0) / 5.0) < 1e-15
