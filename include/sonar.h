@@ -123,8 +123,8 @@ typedef struct {
  *                     whose cell holds its arrival direction instead of the
  *                     launch beam (bounce-1 returns arrive along the reversed
  *                     launch ray); with max_bounces > 1 it needs the
- *                     workspace of sonar_ping_rx or sonar_ping_detect, and
- *                     batches reject it
+ *                     workspace of sonar_ping_rx or sonar_ping_detect (in
+ *                     batches: sonar_batch_prepare_rx)
  *                     Both options need cell-centred beams (grid_mode 0).
  *     SONAR_FLAG_DIFFUSE_BOUNCE  stochastic scattering (Sec. II-B: speckle,
  *                     reverberation): the continuation after a rough facet is
@@ -407,9 +407,10 @@ sonar_status sonar_pulse_compress(const sonar_cf32 *volume, int64_t n_beams, int
 
 /* Host summary of a prepared batch (filled by sonar_batch_prepare): `arc`
  * is the medium type, 0 straight rays, 1 one gradient, 2 a layered profile;
- * `retro` is 1 when the pings take retro-chain returns. */
+ * `retro` is 1 when the pings take retro-chain returns, `rx` the number of
+ * pings with receive-binning lists. */
 typedef struct {
-    int32_t n_pings, max_bounces, arc, max_bins, max_beams, retro;
+    int32_t n_pings, max_bounces, arc, max_bins, max_beams, retro, rx;
     int64_t total_tiles, total_rays;
 } sonar_batch_plan;
 
@@ -448,6 +449,24 @@ sonar_status sonar_batch_prepare(const sonar_scene *scene, int32_t n_pings, cons
 sonar_status sonar_batch_prepare_ssp(const sonar_scene *scene, int32_t n_pings, const sonar_params *params,
                                      const sonar_pose *poses, const sonar_ssp *ssp, sonar_cf32 *const *volumes,
                                      void *host_desc, sonar_batch_plan *plan);
+
+/* Bytes of device workspace for the receive-binning lists of a batch
+ * (pings with SONAR_FLAG_RX_BEAMS and several bounces; 0 when none, or when
+ * a parameter set is invalid). */
+size_t sonar_batch_rx_workspace_size(int32_t n_pings, const sonar_params *params);
+
+/* sonar_batch_prepare (ssp NULL) or sonar_batch_prepare_ssp (one layered
+ * profile) for batches holding pings with receive binning of several
+ * bounces: each such ping gets its list area in `rx_workspace` (device, at
+ * least sonar_batch_rx_workspace_size bytes, 256-byte aligned, owned by the
+ * caller, one batch run at a time). sonar_ping_batch then clears the lists
+ * before the pings and adds them into the volumes after them with
+ * floating-point atomics (the last bits of the affected cells may vary
+ * between runs). The other prepare calls reject such pings. */
+sonar_status sonar_batch_prepare_rx(const sonar_scene *scene, int32_t n_pings, const sonar_params *params,
+                                    const sonar_pose *poses, const sonar_ssp *ssp, sonar_cf32 *const *volumes,
+                                    void *rx_workspace, size_t rx_ws_bytes, void *host_desc,
+                                    sonar_batch_plan *plan);
 
 /* Detection for a prepared batch (Sec. II-A: each ping's point cloud):
  * amends the ping descriptors in `host_desc` (as filled by

@@ -749,6 +749,9 @@ sonar_status sonar_batch_prepare_detect(int32_t n, const sonar_params *params, c
         }
         if (da.n_beams != d[i].n_beams || da.n_bins != d[i].n_bins)
             return fail(SONAR_E_INVALID, "ping %d: parameters differ from the prepared batch", i);
+        if (d[i].rx_list)
+            return fail(SONAR_E_UNSUPPORTED, "ping %d: receive binning with several bounces moves returns after the "
+                                             "in-kernel test: use sonar_detect per ping", i);
         for (int k = 1; k <= 2 * cfar->train; ++k)
             if (!(da.alpha[k] > 1.0))
                 return fail(SONAR_E_UNSUPPORTED, "alpha(N) <= 1 for N = %d: use sonar_detect per ping", k);
@@ -772,11 +775,29 @@ size_t sonar_batch_workspace_size(int32_t n_pings)
     return 256 + 2 * sizeof(unsigned long long) * (size_t)n_pings;
 }
 
+// Bytes of a batch's receive-binning lists: each ping's area (as for one
+// ping), 256-byte aligned, in ping order.
+static size_t batch_rx_bytes(int32_t n, const sonar_params *params)
+{
+    size_t total = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (needs_rx_list(&params[i])) total += (rx_bytes(&params[i]) + 255) & ~(size_t)255;
+    return total;
+}
+
+size_t sonar_batch_rx_workspace_size(int32_t n_pings, const sonar_params *params)
+{
+    if (n_pings < 1 || !params) return 0;
+    for (int32_t i = 0; i < n_pings; ++i)
+        if (check_params(&params[i]) != SONAR_OK) return 0;
+    return batch_rx_bytes(n_pings, params);
+}
+
 // Descriptors of a batch; `ssp` (NULL: none) is the layered profile every
-// ping goes through.
+// ping goes through, `rx_ws` holds the receive-binning lists.
 static sonar_status batch_prepare(const sonar_scene *sc, int32_t n, const sonar_params *params,
                                   const sonar_pose *poses, const sonar_ssp *ssp, sonar_cf32 *const *volumes,
-                                  void *host_desc, sonar_batch_plan *plan)
+                                  void *rx_ws, size_t rx_ws_bytes, void *host_desc, sonar_batch_plan *plan)
 {
     if (!sc || !params || !poses || !volumes || !host_desc || !plan)
         return fail(SONAR_E_INVALID, "scene, params, poses, volumes, host_desc and plan are required");
@@ -784,9 +805,9 @@ static sonar_status batch_prepare(const sonar_scene *sc, int32_t n, const sonar_
     sonar::PingArgs *d = reinterpret_cast<sonar::PingArgs *>(host_desc);
     int64_t tiles = 0, rays = 0;
     int max_bins = 0, max_beams = 0;
+    if (rx_ws && ((uintptr_t)rx_ws & 255) != 0) return fail(SONAR_E_INVALID, "workspace must be 256-byte aligned");
+    size_t rx_off = 0;
     for (int32_t i = 0; i < n; ++i) {
-        if (needs_rx_list(&params[i]))
-            return fail(SONAR_E_UNSUPPORTED, "ping %d: batches do not take receive binning with several bounces", i);
         if ((params[i].flags & SONAR_FLAG_RETRO_CHAIN) != (params[0].flags & SONAR_FLAG_RETRO_CHAIN))
             return fail(SONAR_E_INVALID, "ping %d: the pings of a batch all take retro-chain returns or none", i);
         sonar_status st = ssp ? layered_args(sc, &params[i], &poses[i], ssp, volumes[i], nullptr, nullptr, nullptr,
@@ -801,6 +822,16 @@ static sonar_status batch_prepare(const sonar_scene *sc, int32_t n, const sonar_
         if (params[i].max_bounces != params[0].max_bounces ||
             (!ssp && (params[i].c_grad != 0.0) != (params[0].c_grad != 0.0)))
             return fail(SONAR_E_INVALID, "ping %d: a batch needs one max_bounces and one medium type", i);
+        if (needs_rx_list(&params[i])) {
+            if (!rx_ws)
+                return fail(SONAR_E_UNSUPPORTED, "ping %d: receive binning with several bounces needs the list "
+                                                 "workspace of sonar_batch_prepare_rx", i);
+            const size_t need = (rx_bytes(&params[i]) + 255) & ~(size_t)255;
+            if (rx_off + need > rx_ws_bytes)
+                return fail(SONAR_E_INVALID, "workspace smaller than sonar_batch_rx_workspace_size()");
+            set_rx_area(d[i], &params[i], reinterpret_cast<char *>(rx_ws) + rx_off);
+            rx_off += need;
+        }
         int64_t t = (d[i].n_rays + 255) / 256;
         if (tiles + t > 0x7FFFFFFF) return fail(SONAR_E_INVALID, "batch too large");
         d[i].tile_offset = (int)tiles;
@@ -816,6 +847,9 @@ static sonar_status batch_prepare(const sonar_scene *sc, int32_t n, const sonar_
     plan->max_bins = max_bins;
     plan->max_beams = max_beams;
     plan->retro = (params[0].flags & SONAR_FLAG_RETRO_CHAIN) && params[0].max_bounces > 1;
+    int32_t n_rx = 0;
+    for (int32_t i = 0; i < n; ++i) n_rx += d[i].rx_list != nullptr;
+    plan->rx = n_rx;
     plan->total_tiles = tiles;
     plan->total_rays = rays;
     return SONAR_OK;
@@ -826,7 +860,7 @@ sonar_status sonar_batch_prepare(const sonar_scene *sc, int32_t n, const sonar_p
                                  sonar_batch_plan *plan)
 {
     g_err[0] = 0;
-    return batch_prepare(sc, n, params, poses, nullptr, volumes, host_desc, plan);
+    return batch_prepare(sc, n, params, poses, nullptr, volumes, nullptr, 0, host_desc, plan);
 }
 
 sonar_status sonar_batch_prepare_ssp(const sonar_scene *sc, int32_t n, const sonar_params *params,
@@ -835,7 +869,15 @@ sonar_status sonar_batch_prepare_ssp(const sonar_scene *sc, int32_t n, const son
 {
     g_err[0] = 0;
     if (!ssp) return fail(SONAR_E_INVALID, "ssp is NULL");
-    return batch_prepare(sc, n, params, poses, ssp, volumes, host_desc, plan);
+    return batch_prepare(sc, n, params, poses, ssp, volumes, nullptr, 0, host_desc, plan);
+}
+
+sonar_status sonar_batch_prepare_rx(const sonar_scene *sc, int32_t n, const sonar_params *params,
+                                    const sonar_pose *poses, const sonar_ssp *ssp, sonar_cf32 *const *volumes,
+                                    void *rx_workspace, size_t rx_ws_bytes, void *host_desc, sonar_batch_plan *plan)
+{
+    g_err[0] = 0;
+    return batch_prepare(sc, n, params, poses, ssp, volumes, rx_workspace, rx_ws_bytes, host_desc, plan);
 }
 
 static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_plan *plan, const void *dev_desc,
@@ -857,6 +899,7 @@ static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_p
     b->arc = plan->arc != 0;
     b->layered = plan->arc == 2;
     b->retro = plan->retro != 0;
+    b->rx = plan->rx != 0;
     b->depth = sc->s.stack;
     b->max_bins = plan->max_bins;
     b->total_tiles = plan->total_tiles;

@@ -127,6 +127,7 @@ struct BatchLaunch {
     bool arc;
     bool layered;            // every ping through its layered profile (descriptors carry it)
     bool retro;              // every ping with retro-chain returns
+    bool rx;                 // some ping lists returns for receive binning (clear before, scatter after)
     int depth;               // hierarchy depth (selects the stack size)
     int max_bins;            // largest n_range of the batch (LDS sizing)
     int64_t total_tiles;

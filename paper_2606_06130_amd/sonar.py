@@ -39,7 +39,8 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
            "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb",
-           "sonar_ping_ssp", "sonar_ping_ssp_rx", "sonar_batch_prepare_ssp")
+           "sonar_ping_ssp", "sonar_ping_ssp_rx", "sonar_batch_prepare_ssp", "sonar_batch_rx_workspace_size",
+           "sonar_batch_prepare_rx")
 
 
 class SonarError(RuntimeError):
@@ -105,7 +106,8 @@ class sonar_reverb(C.Structure):
 
 class sonar_batch_plan(C.Structure):
     _fields_ = [("n_pings", C.c_int32), ("max_bounces", C.c_int32), ("arc", C.c_int32), ("max_bins", C.c_int32),
-                ("max_beams", C.c_int32), ("retro", C.c_int32), ("total_tiles", C.c_int64),
+                ("max_beams", C.c_int32), ("retro", C.c_int32), ("rx", C.c_int32),
+                ("total_tiles", C.c_int64),
                 ("total_rays", C.c_int64)]
 
 
@@ -159,6 +161,11 @@ def lib():
         L.sonar_batch_prepare_ssp.restype = C.c_int
         L.sonar_batch_prepare_ssp.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, P(sonar_ssp), C.c_void_p,
                                               C.c_void_p, P(sonar_batch_plan)]
+        L.sonar_batch_rx_workspace_size.restype = C.c_size_t
+        L.sonar_batch_rx_workspace_size.argtypes = [C.c_int32, C.c_void_p]
+        L.sonar_batch_prepare_rx.restype = C.c_int
+        L.sonar_batch_prepare_rx.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_void_p, C.c_size_t, C.c_void_p, P(sonar_batch_plan)]
         L.sonar_ping_batch.restype = C.c_int
         L.sonar_ping_batch.argtypes = [C.c_void_p, P(sonar_batch_plan), C.c_void_p, P(sonar_batch_options),
                                        C.c_void_p, C.c_size_t, C.c_void_p]
@@ -548,7 +555,16 @@ class Batch:
         db = lib().sonar_batch_desc_bytes()
         host = np.zeros(n * db, np.uint8)
         self.plan = sonar_batch_plan()
-        if knots:
+        self.rx_workspace = None
+        rx_bytes = lib().sonar_batch_rx_workspace_size(n, P)
+        if rx_bytes:
+            # receive binning with several bounces: list areas per ping
+            self.rx_workspace = torch.empty(rx_bytes, dtype=torch.uint8, device="cuda")
+            prof = ssp_of(knots) if knots else None
+            _check(lib().sonar_batch_prepare_rx(scene.handle, n, P, Q, C.byref(prof) if knots else None, V,
+                                                _dptr(self.rx_workspace), rx_bytes, host.ctypes.data,
+                                                C.byref(self.plan)))
+        elif knots:
             prof = ssp_of(knots)
             _check(lib().sonar_batch_prepare_ssp(scene.handle, n, P, Q, C.byref(prof), V, host.ctypes.data,
                                                  C.byref(self.plan)))

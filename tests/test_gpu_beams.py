@@ -80,8 +80,25 @@ def test_receive_binning_rejections():
     st = L.sonar_ping_rx(sc.handle, C.byref(p), C.byref(q), sonar._dptr(vol), None, None, None, None,
                          sonar._dptr(ws), ws.numel(), None)
     assert st == sonar.SONAR_E_INVALID
+    # batches: the plain prepare call has no list workspace, fused batch
+    # detection would test the columns before the moved returns land
+    n = 1
+    P = (sonar.sonar_params * n)(p)
+    Q = (sonar.sonar_pose * n)(q)
+    V = (C.c_void_p * n)(vol.data_ptr())
+    host = np.zeros(L.sonar_batch_desc_bytes(), np.uint8)
+    plan = sonar.sonar_batch_plan()
+    st = L.sonar_batch_prepare(sc.handle, n, P, Q, V, host.ctypes.data, C.byref(plan))
+    assert st == sonar.SONAR_E_UNSUPPORTED and b"sonar_batch_prepare_rx" in L.sonar_last_error()
+    need = L.sonar_batch_rx_workspace_size(n, P)
+    assert need == L.sonar_rx_workspace_size(C.byref(p))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    st = L.sonar_batch_prepare_rx(sc.handle, n, P, Q, None, V, sonar._dptr(ws), need - 256, host.ctypes.data,
+                                  C.byref(plan))
+    assert st == sonar.SONAR_E_INVALID
+    b = sonar.Batch(sc, [(cfg, pose)])
     with pytest.raises(sonar.SonarError) as e:
-        sonar.Batch(sc, [(cfg, pose)])
+        b.detect()
     assert e.value.status == sonar.SONAR_E_UNSUPPORTED
     with pytest.raises(sonar.SonarError) as e:
         sonar.ping(sc, cfg.replace(grid_mode=1, rays_per_beam=1), pose)
@@ -125,3 +142,69 @@ def test_harbor_multipath_pattern_and_receive_binning_full_size_records():
     assert res["flagged"] <= 0.05 * res["rays"], res
     launch = np.repeat(beams, cfg.rays_per_beam)[:, None]
     assert ((orc["rxb"][:, 1:] != launch) & (orc["bin"][:, 1:] >= 0) & ok[:, None]).sum() > 10
+
+
+def _close(a, b):
+    """Equal up to the order of the floating-point atomics that add moved
+    returns (a few roundings of the cell's magnitude)."""
+    import torch
+    x, y = a.view(torch.float32), b.view(torch.float32)
+    tol = 1e-6 * float(y.abs().max())
+    return bool(torch.allclose(x, y, rtol=1e-5, atol=tol)) and float(y.abs().max()) > 0
+
+
+@pytest.mark.parametrize("K,g,layered", [(2, 0.0, False), (3, 0.0, False), (3, 0.05, False), (3, 0.0, True)])
+def test_batch_receive_binning_equals_single_pings(K, g, layered):
+    """A batch whose pings bin later returns by arrival direction (mixed
+    layouts, poses, with and without the option, one persistent launch,
+    per-ping lists) writes the volumes of single pings; run twice, since the
+    lists must start empty every time."""
+    torch, sonar = _gpu()
+    knots = ((-9.0, 1497.0), (-6.0, 1498.2), (-3.0, 1499.0), (-0.5, 1500.2), (1.5, 1500.3))
+    mesh, base, _ = _boxes(K, RX | PATTERN, c_grad=g, ssp=knots if layered else ())
+    sc = sonar.Scene(mesh)
+    shapes = [(16, 8, 4, RX | PATTERN), (32, 16, 1, RX), (9, 5, 16, PATTERN), (24, 12, 4, RX | PATTERN)]
+    items = []
+    for i, (nh, nv, nr, fl) in enumerate(shapes):
+        q = S.pose((0.4 * i, -0.3 * i, -0.2 * i), yaw=math.radians(3 * i), pitch_down=math.radians(60 - 2 * i),
+                   ping=i)
+        items.append((base.replace(n_h=nh, n_v=nv, rays_per_beam=nr, flags=fl), q))
+    b = sonar.Batch(sc, items)
+    assert b.rx_workspace is not None and b.plan.rx == 3
+    for rep in range(2):
+        b.run()
+        torch.cuda.synchronize()
+        assert sc.status() == 0
+        for i, (cfg, q) in enumerate(items):
+            ref = sonar.ping(sc, cfg, q)["volume"]
+            torch.cuda.synchronize()
+            if cfg.flags & RX:
+                assert _close(b.volumes[i], ref), (rep, i)
+            else:
+                assert torch.equal(b.volumes[i].view(torch.float32), ref.view(torch.float32)), (rep, i)
+
+
+def test_batch_receive_binning_graph_replays():
+    """The batch with per-ping lists captured in a HIP graph (clear, pings,
+    scatter): every replay, with eager work between them, gives the direct
+    launch's volumes."""
+    torch, sonar = _gpu()
+    mesh, base, _ = _boxes(3, RX | PATTERN)
+    sc = sonar.Scene(mesh)
+    items = [(base.replace(n_h=nh, n_v=nv), S.pose((0.3 * i, 0.0, 0.0), pitch_down=math.radians(58 + i), ping=i))
+             for i, (nh, nv) in enumerate([(16, 8), (20, 10), (12, 6)])]
+    b = sonar.Batch(sc, items)
+    b.run()
+    torch.cuda.synchronize()
+    want = [v.clone() for v in b.volumes]
+    g = b.graph(b.options(blocks_per_cu=1, tiles_per_item=1))
+    for rep in range(3):
+        for v in b.volumes:
+            v.fill_(complex(float("nan"), 0.0))
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, v in enumerate(b.volumes):
+            assert _close(v, want[i]), (rep, i)
+    g.close()
+    assert sc.status() == 0
