@@ -1612,7 +1612,15 @@ void k_ping(PingArgs a, int wave_words)
 {
     extern __shared__ uint32_t lds[];
     uint32_t *W = lds + (size_t)(threadIdx.x / WAVE) * wave_words;
-    ping_tile<DEPTH, K, ARC, STATS, LAYERED, RETRO>(a, xcd_remap(blockIdx.x, gridDim.x), W);
+    if constexpr (LAYERED) {
+        // The profile tables are indexed by layer at run time: read the
+        // argument block where it lies (kernel-argument memory, the block is
+        // the first argument), not from a private per-lane copy of it.
+        const PingArgs *ka = (const PingArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+        ping_tile<DEPTH, K, ARC, STATS, LAYERED, RETRO>(*ka, xcd_remap(blockIdx.x, gridDim.x), W);
+    } else {
+        ping_tile<DEPTH, K, ARC, STATS, LAYERED, RETRO>(a, xcd_remap(blockIdx.x, gridDim.x), W);
+    }
 }
 
 // Persistent batch: every block pops (ping, tile) items from one device
