@@ -163,6 +163,27 @@ def test_rx_workspace_size(L):
     assert b >= a + 256 + 16 * 16 * 8 * 4 * 2
 
 
+def test_batch_rx_workspace_size(L):
+    """The batch's list workspace: each receive-binning ping's area (as for
+    one ping) rounded up to 256 bytes, in ping order; 0 without such pings
+    or with an invalid parameter set."""
+    base = S.sensor_seabed_boxes().replace(max_bounces=2, flags=sonar.FLAG_RX_BEAMS)
+    cfgs = [base.replace(n_h=9, n_v=5, rays_per_beam=1),            # 256 + 16 * 45 = 976 -> 1,024
+            base.replace(n_h=16, n_v=8, rays_per_beam=4, flags=0),  # no list
+            base.replace(n_h=16, n_v=8, rays_per_beam=4)]           # 256 + 16 * 512 = 8,448 -> 8,448
+    P = (sonar.sonar_params * 3)(*[sonar.params_of(c) for c in cfgs])
+    assert L.sonar_batch_rx_workspace_size(3, P) == 1024 + 8448
+    for i, c in enumerate(cfgs):
+        one = L.sonar_rx_workspace_size(C.byref(P[i]))
+        assert L.sonar_batch_rx_workspace_size(1, C.byref(P[i])) == (((one + 255) // 256) * 256 if c.flags else 0)
+    Q = (sonar.sonar_params * 2)(sonar.params_of(cfgs[1]), sonar.params_of(cfgs[1].replace(max_bounces=3)))
+    assert L.sonar_batch_rx_workspace_size(2, Q) == 0
+    Q[1] = sonar.params_of(cfgs[0].replace(flags=16))                  # unknown flag
+    assert L.sonar_batch_rx_workspace_size(2, Q) == 0
+    assert L.sonar_batch_rx_workspace_size(0, P) == 0
+    assert L.sonar_batch_rx_workspace_size(2, None) == 0
+
+
 def test_add_reverb_validates_before_launch(L):
     cfg = S.sensor_seabed_boxes()
     p = sonar.params_of(cfg)
