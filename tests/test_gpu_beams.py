@@ -153,8 +153,9 @@ def _close(a, b):
     return bool(torch.allclose(x, y, rtol=1e-5, atol=tol)) and float(y.abs().max()) > 0
 
 
-@pytest.mark.parametrize("K,g,layered", [(2, 0.0, False), (3, 0.0, False), (3, 0.05, False), (3, 0.0, True)])
-def test_batch_receive_binning_equals_single_pings(K, g, layered):
+@pytest.mark.parametrize("K,g,layered,retro", [(2, 0.0, False, 0), (3, 0.0, False, 0), (3, 0.05, False, 0),
+                                               (3, 0.0, True, 0), (3, 0.05, False, 8), (3, 0.0, True, 8)])
+def test_batch_receive_binning_equals_single_pings(K, g, layered, retro):
     """A batch whose pings bin later returns by arrival direction (mixed
     layouts, poses, with and without the option, one persistent launch,
     per-ping lists) writes the volumes of single pings; run twice, since the
@@ -168,9 +169,9 @@ def test_batch_receive_binning_equals_single_pings(K, g, layered):
     for i, (nh, nv, nr, fl) in enumerate(shapes):
         q = S.pose((0.4 * i, -0.3 * i, -0.2 * i), yaw=math.radians(3 * i), pitch_down=math.radians(60 - 2 * i),
                    ping=i)
-        items.append((base.replace(n_h=nh, n_v=nv, rays_per_beam=nr, flags=fl), q))
+        items.append((base.replace(n_h=nh, n_v=nv, rays_per_beam=nr, flags=fl | retro), q))
     b = sonar.Batch(sc, items)
-    assert b.rx_workspace is not None and b.plan.rx == 3
+    assert b.rx_workspace is not None and b.plan.rx == 3 and b.plan.retro == (retro != 0)
     for rep in range(2):
         b.run()
         torch.cuda.synchronize()
