@@ -1706,26 +1706,28 @@ __global__ __launch_bounds__(256) void k_rx_scatter(const int4 *__restrict__ lis
 }
 
 // Receive binning in a batch: before the pings every list's counter is
-// cleared, after them every ping's list is added into its volume (grid y =
-// ping; pings without a list return at once).
+// cleared, after them every ping's list is added into its volume (grid y
+// strides over the pings; pings without a list are skipped at once).
 __global__ void k_rx_reset_batch(const PingArgs *__restrict__ desc, int n_pings)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_pings && desc[i].rx_count) *desc[i].rx_count = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_rx_scatter_batch(const PingArgs *__restrict__ desc)
+__global__ __launch_bounds__(256) void k_rx_scatter_batch(const PingArgs *__restrict__ desc, int n_pings)
 {
-    const PingArgs &a = desc[blockIdx.y];
-    if (!a.rx_list) return;
-    const uint32_t n = min(*a.rx_count, a.rx_cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int4 e = a.rx_list[i];
-        const size_t cell = (size_t)e.x * a.n_bins + e.y;
-        const float re = __int_as_float(e.z), im = __int_as_float(e.w);
-        atomicAdd(&a.volume[cell].x, re);
-        atomicAdd(&a.volume[cell].y, im);
-        if (a.incoh) atomicAdd(&a.incoh[(size_t)a.n_beams * a.n_bins + cell], re * re + im * im);
+    for (int p = blockIdx.y; p < n_pings; p += gridDim.y) {
+        const PingArgs &a = desc[p];
+        if (!a.rx_list) continue;
+        const uint32_t n = min(*a.rx_count, a.rx_cap);
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const int4 e = a.rx_list[i];
+            const size_t cell = (size_t)e.x * a.n_bins + e.y;
+            const float re = __int_as_float(e.z), im = __int_as_float(e.w);
+            atomicAdd(&a.volume[cell].x, re);
+            atomicAdd(&a.volume[cell].y, im);
+            if (a.incoh) atomicAdd(&a.incoh[(size_t)a.n_beams * a.n_bins + cell], re * re + im * im);
+        }
     }
 }
 
@@ -1877,7 +1879,9 @@ static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int 
     if (b.rx) hipLaunchKernelGGL(k_rx_reset_batch, dim3((b.n_pings + 255) / 256), dim3(256), 0, s, b.desc, b.n_pings);
     hipLaunchKernelGGL((k_ping_batch<D, KK, AR, LAY, RET>), dim3((unsigned)grid), dim3(BLOCK), shmem, s, b.desc, b.n_pings,
                        b.queue, b.t0, b.t1, ww, tpi);
-    if (b.rx) hipLaunchKernelGGL(k_rx_scatter_batch, dim3(64, (unsigned)b.n_pings), dim3(256), 0, s, b.desc);
+    if (b.rx)
+        hipLaunchKernelGGL(k_rx_scatter_batch, dim3(64, (unsigned)(b.n_pings < 4096 ? b.n_pings : 4096)), dim3(256), 0,
+                           s, b.desc, b.n_pings);
     return hipGetLastError();
 }
 
