@@ -94,6 +94,8 @@ def lib():
         L.orc_scene_new.restype = C.c_void_p
         L.orc_scene_new.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_scene_free.argtypes = [C.c_void_p]
+        L.orc_scene_build_grid.argtypes = [C.c_void_p, C.c_double]
+        L.orc_scene_grid_info.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_grid_counts.argtypes = [C.c_double] * 7 + [C.c_void_p]
         L.orc_splitmix64_nth.restype = C.c_uint64
         L.orc_splitmix64_nth.argtypes = [C.c_uint64, C.c_uint64]
@@ -150,8 +152,17 @@ def pose_of(pose) -> PoseS:
     return q
 
 
+GRID_MIN_TRIANGLES = 20000
+
+
 class Scene:
-    def __init__(self, mesh):
+    """The oracle's copy of a mesh. ``grid``: bin the triangles in a uniform
+    grid used as an exact candidate filter (every query visits, in index
+    order, every triangle that could change its result or flags; the
+    arithmetic per triangle is the brute-force one). Default: on for meshes
+    of at least GRID_MIN_TRIANGLES triangles."""
+
+    def __init__(self, mesh, grid=None, cells_per_triangle: float = 0.5):
         self._keep = (np.ascontiguousarray(mesh.vertices, np.float32),
                       np.ascontiguousarray(mesh.indices, np.int32),
                       np.ascontiguousarray(mesh.reflectivity, np.float32),
@@ -160,6 +171,15 @@ class Scene:
         v, i, r, p, m = self._keep
         self.h = lib().orc_scene_new(_ptr(v), v.shape[0], _ptr(i), i.shape[0], _ptr(r), _ptr(p), _ptr(m))
         self.n_triangles = i.shape[0]
+        if grid is None:
+            grid = self.n_triangles >= GRID_MIN_TRIANGLES
+        if grid:
+            lib().orc_scene_build_grid(self.h, float(cells_per_triangle))
+
+    def grid_info(self) -> dict:
+        out = np.zeros(3)
+        lib().orc_scene_grid_info(self.h, _ptr(out))
+        return dict(cells=int(out[0]), entries=int(out[1]), cell=float(out[2]))
 
     def __del__(self):
         if getattr(self, "h", None):

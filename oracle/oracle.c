@@ -139,6 +139,16 @@ enum {
     F_STOP = 1u << 8, F_DEPART = 1u << 9, F_CAUSTIC = 1u << 10
 };
 
+/* Optional uniform grid over the scene (an exact candidate filter, see
+ * grid_candidates): triangle i is listed in every cell that its bounding box,
+ * grown by gpad[i], touches (closed intervals). */
+typedef struct {
+    int nx, ny, nz;
+    double lo[3], h;            /* grid origin and cubic cell size */
+    int64_t *start;             /* [nx ny nz + 1] CSR offsets into ids */
+    int32_t *ids;
+} ogrid;
+
 typedef struct {
     int64_t nt;
     double *p;          /* [nt][9] FP32 vertices promoted exactly */
@@ -146,6 +156,7 @@ typedef struct {
     double *rho, *phi;
     uint8_t *mat;
     double zabs_max;    /* max |z| over all vertices */
+    ogrid *grid;        /* NULL: every query loops over all triangles */
 } oscene;
 
 static const double EPS_SELF = 1e-4;   /* minimum hit distance, metres */
@@ -189,6 +200,7 @@ void orc_scene_free(void *h)
 {
     oscene *s = (oscene *)h;
     if (!s) return;
+    if (s->grid) { free(s->grid->start); free(s->grid->ids); free(s->grid); }
     free(s->p); free(s->nrm); free(s->rho); free(s->phi); free(s->mat); free(s);
 }
 
@@ -218,6 +230,148 @@ static double edge_distance(const oscene *s, int64_t i, v3 P)
         if (d < best) best = d;
     }
     return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact candidate filter (a uniform grid, Amanatides and Woo 1987).         */
+/*                                                                           */
+/* A triangle changes a query's result or flags only through a plane root s  */
+/* on the queried path piece whose point X(s) has edge_distance > -dl, with  */
+/* dl = edge_abs + edge_rel * s (nearest_hit_from, blocked_piece). X then    */
+/* lies in the triangle grown by dl across each edge, inside the triangle's  */
+/* bounding box grown by dl / sin(a / 2), a its smallest angle. The piece    */
+/* lies within its sagitta of the chord between its ends, and the cells the  */
+/* chord passes are walked one by one. Triangles are binned with their box   */
+/* grown by GRID_DL / sin(a / 2) + GRID_FAT, so a query is exact while its   */
+/* dl stays below GRID_DL and its sagitta below GRID_FAT - 1e-6 (rounding of */
+/* the walk is far below the remaining millimetres); other queries loop over */
+/* all triangles. Candidates are visited in increasing index, the order of   */
+/* the full loop, so ties resolve identically. Triangles with no area have   */
+/* no plane roots and are not binned; near-slivers whose grown box would    */
+/* span the scene are tested by every query.                                */
+
+#define GRID_DL 1e-3
+#define GRID_FAT 1e-2
+
+static int cmp_i32(const void *a, const void *b)
+{
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Grid padding of triangle i, or -1 for a triangle without area. */
+static double grid_pad(const oscene *s, int64_t i)
+{
+    v3 n = tri_normal(s, i);
+    if (dot(n, n) == 0.0) return -1.0;
+    double smin = 1.0;
+    for (int c = 0; c < 3; ++c) {
+        v3 a = sub(tri_vertex(s, i, (c + 1) % 3), tri_vertex(s, i, c));
+        v3 b = sub(tri_vertex(s, i, (c + 2) % 3), tri_vertex(s, i, c));
+        double cs = dot(a, b) / (len(a) * len(b));
+        double sh = sqrt(0.5 * (1.0 - cs));        /* sin of half the vertex angle */
+        if (sh < smin) smin = sh;
+    }
+    if (!(smin > 0.0)) return 1e300;
+    return GRID_DL / smin + GRID_FAT + 1e-6;
+}
+
+/* Builds the grid with about `cells_per_tri` cells per triangle. */
+void orc_scene_build_grid(void *hs, double cells_per_tri)
+{
+    oscene *S = (oscene *)hs;
+    if (S->grid) { free(S->grid->start); free(S->grid->ids); free(S->grid); S->grid = NULL; }
+    const int64_t nt = S->nt;
+    double *bx = (double *)malloc(sizeof(double) * 6 * (size_t)nt);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < nt; ++i) {
+        double *b = bx + 6 * i;
+        b[0] = 1.0; b[3] = -1.0;                   /* empty: not binned */
+        if (grid_pad(S, i) < 0.0) continue;
+        for (int a = 0; a < 3; ++a) {
+            double l = S->p[9 * i + a], h = l;
+            for (int c = 1; c < 3; ++c) {
+                double w = S->p[9 * i + 3 * c + a];
+                if (w < l) l = w;
+                if (w > h) h = w;
+            }
+            b[a] = l; b[3 + a] = h;
+            if (l < lo[a]) lo[a] = l;
+            if (h > hi[a]) hi[a] = h;
+        }
+    }
+    /* extent of the scene without padding */
+    double span = 0.0;
+    for (int a = 0; a < 3; ++a) if (hi[a] - lo[a] > span) span = hi[a] - lo[a];
+    ogrid *G = (ogrid *)calloc(1, sizeof(ogrid));
+    const double big = span + 1.0;                 /* a grown box wider than this spans the grid */
+    double glo[3], ghi[3];
+    for (int a = 0; a < 3; ++a) { glo[a] = lo[a] - GRID_FAT - 1.0; ghi[a] = hi[a] + GRID_FAT + 1.0; }
+    double vol = (ghi[0] - glo[0]) * (ghi[1] - glo[1]) * (ghi[2] - glo[2]);
+    double hcell = cbrt(vol / (cells_per_tri * (double)(nt > 0 ? nt : 1)));
+    int n[3];
+    for (int a = 0; a < 3; ++a) {
+        double c = ceil((ghi[a] - glo[a]) / hcell);
+        if (c < 1) c = 1;
+        if (c > 2048) c = 2048;
+        n[a] = (int)c;
+    }
+    /* the cell size must cover the extent with the clamped counts */
+    for (int a = 0; a < 3; ++a) {
+        double need = (ghi[a] - glo[a]) / n[a];
+        if (need > hcell) hcell = need;
+    }
+    G->nx = n[0]; G->ny = n[1]; G->nz = n[2];
+    for (int a = 0; a < 3; ++a) G->lo[a] = glo[a];
+    G->h = hcell;
+    const int64_t ncell = (int64_t)n[0] * n[1] * n[2];
+    G->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    /* two passes over the triangles: counts, then ids (in increasing index within every cell) */
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t *fill = NULL;
+        if (pass == 1) {
+            for (int64_t c = 0; c < ncell; ++c) G->start[c + 1] += G->start[c];
+            G->ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(G->start[ncell] > 0 ? G->start[ncell] : 1));
+            fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+            memcpy(fill, G->start, sizeof(int64_t) * (size_t)ncell);
+        }
+        for (int64_t i = 0; i < nt; ++i) {
+            const double *b = bx + 6 * i;
+            if (b[0] > b[3]) continue;
+            double pad = grid_pad(S, i);
+            if (pad > big) pad = big;              /* a near-sliver: every cell */
+            int c0[3], c1[3];
+            for (int a = 0; a < 3; ++a) {
+                double l = floor((b[a] - pad - glo[a]) / hcell), h = floor((b[3 + a] + pad - glo[a]) / hcell);
+                if (l < 0) l = 0;
+                if (h > n[a] - 1) h = n[a] - 1;
+                c0[a] = (int)l; c1[a] = (int)h;
+            }
+            for (int z = c0[2]; z <= c1[2]; ++z)
+                for (int y = c0[1]; y <= c1[1]; ++y)
+                    for (int x = c0[0]; x <= c1[0]; ++x) {
+                        int64_t c = ((int64_t)z * n[1] + y) * n[0] + x;
+                        if (pass == 0) ++G->start[c + 1];
+                        else G->ids[fill[c]++] = (int32_t)i;
+                    }
+        }
+        free(fill);
+    }
+    free(bx);
+    S->grid = G;
+}
+
+/* Cells in the grid, listed triangle entries, cell size. */
+void orc_scene_grid_info(const void *hs, double out[3])
+{
+    const oscene *S = (const oscene *)hs;
+    out[0] = out[1] = out[2] = 0.0;
+    if (!S->grid) return;
+    const ogrid *G = S->grid;
+    const int64_t nc = (int64_t)G->nx * G->ny * G->nz;
+    out[0] = (double)nc;
+    out[1] = (double)G->start[nc];
+    out[2] = G->h;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -455,6 +609,102 @@ static double layer_exit(const orc_params *P, int i, const opath *p, double g, d
     return best;
 }
 
+static __thread int32_t *tl_cand = NULL;
+static __thread int64_t tl_cap = 0;
+
+static void cand_push(const int32_t *ids, int64_t n, int64_t *cnt)
+{
+    if (*cnt + n > tl_cap) {
+        int64_t cap = tl_cap ? tl_cap : 4096;
+        while (cap < *cnt + n) cap *= 2;
+        tl_cand = (int32_t *)realloc(tl_cand, sizeof(int32_t) * (size_t)cap);
+        tl_cap = cap;
+    }
+    memcpy(tl_cand + *cnt, ids, sizeof(int32_t) * (size_t)n);
+    *cnt += n;
+}
+
+/* Candidates of the path piece p over arc length (0, hi] whose positions on
+ * the whole path run up to s_end (dl grows with them): the number of
+ * candidates, sorted and distinct in *out (thread-local storage, valid until
+ * the next call on the thread), or -1 when the query needs the full loop. */
+static int64_t grid_candidates(const oscene *S, const opath *p, double hi, double s_end, const orc_tol *T,
+                               const int32_t **out)
+{
+    const ogrid *G = S->grid;
+    if (!G) return -1;
+    if (!(T->edge_abs + T->edge_rel * s_end <= GRID_DL)) return -1;
+    double sag = 0.0;
+    if (p->arc) {
+        double u = fabs(p->kappa) * hi;
+        if (!(u <= 1.0)) return -1;
+        double q = sin(0.25 * u);
+        sag = (2.0 * q * q / fabs(p->kappa)) * 1.01 + 1e-9;
+    }
+    if (!(sag <= GRID_FAT - 1e-6)) return -1;
+    v3 A = p->o, B = path_point(p, hi);
+    double a0[3] = {A.x, A.y, A.z}, dv[3] = {B.x - A.x, B.y - A.y, B.z - A.z};
+    const int n[3] = {G->nx, G->ny, G->nz};
+    /* clip t in [0, 1] to the grid box */
+    double t0 = 0.0, t1 = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        double l = G->lo[a], h = G->lo[a] + n[a] * G->h;
+        if (dv[a] == 0.0) {
+            if (a0[a] < l || a0[a] > h) { *out = tl_cand; return 0; }
+            continue;
+        }
+        double ta = (l - a0[a]) / dv[a], tb = (h - a0[a]) / dv[a];
+        if (ta > tb) { double w = ta; ta = tb; tb = w; }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+    }
+    int64_t cnt = 0;
+    if (t0 <= t1) {
+        int c[3], step[3];
+        double tmax[3], tdel[3];
+        for (int a = 0; a < 3; ++a) {
+            double x = a0[a] + t0 * dv[a];
+            int ci = (int)floor((x - G->lo[a]) / G->h);
+            if (ci < 0) ci = 0;
+            if (ci > n[a] - 1) ci = n[a] - 1;
+            c[a] = ci;
+            if (dv[a] > 0.0) {
+                step[a] = 1;
+                tmax[a] = (G->lo[a] + (ci + 1) * G->h - a0[a]) / dv[a];
+                tdel[a] = G->h / dv[a];
+            } else if (dv[a] < 0.0) {
+                step[a] = -1;
+                tmax[a] = (G->lo[a] + ci * G->h - a0[a]) / dv[a];
+                tdel[a] = -G->h / dv[a];
+            } else {
+                step[a] = 0;
+                tmax[a] = 1e300;
+                tdel[a] = 1e300;
+            }
+        }
+        for (;;) {
+            int64_t cell = ((int64_t)c[2] * n[1] + c[1]) * n[0] + c[0];
+            cand_push(G->ids + G->start[cell], G->start[cell + 1] - G->start[cell], &cnt);
+            int a = 0;
+            if (tmax[1] < tmax[a]) a = 1;
+            if (tmax[2] < tmax[a]) a = 2;
+            if (tmax[a] > t1) break;
+            c[a] += step[a];
+            if (c[a] < 0 || c[a] >= n[a]) break;
+            tmax[a] += tdel[a];
+        }
+    }
+    if (cnt > 1) {
+        qsort(tl_cand, (size_t)cnt, sizeof(int32_t), cmp_i32);
+        int64_t m = 1;
+        for (int64_t k = 1; k < cnt; ++k)
+            if (tl_cand[k] != tl_cand[m - 1]) tl_cand[m++] = tl_cand[k];
+        cnt = m;
+    }
+    *out = tl_cand;
+    return cnt;
+}
+
 /* Roots s in (0, hi] of the path meeting the plane of triangle i. */
 static int plane_roots(const oscene *S, int64_t i, const opath *p, double hi, double r[2])
 {
@@ -522,7 +772,11 @@ static ohit nearest_hit_from(const oscene *S, const opath *p, int64_t prev, doub
     double best = 1e300;
     double near1 = 1e300, near2 = 1e300;   /* the two nearest near-candidates */
     int64_t near1_i = -1;
-    for (int64_t i = 0; i < S->nt; ++i) {
+    const int32_t *cand;
+    const int64_t nc = grid_candidates(S, p, hi, hi, T, &cand);
+    const int64_t n_loop = nc >= 0 ? nc : S->nt;
+    for (int64_t c = 0; c < n_loop; ++c) {
+        const int64_t i = nc >= 0 ? (int64_t)cand[c] : c;
         if (i == prev) continue;
         double r[2];
         int m = plane_roots(S, i, p, hi, r);
@@ -564,7 +818,11 @@ static int blocked_piece(const oscene *S, const opath *p, int64_t skip, double s
                          const orc_tol *T, uint32_t *flags)
 {
     int hit = 0;
-    for (int64_t i = 0; i < S->nt; ++i) {
+    const int32_t *cand;
+    const int64_t nc = grid_candidates(S, p, len, s0 + len, T, &cand);
+    const int64_t n_loop = nc >= 0 ? nc : S->nt;
+    for (int64_t c = 0; c < n_loop; ++c) {
+        const int64_t i = nc >= 0 ? (int64_t)cand[c] : c;
         if (i == skip) continue;
         double r[2];
         int m = plane_roots(S, i, p, len, r);
