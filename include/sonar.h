@@ -468,6 +468,19 @@ sonar_status sonar_batch_prepare_rx(const sonar_scene *scene, int32_t n_pings, c
                                     void *rx_workspace, size_t rx_ws_bytes, void *host_desc,
                                     sonar_batch_plan *plan);
 
+/* Optional outputs of one ping of a prepared batch, as sonar_ping takes them
+ * (Sec. II-B: the per-beam G-buffer and incoherent channels, for training
+ * data; the record and ray mask, for testing): amends descriptor `ping` of
+ * the n_pings descriptors in the host buffer `host_desc` (filled by
+ * sonar_batch_prepare*). gbuffer, incoh, record arrays and ray_mask are
+ * device pointers laid out for that ping's layout as for sonar_ping, or NULL
+ * (that output off). Copy the descriptors to the device again afterwards.
+ * SONAR_E_INVALID for a null host_desc, ping outside [0, n_pings), a
+ * partial record or a descriptor not filled by a prepare call;
+ * SONAR_E_UNSUPPORTED for record->stats (batches keep no counters). */
+sonar_status sonar_batch_set_outputs(void *host_desc, int32_t n_pings, int32_t ping, float *gbuffer, float *incoh,
+                                     const sonar_ray_record *record, const uint32_t *ray_mask);
+
 /* Detection for a prepared batch (Sec. II-A: each ping's point cloud):
  * amends the ping descriptors in `host_desc` (as filled by
  * sonar_batch_prepare) so that every ping's kernel runs the CA-CFAR test of

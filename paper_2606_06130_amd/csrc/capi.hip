@@ -557,18 +557,17 @@ sonar_status sonar_detect(const sonar_cf32 *volume, const sonar_params *p, const
     return SONAR_OK;
 }
 
-sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q,
-                               const sonar_cfar *c, sonar_cf32 *volume, sonar_point *points, int32_t capacity,
-                               int32_t *dev_count, void *workspace, size_t ws_bytes, sonar_stream stream)
+// Ping + detection into a given workspace.
+static sonar_status ping_detect_into(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q,
+                                     const sonar_cfar *c, sonar_cf32 *volume, sonar_point *points, int32_t capacity,
+                                     int32_t *dev_count, void *workspace, size_t ws_bytes, hipStream_t s)
 {
-    g_err[0] = 0;
     sonar::PingArgs pa;
     sonar_status st = fill_ping_args(sc, p, q, volume, nullptr, nullptr, nullptr, nullptr, &pa);
     if (st != SONAR_OK) return st;
     sonar::DetectArgs da;
     st = fill_detect_args(volume, p, q, c, points, capacity, dev_count, workspace, ws_bytes, &da);
     if (st != SONAR_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
     if (needs_rx_list(p)) {
         // moved returns land after the ping kernel: detection runs after them
         if (ws_bytes < det_bytes(p) + rx_bytes(p) || ((uintptr_t)workspace & 255) != 0)
@@ -604,6 +603,14 @@ sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, con
     return SONAR_OK;
 }
 
+sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q,
+                               const sonar_cfar *c, sonar_cf32 *volume, sonar_point *points, int32_t capacity,
+                               int32_t *dev_count, void *workspace, size_t ws_bytes, sonar_stream stream)
+{
+    g_err[0] = 0;
+    return ping_detect_into(sc, p, q, c, volume, points, capacity, dev_count, workspace, ws_bytes,
+                            (hipStream_t)stream);
+}
 
 sonar_status sonar_add_reverb(sonar_cf32 *volume, const sonar_params *p, const sonar_pose *q,
                               const sonar_reverb *rv, sonar_stream stream)
@@ -878,6 +885,33 @@ sonar_status sonar_batch_prepare_rx(const sonar_scene *sc, int32_t n, const sona
 {
     g_err[0] = 0;
     return batch_prepare(sc, n, params, poses, ssp, volumes, rx_workspace, rx_ws_bytes, host_desc, plan);
+}
+
+sonar_status sonar_batch_set_outputs(void *host_desc, int32_t n_pings, int32_t ping, float *gbuffer, float *incoh,
+                                     const sonar_ray_record *record, const uint32_t *ray_mask)
+{
+    g_err[0] = 0;
+    if (!host_desc || ping < 0 || ping >= n_pings) return fail(SONAR_E_INVALID, "host_desc and 0 <= ping < n_pings are required");
+    if (record && (!record->tri || !record->bin || !record->vis || !record->amp))
+        return fail(SONAR_E_INVALID, "record arrays tri, bin, vis and amp must all be set");
+    if (record && record->stats)
+        return fail(SONAR_E_UNSUPPORTED, "traversal counters are not kept in batches");
+    if (record && (!record->retro_bin) != (!record->retro_amp))
+        return fail(SONAR_E_INVALID, "record arrays retro_bin and retro_amp go together");
+    sonar::PingArgs &a = reinterpret_cast<sonar::PingArgs *>(host_desc)[ping];
+    if (a.n_beams < 1 || a.n_r < 1 || a.n_tiles < 1) return fail(SONAR_E_INVALID, "descriptor %d is not a prepared one", ping);
+    a.gbuf = gbuffer;
+    a.incoh = incoh;
+    a.rec_tri = record ? record->tri : nullptr;
+    a.rec_bin = record ? record->bin : nullptr;
+    a.rec_vis = record ? record->vis : nullptr;
+    a.rec_amp = record ? reinterpret_cast<float2 *>(record->amp) : nullptr;
+    a.rec_beam = record ? record->beam : nullptr;
+    a.rec_rbin = record ? record->retro_bin : nullptr;
+    a.rec_ramp = record ? reinterpret_cast<float2 *>(record->retro_amp) : nullptr;
+    a.stats = nullptr;
+    a.mask = ray_mask;
+    return SONAR_OK;
 }
 
 static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_plan *plan, const void *dev_desc,

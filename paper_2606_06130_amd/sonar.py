@@ -40,7 +40,7 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
            "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb",
            "sonar_ping_ssp", "sonar_ping_ssp_rx", "sonar_batch_prepare_ssp", "sonar_batch_rx_workspace_size",
-           "sonar_batch_prepare_rx")
+           "sonar_batch_prepare_rx", "sonar_batch_set_outputs")
 
 
 class SonarError(RuntimeError):
@@ -166,6 +166,9 @@ def lib():
         L.sonar_batch_prepare_rx.restype = C.c_int
         L.sonar_batch_prepare_rx.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                              C.c_void_p, C.c_size_t, C.c_void_p, P(sonar_batch_plan)]
+        L.sonar_batch_set_outputs.restype = C.c_int
+        L.sonar_batch_set_outputs.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                              P(sonar_ray_record), C.c_void_p]
         L.sonar_ping_batch.restype = C.c_int
         L.sonar_ping_batch.argtypes = [C.c_void_p, P(sonar_batch_plan), C.c_void_p, P(sonar_batch_options),
                                        C.c_void_p, C.c_size_t, C.c_void_p]
@@ -575,6 +578,30 @@ class Batch:
         self.workspace = torch.empty(lib().sonar_batch_workspace_size(n), dtype=torch.uint8, device="cuda")
         self.n = n
         self.emit = None
+
+    def set_outputs(self, i, gbuffer=False, incoh=False, record=False, ray_mask=None):
+        """Adds sonar_ping's optional outputs to ping i (G-buffer, incoherent
+        channels, per-ray record; ``ray_mask``: device bit mask of rays that
+        add nothing). Returns the dict of allocated tensors."""
+        import torch
+        cfg = self.items[i][0]
+        out = alloc_outputs(cfg, gbuffer, incoh, record)
+        del out["volume"]
+        rec = None
+        if record:
+            rec = sonar_ray_record(tri=out["tri"].data_ptr(), bin=out["bin"].data_ptr(), vis=out["vis"].data_ptr(),
+                                   amp=out["amp"].data_ptr(), stats=None, beam=out["beam"].data_ptr(),
+                                   retro_bin=out["rbin"].data_ptr() if "rbin" in out else None,
+                                   retro_amp=out["ramp"].data_ptr() if "ramp" in out else None)
+        if ray_mask is not None:
+            out["ray_mask"] = ray_mask
+        _check(lib().sonar_batch_set_outputs(self._host.ctypes.data, self.n, i, _dptr(out.get("gbuffer")),
+                                             _dptr(out.get("incoh")), C.byref(rec) if rec is not None else None,
+                                             _dptr(ray_mask)))
+        self.desc = torch.from_numpy(self._host).cuda()
+        self.extras = getattr(self, "extras", {})
+        self.extras[i] = out
+        return out
 
     def detect(self, train=16, guard=4, max_per_beam=4, pfa=1e-4, noise_floor=1e-11):
         """Adds the point cloud of every ping: the CA-CFAR test in each ping's

@@ -65,3 +65,30 @@ def rel_l2(a, b) -> float:
     if nb == 0:
         return float(np.linalg.norm(a))
     return float(np.linalg.norm(a - b) / nb)
+
+
+def compare_points(pts, total, o, beams):
+    """GPU points vs the oracle's, beam by beam, skipping beams with a
+    threshold- or peak-flagged decision. Returns the number of beams compared."""
+    assert total == len(pts)
+    by_beam = {}
+    for p in pts:
+        by_beam.setdefault(int(p["beam"]), []).append(p)
+    compared = 0
+    for q, b in enumerate(beams):
+        if o["beam_flag"][q]:
+            continue
+        fb = o["flag_bins"][q]
+        ob = [x for x in o["bin"][q] if x >= 0]
+        gb = [int(p["bin"]) for p in by_beam.get(int(b), [])]
+        if any(fb[x] for x in set(ob) | set(gb)):
+            continue
+        assert gb == ob, (b, gb, ob)
+        for p, want in zip(by_beam.get(int(b), []), o["pts"][q]):
+            np.testing.assert_allclose([p["x"], p["y"], p["z"]], want[:3], atol=2e-5)
+            assert abs(p["db"] - want[3]) < 1e-3
+        compared += 1
+    # points come out in (beam, range) order
+    keys = pts["beam"].astype(np.int64) * 100000 + pts["bin"]
+    assert np.all(np.diff(keys) > 0)
+    return compared

@@ -193,3 +193,71 @@ def test_batch_detection_rejects_mismatched_parameters():
     with pytest.raises(sonar.SonarError) as e:
         batch.detect()
     assert e.value.status == sonar.SONAR_E_INVALID
+
+
+def test_batch_matches_oracle_multipath_harbor():
+    """Ten pings of the lawnmower trajectory over the 1,991,680-triangle
+    multipath scene (3 bounces, c(z) = 1500 + 0.05 z) in one persistent launch
+    with the fused CA-CFAR: mixed layouts (64 x 32 to 256 x 128 beams), 4-16
+    rays per beam and mixed bin counts (512, 777, 1,024). Each ping carries the
+    oracle's flagged rays as its mask and records its rays; 256 sampled beams
+    per ping are compared with the oracle ray by ray (triangle, bin and
+    visibility bit-exact, contributions) and column by column (volume,
+    G-buffer, incoherent channels), and every ping's point cloud with the
+    oracle's detection on the batch's own volume."""
+    import oracle
+    from tests.parity import compare_points, compare_rays, mask_words, ray_ids, rel_l2
+    torch, sonar = _gpu()
+    mesh = S.scene_harbor_multipath()
+    traj = S.lawnmower_batch()
+    pick = [0, 37, 70, 101, 128, 150, 190, 205, 231, 255]
+    bins = (1024, 512, 777)
+    items = [(traj[p][0].replace(n_range=bins[i % 3]), traj[p][1]) for i, p in enumerate(pick)]
+    layouts = {(c.n_h, c.rays_per_beam) for c, _ in items}
+    assert len({c.n_h for c, _ in items}) == 3 and len({c.rays_per_beam for c, _ in items}) == 3, layouts
+    sc = sonar.Scene(mesh)
+    osc = oracle.Scene(mesh)
+    batch = sonar.Batch(sc, items)
+    rng = np.random.Generator(np.random.PCG64(77))
+    orcs, sampled = [], []
+    for i, (cfg, pose) in enumerate(items):
+        beams = np.sort(rng.choice(cfg.n_beams, 256, replace=False))
+        orc = oracle.trace_beams(osc, cfg, pose, beams, want_incoh=True, want_gbuf=True)
+        rays = ray_ids(beams, cfg.rays_per_beam)
+        mask = torch.from_numpy(mask_words(cfg.n_rays, rays[orc["flags"] != 0])).cuda()
+        batch.set_outputs(i, gbuffer=True, incoh=True, record=True, ray_mask=mask)
+        orcs.append(orc)
+        sampled.append((beams, rays))
+    batch.detect()
+    batch.run(batch.options(blocks_per_cu=2, tiles_per_item=1))
+    torch.cuda.synchronize()
+    assert sc.status() == 0
+    flagged = total_rays = im_energy = 0
+    for i, (cfg, pose) in enumerate(items):
+        beams, rays = sampled[i]
+        orc = orcs[i]
+        ex = batch.extras[i]
+        g = {k: v.cpu().numpy() for k, v in ex.items() if k != "ray_mask"}
+        res = compare_rays(g, orc, rays)
+        for key in ("tri_mismatch", "bin_mismatch", "vis_mismatch"):
+            assert res[key] == 0, (i, res)
+        ok = orc["flags"] == 0
+        if np.abs(orc["amp"][ok]).sum() > 0:
+            assert rel_l2(g["amp"][rays][ok], orc["amp"][ok]) <= 1e-4, i
+        vol = batch.volumes[i].cpu().numpy().reshape(cfg.n_beams, cfg.n_range)
+        assert rel_l2(vol[beams], orc["col"]) <= 1e-4, (i, res)
+        inc = g["incoh"].reshape(2, cfg.n_beams, cfg.n_range)[:, beams]
+        assert rel_l2(inc[0], orc["incoh"][:, 0]) <= 1e-4, i
+        if orc["incoh"][:, 1].sum() > 0:
+            assert rel_l2(inc[1], orc["incoh"][:, 1]) <= 1e-4, i
+        im_energy += float(orc["incoh"][:, 1].sum())
+        assert np.abs(g["gbuffer"].reshape(cfg.n_beams, 8)[beams] - orc["gbuf"]).max() <= 1e-5, i
+        flagged += res["flagged"]
+        total_rays += res["rays"]
+        pts, n = batch.point_cloud(i)
+        o = oracle.detect(vol, cfg, pose, np.arange(cfg.n_beams))
+        compared = compare_points(pts, n, o, np.arange(cfg.n_beams))
+        assert compared >= 0.99 * cfg.n_beams, (i, compared)
+        _log("batch ping", i, cfg.n_h, cfg.n_v, cfg.rays_per_beam, cfg.n_range, "flagged", res["flagged"], "points", n)
+    assert im_energy > 0
+    assert flagged <= 0.01 * 5 * total_rays, (flagged, total_rays)

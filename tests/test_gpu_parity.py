@@ -8,7 +8,7 @@ import pytest
 import oracle
 from paper_2606_06130_amd import scenes as S
 from tests import meshes as M
-from tests.parity import compare_rays, mask_words, ray_ids, rel_l2
+from tests.parity import compare_points as _compare_points, compare_rays, mask_words, ray_ids, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -169,42 +169,16 @@ def test_surface_multipath_straight():
     assert res["im_energy"] > 0
 
 
-def test_harbor_full_size_sampled_beams():
+def test_harbor_full_size_every_ray():
     """601,088 triangles, 256 x 128 beams x 16 rays, 1,024 bins: the full ping
-    runs as benchmarked; 96 beams are compared ray by ray and column by column."""
+    as benchmarked, every one of its 524,288 rays compared with the oracle ray
+    by ray and every beam column by column (volume, G-buffer, incoherent
+    channel)."""
     mesh = S.scene_harbor()
     cfg, pose = S.sensor_harbor(), S.pose_harbor()
-    rng = np.random.Generator(np.random.PCG64(42))
-    beams = np.sort(rng.choice(cfg.n_beams, 96, replace=False))
-    res, g, orc = run_parity(mesh, cfg, pose, beams=beams)
+    res, g, orc = run_parity(mesh, cfg, pose)
     assert_parity(res)
-
-
-def _compare_points(pts, total, o, beams):
-    """GPU points vs the oracle's, beam by beam, skipping beams with a
-    threshold- or peak-flagged decision. Returns the number of beams compared."""
-    assert total == len(pts)
-    by_beam = {}
-    for p in pts:
-        by_beam.setdefault(int(p["beam"]), []).append(p)
-    compared = 0
-    for q, b in enumerate(beams):
-        if o["beam_flag"][q]:
-            continue
-        fb = o["flag_bins"][q]
-        ob = [x for x in o["bin"][q] if x >= 0]
-        gb = [int(p["bin"]) for p in by_beam.get(int(b), [])]
-        if any(fb[x] for x in set(ob) | set(gb)):
-            continue
-        assert gb == ob, (b, gb, ob)
-        for p, want in zip(by_beam.get(int(b), []), o["pts"][q]):
-            np.testing.assert_allclose([p["x"], p["y"], p["z"]], want[:3], atol=2e-5)
-            assert abs(p["db"] - want[3]) < 1e-3
-        compared += 1
-    # points come out in (beam, range) order
-    keys = pts["beam"].astype(np.int64) * 100000 + pts["bin"]
-    assert np.all(np.diff(keys) > 0)
-    return compared
+    assert res["rays"] == cfg.n_rays
 
 
 @pytest.mark.parametrize("n_range,train,guard,M", [
@@ -312,15 +286,29 @@ def test_scene_info_and_device_inputs():
     _log("harbor hierarchy", ia)
 
 
+def _scene_of(which):
+    if which == "harbor":
+        return S.scene_harbor(), S.sensor_harbor(), S.pose_harbor()
+    return S.scene_seabed_boxes(), S.sensor_seabed_boxes(), S.pose_seabed_boxes()
+
+
+def _by_beam(pts):
+    out = {}
+    for p in pts:
+        out.setdefault(int(p["beam"]), []).append(int(p["bin"]))
+    return out
+
+
 @pytest.mark.parametrize("which", ["harbor", "boxes"])
 def test_fused_ping_detect_matches_separate(which):
-    """sonar_ping_detect == sonar_ping + sonar_detect: same volume bits, same
-    points except decisions within 1e-9 relative of their threshold."""
+    """sonar_ping_detect == sonar_ping + sonar_detect: same volume bits; the
+    point lists of a beam differ only where a decision of the beam lies within
+    1e-6 relative of its CFAR threshold or of a neighbour's power (FP32
+    rounding of the power, FP64 order of the training sums), or the top-M
+    choice is that close: every differing beam is checked against the
+    oracle's flags computed from the shared volume."""
     torch, sonar = _gpu()
-    if which == "harbor":
-        mesh, cfg, pose = S.scene_harbor(), S.sensor_harbor(), S.pose_harbor()
-    else:
-        mesh, cfg, pose = S.scene_seabed_boxes(), S.sensor_seabed_boxes(), S.pose_seabed_boxes()
+    mesh, cfg, pose = _scene_of(which)
     sc = sonar.Scene(mesh)
     v1 = sonar.ping(sc, cfg, pose)["volume"]
     d1 = sonar.Detector(cfg)
@@ -331,13 +319,19 @@ def test_fused_ping_detect_matches_separate(which):
     d2.ping_detect(sc, v2, pose)
     p2, n2 = d2.fetch()
     assert torch.equal(v1.view(torch.float32), v2.view(torch.float32))
-    _log(which, "detections", n1, n2)
     assert n1 > 0
-    assert abs(n1 - n2) <= max(2, n1 // 10000)
-    k1 = set(zip(p1["beam"].tolist(), p1["bin"].tolist()))
-    k2 = set(zip(p2["beam"].tolist(), p2["bin"].tolist()))
-    assert len(k1 ^ k2) <= max(4, n1 // 5000)
-    common = sorted(k1 & k2)
+    b1, b2 = _by_beam(p1), _by_beam(p2)
+    differ = sorted(b for b in set(b1) | set(b2) if b1.get(b, []) != b2.get(b, []))
+    _log(which, "detections", n1, n2, "beams that differ", len(differ))
+    if differ:
+        v = v1.cpu().numpy().reshape(cfg.n_beams, cfg.n_range)
+        o = oracle.detect(v, cfg, pose, np.array(differ), rel_thr=1e-6, rel_peak=1e-6)
+        for q, b in enumerate(differ):
+            bins = set(b1.get(b, [])) ^ set(b2.get(b, []))
+            assert o["beam_flag"][q] or any(o["flag_bins"][q][x] for x in bins) or \
+                set(b1.get(b, [])) == set(b2.get(b, [])), (b, b1.get(b), b2.get(b))
+    common = sorted(set(zip(p1["beam"].tolist(), p1["bin"].tolist())) & set(zip(p2["beam"].tolist(),
+                                                                                 p2["bin"].tolist())))
     i1 = {k: i for i, k in enumerate(zip(p1["beam"].tolist(), p1["bin"].tolist()))}
     i2 = {k: i for i, k in enumerate(zip(p2["beam"].tolist(), p2["bin"].tolist()))}
     a = p1[[i1[k] for k in common]]
@@ -346,6 +340,29 @@ def test_fused_ping_detect_matches_separate(which):
         np.testing.assert_array_equal(a[f], b[f])
     # the FP32 power may differ in its last bit (fused multiply-add contraction)
     np.testing.assert_allclose(a["db"], b["db"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("which", ["harbor", "boxes"])
+def test_fused_ping_detect_matches_oracle(which):
+    """The fused call's points against the oracle's detection on the fused
+    call's own volume, every beam: identical bins, positions and powers on
+    every beam without a flagged decision (within 1e-4 of a threshold or 1e-6
+    of a neighbour); flagged beams are counted."""
+    torch, sonar = _gpu()
+    mesh, cfg, pose = _scene_of(which)
+    sc = sonar.Scene(mesh)
+    vol = torch.empty(sonar.beams_of(cfg) + (cfg.n_range,), dtype=torch.complex64, device="cuda")
+    det = sonar.Detector(cfg)
+    det.ping_detect(sc, vol, pose)
+    pts, total = det.fetch()
+    v = vol.cpu().numpy().reshape(cfg.n_beams, cfg.n_range)
+    beams = np.arange(cfg.n_beams)
+    o = oracle.detect(v, cfg, pose, beams)
+    compared = _compare_points(pts, total, o, beams)
+    skipped = cfg.n_beams - compared
+    _log(which, "fused CFAR vs oracle: points", total, "beams compared", compared, "flagged beams", skipped)
+    assert total > 0
+    assert skipped <= max(0.01 * cfg.n_beams, 2)
 
 
 # ---------------------------------------------------------------------------
@@ -382,16 +399,16 @@ def test_multibounce_gradient_seabed_boxes():
     assert_parity(res)
 
 
-def test_harbor_multipath_full_size_sampled_beams():
+def test_harbor_multipath_full_size_every_ray():
     """1,991,680 triangles (wall, seabed, surface, 50 piles), 3 bounces, Phong-20
     + diffuse, c(z) = 1500 + 0.05 z, 256 x 128 beams x 16 rays, 1,024 bins: the
-    full ping runs; 40 beams are compared ray by ray, bounce by bounce."""
+    full ping, every ray compared bounce by bounce and every beam column by
+    column."""
     mesh = S.scene_harbor_multipath()
     cfg, pose = S.sensor_harbor_multipath(), S.pose_harbor()
-    rng = np.random.Generator(np.random.PCG64(43))
-    beams = np.sort(rng.choice(cfg.n_beams, 40, replace=False))
-    res, g, orc = run_parity(mesh, cfg, pose, beams=beams)
-    assert_parity(res)
+    res, g, orc = run_parity(mesh, cfg, pose)
+    assert_parity(res, bounces=3)
+    assert res["rays"] == cfg.n_rays
     assert res["im_energy"] > 0
 
 
