@@ -334,6 +334,27 @@ sonar_status sonar_ping_detect(const sonar_scene *scene, const sonar_params *par
                                const sonar_cfar *cfar, sonar_cf32 *volume, sonar_point *points, int32_t capacity,
                                int32_t *dev_count, void *workspace, size_t workspace_bytes, sonar_stream stream);
 
+/* sonar_ping_detect without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation). The detection workspace (and, for receive
+ * binning with several bounces, the list of moved returns) lives in a
+ * static device array of SONAR_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends; the call itself allocates
+ * nothing. Outputs, results and asynchrony as sonar_ping_detect (identical
+ * volume bits and points). Every call on one GPU shares that GPU's array
+ * and leaves its contents behind (nothing in it needs clearing: each call
+ * writes what it reads), so calls that overlap in time on one GPU (on
+ * several streams, or from several threads without ordering) race and must
+ * be serialised by the caller. The scene's device must be current.
+ * SONAR_E_INVALID when the parameters need more scratch than the array holds
+ * (about 63,000 beams without receive binning) or for any argument
+ * sonar_ping_detect rejects; SONAR_E_DEVICE if the array's address cannot
+ * be resolved. */
+#define SONAR_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+sonar_status sonar_ping_detect_noalloc(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
+                                       const sonar_cfar *cfar, sonar_cf32 *volume, sonar_point *points,
+                                       int32_t capacity, int32_t *dev_count, sonar_stream stream);
+
 /* ---------------------------------------------------------------------- */
 /* Water-column volume reverberation and receiver noise (Sec. II-B:
  * volumetric backscatter paths from the water column; speckle). Every range

@@ -11,6 +11,7 @@
 
 #include <stdlib.h>
 
+#include <mutex>
 #include <string>
 
 struct sonar_scene {
@@ -291,6 +292,39 @@ sonar_status fill_detect_args(const sonar_cf32 *volume, const sonar_params *p, c
 
 }  // namespace
 
+// Device scratch of sonar_ping_detect_noalloc: the detection workspace (and a
+// receive-binning list) of one call, held by every GPU the library runs on
+// until the process ends. Host code never uses the array's name as an
+// address: each device's copy is resolved once through hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[SONAR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_SCRATCH_DEVICES] = {};
+
+// The address of the current device's scratch (resolved on its first use).
+sonar_status device_scratch(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_SCRATCH_DEVICES) return fail(SONAR_E_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SONAR_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SONAR_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sonar_last_error(void) { return g_err; }
@@ -557,7 +591,8 @@ sonar_status sonar_detect(const sonar_cf32 *volume, const sonar_params *p, const
     return SONAR_OK;
 }
 
-// Ping + detection into a given workspace.
+// Ping + detection into a given workspace (the caller's, or the static
+// scratch of the allocation-free entry point).
 static sonar_status ping_detect_into(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q,
                                      const sonar_cfar *c, sonar_cf32 *volume, sonar_point *points, int32_t capacity,
                                      int32_t *dev_count, void *workspace, size_t ws_bytes, hipStream_t s)
@@ -609,6 +644,30 @@ sonar_status sonar_ping_detect(const sonar_scene *sc, const sonar_params *p, con
 {
     g_err[0] = 0;
     return ping_detect_into(sc, p, q, c, volume, points, capacity, dev_count, workspace, ws_bytes,
+                            (hipStream_t)stream);
+}
+
+sonar_status sonar_ping_detect_noalloc(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q,
+                                       const sonar_cfar *c, sonar_cf32 *volume, sonar_point *points,
+                                       int32_t capacity, int32_t *dev_count, sonar_stream stream)
+{
+    g_err[0] = 0;
+    if (!sc) return fail(SONAR_E_INVALID, "scene is NULL");
+    sonar_status st = check_params(p);
+    if (st != SONAR_OK) return st;
+    const size_t need = det_bytes(p) + (needs_rx_list(p) ? rx_bytes(p) : 0);
+    if (need > SONAR_NOALLOC_SCRATCH_BYTES)
+        return fail(SONAR_E_INVALID, "these parameters need %zu bytes of scratch, more than the %zu of "
+                                     "sonar_ping_detect_noalloc (use sonar_ping_detect with a workspace)",
+                    need, (size_t)SONAR_NOALLOC_SCRATCH_BYTES);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev != sc->s.device) return fail(SONAR_E_INVALID, "the scene's device (%d) must be current, not %d",
+                                         sc->s.device, dev);
+    void *ws = nullptr;
+    if ((st = device_scratch(&ws)) != SONAR_OK) return st;
+    return ping_detect_into(sc, p, q, c, volume, points, capacity, dev_count, ws, SONAR_NOALLOC_SCRATCH_BYTES,
                             (hipStream_t)stream);
 }
 

@@ -40,7 +40,7 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
            "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb",
            "sonar_ping_ssp", "sonar_ping_ssp_rx", "sonar_batch_prepare_ssp", "sonar_batch_rx_workspace_size",
-           "sonar_batch_prepare_rx", "sonar_batch_set_outputs")
+           "sonar_batch_prepare_rx", "sonar_batch_set_outputs", "sonar_ping_detect_noalloc")
 
 
 class SonarError(RuntimeError):
@@ -145,6 +145,9 @@ def lib():
         L.sonar_ping_detect.restype = C.c_int
         L.sonar_ping_detect.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_cfar), C.c_void_p,
                                         C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.sonar_ping_detect_noalloc.restype = C.c_int
+        L.sonar_ping_detect_noalloc.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_cfar),
+                                                C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.sonar_device_status.restype = C.c_int
         L.sonar_device_status.argtypes = [C.c_void_p, C.c_void_p]
         L.sonar_status_string.restype = C.c_char_p
@@ -454,6 +457,16 @@ class Detector:
         st = lib().sonar_ping_detect(scene.handle, C.byref(self.params), C.byref(q), C.byref(self.cfar),
                                      _dptr(volume), _dptr(self.points), self.capacity, _dptr(self.count),
                                      _dptr(self.workspace), self.workspace.numel(), _stream(stream))
+        _check(st)
+        return self.points, self.count
+
+    def ping_detect_noalloc(self, scene: "Scene", volume, pose, stream=None, pose_s=None):
+        """As ping_detect, through the allocation-free entry point (the
+        library's per-GPU static scratch instead of this detector's workspace)."""
+        q = pose_s if pose_s is not None else pose_of(pose)
+        st = lib().sonar_ping_detect_noalloc(scene.handle, C.byref(self.params), C.byref(q), C.byref(self.cfar),
+                                             _dptr(volume), _dptr(self.points), self.capacity, _dptr(self.count),
+                                             _stream(stream))
         _check(st)
         return self.points, self.count
 
