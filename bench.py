@@ -37,6 +37,34 @@ def _src_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+MP_PMC_FILE = os.path.join(ROOT, "profiles", "multipath_ping_staged_kernels_counters.json")
+BATCH_PMC_FILE = os.path.join(ROOT, "profiles", "batch_lawnmower_persistent_kernel_counters.json")
+SRC_DIR = os.path.join(ROOT, "paper_2606_06130_amd", "csrc")
+
+
+def _sources_hash():
+    """Hash of the kernel sources (a counter summary stays valid while they do)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(SRC_DIR)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(SRC_DIR, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_of(path, alg_bytes):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel sources changed since it was taken."""
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("sources_sha256_16") != _sources_hash():
+        return None
+    return d.get("derived", {}).get("hbm_bytes_per_launch")
+
+
 def _traffic(n_launch_bytes_alg):
     """HBM bytes per ping launch from the committed rocprofv3 counter summary,
     or None if the kernel source changed since the counters were taken."""
@@ -96,9 +124,11 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(mesh, cfg, pose, budget_s=10.0, single_budget_s=3.0):
-    """The oracle as it stands, brute force, on bounded random samples of
-    beams: with up to 16 host threads, and on one thread."""
+def cpu_baseline(mesh, cfg, pose, budget_s=12.0, single_budget_s=3.0, brute_budget_s=4.0):
+    """The oracle as it stands (its exact uniform-grid candidate filter on,
+    as for any scene of this size) on bounded random samples of beams: with
+    up to 16 host threads (the main figure), on one thread, and the
+    brute-force loop over every triangle on a small sample."""
     import numpy as np
 
     import oracle
@@ -107,28 +137,86 @@ def cpu_baseline(mesh, cfg, pose, budget_s=10.0, single_budget_s=3.0):
     rng = np.random.Generator(np.random.PCG64(123))
     order = rng.permutation(cfg.n_beams)
 
-    def sample(n_threads, budget):
+    def sample(scene, n_threads, budget, chunk0):
         done, t0 = 0, time.perf_counter()
-        chunk = 4 if n_threads == 1 else 16
+        chunk = chunk0
         while True:
-            oracle.trace_beams(sc, cfg, pose, order[done:done + chunk], threads=n_threads, want_all=False)
+            oracle.trace_beams(scene, cfg, pose, order[done:done + chunk], threads=n_threads, want_all=False)
             done += chunk
             el = time.perf_counter() - t0
             if el >= budget or done >= cfg.n_beams:
                 return done, el
-            chunk = min(chunk * 2, 256)
+            chunk = min(chunk * 2, 4096)
 
-    done, el = sample(threads, budget_s)
+    done, el = sample(sc, threads, budget_s, 256)
     rays = done * cfg.rays_per_beam
-    done1, el1 = sample(1, single_budget_s)
+    done1, el1 = sample(sc, 1, single_budget_s, 16)
     rays1 = done1 * cfg.rays_per_beam
+    brute = oracle.Scene(mesh, grid=False)
+    doneb, elb = sample(brute, threads, brute_budget_s, 16)
+    raysb = doneb * cfg.rays_per_beam
     return {"value": rays / cfg.n_rays / el, "unit": "pings/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} random beams x {cfg.rays_per_beam} rays ({rays} rays) of the harbor ping, brute force "
-                      f"FP64 in {el:.1f} s on {threads} threads, scaled to one {cfg.n_rays}-ray ping",
+            "sample": f"{done} random beams x {cfg.rays_per_beam} rays ({rays} rays) of the harbor ping, FP64 oracle "
+                      f"(exact grid candidate filter) in {el:.1f} s on {threads} threads, scaled to one "
+                      f"{cfg.n_rays}-ray ping",
             "mrays_per_s": rays / el / 1e6,
             "single_thread": {"pings_per_s": rays1 / cfg.n_rays / el1, "mrays_per_s": rays1 / el1 / 1e6,
                               "sample": f"{done1} beams ({rays1} rays) in {el1:.1f} s"},
+            "brute_force": {"pings_per_s": raysb / cfg.n_rays / elb, "mrays_per_s": raysb / elb / 1e6,
+                            "threads": threads,
+                            "sample": f"{doneb} beams ({raysb} rays) in {elb:.1f} s, every triangle tested per query"},
             "cpu_model": _cpu_model()}
+
+
+def parity_sample(torch, sonar, np, scene, mesh, cfg, pose, n_beams, seed, staged=False):
+    """Part of the CPU-baseline leg: one sampled parity check outside the
+    timed regions. The oracle traces n_beams random beams; the full ping runs
+    on the GPU with the oracle's flagged rays masked and its per-ray record;
+    hit triangle, bin and visibility are compared bit for bit on every
+    unflagged sampled ray, and the sampled columns (volume, G-buffer,
+    incoherent channels) to relative L2. Flagged rays are counted by reason."""
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(seed))
+    beams = np.sort(rng.choice(cfg.n_beams, n_beams, replace=False))
+    t0 = time.perf_counter()
+    orc = oracle.trace_beams(oracle.Scene(mesh), cfg, pose, beams, want_incoh=True, want_gbuf=True, want_all=False)
+    t_orc = time.perf_counter() - t0
+    rays = (beams[:, None] * cfg.rays_per_beam + np.arange(cfg.rays_per_beam)[None, :]).reshape(-1)
+    flagged = rays[orc["flags"] != 0]
+    words = np.zeros((cfg.n_rays + 31) // 32, np.uint32)
+    np.bitwise_or.at(words, flagged >> 5, (np.uint32(1) << (flagged & 31).astype(np.uint32)))
+    out = sonar.ping(scene, cfg, pose, gbuffer=True, incoh=True, record=True,
+                     ray_mask=torch.from_numpy(words).cuda(), staged=staged)
+    torch.cuda.synchronize()
+    ok = orc["flags"] == 0
+    res = {"beams": int(n_beams), "rays": int(rays.size), "oracle_s": t_orc}
+    for key in ("tri", "bin", "vis"):
+        g = out[key].cpu().numpy()[rays][ok]
+        o = orc[key][ok]
+        if key == "vis":
+            has = orc["tri"][ok] >= 0
+            g, o = np.where(has, g, 0), np.where(has, o, 0)
+        res[key + "_mismatch_rays"] = int((g != o).any(axis=1).sum())
+
+    def rel(a, b):
+        a, b = np.asarray(a, np.complex128), np.asarray(b, np.complex128)
+        nb = np.linalg.norm(b)
+        return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+    nb, NB = cfg.n_beams, cfg.n_range
+    res["volume_rel_l2"] = rel(out["volume"].cpu().numpy().reshape(nb, NB)[beams], orc["col"])
+    inc = out["incoh"].cpu().numpy().reshape(2, nb, NB)[:, beams]
+    res["i1_rel_l2"] = rel(inc[0], orc["incoh"][:, 0])
+    if orc["incoh"][:, 1].sum() > 0:
+        res["im_rel_l2"] = rel(inc[1], orc["incoh"][:, 1])
+    res["gbuffer_max_abs"] = float(np.abs(out["gbuffer"].cpu().numpy().reshape(nb, 8)[beams] - orc["gbuf"]).max())
+    res["contrib_rel_l2"] = rel(out["amp"].cpu().numpy()[rays][ok], orc["amp"][ok])
+    fl = orc["flags"]
+    res["flagged_rays"] = int((fl != 0).sum())
+    res["flagged_fraction"] = float((fl != 0).mean())
+    res["flagged_by_reason"] = {nm: int(((fl >> i) & 1).sum()) for i, nm in enumerate(oracle.FLAG_NAMES)
+                                if ((fl >> i) & 1).any()}
+    res["tolerances"] = "indices bit-exact on unflagged rays; volume, channels, contributions <= 1e-4 relative L2"
+    return res
 
 
 def multipath_and_batch(torch, sonar, S, np, replays=5):
@@ -140,17 +228,22 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     scene = sonar.Scene(mesh)
     cfg, pose = S.sensor_harbor_multipath(), S.pose_harbor()
     out = sonar.alloc_outputs(cfg)
-    for _ in range(3):
-        sonar.ping(scene, cfg, pose, out=out)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
-    for a, b in ev:
-        a.record(stream)
-        sonar.ping(scene, cfg, pose, out=out)
-        b.record(stream)
-    torch.cuda.synchronize()
-    assert scene.status() == 0
-    mp_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    def timed(fn, n=10, warm=3):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        assert scene.status() == 0
+        return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+    mp_ms = timed(lambda: sonar.ping(scene, cfg, pose, out=out, staged=True))
+    fused_ms = timed(lambda: sonar.ping(scene, cfg, pose, out=out))
     trav = traversal_work(torch, sonar, np, scene, cfg, pose)
     trav["visit_gbs"] = trav["visit_bytes_per_ping"] / (mp_ms * 1e-3) / 1e9
     trav["note"] = "all traversals of a ray (up to 3 nearest-hit and 2 any-hit connection queries)"
@@ -201,9 +294,23 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     assert scene.status() == 0
     retro_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     del out_r
+    info = scene.info()
+    scene_bytes = info["node_bytes"] + info["tri_bytes"]
+    mp_alg = cfg.n_beams * cfg.n_range * 8 + scene_bytes
     multipath = {"workload": "harbor multipath ping: 1,991,680 triangles, 256x128 beams x 16 rays, 3 bounces, "
                              "Phong-20 + diffuse, c(z) = 1500 + 0.05 z, 1,024 bins",
+                 "roofline": {"bound": "hbm", "kernel": "staged multipath ping (3 nearest-hit, 2 visibility and the "
+                                                         "accumulation kernel)",
+                              "achieved": mp_alg / (mp_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": mp_alg / (mp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "traffic": _traffic_of(MP_PMC_FILE, mp_alg),
+                              "alg_bytes_per_launch": mp_alg,
+                              "alg_bytes_note": "volume write (beams x bins x 8 B) + the scene's node and triangle "
+                                                "arrays; duration from events around the ping call (all its kernels)"},
                  "ping_ms": mp_ms, "pings_per_s": 1e3 / mp_ms, "mrays_per_s": cfg.n_rays / mp_ms / 1e3,
+                 "kernels": "staged: one kernel per bounce's nearest-hit traversal and per bounce's visibility "
+                            "traversal, FP64 ray state through a workspace, then the per-beam accumulation",
+                 "fused_kernel_ping_ms": fused_ms,
                  "traversal": trav,
                  "beam_pattern_rx_binning": {"ping_ms": rx_ms, "moved_returns": moved,
                                              "note": "same ping with the Gaussian transmit-receive pattern and "
@@ -280,6 +387,8 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     lat = np.concatenate(lat)
     points = int(batch.counts.sum().item())
     g.close()
+    vol_bytes = sum(int(v.numel()) * 8 for v in batch.volumes)
+    b_alg = vol_bytes + scene_bytes + 24 * points
     res = {"workload": "256 pings on a lawnmower path over the multipath scene, layouts {64x32,128x64,256x128} x "
                        "{4,8,16} rays, 3 bounces, gradient; CA-CFAR (16 train, 4 guard, 4 per beam) in the ping "
                        "kernel; one graph: queue reset, persistent ping launch, batched point emission",
@@ -287,7 +396,15 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
            "pings_per_s": batch.n / rep_ms * 1e3, "mrays_per_s": batch.plan.total_rays / rep_ms / 1e3,
            "points": points, "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
            "autotuned": {"blocks_per_cu": best.blocks_per_cu, "tiles_per_item": best.tiles_per_item,
-                         "ms": tune_ms}}
+                         "ms": tune_ms},
+           "roofline": {"bound": "hbm", "kernel": "graph replay: queue reset, persistent ping kernel, batched "
+                                                  "point emission",
+                        "achieved": b_alg / (rep_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": b_alg / (rep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": _traffic_of(BATCH_PMC_FILE, b_alg),
+                        "alg_bytes_per_launch": b_alg,
+                        "alg_bytes_note": "the 256 volumes (beams x bins x 8 B each) + the scene's node and "
+                                          "triangle arrays + the points (24 B each); duration = median replay"}}
     del batch
     return multipath, res
 
@@ -360,6 +477,29 @@ def layered_ping(torch, sonar, np, scene, cfg, pose, reps=10):
             "pings_per_s": 1e3 / ms}
 
 
+def profile_case(torch, sonar, S, case, steps, warmup):
+    """One workload alone, for profiler runs: the harbor multipath ping on
+    one stream, or graph replays of the 256-ping lawnmower batch with CFAR."""
+    scene = sonar.Scene(S.scene_harbor_multipath())
+    if case in ("multipath", "multipath_fused", "multipath_straight"):
+        cfg, pose = S.sensor_harbor_multipath(), S.pose_harbor()
+        if case == "multipath_straight":
+            cfg = cfg.replace(c_grad=0.0)
+        out = sonar.alloc_outputs(cfg)
+        staged = case != "multipath_fused"
+        run = lambda: sonar.ping(scene, cfg, pose, out=out, staged=staged)     # noqa: E731
+    else:
+        batch = sonar.Batch(scene, S.lawnmower_batch())
+        batch.detect()
+        g = batch.graph(batch.options(blocks_per_cu=3, tiles_per_item=1))
+        run = g.launch
+    for i in range(warmup + steps):
+        run()
+        torch.cuda.synchronize()
+        print(f"{case} {i + 1}/{warmup + steps}", flush=True)
+    assert scene.status() == 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,6 +512,8 @@ def main():
     ap.add_argument("--latency-steps", type=int, default=50, help="single-stream pings timed one by one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for counter calibration) and exit")
+    ap.add_argument("--case", choices=("multipath", "multipath_fused", "multipath_straight", "batch"), default=None,
+                    help="run only this workload --steps times after --warmup (for profiler runs) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path (independent pings would "
@@ -398,6 +540,10 @@ def main():
 
     from paper_2606_06130_amd import scenes as S
     from paper_2606_06130_amd import sonar
+
+    if args.case:
+        profile_case(torch, sonar, S, args.case, args.steps, args.warmup)
+        return
 
     mesh = S.scene_harbor()
     cfg, pose = S.sensor_harbor(), S.pose_harbor()
@@ -540,6 +686,14 @@ def main():
         res["batch"] = bt
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(mesh, cfg, pose)
+        par = {"harbor_ping": parity_sample(torch, sonar, np, scene, mesh, cfg, pose, 4096, 11)}
+        if not args.no_extras:
+            mmesh = S.scene_harbor_multipath()
+            mscene = sonar.Scene(mmesh)
+            par["multipath_ping"] = parity_sample(torch, sonar, np, mscene, mmesh, S.sensor_harbor_multipath(),
+                                                  S.pose_harbor(), 1024, 12, staged=True)
+            del mscene
+        res["cpu_baseline"]["parity"] = par
     print(json.dumps(res))
 
 

@@ -211,7 +211,10 @@ typedef struct {
     int64_t tri_bytes;      /* bytes of the triangle array */
 } sonar_scene_info;
 
-/* Builds the ray-traversal hierarchy of a mesh (linear BVH: Morton codes of
+/* Builds the scene a ping traces (Sec. II-B: the simulation engine supplies
+ * the geometry and per-material metadata; Sec. II-A: rays are cast in
+ * parallel through it): the triangle records with their reflectivity, phase
+ * and material, and the ray-traversal hierarchy (linear BVH: Morton codes of
  * triangle centroids, radix sort, binary radix tree, bottom-up bounds, then
  * 4-wide nodes from every second binary level).
  * Synchronous on `stream`. Returns SONAR_E_INVALID for null pointers,
@@ -301,9 +304,39 @@ sonar_status sonar_ping_rx(const sonar_scene *scene, const sonar_params *params,
                            sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *record,
                            const uint32_t *ray_mask, void *workspace, size_t workspace_bytes, sonar_stream stream);
 
-/* Bytes of device workspace sonar_detect needs for these parameters (with
- * SONAR_FLAG_RX_BEAMS and several bounces it includes the receive-binning
- * list, so that sonar_ping_detect can use it). */
+/* Bytes of device workspace a ping with a workspace (sonar_ping_ws) needs
+ * for these parameters, times n_pings (one area per ping in flight at once):
+ * with several bounces, the per-ray state of the staged kernels (80 bytes
+ * per ray), the winner of each traversal (8 bytes per ray), the pending
+ * connection queries (64 bytes per ray) and the
+ * contribution slots (20 bytes per ray and contribution: K, or 2K - 1 with
+ * retro-chain returns; plus 4 bytes per ray and bounce for receive beams),
+ * and the receive-binning list when SONAR_FLAG_RX_BEAMS needs it. 0 for a
+ * single bounce without receive binning (no workspace needed), for a null
+ * scene, n_pings < 1 or invalid parameters. */
+size_t sonar_workspace_size(const sonar_scene *scene, const sonar_params *params, int32_t n_pings);
+
+/* sonar_ping with a workspace (device memory of at least
+ * sonar_workspace_size(scene, params, 1) bytes, 256-byte aligned, owned by
+ * the caller, one ping at a time per area). With several bounces the ping
+ * runs in stages (Sec. II-B: a bounded number of secondary reflections):
+ * each bounce's nearest-hit traversal and each return path's visibility
+ * traversal is a kernel over all rays, the FP64 ray state passing between
+ * them through the workspace, and a last kernel reduces the contributions
+ * into the columns in the fixed order of sonar_ping: records are identical
+ * and volumes equal up to FP32 rounding. A request for traversal counters
+ * (record->stats) runs the fused kernel. Otherwise as sonar_ping (and
+ * sonar_ping_rx for receive binning). Asynchronous on `stream`; no
+ * allocation. */
+sonar_status sonar_ping_ws(const sonar_scene *scene, const sonar_params *params, const sonar_pose *pose,
+                           sonar_cf32 *volume, float *gbuffer, float *incoh, const sonar_ray_record *record,
+                           const uint32_t *ray_mask, void *workspace, size_t workspace_bytes, sonar_stream stream);
+
+/* Bytes of device workspace sonar_detect needs for these parameters; with
+ * several bounces it also holds the receive-binning list (with
+ * SONAR_FLAG_RX_BEAMS) and the staged kernels' buffers, so that
+ * sonar_ping_detect runs the staged ping (a smaller workspace that still
+ * holds the detection and list areas runs the fused kernel). */
 size_t sonar_detect_workspace_size(const sonar_params *params);
 
 /* Per-beam CA-CFAR detection of a volume into a point cloud (Sec. II-A: an
@@ -392,6 +425,16 @@ sonar_status sonar_add_reverb(sonar_cf32 *volume, const sonar_params *params, co
 
 #define SONAR_MAX_PULSE_TAPS 64
 #define SONAR_MAX_PULSE_BINS 2048
+
+/* Two-way delay spacing of a ping's range bins (the time axis its volume
+ * columns sample): dt = 2 dr / c_ref, dr = (r_max - r_min) / n_range, with
+ * c_ref the sound speed at the sensor depth that converts travel time to
+ * range in the ping (c0 + c_grad z_sensor, or the layered profile `ssp` at
+ * z_sensor when it is not NULL).
+ *   dt  host double, receives the spacing (s)
+ * SONAR_E_INVALID for invalid parameters, pose or profile, a non-positive
+ * speed at the sensor, or dt NULL. Host only. */
+sonar_status sonar_pulse_dt(const sonar_params *params, const sonar_pose *pose, const sonar_ssp *ssp, double *dt);
 
 /* Baseband linear-FM pulse of bandwidth B over `duration`:
  * L = max(1, round(duration / dt)) samples at t_k = (k + 1/2) dt - L dt / 2,

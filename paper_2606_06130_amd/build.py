@@ -1,6 +1,7 @@
 """Compiles the HIP library ``libsonar.so`` for gfx950 with hipcc, in-tree.
 
-Usage: ``python -m paper_2606_06130_amd.build``.
+Usage: ``python -m paper_2606_06130_amd.build`` (``--changed``: only sources
+whose object is older than the source or a header).
 """
 from __future__ import annotations
 
@@ -14,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsonar.so")
-SOURCES = ["bvh_build.hip", "ping.hip", "detect.hip", "pulse.hip", "reverb.hip", "surrogate.hip", "capi.hip"]
-HEADERS = ["internal.hpp", os.path.join("..", "..", "include", "sonar.h")]
+SOURCES = ["bvh_build.hip", "ping.hip", "staged.hip", "detect.hip", "pulse.hip", "reverb.hip", "surrogate.hip", "capi.hip"]
+HEADERS = ["internal.hpp", "trace.hpp", os.path.join("..", "..", "include", "sonar.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SONAR_OFFLOAD_ARCH", "gfx950")
@@ -34,10 +35,23 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def _stale(src: str) -> bool:
+    obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in HEADERS]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = True, changed_only: bool = False) -> str:
+    """Compiles every source (or, with `changed_only`, those whose object is
+    older than the source or a header) and links the library."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    todo = [s for s in SOURCES if _stale(s)] if changed_only else list(SOURCES)
+    with cf.ThreadPoolExecutor(max_workers=min(4, max(1, len(todo)))) as ex:
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OUT_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,5 +64,5 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(changed_only="--changed" in sys.argv[1:])
     sys.exit(0)

@@ -137,12 +137,28 @@ static void set_rx_area(sonar::PingArgs &a, const sonar_params *p, void *area)
     a.rx_cap = (uint32_t)(a.n_rays * (p->max_bounces - 1));
 }
 
+// Staged multi-bounce buffers of one ping: 0 for a single bounce (the
+// fused kernel always applies then).
+static size_t staged_bytes(const sonar_params *p)
+{
+    if (p->max_bounces < 2) return 0;
+    const int64_t rays = (int64_t)beams_h_of(p) * beams_v_of(p) * p->rays_per_beam;
+    return sonar::staged_workspace_bytes(rays, p->max_bounces, (p->flags & SONAR_FLAG_RETRO_CHAIN) != 0,
+                                         (p->flags & SONAR_FLAG_RX_BEAMS) != 0);
+}
+
+// The ping kernels: staged when their area is set, else the fused kernel.
+static hipError_t launch_any(const sonar::PingArgs &a, int stack, hipStream_t s)
+{
+    return a.stg_state ? sonar::launch_ping_staged(a, stack, s) : sonar::launch_ping(a, stack, s);
+}
+
 // reset -> ping -> scatter of the moved returns (or the plain ping)
 static hipError_t launch_ping_rx(const sonar::PingArgs &a, int stack, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     if (a.rx_list) e = sonar::launch_rx_reset(a.rx_count, s);
-    if (e == hipSuccess) e = sonar::launch_ping(a, stack, s);
+    if (e == hipSuccess) e = launch_any(a, stack, s);
     if (e == hipSuccess && a.rx_list) e = sonar::launch_rx_scatter(a, s);
     return e;
 }
@@ -566,16 +582,53 @@ sonar_status sonar_ping_rx(const sonar_scene *sc, const sonar_params *p, const s
     return SONAR_OK;
 }
 
+size_t sonar_workspace_size(const sonar_scene *sc, const sonar_params *p, int32_t n_pings)
+{
+    if (!sc || n_pings < 1 || check_params(p) != SONAR_OK) return 0;
+    const size_t one = (needs_rx_list(p) ? ((rx_bytes(p) + 255) & ~(size_t)255) : 0) + staged_bytes(p);
+    return one * (size_t)n_pings;
+}
+
+sonar_status sonar_ping_ws(const sonar_scene *sc, const sonar_params *p, const sonar_pose *q, sonar_cf32 *volume,
+                           float *gbuffer, float *incoh, const sonar_ray_record *rec, const uint32_t *ray_mask,
+                           void *workspace, size_t ws_bytes, sonar_stream stream)
+{
+    g_err[0] = 0;
+    sonar::PingArgs a;
+    sonar_status st = fill_ping_args(sc, p, q, volume, gbuffer, incoh, rec, ray_mask, &a);
+    if (st != SONAR_OK) return st;
+    const size_t need = sonar_workspace_size(sc, p, 1);
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(SONAR_E_INVALID, "workspace smaller than sonar_workspace_size()");
+    if (need > 0 && ((uintptr_t)workspace & 255) != 0) return fail(SONAR_E_INVALID, "workspace must be 256-byte aligned");
+    char *w = reinterpret_cast<char *>(workspace);
+    if (needs_rx_list(p)) {
+        set_rx_area(a, p, w);
+        w += (rx_bytes(p) + 255) & ~(size_t)255;
+    }
+    // the counting kernels are fused ones: with counters the staged area stays unused
+    if (staged_bytes(p) > 0 && !a.stats) sonar::set_staged_area(a, w);
+    hipError_t e = launch_ping_rx(a, sc->s.stack, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping launch: %s", hipGetErrorString(e));
+    return SONAR_OK;
+}
+
 // detection workspace, then (receive binning with several bounces) the list area
 static size_t det_bytes(const sonar_params *p)
 {
     return (sonar::detect_workspace_bytes(beams_h_of(p) * beams_v_of(p), 16) + 255) & ~(size_t)255;
 }
 
+// rx list area rounded so that a staged area after it stays aligned
+static size_t rx_bytes_aligned(const sonar_params *p)
+{
+    return needs_rx_list(p) ? (rx_bytes(p) + 255) & ~(size_t)255 : 0;
+}
+
 size_t sonar_detect_workspace_size(const sonar_params *p)
 {
     if (check_params(p) != SONAR_OK) return 0;
-    return det_bytes(p) + (needs_rx_list(p) ? rx_bytes(p) : 0);
+    return det_bytes(p) + rx_bytes_aligned(p) + staged_bytes(p);
 }
 
 sonar_status sonar_detect(const sonar_cf32 *volume, const sonar_params *p, const sonar_pose *q,
@@ -603,6 +656,10 @@ static sonar_status ping_detect_into(const sonar_scene *sc, const sonar_params *
     sonar::DetectArgs da;
     st = fill_detect_args(volume, p, q, c, points, capacity, dev_count, workspace, ws_bytes, &da);
     if (st != SONAR_OK) return st;
+    // several bounces with a workspace that holds the staged area: the staged kernels
+    const size_t stg = staged_bytes(p);
+    if (stg > 0 && ws_bytes >= det_bytes(p) + rx_bytes_aligned(p) + stg && ((uintptr_t)workspace & 255) == 0)
+        sonar::set_staged_area(pa, reinterpret_cast<char *>(workspace) + det_bytes(p) + rx_bytes_aligned(p));
     if (needs_rx_list(p)) {
         // moved returns land after the ping kernel: detection runs after them
         if (ws_bytes < det_bytes(p) + rx_bytes(p) || ((uintptr_t)workspace & 255) != 0)
@@ -628,10 +685,10 @@ static sonar_status ping_detect_into(const sonar_scene *sc, const sonar_params *
         pa.det_M = c->max_per_beam;
         pa.det_n0 = (float)c->noise_floor;
         for (int n = 0; n <= 2 * 64; ++n) pa.det_alpha[n] = da.alpha[n];
-        e = sonar::launch_ping(pa, sc->s.stack, s);
+        e = launch_any(pa, sc->s.stack, s);
         if (e == hipSuccess) e = sonar::launch_emit(da, s);
     } else {
-        e = sonar::launch_ping(pa, sc->s.stack, s);
+        e = launch_any(pa, sc->s.stack, s);
         if (e == hipSuccess) e = sonar::launch_detect(da, s);
     }
     if (e != hipSuccess) return fail(SONAR_E_DEVICE, "ping/detect launch: %s", hipGetErrorString(e));
@@ -704,6 +761,37 @@ sonar_status sonar_add_reverb(sonar_cf32 *volume, const sonar_params *p, const s
 
 static_assert(SONAR_MAX_PULSE_TAPS == sonar::MAX_PULSE_TAPS, "pulse tap bound");
 static_assert(SONAR_MAX_PULSE_BINS == sonar::MAX_PULSE_BINS, "pulse bin bound");
+
+sonar_status sonar_pulse_dt(const sonar_params *p, const sonar_pose *q, const sonar_ssp *ssp, double *dt)
+{
+    g_err[0] = 0;
+    if (!dt) return fail(SONAR_E_INVALID, "dt is NULL");
+    sonar_status st = check_params(p);
+    if (st != SONAR_OK) return st;
+    if ((st = check_pose(q)) != SONAR_OK) return st;
+    const double z = q->position[2];
+    double c;
+    if (ssp) {
+        // the layer holding the sensor depth (a point on a knot belongs to the layer above)
+        const int n = ssp->n_knots;
+        if (n < 2 || n > SONAR_MAX_SSP_KNOTS)
+            return fail(SONAR_E_INVALID, "n_knots must be in [2, %d]", SONAR_MAX_SSP_KNOTS);
+        for (int k = 0; k < n; ++k) {
+            if (!isfinite(ssp->z[k]) || !(ssp->c[k] > 0) || !isfinite(ssp->c[k]))
+                return fail(SONAR_E_INVALID, "knot %d: z finite and c > 0 required", k);
+            if (k > 0 && !(ssp->z[k] > ssp->z[k - 1])) return fail(SONAR_E_INVALID, "knot depths must increase");
+        }
+        int i = 0;
+        while (i + 1 < n - 1 && z >= ssp->z[i + 1]) ++i;
+        const double g = (ssp->c[i + 1] - ssp->c[i]) / (ssp->z[i + 1] - ssp->z[i]);
+        c = ssp->c[i] + g * (z - ssp->z[i]);
+    } else {
+        c = p->c0 + p->c_grad * z;
+    }
+    if (!(c > 0.0) || !isfinite(c)) return fail(SONAR_E_INVALID, "sound speed at the sensor must be positive");
+    *dt = 2.0 * ((p->r_max - p->r_min) / p->n_range) / c;
+    return SONAR_OK;
+}
 
 sonar_status sonar_lfm_pulse(double bandwidth_hz, double duration_s, double dt_s, int32_t window, sonar_cf32 *taps,
                              int32_t max_len, int32_t *len)

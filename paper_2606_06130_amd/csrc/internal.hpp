@@ -68,6 +68,30 @@ constexpr uint32_t FLAG_RX_BEAMS = 2u;
 constexpr uint32_t FLAG_DIFFUSE_BOUNCE = 4u;
 constexpr uint32_t FLAG_RETRO_CHAIN = 8u;
 
+// Staged multi-bounce ping: what one bounce hands to the next (FP64 origin
+// and direction of the continuation, out-path length and time, path
+// weight; L_out < 0 marks a ray that has stopped).
+struct alignas(16) RayState {
+    double o[3];
+    double d[3];
+    double L_out, T_out, Wt;
+    uint32_t prev;       // the facet the continuation leaves from
+    float w_tx;          // transmit pattern at the launch direction
+};
+// One traversal query in FP32 (a straight ray, or the chord of an arc with
+// its tangent, centre normal, curvature and box inflation), ready for a
+// traversal kernel: the continuation of a bounce or the return path of a
+// vertex (visibility).
+struct alignas(16) SegRec {
+    float o[3], sigma;
+    float d[3], tmin;
+    float ad[3], tmax;
+    float anc[3], kappa;
+    float smin, smax;
+    uint32_t skip;       // the facet the query leaves from (never reported)
+    int32_t live;        // 0: nothing to trace
+};
+
 struct PingArgs {
     const float4 *nodes;
     const float4 *tris;
@@ -116,6 +140,16 @@ struct PingArgs {
     // batch bookkeeping (descriptor of one ping in a batch)
     int tile_offset;         // first global tile of this ping
     int n_tiles;             // 256-ray tiles of this ping
+    // staged multi-bounce path (stg_state == nullptr: the fused kernel):
+    // per-ray state, connection queries, and contribution slots
+    // [KS][n_rays] (bin, value) plus their receive beams [K][n_rays]
+    RayState *stg_state;
+    SegRec *stg_seg;         // [n_rays]: next nearest-hit query of every ray
+    SegRec *stg_cseg;        // [n_rays]: return-path (visibility) query of the last bounce
+    int2 *stg_hit;           // [n_rays]: winner of the last traversal (record index, FP32 arc length bits)
+    int32_t *stg_bin;
+    float4 *stg_val;
+    int32_t *stg_rxb;
 };
 
 // One batch launch: descriptors in device memory, one kernel class.
@@ -143,6 +177,11 @@ int batch_max_blocks_per_cu(const BatchLaunch &b);
 
 // Host-side launchers (one per translation unit).
 hipError_t launch_ping(const PingArgs &a, int stack_depth, hipStream_t s);
+// Multi-bounce ping in stages (staged.hip): bytes of its per-ray buffers,
+// their placement in a workspace area (256-byte aligned), and the launches.
+size_t staged_workspace_bytes(int64_t n_rays, int K, bool retro, bool rx);
+void set_staged_area(PingArgs &a, void *area);
+hipError_t launch_ping_staged(const PingArgs &a, int stack_depth, hipStream_t s);
 // Single-bounce ping through a piecewise-linear sound-speed profile.
 hipError_t launch_ping_layered(const PingArgs &a, int stack_depth, hipStream_t s);
 // Receive binning: clear the list's counter before a ping; add the listed

@@ -40,7 +40,8 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
            "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb",
            "sonar_ping_ssp", "sonar_ping_ssp_rx", "sonar_batch_prepare_ssp", "sonar_batch_rx_workspace_size",
-           "sonar_batch_prepare_rx", "sonar_batch_set_outputs", "sonar_ping_detect_noalloc")
+           "sonar_batch_prepare_rx", "sonar_batch_set_outputs", "sonar_ping_detect_noalloc",
+           "sonar_workspace_size", "sonar_ping_ws", "sonar_pulse_dt")
 
 
 class SonarError(RuntimeError):
@@ -238,9 +239,16 @@ def lib():
         L.sonar_add_reverb.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), P(sonar_reverb), C.c_void_p]
         L.sonar_rx_workspace_size.restype = C.c_size_t
         L.sonar_rx_workspace_size.argtypes = [P(sonar_params)]
+        L.sonar_workspace_size.restype = C.c_size_t
+        L.sonar_workspace_size.argtypes = [C.c_void_p, P(sonar_params), C.c_int32]
+        L.sonar_ping_ws.restype = C.c_int
+        L.sonar_ping_ws.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.sonar_ping_rx.restype = C.c_int
         L.sonar_ping_rx.argtypes = [C.c_void_p, P(sonar_params), P(sonar_pose), C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.sonar_pulse_dt.restype = C.c_int
+        L.sonar_pulse_dt.argtypes = [P(sonar_params), P(sonar_pose), C.c_void_p, P(C.c_double)]
         L.sonar_lfm_pulse.restype = C.c_int
         L.sonar_lfm_pulse.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32,
                                       P(C.c_int32)]
@@ -381,9 +389,21 @@ def _rx_workspace(out, p):
     return ws
 
 
+def _ping_workspace(scene, out, p):
+    """The workspace of sonar_ping_ws, kept with the outputs (grown when too small)."""
+    import torch
+    need = max(lib().sonar_workspace_size(scene.handle, C.byref(p), 1), 256)
+    ws = out.get("workspace")
+    if ws is None or ws.numel() < need:
+        ws = out["workspace"] = torch.empty(need, dtype=torch.uint8, device=out["volume"].device)
+    return ws
+
+
 def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=False, ray_mask=None, stream=None,
-         params=None, pose_s=None, stats=False):
-    """One ping; returns the dict of output tensors (allocated if ``out`` is None)."""
+         params=None, pose_s=None, stats=False, staged=False):
+    """One ping; returns the dict of output tensors (allocated if ``out`` is None).
+    ``staged``: through sonar_ping_ws with a workspace kept in ``out`` (several
+    bounces run in stages)."""
     if out is None:
         out = alloc_outputs(cfg, gbuffer, incoh, record, stats)
     rec = None
@@ -409,6 +429,13 @@ def ping(scene: Scene, cfg, pose, out=None, gbuffer=False, incoh=False, record=F
         _check(lib().sonar_ping_ssp(scene.handle, C.byref(p), C.byref(q), C.byref(prof), _dptr(out["volume"]),
                                     _dptr(out.get("gbuffer")), _dptr(out.get("incoh")),
                                     C.byref(rec) if rec is not None else None, _dptr(ray_mask), _stream(stream)))
+        return out
+    if staged:
+        ws = _ping_workspace(scene, out, p)
+        _check(lib().sonar_ping_ws(scene.handle, C.byref(p), C.byref(q), _dptr(out["volume"]),
+                                   _dptr(out.get("gbuffer")), _dptr(out.get("incoh")),
+                                   C.byref(rec) if rec is not None else None, _dptr(ray_mask), _dptr(ws), ws.numel(),
+                                   _stream(stream)))
         return out
     if (p.flags & FLAG_RX_BEAMS) and p.max_bounces > 1:
         ws = _rx_workspace(out, p)
@@ -496,9 +523,12 @@ def add_reverb(volume, cfg, pose, sv_db: float, noise_power: float = 0.0, seed: 
 
 
 def pulse_dt(cfg, pose) -> float:
-    """Two-way delay spacing of the range bins: 2 dr / c(z_sensor)."""
-    dr = (cfg.r_max - cfg.r_min) / cfg.n_range
-    return 2.0 * dr / (cfg.c0 + cfg.c_grad * float(pose.position[2]))
+    """Two-way delay spacing of the range bins (sonar_pulse_dt)."""
+    dt = C.c_double()
+    prof = ssp_of(cfg.ssp) if getattr(cfg, "ssp", ()) else None
+    _check(lib().sonar_pulse_dt(C.byref(params_of(cfg)), C.byref(pose_of(pose)),
+                                C.byref(prof) if prof is not None else None, C.byref(dt)))
+    return float(dt.value)
 
 
 def lfm_pulse(bandwidth_hz: float, duration_s: float, dt_s: float, window: int = 0) -> np.ndarray:

@@ -198,3 +198,31 @@ def test_add_reverb_validates_before_launch(L):
         assert L.sonar_add_reverb(vol, C.byref(p), C.byref(q), C.byref(bad), None) == sonar.SONAR_E_INVALID
     p1 = sonar.params_of(cfg.replace(grid_mode=1, rays_per_beam=1))
     assert L.sonar_add_reverb(vol, C.byref(p1), C.byref(q), C.byref(good), None) == sonar.SONAR_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("g,z,knots", [(0.0, -3.0, ()), (0.05, -3.0, ()), (-0.08, 1.25, ()),
+                                       (0.0, -2.0, ((-9.0, 1497.0), (-3.0, 1499.0), (1.5, 1500.3))),
+                                       (0.0, -9.5, ((-9.0, 1497.0), (-3.0, 1499.0), (1.5, 1500.3))),
+                                       (0.0, 2.5, ((-9.0, 1497.0), (-3.0, 1499.0), (1.5, 1500.3)))])
+def test_pulse_dt_is_two_bin_widths_over_sensor_speed(L, g, z, knots):
+    """dt = 2 dr / c(z_sensor): the gradient's c0 + g z, or the layered
+    profile interpolated in the layer holding z (end layers extended)."""
+    cfg = S.sensor_harbor().replace(c_grad=g, ssp=knots)
+    pose = S.pose((0.0, 0.0, z))
+    if knots:
+        zs, cs = np.array([k[0] for k in knots]), np.array([k[1] for k in knots])
+        i = int(np.clip(np.searchsorted(zs, z, side="right") - 1, 0, len(zs) - 2))
+        c = cs[i] + (cs[i + 1] - cs[i]) / (zs[i + 1] - zs[i]) * (z - zs[i])
+    else:
+        c = cfg.c0 + g * z
+    dr = (cfg.r_max - cfg.r_min) / cfg.n_range
+    assert sonar.pulse_dt(cfg, pose) == pytest.approx(2 * dr / c, rel=1e-14)
+
+
+def test_pulse_dt_rejects(L):
+    p = sonar.params_of(S.sensor_harbor())
+    q = sonar.pose_of(S.pose_harbor())
+    assert L.sonar_pulse_dt(C.byref(p), C.byref(q), None, None) == sonar.SONAR_E_INVALID
+    bad = sonar.ssp_of(((0.0, 1500.0), (-1.0, 1490.0)))
+    dt = C.c_double()
+    assert L.sonar_pulse_dt(C.byref(p), C.byref(q), C.byref(bad), C.byref(dt)) == sonar.SONAR_E_INVALID
