@@ -219,7 +219,12 @@ def parity_sample(torch, sonar, np, scene, mesh, cfg, pose, n_beams, seed, stage
     return res
 
 
-def multipath_and_batch(torch, sonar, S, np, replays=5):
+# multiply-adds per beam of the surrogate network (fan-in x fan-out of each
+# layer, the 3 x 3 x 8 convolution as 72 inputs)
+SURROGATE_MACS_PER_ROW = 72 * 64 + 64 * 256 + 2 * 256 * 256 + 256 * 64
+
+
+def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
     """Multipath ping (1.99M triangles, 3 bounces, c(z) gradient) and a batch
     of 256 mixed pings along a lawnmower path over the same scene, captured in
     a HIP graph with autotuned launch knobs."""
@@ -325,13 +330,15 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     del out
 
     # surrogate ping: single-bounce ping with G-buffer and incoherent channel,
-    # network forward, predicted multi-bounce profile (all on the GPU)
+    # fused network inference and the predicted multi-bounce profile (all on
+    # the GPU), with the committed weights
+    from paper_2606_06130_amd import surrogate as SU
     cfg1 = cfg.replace(max_bounces=1)
     o1 = sonar.alloc_outputs(cfg1, gbuffer=True, incoh=True)
     bv, bh = sonar.beams_of(cfg1)
     rows = bv * bh
     sur = sonar.Surrogate(rows, cfg1.n_range, cfg1.r_min, cfg1.r_max)
-    sur.set_state(S.surrogate_init_params(11))
+    _, _, sur_steps, sur_meta = SU.load_checkpoint(SU.WEIGHTS, sur)
     coef = torch.empty((rows, 64), dtype=torch.float32, device="cuda")
     gview = o1["gbuffer"].view(1, bv, bh, 8)
     i1 = o1["incoh"].view(2, rows, cfg1.n_range)[0]
@@ -341,28 +348,30 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
         sur.forward(gview, out=coef)
         sur.profile(coef, i1, gview, im=None, want_profile=True)
 
-    for _ in range(3):
-        sur_ping()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
-    for a, b in ev:
-        a.record(stream)
-        sur_ping()
-        b.record(stream)
-    torch.cuda.synchronize()
-    sp_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    surrogate = {"workload": "single-bounce ping with G-buffer + network (169,344 parameters, BF16 MFMA) + "
-                             "predicted 1,024-bin multi-bounce profile, same scene and layout",
-                 "ping_ms": sp_ms, "pings_per_s": 1e3 / sp_ms, "rate_vs_full_multipath": mp_ms / sp_ms}
-    try:
-        with open(os.path.join(ROOT, "profiles", "surrogate_harbor_multipath_training.json")) as f:
-            tr = json.load(f)
-        surrogate["held_out_error_db"] = {k: tr[k] for k in ("surrogate", "single_bounce", "mean_residual",
-                                                              "truncated_truth", "surrogate_vs_truncated_truth")
-                                          if k in tr}
-        surrogate["held_out_error_source"] = "profiles/surrogate_harbor_multipath_training.json (training run)"
-    except (OSError, ValueError, KeyError):
-        pass
+    sp_ms = timed(sur_ping)
+    fwd_ms = timed(lambda: sur.forward(gview, out=coef), n=20)
+    fwd_tflops = 2.0 * SURROGATE_MACS_PER_ROW * rows / (fwd_ms * 1e-3) / 1e12
+    surrogate = {"workload": "single-bounce ping with G-buffer + fused network inference (169,344 parameters, "
+                             "BF16 MFMA) + predicted 1,024-bin multi-bounce profile, same scene and layout",
+                 "ping_ms": sp_ms, "pings_per_s": 1e3 / sp_ms, "rate_vs_full_multipath": mp_ms / sp_ms,
+                 "weights": os.path.relpath(SU.WEIGHTS, ROOT), "weights_train_steps": sur_steps,
+                 "weights_meta": sur_meta,
+                 "forward": {"ms": fwd_ms, "rows": rows, "tflops": fwd_tflops,
+                             "roofline": {"bound": "mfma", "achieved": fwd_tflops, "peak": 2500.0,
+                                          "unit": "TFLOP/s", "frac": fwd_tflops / 2500.0,
+                                          "alg_flop_per_row": 2 * SURROGATE_MACS_PER_ROW}}}
+    if sur_eval_poses > 0:
+        # held-out evaluation: full multipath pings from poses outside the training set
+        t0 = time.perf_counter()
+        held = SU.evaluate(sur, SU.PingSource(scene, cfg), S.random_poses(6, sur_eval_poses))
+        held["eval_seconds"] = time.perf_counter() - t0
+        surrogate["held_out"] = held
+        surrogate["error_db"] = held["surrogate"]["mean_db"]
+        surrogate["error_floor_db"] = held["truncated_truth"]["mean_db"]
+        surrogate["meets_1db"] = held["meets_1db"]
+        surrogate["rate_note"] = (f"rate_vs_full_multipath is quoted at {held['surrogate']['mean_db']:.2f} dB mean "
+                                  "error against the smoothed truth, not at the 1 dB the metric names"
+                                  if not held["meets_1db"] else "rate quoted at <= 1 dB mean error")
     del o1, sur, coef
     multipath["surrogate"] = surrogate
 
@@ -370,6 +379,7 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
     batch = sonar.Batch(scene, items)
     batch.detect()
     best, tune_ms = batch.autotune()
+    default_ms = timed(lambda: batch.run(), n=3, warm=1)       # the default knobs (occupancy limit, 4 waves, 1 unit)
     g = batch.graph(best)
     g.launch()
     torch.cuda.synchronize()
@@ -396,7 +406,8 @@ def multipath_and_batch(torch, sonar, S, np, replays=5):
            "pings_per_s": batch.n / rep_ms * 1e3, "mrays_per_s": batch.plan.total_rays / rep_ms / 1e3,
            "points": points, "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
            "autotuned": {"blocks_per_cu": best.blocks_per_cu, "tiles_per_item": best.tiles_per_item,
-                         "ms": tune_ms},
+                         "waves_per_block": best.waves_per_block, "ms": tune_ms,
+                         "default_knobs_ms": default_ms, "speedup_over_default": default_ms / tune_ms},
            "roofline": {"bound": "hbm", "kernel": "graph replay: queue reset, persistent ping kernel, batched "
                                                   "point emission",
                         "achieved": b_alg / (rep_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -510,6 +521,8 @@ def main():
     ap.add_argument("--streams", type=int, default=4,
                     help="streams the job's pings are issued on round-robin (independent pings overlap)")
     ap.add_argument("--latency-steps", type=int, default=50, help="single-stream pings timed one by one")
+    ap.add_argument("--surrogate-eval-poses", type=int, default=1000,
+                    help="held-out poses the committed surrogate weights are evaluated on (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for counter calibration) and exit")
     ap.add_argument("--case", choices=("multipath", "multipath_fused", "multipath_straight", "batch"), default=None,
@@ -681,7 +694,7 @@ def main():
         res["reverberation"] = reverb_noise(torch, sonar, np, cfg, pose, out["volume"])
         res["layered_profile"] = layered_ping(torch, sonar, np, scene, cfg, pose)
         del out, det
-        mp, bt = multipath_and_batch(torch, sonar, S, np)
+        mp, bt = multipath_and_batch(torch, sonar, S, np, sur_eval_poses=args.surrogate_eval_poses)
         res["multipath_ping"] = mp
         res["batch"] = bt
     if not args.no_cpu_baseline:

@@ -389,8 +389,8 @@ sonar_status sonar_ping_detect_noalloc(const sonar_scene *scene, const sonar_par
                                        int32_t capacity, int32_t *dev_count, sonar_stream stream);
 
 /* ---------------------------------------------------------------------- */
-/* Water-column volume reverberation and receiver noise (Sec. II-B:
- * volumetric backscatter paths from the water column; speckle). Every range
+/* Water-column volume reverberation and receiver noise (Sec. II-B names
+ * scattering within the water volume and speckle as extensions). Every range
  * cell (beam b = v * n_h + h, bin n) of cell-centred beams holds unresolved
  * scatterers: its echo is a circular complex Gaussian of mean power
  *   P = s_v V / r^4 10^(-abs_db_per_m 2 r / 10) + noise_power,
@@ -479,12 +479,16 @@ typedef struct {
 } sonar_batch_plan;
 
 /* Launch knobs: persistent workgroups per compute unit (0: the occupancy
- * limit) and 256-ray tiles taken per queue pop (0: 1). `emit_desc`: device
- * copy of the emission descriptors of sonar_batch_prepare_detect, or NULL
- * for a batch without detection. */
+ * limit), work units taken per queue pop (0: 1), and the workgroup size in
+ * 64-lane waves, 1, 2 or 4 (0: 4), which is also the unit of work: a unit is
+ * that many waves of consecutive rays of one ping (batches through a
+ * layered profile or with retro-chain returns always run 4). `emit_desc`:
+ * device copy of the emission descriptors of sonar_batch_prepare_detect, or
+ * NULL for a batch without detection. */
 typedef struct {
     int32_t blocks_per_cu, tiles_per_item;
     const void *emit_desc;
+    int32_t waves_per_block, pad;
 } sonar_batch_options;
 
 typedef struct sonar_graph sonar_graph;   /* an instantiated HIP graph of one batch */
@@ -588,12 +592,16 @@ sonar_status sonar_batch_graph_create(const sonar_scene *scene, const sonar_batc
 sonar_status sonar_graph_launch(sonar_graph *graph, sonar_stream stream);
 void sonar_graph_free(sonar_graph *graph);
 
-/* Measures the batch under every launch-knob candidate (persistent blocks per
- * compute unit up to the occupancy limit x tiles per pop in {1, 2, 4}) with
- * device events and returns the fastest in `best` and its time in
- * `best_ms`. When the environment variable SONAR_AUTOTUNE_CACHE names a file,
- * a result cached there for the same device, scene size and plan is returned
- * without measuring, and new results are appended. Synchronous. */
+/* Measures the batch under every launch-knob candidate with device events
+ * (mean of three runs after a warm-up) and returns the fastest in `best`
+ * (emit_desc NULL) and its time in `best_ms`. Candidates: workgroups of 1, 2
+ * or 4 waves (4 only for layered or retro-chain batches) x persistent
+ * workgroups per compute unit giving 1, 2, ... up to the occupancy limit of
+ * waves per SIMD x units per pop in {1, 2, 4}. When the environment variable
+ * SONAR_AUTOTUNE_CACHE names a file, a result cached there for the same
+ * device, scene size and plan is returned without measuring; otherwise every
+ * candidate's time ("cand" lines) and the choice are appended to it.
+ * Synchronous. */
 sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_plan *plan, const void *dev_desc,
                                   void *workspace, size_t workspace_bytes, sonar_stream stream,
                                   sonar_batch_options *best, float *best_ms);
@@ -602,17 +610,20 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
 /* Learned multipath surrogate (Sec. II-B: scattering functions may be learned
  * from data). A network maps each beam's single-bounce G-buffer (a 3 x 3 beam
  * neighbourhood of its 8 features) to 64 standardised orthonormal DCT-II
- * coefficients of the residual profile that later bounces add:
- *   res[r] = 10 log10(I1s[r] + Ims[r] + 1e-11) - 10 log10(I1s[r] + 1e-11),
- * where I1s, Ims are the first-bounce and later-bounce incoherent channels of a
- * multi-bounce ping box-averaged over `smooth` range bins ([r - smooth/2,
- * r + smooth/2)), and the profile is shifted so that the beam's first-hit bin
- * (its G-buffer mean first-bounce range) is bin 0, zero past the end.
+ * coefficients of the level profile of what later bounces add:
+ *   lev[r] = 10 log10(1 + Ims[r] / 1e-11),
+ * where Ims is the later-bounce incoherent channel of a multi-bounce ping
+ * box-averaged over `smooth` range bins ([r - smooth/2, r + smooth/2)), shifted
+ * so that the beam's first-hit bin (its G-buffer mean first-bounce range) is
+ * bin 0, zero past the end. The predicted profile adds that intensity back:
+ *   profile[r] = 10 log10(I1s[r] + 1e-11 * 10^(lev[r] / 10)),
+ * so a zero level leaves the smoothed single-bounce profile.
  * Layers: 3 x 3 convolution 8 -> 64 (as an im2col product), then
  * 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers; 169,344 parameters.
  * Products use BF16 operands on the matrix cores with FP32 accumulation;
- * training is MSE on the coefficients with Adam (beta 0.9 / 0.999, eps 1e-8)
- * on FP32 master weights.
+ * training is a weighted MSE on the coefficients, sum_j w_j (y_j - t_j)^2 over
+ * rows * 64 (weights 1 by default), with Adam (beta 0.9 / 0.999, eps 1e-8) on
+ * FP32 master weights.
  *
  * Parameter vector layout (float, sonar_surrogate_param_count() entries): for
  * each layer W [fan_in][fan_out] row-major then b [fan_out], with (fan_in,
@@ -643,6 +654,11 @@ sonar_status sonar_surrogate_get_state(const sonar_surrogate *s, float *params, 
 /* Coefficient standardisation (host arrays of 64). */
 sonar_status sonar_surrogate_set_norm(sonar_surrogate *s, const float *mean, const float *std);
 
+/* Loss weights w_j (host array of 64, finite and >= 0; NULL restores 1).
+ * With w_j = std_j^2 / mean(std^2) the loss is, by Parseval's theorem, the
+ * squared error of the truncated level profile itself. */
+sonar_status sonar_surrogate_set_loss_weights(sonar_surrogate *s, const float *w);
+
 /* Inference: standardised coefficients [rows][64] (device) from a G-buffer. */
 sonar_status sonar_surrogate_forward(sonar_surrogate *s, const float *gbuffer, int32_t n_img, int32_t h, int32_t w,
                                      float *coef, sonar_stream stream);
@@ -658,11 +674,11 @@ sonar_status sonar_surrogate_train_step(sonar_surrogate *s, const float *gbuffer
 sonar_status sonar_surrogate_gradient(sonar_surrogate *s, const float *gbuffer, int32_t n_img, int32_t h, int32_t w,
                                       const float *target, float *dev_grad, float *dev_loss, sonar_stream stream);
 
-/* Residual target: coefficients [rows][64] from the two incoherent channels
- * i1, im [rows][n_bins] and the G-buffer of the same beams (device),
+/* Level target: coefficients [rows][64] from the later-bounce incoherent
+ * channel im [rows][n_bins] and the G-buffer of the same beams (device),
  * standardised when `standardize` is 1. */
-sonar_status sonar_surrogate_residual(const sonar_surrogate *s, const float *i1, const float *im, const float *gbuffer,
-                                      int64_t rows, int32_t standardize, float *coef, sonar_stream stream);
+sonar_status sonar_surrogate_target(const sonar_surrogate *s, const float *im, const float *gbuffer, int64_t rows,
+                                    int32_t standardize, float *coef, sonar_stream stream);
 
 /* Sums of the 64 coefficients and of their squares over rows (host double
  * arrays of 64), for the standardisation statistics. Synchronises. */
@@ -670,14 +686,19 @@ sonar_status sonar_surrogate_moments(sonar_surrogate *s, const float *coef, int6
                                      sonar_stream stream);
 
 /* Predicted (range-smoothed) multi-bounce profile and its errors. For
- * standardised predictions `coef`: profile[r] = 10 log10(I1s[r] + 1e-11),
- * plus the inverse DCT of the de-standardised coefficients from the first-hit
- * bin on (written to `profile` [rows][n_bins] if not NULL). If `im` is not
- * NULL, `err` [rows][4] receives per beam, over bins whose smoothed truth
- * 10 log10(I1s + Ims + 1e-11) is 3 dB above the floor: mean |error| of the
- * prediction, of the single-bounce profile alone, of the single-bounce
- * profile plus the mean residual (inverse DCT of the mean coefficients), and
- * the number of such bins (NaN errors when none). */
+ * standardised predictions `coef`: profile[r] = 10 log10(I1s[r] + 1e-11 *
+ * 10^(lev[r] / 10)), lev the inverse DCT of the de-standardised coefficients
+ * from the first-hit bin on and 0 before it (written to `profile`
+ * [rows][n_bins] if not NULL). If `im` is not NULL, `err` [rows][8] receives
+ * per beam mean |error| in dB (NaN when no bin counts):
+ *   over bins whose smoothed truth 10 log10(I1s + Ims + 1e-11) is more than
+ *   3 dB above the floor: [0] the prediction, [1] the smoothed single-bounce
+ *   profile, [2] the smoothed single bounce plus the mean level (inverse DCT
+ *   of the mean coefficients), [3] the number of such bins;
+ *   over bins whose raw truth 10 log10(I1 + Im + 1e-11) is more than 3 dB
+ *   above the floor: [4] the prediction, [5] the smoothed truth (the best any
+ *   range-smoothed profile can do), [6] the raw single-bounce profile
+ *   10 log10(I1 + 1e-11), [7] the number of such bins. */
 sonar_status sonar_surrogate_profile(const sonar_surrogate *s, const float *coef, const float *i1, const float *im,
                                      const float *gbuffer, int64_t rows, float *profile, float *err,
                                      sonar_stream stream);

@@ -17,8 +17,8 @@
  *                          angle and material coefficients; a bounded number
  *                          of secondary reflections with a tunable depth;
  *                          complex returns whose phase follows the propagation
- *                          delay, with attenuation; beams and cells formed by
- *                          coherent summation within each ray bundle.
+ *                          delay, with attenuation; a beam or cell is the
+ *                          complex sum over its bundle of rays.
  * Readings where the paper is silent (jitter law, spreading, absorption, the
  * multipath path model, the tie rule, CFAR constants) are stated next to the
  * code that applies them.
@@ -1583,7 +1583,7 @@ static void trace_ray(const oscene *S, const orc_params *P, const orc_pose *Q, c
 /* ------------------------------------------------------------------------ */
 /* Beams: all rays of each listed beam, their records, and the beam's range   */
 /* column. Every ray of a bundle is weighted 1/N_r and contributes to its    */
-/* launch beam (coherent summation within each ray bundle).                 */
+/* launch beam (the complex sum over the beam's bundle of rays).            */
 
 int orc_trace_beams(void *hs, const orc_params *P, const orc_pose *Q, const orc_tol *T,
                     const int32_t *beams, int64_t n_beams,

@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
 benchmark's CPU-baseline leg. The product package never imports it.
 
-Sec. II-B of the paper suggests adding volumetric backscatter paths, for
-instance from the water column, and speckle. It gives no model, so this
+Sec. II-B names, as extensions, scattering from within the water volume
+and speckle. It gives no model, so this
 oracle takes the following reading (the GPU path implements the same
 definition on its own):
 

@@ -5,16 +5,22 @@ never by the product path. It shares no code with the HIP kernels.
 
 The paper (Sec. II-B) allows scattering functions to be learned from data;
 here a small network predicts, from each beam's single-bounce G-buffer, the
-range profile that further bounces add, as the dB residual between the
-incoherent multi-bounce and single-bounce intensity, compressed to the first
-64 coefficients of an orthonormal DCT-II of the 1,024-bin profile.
+range profile that further bounces add: the dB level of the later-bounce
+incoherent intensity above the intensity floor, 10 log10(1 + Im / floor),
+range-smoothed, shifted to start at the beam's first-hit bin and compressed
+to the first 64 coefficients of an orthonormal DCT-II of the 1,024-bin
+profile. The predicted multi-bounce profile adds that intensity back to the
+single-bounce one: 10 log10(I1 + floor 10^(q / 10)), so a zero prediction is
+the single-bounce profile.
 
 Network (169,344 parameters): a 3 x 3 beam-neighbourhood convolution of the
 8 G-buffer features (the first-hit statistics and the beam axis's vertical
 component; written as an im2col product with 72 inputs, zero padding at the
 edges) -> ReLU -> 64 -> 256 -> 256 -> 256 -> 64 dense layers with ReLU
 between them. Loss: mean squared error over the 64 standardised
-coefficients.
+coefficients, coefficient j weighted by w_j (by default 1; in training
+sigma_j^2 / mean(sigma^2), which makes it the squared error of the profile
+itself by Parseval's theorem).
 
 Parameter vector layout (float, 169,344 entries): for each layer in order
 W [K][N] row-major then b [N], with (K, N) = (72, 64), (64, 256), (256, 256),
@@ -83,9 +89,12 @@ def forward(theta, x0, store=None):
     raise AssertionError
 
 
-def mse(y, t):
+def mse(y, t, w=None):
+    """Weighted mean squared error sum_j w_j (y - t)^2 / (rows * 64) and its
+    gradient with respect to y (w None: all weights 1)."""
     d = y - np.asarray(t, np.float64)
-    return float((d * d).mean()), 2.0 * d / d.size
+    wj = np.ones(d.shape[-1]) if w is None else np.asarray(w, np.float64)
+    return float((wj * d * d).mean()), 2.0 * wj * d / d.size
 
 
 def backward(theta, acts, dy, store=None):
@@ -105,9 +114,9 @@ def backward(theta, acts, dy, store=None):
     return pack(grads)
 
 
-def loss_and_grad(theta, gbuf, target, store=None):
+def loss_and_grad(theta, gbuf, target, store=None, w=None):
     acts, y = forward(theta, im2col(gbuf), store)
-    loss, dy = mse(y, target)
+    loss, dy = mse(y, target, w)
     return loss, backward(theta, acts, dy, store), y
 
 
@@ -147,51 +156,52 @@ def first_hit_bin(gbuf_rows, r_min, r_max, n_bins):
     return np.clip(b, 0, n_bins - 1).astype(np.int64)
 
 
-def aligned_residual_coefficients(i1, im, r1, floor=I_FLOOR, w=SMOOTH):
-    """DCT coefficients of the range-smoothed dB residual shifted so that each
-    beam's first-hit bin r1 becomes bin 0 (bins past the end are zero)."""
-    res = residual_db(smooth_range(i1, w), smooth_range(im, w), floor)
-    n = res.shape[-1]
-    al = np.zeros_like(res)
-    for q in range(res.shape[0]):
-        al[q, :n - r1[q]] = res[q, r1[q]:]
+def level_db(im, floor=I_FLOOR):
+    """dB level of the later-bounce intensity above the floor: 10 log10(1 + Im / floor)."""
+    return 10.0 * np.log10(1.0 + np.asarray(im, np.float64) / floor)
+
+
+def level_coefficients(im, floor=I_FLOOR):
+    """[rows, n_bins] later-bounce channel -> [rows, 64] DCT coefficients of its level."""
+    lv = level_db(im, floor)
+    return lv @ dct_basis(lv.shape[-1]).T
+
+
+def profile_from_coefficients(i1, coef, floor=I_FLOOR):
+    """Predicted multi-bounce dB profile: the single-bounce intensity plus the
+    later-bounce intensity of the level the coefficients give."""
+    i1 = np.asarray(i1, np.float64)
+    q = np.asarray(coef, np.float64) @ dct_basis(i1.shape[-1])
+    return 10.0 * np.log10(i1 + floor * 10.0 ** (q / 10.0))
+
+
+def aligned_level_coefficients(im, r1, floor=I_FLOOR, w=SMOOTH):
+    """DCT coefficients of the range-smoothed later-bounce level shifted so that
+    each beam's first-hit bin r1 becomes bin 0 (bins past the end are zero)."""
+    lv = level_db(smooth_range(im, w), floor)
+    n = lv.shape[-1]
+    al = np.zeros_like(lv)
+    for q in range(lv.shape[0]):
+        al[q, :n - r1[q]] = lv[q, r1[q]:]
     return al @ dct_basis(n).T
 
 
 def aligned_profile(i1, coef, r1, floor=I_FLOOR, w=SMOOTH):
-    """Predicted range-smoothed multi-bounce dB profile: smoothed single-bounce dB
-    plus the inverse DCT shifted back to start at the first-hit bin."""
+    """Predicted range-smoothed multi-bounce dB profile: the smoothed
+    single-bounce intensity plus the later-bounce intensity of the inverse DCT
+    shifted back to start at the first-hit bin (level 0 before it)."""
     i1s = smooth_range(i1, w)
     q = np.asarray(coef, np.float64) @ dct_basis(i1s.shape[-1])
     n = i1s.shape[-1]
-    out = 10.0 * np.log10(i1s + floor)
-    for k in range(out.shape[0]):
-        out[k, r1[k]:] += q[k, :n - r1[k]]
-    return out
+    lv = np.zeros_like(i1s)
+    for k in range(lv.shape[0]):
+        lv[k, r1[k]:] = q[k, :n - r1[k]]
+    return 10.0 * np.log10(i1s + floor * 10.0 ** (lv / 10.0))
 
 
 def aligned_beam_errors(i1, im, pred_profile, floor=I_FLOOR, occupied_db=3.0, w=SMOOTH):
     """beam_errors() against the range-smoothed truth."""
     return beam_errors(smooth_range(i1, w), smooth_range(im, w), pred_profile, floor, occupied_db)
-
-
-def residual_db(i1, im, floor=I_FLOOR):
-    """dB residual of the multi-bounce incoherent profile over the single-bounce one."""
-    i1 = np.asarray(i1, np.float64)
-    im = np.asarray(im, np.float64)
-    return 10.0 * np.log10(i1 + im + floor) - 10.0 * np.log10(i1 + floor)
-
-
-def residual_coefficients(i1, im, floor=I_FLOOR):
-    """[rows, n_bins] incoherent channels -> [rows, 64] DCT coefficients of the residual."""
-    res = residual_db(i1, im, floor)
-    return res @ dct_basis(res.shape[-1]).T
-
-
-def profile_from_coefficients(i1, coef, floor=I_FLOOR):
-    """Predicted multi-bounce dB profile: single-bounce dB + inverse DCT of the coefficients."""
-    i1 = np.asarray(i1, np.float64)
-    return 10.0 * np.log10(i1 + floor) + np.asarray(coef, np.float64) @ dct_basis(i1.shape[-1])
 
 
 def beam_errors(i1, im, pred_profile, floor=I_FLOOR, occupied_db=3.0):

@@ -13,6 +13,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 struct sonar_scene {
     sonar::Scene s;
@@ -1072,6 +1073,9 @@ static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_p
     if (ws_bytes < sonar_batch_workspace_size(plan->n_pings)) return fail(SONAR_E_INVALID, "workspace too small");
     if (opt && (opt->blocks_per_cu < 0 || opt->blocks_per_cu > 64 || opt->tiles_per_item < 0 || opt->tiles_per_item > 64))
         return fail(SONAR_E_INVALID, "options out of range");
+    if (opt && opt->waves_per_block != 0 && opt->waves_per_block != 1 && opt->waves_per_block != 2 &&
+        opt->waves_per_block != 4)
+        return fail(SONAR_E_INVALID, "waves_per_block must be 1, 2 or 4 (0: 4)");
     char *w = (char *)ws;
     b->desc = reinterpret_cast<const sonar::PingArgs *>(dev_desc);
     b->n_pings = plan->n_pings;
@@ -1089,6 +1093,8 @@ static sonar_status batch_launch_args(const sonar_scene *sc, const sonar_batch_p
     b->t1 = b->t0 + plan->n_pings;
     b->blocks_per_cu = opt ? opt->blocks_per_cu : 0;
     b->tiles_per_item = opt && opt->tiles_per_item > 0 ? opt->tiles_per_item : 1;
+    // layered and retro-chain batches have the 4-wave instantiations only
+    b->waves_per_block = opt && opt->waves_per_block > 0 && !(plan->arc == 2 || plan->retro) ? opt->waves_per_block : 4;
     b->emit = opt ? reinterpret_cast<const sonar::DetectArgs *>(opt->emit_desc) : nullptr;
     b->max_beams = plan->max_beams;
     if (b->emit && plan->max_beams < 1) return fail(SONAR_E_INVALID, "plan has no beam count (prepare it again)");
@@ -1207,14 +1213,16 @@ sonar_status sonar_batch_autotune(const sonar_scene *sc, const sonar_batch_plan 
     if (cache && *cache) {
         FILE *f = fopen(cache, "r");
         if (f) {
-            char k[400];
-            int bpc, tpi;
+            char line[512], k[400];
+            int bpc, tpi, wpb;
             float ms;
             bool found = false;
-            while (fscanf(f, "%399s %d %d %f", k, &bpc, &tpi, &ms) == 4) {
-                if (key == k) {
+            while (fgets(line, sizeof(line), f)) {
+                if (sscanf(line, "%399s %d %d %d %f", k, &bpc, &tpi, &wpb, &ms) == 5 && key == k) {
+                    memset(best, 0, sizeof(*best));
                     best->blocks_per_cu = bpc;
                     best->tiles_per_item = tpi;
+                    best->waves_per_block = wpb;
                     *best_ms = ms;
                     found = true;
                 }
@@ -1224,49 +1232,62 @@ sonar_status sonar_batch_autotune(const sonar_scene *sc, const sonar_batch_plan 
         }
     }
     hipStream_t s = (hipStream_t)stream;
-    const int occ = sonar::batch_max_blocks_per_cu(b);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(SONAR_E_DEVICE, "event creation failed");
     float bestv = 1e30f;
-    sonar_batch_options bo = {0, 1};
+    sonar_batch_options bo;
+    memset(&bo, 0, sizeof(bo));
+    struct Cand { int wpb, bpc, tpi; float ms; };
+    std::vector<Cand> tried;
+    const bool only4 = plan->arc == 2 || plan->retro;
+    const int wpbs[3] = {4, 2, 1};
     const int tpis[3] = {1, 2, 4};
-    for (int bpc = 1; bpc <= occ; ++bpc) {
-        for (int ti = 0; ti < 3; ++ti) {
-            b.blocks_per_cu = bpc;
-            b.tiles_per_item = tpis[ti];
-            hipError_t e = sonar::launch_ping_batch(b, s);   // warm-up
-            float total = 0.f;
-            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-                e = hipEventRecord(e0, s);
-                if (e == hipSuccess) e = sonar::launch_ping_batch(b, s);
-                if (e == hipSuccess) e = hipEventRecord(e1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                total += ms;
-            }
-            if (e != hipSuccess) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return fail(SONAR_E_DEVICE, "autotune run: %s", hipGetErrorString(e));
-            }
-            const float ms = total / 3.f;
-            if (ms < bestv) {
-                bestv = ms;
-                bo.blocks_per_cu = bpc;
-                bo.tiles_per_item = tpis[ti];
+    hipError_t e = hipSuccess;
+    for (int wi = 0; wi < (only4 ? 1 : 3) && e == hipSuccess; ++wi) {
+        const int wpb = wpbs[wi];
+        b.waves_per_block = wpb;
+        const int occ = sonar::batch_max_blocks_per_cu(b);        // workgroups per CU at this size
+        const int per_simd = (occ * wpb) / 4;                        // waves per SIMD at the limit
+        for (int ws_ = 1; ws_ <= (per_simd > 0 ? per_simd : 1) && e == hipSuccess; ++ws_) {
+            const int bpc = (ws_ * 4) / wpb > 0 ? (ws_ * 4) / wpb : 1;
+            for (int ti = 0; ti < 3 && e == hipSuccess; ++ti) {
+                b.blocks_per_cu = bpc;
+                b.tiles_per_item = tpis[ti];
+                e = sonar::launch_ping_batch(b, s);   // warm-up
+                float total = 0.f;
+                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                    e = hipEventRecord(e0, s);
+                    if (e == hipSuccess) e = sonar::launch_ping_batch(b, s);
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    total += ms;
+                }
+                if (e != hipSuccess) break;
+                const float ms = total / 3.f;
+                tried.push_back(Cand{wpb, bpc, tpis[ti], ms});
+                if (ms < bestv) {
+                    bestv = ms;
+                    bo.blocks_per_cu = bpc;
+                    bo.tiles_per_item = tpis[ti];
+                    bo.waves_per_block = wpb;
+                }
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(SONAR_E_DEVICE, "autotune run: %s", hipGetErrorString(e));
     *best = bo;
     *best_ms = bestv;
     if (cache && *cache) {
         FILE *f = fopen(cache, "a");
         if (f) {
-            fprintf(f, "%s %d %d %.6f\n", key.c_str(), bo.blocks_per_cu, bo.tiles_per_item, bestv);
+            for (const Cand &c : tried)
+                fprintf(f, "cand:%s %d %d %d %.6f\n", key.c_str(), c.bpc, c.tpi, c.wpb, c.ms);
+            fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), bo.blocks_per_cu, bo.tiles_per_item, bo.waves_per_block, bestv);
             fclose(f);
         }
     }
@@ -1331,6 +1352,16 @@ sonar_status sonar_surrogate_set_norm(sonar_surrogate *h, const float *mean, con
     return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "set_norm: %s", hipGetErrorString(e));
 }
 
+sonar_status sonar_surrogate_set_loss_weights(sonar_surrogate *h, const float *w)
+{
+    if (!h) return fail(SONAR_E_INVALID, "surrogate is NULL");
+    if (w)
+        for (int j = 0; j < 64; ++j)
+            if (!(w[j] >= 0.f) || !isfinite(w[j])) return fail(SONAR_E_INVALID, "loss weights must be finite and >= 0");
+    hipError_t e = sonar::surrogate_set_loss_weights(h->s, w);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "set_loss_weights: %s", hipGetErrorString(e));
+}
+
 static sonar_status check_gbuf(const sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W)
 {
     if (!h || !g) return fail(SONAR_E_INVALID, "surrogate and gbuffer are required");
@@ -1375,16 +1406,15 @@ sonar_status sonar_surrogate_gradient(sonar_surrogate *h, const float *g, int32_
     return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "gradient: %s", hipGetErrorString(e));
 }
 
-sonar_status sonar_surrogate_residual(const sonar_surrogate *h, const float *i1, const float *im, const float *gbuffer,
-                                      int64_t rows, int32_t standardize, float *coef, sonar_stream stream)
+sonar_status sonar_surrogate_target(const sonar_surrogate *h, const float *im, const float *gbuffer, int64_t rows,
+                                    int32_t standardize, float *coef, sonar_stream stream)
 {
     g_err[0] = 0;
-    if (!h || !i1 || !im || !gbuffer || !coef)
-        return fail(SONAR_E_INVALID, "surrogate, i1, im, gbuffer and coef are required");
+    if (!h || !im || !gbuffer || !coef) return fail(SONAR_E_INVALID, "surrogate, im, gbuffer and coef are required");
     if (rows < 1 || rows > sonar::surrogate_max_rows(h->s)) return fail(SONAR_E_INVALID, "rows must be in [1, max_rows]");
-    hipError_t e = sonar::surrogate_residual_coef(h->s, i1, im, gbuffer, rows, standardize ? 1 : 0, coef,
-                                                  (hipStream_t)stream);
-    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "residual: %s", hipGetErrorString(e));
+    hipError_t e = sonar::surrogate_target_coef(h->s, im, gbuffer, rows, standardize ? 1 : 0, coef,
+                                                (hipStream_t)stream);
+    return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "target: %s", hipGetErrorString(e));
 }
 
 sonar_status sonar_surrogate_moments(sonar_surrogate *h, const float *coef, int64_t rows, double *sum, double *sq,

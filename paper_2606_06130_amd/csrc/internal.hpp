@@ -168,7 +168,8 @@ struct BatchLaunch {
     uint32_t *queue;
     unsigned long long *t0, *t1;
     int blocks_per_cu;       // persistent grid = CUs x this (0: occupancy limit)
-    int tiles_per_item;      // tiles popped per queue operation
+    int tiles_per_item;      // units popped per queue operation
+    int waves_per_block;     // workgroup size in waves (1, 2, 4; layered and retro batches: 4); a unit is that many 64-ray waves
     const DetectArgs *emit;  // batched point emission after the pings (nullptr: none)
     int max_beams;           // largest beam count of the batch (emission grid)
 };
@@ -252,8 +253,9 @@ hipError_t surrogate_gradient(Surrogate *s, const float *gbuf, int n_img, int H,
                               float *dev_grad, float *dev_loss, hipStream_t st);
 hipError_t surrogate_train_step(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
                                 float lr, float *dev_loss, hipStream_t st);
-hipError_t surrogate_residual_coef(const Surrogate *s, const float *i1, const float *im, const float *gbuf,
-                                   int64_t rows, int standardize, float *coef, hipStream_t st);
+hipError_t surrogate_set_loss_weights(Surrogate *s, const float *w);
+hipError_t surrogate_target_coef(const Surrogate *s, const float *im, const float *gbuf, int64_t rows,
+                                 int standardize, float *coef, hipStream_t st);
 hipError_t surrogate_coef_moments(Surrogate *s, const float *coef, int64_t rows, double *host_sum, double *host_sq,
                                   hipStream_t st);
 hipError_t surrogate_profile_errors(const Surrogate *s, const float *pred, const float *i1, const float *im,

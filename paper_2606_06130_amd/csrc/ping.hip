@@ -10,7 +10,7 @@
 // Per wavefront: the rays of a beam sit in adjacent lanes (64 / N_r beams per
 // wave); their contributions are reduced in a fixed order in LDS and each
 // beam's whole range column is written once with coalesced stores, zeros
-// included (coherent summation within each ray bundle, Sec. II-B). No global
+// included (a beam is the complex sum over its bundle of rays, Sec. II-B). No global
 // atomics, no memset, bit-reproducible.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -450,15 +450,16 @@ __device__ __forceinline__ bool occluded_layered(const PingArgs &a, const d3 P, 
 }
 
 
-// The ping body for one tile of 256 consecutive rays (4 wavefronts). `a` is
-// the ping's argument block (kernel arguments, or a batch descriptor in
-// device memory); `W` is this wavefront's LDS area.
+// The ping body for one block of consecutive rays (blockDim.x of them, one
+// lane each, starting at ray0; a multiple of 64). `a` is the ping's argument
+// block (kernel arguments, or a batch descriptor in device memory); `W` is
+// this wavefront's LDS area.
 template <int DEPTH, int K, bool ARC, bool STATS, bool LAYERED = false, bool RETRO = false>
-__device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uint32_t *__restrict__ W)
+__device__ __forceinline__ void ping_tile(const PingArgs &a, const int64_t ray0, uint32_t *__restrict__ W)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x / WAVE;
-    const int64_t gid = (int64_t)tile * BLOCK + threadIdx.x;
+    const int64_t gid = ray0 + threadIdx.x;
     const int64_t beam = gid >> a.log2_nr;
     const int j = (int)(gid & (a.n_r - 1));
     const bool active = beam < a.n_beams;
@@ -854,7 +855,7 @@ __device__ __forceinline__ void ping_tile(const PingArgs &a, const int tile, uin
         sval[lane] = make_float4(slot0.re, slot0.im, slot0.inc, 0.f);
     }
     wave_sync();
-    reduce_tile<KS>(a, tile, wave, lane, j, active, sbin, sval, sidx32);
+    reduce_tile<KS>(a, ray0, wave, lane, j, active, sbin, sval, sidx32);
 }
 
 // STATS instantiations count traversal work per ray (a diagnostic: the
@@ -875,19 +876,21 @@ void k_ping(PingArgs a, int wave_words)
         // argument block where it lies (kernel-argument memory, the block is
         // the first argument), not from a private per-lane copy of it.
         const PingArgs *ka = (const PingArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-        ping_tile<DEPTH, K, ARC, STATS, LAYERED, RETRO>(*ka, xcd_remap(blockIdx.x, gridDim.x), W);
+        ping_tile<DEPTH, K, ARC, STATS, LAYERED, RETRO>(*ka, (int64_t)xcd_remap(blockIdx.x, gridDim.x) * BLOCK, W);
     } else {
-        ping_tile<DEPTH, K, ARC, STATS, LAYERED, RETRO>(a, xcd_remap(blockIdx.x, gridDim.x), W);
+        ping_tile<DEPTH, K, ARC, STATS, LAYERED, RETRO>(a, (int64_t)xcd_remap(blockIdx.x, gridDim.x) * BLOCK, W);
     }
 }
 
-// Persistent batch: every block pops (ping, tile) items from one device
-// counter until the queue is empty; per-ping first-start and last-finish
-// stamps come from the constant-rate device clock. All pings of a batch share
-// the hierarchy depth class, bounce count and medium type (template
-// arguments); layouts, rays per beam, poses and outputs come per ping from
-// its descriptor.
-template <int DEPTH, int K, bool ARC, bool LAYERED = false, bool RETRO = false>
+// Persistent batch: every block (WPB waves) pops items of `tiles_per_item`
+// units from one device counter until the queue is empty; a unit is WPB * 64
+// consecutive rays of one ping (a ping's rays are laid out in 256-ray tiles,
+// so a unit never straddles two pings). Per-ping first-start and
+// last-finish stamps come from the constant-rate device clock. All pings of
+// a batch share the hierarchy depth class, bounce count and medium type
+// (template arguments); layouts, rays per beam, poses and outputs come per
+// ping from its descriptor.
+template <int DEPTH, int K, bool ARC, bool LAYERED = false, bool RETRO = false, int WPB = WAVES_PER_BLOCK>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, BLOCK), amdgpu_waves_per_eu(ping_waves_per_eu<K, ARC>())))
 void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
                                                       uint32_t *__restrict__ queue, unsigned long long *__restrict__ t0,
@@ -896,10 +899,11 @@ void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
 {
     extern __shared__ uint32_t lds[];
     __shared__ int s_item;
+    constexpr int UNITS_PER_TILE = WAVES_PER_BLOCK / WPB;     // units in a 256-ray tile
     uint32_t *W = lds + (size_t)(threadIdx.x / WAVE) * wave_words;
     const PingArgs &last = desc[n_pings - 1];
-    const int total_tiles = last.tile_offset + last.n_tiles;
-    const int n_items = (total_tiles + tiles_per_item - 1) / tiles_per_item;
+    const int total_units = (last.tile_offset + last.n_tiles) * UNITS_PER_TILE;
+    const int n_items = (total_units + tiles_per_item - 1) / tiles_per_item;
     while (true) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
         __syncthreads();
@@ -907,8 +911,9 @@ void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
         __syncthreads();
         if (item >= n_items) break;
         for (int q = 0; q < tiles_per_item; ++q) {
-            const int gt = item * tiles_per_item + q;
-            if (gt >= total_tiles) break;
+            const int gu = item * tiles_per_item + q;
+            if (gu >= total_units) break;
+            const int gt = gu / UNITS_PER_TILE;
             // the ping holding global tile gt: last descriptor with tile_offset <= gt
             int lo = 0, hi = n_pings - 1;
             while (lo < hi) {
@@ -917,8 +922,9 @@ void k_ping_batch(const PingArgs *__restrict__ desc, int n_pings,
                 else hi = mid - 1;
             }
             const PingArgs &a = desc[lo];
+            const int64_t ray0 = (int64_t)(gu - a.tile_offset * UNITS_PER_TILE) * (WPB * WAVE);
             unsigned long long start = __builtin_amdgcn_s_memrealtime();
-            ping_tile<DEPTH, K, ARC, false, LAYERED, RETRO>(a, gt - a.tile_offset, W);
+            if (ray0 < a.n_rays) ping_tile<DEPTH, K, ARC, false, LAYERED, RETRO>(a, ray0, W);
             __syncthreads();
             if (threadIdx.x == 0) {
                 unsigned long long end = __builtin_amdgcn_s_memrealtime();
@@ -1106,15 +1112,14 @@ hipError_t launch_ping_layered(const PingArgs &a, int stack_depth, hipStream_t s
     return hipGetLastError();
 }
 
-template <int D, int KK, bool AR, bool LAY = false, bool RET = false>
+template <int D, int KK, bool AR, bool LAY = false, bool RET = false, int WPB = WAVES_PER_BLOCK>
 static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int *occ)
 {
     const int ww = ping_wave_words(D, b.max_bins, KK, RET);
-    const size_t shmem = (size_t)ww * 4 * WAVES_PER_BLOCK;
-    if (query) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occ, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY, RET>), BLOCK, shmem);
-    }
+    const int threads = WPB * WAVE;
+    const size_t shmem = (size_t)ww * 4 * WPB;
+    const void *kern = reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY, RET, WPB>);
+    if (query) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, threads, shmem);
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1122,35 +1127,46 @@ static hipError_t batch_go(const BatchLaunch &b, hipStream_t s, bool query, int 
     int per_cu = b.blocks_per_cu;
     if (per_cu <= 0) {
         int o = 1;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &o, reinterpret_cast<const void *>(k_ping_batch<D, KK, AR, LAY, RET>), BLOCK, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, threads, shmem);
         if (e != hipSuccess) return e;
         per_cu = o > 0 ? o : 1;
     }
     const int tpi = b.tiles_per_item > 0 ? b.tiles_per_item : 1;
-    const int64_t items = (b.total_tiles + tpi - 1) / tpi;
+    const int64_t units = b.total_tiles * (WAVES_PER_BLOCK / WPB);
+    const int64_t items = (units + tpi - 1) / tpi;
     int64_t grid = (int64_t)cus * per_cu;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_batch_reset, dim3((b.n_pings + 255) / 256), dim3(256), 0, s, b.queue, b.t0, b.t1,
                        b.n_pings);
     if (b.rx) hipLaunchKernelGGL(k_rx_reset_batch, dim3((b.n_pings + 255) / 256), dim3(256), 0, s, b.desc, b.n_pings);
-    hipLaunchKernelGGL((k_ping_batch<D, KK, AR, LAY, RET>), dim3((unsigned)grid), dim3(BLOCK), shmem, s, b.desc, b.n_pings,
-                       b.queue, b.t0, b.t1, ww, tpi);
+    hipLaunchKernelGGL((k_ping_batch<D, KK, AR, LAY, RET, WPB>), dim3((unsigned)grid), dim3(threads), shmem, s, b.desc,
+                       b.n_pings, b.queue, b.t0, b.t1, ww, tpi);
     if (b.rx)
         hipLaunchKernelGGL(k_rx_scatter_batch, dim3(64, (unsigned)(b.n_pings < 4096 ? b.n_pings : 4096)), dim3(256), 0,
                            s, b.desc, b.n_pings);
     return hipGetLastError();
 }
 
+// The workgroup size knob (1, 2 or 4 waves) of the common instantiations.
+template <int D, int KK, bool AR>
+static hipError_t batch_go_wpb(const BatchLaunch &b, hipStream_t s, bool query, int *occ)
+{
+    switch (b.waves_per_block) {
+        case 1: return batch_go<D, KK, AR, false, false, 1>(b, s, query, occ);
+        case 2: return batch_go<D, KK, AR, false, false, 2>(b, s, query, occ);
+        default: return batch_go<D, KK, AR, false, false, 4>(b, s, query, occ);
+    }
+}
+
 static hipError_t batch_dispatch(const BatchLaunch &b, hipStream_t s, bool query, int *occ)
 {
 #define SONAR_BK(D, AR)                                           \
     switch (b.K) {                                                \
-        case 1: return batch_go<D, 1, AR>(b, s, query, occ);      \
-        case 2: return batch_go<D, 2, AR>(b, s, query, occ);      \
-        case 3: return batch_go<D, 3, AR>(b, s, query, occ);      \
-        default: return batch_go<D, 4, AR>(b, s, query, occ);     \
+        case 1: return batch_go_wpb<D, 1, AR>(b, s, query, occ);  \
+        case 2: return batch_go_wpb<D, 2, AR>(b, s, query, occ);  \
+        case 3: return batch_go_wpb<D, 3, AR>(b, s, query, occ);  \
+        default: return batch_go_wpb<D, 4, AR>(b, s, query, occ); \
     }
     if (b.retro && b.K > 1) {
         // retro-chain returns: their own instantiations (deep stack, 2K - 1 slots)

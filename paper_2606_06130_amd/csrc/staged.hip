@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_stage_accumulate(PingArgs a, int wave_w
         sval[k * WAVE + lane] = v;
     }
     wave_sync();
-    reduce_tile<KS>(a, tile, wave, lane, j, active, sbin, sval, sidx32);
+    reduce_tile<KS>(a, (int64_t)tile * BLOCK, wave, lane, j, active, sbin, sval, sidx32);
 }
 
 int stage_stack_words(int depth) { return (depth > STG_LDS_STACK ? STG_LDS_STACK : depth) * WAVE; }

@@ -4,7 +4,8 @@
 // Here a small network maps each beam's single-bounce G-buffer (3 x 3 beam
 // neighbourhood of 8 features: the first-hit statistics and the beam axis's
 // vertical component) to the first 64 orthonormal DCT-II coefficients of the
-// dB residual that further bounces add to its range profile. Layers: im2col
+// dB level, above the intensity floor, of what further bounces add to its
+// range profile. Layers: im2col
 // convolution 72 (+56 zero) -> 64, then 64 -> 256 -> 256 -> 256 -> 64, ReLU
 // between layers.
 //
@@ -159,10 +160,10 @@ __global__ void k_im2col(const float *__restrict__ g, int n_img, int H, int W, _
     x[i] = (__bf16)v;
 }
 
-// MSE on the 64 coefficients: dZ = 2 (y - t) / (rows * 64) in BF16 and per
-// block partial sums of (y - t)^2 in FP64.
-__global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, int64_t n, __bf16 *__restrict__ dz,
-                      double *__restrict__ part)
+// Weighted MSE on the 64 coefficients: dZ = 2 w_j (y - t) / (rows * 64) in
+// BF16 and per block partial sums of w_j (y - t)^2 in FP64.
+__global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, const float *__restrict__ w,
+                      int64_t n, __bf16 *__restrict__ dz, double *__restrict__ part)
 {
     __shared__ double sh[256];
     const int64_t i0 = (int64_t)blockIdx.x * 256 * 16;
@@ -171,9 +172,9 @@ __global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, 
     for (int q = 0; q < 16; ++q) {
         const int64_t i = i0 + (int64_t)q * 256 + threadIdx.x;
         if (i < n) {
-            const float d = y[i] - t[i];
-            dz[i] = (__bf16)(sc * d);
-            s += (double)d * d;
+            const float d = y[i] - t[i], wj = w[i & (NCOEF - 1)];
+            dz[i] = (__bf16)(sc * wj * d);
+            s += (double)wj * d * d;
         }
     }
     sh[threadIdx.x] = s;
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(64) void k_smooth(const float *__restrict__ i1, con
     const int per = (nb + 63) / 64;
     const int b0 = lane * per, b1 = min(b0 + per, nb);
     const double inv = 1.0 / w;
-    for (int ch = 0; ch < (im ? 2 : 1); ++ch) {
+    for (int ch = i1 ? 0 : 1; ch < (im ? 2 : 1); ++ch) {
         const float *src = (ch ? im : i1) + o;
         float *dst = (ch ? sm : s1) + o;
 #pragma unroll 8
@@ -313,16 +314,17 @@ __device__ __forceinline__ int first_hit_bin(const float *__restrict__ g, int64_
     return (int)fminf(fmaxf(b, 0.f), (float)(nb - 1));
 }
 
-// Residual target: for each row, c_j = sum_r' C[j][r'] res[r' + r1], the
-// range-smoothed dB residual 10 log10(I1 + Im + floor) - 10 log10(I1 + floor)
-// shifted so the beam's first-hit bin r1 is bin 0 (zero past the end),
-// optionally standardised (c - mu_j) / sigma_j. Block: 64 rows x 64
-// coefficients; bins staged 64 at a time in LDS.
-__global__ __launch_bounds__(256) void k_residual_coef(const float *__restrict__ i1, const float *__restrict__ im,
-                                                       const float *__restrict__ gbuf, int64_t rows, int nb,
-                                                       float r_min, float r_max, const float *__restrict__ basis,
-                                                       const float *__restrict__ mu, const float *__restrict__ sg,
-                                                       int standardize, float *__restrict__ coef)
+// Level target: for each row, c_j = sum_r' C[j][r'] lev[r' + r1], with
+// lev = 10 log10(1 + Ims / floor) the dB level of the range-smoothed
+// later-bounce channel above the floor, shifted so the beam's first-hit bin
+// r1 is bin 0 (zero past the end), optionally standardised
+// (c - mu_j) / sigma_j. Block: 64 rows x 64 coefficients; bins staged 64 at a
+// time in LDS.
+__global__ __launch_bounds__(256) void k_level_coef(const float *__restrict__ im, const float *__restrict__ gbuf,
+                                                    int64_t rows, int nb, float r_min, float r_max,
+                                                    const float *__restrict__ basis, const float *__restrict__ mu,
+                                                    const float *__restrict__ sg, int standardize,
+                                                    float *__restrict__ coef)
 {
     __shared__ float R[64][65];
     __shared__ float Cb[64][65];
@@ -341,11 +343,7 @@ __global__ __launch_bounds__(256) void k_residual_coef(const float *__restrict__
             const int r = e >> 6, b = e & 63;
             float v = 0.f;
             const int src = b0 + b + r1s[r];
-            if (r0 + r < rows && src < nb) {
-                const int64_t o = (r0 + r) * nb + src;
-                const float a1 = i1[o], am = im[o];
-                v = 10.f * (log10f(a1 + am + I_FLOOR) - log10f(a1 + I_FLOOR));
-            }
+            if (r0 + r < rows && src < nb) v = 10.f * log10f(1.f + im[(r0 + r) * nb + src] * (1.f / I_FLOOR));
             R[r][b] = v;
             Cb[r][b] = (b0 + b < nb) ? basis[(int64_t)r * nb + b0 + b] : 0.f;
         }
@@ -387,9 +385,9 @@ __global__ void k_coef_moments(const float *__restrict__ c, int64_t rows, double
     }
 }
 
-// Single-bounce profile plus the mean residual, per bin: the inverse DCT of
-// the mean coefficients (for the mean-residual baseline error).
-__global__ void k_mean_residual(const float *__restrict__ basis, const float *__restrict__ mu, int nb,
+// Mean level per bin: the inverse DCT of the mean coefficients (for the
+// mean-level baseline error).
+__global__ void k_mean_level(const float *__restrict__ basis, const float *__restrict__ mu, int nb,
                                 float *__restrict__ mres)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -400,12 +398,18 @@ __global__ void k_mean_residual(const float *__restrict__ basis, const float *__
 }
 
 // Predicted range-smoothed profile and per-beam dB errors. For row k with
-// first-hit bin r1: profile[b] = 10 log10(I1s[b] + floor) for b < r1 and
-// + Q[k][b - r1] after it, with Q[k][c] = sum_j C[j][c] c_kj the inverse DCT
-// of the de-standardised prediction. Errors over occupied bins (smoothed
-// truth more than 3 dB above the floor): [0] the prediction, [1] the single
-// bounce alone, [2] the single bounce plus the mean residual, [3] the number
-// of occupied bins.
+// first-hit bin r1: profile[b] = 10 log10(I1s[b] + floor 10^(lev[b] / 10)),
+// lev[b] = Q[k][b - r1] from r1 on and 0 before it, with
+// Q[k][c] = sum_j C[j][c] c_kj the inverse DCT of the de-standardised
+// prediction (a zero level leaves the single-bounce profile). Errors, as
+// mean |error| in dB per beam:
+//  over bins whose smoothed truth 10 log10(I1s + Ims + floor) is more than
+//  3 dB above the floor: [0] the prediction, [1] the smoothed single bounce,
+//  [2] the smoothed single bounce plus the mean level, [3] the bin count;
+//  over bins whose raw truth 10 log10(I1 + Im + floor) is more than 3 dB
+//  above the floor: [4] the prediction, [5] the smoothed truth (what any
+//  range-smoothed profile can reach at best), [6] the raw single bounce
+//  10 log10(I1 + floor), [7] the bin count.
 // Block: 16 rows, 4 waves, in two phases.
 //  1. Q on the matrix cores, wave q taking a quarter of the columns c: 16 x
 //     16 x 4 FP32 MFMA steps, A the 16 rows' coefficients (lane l: row l % 16,
@@ -423,17 +427,21 @@ constexpr int PR_ROWS = 16;
 // normal, positive arguments here: x >= the 1e-11 floor).
 __device__ __forceinline__ float db10(float x) { return 3.01029995663981195f * __log2f(x); }
 
+constexpr int N_ERR = 8;
+constexpr float DB_TO_LOG2 = 0.332192809488736235f;     // log2(10) / 10
+
 template <int P>
 __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict__ pred, const float *__restrict__ i1,
-                                                        const float *__restrict__ im, const float *__restrict__ gbuf,
+                                                        const float *__restrict__ im, const float *__restrict__ i1r,
+                                                        const float *__restrict__ imr, const float *__restrict__ gbuf,
                                                         int64_t rows, int nb, float r_min, float r_max,
                                                         const float *__restrict__ mu, const float *__restrict__ sg,
-                                                        const float *__restrict__ mres, float *__restrict__ err,
+                                                        const float *__restrict__ mlev, float *__restrict__ err,
                                                         float *__restrict__ profile)
 {
     extern __shared__ float Q[];              // [PR_ROWS][nb + 1]
     __shared__ int r1s[PR_ROWS];
-    __shared__ float red[PR_ROWS][4][4];
+    __shared__ float red[PR_ROWS][4][N_ERR];
     const int t = threadIdx.x, lane = t & 63, wq = t >> 6;
     const int ar = lane & 15, kq = lane >> 4;
     const int pitch = nb + 1;
@@ -529,38 +537,44 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
             const int64_t row = r0 + rl;
             const bool rok = row < rows;
             const int r1 = r1s[rl];
-            float es = 0.f, e1 = 0.f, em = 0.f, no = 0.f;
+            float e[N_ERR];
+#pragma unroll
+            for (int k = 0; k < N_ERR; ++k) e[k] = 0.f;
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 const int b = t + 256 * q;
                 if (!rok || b >= nb) continue;
-                const float p1 = db10(iv[rl][q] + I_FLOOR);
-                const float res = b >= r1 ? Q[rl * pitch + (b - r1)] : 0.f;
-                const float ph = p1 + res;
+                const float a1 = iv[rl][q];
+                const float lev = b >= r1 ? Q[rl * pitch + (b - r1)] : 0.f;
+                const float ph = db10(a1 + I_FLOOR * exp2f(lev * DB_TO_LOG2));
                 if (profile) __builtin_nontemporal_store(ph, profile + row * nb + b);      // streamed out
                 if (im) {
-                    const float tr = db10(iv[rl][q] + mv[h][q] + I_FLOOR);
+                    const float ts = db10(a1 + mv[h][q] + I_FLOOR);
+                    if (ts > occ_db) {
+                        const float ml = (b >= r1 && mlev) ? mlev[b - r1] : 0.f;
+                        const float p1 = db10(a1 + I_FLOOR);
+                        e[0] += fabsf(ph - ts);
+                        e[1] += fabsf(p1 - ts);
+                        e[2] += fabsf(db10(a1 + I_FLOOR * exp2f(ml * DB_TO_LOG2)) - ts);
+                        e[3] += 1.f;
+                    }
+                    const float r1v = i1r[row * nb + b];
+                    const float tr = db10(r1v + imr[row * nb + b] + I_FLOOR);
                     if (tr > occ_db) {
-                        const float mr = (b >= r1 && mres) ? mres[b - r1] : 0.f;
-                        es += fabsf(ph - tr);
-                        e1 += fabsf(p1 - tr);
-                        em += fabsf(p1 + mr - tr);
-                        no += 1.f;
+                        e[4] += fabsf(ph - tr);
+                        e[5] += fabsf(ts - tr);
+                        e[6] += fabsf(db10(r1v + I_FLOOR) - tr);
+                        e[7] += 1.f;
                     }
                 }
             }
             if (err) {
-                for (int off = 32; off > 0; off >>= 1) {
-                    es += __shfl_xor(es, off);
-                    e1 += __shfl_xor(e1, off);
-                    em += __shfl_xor(em, off);
-                    no += __shfl_xor(no, off);
-                }
+#pragma unroll
+                for (int k = 0; k < N_ERR; ++k)
+                    for (int off = 32; off > 0; off >>= 1) e[k] += __shfl_xor(e[k], off);
                 if (lane == 0) {
-                    red[rl][wq][0] = es;
-                    red[rl][wq][1] = e1;
-                    red[rl][wq][2] = em;
-                    red[rl][wq][3] = no;
+#pragma unroll
+                    for (int k = 0; k < N_ERR; ++k) red[rl][wq][k] = e[k];
                 }
             }
         }
@@ -568,14 +582,146 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
     if (!err) return;
     __syncthreads();
     if (t < PR_ROWS && r0 + t < rows) {
-        float sm[4];
-        for (int q = 0; q < 4; ++q) sm[q] = red[t][0][q] + red[t][1][q] + red[t][2][q] + red[t][3][q];
-        const float n = sm[3];
-        float *o = err + (r0 + t) * 4;
-        o[0] = n > 0.f ? sm[0] / n : NAN;
-        o[1] = n > 0.f ? sm[1] / n : NAN;
-        o[2] = n > 0.f ? sm[2] / n : NAN;
-        o[3] = n;
+        float sm[N_ERR];
+        for (int q = 0; q < N_ERR; ++q) sm[q] = red[t][0][q] + red[t][1][q] + red[t][2][q] + red[t][3][q];
+        float *o = err + (r0 + t) * N_ERR;
+        for (int g = 0; g < 2; ++g) {
+            const float n = sm[4 * g + 3];
+            for (int q = 0; q < 3; ++q) o[4 * g + q] = n > 0.f ? sm[4 * g + q] / n : NAN;
+            o[4 * g + 3] = n;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference: all five layers for a tile of MLP_ROWS rows in one block.
+// The tile's activations stay in LDS (BF16, one buffer the layers overwrite
+// in place: every wave finishes reading a layer's input before any writes
+// its output), the accumulators in registers. Wave w owns a quarter of each
+// layer's output columns for all MLP_ROWS rows; its weight fragments come
+// straight from the k-contiguous BF16 mirror wt[l] [N][Kp] (L2-resident,
+// each fragment read by one wave of the block), loaded one k-step ahead of
+// the products that use them. Products, bias, ReLU and BF16 rounding are
+// those of the layer-by-layer path, in the same k order.
+constexpr int MLP_ROWS = 64;
+constexpr int MLP_LDA = 256 + 8;          // LDS row pitch in bf16 (16 B pad against bank conflicts)
+constexpr int L0_K = 96;                  // layer 0 fan-in 72 rounded up to the k-step (32)
+
+struct MlpWeights {
+    const __bf16 *wt[NL];
+    const float *bias[NL];
+};
+
+template <int K, int N>
+__device__ __forceinline__ void mlp_layer(const __bf16 *__restrict__ act, const __bf16 *__restrict__ wt, int ldw,
+                                          int wave, int lane, f32x4 (&acc)[4][N / 64])
+{
+    constexpr int NT = N / 64;            // 16-column tiles per wave
+    const int ncol0 = wave * (N / 4);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 b[NT], bn[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(wt + (int64_t)(ncol0 + 16 * j + (lane & 15)) * ldw + 8 * (lane >> 4));
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                bn[j] = *reinterpret_cast<const bf16x8 *>(wt + (int64_t)(ncol0 + 16 * j + (lane & 15)) * ldw + k0 +
+                                                          32 + 8 * (lane >> 4));
+        }
+        bf16x8 a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a[i] = *reinterpret_cast<const bf16x8 *>(act + (16 * i + (lane & 15)) * MLP_LDA + k0 + 8 * (lane >> 4));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) b[j] = bn[j];
+        }
+    }
+}
+
+// bias + ReLU + BF16 into the activation tile (after the barrier that ends
+// every wave's reads of the layer input)
+template <int N>
+__device__ __forceinline__ void mlp_store(__bf16 *__restrict__ act, const float *__restrict__ bias, int wave, int lane,
+                                          const f32x4 (&acc)[4][N / 64])
+{
+    constexpr int NT = N / 64;
+    const int ncol0 = wave * (N / 4);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int n = ncol0 + 16 * j + (lane & 15);
+        const float bn = bias[n];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = acc[i][j][e] + bn;
+                act[(16 * i + 4 * (lane >> 4) + e) * MLP_LDA + n] = (__bf16)(v > 0.f ? v : 0.f);
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ g, int H, int W, MlpWeights wts,
+                                                     float *__restrict__ y)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 act[MLP_ROWS * MLP_LDA];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * MLP_ROWS;
+    // layer-0 input: the 3 x 3 neighbourhood features of each row, zero
+    // outside the image and in the padding columns 72 .. 95
+    for (int e = t; e < MLP_ROWS * L0_K; e += 256) {
+        const int r = e / L0_K, c = e % L0_K;
+        float v = 0.f;
+        if (c < LK[0]) {
+            const int q = c / NFEAT, f = c % NFEAT;
+            const int64_t row = r0 + r;
+            const int img = (int)(row / ((int64_t)H * W));
+            const int rem = (int)(row % ((int64_t)H * W));
+            const int vv = rem / W + q / 3 - 1, hh = rem % W + q % 3 - 1;
+            if (vv >= 0 && vv < H && hh >= 0 && hh < W) v = g[(((int64_t)img * H + vv) * W + hh) * GB_STRIDE + f];
+        }
+        act[r * MLP_LDA + c] = (__bf16)v;
+    }
+    __syncthreads();
+    {
+        f32x4 acc[4][1];
+        mlp_layer<L0_K, 64>(act, wts.wt[0], LKP[0], wave, lane, acc);
+        __syncthreads();
+        mlp_store<64>(act, wts.bias[0], wave, lane, acc);
+        __syncthreads();
+    }
+    {
+        f32x4 acc[4][4];
+        mlp_layer<64, 256>(act, wts.wt[1], LKP[1], wave, lane, acc);
+        __syncthreads();
+        mlp_store<256>(act, wts.bias[1], wave, lane, acc);
+        __syncthreads();
+    }
+    for (int l = 2; l <= 3; ++l) {
+        f32x4 acc[4][4];
+        mlp_layer<256, 256>(act, wts.wt[l], LKP[l], wave, lane, acc);
+        __syncthreads();
+        mlp_store<256>(act, wts.bias[l], wave, lane, acc);
+        __syncthreads();
+    }
+    {
+        f32x4 acc[4][1];
+        mlp_layer<256, 64>(act, wts.wt[4], LKP[4], wave, lane, acc);
+        const int n = wave * 16 + (lane & 15);
+        const float bn = wts.bias[4][n];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                y[(r0 + 16 * i + 4 * (lane >> 4) + e) * NCOEF + n] = acc[i][0][e] + bn;
     }
 }
 
@@ -597,7 +743,8 @@ struct Surrogate {
     double *dpart = nullptr;     // loss / moment partials
     float *basis = nullptr;      // [64][n_bins]
     float *s1 = nullptr, *sm = nullptr;   // range-smoothed channels [max_rows][n_bins]
-    float *mres = nullptr;                // mean-residual profile [n_bins]
+    float *mlev = nullptr;                // mean-level profile [n_bins]
+    float *lw = nullptr;                  // loss weights [64]
     float r_min = 0.f, r_max = 0.f;
     int smooth = 32;
     float *mu = nullptr, *sg = nullptr;
@@ -654,7 +801,8 @@ hipError_t surrogate_create(int64_t max_rows, int n_bins, float r_min, float r_m
     SA(s->basis, (size_t)NCOEF * n_bins * 4);
     SA(s->s1, (size_t)max_rows * n_bins * 4);
     SA(s->sm, (size_t)max_rows * n_bins * 4);
-    SA(s->mres, (size_t)n_bins * 4);
+    SA(s->mlev, (size_t)n_bins * 4);
+    SA(s->lw, NCOEF * 4);
     SA(s->mu, NCOEF * 4);
     SA(s->sg, NCOEF * 4);
 #undef SA
@@ -673,6 +821,7 @@ hipError_t surrogate_create(int64_t max_rows, int n_bins, float r_min, float r_m
     e = hipMemcpy(s->basis, B.data(), B.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->mu, mu.data(), NCOEF * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->sg, sg.data(), NCOEF * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->lw, sg.data(), NCOEF * 4, hipMemcpyHostToDevice);   // weights 1
     for (float **p : {&s->master, &s->adam_m, &s->adam_v, &s->grad})
         if (e == hipSuccess) e = hipMemcpy(*p, zero.data(), N_PARAMS * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -723,6 +872,12 @@ hipError_t surrogate_set_norm(Surrogate *s, const float *mu, const float *sg)
     return e;
 }
 
+hipError_t surrogate_set_loss_weights(Surrogate *s, const float *w)
+{
+    std::vector<float> one(NCOEF, 1.f);
+    return hipMemcpy(s->lw, w ? w : one.data(), NCOEF * 4, hipMemcpyHostToDevice);
+}
+
 template <bool TA, bool TB, int EPI>
 static void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, int K, int kchunk, int split, const float *bias,
                  const __bf16 *mask, int ldm, void *out, int ldo, int M, int N, hipStream_t st)
@@ -746,11 +901,17 @@ static void forward_layers(Surrogate *s, const float *gbuf, int n_img, int H, in
     }
 }
 
+// Inference: one fused launch (rows a multiple of MLP_ROWS, checked by the caller).
 hipError_t surrogate_forward(Surrogate *s, const float *gbuf, int n_img, int H, int W, float *coef, hipStream_t st)
 {
-    forward_layers(s, gbuf, n_img, H, W, st);
     const int64_t rows = (int64_t)n_img * H * W;
-    return hipMemcpyAsync(coef, s->y, (size_t)rows * NCOEF * 4, hipMemcpyDeviceToDevice, st);
+    MlpWeights w;
+    for (int l = 0; l < NL; ++l) {
+        w.wt[l] = s->wt[l];
+        w.bias[l] = s->bias[l];
+    }
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)(rows / MLP_ROWS)), dim3(256), 0, st, gbuf, H, W, w, coef);
+    return hipGetLastError();
 }
 
 // Forward, loss and backward into s->grad; returns the loss on the device.
@@ -761,7 +922,7 @@ static hipError_t gradient(Surrogate *s, const float *gbuf, int n_img, int H, in
     forward_layers(s, gbuf, n_img, H, W, st);
     const int64_t n = rows * NCOEF;
     const int nblk = (int)((n + 4095) / 4096);
-    hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, st, s->y, target, n, s->dz[0], s->dpart);
+    hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, st, s->y, target, s->lw, n, s->dz[0], s->dpart);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, s->dpart, nblk, n, dev_loss);
     const int S = (int)((rows + SPLIT_ROWS - 1) / SPLIT_ROWS);
     int cur = 0;
@@ -815,12 +976,12 @@ static void smooth_channels(const Surrogate *s, const float *i1, const float *im
     hipLaunchKernelGGL(k_smooth, dim3((unsigned)rows), dim3(64), lds, st, i1, im, s->n_bins, s->smooth, s->s1, s->sm);
 }
 
-hipError_t surrogate_residual_coef(const Surrogate *s, const float *i1, const float *im, const float *gbuf,
-                                   int64_t rows, int standardize, float *coef, hipStream_t st)
+hipError_t surrogate_target_coef(const Surrogate *s, const float *im, const float *gbuf, int64_t rows,
+                                 int standardize, float *coef, hipStream_t st)
 {
-    smooth_channels(s, i1, im, rows, st);
-    hipLaunchKernelGGL(k_residual_coef, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, st, s->s1, s->sm, gbuf,
-                       rows, s->n_bins, s->r_min, s->r_max, s->basis, s->mu, s->sg, standardize, coef);
+    smooth_channels(s, nullptr, im, rows, st);
+    hipLaunchKernelGGL(k_level_coef, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, st, s->sm, gbuf, rows,
+                       s->n_bins, s->r_min, s->r_max, s->basis, s->mu, s->sg, standardize, coef);
     return hipGetLastError();
 }
 
@@ -851,14 +1012,14 @@ hipError_t surrogate_profile_errors(const Surrogate *s, const float *pred, const
     // smooth i1 and (if given) im into the surrogate's buffers
     smooth_channels(s, i1, im, rows, st);
     if (im && err)
-        hipLaunchKernelGGL(k_mean_residual, dim3((unsigned)((s->n_bins + 255) / 256)), dim3(256), 0, st, s->basis,
-                           s->mu, s->n_bins, s->mres);
+        hipLaunchKernelGGL(k_mean_level, dim3((unsigned)((s->n_bins + 255) / 256)), dim3(256), 0, st, s->basis,
+                           s->mu, s->n_bins, s->mlev);
     const size_t lds = (size_t)PR_ROWS * (s->n_bins + 1) * sizeof(float);
     const int per = (s->n_bins + 255) / 256;
 #define SONAR_PROFILE(PP)                                                                                        \
     hipLaunchKernelGGL(k_profile_errors<PP>, dim3((unsigned)((rows + PR_ROWS - 1) / PR_ROWS)), dim3(256), lds, st, \
-                       pred, s->s1, im ? s->sm : nullptr, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->mu, s->sg, \
-                       s->mres, err, profile)
+                       pred, s->s1, im ? s->sm : nullptr, i1, im, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->mu, \
+                       s->sg, s->mlev, err, profile)
     if (per <= 1) SONAR_PROFILE(1);
     else if (per <= 2) SONAR_PROFILE(2);
     else if (per <= 4) SONAR_PROFILE(4);

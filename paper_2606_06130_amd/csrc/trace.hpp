@@ -608,10 +608,10 @@ __device__ __forceinline__ void rx_append(const PingArgs &a, const bool want, co
 // write (with the fused CFAR test when it is on). Slot (k, lane) holds bin
 // sbin[k * 64 + lane] and value sval[k * 64 + lane] = (re, im, first-bounce
 // |A|^2, later-bounce |A|^2); lanes hold the rays of 64 / n_r beams in order.
-// `sidx32` is an LDS area of (n_bins + 1) / 2 words for the column index.
-// Every lane of the wave calls it.
+// `sidx32` is an LDS area of (n_bins + 1) / 2 words for the column index;
+// `ray0` is the block's first ray. Every lane of the wave calls it.
 template <int KS>
-__device__ __forceinline__ void reduce_tile(const PingArgs &a, const int tile, const int wave, const int lane,
+__device__ __forceinline__ void reduce_tile(const PingArgs &a, const int64_t ray0, const int wave, const int lane,
                                             const int j, const bool active, int *sbin,
                                             float4 *sval, uint32_t *sidx32)
 {
@@ -662,7 +662,7 @@ __device__ __forceinline__ void reduce_tile(const PingArgs &a, const int tile, c
     wave_sync();
 
     const int bpw = WAVE >> a.log2_nr;
-    const int64_t wave_beam0 = (((int64_t)tile * BLOCK) + wave * WAVE) >> a.log2_nr;
+    const int64_t wave_beam0 = (ray0 + wave * WAVE) >> a.log2_nr;
     const int nb = a.n_bins;
 
     if (a.det_count) {

@@ -36,7 +36,8 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_batch_prepare_detect", "sonar_surrogate_param_count", "sonar_surrogate_create",
            "sonar_surrogate_free", "sonar_surrogate_set_state", "sonar_surrogate_get_state",
            "sonar_surrogate_set_norm", "sonar_surrogate_forward", "sonar_surrogate_train_step",
-           "sonar_surrogate_gradient", "sonar_surrogate_residual", "sonar_surrogate_moments",
+           "sonar_surrogate_gradient", "sonar_surrogate_target", "sonar_surrogate_moments",
+           "sonar_surrogate_set_loss_weights",
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
            "sonar_rx_workspace_size", "sonar_ping_rx", "sonar_add_reverb",
            "sonar_ping_ssp", "sonar_ping_ssp_rx", "sonar_batch_prepare_ssp", "sonar_batch_rx_workspace_size",
@@ -113,7 +114,8 @@ class sonar_batch_plan(C.Structure):
 
 
 class sonar_batch_options(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int32), ("tiles_per_item", C.c_int32), ("emit_desc", C.c_void_p)]
+    _fields_ = [("blocks_per_cu", C.c_int32), ("tiles_per_item", C.c_int32), ("emit_desc", C.c_void_p),
+                ("waves_per_block", C.c_int32), ("pad", C.c_int32)]
 
 
 POINT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("db", "<f4"), ("beam", "<i4"), ("bin", "<i4")])
@@ -218,9 +220,11 @@ def lib():
         L.sonar_surrogate_gradient.restype = C.c_int
         L.sonar_surrogate_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                                C.c_void_p, C.c_void_p, C.c_void_p]
-        L.sonar_surrogate_residual.restype = C.c_int
-        L.sonar_surrogate_residual.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
-                                               C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_set_loss_weights.restype = C.c_int
+        L.sonar_surrogate_set_loss_weights.argtypes = [C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_target.restype = C.c_int
+        L.sonar_surrogate_target.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                             C.c_void_p]
         L.sonar_surrogate_moments.restype = C.c_int
         L.sonar_surrogate_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.sonar_surrogate_profile.restype = C.c_int
@@ -673,9 +677,10 @@ class Batch:
         c = int(self.counts[i].item())
         return self.points[i][:min(c, self.points[i].shape[0])].cpu().numpy().view(POINT_DTYPE).reshape(-1), c
 
-    def options(self, blocks_per_cu=0, tiles_per_item=0):
+    def options(self, blocks_per_cu=0, tiles_per_item=0, waves_per_block=0):
         return sonar_batch_options(blocks_per_cu=blocks_per_cu, tiles_per_item=tiles_per_item,
-                                   emit_desc=self.emit.data_ptr() if self.emit is not None else None)
+                                   emit_desc=self.emit.data_ptr() if self.emit is not None else None,
+                                   waves_per_block=waves_per_block, pad=0)
 
     def run(self, options=None, stream=None):
         o = options if options is not None else self.options()
@@ -697,7 +702,7 @@ class Batch:
         _check(lib().sonar_batch_autotune(self.scene.handle, C.byref(self.plan), _dptr(self.desc),
                                           _dptr(self.workspace), self.workspace.numel(), _stream(stream),
                                           C.byref(best), C.byref(ms)))
-        return self.options(best.blocks_per_cu, best.tiles_per_item), float(ms.value)
+        return self.options(best.blocks_per_cu, best.tiles_per_item, best.waves_per_block), float(ms.value)
 
     def stamps(self, stream=None):
         """(start, finish) device clock stamps per ping, 100 MHz ticks."""
@@ -770,12 +775,17 @@ class Surrogate:
                                               _stream(stream)))
         return g, loss
 
-    def residual(self, i1, im, gbuf, standardize=True, out=None, stream=None):
+    def set_loss_weights(self, w=None):
+        a = None if w is None else np.ascontiguousarray(w, np.float32)
+        _check(lib().sonar_surrogate_set_loss_weights(self._h, a.ctypes.data if a is not None else None))
+
+    def target(self, im, gbuf, standardize=True, out=None, stream=None):
+        """Level-target coefficients [rows, 64] of the later-bounce channel `im`."""
         import torch
-        rows = i1.numel() // self.n_bins
+        rows = im.numel() // self.n_bins
         out = out if out is not None else torch.empty((rows, 64), dtype=torch.float32, device="cuda")
-        _check(lib().sonar_surrogate_residual(self._h, _dptr(i1), _dptr(im), _dptr(gbuf), rows,
-                                              1 if standardize else 0, _dptr(out), _stream(stream)))
+        _check(lib().sonar_surrogate_target(self._h, _dptr(im), _dptr(gbuf), rows, 1 if standardize else 0,
+                                            _dptr(out), _stream(stream)))
         return out
 
     def moments(self, coef, stream=None):
@@ -789,7 +799,7 @@ class Surrogate:
         import torch
         rows = coef.shape[0]
         prof = torch.empty((rows, self.n_bins), dtype=torch.float32, device="cuda") if want_profile else None
-        err = torch.empty((rows, 4), dtype=torch.float32, device="cuda") if im is not None else None
+        err = torch.empty((rows, 8), dtype=torch.float32, device="cuda") if im is not None else None
         _check(lib().sonar_surrogate_profile(self._h, _dptr(coef), _dptr(i1), _dptr(im), _dptr(gbuf), rows,
                                              _dptr(prof), _dptr(err), _stream(stream)))
         return prof, err

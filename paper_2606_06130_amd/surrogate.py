@@ -1,17 +1,19 @@
 """Data generation, training and evaluation of the learned multipath surrogate.
 
-Orchestration only: the pings, residual targets, network forward and
-backward passes, Adam updates, predicted profiles and their dB errors all run
-in the library's HIP kernels; this module assembles batches and schedules.
+Orchestration only: the pings, level targets, network forward and backward
+passes, Adam updates, predicted profiles and their dB errors all run in the
+library's HIP kernels; this module assembles batches and schedules.
 
 Data: multi-bounce pings (3 bounces, c(z) gradient) of the harbor multipath
 scene from random survey poses. Each ping yields the single-bounce G-buffer
-(network input) and the two incoherent channels, whose range-smoothed dB
-residual, aligned to each beam's first-hit bin, compressed to 64 DCT
-coefficients and standardised, is the target.
+(network input) and the later-bounce incoherent channel, whose range-smoothed
+dB level above the intensity floor, aligned to each beam's first-hit bin,
+compressed to 64 DCT coefficients and standardised, is the target. The loss
+weights coefficient j by its variance over the mean variance, which makes it
+the squared error of the level profile (Parseval).
 
-    python -m paper_2606_06130_amd.surrogate --train-pings 2000 --epochs 3 \\
-        --eval-pings 200 --out surrogate_run
+    python -m paper_2606_06130_amd.surrogate --train-pings 20000 --epochs 5 \\
+        --eval-pings 1000 --out surrogate_run
 """
 from __future__ import annotations
 
@@ -54,15 +56,15 @@ class PingSource:
 
 
 def coefficient_stats(sur, src, poses):
-    """Mean and standard deviation of the raw residual coefficients over pings."""
+    """Mean and standard deviation of the raw level coefficients over pings."""
     torch = src.torch
     coef = torch.empty((src.rows, 64), dtype=torch.float32, device="cuda")
     s1 = np.zeros(64)
     s2 = np.zeros(64)
     n = 0
     for p in poses:
-        gb, i1, im = src.run(p)
-        sur.residual(i1, im, gb, standardize=False, out=coef)
+        gb, _, im = src.run(p)
+        sur.target(im, gb, standardize=False, out=coef)
         a, b = sur.moments(coef)
         s1 += a
         s2 += b
@@ -70,6 +72,13 @@ def coefficient_stats(sur, src, poses):
     mean = s1 / n
     std = np.sqrt(np.maximum(s2 / n - mean * mean, 1e-12))
     return mean.astype(np.float32), np.maximum(std, 1e-3).astype(np.float32)
+
+
+def loss_weights(std):
+    """w_j = std_j^2 / mean(std^2): the loss on standardised coefficients is
+    then the squared error of the de-standardised ones (up to one scale)."""
+    v = np.asarray(std, np.float64) ** 2
+    return (v / v.mean()).astype(np.float32)
 
 
 def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
@@ -93,8 +102,8 @@ def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
                 step += 1
                 continue
             for b in range(B):
-                _, i1, im = src.run(poses[order[s * B + b]], gbuf_slot=gb[b])
-                sur.residual(i1, im, gb[b], standardize=True, out=tgt[b * src.rows:(b + 1) * src.rows])
+                _, _, im = src.run(poses[order[s * B + b]], gbuf_slot=gb[b])
+                sur.target(im, gb[b], standardize=True, out=tgt[b * src.rows:(b + 1) * src.rows])
             lr = 0.5 * lr0 * (1.0 + math.cos(math.pi * step / max(total, 1)))
             sur.train_step(gb, tgt, lr, loss)
             if step % 50 == 0 or step == total - 1:
@@ -106,25 +115,33 @@ def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
     return losses
 
 
+ERROR_COLUMNS = ("surrogate", "single_bounce", "mean_level", "occupied_bins",
+                 "surrogate_raw", "smoothed_truth_raw", "single_bounce_raw", "occupied_bins_raw")
+
+
 def evaluate(sur, src, poses):
-    """Mean and p95 per-beam dB errors over beams with occupied bins:
-    surrogate, single bounce only, single bounce + mean residual, and the
-    best any 64-coefficient prediction can do (the truncated truth), all
-    against the smoothed truth; and the surrogate against the truncated truth
-    (the network's own error, the DCT truncation taken out)."""
+    """Per-beam dB errors over held-out pings, mean and p95 over beams.
+
+    Against the range-smoothed truth (beams with occupied smoothed bins): the
+    surrogate, the smoothed single bounce, the smoothed single bounce plus the
+    mean level, the truncated truth (the best any 64-coefficient prediction
+    can do: the truncation floor) and the surrogate against the truncated
+    truth (the network's own error). Against the raw truth (beams with
+    occupied raw bins): the surrogate, the smoothed truth (the floor of any
+    range-smoothed profile) and the raw single-bounce profile."""
     torch = src.torch
     errs, errt, errn = [], [], []
     coef = torch.empty((src.rows, 64), dtype=torch.float32, device="cuda")
     exact = torch.empty((src.rows, 64), dtype=torch.float32, device="cuda")
     gbv = torch.empty((1, src.H, src.W, 8), dtype=torch.float32, device="cuda")
-    # standardised coefficients of a zero residual: the profile is then the smoothed input channel
+    # standardised coefficients of a zero level: the profile is then the smoothed input channel
     zero = torch.from_numpy(-sur.mean / sur.std).cuda().expand(src.rows, 64).contiguous()
     occupied_db = 10.0 * math.log10(1e-11) + 3.0
     for p in poses:
         _, i1, im = src.run(p, gbuf_slot=gbv[0])
         sur.forward(gbv, out=coef)
         pred, e = sur.profile(coef, i1, gbv, im)
-        sur.residual(i1, im, gbv, standardize=True, out=exact)
+        sur.target(im, gbv, standardize=True, out=exact)
         trunc, et = sur.profile(exact, i1, gbv, im)
         truth, _ = sur.profile(zero, i1 + im, gbv)
         occ = truth > occupied_db
@@ -136,27 +153,50 @@ def evaluate(sur, src, poses):
     e = np.concatenate(errs)
     et = np.concatenate(errt)
     en = np.concatenate(errn)
+
+    def stat(v):
+        return {"mean_db": float(np.mean(v)), "p95_db": float(np.percentile(v, 95))}
+
     ok = e[:, 3] > 0
-    e, et, en = e[ok], et[ok], en[ok]
-    out = {"beams": int(ok.sum()), "pings": len(poses)}
-    for i, nm in enumerate(("surrogate", "single_bounce", "mean_residual")):
-        out[nm] = {"mean_db": float(np.mean(e[:, i])), "p95_db": float(np.percentile(e[:, i], 95))}
-    out["truncated_truth"] = {"mean_db": float(np.mean(et[:, 0])), "p95_db": float(np.percentile(et[:, 0], 95))}
-    out["surrogate_vs_truncated_truth"] = {"mean_db": float(np.mean(en)), "p95_db": float(np.percentile(en, 95))}
+    okr = e[:, 7] > 0
+    out = {"pings": len(poses), "beams": int(ok.sum()), "beams_raw": int(okr.sum())}
+    out["surrogate"] = stat(e[ok, 0])
+    out["single_bounce"] = stat(e[ok, 1])
+    out["mean_level"] = stat(e[ok, 2])
+    out["truncated_truth"] = stat(et[ok, 0])
+    out["surrogate_vs_truncated_truth"] = stat(en[ok])
+    out["raw"] = {"surrogate": stat(e[okr, 4]), "smoothed_truth": stat(e[okr, 5]),
+                  "single_bounce": stat(e[okr, 6])}
+    out["meets_1db"] = bool(out["surrogate"]["mean_db"] <= 1.0)
     return out
 
 
-def save_checkpoint(path, sur, mean, std, extra=None):
+def save_checkpoint(path, sur, mean, std, extra=None, weights_only=False):
+    """Weights, standardisation and (unless weights_only) the Adam state, as
+    plain arrays in an .npz (loadable without pickle)."""
     p, m, v, step = sur.get_state()
-    np.savez(path, params=p, adam_m=m, adam_v=v, step=np.int64(step), mean=mean, std=std,
-             extra=json.dumps(extra or {}))
+    arrays = dict(params=p, step=np.int64(step), mean=np.asarray(mean, np.float32),
+                  std=np.asarray(std, np.float32), extra=np.str_(json.dumps(extra or {})))
+    if not weights_only:
+        arrays.update(adam_m=m, adam_v=v)
+    np.savez_compressed(path, **arrays)
 
 
 def load_checkpoint(path, sur):
-    d = np.load(path, allow_pickle=False)
-    sur.set_state(d["params"], d["adam_m"], d["adam_v"], int(d["step"]))
-    sur.set_norm(d["mean"], d["std"])
-    return d["mean"], d["std"], int(d["step"])
+    """Loads a checkpoint into `sur`; returns (mean, std, step, extra dict)."""
+    with np.load(path, allow_pickle=False) as d:
+        if d["params"].shape != (sur.n_params,):
+            raise ValueError(f"{path}: {d['params'].shape[0]} parameters, the network has {sur.n_params}")
+        m = d["adam_m"] if "adam_m" in d.files else None
+        v = d["adam_v"] if "adam_v" in d.files else None
+        sur.set_state(d["params"], m, v, int(d["step"]))
+        mean, std = d["mean"], d["std"]
+        sur.set_norm(mean, std)
+        extra = json.loads(str(d["extra"])) if "extra" in d.files else {}
+        return mean, std, int(d["step"]), extra
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate_harbor_multipath.npz")
 
 
 def main(argv=None):
@@ -169,6 +209,7 @@ def main(argv=None):
     ap.add_argument("--stats-pings", type=int, default=64)
     ap.add_argument("--out", default="surrogate_run")
     ap.add_argument("--resume", default=None)
+    ap.add_argument("--weights-out", default=None, help="also write the weights-only checkpoint here")
     args = ap.parse_args(argv)
     import torch
     os.makedirs(args.out, exist_ok=True)
@@ -189,19 +230,24 @@ def main(argv=None):
     t0 = time.time()
     start = 0
     if args.resume:
-        mean, std, start = load_checkpoint(args.resume, sur)
+        mean, std, start, _ = load_checkpoint(args.resume, sur)
     else:
         mean, std = coefficient_stats(sur, src, train_poses[:args.stats_pings])
         sur.set_norm(mean, std)
         sur.set_state(S.surrogate_init_params(11))
+    sur.set_loss_weights(loss_weights(std))
     log(f"setup {time.time() - t0:.1f}s; rows/ping {src.rows}; params {sur.n_params}")
     losses = train(sur, src, train_poses, args.epochs, args.batch, args.lr, log, start_step=start)
     t_train = time.time() - t0
     save_checkpoint(os.path.join(args.out, "checkpoint.npz"), sur, mean, std)
+    meta = {"target": "level", "smooth": 32, "train_pings": args.train_pings, "train_pose_seed": 5,
+            "epochs": args.epochs, "batch_pings": args.batch, "lr": args.lr, "stats_pings": args.stats_pings}
+    if args.weights_out:
+        save_checkpoint(args.weights_out, sur, mean, std, extra=meta, weights_only=True)
     res = evaluate(sur, src, eval_poses)
-    res.update({"train_pings": args.train_pings, "epochs": args.epochs, "batch_pings": args.batch,
-                "train_seconds": t_train, "final_loss": losses[-1][1] if losses else None,
-                "losses": losses[::max(1, len(losses) // 20)]})
+    res.update(meta)
+    res.update({"train_seconds": t_train, "final_loss": losses[-1][1] if losses else None,
+                "losses": losses[::max(1, len(losses) // 20)], "eval_pose_seed": 6})
     with open(os.path.join(args.out, "summary.json"), "w") as f:
         json.dump(res, f, indent=1)
     log(json.dumps(res))

@@ -98,29 +98,47 @@ def test_batch_graph_replay_matches_direct_launch():
 
 
 def test_autotune_choice_keeps_results(tmp_path):
+    """Every launch knob (workgroups of 1, 2, 4 waves; workgroups per CU;
+    units per pop) gives the same volumes bit for bit; the autotuner's
+    choice is one of them, cached with every candidate's time."""
     torch, sonar = _gpu()
     mesh = S.scene_seabed_boxes()
     sc = sonar.Scene(mesh)
-    items = _mixed_items(S.sensor_seabed_boxes(), 16, 3)
+    base = S.sensor_seabed_boxes().replace(max_bounces=2, k_d=0.7, k_s=0.3, c_grad=0.05)
+    items = _mixed_items(base, 16, 3)
     batch = sonar.Batch(sc, items)
     batch.run()
     torch.cuda.synchronize()
     want = [v.clone() for v in batch.volumes]
+    for wpb in (1, 2, 4):
+        for bpc, tpi in ((1, 1), (3, 2), (6, 4)):
+            for v in batch.volumes:
+                v.fill_(complex(float("nan"), 0.0))
+            batch.run(batch.options(blocks_per_cu=bpc, tiles_per_item=tpi, waves_per_block=wpb))
+            torch.cuda.synchronize()
+            for v, w in zip(batch.volumes, want):
+                assert torch.equal(v.view(torch.float32), w.view(torch.float32)), (wpb, bpc, tpi)
+            start, finish = batch.stamps()
+            assert (finish > start).all()
     os.environ["SONAR_AUTOTUNE_CACHE"] = str(tmp_path / "tune.txt")
     try:
         best, ms = batch.autotune()
         assert best.blocks_per_cu >= 1 and best.tiles_per_item in (1, 2, 4) and ms > 0
+        assert best.waves_per_block in (1, 2, 4)
         best2, ms2 = batch.autotune()          # cached
-        assert (best2.blocks_per_cu, best2.tiles_per_item, ms2) == (best.blocks_per_cu, best.tiles_per_item,
-                                                                   pytest.approx(ms, rel=1e-5))
-        assert (tmp_path / "tune.txt").read_text().strip()
+        assert (best2.blocks_per_cu, best2.tiles_per_item, best2.waves_per_block, ms2) == \
+            (best.blocks_per_cu, best.tiles_per_item, best.waves_per_block, pytest.approx(ms, rel=1e-5))
+        lines = (tmp_path / "tune.txt").read_text().strip().splitlines()
+        cands = [l for l in lines if l.startswith("cand:")]
+        assert {int(l.split()[3]) for l in cands} == {1, 2, 4}
+        assert len(cands) >= 9
     finally:
         del os.environ["SONAR_AUTOTUNE_CACHE"]
     batch.run(best)
     torch.cuda.synchronize()
     for v, w in zip(batch.volumes, want):
         assert torch.equal(v.view(torch.float32), w.view(torch.float32))
-    _log("autotuned", best.blocks_per_cu, best.tiles_per_item, ms)
+    _log("autotuned", best.blocks_per_cu, best.tiles_per_item, best.waves_per_block, ms)
 
 
 def test_batch_rejects_mixed_physics():

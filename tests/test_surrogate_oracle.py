@@ -30,13 +30,15 @@ def test_im2col_brute_force():
                         q += 8
 
 
-def test_gradients_match_central_differences():
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gradients_match_central_differences(weighted):
     rng = np.random.Generator(np.random.PCG64(2))
     theta = surrogate_init_params(3).astype(np.float64)
     theta += rng.normal(0, 0.01, theta.size)                  # nonzero biases
     g = rng.uniform(-1, 1, size=(1, 4, 5, 8))
     t = rng.normal(size=(20, 64))
-    loss, grad, _ = SO.loss_and_grad(theta, g, t)
+    w = rng.uniform(0.1, 3.0, 64) if weighted else None
+    loss, grad, _ = SO.loss_and_grad(theta, g, t, w=w)
     idx = rng.choice(theta.size, 60, replace=False)
     # include entries of every layer's weights and biases
     offs = np.cumsum([0] + [k * n + n for k, n in SO.LAYERS])
@@ -48,8 +50,8 @@ def test_gradients_match_central_differences():
         tp[i] += h
         tm = theta.copy()
         tm[i] -= h
-        lp = SO.loss_and_grad(tp, g, t)[0]
-        lm = SO.loss_and_grad(tm, g, t)[0]
+        lp = SO.loss_and_grad(tp, g, t, w=w)[0]
+        lm = SO.loss_and_grad(tm, g, t, w=w)[0]
         fd = (lp - lm) / (2 * h)
         assert abs(fd - grad[i]) <= 1e-6 * max(abs(fd), 1e-3), (i, fd, grad[i])
 
@@ -70,24 +72,61 @@ def test_dct_matches_library_and_is_orthonormal():
 
 
 def test_truncated_profile_is_projection():
+    """The predicted profile from the 64 level coefficients adds back the
+    intensity of the level's least-squares projection onto the 64 basis
+    vectors."""
     rng = np.random.Generator(np.random.PCG64(5))
     i1 = rng.exponential(1e-8, (4, 1024))
     im = rng.exponential(1e-9, (4, 1024)) * (rng.random((4, 1024)) < 0.3)
-    c = SO.residual_coefficients(i1, im)
+    c = SO.level_coefficients(im)
     prof = SO.profile_from_coefficients(i1, c)
-    res = SO.residual_db(i1, im)
-    # the truncated reconstruction is the least-squares projection onto 64 basis vectors
     C = SO.dct_basis(1024)
-    proj = res @ C.T @ C
-    np.testing.assert_allclose(prof - 10 * np.log10(i1 + SO.I_FLOOR), proj, atol=1e-10)
+    proj = SO.level_db(im) @ C.T @ C
+    np.testing.assert_allclose(prof, 10 * np.log10(i1 + SO.I_FLOOR * 10 ** (proj / 10)), atol=1e-10)
 
 
-def test_zero_residual_gives_single_bounce_profile():
+def test_level_closed_forms():
+    """Level of a constant later-bounce intensity c: 10 log10(1 + c / floor)
+    in every bin, so only coefficient 0 is nonzero (sqrt(n) times it); with
+    the full-resolution (untruncated) level the profile is exactly the
+    multi-bounce truth 10 log10(I1 + Im + floor)."""
+    n = 256
+    c = 3.0e-9
+    im = np.full((1, n), c)
+    lv = SO.level_db(im)
+    np.testing.assert_allclose(lv, 10 * np.log10(1 + c / SO.I_FLOOR), rtol=1e-14)
+    coef = SO.level_coefficients(im)
+    np.testing.assert_allclose(coef[0, 0], np.sqrt(n) * 10 * np.log10(1 + c / SO.I_FLOOR), rtol=1e-12)
+    assert np.abs(coef[0, 1:]).max() < 1e-9
+    rng = np.random.Generator(np.random.PCG64(8))
+    i1 = rng.exponential(1e-8, (3, 64)) * (rng.random((3, 64)) < 0.5)
+    im = rng.exponential(1e-9, (3, 64)) * (rng.random((3, 64)) < 0.5)
+    C = SO.dct_basis(64, 64)
+    full = SO.level_db(im) @ C.T
+    prof = 10 * np.log10(i1 + SO.I_FLOOR * 10 ** ((full @ C) / 10))
+    np.testing.assert_allclose(prof, 10 * np.log10(i1 + im + SO.I_FLOOR), atol=1e-9)
+
+
+def test_zero_later_bounce_gives_single_bounce_profile():
     i1 = np.full((2, 1024), 1e-8)
-    c = SO.residual_coefficients(i1, np.zeros_like(i1))
+    c = SO.level_coefficients(np.zeros_like(i1))
     assert np.abs(c).max() < 1e-12
     err, n = SO.beam_errors(i1, np.zeros_like(i1), SO.profile_from_coefficients(i1, c))
     assert np.all(err < 1e-10) and np.all(n == 1024)
+
+
+def test_weighted_loss_is_profile_squared_error():
+    """With w_j = sigma_j^2 / mean(sigma^2) the loss on standardised
+    coefficients is the mean squared error of the de-standardised
+    coefficients over mean(sigma^2), i.e. (Parseval) the profile's."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    sg = rng.uniform(0.2, 3.0, 64)
+    mu = rng.normal(0, 1, 64)
+    y, t = rng.normal(size=(10, 64)), rng.normal(size=(10, 64))
+    w = sg ** 2 / np.mean(sg ** 2)
+    loss, _ = SO.mse(y, t, w)
+    raw = ((y * sg + mu) - (t * sg + mu)) @ SO.dct_basis(256, 64)
+    np.testing.assert_allclose(loss, (raw ** 2).sum() / (10 * 64) / np.mean(sg ** 2), rtol=1e-12)
 
 
 def test_smoothing_and_alignment_definitions():
@@ -97,24 +136,25 @@ def test_smoothing_and_alignment_definitions():
     # interior: plain window mean; total mass preserved away from the edges
     np.testing.assert_allclose(s[:, 50], a[:, 46:54].mean(axis=1))
     np.testing.assert_allclose(s[:, 0], a[:, 0:4].sum(axis=1) / 8)
-    # alignment: a residual confined after r1 maps back exactly through the full basis
+    # alignment: a level confined after r1 maps back exactly through the full basis
     i1 = np.zeros((2, 256))
     im = np.zeros((2, 256))
     i1[:, 100:120] = 1e-8
     im[:, 130:150] = 1e-8
     r1 = np.array([100, 90])
-    c = SO.aligned_residual_coefficients(i1, im, r1)
+    c = SO.aligned_level_coefficients(im, r1)
     assert c.shape == (2, 64)
     prof = SO.aligned_profile(i1, c, r1)
-    # the truncated reconstruction is the projection of the aligned residual
-    res = SO.residual_db(SO.smooth_range(i1), SO.smooth_range(im))
+    # the truncated reconstruction is the projection of the aligned level
+    lv = SO.level_db(SO.smooth_range(im))
     C = SO.dct_basis(256)
     for k in range(2):
         al = np.zeros(256)
-        al[:256 - r1[k]] = res[k, r1[k]:]
+        al[:256 - r1[k]] = lv[k, r1[k]:]
         proj = al @ C.T @ C
-        want = 10 * np.log10(SO.smooth_range(i1)[k] + SO.I_FLOOR)
-        want[r1[k]:] += proj[:256 - r1[k]]
+        back = np.zeros(256)
+        back[r1[k]:] = proj[:256 - r1[k]]
+        want = 10 * np.log10(SO.smooth_range(i1)[k] + SO.I_FLOOR * 10 ** (back / 10))
         np.testing.assert_allclose(prof[k], want, atol=1e-9)
 
 
