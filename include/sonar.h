@@ -685,20 +685,22 @@ sonar_status sonar_surrogate_target(const sonar_surrogate *s, const float *im, c
 sonar_status sonar_surrogate_moments(sonar_surrogate *s, const float *coef, int64_t rows, double *sum, double *sum_sq,
                                      sonar_stream stream);
 
-/* Predicted (range-smoothed) multi-bounce profile and its errors. For
- * standardised predictions `coef`: profile[r] = 10 log10(I1s[r] + 1e-11 *
- * 10^(lev[r] / 10)), lev the inverse DCT of the de-standardised coefficients
- * from the first-hit bin on and 0 before it (written to `profile`
- * [rows][n_bins] if not NULL). If `im` is not NULL, `err` [rows][8] receives
- * per beam mean |error| in dB (NaN when no bin counts):
- *   over bins whose smoothed truth 10 log10(I1s + Ims + 1e-11) is more than
- *   3 dB above the floor: [0] the prediction, [1] the smoothed single-bounce
- *   profile, [2] the smoothed single bounce plus the mean level (inverse DCT
- *   of the mean coefficients), [3] the number of such bins;
- *   over bins whose raw truth 10 log10(I1 + Im + 1e-11) is more than 3 dB
- *   above the floor: [4] the prediction, [5] the smoothed truth (the best any
- *   range-smoothed profile can do), [6] the raw single-bounce profile
- *   10 log10(I1 + 1e-11), [7] the number of such bins. */
+/* Predicted multi-bounce profile and its errors. For standardised
+ * predictions `coef`: profile[r] = 10 log10(I1[r] + 1e-11 * 10^(lev[r] / 10))
+ * at full range resolution, with I1 the single-bounce channel as given and
+ * lev the inverse DCT of the de-standardised coefficients from the first-hit
+ * bin on and 0 before it (written to `profile` [rows][n_bins] if not NULL).
+ * If `im` is not NULL, `err` [rows][8] receives per beam mean |error| in dB
+ * (NaN when no bin counts):
+ *   the range-smoothed prediction 10 log10(I1s + 1e-11 * 10^(lev / 10)) over
+ *   bins whose smoothed truth 10 log10(I1s + Ims + 1e-11) is more than 3 dB
+ *   above the floor: [0] the prediction, [1] the smoothed single bounce,
+ *   [2] the smoothed single bounce plus the mean level (inverse DCT of the
+ *   mean coefficients), [3] the number of such bins;
+ *   the full-resolution profile over bins whose raw truth
+ *   10 log10(I1 + Im + 1e-11) is more than 3 dB above the floor: [4] the
+ *   prediction, [5] the single bounce plus the mean level, [6] the single
+ *   bounce 10 log10(I1 + 1e-11), [7] the number of such bins. */
 sonar_status sonar_surrogate_profile(const sonar_surrogate *s, const float *coef, const float *i1, const float *im,
                                      const float *gbuffer, int64_t rows, float *profile, float *err,
                                      sonar_stream stream);

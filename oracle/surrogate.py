@@ -186,17 +186,30 @@ def aligned_level_coefficients(im, r1, floor=I_FLOOR, w=SMOOTH):
     return al @ dct_basis(n).T
 
 
-def aligned_profile(i1, coef, r1, floor=I_FLOOR, w=SMOOTH):
-    """Predicted range-smoothed multi-bounce dB profile: the smoothed
-    single-bounce intensity plus the later-bounce intensity of the inverse DCT
-    shifted back to start at the first-hit bin (level 0 before it)."""
-    i1s = smooth_range(i1, w)
-    q = np.asarray(coef, np.float64) @ dct_basis(i1s.shape[-1])
-    n = i1s.shape[-1]
-    lv = np.zeros_like(i1s)
+def aligned_level(coef, r1, n):
+    """[rows, n] level profile: the inverse DCT of the coefficients shifted
+    back to start at each beam's first-hit bin (level 0 before it)."""
+    q = np.asarray(coef, np.float64) @ dct_basis(n)
+    lv = np.zeros((q.shape[0], n))
     for k in range(lv.shape[0]):
         lv[k, r1[k]:] = q[k, :n - r1[k]]
+    return lv
+
+
+def aligned_profile(i1, coef, r1, floor=I_FLOOR, w=SMOOTH):
+    """Predicted range-smoothed multi-bounce dB profile: the smoothed
+    single-bounce intensity plus the later-bounce intensity of the level."""
+    i1s = smooth_range(i1, w)
+    lv = aligned_level(coef, r1, i1s.shape[-1])
     return 10.0 * np.log10(i1s + floor * 10.0 ** (lv / 10.0))
+
+
+def full_profile(i1, coef, r1, floor=I_FLOOR):
+    """Predicted multi-bounce dB profile at full range resolution: the raw
+    single-bounce intensity plus the later-bounce intensity of the level."""
+    i1 = np.asarray(i1, np.float64)
+    lv = aligned_level(coef, r1, i1.shape[-1])
+    return 10.0 * np.log10(i1 + floor * 10.0 ** (lv / 10.0))
 
 
 def aligned_beam_errors(i1, im, pred_profile, floor=I_FLOOR, occupied_db=3.0, w=SMOOTH):

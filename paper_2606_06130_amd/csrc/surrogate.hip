@@ -397,19 +397,20 @@ __global__ void k_mean_level(const float *__restrict__ basis, const float *__res
     mres[c] = a;
 }
 
-// Predicted range-smoothed profile and per-beam dB errors. For row k with
-// first-hit bin r1: profile[b] = 10 log10(I1s[b] + floor 10^(lev[b] / 10)),
-// lev[b] = Q[k][b - r1] from r1 on and 0 before it, with
+// Predicted profile and per-beam dB errors. For row k with first-hit bin
+// r1: profile[b] = 10 log10(I1[b] + floor 10^(lev[b] / 10)) at full range
+// resolution, lev[b] = Q[k][b - r1] from r1 on and 0 before it, with
 // Q[k][c] = sum_j C[j][c] c_kj the inverse DCT of the de-standardised
 // prediction (a zero level leaves the single-bounce profile). Errors, as
 // mean |error| in dB per beam:
-//  over bins whose smoothed truth 10 log10(I1s + Ims + floor) is more than
-//  3 dB above the floor: [0] the prediction, [1] the smoothed single bounce,
+//  the range-smoothed prediction 10 log10(I1s + floor 10^(lev / 10)) over
+//  bins whose smoothed truth 10 log10(I1s + Ims + floor) is more than 3 dB
+//  above the floor: [0] the prediction, [1] the smoothed single bounce,
 //  [2] the smoothed single bounce plus the mean level, [3] the bin count;
-//  over bins whose raw truth 10 log10(I1 + Im + floor) is more than 3 dB
-//  above the floor: [4] the prediction, [5] the smoothed truth (what any
-//  range-smoothed profile can reach at best), [6] the raw single bounce
-//  10 log10(I1 + floor), [7] the bin count.
+//  the full-resolution profile over bins whose raw truth
+//  10 log10(I1 + Im + floor) is more than 3 dB above the floor: [4] the
+//  prediction, [5] the single bounce plus the mean level, [6] the single
+//  bounce 10 log10(I1 + floor), [7] the bin count.
 // Block: 16 rows, 4 waves, in two phases.
 //  1. Q on the matrix cores, wave q taking a quarter of the columns c: 16 x
 //     16 x 4 FP32 MFMA steps, A the 16 rows' coefficients (lane l: row l % 16,
@@ -431,9 +432,9 @@ constexpr int N_ERR = 8;
 constexpr float DB_TO_LOG2 = 0.332192809488736235f;     // log2(10) / 10
 
 template <int P>
-__global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict__ pred, const float *__restrict__ i1,
-                                                        const float *__restrict__ im, const float *__restrict__ i1r,
-                                                        const float *__restrict__ imr, const float *__restrict__ gbuf,
+__global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict__ pred, const float *__restrict__ i1r,
+                                                        const float *__restrict__ imr, const float *__restrict__ i1s,
+                                                        const float *__restrict__ ims, const float *__restrict__ gbuf,
                                                         int64_t rows, int nb, float r_min, float r_max,
                                                         const float *__restrict__ mu, const float *__restrict__ sg,
                                                         const float *__restrict__ mlev, float *__restrict__ err,
@@ -449,13 +450,13 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
     const float dr = (r_max - r_min) / nb;
     const float occ_db = db10(I_FLOOR) + 3.f;
     if (t < PR_ROWS) r1s[t] = (r0 + t < rows) ? first_hit_bin(gbuf, r0 + t, r_min, r_max, dr, nb) : nb;
-    // the single-bounce channel of the 16 rows, in flight during phase 1
+    // the raw single-bounce channel of the 16 rows, in flight during phase 1
     float iv[PR_ROWS][P];
 #pragma unroll
     for (int rl = 0; rl < PR_ROWS; ++rl) {
         const int64_t rowc = min(r0 + rl, rows - 1);
 #pragma unroll
-        for (int q = 0; q < P; ++q) iv[rl][q] = i1[rowc * nb + min(t + 256 * q, nb - 1)];
+        for (int q = 0; q < P; ++q) iv[rl][q] = i1r[rowc * nb + min(t + 256 * q, nb - 1)];
     }
 
     // phase 1: Q of this wave's column quarter
@@ -523,12 +524,12 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
 #pragma unroll
     for (int rp = 0; rp < PR_ROWS; rp += 2) {
         float mv[2][P];
-        if (im) {
+        if (imr) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int64_t rowc = min(r0 + rp + h, rows - 1);
 #pragma unroll
-                for (int q = 0; q < P; ++q) mv[h][q] = im[rowc * nb + min(t + 256 * q, nb - 1)];
+                for (int q = 0; q < P; ++q) mv[h][q] = imr[rowc * nb + min(t + 256 * q, nb - 1)];
             }
         }
 #pragma unroll
@@ -544,26 +545,26 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
             for (int q = 0; q < P; ++q) {
                 const int b = t + 256 * q;
                 if (!rok || b >= nb) continue;
-                const float a1 = iv[rl][q];
+                const float ar = iv[rl][q];
                 const float lev = b >= r1 ? Q[rl * pitch + (b - r1)] : 0.f;
-                const float ph = db10(a1 + I_FLOOR * exp2f(lev * DB_TO_LOG2));
+                const float fl = I_FLOOR * exp2f(lev * DB_TO_LOG2);     // floor + predicted later-bounce intensity
+                const float ph = db10(ar + fl);
                 if (profile) __builtin_nontemporal_store(ph, profile + row * nb + b);      // streamed out
-                if (im) {
-                    const float ts = db10(a1 + mv[h][q] + I_FLOOR);
+                if (imr) {
+                    const float fm = I_FLOOR * exp2f(((b >= r1 && mlev) ? mlev[b - r1] : 0.f) * DB_TO_LOG2);
+                    const float as = i1s[row * nb + b];
+                    const float ts = db10(as + ims[row * nb + b] + I_FLOOR);
                     if (ts > occ_db) {
-                        const float ml = (b >= r1 && mlev) ? mlev[b - r1] : 0.f;
-                        const float p1 = db10(a1 + I_FLOOR);
-                        e[0] += fabsf(ph - ts);
-                        e[1] += fabsf(p1 - ts);
-                        e[2] += fabsf(db10(a1 + I_FLOOR * exp2f(ml * DB_TO_LOG2)) - ts);
+                        e[0] += fabsf(db10(as + fl) - ts);
+                        e[1] += fabsf(db10(as + I_FLOOR) - ts);
+                        e[2] += fabsf(db10(as + fm) - ts);
                         e[3] += 1.f;
                     }
-                    const float r1v = i1r[row * nb + b];
-                    const float tr = db10(r1v + imr[row * nb + b] + I_FLOOR);
+                    const float tr = db10(ar + mv[h][q] + I_FLOOR);
                     if (tr > occ_db) {
                         e[4] += fabsf(ph - tr);
-                        e[5] += fabsf(ts - tr);
-                        e[6] += fabsf(db10(r1v + I_FLOOR) - tr);
+                        e[5] += fabsf(db10(ar + fm) - tr);
+                        e[6] += fabsf(db10(ar + I_FLOOR) - tr);
                         e[7] += 1.f;
                     }
                 }
@@ -1009,17 +1010,18 @@ hipError_t surrogate_coef_moments(Surrogate *s, const float *coef, int64_t rows,
 hipError_t surrogate_profile_errors(const Surrogate *s, const float *pred, const float *i1, const float *im,
                                     const float *gbuf, int64_t rows, float *err, float *profile, hipStream_t st)
 {
-    // smooth i1 and (if given) im into the surrogate's buffers
-    smooth_channels(s, i1, im, rows, st);
-    if (im && err)
+    // the errors against the smoothed truth need both channels smoothed; the
+    // profile itself uses the raw single-bounce channel
+    if (im) smooth_channels(s, i1, im, rows, st);
+    if (im)
         hipLaunchKernelGGL(k_mean_level, dim3((unsigned)((s->n_bins + 255) / 256)), dim3(256), 0, st, s->basis,
                            s->mu, s->n_bins, s->mlev);
     const size_t lds = (size_t)PR_ROWS * (s->n_bins + 1) * sizeof(float);
     const int per = (s->n_bins + 255) / 256;
 #define SONAR_PROFILE(PP)                                                                                        \
     hipLaunchKernelGGL(k_profile_errors<PP>, dim3((unsigned)((rows + PR_ROWS - 1) / PR_ROWS)), dim3(256), lds, st, \
-                       pred, s->s1, im ? s->sm : nullptr, i1, im, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->mu, \
-                       s->sg, s->mlev, err, profile)
+                       pred, i1, im, s->s1, s->sm, gbuf, rows, s->n_bins, s->r_min, s->r_max, s->mu, s->sg, s->mlev, \
+                       err, profile)
     if (per <= 1) SONAR_PROFILE(1);
     else if (per <= 2) SONAR_PROFILE(2);
     else if (per <= 4) SONAR_PROFILE(4);

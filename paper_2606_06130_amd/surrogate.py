@@ -116,19 +116,19 @@ def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
 
 
 ERROR_COLUMNS = ("surrogate", "single_bounce", "mean_level", "occupied_bins",
-                 "surrogate_raw", "smoothed_truth_raw", "single_bounce_raw", "occupied_bins_raw")
+                 "surrogate_raw", "mean_level_raw", "single_bounce_raw", "occupied_bins_raw")
 
 
 def evaluate(sur, src, poses):
     """Per-beam dB errors over held-out pings, mean and p95 over beams.
 
-    Against the range-smoothed truth (beams with occupied smoothed bins): the
-    surrogate, the smoothed single bounce, the smoothed single bounce plus the
-    mean level, the truncated truth (the best any 64-coefficient prediction
-    can do: the truncation floor) and the surrogate against the truncated
-    truth (the network's own error). Against the raw truth (beams with
-    occupied raw bins): the surrogate, the smoothed truth (the floor of any
-    range-smoothed profile) and the raw single-bounce profile."""
+    Against the range-smoothed truth (beams with occupied smoothed bins), of
+    range-smoothed profiles: the surrogate, the single bounce, the single
+    bounce plus the mean level and the truncated truth (the best any
+    64-coefficient prediction can do: the truncation floor). Against the raw
+    truth (beams with occupied raw bins), of full-resolution profiles (the
+    raw single-bounce channel plus a level): the same four, and the surrogate
+    against the truncated truth (the network's own error)."""
     torch = src.torch
     errs, errt, errn = [], [], []
     coef = torch.empty((src.rows, 64), dtype=torch.float32, device="cuda")
@@ -143,7 +143,7 @@ def evaluate(sur, src, poses):
         pred, e = sur.profile(coef, i1, gbv, im)
         sur.target(im, gbv, standardize=True, out=exact)
         trunc, et = sur.profile(exact, i1, gbv, im)
-        truth, _ = sur.profile(zero, i1 + im, gbv)
+        truth, _ = sur.profile(zero, i1 + im, gbv)     # 10 log10(I1 + Im + floor): the raw truth
         occ = truth > occupied_db
         cnt = occ.sum(dim=1)
         en = torch.where(occ, (pred - trunc).abs(), torch.zeros_like(pred)).sum(dim=1) / cnt.clamp(min=1)
@@ -164,9 +164,8 @@ def evaluate(sur, src, poses):
     out["single_bounce"] = stat(e[ok, 1])
     out["mean_level"] = stat(e[ok, 2])
     out["truncated_truth"] = stat(et[ok, 0])
-    out["surrogate_vs_truncated_truth"] = stat(en[ok])
-    out["raw"] = {"surrogate": stat(e[okr, 4]), "smoothed_truth": stat(e[okr, 5]),
-                  "single_bounce": stat(e[okr, 6])}
+    out["raw"] = {"surrogate": stat(e[okr, 4]), "single_bounce": stat(e[okr, 6]), "mean_level": stat(e[okr, 5]),
+                  "truncated_truth": stat(et[okr, 4]), "surrogate_vs_truncated_truth": stat(en[okr])}
     out["meets_1db"] = bool(out["surrogate"]["mean_db"] <= 1.0)
     return out
 

@@ -137,15 +137,17 @@ def test_level_coefficients_and_profile_match_oracle():
     prof, err = sur.profile(torch.from_numpy(pred).cuda(), ti1, tgb, tim)
     prof, err = prof.cpu().numpy(), err.cpu().numpy()
     coef = pred.astype(np.float64) * std + mean
-    want_prof = SO.aligned_profile(i1, coef, r1)
+    mean_rows = np.broadcast_to(mean, (rows, 64))
+    want_prof = SO.full_profile(i1, coef, r1)
     assert np.abs(prof - want_prof).max() <= 2e-3
-    i1s, ims = SO.smooth_range(i1), SO.smooth_range(im)
-    e_sur, n = SO.aligned_beam_errors(i1, im, want_prof)
+    i1s = SO.smooth_range(i1)
+    # smoothed truth, range-smoothed profiles
+    e_sur, n = SO.aligned_beam_errors(i1, im, SO.aligned_profile(i1, coef, r1))
     e_one, _ = SO.aligned_beam_errors(i1, im, 10 * np.log10(i1s + SO.I_FLOOR))
-    e_mean, _ = SO.aligned_beam_errors(i1, im, SO.aligned_profile(i1, np.broadcast_to(mean, (rows, 64)), r1))
-    # raw truth: the prediction, the smoothed truth and the raw single bounce
+    e_mean, _ = SO.aligned_beam_errors(i1, im, SO.aligned_profile(i1, mean_rows, r1))
+    # raw truth, full-resolution profiles
     r_sur, nr = SO.beam_errors(i1, im, want_prof)
-    r_fl, _ = SO.beam_errors(i1, im, 10 * np.log10(i1s + ims + SO.I_FLOOR))
+    r_mean, _ = SO.beam_errors(i1, im, SO.full_profile(i1, mean_rows, r1))
     r_one, _ = SO.beam_errors(i1, im, 10 * np.log10(i1.astype(np.float64) + SO.I_FLOOR))
     np.testing.assert_array_equal(err[:, 3], n)
     np.testing.assert_array_equal(err[:, 7], nr)
@@ -155,12 +157,12 @@ def test_level_coefficients_and_profile_match_oracle():
     np.testing.assert_allclose(err[ok, 1], e_one[ok], atol=2e-3)
     np.testing.assert_allclose(err[ok, 2], e_mean[ok], atol=2e-3)
     np.testing.assert_allclose(err[okr, 4], r_sur[okr], atol=2e-3)
-    np.testing.assert_allclose(err[okr, 5], r_fl[okr], atol=2e-3)
+    np.testing.assert_allclose(err[okr, 5], r_mean[okr], atol=2e-3)
     np.testing.assert_allclose(err[okr, 6], r_one[okr], atol=2e-3)
-    # a zero level (standardised -mean / std) gives the smoothed single-bounce profile
+    # a zero level (standardised -mean / std) gives the single-bounce profile
     zero = torch.from_numpy(-mean / std).cuda().expand(rows, 64).contiguous()
     pz, _ = sur.profile(zero, ti1, tgb)
-    assert np.abs(pz.cpu().numpy() - 10 * np.log10(i1s + SO.I_FLOOR)).max() <= 2e-3
+    assert np.abs(pz.cpu().numpy() - 10 * np.log10(i1.astype(np.float64) + SO.I_FLOOR)).max() <= 2e-3
 
 
 def test_training_reduces_loss_and_resumes_bit_exactly():
@@ -218,7 +220,7 @@ def test_surrogate_gains_over_single_bounce():
 def test_committed_weights_beat_single_bounce():
     """The committed checkpoint (trained on the full 256 x 128-beam layout)
     loads without pickle and, on 16 held-out poses, beats the single-bounce
-    and mean-level profiles against the smoothed truth."""
+    and mean-level profiles against the smoothed and the raw truth."""
     torch, sonar = _gpu()
     from paper_2606_06130_amd import surrogate as SU
     mesh = S.scene_harbor_multipath()
@@ -233,4 +235,6 @@ def test_committed_weights_beat_single_bounce():
     assert res["beams"] > 100000
     assert res["surrogate"]["mean_db"] < res["single_bounce"]["mean_db"]
     assert res["surrogate"]["mean_db"] < res["mean_level"]["mean_db"]
+    assert res["raw"]["surrogate"]["mean_db"] < res["raw"]["single_bounce"]["mean_db"]
+    assert res["raw"]["surrogate"]["mean_db"] < res["raw"]["mean_level"]["mean_db"]
     assert res["truncated_truth"]["mean_db"] < res["surrogate"]["mean_db"]

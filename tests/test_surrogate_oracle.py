@@ -115,6 +115,26 @@ def test_zero_later_bounce_gives_single_bounce_profile():
     assert np.all(err < 1e-10) and np.all(n == 1024)
 
 
+def test_full_profile_definitions():
+    """Full-resolution profile: zero coefficients give the raw single-bounce
+    profile; coefficients of a constant level c from bin 0 add the intensity
+    floor (10^(c/10) - 1) to every bin from the first-hit bin on."""
+    rng = np.random.Generator(np.random.PCG64(10))
+    n = 128
+    i1 = rng.exponential(1e-8, (3, n)) * (rng.random((3, n)) < 0.4)
+    r1 = np.array([0, 17, 100])
+    z = SO.full_profile(i1, np.zeros((3, 64)), r1)
+    np.testing.assert_allclose(z, 10 * np.log10(i1 + SO.I_FLOOR), atol=1e-12)
+    c = 6.0
+    coef = np.zeros((3, 64))
+    coef[:, 0] = c * np.sqrt(n)          # a constant level c over all n bins
+    p = SO.full_profile(i1, coef, r1)
+    for k in range(3):
+        want = i1[k] + SO.I_FLOOR
+        want[r1[k]:] += SO.I_FLOOR * (10 ** (c / 10) - 1)
+        np.testing.assert_allclose(p[k], 10 * np.log10(want), atol=1e-9)
+
+
 def test_weighted_loss_is_profile_squared_error():
     """With w_j = sigma_j^2 / mean(sigma^2) the loss on standardised
     coefficients is the mean squared error of the de-standardised
