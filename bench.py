@@ -28,54 +28,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pings/s & Mrays/s on 1 GPU; surrogate vs full multipath ping rate at ≤1 dB error"
 HBM_PEAK_GBS = 8000.0
+SRC_DIR = os.path.join(ROOT, "paper_2606_06130_amd", "csrc")
+# committed rocprofv3 counter summaries (HBM bytes per launch of the timed kernels)
 PMC_FILE = os.path.join(ROOT, "profiles", "ping_harbor_pmc.json")
-PING_SRC = os.path.join(ROOT, "paper_2606_06130_amd", "csrc", "ping.hip")
-
-
-def _src_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
 MP_PMC_FILE = os.path.join(ROOT, "profiles", "multipath_ping_staged_kernels_counters.json")
 BATCH_PMC_FILE = os.path.join(ROOT, "profiles", "batch_lawnmower_persistent_kernel_counters.json")
-SRC_DIR = os.path.join(ROOT, "paper_2606_06130_amd", "csrc")
 
 
-def _sources_hash():
-    """Hash of the kernel sources (a counter summary stays valid while they do)."""
+def sources_hash(names):
+    """Hash of the named kernel sources (a counter summary stays valid while
+    the sources its kernels are compiled from do)."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(SRC_DIR)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(SRC_DIR, name), "rb") as f:
-                h.update(name.encode() + f.read())
+    for name in sorted(names):
+        with open(os.path.join(SRC_DIR, name), "rb") as f:
+            h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 
-def _traffic_of(path, alg_bytes):
-    """HBM bytes per launch from a committed counter summary, or None when the
-    kernel sources changed since it was taken."""
+def _traffic_of(path):
+    """HBM bytes per launch from a committed counter summary, or None when it
+    is missing or the sources it lists changed since it was taken."""
     try:
         with open(path) as f:
             d = json.load(f)
-    except (OSError, ValueError):
+        if d.get("sources_sha256_16") != sources_hash(d["sources"]):
+            return None
+        return d["derived"]["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError, TypeError):
         return None
-    if d.get("sources_sha256_16") != _sources_hash():
-        return None
-    return d.get("derived", {}).get("hbm_bytes_per_launch")
-
-
-def _traffic(n_launch_bytes_alg):
-    """HBM bytes per ping launch from the committed rocprofv3 counter summary,
-    or None if the kernel source changed since the counters were taken."""
-    try:
-        with open(PMC_FILE) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if d.get("ping_src_sha256_16") != _src_hash(PING_SRC):
-        return None
-    return d.get("hbm_bytes_per_launch")
 
 
 NODE_BYTES, TRI_BYTES = 128, 48     # one 4-wide hierarchy node, one triangle record
@@ -249,6 +229,26 @@ def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
 
     mp_ms = timed(lambda: sonar.ping(scene, cfg, pose, out=out, staged=True))
     fused_ms = timed(lambda: sonar.ping(scene, cfg, pose, out=out))
+    # independent multipath pings issued round-robin on several streams (each
+    # with its own outputs and workspace), as in the harbor job: one ping's
+    # kernel tails overlap the next one's kernels
+    ns = 4
+    mp_streams = [torch.cuda.Stream() for _ in range(ns)]
+    mp_outs = [sonar.alloc_outputs(cfg) for _ in range(ns)]
+
+    def mp_job(n):
+        for i in range(n):
+            sonar.ping(scene, cfg, pose, out=mp_outs[i % ns], staged=True, stream=mp_streams[i % ns])
+
+    mp_job(2 * ns)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_job = 48
+    mp_job(n_job)
+    torch.cuda.synchronize()
+    job_ms = (time.perf_counter() - t0) * 1e3 / n_job
+    assert scene.status() == 0
+    del mp_outs, mp_streams
     trav = traversal_work(torch, sonar, np, scene, cfg, pose)
     trav["visit_gbs"] = trav["visit_bytes_per_ping"] / (mp_ms * 1e-3) / 1e9
     trav["note"] = "all traversals of a ray (up to 3 nearest-hit and 2 any-hit connection queries)"
@@ -308,11 +308,15 @@ def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
                                                          "accumulation kernel)",
                               "achieved": mp_alg / (mp_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": mp_alg / (mp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "traffic": _traffic_of(MP_PMC_FILE, mp_alg),
+                              "traffic": _traffic_of(MP_PMC_FILE),
                               "alg_bytes_per_launch": mp_alg,
                               "alg_bytes_note": "volume write (beams x bins x 8 B) + the scene's node and triangle "
                                                 "arrays; duration from events around the ping call (all its kernels)"},
                  "ping_ms": mp_ms, "pings_per_s": 1e3 / mp_ms, "mrays_per_s": cfg.n_rays / mp_ms / 1e3,
+                 "job": {"streams": ns, "pings": n_job, "ms_per_ping": job_ms, "pings_per_s": 1e3 / job_ms,
+                         "mrays_per_s": cfg.n_rays / job_ms / 1e3,
+                         "note": "independent pings of the same workload issued round-robin on the streams, wall "
+                                 "clock over the job"},
                  "kernels": "staged: one kernel per bounce's nearest-hit traversal and per bounce's visibility "
                             "traversal, FP64 ray state through a workspace, then the per-beam accumulation",
                  "fused_kernel_ping_ms": fused_ms,
@@ -412,7 +416,7 @@ def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
                                                   "point emission",
                         "achieved": b_alg / (rep_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": b_alg / (rep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                        "traffic": _traffic_of(BATCH_PMC_FILE, b_alg),
+                        "traffic": _traffic_of(BATCH_PMC_FILE),
                         "alg_bytes_per_launch": b_alg,
                         "alg_bytes_note": "the 256 volumes (beams x bins x 8 B each) + the scene's node and "
                                           "triangle arrays + the points (24 B each); duration = median replay"}}
@@ -488,7 +492,7 @@ def layered_ping(torch, sonar, np, scene, cfg, pose, reps=10):
             "pings_per_s": 1e3 / ms}
 
 
-def profile_case(torch, sonar, S, case, steps, warmup):
+def profile_case(torch, sonar, S, case, steps, warmup, knobs=(12, 1, 1)):
     """One workload alone, for profiler runs: the harbor multipath ping on
     one stream, or graph replays of the 256-ping lawnmower batch with CFAR."""
     scene = sonar.Scene(S.scene_harbor_multipath())
@@ -502,7 +506,7 @@ def profile_case(torch, sonar, S, case, steps, warmup):
     else:
         batch = sonar.Batch(scene, S.lawnmower_batch())
         batch.detect()
-        g = batch.graph(batch.options(blocks_per_cu=3, tiles_per_item=1))
+        g = batch.graph(batch.options(blocks_per_cu=knobs[0], tiles_per_item=knobs[1], waves_per_block=knobs[2]))
         run = g.launch
     for i in range(warmup + steps):
         run()
@@ -527,6 +531,9 @@ def main():
                     help="run only a 1 GiB device copy (for counter calibration) and exit")
     ap.add_argument("--case", choices=("multipath", "multipath_fused", "multipath_straight", "batch"), default=None,
                     help="run only this workload --steps times after --warmup (for profiler runs) and exit")
+    ap.add_argument("--batch-knobs", default="12,1,1",
+                    help="blocks per CU, tiles per pop, waves per block of the batch profiler case (the values the "
+                         "autotuner picks on one MI355X)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path (independent pings would "
@@ -555,7 +562,8 @@ def main():
     from paper_2606_06130_amd import sonar
 
     if args.case:
-        profile_case(torch, sonar, S, args.case, args.steps, args.warmup)
+        profile_case(torch, sonar, S, args.case, args.steps, args.warmup,
+                     tuple(int(x) for x in args.batch_knobs.split(",")))
         return
 
     mesh = S.scene_harbor()
@@ -643,7 +651,7 @@ def main():
     alg_bytes = vol_bytes + scene_bytes
     t_ping = float(ping_ms.mean()) * 1e-3
     achieved = alg_bytes / t_ping / 1e9
-    traffic = _traffic(alg_bytes)
+    traffic = _traffic_of(PMC_FILE)
 
     res = {
         "metric": METRIC,

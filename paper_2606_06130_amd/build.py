@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsonar.so")
 SOURCES = ["bvh_build.hip", "ping.hip", "staged.hip", "detect.hip", "pulse.hip", "reverb.hip", "surrogate.hip", "capi.hip"]
-HEADERS = ["internal.hpp", "trace.hpp", os.path.join("..", "..", "include", "sonar.h")]
+HEADERS = ["internal.hpp", "trace.hpp", "surrogate.hpp", os.path.join("..", "..", "include", "sonar.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SONAR_OFFLOAD_ARCH", "gfx950")

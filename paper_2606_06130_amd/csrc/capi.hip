@@ -8,6 +8,7 @@
 #include <new>
 
 #include "internal.hpp"
+#include "surrogate.hpp"
 
 #include <stdlib.h>
 

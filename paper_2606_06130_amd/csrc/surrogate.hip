@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "surrogate.hpp"
 
 namespace sonar {
 
