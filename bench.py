@@ -200,8 +200,8 @@ def parity_sample(torch, sonar, np, scene, mesh, cfg, pose, n_beams, seed, stage
 
 
 # multiply-adds per beam of the surrogate network (fan-in x fan-out of each
-# layer, the 3 x 3 x 8 convolution as 72 inputs)
-SURROGATE_MACS_PER_ROW = 72 * 64 + 64 * 256 + 2 * 256 * 256 + 256 * 64
+# layer: the 72 neighbourhood and 45 geometry inputs, then the dense layers)
+SURROGATE_MACS_PER_ROW = 117 * 64 + 64 * 256 + 2 * 256 * 256 + 256 * 64
 
 
 def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
@@ -346,16 +346,17 @@ def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
     coef = torch.empty((rows, 64), dtype=torch.float32, device="cuda")
     gview = o1["gbuffer"].view(1, bv, bh, 8)
     i1 = o1["incoh"].view(2, rows, cfg1.n_range)[0]
+    geo = torch.from_numpy(sonar.surrogate_geometry(cfg1, [pose])).cuda()     # the ping's pose, resident like it
 
     def sur_ping():
         sonar.ping(scene, cfg1, pose, out=o1)
-        sur.forward(gview, out=coef)
+        sur.forward(gview, geo, out=coef)
         sur.profile(coef, i1, gview, im=None, want_profile=True)
 
     sp_ms = timed(sur_ping)
-    fwd_ms = timed(lambda: sur.forward(gview, out=coef), n=20)
+    fwd_ms = timed(lambda: sur.forward(gview, geo, out=coef), n=20)
     fwd_tflops = 2.0 * SURROGATE_MACS_PER_ROW * rows / (fwd_ms * 1e-3) / 1e12
-    surrogate = {"workload": "single-bounce ping with G-buffer + fused network inference (169,344 parameters, "
+    surrogate = {"workload": "single-bounce ping with G-buffer + fused network inference (172,224 parameters, "
                              "BF16 MFMA) + predicted 1,024-bin multi-bounce profile, same scene and layout",
                  "ping_ms": sp_ms, "pings_per_s": 1e3 / sp_ms, "rate_vs_full_multipath": mp_ms / sp_ms,
                  "weights": os.path.relpath(SU.WEIGHTS, ROOT), "weights_train_steps": sur_steps,

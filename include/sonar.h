@@ -609,8 +609,9 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
 /* ---------------------------------------------------------------------- */
 /* Learned multipath surrogate (Sec. II-B: scattering functions may be learned
  * from data). A network maps each beam's single-bounce G-buffer (a 3 x 3 beam
- * neighbourhood of its 8 features) to 64 standardised orthonormal DCT-II
- * coefficients of the level profile of what later bounces add:
+ * neighbourhood of its 8 features) and the beam's geometry to 64
+ * standardised orthonormal DCT-II coefficients of the level profile of what
+ * later bounces add:
  *   lev[r] = 10 log10(1 + Ims[r] / 1e-11),
  * where Ims is the later-bounce incoherent channel of a multi-bounce ping
  * box-averaged over `smooth` range bins ([r - smooth/2, r + smooth/2)), shifted
@@ -618,8 +619,19 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
  * bin 0, zero past the end. The predicted profile adds that intensity back:
  *   profile[r] = 10 log10(I1s[r] + 1e-11 * 10^(lev[r] / 10)),
  * so a zero level leaves the smoothed single-bounce profile.
- * Layers: 3 x 3 convolution 8 -> 64 (as an im2col product), then
- * 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers; 169,344 parameters.
+ * Geometry of a beam, from its image's geometry block (16 floats: sensor
+ * position, the sensor-to-world rotation row-major, hfov, vfov, two zeros;
+ * sonar_surrogate_geometry fills one) and its G-buffer entry: the beam axis u
+ * in the world (cell-centred beams: azimuth -hfov/2 + (h + 1/2) hfov / W,
+ * elevation -vfov/2 + (v + 1/2) vfov / H), the mean first hit on it P = S +
+ * r_max g0 u (the origin for a beam without hits, g6 = 0), and 45 columns:
+ * P / 10, u, S / 10 (lengths in metres), then sin(pi/2 2^k x) for the six
+ * values x of P / 10 and u (x-major, k = 0, 1, 2), then the cosines. Later
+ * bounces go where the scene sends the continuation of the first hit: for
+ * one scene the network learns that from where the hit is.
+ * Layers: the 72 neighbourhood columns (an im2col product) and the 45
+ * geometry columns -> 64, then 64 -> 256 -> 256 -> 256 -> 64, ReLU between
+ * layers; 172,224 parameters.
  * Products use BF16 operands on the matrix cores with FP32 accumulation;
  * training is a weighted MSE on the coefficients, sum_j w_j (y_j - t_j)^2 over
  * rows * 64 (weights 1 by default), with Adam (beta 0.9 / 0.999, eps 1e-8) on
@@ -627,9 +639,11 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
  *
  * Parameter vector layout (float, sonar_surrogate_param_count() entries): for
  * each layer W [fan_in][fan_out] row-major then b [fan_out], with (fan_in,
- * fan_out) = (72, 64), (64, 256), (256, 256), (256, 256), (256, 64).
- * G-buffer: float [n_img][H][W][8] as sonar_ping writes it; rows = n_img * H * W
- * (a multiple of 64 for the network, at most max_rows everywhere).
+ * fan_out) = (117, 64), (64, 256), (256, 256), (256, 256), (256, 64); input
+ * column order: the neighbourhood (dv, dh, feature), then the geometry.
+ * G-buffer: float [n_img][H][W][8] as sonar_ping writes it; geometry: float
+ * [n_img][16] on the device; rows = n_img * H * W (a multiple of 64 for the
+ * network, at most max_rows everywhere).
  * Standardisation: coefficient j is (c_j - mean_j) / std_j (defaults 0, 1). */
 typedef struct sonar_surrogate sonar_surrogate;
 
@@ -659,20 +673,28 @@ sonar_status sonar_surrogate_set_norm(sonar_surrogate *s, const float *mean, con
  * squared error of the truncated level profile itself. */
 sonar_status sonar_surrogate_set_loss_weights(sonar_surrogate *s, const float *w);
 
-/* Inference: standardised coefficients [rows][64] (device) from a G-buffer. */
-sonar_status sonar_surrogate_forward(sonar_surrogate *s, const float *gbuffer, int32_t n_img, int32_t h, int32_t w,
-                                     float *coef, sonar_stream stream);
+/* Host: the geometry block of one ping (16 floats) from its sensor
+ * parameters and pose. SONAR_E_UNSUPPORTED for the LiDAR grid (grid_mode 1),
+ * SONAR_E_INVALID for null pointers or non-positive fields of view. */
+sonar_status sonar_surrogate_geometry(const sonar_params *params, const sonar_pose *pose, float block[16]);
 
-/* One training step on (G-buffer, standardised target [rows][64]): forward,
- * MSE, backward, Adam with learning rate lr. The loss before the update goes
- * to dev_loss (device float). */
-sonar_status sonar_surrogate_train_step(sonar_surrogate *s, const float *gbuffer, int32_t n_img, int32_t h, int32_t w,
-                                        const float *target, float lr, float *dev_loss, sonar_stream stream);
+/* Inference: standardised coefficients [rows][64] (device) from a G-buffer
+ * and the images' geometry blocks (device). */
+sonar_status sonar_surrogate_forward(sonar_surrogate *s, const float *gbuffer, const float *geometry, int32_t n_img,
+                                     int32_t h, int32_t w, float *coef, sonar_stream stream);
+
+/* One training step on (G-buffer, geometry, standardised target
+ * [rows][64]): forward, MSE, backward, Adam with learning rate lr. The loss
+ * before the update goes to dev_loss (device float). */
+sonar_status sonar_surrogate_train_step(sonar_surrogate *s, const float *gbuffer, const float *geometry, int32_t n_img,
+                                        int32_t h, int32_t w, const float *target, float lr, float *dev_loss,
+                                        sonar_stream stream);
 
 /* Gradient of the MSE w.r.t. the parameter vector (device float
  * [param_count]) without updating; for checks. */
-sonar_status sonar_surrogate_gradient(sonar_surrogate *s, const float *gbuffer, int32_t n_img, int32_t h, int32_t w,
-                                      const float *target, float *dev_grad, float *dev_loss, sonar_stream stream);
+sonar_status sonar_surrogate_gradient(sonar_surrogate *s, const float *gbuffer, const float *geometry, int32_t n_img,
+                                      int32_t h, int32_t w, const float *target, float *dev_grad, float *dev_loss,
+                                      sonar_stream stream);
 
 /* Level target: coefficients [rows][64] from the later-bounce incoherent
  * channel im [rows][n_bins] and the G-buffer of the same beams (device),

@@ -13,25 +13,35 @@ profile. The predicted multi-bounce profile adds that intensity back to the
 single-bounce one: 10 log10(I1 + floor 10^(q / 10)), so a zero prediction is
 the single-bounce profile.
 
-Network (169,344 parameters): a 3 x 3 beam-neighbourhood convolution of the
-8 G-buffer features (the first-hit statistics and the beam axis's vertical
+Network input per beam: a 3 x 3 beam-neighbourhood convolution of the 8
+G-buffer features (the first-hit statistics and the beam axis's vertical
 component; written as an im2col product with 72 inputs, zero padding at the
-edges) -> ReLU -> 64 -> 256 -> 256 -> 256 -> 64 dense layers with ReLU
+edges), followed by the beam's geometry (geometry_features): where its mean
+first hit lies in the world, the beam axis in the world and the sensor
+position, plus sines and cosines of the first two at N_FREQ octaves. Later
+bounces go where the scene sends the continuation of that first hit, so the
+network of one scene needs to know where in the scene the hit is.
+
+Network: input -> 64 -> 256 -> 256 -> 256 -> 64 dense layers with ReLU
 between them. Loss: mean squared error over the 64 standardised
 coefficients, coefficient j weighted by w_j (by default 1; in training
 sigma_j^2 / mean(sigma^2), which makes it the squared error of the profile
 itself by Parseval's theorem).
 
-Parameter vector layout (float, 169,344 entries): for each layer in order
-W [K][N] row-major then b [N], with (K, N) = (72, 64), (64, 256), (256, 256),
-(256, 256), (256, 64).
+Parameter vector layout (float, param_count() entries): for each layer in
+order W [K][N] row-major then b [N], with (K, N) = (N_IN, 64), (64, 256),
+(256, 256), (256, 256), (256, 64).
 """
 from __future__ import annotations
 
 import numpy as np
 
-LAYERS = ((72, 64), (64, 256), (256, 256), (256, 256), (256, 64))
 N_FEAT = 8
+N_FREQ = 3                       # octaves of the geometry's sines and cosines
+N_GEO = 9 + 12 * N_FREQ          # geometry features per beam
+N_IN = 9 * N_FEAT + N_GEO        # network inputs per beam
+GEO_STRIDE = 16                  # floats of one image's geometry block
+LAYERS = ((N_IN, 64), (64, 256), (256, 256), (256, 256), (256, 64))
 N_COEF = 64
 I_FLOOR = 1e-11
 
@@ -69,6 +79,54 @@ def im2col(gbuf):
         for dh in (-1, 0, 1):
             cols.append(pad[:, 1 + dv:1 + dv + H, 1 + dh:1 + dh + W])
     return np.concatenate(cols, axis=-1).reshape(n * H * W, 9 * N_FEAT)
+
+
+def geometry_block(position, rot, hfov, vfov):
+    """One image's geometry block (GEO_STRIDE floats): sensor position (3),
+    the sensor-to-world rotation row-major (9), the horizontal and vertical
+    fields of view, two zeros."""
+    g = np.zeros(GEO_STRIDE)
+    g[0:3] = np.asarray(position, np.float64)
+    g[3:12] = np.asarray(rot, np.float64).reshape(9)
+    g[12], g[13] = hfov, vfov
+    return g
+
+
+def geometry_features(gbuf, geo, r_max):
+    """gbuf [n_img, H, W, 8], geo [n_img, GEO_STRIDE] -> [n_img * H * W, N_GEO].
+
+    Beam (v, h) of a cell-centred H x W layout has its axis at azimuth
+    -hfov/2 + (h + 1/2) hfov / W and elevation -vfov/2 + (v + 1/2) vfov / H,
+    the unit vector (cos el cos az, cos el sin az, sin el) in the sensor
+    frame, u = R times it in the world. Its mean first hit is taken on that
+    axis at the G-buffer's mean range: P = S + r_max g0 u when the beam has a
+    hit (g6 > 0), else the origin. Features, in metres / 10 and unit vectors:
+    P / 10 (3), u (3), S / 10 (3), then sin(pi/2 2^k x) for x in (P / 10, u)
+    and k = 0 .. N_FREQ - 1 (x-major), then the cosines in the same order."""
+    g = np.asarray(gbuf, np.float64)
+    n, H, W, _ = g.shape
+    out = np.zeros((n, H, W, N_GEO))
+    for i in range(n):
+        S = np.asarray(geo[i][0:3], np.float64)
+        R = np.asarray(geo[i][3:12], np.float64).reshape(3, 3)
+        hfov, vfov = float(geo[i][12]), float(geo[i][13])
+        for v in range(H):
+            el = -0.5 * vfov + (v + 0.5) * vfov / H
+            for h in range(W):
+                az = -0.5 * hfov + (h + 0.5) * hfov / W
+                us = np.array([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)])
+                u = R @ us
+                P = S + r_max * g[i, v, h, 0] * u if g[i, v, h, 6] > 0 else np.zeros(3)
+                x = np.concatenate([P / 10.0, u])
+                arg = np.array([[np.pi / 2.0 * 2.0 ** k * xx for k in range(N_FREQ)] for xx in x])
+                out[i, v, h] = np.concatenate([P / 10.0, u, S / 10.0, np.sin(arg).reshape(-1),
+                                               np.cos(arg).reshape(-1)])
+    return out.reshape(n * H * W, N_GEO)
+
+
+def inputs(gbuf, geo, r_max):
+    """Network input rows [n_img * H * W, N_IN]: im2col of the G-buffer, then the geometry."""
+    return np.concatenate([im2col(gbuf), geometry_features(gbuf, geo, r_max)], axis=1)
 
 
 def forward(theta, x0, store=None):
@@ -114,8 +172,9 @@ def backward(theta, acts, dy, store=None):
     return pack(grads)
 
 
-def loss_and_grad(theta, gbuf, target, store=None, w=None):
-    acts, y = forward(theta, im2col(gbuf), store)
+def loss_and_grad(theta, x0, target, store=None, w=None):
+    """Loss, parameter gradient and output for input rows x0 (inputs())."""
+    acts, y = forward(theta, x0, store)
     loss, dy = mse(y, target, w)
     return loss, backward(theta, acts, dy, store), y
 

@@ -1373,37 +1373,53 @@ static sonar_status check_gbuf(const sonar_surrogate *h, const float *g, int32_t
     return SONAR_OK;
 }
 
-sonar_status sonar_surrogate_forward(sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W, float *coef,
-                                     sonar_stream stream)
+sonar_status sonar_surrogate_geometry(const sonar_params *p, const sonar_pose *q, float block[16])
+{
+    g_err[0] = 0;
+    if (!p || !q || !block) return fail(SONAR_E_INVALID, "params, pose and block are required");
+    if (p->grid_mode != 0) return fail(SONAR_E_UNSUPPORTED, "the surrogate's beams are cell-centred (grid_mode 0)");
+    if (!(p->hfov > 0.0) || !(p->vfov > 0.0)) return fail(SONAR_E_INVALID, "fields of view must be positive");
+    for (int i = 0; i < 3; ++i) block[i] = (float)q->position[i];
+    for (int i = 0; i < 9; ++i) block[3 + i] = (float)q->rot[i];
+    block[12] = (float)p->hfov;
+    block[13] = (float)p->vfov;
+    block[14] = block[15] = 0.f;
+    return SONAR_OK;
+}
+
+sonar_status sonar_surrogate_forward(sonar_surrogate *h, const float *g, const float *geo, int32_t n, int32_t H,
+                                     int32_t W, float *coef, sonar_stream stream)
 {
     g_err[0] = 0;
     sonar_status st = check_gbuf(h, g, n, H, W);
     if (st != SONAR_OK) return st;
-    if (!coef) return fail(SONAR_E_INVALID, "coef is NULL");
-    hipError_t e = sonar::surrogate_forward(h->s, g, n, H, W, coef, (hipStream_t)stream);
+    if (!coef || !geo) return fail(SONAR_E_INVALID, "coef and geometry are required");
+    hipError_t e = sonar::surrogate_forward(h->s, g, geo, n, H, W, coef, (hipStream_t)stream);
     return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "forward: %s", hipGetErrorString(e));
 }
 
-sonar_status sonar_surrogate_train_step(sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W,
-                                        const float *target, float lr, float *dev_loss, sonar_stream stream)
+sonar_status sonar_surrogate_train_step(sonar_surrogate *h, const float *g, const float *geo, int32_t n, int32_t H,
+                                        int32_t W, const float *target, float lr, float *dev_loss, sonar_stream stream)
 {
     g_err[0] = 0;
     sonar_status st = check_gbuf(h, g, n, H, W);
     if (st != SONAR_OK) return st;
-    if (!target || !dev_loss) return fail(SONAR_E_INVALID, "target and dev_loss are required");
+    if (!target || !dev_loss || !geo) return fail(SONAR_E_INVALID, "geometry, target and dev_loss are required");
     if (!(lr >= 0.f) || !isfinite(lr)) return fail(SONAR_E_INVALID, "lr must be finite and >= 0");
-    hipError_t e = sonar::surrogate_train_step(h->s, g, n, H, W, target, lr, dev_loss, (hipStream_t)stream);
+    hipError_t e = sonar::surrogate_train_step(h->s, g, geo, n, H, W, target, lr, dev_loss, (hipStream_t)stream);
     return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "train_step: %s", hipGetErrorString(e));
 }
 
-sonar_status sonar_surrogate_gradient(sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W,
-                                      const float *target, float *dev_grad, float *dev_loss, sonar_stream stream)
+sonar_status sonar_surrogate_gradient(sonar_surrogate *h, const float *g, const float *geo, int32_t n, int32_t H,
+                                      int32_t W, const float *target, float *dev_grad, float *dev_loss,
+                                      sonar_stream stream)
 {
     g_err[0] = 0;
     sonar_status st = check_gbuf(h, g, n, H, W);
     if (st != SONAR_OK) return st;
-    if (!target || !dev_grad || !dev_loss) return fail(SONAR_E_INVALID, "target, dev_grad and dev_loss are required");
-    hipError_t e = sonar::surrogate_gradient(h->s, g, n, H, W, target, dev_grad, dev_loss, (hipStream_t)stream);
+    if (!target || !dev_grad || !dev_loss || !geo)
+        return fail(SONAR_E_INVALID, "geometry, target, dev_grad and dev_loss are required");
+    hipError_t e = sonar::surrogate_gradient(h->s, g, geo, n, H, W, target, dev_grad, dev_loss, (hipStream_t)stream);
     return e == hipSuccess ? SONAR_OK : fail(SONAR_E_DEVICE, "gradient: %s", hipGetErrorString(e));
 }
 

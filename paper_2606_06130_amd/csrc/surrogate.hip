@@ -35,15 +35,19 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int NL = 5;                                       // layers
-constexpr int LK[NL] = {72, 64, 256, 256, 256};             // true fan-in
+constexpr int NFEAT = 8;                                    // G-buffer features per beam
+constexpr int NIM2COL = 9 * NFEAT;                          // 3 x 3 neighbourhood columns
+constexpr int NGEO_FREQ = 3;                                // octaves of the geometry's sines and cosines
+constexpr int NGEO = 9 + 12 * NGEO_FREQ;                    // geometry columns
+constexpr int GEO_STRIDE = 16;                              // floats of one image's geometry block
+constexpr int LK[NL] = {NIM2COL + NGEO, 64, 256, 256, 256}; // true fan-in
 // padded fan-in: a multiple of 64, since the weight gradient X^T dZ has it as
 // its row count and the products tile rows and columns by 64
-constexpr int LKP[NL] = {128, 64, 256, 256, 256};
+constexpr int LKP[NL] = {(LK[0] + 63) / 64 * 64, 64, 256, 256, 256};
 static_assert(LKP[0] % 64 == 0 && LKP[1] % 64 == 0 && LKP[2] % 64 == 0 && LKP[3] % 64 == 0 && LKP[4] % 64 == 0,
               "padded fan-ins tile by 64");
 constexpr int LN[NL] = {64, 256, 256, 256, 64};             // fan-out
 constexpr int NCOEF = 64;
-constexpr int NFEAT = 8;
 constexpr int GB_STRIDE = 8;                                // floats per beam in the G-buffer
 constexpr int TM = 64, TN = 64, TK = 32, LDT = TK + 8;      // GEMM tiles; LDS row stride in bf16
 constexpr int SPLIT_ROWS = 4096;                            // reduction chunk of the weight gradients
@@ -138,9 +142,65 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int 
             }
 }
 
+// Geometry columns of beam (v, h) of a cell-centred H x W image, from the
+// image's geometry block (sensor position, sensor-to-world rotation
+// row-major, horizontal and vertical fields of view) and the beam's G-buffer
+// entry: the beam axis u (world), the mean first hit P = S + r_max g0 u on it
+// (the origin without a hit), then P / 10 (3), u (3), S / 10 (3), and
+// sin(pi/2 2^k x), then cos(pi/2 2^k x), for x in (P / 10, u), x-major, k =
+// 0 .. NGEO_FREQ - 1. Lengths in metres.
+__device__ __forceinline__ void geo_columns(const float *__restrict__ geo, const float *__restrict__ gb, int v, int h,
+                                            int H, int W, float r_max, float (&out)[NGEO])
+{
+    const float hfov = geo[12], vfov = geo[13];
+    const float az = -0.5f * hfov + ((float)h + 0.5f) * hfov / (float)W;
+    const float el = -0.5f * vfov + ((float)v + 0.5f) * vfov / (float)H;
+    float sa, ca, se, ce;
+    sincosf(az, &sa, &ca);
+    sincosf(el, &se, &ce);
+    const float us0 = ce * ca, us1 = ce * sa, us2 = se;
+    const bool hit = gb[6] > 0.f;
+    const float r = r_max * gb[0];
+    float x[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float u = geo[3 + 3 * i] * us0 + geo[4 + 3 * i] * us1 + geo[5 + 3 * i] * us2;
+        x[3 + i] = u;
+        x[i] = hit ? (geo[i] + r * u) * 0.1f : 0.f;
+        out[6 + i] = geo[i] * 0.1f;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        out[q] = x[q];
+#pragma unroll
+        for (int k = 0; k < NGEO_FREQ; ++k) {
+            float sn, cs;
+            sincosf(1.57079632679489662f * (float)(1 << k) * x[q], &sn, &cs);
+            out[9 + q * NGEO_FREQ + k] = sn;
+            out[9 + 6 * NGEO_FREQ + q * NGEO_FREQ + k] = cs;
+        }
+    }
+}
+
+// Geometry columns of the layer-0 input, one thread per row.
+__global__ void k_geo_cols(const float *__restrict__ g, const float *__restrict__ geo, int n_img, int H, int W,
+                           float r_max, __bf16 *__restrict__ x)
+{
+    const int64_t rows = (int64_t)n_img * H * W;
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= rows) return;
+    const int img = (int)(row / ((int64_t)H * W));
+    const int rem = (int)(row % ((int64_t)H * W));
+    float f[NGEO];
+    geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, rem / W, rem % W, H, W, r_max, f);
+#pragma unroll
+    for (int j = 0; j < NGEO; ++j) x[row * LKP[0] + NIM2COL + j] = (__bf16)f[j];
+}
+
 // im2col of the G-buffer: row (img, v, h) gets the 8 features of the 3 x 3
-// neighbourhood ordered (dv, dh, feature), zero outside the image, then zero
-// columns up to the padded width. One thread per output element.
+// neighbourhood ordered (dv, dh, feature), zero outside the image, and zero
+// columns from the geometry's end to the padded width (k_geo_cols writes the
+// geometry columns). One thread per output element.
 __global__ void k_im2col(const float *__restrict__ g, int n_img, int H, int W, __bf16 *__restrict__ x)
 {
     const int64_t rows = (int64_t)n_img * H * W;
@@ -148,8 +208,9 @@ __global__ void k_im2col(const float *__restrict__ g, int n_img, int H, int W, _
     if (i >= rows * LKP[0]) return;
     const int64_t row = i / LKP[0];
     const int c = (int)(i % LKP[0]);
+    if (c >= NIM2COL && c < LK[0]) return;
     float v = 0.f;
-    if (c < LK[0]) {
+    if (c < NIM2COL) {
         const int q = c / NFEAT, f = c % NFEAT;
         const int dv = q / 3 - 1, dh = q % 3 - 1;
         const int img = (int)(row / ((int64_t)H * W));
@@ -607,7 +668,8 @@ __global__ __launch_bounds__(256) void k_profile_errors(const float *__restrict_
 // those of the layer-by-layer path, in the same k order.
 constexpr int MLP_ROWS = 64;
 constexpr int MLP_LDA = 256 + 8;          // LDS row pitch in bf16 (16 B pad against bank conflicts)
-constexpr int L0_K = 96;                  // layer 0 fan-in 72 rounded up to the k-step (32)
+constexpr int L0_K = (LK[0] + 31) / 32 * 32;   // layer-0 fan-in rounded up to the k-step (32)
+static_assert(L0_K <= LKP[0] && L0_K + 8 <= MLP_LDA, "layer-0 input fits the padded weights and the LDS row");
 
 struct MlpWeights {
     const __bf16 *wt[NL];
@@ -671,18 +733,29 @@ __device__ __forceinline__ void mlp_store(__bf16 *__restrict__ act, const float 
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ g, int H, int W, MlpWeights wts,
-                                                     float *__restrict__ y)
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ g, const float *__restrict__ geo,
+                                                     int H, int W, float r_max, MlpWeights wts, float *__restrict__ y)
 {
     __shared__ __attribute__((aligned(16))) __bf16 act[MLP_ROWS * MLP_LDA];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * MLP_ROWS;
-    // layer-0 input: the 3 x 3 neighbourhood features of each row, zero
-    // outside the image and in the padding columns 72 .. 95
+    // layer-0 input: the 3 x 3 neighbourhood features of each row (zero
+    // outside the image), its geometry columns (one thread per row), zero
+    // padding up to the k-step
+    if (t < MLP_ROWS) {
+        const int64_t row = r0 + t;
+        const int img = (int)(row / ((int64_t)H * W));
+        const int rem = (int)(row % ((int64_t)H * W));
+        float f[NGEO];
+        geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, rem / W, rem % W, H, W, r_max, f);
+#pragma unroll
+        for (int j = 0; j < NGEO; ++j) act[t * MLP_LDA + NIM2COL + j] = (__bf16)f[j];
+    }
     for (int e = t; e < MLP_ROWS * L0_K; e += 256) {
         const int r = e / L0_K, c = e % L0_K;
+        if (c >= NIM2COL && c < LK[0]) continue;
         float v = 0.f;
-        if (c < LK[0]) {
+        if (c < NIM2COL) {
             const int q = c / NFEAT, f = c % NFEAT;
             const int64_t row = r0 + r;
             const int img = (int)(row / ((int64_t)H * W));
@@ -888,11 +961,13 @@ static void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, int K, int 
                        bias, mask, ldm, out, ldo, M, N);
 }
 
-static void forward_layers(Surrogate *s, const float *gbuf, int n_img, int H, int W, hipStream_t st)
+static void forward_layers(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W, hipStream_t st)
 {
     const int64_t rows = (int64_t)n_img * H * W;
     hipLaunchKernelGGL(k_im2col, dim3((unsigned)((rows * LKP[0] + 255) / 256)), dim3(256), 0, st, gbuf, n_img, H, W,
                        s->x[0]);
+    hipLaunchKernelGGL(k_geo_cols, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, gbuf, geo, n_img, H, W,
+                       s->r_max, s->x[0]);
     for (int l = 0; l < NL; ++l) {
         if (l < NL - 1)
             gemm<false, false, EPI_BIAS_RELU>(s->x[l], LKP[l], s->wt[l], LKP[l], LKP[l], LKP[l], 1, s->bias[l],
@@ -904,7 +979,8 @@ static void forward_layers(Surrogate *s, const float *gbuf, int n_img, int H, in
 }
 
 // Inference: one fused launch (rows a multiple of MLP_ROWS, checked by the caller).
-hipError_t surrogate_forward(Surrogate *s, const float *gbuf, int n_img, int H, int W, float *coef, hipStream_t st)
+hipError_t surrogate_forward(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W, float *coef,
+                             hipStream_t st)
 {
     const int64_t rows = (int64_t)n_img * H * W;
     MlpWeights w;
@@ -912,16 +988,17 @@ hipError_t surrogate_forward(Surrogate *s, const float *gbuf, int n_img, int H, 
         w.wt[l] = s->wt[l];
         w.bias[l] = s->bias[l];
     }
-    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)(rows / MLP_ROWS)), dim3(256), 0, st, gbuf, H, W, w, coef);
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)(rows / MLP_ROWS)), dim3(256), 0, st, gbuf, geo, H, W, s->r_max,
+                       w, coef);
     return hipGetLastError();
 }
 
 // Forward, loss and backward into s->grad; returns the loss on the device.
-static hipError_t gradient(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
-                           float *dev_loss, hipStream_t st)
+static hipError_t gradient(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W,
+                           const float *target, float *dev_loss, hipStream_t st)
 {
     const int64_t rows = (int64_t)n_img * H * W;
-    forward_layers(s, gbuf, n_img, H, W, st);
+    forward_layers(s, gbuf, geo, n_img, H, W, st);
     const int64_t n = rows * NCOEF;
     const int nblk = (int)((n + 4095) / 4096);
     hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, st, s->y, target, s->lw, n, s->dz[0], s->dpart);
@@ -950,18 +1027,18 @@ static hipError_t gradient(Surrogate *s, const float *gbuf, int n_img, int H, in
     return hipGetLastError();
 }
 
-hipError_t surrogate_gradient(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
-                              float *dev_grad, float *dev_loss, hipStream_t st)
+hipError_t surrogate_gradient(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W,
+                              const float *target, float *dev_grad, float *dev_loss, hipStream_t st)
 {
-    hipError_t e = gradient(s, gbuf, n_img, H, W, target, dev_loss, st);
+    hipError_t e = gradient(s, gbuf, geo, n_img, H, W, target, dev_loss, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dev_grad, s->grad, N_PARAMS * 4, hipMemcpyDeviceToDevice, st);
     return e;
 }
 
-hipError_t surrogate_train_step(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
-                                float lr, float *dev_loss, hipStream_t st)
+hipError_t surrogate_train_step(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W,
+                                const float *target, float lr, float *dev_loss, hipStream_t st)
 {
-    hipError_t e = gradient(s, gbuf, n_img, H, W, target, dev_loss, st);
+    hipError_t e = gradient(s, gbuf, geo, n_img, H, W, target, dev_loss, st);
     if (e != hipSuccess) return e;
     s->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;

@@ -16,11 +16,13 @@ int surrogate_bins(const Surrogate *s);
 hipError_t surrogate_set_state(Surrogate *s, const float *master, const float *m, const float *v, int64_t step);
 hipError_t surrogate_get_state(const Surrogate *s, float *master, float *m, float *v, int64_t *step);
 hipError_t surrogate_set_norm(Surrogate *s, const float *mu, const float *sg);
-hipError_t surrogate_forward(Surrogate *s, const float *gbuf, int n_img, int H, int W, float *coef, hipStream_t st);
-hipError_t surrogate_gradient(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
-                              float *dev_grad, float *dev_loss, hipStream_t st);
-hipError_t surrogate_train_step(Surrogate *s, const float *gbuf, int n_img, int H, int W, const float *target,
-                                float lr, float *dev_loss, hipStream_t st);
+// `geo`: one geometry block of 16 floats per image (device), see sonar.h
+hipError_t surrogate_forward(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W, float *coef,
+                             hipStream_t st);
+hipError_t surrogate_gradient(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W,
+                              const float *target, float *dev_grad, float *dev_loss, hipStream_t st);
+hipError_t surrogate_train_step(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W,
+                                const float *target, float lr, float *dev_loss, hipStream_t st);
 hipError_t surrogate_set_loss_weights(Surrogate *s, const float *w);
 hipError_t surrogate_target_coef(const Surrogate *s, const float *im, const float *gbuf, int64_t rows,
                                  int standardize, float *coef, hipStream_t st);

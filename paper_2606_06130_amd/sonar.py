@@ -35,7 +35,8 @@ EXPORTS = ("sonar_build_scene", "sonar_free_scene", "sonar_get_scene_info", "son
            "sonar_batch_autotune", "sonar_batch_emit_desc_bytes", "sonar_batch_detect_workspace_size",
            "sonar_batch_prepare_detect", "sonar_surrogate_param_count", "sonar_surrogate_create",
            "sonar_surrogate_free", "sonar_surrogate_set_state", "sonar_surrogate_get_state",
-           "sonar_surrogate_set_norm", "sonar_surrogate_forward", "sonar_surrogate_train_step",
+           "sonar_surrogate_set_norm", "sonar_surrogate_geometry", "sonar_surrogate_forward",
+           "sonar_surrogate_train_step",
            "sonar_surrogate_gradient", "sonar_surrogate_target", "sonar_surrogate_moments",
            "sonar_surrogate_set_loss_weights",
            "sonar_surrogate_profile", "sonar_lfm_pulse", "sonar_pulse_compress",
@@ -211,15 +212,17 @@ def lib():
         L.sonar_surrogate_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
         L.sonar_surrogate_set_norm.restype = C.c_int
         L.sonar_surrogate_set_norm.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_geometry.restype = C.c_int
+        L.sonar_surrogate_geometry.argtypes = [P(sonar_params), P(sonar_pose), C.c_void_p]
         L.sonar_surrogate_forward.restype = C.c_int
-        L.sonar_surrogate_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
-                                              C.c_void_p]
+        L.sonar_surrogate_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                              C.c_void_p, C.c_void_p]
         L.sonar_surrogate_train_step.restype = C.c_int
-        L.sonar_surrogate_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
-                                                 C.c_float, C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                                 C.c_void_p, C.c_float, C.c_void_p, C.c_void_p]
         L.sonar_surrogate_gradient.restype = C.c_int
-        L.sonar_surrogate_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
-                                               C.c_void_p, C.c_void_p, C.c_void_p]
+        L.sonar_surrogate_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.sonar_surrogate_set_loss_weights.restype = C.c_int
         L.sonar_surrogate_set_loss_weights.argtypes = [C.c_void_p, C.c_void_p]
         L.sonar_surrogate_target.restype = C.c_int
@@ -712,6 +715,22 @@ class Batch:
         return a, b
 
 
+def surrogate_geometry(cfg, poses):
+    """Host float32 [len(poses), 16]: the surrogate's geometry block of each
+    pose (sonar_surrogate_geometry)."""
+    p = params_of(cfg)
+    out = np.zeros((len(poses), 16), np.float32)
+    for i, pose in enumerate(poses):
+        q = pose_of(pose)
+        _check(lib().sonar_surrogate_geometry(C.byref(p), C.byref(q), out[i].ctypes.data))
+    return out
+
+
+def _geo_check(geo, n):
+    if tuple(geo.shape) != (n, 16) or not geo.is_contiguous():
+        raise ValueError(f"geometry must be a contiguous [{n}, 16] tensor, got {tuple(geo.shape)}")
+
+
 class Surrogate:
     """The learned multipath surrogate (weights, Adam state, activations on the device)."""
 
@@ -754,25 +773,29 @@ class Surrogate:
         _check(lib().sonar_surrogate_set_norm(self._h, a.ctypes.data, b.ctypes.data))
         self.mean, self.std = a, b
 
-    def forward(self, gbuf, out=None, stream=None):
+    def forward(self, gbuf, geo, out=None, stream=None):
+        """`gbuf` [n, H, W, 8] and `geo` [n, 16] (surrogate_geometry) on the device."""
         import torch
         n, H, W = gbuf.shape[0], gbuf.shape[1], gbuf.shape[2]
+        _geo_check(geo, n)
         out = out if out is not None else torch.empty((n * H * W, 64), dtype=torch.float32, device="cuda")
-        _check(lib().sonar_surrogate_forward(self._h, _dptr(gbuf), n, H, W, _dptr(out), _stream(stream)))
+        _check(lib().sonar_surrogate_forward(self._h, _dptr(gbuf), _dptr(geo), n, H, W, _dptr(out), _stream(stream)))
         return out
 
-    def train_step(self, gbuf, target, lr, loss_out, stream=None):
+    def train_step(self, gbuf, geo, target, lr, loss_out, stream=None):
         n, H, W = gbuf.shape[0], gbuf.shape[1], gbuf.shape[2]
-        _check(lib().sonar_surrogate_train_step(self._h, _dptr(gbuf), n, H, W, _dptr(target), float(lr),
+        _geo_check(geo, n)
+        _check(lib().sonar_surrogate_train_step(self._h, _dptr(gbuf), _dptr(geo), n, H, W, _dptr(target), float(lr),
                                                 _dptr(loss_out), _stream(stream)))
 
-    def gradient(self, gbuf, target, stream=None):
+    def gradient(self, gbuf, geo, target, stream=None):
         import torch
         n, H, W = gbuf.shape[0], gbuf.shape[1], gbuf.shape[2]
+        _geo_check(geo, n)
         g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
         loss = torch.empty(1, dtype=torch.float32, device="cuda")
-        _check(lib().sonar_surrogate_gradient(self._h, _dptr(gbuf), n, H, W, _dptr(target), _dptr(g), _dptr(loss),
-                                              _stream(stream)))
+        _check(lib().sonar_surrogate_gradient(self._h, _dptr(gbuf), _dptr(geo), n, H, W, _dptr(target), _dptr(g),
+                                              _dptr(loss), _stream(stream)))
         return g, loss
 
     def set_loss_weights(self, w=None):

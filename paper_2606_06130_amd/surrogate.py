@@ -81,11 +81,17 @@ def loss_weights(std):
     return (v / v.mean()).astype(np.float32)
 
 
+def geometry(src, poses):
+    """Device [len(poses), 16]: the geometry blocks of the poses."""
+    return src.torch.from_numpy(sonar.surrogate_geometry(src.cfg, poses)).cuda()
+
+
 def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
     """Adam with cosine learning-rate decay over mini-batches of `batch_pings`
     pings. Returns the per-step losses."""
     torch = src.torch
     B = batch_pings
+    geo_all = geometry(src, poses)
     gb = torch.empty((B, src.H, src.W, 8), dtype=torch.float32, device="cuda")
     tgt = torch.empty((B * src.rows, 64), dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
@@ -101,11 +107,13 @@ def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
             if step < start_step:
                 step += 1
                 continue
+            pick = order[s * B:(s + 1) * B]
             for b in range(B):
-                _, _, im = src.run(poses[order[s * B + b]], gbuf_slot=gb[b])
+                _, _, im = src.run(poses[pick[b]], gbuf_slot=gb[b])
                 sur.target(im, gb[b], standardize=True, out=tgt[b * src.rows:(b + 1) * src.rows])
+            geo = geo_all[torch.from_numpy(pick).cuda()].contiguous()
             lr = 0.5 * lr0 * (1.0 + math.cos(math.pi * step / max(total, 1)))
-            sur.train_step(gb, tgt, lr, loss)
+            sur.train_step(gb, geo, tgt, lr, loss)
             if step % 50 == 0 or step == total - 1:
                 lv = float(loss.item())
                 losses.append((step, lv))
@@ -137,9 +145,10 @@ def evaluate(sur, src, poses):
     # standardised coefficients of a zero level: the profile is then the smoothed input channel
     zero = torch.from_numpy(-sur.mean / sur.std).cuda().expand(src.rows, 64).contiguous()
     occupied_db = 10.0 * math.log10(1e-11) + 3.0
-    for p in poses:
+    geo_all = geometry(src, poses)
+    for i, p in enumerate(poses):
         _, i1, im = src.run(p, gbuf_slot=gbv[0])
-        sur.forward(gbv, out=coef)
+        sur.forward(gbv, geo_all[i:i + 1], out=coef)
         pred, e = sur.profile(coef, i1, gbv, im)
         sur.target(im, gbv, standardize=True, out=exact)
         trunc, et = sur.profile(exact, i1, gbv, im)
@@ -239,7 +248,8 @@ def main(argv=None):
     losses = train(sur, src, train_poses, args.epochs, args.batch, args.lr, log, start_step=start)
     t_train = time.time() - t0
     save_checkpoint(os.path.join(args.out, "checkpoint.npz"), sur, mean, std)
-    meta = {"target": "level", "smooth": 32, "train_pings": args.train_pings, "train_pose_seed": 5,
+    meta = {"target": "level", "inputs": "gbuffer+geometry", "smooth": 32, "train_pings": args.train_pings,
+            "train_pose_seed": 5,
             "epochs": args.epochs, "batch_pings": args.batch, "lr": args.lr, "stats_pings": args.stats_pings}
     if args.weights_out:
         save_checkpoint(args.weights_out, sur, mean, std, extra=meta, weights_only=True)

@@ -32,9 +32,22 @@ def bf16_round(x):
     return r.astype(np.uint32).view(np.float32)
 
 
+R_MAX = 15.0
+
+
+def _rot(yaw, pitch):
+    cy, sy, cp, sp = math.cos(yaw), math.sin(yaw), math.cos(pitch), math.sin(pitch)
+    return np.array([[cy, -sy, 0.0], [sy, cy, 0.0], [0.0, 0.0, 1.0]]) @ np.array([[cp, 0.0, sp], [0.0, 1.0, 0.0],
+                                                                                  [-sp, 0.0, cp]])
+
+
 def _inputs(seed, n=1, H=8, W=16):
+    """Random G-buffers (BF16 values), geometry blocks of random poses, targets, weights."""
     rng = np.random.Generator(np.random.PCG64(seed))
     g = bf16_round(rng.uniform(-1, 1, (n, H, W, 8)).astype(np.float32))
+    g[..., 0] = bf16_round(rng.uniform(0.02, 1.0, (n, H, W)).astype(np.float32))     # mean range / r_max
+    geo = np.stack([SO.geometry_block(rng.uniform(-8, 8, 3), _rot(rng.uniform(-3, 3), rng.uniform(-0.8, 0.8)),
+                                      math.radians(90), math.radians(40)) for _ in range(n)]).astype(np.float32)
     t = rng.normal(0, 1, (n * H * W, 64)).astype(np.float32)
     theta = S.surrogate_init_params(seed + 1)
     # BF16 weights so both sides use the same operand values; biases stay FP32
@@ -44,7 +57,7 @@ def _inputs(seed, n=1, H=8, W=16):
         off += k * nn
         theta[off:off + nn] = rng.normal(0, 0.05, nn)
         off += nn
-    return g, t, theta
+    return g, geo, t, theta
 
 
 def _split(v):
@@ -60,17 +73,18 @@ def _split(v):
 @pytest.mark.parametrize("weighted", [False, True])
 def test_gradient_matches_oracle(weighted):
     torch, sonar = _gpu()
-    g, t, theta = _inputs(1)
-    sur = sonar.Surrogate(128, 1024)
+    g, geo, t, theta = _inputs(1)
+    sur = sonar.Surrogate(128, 1024, 0.3, R_MAX)
     sur.set_state(theta)
     w = np.random.Generator(np.random.PCG64(12)).uniform(0.1, 3.0, 64).astype(np.float32) if weighted else None
     sur.set_loss_weights(w)
-    gd, loss = sur.gradient(torch.from_numpy(g).cuda(), torch.from_numpy(t).cuda())
+    gd, loss = sur.gradient(torch.from_numpy(g).cuda(), torch.from_numpy(geo).cuda(), torch.from_numpy(t).cuda())
     gg = gd.cpu().numpy().astype(np.float64)
-    lo, go, _ = SO.loss_and_grad(theta.astype(np.float64), g, t, w=w)
+    x0 = SO.inputs(g, geo, R_MAX)
+    lo, go, _ = SO.loss_and_grad(theta.astype(np.float64), x0, t, w=w)
     # the same FP64 definition with activations and layer gradients stored in
     # BF16, as the kernels store them
-    lb, gob, _ = SO.loss_and_grad(theta.astype(np.float64), g, t, store=lambda a: bf16_round(a).astype(np.float64),
+    lb, gob, _ = SO.loss_and_grad(theta.astype(np.float64), x0, t, store=lambda a: bf16_round(a).astype(np.float64),
                                   w=w)
     assert abs(float(loss.item()) - lo) <= 2e-2 * lo
     res = []
@@ -97,12 +111,13 @@ def test_forward_matches_oracle(n, H, W):
     """The fused inference kernel (64-row tiles; with 6 x 16 and 8 x 24
     images the tiles straddle image rows and images)."""
     torch, sonar = _gpu()
-    g, _, theta = _inputs(2, n=n, H=H, W=W)
-    sur = sonar.Surrogate(256, 1024)
+    g, geo, _, theta = _inputs(2, n=n, H=H, W=W)
+    sur = sonar.Surrogate(256, 1024, 0.3, R_MAX)
     sur.set_state(theta)
-    y = sur.forward(torch.from_numpy(g).cuda()).cpu().numpy()
-    _, yo = SO.forward(theta.astype(np.float64), SO.im2col(g))
-    _, yb = SO.forward(theta.astype(np.float64), SO.im2col(g), store=lambda a: bf16_round(a).astype(np.float64))
+    y = sur.forward(torch.from_numpy(g).cuda(), torch.from_numpy(geo).cuda()).cpu().numpy()
+    x0 = SO.inputs(g, geo, R_MAX)
+    _, yo = SO.forward(theta.astype(np.float64), x0)
+    _, yb = SO.forward(theta.astype(np.float64), x0, store=lambda a: bf16_round(a).astype(np.float64))
     rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
     relb = np.linalg.norm(y - yb) / np.linalg.norm(yb)
     _log("forward rel", rel, "vs bf16-stored", relb)
@@ -167,25 +182,25 @@ def test_level_coefficients_and_profile_match_oracle():
 
 def test_training_reduces_loss_and_resumes_bit_exactly():
     torch, sonar = _gpu()
-    g, t, theta = _inputs(4, n=2)
-    G, T = torch.from_numpy(g).cuda(), torch.from_numpy(t).cuda()
+    g, geo, t, theta = _inputs(4, n=2)
+    G, GEO, T = torch.from_numpy(g).cuda(), torch.from_numpy(geo).cuda(), torch.from_numpy(t).cuda()
     loss = torch.zeros(1, device="cuda")
     a = sonar.Surrogate(256, 1024)
     a.set_state(theta)
-    a.train_step(G, T, 1e-3, loss)
+    a.train_step(G, GEO, T, 1e-3, loss)
     first = float(loss.item())
     for _ in range(49):
-        a.train_step(G, T, 1e-3, loss)
+        a.train_step(G, GEO, T, 1e-3, loss)
     mid = a.get_state()
     for _ in range(150):
-        a.train_step(G, T, 1e-3, loss)
+        a.train_step(G, GEO, T, 1e-3, loss)
     last = float(loss.item())
     _log("loss", first, last)
     assert last < first / 5
     b = sonar.Surrogate(256, 1024)
     b.set_state(*mid)
     for _ in range(150):
-        b.train_step(G, T, 1e-3, loss)
+        b.train_step(G, GEO, T, 1e-3, loss)
     pa, ma, va, sa = a.get_state()
     pb, mb, vb, sb = b.get_state()
     assert sa == sb == 200
@@ -229,7 +244,7 @@ def test_committed_weights_beat_single_bounce():
     src = SU.PingSource(scene, cfg)
     sur = sonar.Surrogate(src.rows, cfg.n_range, cfg.r_min, cfg.r_max)
     mean, std, step, meta = SU.load_checkpoint(SU.WEIGHTS, sur)
-    assert step > 0 and meta.get("target") == "level"
+    assert step > 0 and meta.get("target") == "level" and meta.get("inputs") == "gbuffer+geometry"
     res = SU.evaluate(sur, src, S.random_poses(6, 16))
     _log("committed weights, 16 held-out poses", res)
     assert res["beams"] > 100000

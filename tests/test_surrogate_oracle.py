@@ -9,7 +9,101 @@ from paper_2606_06130_amd.scenes import surrogate_init_params
 
 
 def test_parameter_count():
-    assert SO.param_count() == 169344
+    # (72 neighbourhood + 45 geometry inputs) x 64, then 64 x 256, 2 x 256 x 256 and 256 x 64, with biases
+    assert SO.N_IN == 117 and SO.N_GEO == 45
+    assert SO.param_count() == 117 * 64 + 64 + 64 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 64 + 64 == 172224
+
+
+def _rot_z(a):
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def _rot_y(a):
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
+
+
+def _geo_cols(f):
+    """Split geometry columns: P/10, u, S/10, sines [6, N_FREQ], cosines [6, N_FREQ]."""
+    F = SO.N_FREQ
+    return f[:, 0:3], f[:, 3:6], f[:, 6:9], f[:, 9:9 + 6 * F].reshape(-1, 6, F), f[:, 9 + 6 * F:].reshape(-1, 6, F)
+
+
+def test_geometry_axis_hit_point_and_rotation():
+    """The centre beam of a 1 x 1 layout looks along the sensor's x axis: with
+    a 90-degree yaw that is the world y axis, and the mean first hit lies on
+    it at the G-buffer range; a sensor pitched down by a leaves it with
+    vertical component -sin a."""
+    S = np.array([1.0, -2.0, -3.0])
+    g = np.zeros((1, 1, 1, 8))
+    g[..., 0] = 0.4
+    g[..., 6] = 1.0
+    f = SO.geometry_features(g, [SO.geometry_block(S, _rot_z(np.pi / 2), 0.3, 0.2)], 15.0)
+    P10, u, S10, _, _ = _geo_cols(f)
+    np.testing.assert_allclose(u[0], [0.0, 1.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(P10[0] * 10.0, S + np.array([0.0, 6.0, 0.0]), atol=1e-12)
+    np.testing.assert_allclose(S10[0] * 10.0, S, atol=1e-15)
+    a = 0.35
+    f = SO.geometry_features(g, [SO.geometry_block(S, _rot_y(a), 0.3, 0.2)], 15.0)
+    _, u, _, _, _ = _geo_cols(f)
+    np.testing.assert_allclose(u[0], [np.cos(a), 0.0, -np.sin(a)], atol=1e-15)
+
+
+def test_geometry_layout_symmetry_and_range():
+    """Cell-centred beams of a 2 x 2 layout: opposite corners mirror in the
+    sensor's y and z, each axis is a unit vector, and P - S is the axis times
+    the G-buffer range; a beam without a hit has P at the origin."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    g = np.zeros((1, 2, 2, 8))
+    g[..., 0] = rng.uniform(0.1, 0.9, (1, 2, 2))
+    g[..., 6] = 1.0
+    g[0, 1, 0, 6] = 0.0                                    # no hit in beam (v=1, h=0)
+    S = rng.normal(size=3)
+    f = SO.geometry_features(g, [SO.geometry_block(S, np.eye(3), 0.8, 0.6)], 15.0)
+    P10, u, _, _, _ = _geo_cols(f)
+    np.testing.assert_allclose(np.linalg.norm(u, axis=1), 1.0, atol=1e-15)
+    # rows are (v, h) = (0,0), (0,1), (1,0), (1,1): (0,0) and (1,1) mirror in y and z
+    np.testing.assert_allclose(u[0] * [1, -1, -1], u[3], atol=1e-15)
+    np.testing.assert_allclose(u[1] * [1, -1, -1], u[2], atol=1e-15)
+    assert u[0, 1] < 0 and u[0, 2] < 0                    # h = 0 looks right (-y), v = 0 looks down
+    for row, v, h in ((0, 0, 0), (1, 0, 1), (3, 1, 1)):
+        np.testing.assert_allclose(P10[row] * 10.0 - S, 15.0 * g[0, v, h, 0] * u[row], atol=1e-12)
+    np.testing.assert_array_equal(P10[2], 0.0)
+
+
+def test_geometry_fourier_columns():
+    """Sines and cosines at octaves: sin^2 + cos^2 = 1, each octave's sine is
+    the double angle of the one below (sin 2t = 2 sin t cos t), the lowest
+    octave is a quarter turn per unit, and a zero input gives (0, 1)."""
+    rng = np.random.Generator(np.random.PCG64(10))
+    g = np.zeros((2, 3, 4, 8))
+    g[..., 0] = rng.uniform(0.05, 1.0, (2, 3, 4))
+    g[..., 6] = rng.random((2, 3, 4)) < 0.7
+    geo = [SO.geometry_block(rng.normal(size=3) * 5, _rot_z(rng.uniform(-3, 3)) @ _rot_y(rng.uniform(-1, 1)), 1.2, 0.5)
+           for _ in range(2)]
+    f = SO.geometry_features(g, geo, 15.0)
+    P10, u, _, sn, cs = _geo_cols(f)
+    x = np.concatenate([P10, u], axis=1)
+    np.testing.assert_allclose(sn ** 2 + cs ** 2, 1.0, atol=1e-14)
+    np.testing.assert_allclose(sn[:, :, 0], np.sin(np.pi / 2 * x), atol=1e-14)
+    for k in range(1, SO.N_FREQ):
+        np.testing.assert_allclose(sn[:, :, k], 2 * sn[:, :, k - 1] * cs[:, :, k - 1], atol=1e-13)
+        np.testing.assert_allclose(cs[:, :, k], cs[:, :, k - 1] ** 2 - sn[:, :, k - 1] ** 2, atol=1e-13)
+    nohit = (g[..., 6] <= 0).reshape(-1)
+    assert nohit.any()
+    np.testing.assert_array_equal(sn[nohit, :3], 0.0)
+    np.testing.assert_array_equal(cs[nohit, :3], 1.0)
+
+
+def test_inputs_concatenate_im2col_and_geometry():
+    rng = np.random.Generator(np.random.PCG64(11))
+    g = rng.normal(size=(1, 3, 5, 8))
+    geo = [SO.geometry_block([0.0, 1.0, 2.0], np.eye(3), 1.0, 0.4)]
+    x = SO.inputs(g, geo, 15.0)
+    assert x.shape == (15, SO.N_IN)
+    np.testing.assert_array_equal(x[:, :72], SO.im2col(g))
+    np.testing.assert_array_equal(x[:, 72:], SO.geometry_features(g, geo, 15.0))
 
 
 def test_im2col_brute_force():
@@ -36,9 +130,10 @@ def test_gradients_match_central_differences(weighted):
     theta = surrogate_init_params(3).astype(np.float64)
     theta += rng.normal(0, 0.01, theta.size)                  # nonzero biases
     g = rng.uniform(-1, 1, size=(1, 4, 5, 8))
+    x0 = SO.inputs(g, [SO.geometry_block(rng.normal(size=3), _rot_z(0.7), 1.0, 0.5)], 15.0)
     t = rng.normal(size=(20, 64))
     w = rng.uniform(0.1, 3.0, 64) if weighted else None
-    loss, grad, _ = SO.loss_and_grad(theta, g, t, w=w)
+    loss, grad, _ = SO.loss_and_grad(theta, x0, t, w=w)
     idx = rng.choice(theta.size, 60, replace=False)
     # include entries of every layer's weights and biases
     offs = np.cumsum([0] + [k * n + n for k, n in SO.LAYERS])
@@ -50,8 +145,8 @@ def test_gradients_match_central_differences(weighted):
         tp[i] += h
         tm = theta.copy()
         tm[i] -= h
-        lp = SO.loss_and_grad(tp, g, t, w=w)[0]
-        lm = SO.loss_and_grad(tm, g, t, w=w)[0]
+        lp = SO.loss_and_grad(tp, x0, t, w=w)[0]
+        lm = SO.loss_and_grad(tm, x0, t, w=w)[0]
         fd = (lp - lm) / (2 * h)
         assert abs(fd - grad[i]) <= 1e-6 * max(abs(fd), 1e-3), (i, fd, grad[i])
 
