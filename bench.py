@@ -348,17 +348,48 @@ def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
     i1 = o1["incoh"].view(2, rows, cfg1.n_range)[0]
     geo = torch.from_numpy(sonar.surrogate_geometry(cfg1, [pose])).cuda()     # the ping's pose, resident like it
 
+    prof = torch.empty((rows, cfg1.n_range), dtype=torch.float32, device="cuda")
+
     def sur_ping():
         sonar.ping(scene, cfg1, pose, out=o1)
         sur.forward(gview, geo, out=coef)
-        sur.profile(coef, i1, gview, im=None, want_profile=True)
+        sur.profile(coef, i1, gview, im=None, want_profile=True, out=prof)
 
     sp_ms = timed(sur_ping)
     fwd_ms = timed(lambda: sur.forward(gview, geo, out=coef), n=20)
+    # the surrogate ping as a job of independent pings on four streams, like
+    # the multipath job: each stream with its own ping outputs, coefficients
+    # and profile (the network's weights are shared, read-only)
+    s_streams = [torch.cuda.Stream() for _ in range(ns)]
+    s_bufs = []
+    for _ in range(ns):
+        ob = sonar.alloc_outputs(cfg1, gbuffer=True, incoh=True)
+        s_bufs.append((ob, ob["gbuffer"].view(1, bv, bh, 8), ob["incoh"].view(2, rows, cfg1.n_range)[0],
+                       torch.empty((rows, 64), dtype=torch.float32, device="cuda"),
+                       torch.empty((rows, cfg1.n_range), dtype=torch.float32, device="cuda")))
+
+    def sur_job(n):
+        for i in range(n):
+            ob, gv, ii, cf, pf = s_bufs[i % ns]
+            st = s_streams[i % ns]
+            sonar.ping(scene, cfg1, pose, out=ob, stream=st)
+            sur.forward(gv, geo, out=cf, stream=st)
+            sur.profile(cf, ii, gv, im=None, want_profile=True, stream=st, out=pf)
+
+    sur_job(2 * ns)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sur_job(n_job)
+    torch.cuda.synchronize()
+    sjob_ms = (time.perf_counter() - t0) * 1e3 / n_job
+    assert scene.status() == 0
+    del s_bufs, s_streams
     fwd_tflops = 2.0 * SURROGATE_MACS_PER_ROW * rows / (fwd_ms * 1e-3) / 1e12
     surrogate = {"workload": "single-bounce ping with G-buffer + fused network inference (172,224 parameters, "
                              "BF16 MFMA) + predicted 1,024-bin multi-bounce profile, same scene and layout",
                  "ping_ms": sp_ms, "pings_per_s": 1e3 / sp_ms, "rate_vs_full_multipath": mp_ms / sp_ms,
+                 "job": {"streams": ns, "pings": n_job, "ms_per_ping": sjob_ms, "pings_per_s": 1e3 / sjob_ms,
+                         "rate_vs_full_multipath_job": job_ms / sjob_ms},
                  "weights": os.path.relpath(SU.WEIGHTS, ROOT), "weights_train_steps": sur_steps,
                  "weights_meta": sur_meta,
                  "forward": {"ms": fwd_ms, "rows": rows, "tflops": fwd_tflops,
@@ -377,7 +408,7 @@ def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
         surrogate["rate_note"] = (f"rate_vs_full_multipath is quoted at {held['surrogate']['mean_db']:.2f} dB mean "
                                   "error against the smoothed truth, not at the 1 dB the metric names"
                                   if not held["meets_1db"] else "rate quoted at <= 1 dB mean error")
-    del o1, sur, coef
+    del o1, sur, coef, prof
     multipath["surrogate"] = surrogate
 
     items = S.lawnmower_batch()
@@ -495,9 +526,29 @@ def layered_ping(torch, sonar, np, scene, cfg, pose, reps=10):
 
 def profile_case(torch, sonar, S, case, steps, warmup, knobs=(12, 1, 1)):
     """One workload alone, for profiler runs: the harbor multipath ping on
-    one stream, or graph replays of the 256-ping lawnmower batch with CFAR."""
+    one stream, the surrogate ping (single-bounce ping, fused inference,
+    predicted profile) with the committed weights, or graph replays of the
+    256-ping lawnmower batch with CFAR."""
     scene = sonar.Scene(S.scene_harbor_multipath())
-    if case in ("multipath", "multipath_fused", "multipath_straight"):
+    if case == "surrogate":
+        from paper_2606_06130_amd import surrogate as SU
+        cfg1, pose = S.sensor_harbor_multipath().replace(max_bounces=1), S.pose_harbor()
+        o1 = sonar.alloc_outputs(cfg1, gbuffer=True, incoh=True)
+        bv, bh = sonar.beams_of(cfg1)
+        rows = bv * bh
+        sur = sonar.Surrogate(rows, cfg1.n_range, cfg1.r_min, cfg1.r_max)
+        SU.load_checkpoint(SU.WEIGHTS, sur)
+        coef = torch.empty((rows, 64), dtype=torch.float32, device="cuda")
+        prof = torch.empty((rows, cfg1.n_range), dtype=torch.float32, device="cuda")
+        geo = torch.from_numpy(sonar.surrogate_geometry(cfg1, [pose])).cuda()
+        gview = o1["gbuffer"].view(1, bv, bh, 8)
+        i1 = o1["incoh"].view(2, rows, cfg1.n_range)[0]
+
+        def run():
+            sonar.ping(scene, cfg1, pose, out=o1)
+            sur.forward(gview, geo, out=coef)
+            sur.profile(coef, i1, gview, im=None, want_profile=True, out=prof)
+    elif case in ("multipath", "multipath_fused", "multipath_straight"):
         cfg, pose = S.sensor_harbor_multipath(), S.pose_harbor()
         if case == "multipath_straight":
             cfg = cfg.replace(c_grad=0.0)
@@ -530,7 +581,8 @@ def main():
                     help="held-out poses the committed surrogate weights are evaluated on (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for counter calibration) and exit")
-    ap.add_argument("--case", choices=("multipath", "multipath_fused", "multipath_straight", "batch"), default=None,
+    ap.add_argument("--case", choices=("multipath", "multipath_fused", "multipath_straight", "batch", "surrogate"),
+                    default=None,
                     help="run only this workload --steps times after --warmup (for profiler runs) and exit")
     ap.add_argument("--batch-knobs", default="12,1,1",
                     help="blocks per CU, tiles per pop, waves per block of the batch profiler case (the values the "

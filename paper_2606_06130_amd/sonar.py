@@ -818,10 +818,14 @@ class Surrogate:
                                              _stream(stream)))
         return s1, s2
 
-    def profile(self, coef, i1, gbuf, im=None, want_profile=True, stream=None):
+    def profile(self, coef, i1, gbuf, im=None, want_profile=True, stream=None, out=None):
+        """Predicted profile [rows, n_bins] (into `out` if given) and, with `im`,
+        the per-beam errors [rows, 8]."""
         import torch
         rows = coef.shape[0]
-        prof = torch.empty((rows, self.n_bins), dtype=torch.float32, device="cuda") if want_profile else None
+        prof = None
+        if want_profile:
+            prof = out if out is not None else torch.empty((rows, self.n_bins), dtype=torch.float32, device="cuda")
         err = torch.empty((rows, 8), dtype=torch.float32, device="cuda") if im is not None else None
         _check(lib().sonar_surrogate_profile(self._h, _dptr(coef), _dptr(i1), _dptr(im), _dptr(gbuf), rows,
                                              _dptr(prof), _dptr(err), _stream(stream)))
