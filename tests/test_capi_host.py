@@ -226,3 +226,21 @@ def test_pulse_dt_rejects(L):
     bad = sonar.ssp_of(((0.0, 1500.0), (-1.0, 1490.0)))
     dt = C.c_double()
     assert L.sonar_pulse_dt(C.byref(p), C.byref(q), C.byref(bad), C.byref(dt)) == sonar.SONAR_E_INVALID
+
+
+def test_surrogate_geometry_block(L):
+    """The surrogate's per-ping geometry block: sensor position, rotation
+    row-major, fields of view, two zeros; the oracle's block of the same pose
+    equals it; the LiDAR grid and bad fields of view are rejected."""
+    from oracle import surrogate as SO
+    cfg = S.sensor_harbor_multipath()
+    poses = [S.pose((1.5, -2.0, -3.25), yaw=0.3, pitch_down=0.4), S.pose((0.0, 4.0, -1.0), yaw=-1.1)]
+    blk = sonar.surrogate_geometry(cfg, poses)
+    assert blk.shape == (2, 16) and blk.dtype == np.float32
+    for i, p in enumerate(poses):
+        want = SO.geometry_block(p.position, p.rot, cfg.hfov, cfg.vfov).astype(np.float32)
+        np.testing.assert_array_equal(blk[i], want)
+    with pytest.raises(sonar.SonarError):
+        sonar.surrogate_geometry(cfg.replace(grid_mode=1), poses[:1])
+    with pytest.raises(sonar.SonarError):
+        sonar.surrogate_geometry(cfg.replace(vfov=0.0), poses[:1])
