@@ -641,7 +641,7 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
  * each layer W [fan_in][fan_out] row-major then b [fan_out], with (fan_in,
  * fan_out) = (117, 64), (64, 256), (256, 256), (256, 256), (256, 64); input
  * column order: the neighbourhood (dv, dh, feature), then the geometry.
- * G-buffer: float [n_img][H][W][8] as sonar_ping writes it; geometry: float
+ * G-buffer: float [n_img][H][W][8] as sonar_ping writes it (16-byte aligned); geometry: float
  * [n_img][16] on the device; rows = n_img * H * W (a multiple of 64 for the
  * network, at most max_rows everywhere).
  * Standardisation: coefficient j is (c_j - mean_j) / std_j (defaults 0, 1). */

@@ -1366,6 +1366,7 @@ sonar_status sonar_surrogate_set_loss_weights(sonar_surrogate *h, const float *w
 static sonar_status check_gbuf(const sonar_surrogate *h, const float *g, int32_t n, int32_t H, int32_t W)
 {
     if (!h || !g) return fail(SONAR_E_INVALID, "surrogate and gbuffer are required");
+    if (((uintptr_t)g & 15) != 0) return fail(SONAR_E_INVALID, "gbuffer must be 16-byte aligned");
     if (n < 1 || H < 1 || W < 1) return fail(SONAR_E_INVALID, "n_img, h, w must be >= 1");
     const int64_t rows = (int64_t)n * H * W;
     if (rows % 64 != 0) return fail(SONAR_E_INVALID, "n_img * h * w must be a multiple of 64");

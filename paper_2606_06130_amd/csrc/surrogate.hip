@@ -182,7 +182,8 @@ __device__ __forceinline__ void geo_columns(const float *__restrict__ geo, const
     }
 }
 
-// Geometry columns of the layer-0 input, one thread per row.
+// Geometry columns of the layer-0 input, and zeros in its padding columns,
+// one thread per row.
 __global__ void k_geo_cols(const float *__restrict__ g, const float *__restrict__ geo, int n_img, int H, int W,
                            float r_max, __bf16 *__restrict__ x)
 {
@@ -195,31 +196,33 @@ __global__ void k_geo_cols(const float *__restrict__ g, const float *__restrict_
     geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, rem / W, rem % W, H, W, r_max, f);
 #pragma unroll
     for (int j = 0; j < NGEO; ++j) x[row * LKP[0] + NIM2COL + j] = (__bf16)f[j];
+#pragma unroll
+    for (int c = LK[0]; c < LKP[0]; ++c) x[row * LKP[0] + c] = (__bf16)0.f;
 }
 
-// im2col of the G-buffer: row (img, v, h) gets the 8 features of the 3 x 3
-// neighbourhood ordered (dv, dh, feature), zero outside the image, and zero
-// columns from the geometry's end to the padded width (k_geo_cols writes the
-// geometry columns). One thread per output element.
+// im2col of the G-buffer: row (img, v, h) gets the 8 features of its 3 x 3
+// neighbourhood ordered (dv, dh, feature), zero outside the image (k_geo_cols
+// writes the remaining columns). One thread per (row, neighbour): two
+// 16-byte loads and one 16-byte store.
 __global__ void k_im2col(const float *__restrict__ g, int n_img, int H, int W, __bf16 *__restrict__ x)
 {
     const int64_t rows = (int64_t)n_img * H * W;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows * LKP[0]) return;
-    const int64_t row = i / LKP[0];
-    const int c = (int)(i % LKP[0]);
-    if (c >= NIM2COL && c < LK[0]) return;
-    float v = 0.f;
-    if (c < NIM2COL) {
-        const int q = c / NFEAT, f = c % NFEAT;
-        const int dv = q / 3 - 1, dh = q % 3 - 1;
-        const int img = (int)(row / ((int64_t)H * W));
-        const int rem = (int)(row % ((int64_t)H * W));
-        const int vv = rem / W + dv, hh = rem % W + dh;
-        if (vv >= 0 && vv < H && hh >= 0 && hh < W)
-            v = g[(((int64_t)img * H + vv) * W + hh) * GB_STRIDE + f];
+    if (i >= rows * 9) return;
+    const int64_t row = i / 9;
+    const int q = (int)(i - row * 9);
+    const int img = (int)(row / ((int64_t)H * W));
+    const int rem = (int)(row - img * ((int64_t)H * W));
+    const int vv = rem / W + q / 3 - 1, hh = rem % W + q % 3 - 1;
+    float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+    if (vv >= 0 && vv < H && hh >= 0 && hh < W) {
+        const float4 *src = reinterpret_cast<const float4 *>(g + (((int64_t)img * H + vv) * W + hh) * GB_STRIDE);
+        lo = src[0];
+        hi = src[1];
     }
-    x[i] = (__bf16)v;
+    const bf16x8 w8 = {(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
+                       (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
+    *reinterpret_cast<bf16x8 *>(x + row * LKP[0] + q * NFEAT) = w8;      // rows of 256 bytes: aligned
 }
 
 // Weighted MSE on the 64 coefficients: dZ = 2 w_j (y - t) / (rows * 64) in
@@ -737,33 +740,45 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ g
                                                      int H, int W, float r_max, MlpWeights wts, float *__restrict__ y)
 {
     __shared__ __attribute__((aligned(16))) __bf16 act[MLP_ROWS * MLP_LDA];
+    __shared__ int rpos[MLP_ROWS][3];     // image, v, h of each row
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * MLP_ROWS;
-    // layer-0 input: the 3 x 3 neighbourhood features of each row (zero
-    // outside the image), its geometry columns (one thread per row), zero
-    // padding up to the k-step
+    const int64_t hw = (int64_t)H * W;
+    // layer-0 input. Each row's image and beam are decoded once (the 64-bit
+    // and run-time divisions stay out of the per-element loop); its geometry
+    // columns come from one thread per row
     if (t < MLP_ROWS) {
         const int64_t row = r0 + t;
-        const int img = (int)(row / ((int64_t)H * W));
-        const int rem = (int)(row % ((int64_t)H * W));
+        const int img = (int)(row / hw);
+        const int rem = (int)(row - img * hw);
+        const int v = rem / W, h = rem - (rem / W) * W;
+        rpos[t][0] = img;
+        rpos[t][1] = v;
+        rpos[t][2] = h;
         float f[NGEO];
-        geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, rem / W, rem % W, H, W, r_max, f);
+        geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, v, h, H, W, r_max, f);
 #pragma unroll
         for (int j = 0; j < NGEO; ++j) act[t * MLP_LDA + NIM2COL + j] = (__bf16)f[j];
+#pragma unroll
+        for (int c = LK[0]; c < L0_K; ++c) act[t * MLP_LDA + c] = (__bf16)0.f;
     }
-    for (int e = t; e < MLP_ROWS * L0_K; e += 256) {
-        const int r = e / L0_K, c = e % L0_K;
-        if (c >= NIM2COL && c < LK[0]) continue;
-        float v = 0.f;
-        if (c < NIM2COL) {
-            const int q = c / NFEAT, f = c % NFEAT;
-            const int64_t row = r0 + r;
-            const int img = (int)(row / ((int64_t)H * W));
-            const int rem = (int)(row % ((int64_t)H * W));
-            const int vv = rem / W + q / 3 - 1, hh = rem % W + q % 3 - 1;
-            if (vv >= 0 && vv < H && hh >= 0 && hh < W) v = g[(((int64_t)img * H + vv) * W + hh) * GB_STRIDE + f];
+    __syncthreads();
+    // the 3 x 3 neighbourhood features, one (row, neighbour) pair per step:
+    // its 8 G-buffer floats as two 16-byte loads (zero outside the image)
+    // and one 16-byte LDS store
+    for (int e = t; e < MLP_ROWS * 9; e += 256) {
+        const int r = e / 9, q = e - (e / 9) * 9;
+        const int vv = rpos[r][1] + q / 3 - 1, hh = rpos[r][2] + q % 3 - 1;
+        float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+        if (vv >= 0 && vv < H && hh >= 0 && hh < W) {
+            const float4 *src = reinterpret_cast<const float4 *>(
+                g + (((int64_t)rpos[r][0] * H + vv) * W + hh) * GB_STRIDE);
+            lo = src[0];
+            hi = src[1];
         }
-        act[r * MLP_LDA + c] = (__bf16)v;
+        const bf16x8 w8 = {(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
+                           (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
+        *reinterpret_cast<bf16x8 *>(act + r * MLP_LDA + q * NFEAT) = w8;      // 16-byte aligned
     }
     __syncthreads();
     {
@@ -964,7 +979,7 @@ static void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, int K, int 
 static void forward_layers(Surrogate *s, const float *gbuf, const float *geo, int n_img, int H, int W, hipStream_t st)
 {
     const int64_t rows = (int64_t)n_img * H * W;
-    hipLaunchKernelGGL(k_im2col, dim3((unsigned)((rows * LKP[0] + 255) / 256)), dim3(256), 0, st, gbuf, n_img, H, W,
+    hipLaunchKernelGGL(k_im2col, dim3((unsigned)((rows * 9 + 255) / 256)), dim3(256), 0, st, gbuf, n_img, H, W,
                        s->x[0]);
     hipLaunchKernelGGL(k_geo_cols, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, gbuf, geo, n_img, H, W,
                        s->r_max, s->x[0]);
