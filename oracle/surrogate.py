@@ -37,7 +37,7 @@ from __future__ import annotations
 import numpy as np
 
 N_FEAT = 8
-N_FREQ = 3                       # octaves of the geometry's sines and cosines
+N_FREQ = 5                       # octaves of the geometry's sines and cosines
 N_GEO = 9 + 12 * N_FREQ          # geometry features per beam
 N_IN = 9 * N_FEAT + N_GEO        # network inputs per beam
 GEO_STRIDE = 16                  # floats of one image's geometry block

@@ -37,7 +37,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 constexpr int NL = 5;                                       // layers
 constexpr int NFEAT = 8;                                    // G-buffer features per beam
 constexpr int NIM2COL = 9 * NFEAT;                          // 3 x 3 neighbourhood columns
-constexpr int NGEO_FREQ = 3;                                // octaves of the geometry's sines and cosines
+constexpr int NGEO_FREQ = 5;                                // octaves of the geometry's sines and cosines
 constexpr int NGEO = 9 + 12 * NGEO_FREQ;                    // geometry columns
 constexpr int GEO_STRIDE = 16;                              // floats of one image's geometry block
 constexpr int LK[NL] = {NIM2COL + NGEO, 64, 256, 256, 256}; // true fan-in

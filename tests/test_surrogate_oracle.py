@@ -9,9 +9,9 @@ from paper_2606_06130_amd.scenes import surrogate_init_params
 
 
 def test_parameter_count():
-    # (72 neighbourhood + 45 geometry inputs) x 64, then 64 x 256, 2 x 256 x 256 and 256 x 64, with biases
-    assert SO.N_IN == 117 and SO.N_GEO == 45
-    assert SO.param_count() == 117 * 64 + 64 + 64 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 64 + 64 == 172224
+    # (72 neighbourhood + 69 geometry inputs) x 64, then 64 x 256, 2 x 256 x 256 and 256 x 64, with biases
+    assert SO.N_IN == 141 and SO.N_GEO == 69
+    assert SO.param_count() == 141 * 64 + 64 + 64 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 64 + 64 == 173760
 
 
 def _rot_z(a):
