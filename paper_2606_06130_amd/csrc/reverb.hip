@@ -22,18 +22,25 @@ __global__ __launch_bounds__(256) void k_reverb(ReverbArgs a)
 {
     const int64_t b = blockIdx.x;
     const int n = blockIdx.y * 256 + threadIdx.x;
+    // the beam's factor s_v cos(el) dth_h dth_v dr is the same for the whole
+    // block: one lane evaluates it (the kernel is as much ALU- as HBM-bound)
+    __shared__ float beam_k;
+    if (threadIdx.x == 0) {
+        const int v = (int)(b / a.beams_h);
+        const float el = -0.5f * a.vfov + ((float)v + 0.5f) * a.dth_v;
+        beam_k = a.sv * cosf(el) * a.cell_solid * a.dr;
+    }
+    __syncthreads();
     if (n >= a.n_bins) return;
-    const int v = (int)(b / a.beams_h);
     const float r = a.r_min + ((float)n + 0.5f) * a.dr;
-    const float el = -0.5f * a.vfov + ((float)v + 0.5f) * a.dth_v;
-    const float P = a.sv * cosf(el) * a.cell_solid * a.dr / (r * r) * exp10f(-0.2f * a.alpha_db * r) + a.noise;
+    const float P = beam_k / (r * r) * exp10f(-0.2f * a.alpha_db * r) + a.noise;
     const uint64_t c = ((uint64_t)a.ping << 43) ^ ((uint64_t)b << 12) ^ (uint64_t)n;
     const uint64_t z = splitmix64_nth(a.seed, c + 1);
     const float u1 = (float)((z >> 40) + 1) * (1.f / 16777216.f);
     const float u2 = (float)((z >> 16) & 0xFFFFFFull) * (1.f / 16777216.f);
     float sn, cs;
     sincospif(2.f * u2, &sn, &cs);
-    const float amp = sqrtf(0.5f * P) * sqrtf(-2.f * logf(u1));
+    const float amp = sqrtf(-P * logf(u1));      // sqrt(P / 2) sqrt(-2 ln u1)
     typedef float f2v __attribute__((ext_vector_type(2)));
     f2v *cell = reinterpret_cast<f2v *>(a.volume) + b * a.n_bins + n;
     const f2v e = *cell;
