@@ -104,11 +104,13 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(mesh, cfg, pose, budget_s=12.0, single_budget_s=3.0, brute_budget_s=4.0):
+def cpu_baseline(mesh, cfg, poses, budget_s=12.0, single_budget_s=3.0, brute_budget_s=4.0):
     """The oracle as it stands (its exact uniform-grid candidate filter on,
-    as for any scene of this size) on bounded random samples of beams: with
-    up to 16 host threads (the main figure), on one thread, and the
-    brute-force loop over every triangle on a small sample."""
+    as for any scene of this size) on bounded samples of the job's pings:
+    beams in a random order, ping after ping along the job's sweep of poses
+    until the time budget is spent; with up to 16 host threads (the main
+    figure), on one thread, and the brute-force loop over every triangle on a
+    small sample."""
     import numpy as np
 
     import oracle
@@ -121,10 +123,12 @@ def cpu_baseline(mesh, cfg, pose, budget_s=12.0, single_budget_s=3.0, brute_budg
         done, t0 = 0, time.perf_counter()
         chunk = chunk0
         while True:
-            oracle.trace_beams(scene, cfg, pose, order[done:done + chunk], threads=n_threads, want_all=False)
-            done += chunk
+            ping, first = divmod(done, cfg.n_beams)
+            beams = order[first:first + chunk]
+            oracle.trace_beams(scene, cfg, poses[ping % len(poses)], beams, threads=n_threads, want_all=False)
+            done += len(beams)
             el = time.perf_counter() - t0
-            if el >= budget or done >= cfg.n_beams:
+            if el >= budget:
                 return done, el
             chunk = min(chunk * 2, 4096)
 
@@ -136,9 +140,9 @@ def cpu_baseline(mesh, cfg, pose, budget_s=12.0, single_budget_s=3.0, brute_budg
     doneb, elb = sample(brute, threads, brute_budget_s, 16)
     raysb = doneb * cfg.rays_per_beam
     return {"value": rays / cfg.n_rays / el, "unit": "pings/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} random beams x {cfg.rays_per_beam} rays ({rays} rays) of the harbor ping, FP64 oracle "
-                      f"(exact grid candidate filter) in {el:.1f} s on {threads} threads, scaled to one "
-                      f"{cfg.n_rays}-ray ping",
+            "sample": f"{done} beams x {cfg.rays_per_beam} rays ({rays} rays, {done / cfg.n_beams:.2f} pings of "
+                      f"the job's sweep, beams in a random order) of the harbor ping, FP64 oracle (exact grid "
+                      f"candidate filter) in {el:.1f} s on {threads} threads, scaled to one {cfg.n_rays}-ray ping",
             "mrays_per_s": rays / el / 1e6,
             "single_thread": {"pings_per_s": rays1 / cfg.n_rays / el1, "mrays_per_s": rays1 / el1 / 1e6,
                               "sample": f"{done1} beams ({rays1} rays) in {el1:.1f} s"},
@@ -640,9 +644,10 @@ def main():
     # the job: one ping per step along a short sweep in front of the wall
     # (lateral and depth offsets of a few decimetres, yaw within 3 degrees),
     # pings issued round-robin on `streams` streams, each with its own outputs
-    sweep = [sonar.pose_of(S.pose((0.0, 0.25 * math.sin(0.37 * i), -3.0 + 0.1 * math.cos(0.23 * i)),
-                                  yaw=math.radians(3.0 * math.sin(0.11 * i)), pitch_down=math.radians(35.0)))
-             for i in range(64)]
+    sweep_poses = [S.pose((0.0, 0.25 * math.sin(0.37 * i), -3.0 + 0.1 * math.cos(0.23 * i)),
+                          yaw=math.radians(3.0 * math.sin(0.11 * i)), pitch_down=math.radians(35.0))
+                   for i in range(64)]
+    sweep = [sonar.pose_of(p) for p in sweep_poses]
     ns = args.streams
     streams = [torch.cuda.Stream() for _ in range(ns)] if ns > 1 else [stream]
     outs = [sonar.alloc_outputs(cfg) for _ in range(ns)]
@@ -759,7 +764,7 @@ def main():
         res["multipath_ping"] = mp
         res["batch"] = bt
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(mesh, cfg, pose)
+        res["cpu_baseline"] = cpu_baseline(mesh, cfg, sweep_poses)
         par = {"harbor_ping": parity_sample(torch, sonar, np, scene, mesh, cfg, pose, 4096, 11)}
         if not args.no_extras:
             mmesh = S.scene_harbor_multipath()
