@@ -3,11 +3,13 @@
 // Sec. II-B lets scattering and reverberation effects be learned from data.
 // Here a small network maps each beam's single-bounce G-buffer (3 x 3 beam
 // neighbourhood of 8 features: the first-hit statistics and the beam axis's
-// vertical component) to the first 64 orthonormal DCT-II coefficients of the
-// dB level, above the intensity floor, of what further bounces add to its
-// range profile. Layers: im2col
-// convolution 72 (+56 zero) -> 64, then 64 -> 256 -> 256 -> 256 -> 64, ReLU
-// between layers.
+// vertical component) and the beam's geometry (mean first-hit point, beam
+// axis, sensor position; sines and cosines of the first two at five
+// octaves) to the first 64
+// orthonormal DCT-II coefficients of the dB level, above the intensity
+// floor, of what further bounces add to its range profile. Layers: 72
+// im2col convolution columns + 69 geometry columns (141, zero-padded to 192)
+// -> 64, then 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers.
 //
 // Dense products run on the CDNA4 matrix cores: v_mfma_f32_16x16x32_bf16
 // (BF16 operands, FP32 accumulation), 64 x 64 block tiles staged through LDS

@@ -180,6 +180,45 @@ def test_level_coefficients_and_profile_match_oracle():
     assert np.abs(pz.cpu().numpy() - 10 * np.log10(i1.astype(np.float64) + SO.I_FLOOR)).max() <= 2e-3
 
 
+@pytest.mark.parametrize("nb", [1024, 1000, 200])
+def test_profile_alone_matches_profile_with_errors_and_oracle(nb):
+    """The inference profile (no truth channels, no errors) against the
+    error path's profile and the oracle: ragged rows, beams without a hit
+    (r1 = 0), first hits at the last bins, a 16-row group whose first hits
+    all lie past the middle, and bin counts that split into quarters off the
+    16-column tiles."""
+    torch, sonar = _gpu()
+    rng = np.random.Generator(np.random.PCG64(17))
+    rows = 100
+    i1 = (rng.exponential(1e-8, (rows, nb)) * (rng.random((rows, nb)) < 0.2)).astype(np.float32)
+    im = (rng.exponential(1e-9, (rows, nb)) * (rng.random((rows, nb)) < 0.3)).astype(np.float32)
+    gb = np.zeros((rows, 8), np.float32)
+    gb[:, 0] = rng.uniform(0.0, 1.0, rows)
+    gb[:, 6] = (rng.random(rows) < 0.8) * rng.uniform(0.2, 1.0, rows)
+    gb[16:32, 0] = rng.uniform(0.8, 1.0, 16)      # a whole 16-row group with late first hits
+    gb[16:32, 6] = 1.0
+    gb[40:44, 0] = 1.0                             # first hit in the last bin
+    gb[40:44, 6] = 1.0
+    r1 = SO.first_hit_bin(gb, 0.3, 15.0, nb)
+    assert (r1 == 0).sum() > 5 and (r1 == nb - 1).sum() >= 4 and r1[16:32].min() > nb // 2
+    sur = sonar.Surrogate(128, nb, 0.3, 15.0, 32)
+    mean = rng.normal(0, 1, 64).astype(np.float32)
+    std = rng.uniform(0.5, 2, 64).astype(np.float32)
+    sur.set_norm(mean, std)
+    ti1, tim, tgb = torch.from_numpy(i1).cuda(), torch.from_numpy(im).cuda(), torch.from_numpy(gb).cuda()
+    pred = rng.normal(0, 1, (rows, 64)).astype(np.float32)
+    tp = torch.from_numpy(pred).cuda()
+    with_err, _ = sur.profile(tp, ti1, tgb, tim)
+    out = torch.full((rows, nb), float("nan"), device="cuda")
+    alone, err = sur.profile(tp, ti1, tgb, out=out)
+    assert err is None
+    alone, with_err = alone.cpu().numpy(), with_err.cpu().numpy()
+    assert np.isfinite(alone).all()                # every bin written
+    assert np.abs(alone - with_err).max() <= 1e-5
+    want = SO.full_profile(i1, pred.astype(np.float64) * std + mean, r1)
+    assert np.abs(alone - want).max() <= 2e-3
+
+
 def test_training_reduces_loss_and_resumes_bit_exactly():
     torch, sonar = _gpu()
     g, geo, t, theta = _inputs(4, n=2)
