@@ -36,8 +36,9 @@ BATCH_PMC_FILE = os.path.join(ROOT, "profiles", "batch_lawnmower_persistent_kern
 
 
 def sources_hash(names):
-    """Hash of the named kernel sources (a counter summary stays valid while
-    the sources its kernels are compiled from do)."""
+    """Hash of the named sources (a counter summary stays valid while the
+    sources its kernels are compiled from, and the hierarchy builder whose
+    output they traverse, do)."""
     h = hashlib.sha256()
     for name in sorted(names):
         with open(os.path.join(SRC_DIR, name), "rb") as f:

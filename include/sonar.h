@@ -216,7 +216,8 @@ typedef struct {
  * parallel through it): the triangle records with their reflectivity, phase
  * and material, and the ray-traversal hierarchy (linear BVH: Morton codes of
  * triangle centroids, radix sort, binary radix tree, bottom-up bounds, then
- * 4-wide nodes from every second binary level).
+ * 4-wide nodes collapsed greedily by surface area: a node opens its largest
+ * non-leaf child until it has four).
  * Synchronous on `stream`. Returns SONAR_E_INVALID for null pointers,
  * n_triangles < 1 or >= 2^28, indices out of range or non-finite vertices
  * (checked on the device, reported after the build's synchronisation), and

@@ -466,10 +466,15 @@ __global__ void k_refit_level(int level, int64_t n_int, const int32_t *__restric
     height[i] = max(height[a], height[b]) + 1;
 }
 
-// K6: 4-wide nodes. They are the binary nodes of even depth that hold more
-// than leaf_size triangles; each takes as children its binary grandchildren,
-// or a binary child itself when that child is a leaf (at most leaf_size
-// consecutive triangle records). Node layout, 8 float4: lo x, hi x, lo y,
+// K6: 4-wide nodes. A 4-wide node starts from a binary node's two children
+// and opens, while it has fewer than four, the child of largest surface
+// area that is not a leaf (a leaf: at most leaf_size consecutive triangle
+// records), putting that child's two children in its place (the greedy
+// collapse of a binary hierarchy by surface area, as wide-BVH builders do:
+// large boxes, the ones rays most often enter, are split first). The
+// children that are not leaves become 4-wide nodes in turn; the binary root
+// is the top node. Which binary nodes become 4-wide nodes is decided top
+// down, one binary depth per launch. Node layout, 8 float4: lo x, hi x, lo y,
 // hi y, lo z, hi z of children 0..3, then the four child links; an empty
 // child slot has an inverted box and the empty link.
 __device__ __forceinline__ int32_t tri_count(int32_t c, int64_t n, const int32_t *rlo, const int32_t *rhi)
@@ -477,18 +482,82 @@ __device__ __forceinline__ int32_t tri_count(int32_t c, int64_t n, const int32_t
     return c >= n - 1 ? 1 : rhi[c] - rlo[c] + 1;
 }
 
-__global__ __launch_bounds__(BT) void k_mark4(int64_t n, const int32_t *__restrict__ depth,
-                                             const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi,
-                                             int leaf_size, uint32_t *__restrict__ flag, uint32_t *__restrict__ id4,
+__device__ __forceinline__ float half_area(float4 l, float4 h)
+{
+    const float dx = h.x - l.x, dy = h.y - l.y, dz = h.z - l.z;
+    return dx * dy + dy * dz + dz * dx;
+}
+
+// The children of the 4-wide node made from binary node x (2 to 4 of them).
+__device__ int expand4(int32_t x, int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                       const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi,
+                       const float4 *__restrict__ blo, const float4 *__restrict__ bhi, int leaf_size, int32_t ch[4])
+{
+    int nc = 2;
+    ch[0] = left[x];
+    ch[1] = right[x];
+    while (nc < 4) {
+        int best = -1;
+        float ba = -1.f;
+        for (int q = 0; q < nc; ++q) {
+            const int32_t c = ch[q];
+            if (tri_count(c, n, rlo, rhi) <= leaf_size) continue;
+            const float a = half_area(blo[c], bhi[c]);
+            if (a > ba) {
+                ba = a;
+                best = q;
+            }
+        }
+        if (best < 0) break;
+        const int32_t c = ch[best];
+        ch[best] = left[c];
+        ch[nc++] = right[c];
+    }
+    return nc;
+}
+
+// The binary root becomes the top 4-wide node (level 0); no other node yet.
+__global__ __launch_bounds__(BT) void k_mark4_root(int64_t n_int, uint32_t *__restrict__ flag,
+                                                  int32_t *__restrict__ lev4)
+{
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n_int) return;
+    flag[i] = i == 0 ? 1u : 0u;
+    lev4[i] = 0;
+}
+
+// The 4-wide nodes of binary depth `level` (decided by their ancestors,
+// which are shallower) mark their non-leaf children as 4-wide nodes one
+// level further down.
+__global__ __launch_bounds__(BT) void k_expand4(int level, int64_t n, const int32_t *__restrict__ depth,
+                                               const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                                               const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi,
+                                               const float4 *__restrict__ blo, const float4 *__restrict__ bhi,
+                                               int leaf_size, uint32_t *__restrict__ flag, int32_t *__restrict__ lev4)
+{
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n - 1 || depth[i] != level || !flag[i]) return;
+    int32_t ch[4];
+    const int nc = expand4((int32_t)i, n, left, right, rlo, rhi, blo, bhi, leaf_size, ch);
+    for (int q = 0; q < nc; ++q) {
+        const int32_t c = ch[q];
+        if (tri_count(c, n, rlo, rhi) > leaf_size) {
+            flag[c] = 1u;
+            lev4[c] = lev4[i] + 1;
+        }
+    }
+}
+
+// Numbering input (the flags, scanned next) and the deepest 4-wide level.
+__global__ __launch_bounds__(BT) void k_mark4(int64_t n_int, const uint32_t *__restrict__ flag,
+                                             const int32_t *__restrict__ lev4, uint32_t *__restrict__ id4,
                                              int32_t *__restrict__ part)
 {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     int lv = -1;
-    if (i < n - 1) {
-        const bool f = (depth[i] & 1) == 0 && rhi[i] - rlo[i] + 1 > leaf_size;
-        flag[i] = f ? 1u : 0u;
+    if (i < n_int) {
         id4[i] = flag[i];
-        if (f) lv = depth[i] >> 1;
+        if (flag[i]) lv = lev4[i];
     }
     block_max_to(lv, part);
 }
@@ -502,17 +571,7 @@ __global__ void k_pack4(int64_t n, const int32_t *__restrict__ left, const int32
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= n - 1 || !flag[i]) return;
     int32_t ch[4];
-    int nc = 0;
-    const int32_t kids[2] = {left[i], right[i]};
-    for (int q = 0; q < 2; ++q) {
-        const int32_t c = kids[q];
-        if (tri_count(c, n, rlo, rhi) <= leaf_size) {
-            ch[nc++] = c;
-        } else {
-            ch[nc++] = left[c];
-            ch[nc++] = right[c];
-        }
-    }
+    const int nc = expand4((int32_t)i, n, left, right, rlo, rhi, blo, bhi, leaf_size, ch);
     float lo[3][4], hi[3][4];
     uint32_t link[4];
     for (int q = 0; q < 4; ++q) {
@@ -673,9 +732,10 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     BCHECK(hipMalloc(&bpart.p, sizeof(uint32_t) * 12 * (size_t)nblk(n > n_int ? n : n_int)));
     BCHECK(hipMalloc(&hgt.p, sizeof(int32_t) * n_all));
 
-    DevBuf flg, id4;
+    DevBuf flg, id4, lv4;
     BCHECK(hipMalloc(&flg.p, sizeof(uint32_t) * n_int));
     BCHECK(hipMalloc(&id4.p, sizeof(uint32_t) * n_int));
+    BCHECK(hipMalloc(&lv4.p, sizeof(int32_t) * n_int));
     const int n_scan4 = (int)((n_int + SCAN_TILE - 1) / SCAN_TILE);
     DevBuf tsum4;
     BCHECK(hipMalloc(&tsum4.p, sizeof(uint32_t) * n_scan4));
@@ -720,12 +780,12 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
     }
     k_leaf_boxes<<<nblk(n), BT, 0, s>>>(va, n, (const float4 *)tlo.p, (const float4 *)thi.p, (float4 *)blo.p,
                                         (float4 *)bhi.p, (int32_t *)hgt.p);
+    int max_level = 0;
     if (n > 1) {
         // levels of the tree: one short synchronisation for the deepest level
         k_depth<<<nblk(n_int), BT, 0, s>>>((const int32_t *)par.p, n_int, (int32_t *)ndp.p, (int32_t *)bpart.p,
                                            st_build);
         k_reduce_max<<<1, 1024, 0, s>>>((const int32_t *)bpart.p, (int)nblk(n_int), (int32_t *)dep.p);
-        int max_level = 0;
         BCHECK(hipMemcpyAsync(&max_level, dep.p, sizeof(int), hipMemcpyDeviceToHost, s));
         BCHECK(hipStreamSynchronize(s));
         if (max_level >= MAX_WALK) {
@@ -737,11 +797,18 @@ sonar_status build_hierarchy(const sonar_mesh &m, hipStream_t s, Scene *out, cha
                                                      (const int32_t *)rgt.p, (float4 *)blo.p, (float4 *)bhi.p,
                                                      (int32_t *)hgt.p);
     }
-    // 4-wide nodes: mark, number (exclusive scan), count (a short synchronisation), pack
+    // 4-wide nodes: mark top down (one launch per binary depth), number
+    // (exclusive scan), count (a short synchronisation), pack
     int n4 = 0, levels4 = 1;
     if (n > leaf_size_of(m)) {
-        k_mark4<<<nblk(n_int), BT, 0, s>>>(n, (const int32_t *)ndp.p, (const int32_t *)rlo.p,
-                                           (const int32_t *)rhi.p, m.leaf_size, (uint32_t *)flg.p,
+        k_mark4_root<<<nblk(n_int), BT, 0, s>>>(n_int, (uint32_t *)flg.p, (int32_t *)lv4.p);
+        for (int level = 0; level <= max_level; ++level)
+            k_expand4<<<nblk(n_int), BT, 0, s>>>(level, n, (const int32_t *)ndp.p, (const int32_t *)lft.p,
+                                                 (const int32_t *)rgt.p, (const int32_t *)rlo.p,
+                                                 (const int32_t *)rhi.p, (const float4 *)blo.p,
+                                                 (const float4 *)bhi.p, m.leaf_size, (uint32_t *)flg.p,
+                                                 (int32_t *)lv4.p);
+        k_mark4<<<nblk(n_int), BT, 0, s>>>(n_int, (const uint32_t *)flg.p, (const int32_t *)lv4.p,
                                            (uint32_t *)id4.p, (int32_t *)bpart.p);
         k_reduce_max<<<1, 1024, 0, s>>>((const int32_t *)bpart.p, (int)nblk(n_int), (int32_t *)dep.p);
         k_scan_tiles<<<n_scan4, SCAN_THREADS, 0, s>>>((const uint32_t *)id4.p, n_int, (uint32_t *)tsum4.p);
