@@ -205,8 +205,8 @@ def parity_sample(torch, sonar, np, scene, mesh, cfg, pose, n_beams, seed, stage
 
 
 # multiply-adds per beam of the surrogate network (fan-in x fan-out of each
-# layer: the 72 neighbourhood and 69 geometry inputs, then the dense layers)
-SURROGATE_MACS_PER_ROW = 141 * 64 + 64 * 256 + 2 * 256 * 256 + 256 * 64
+# layer: the 72 neighbourhood and 102 geometry inputs, then the dense layers)
+SURROGATE_MACS_PER_ROW = 174 * 64 + 64 * 256 + 2 * 256 * 256 + 256 * 64
 
 
 def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
@@ -390,7 +390,7 @@ def multipath_and_batch(torch, sonar, S, np, replays=5, sur_eval_poses=1000):
     assert scene.status() == 0
     del s_bufs, s_streams
     fwd_tflops = 2.0 * SURROGATE_MACS_PER_ROW * rows / (fwd_ms * 1e-3) / 1e12
-    surrogate = {"workload": "single-bounce ping with G-buffer + fused network inference (173,760 parameters, "
+    surrogate = {"workload": "single-bounce ping with G-buffer + fused network inference (175,872 parameters, "
                              "BF16 MFMA) + predicted 1,024-bin multi-bounce profile, same scene and layout",
                  "ping_ms": sp_ms, "pings_per_s": 1e3 / sp_ms, "rate_vs_full_multipath": mp_ms / sp_ms,
                  "job": {"streams": ns, "pings": n_job, "ms_per_ping": sjob_ms, "pings_per_s": 1e3 / sjob_ms,

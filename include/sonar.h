@@ -625,14 +625,17 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
  * sonar_surrogate_geometry fills one) and its G-buffer entry: the beam axis u
  * in the world (cell-centred beams: azimuth -hfov/2 + (h + 1/2) hfov / W,
  * elevation -vfov/2 + (v + 1/2) vfov / H), the mean first hit on it P = S +
- * r_max g0 u (the origin for a beam without hits, g6 = 0), and 69 columns:
- * P / 10, u, S / 10 (lengths in metres), then sin(pi/2 2^k x) for the six
- * values x of P / 10 and u (x-major, k = 0 .. 4), then the cosines. Later
- * bounces go where the scene sends the continuation of the first hit: for
- * one scene the network learns that from where the hit is.
- * Layers: the 72 neighbourhood columns (an im2col product) and the 69
+ * r_max g0 u (the origin for a beam without hits, g6 = 0), the axis mirrored
+ * at the mean first-hit normal n = (g3, g4, g5), m = u - 2 (u . n) n / |n|^2
+ * (zero without a hit or a normal), and 102 columns: P / 10, u, S / 10, m
+ * (lengths in metres), then sin(pi/2 2^k x) for the nine values x of P / 10,
+ * u and m (x-major, k = 0 .. 4), then the cosines. Later bounces go where
+ * the scene sends the continuation of the first hit: for one scene the
+ * network learns that from where the hit is and where it sends the
+ * continuation.
+ * Layers: the 72 neighbourhood columns (an im2col product) and the 102
  * geometry columns -> 64, then 64 -> 256 -> 256 -> 256 -> 64, ReLU between
- * layers; 173,760 parameters.
+ * layers; 175,872 parameters.
  * Products use BF16 operands on the matrix cores with FP32 accumulation;
  * training is a weighted MSE on the coefficients, sum_j w_j (y_j - t_j)^2 over
  * rows * 64 (weights 1 by default), with Adam (beta 0.9 / 0.999, eps 1e-8) on
@@ -640,7 +643,7 @@ sonar_status sonar_batch_autotune(const sonar_scene *scene, const sonar_batch_pl
  *
  * Parameter vector layout (float, sonar_surrogate_param_count() entries): for
  * each layer W [fan_in][fan_out] row-major then b [fan_out], with (fan_in,
- * fan_out) = (141, 64), (64, 256), (256, 256), (256, 256), (256, 64); input
+ * fan_out) = (174, 64), (64, 256), (256, 256), (256, 256), (256, 64); input
  * column order: the neighbourhood (dv, dh, feature), then the geometry.
  * G-buffer: float [n_img][H][W][8] as sonar_ping writes it (16-byte aligned); geometry: float
  * [n_img][16] on the device; rows = n_img * H * W (a multiple of 64 for the

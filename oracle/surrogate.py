@@ -17,10 +17,12 @@ Network input per beam: a 3 x 3 beam-neighbourhood convolution of the 8
 G-buffer features (the first-hit statistics and the beam axis's vertical
 component; written as an im2col product with 72 inputs, zero padding at the
 edges), followed by the beam's geometry (geometry_features): where its mean
-first hit lies in the world, the beam axis in the world and the sensor
-position, plus sines and cosines of the first two at N_FREQ octaves. Later
-bounces go where the scene sends the continuation of that first hit, so the
-network of one scene needs to know where in the scene the hit is.
+first hit lies in the world, the beam axis in the world, the sensor
+position and the axis mirrored at the mean first-hit normal (the direction
+a specular continuation takes), plus sines and cosines of all but the
+sensor position at N_FREQ octaves. Later bounces go where the scene sends
+the continuation of that first hit, so the network of one scene needs to
+know where in the scene the hit is and where it sends the continuation.
 
 Network: input -> 64 -> 256 -> 256 -> 256 -> 64 dense layers with ReLU
 between them. Loss: mean squared error over the 64 standardised
@@ -38,7 +40,7 @@ import numpy as np
 
 N_FEAT = 8
 N_FREQ = 5                       # octaves of the geometry's sines and cosines
-N_GEO = 9 + 12 * N_FREQ          # geometry features per beam
+N_GEO = 12 + 18 * N_FREQ         # geometry features per beam
 N_IN = 9 * N_FEAT + N_GEO        # network inputs per beam
 GEO_STRIDE = 16                  # floats of one image's geometry block
 LAYERS = ((N_IN, 64), (64, 256), (256, 256), (256, 256), (256, 64))
@@ -100,9 +102,13 @@ def geometry_features(gbuf, geo, r_max):
     the unit vector (cos el cos az, cos el sin az, sin el) in the sensor
     frame, u = R times it in the world. Its mean first hit is taken on that
     axis at the G-buffer's mean range: P = S + r_max g0 u when the beam has a
-    hit (g6 > 0), else the origin. Features, in metres / 10 and unit vectors:
-    P / 10 (3), u (3), S / 10 (3), then sin(pi/2 2^k x) for x in (P / 10, u)
-    and k = 0 .. N_FREQ - 1 (x-major), then the cosines in the same order."""
+    hit (g6 > 0), else the origin. The mirror direction reflects u at the
+    mean first-hit normal n = (g3, g4, g5) (the law of specular reflection,
+    for a normal of any length): m = u - 2 (u . n) n / (n . n), zero without
+    a hit or with a zero normal. Features, in metres / 10 and unit vectors:
+    P / 10 (3), u (3), S / 10 (3), m (3), then sin(pi/2 2^k x) for x in
+    (P / 10, u, m) and k = 0 .. N_FREQ - 1 (x-major), then the cosines in the
+    same order."""
     g = np.asarray(gbuf, np.float64)
     n, H, W, _ = g.shape
     out = np.zeros((n, H, W, N_GEO))
@@ -116,10 +122,14 @@ def geometry_features(gbuf, geo, r_max):
                 az = -0.5 * hfov + (h + 0.5) * hfov / W
                 us = np.array([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)])
                 u = R @ us
-                P = S + r_max * g[i, v, h, 0] * u if g[i, v, h, 6] > 0 else np.zeros(3)
-                x = np.concatenate([P / 10.0, u])
+                hit = g[i, v, h, 6] > 0
+                P = S + r_max * g[i, v, h, 0] * u if hit else np.zeros(3)
+                nrm = g[i, v, h, 3:6]
+                nn = float(nrm @ nrm)
+                m = u - 2.0 * float(u @ nrm) / nn * nrm if (hit and nn > 1e-12) else np.zeros(3)
+                x = np.concatenate([P / 10.0, u, m])
                 arg = np.array([[np.pi / 2.0 * 2.0 ** k * xx for k in range(N_FREQ)] for xx in x])
-                out[i, v, h] = np.concatenate([P / 10.0, u, S / 10.0, np.sin(arg).reshape(-1),
+                out[i, v, h] = np.concatenate([P / 10.0, u, S / 10.0, m, np.sin(arg).reshape(-1),
                                                np.cos(arg).reshape(-1)])
     return out.reshape(n * H * W, N_GEO)
 

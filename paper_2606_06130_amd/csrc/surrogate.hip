@@ -4,12 +4,13 @@
 // Here a small network maps each beam's single-bounce G-buffer (3 x 3 beam
 // neighbourhood of 8 features: the first-hit statistics and the beam axis's
 // vertical component) and the beam's geometry (mean first-hit point, beam
-// axis, sensor position; sines and cosines of the first two at five
-// octaves) to the first 64
+// axis, sensor position, the axis mirrored at the mean first-hit normal;
+// sines and cosines of all but the sensor position at five octaves) to the
+// first 64
 // orthonormal DCT-II coefficients of the dB level, above the intensity
 // floor, of what further bounces add to its range profile. Layers: 72
-// im2col convolution columns + 69 geometry columns (141, zero-padded to 192)
-// -> 64, then 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers.
+// im2col convolution columns + 102 geometry columns (174, zero-padded to
+// 192) -> 64, then 64 -> 256 -> 256 -> 256 -> 64, ReLU between layers.
 //
 // Dense products run on the CDNA4 matrix cores: v_mfma_f32_16x16x32_bf16
 // (BF16 operands, FP32 accumulation), 64 x 64 block tiles staged through LDS
@@ -40,7 +41,7 @@ constexpr int NL = 5;                                       // layers
 constexpr int NFEAT = 8;                                    // G-buffer features per beam
 constexpr int NIM2COL = 9 * NFEAT;                          // 3 x 3 neighbourhood columns
 constexpr int NGEO_FREQ = 5;                                // octaves of the geometry's sines and cosines
-constexpr int NGEO = 9 + 12 * NGEO_FREQ;                    // geometry columns
+constexpr int NGEO = 12 + 18 * NGEO_FREQ;                   // geometry columns
 constexpr int GEO_STRIDE = 16;                              // floats of one image's geometry block
 constexpr int LK[NL] = {NIM2COL + NGEO, 64, 256, 256, 256}; // true fan-in
 // padded fan-in: a multiple of 64, since the weight gradient X^T dZ has it as
@@ -148,11 +149,16 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int 
 // image's geometry block (sensor position, sensor-to-world rotation
 // row-major, horizontal and vertical fields of view) and the beam's G-buffer
 // entry: the beam axis u (world), the mean first hit P = S + r_max g0 u on it
-// (the origin without a hit), then P / 10 (3), u (3), S / 10 (3), and
-// sin(pi/2 2^k x), then cos(pi/2 2^k x), for x in (P / 10, u), x-major, k =
-// 0 .. NGEO_FREQ - 1. Lengths in metres.
+// (the origin without a hit), the axis mirrored at the mean first-hit normal
+// n (g3..g5), m = u - 2 (u . n) n / |n|^2 (zero without a hit or normal):
+// where a specular continuation of the first hit heads. Columns: P / 10 (3),
+// u (3), S / 10 (3), m (3), then sin(pi/2 2^k x), then cos(pi/2 2^k x), for
+// x in (P / 10, u, m), x-major, k = 0 .. NGEO_FREQ - 1. Lengths in metres.
+// Each column j goes out through put(j, value) as it is computed (no array
+// of all columns held in registers).
+template <class Put>
 __device__ __forceinline__ void geo_columns(const float *__restrict__ geo, const float *__restrict__ gb, int v, int h,
-                                            int H, int W, float r_max, float (&out)[NGEO])
+                                            int H, int W, float r_max, Put put)
 {
     const float hfov = geo[12], vfov = geo[13];
     const float az = -0.5f * hfov + ((float)h + 0.5f) * hfov / (float)W;
@@ -163,23 +169,32 @@ __device__ __forceinline__ void geo_columns(const float *__restrict__ geo, const
     const float us0 = ce * ca, us1 = ce * sa, us2 = se;
     const bool hit = gb[6] > 0.f;
     const float r = r_max * gb[0];
-    float x[6];
+    float x[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const float u = geo[3 + 3 * i] * us0 + geo[4 + 3 * i] * us1 + geo[5 + 3 * i] * us2;
         x[3 + i] = u;
         x[i] = hit ? (geo[i] + r * u) * 0.1f : 0.f;
-        out[6 + i] = geo[i] * 0.1f;
+        put(6 + i, geo[i] * 0.1f);
     }
+    const float nx = gb[3], ny = gb[4], nz = gb[5];
+    const float nn = nx * nx + ny * ny + nz * nz;
+    const bool mir = hit && nn > 1e-12f;
+    const float f = mir ? 2.f * (x[3] * nx + x[4] * ny + x[5] * nz) / nn : 0.f;
+    x[6] = mir ? x[3] - f * nx : 0.f;
+    x[7] = mir ? x[4] - f * ny : 0.f;
+    x[8] = mir ? x[5] - f * nz : 0.f;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        out[q] = x[q];
+    for (int i = 0; i < 3; ++i) put(9 + i, x[6 + i]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        if (q < 6) put(q, x[q]);
 #pragma unroll
         for (int k = 0; k < NGEO_FREQ; ++k) {
             float sn, cs;
             sincosf(1.57079632679489662f * (float)(1 << k) * x[q], &sn, &cs);
-            out[9 + q * NGEO_FREQ + k] = sn;
-            out[9 + 6 * NGEO_FREQ + q * NGEO_FREQ + k] = cs;
+            put(12 + q * NGEO_FREQ + k, sn);
+            put(12 + 9 * NGEO_FREQ + q * NGEO_FREQ + k, cs);
         }
     }
 }
@@ -194,10 +209,9 @@ __global__ void k_geo_cols(const float *__restrict__ g, const float *__restrict_
     if (row >= rows) return;
     const int img = (int)(row / ((int64_t)H * W));
     const int rem = (int)(row % ((int64_t)H * W));
-    float f[NGEO];
-    geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, rem / W, rem % W, H, W, r_max, f);
-#pragma unroll
-    for (int j = 0; j < NGEO; ++j) x[row * LKP[0] + NIM2COL + j] = (__bf16)f[j];
+    __bf16 *xr = x + row * LKP[0] + NIM2COL;
+    geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, rem / W, rem % W, H, W, r_max,
+                [&](int j, float v) { xr[j] = (__bf16)v; });
 #pragma unroll
     for (int c = LK[0]; c < LKP[0]; ++c) x[row * LKP[0] + c] = (__bf16)0.f;
 }
@@ -224,7 +238,7 @@ __global__ void k_im2col(const float *__restrict__ g, int n_img, int H, int W, _
     }
     const bf16x8 w8 = {(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
                        (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
-    *reinterpret_cast<bf16x8 *>(x + row * LKP[0] + q * NFEAT) = w8;      // rows of 256 bytes: aligned
+    *reinterpret_cast<bf16x8 *>(x + row * LKP[0] + q * NFEAT) = w8;      // rows of LKP[0] (a multiple of 64) bf16: aligned
 }
 
 // Weighted MSE on the 64 coefficients: dZ = 2 w_j (y - t) / (rows * 64) in
@@ -757,10 +771,9 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ g
         rpos[t][0] = img;
         rpos[t][1] = v;
         rpos[t][2] = h;
-        float f[NGEO];
-        geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, v, h, H, W, r_max, f);
-#pragma unroll
-        for (int j = 0; j < NGEO; ++j) act[t * MLP_LDA + NIM2COL + j] = (__bf16)f[j];
+        __bf16 *ar = act + t * MLP_LDA + NIM2COL;
+        geo_columns(geo + (int64_t)img * GEO_STRIDE, g + row * GB_STRIDE, v, h, H, W, r_max,
+                    [&](int j, float val) { ar[j] = (__bf16)val; });
 #pragma unroll
         for (int c = LK[0]; c < L0_K; ++c) act[t * MLP_LDA + c] = (__bf16)0.f;
     }

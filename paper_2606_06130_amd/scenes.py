@@ -424,7 +424,7 @@ def random_poses(seed: int, n: int, pile_seed: int = 3):
 # initial weights of the multipath surrogate (random draws shared by the
 # library and its checks)
 
-SURROGATE_LAYERS = ((141, 64), (64, 256), (256, 256), (256, 256), (256, 64))
+SURROGATE_LAYERS = ((174, 64), (64, 256), (256, 256), (256, 256), (256, 64))
 
 
 def surrogate_init_params(seed: int) -> np.ndarray:

@@ -248,7 +248,7 @@ def main(argv=None):
     losses = train(sur, src, train_poses, args.epochs, args.batch, args.lr, log, start_step=start)
     t_train = time.time() - t0
     save_checkpoint(os.path.join(args.out, "checkpoint.npz"), sur, mean, std)
-    meta = {"target": "level", "inputs": "gbuffer+geometry", "smooth": 32, "train_pings": args.train_pings,
+    meta = {"target": "level", "inputs": "gbuffer+geometry+mirror", "smooth": 32, "train_pings": args.train_pings,
             "train_pose_seed": 5,
             "epochs": args.epochs, "batch_pings": args.batch, "lr": args.lr, "stats_pings": args.stats_pings}
     if args.weights_out:

@@ -283,7 +283,7 @@ def test_committed_weights_beat_single_bounce():
     src = SU.PingSource(scene, cfg)
     sur = sonar.Surrogate(src.rows, cfg.n_range, cfg.r_min, cfg.r_max)
     mean, std, step, meta = SU.load_checkpoint(SU.WEIGHTS, sur)
-    assert step > 0 and meta.get("target") == "level" and meta.get("inputs") == "gbuffer+geometry"
+    assert step > 0 and meta.get("target") == "level" and meta.get("inputs") == "gbuffer+geometry+mirror"
     res = SU.evaluate(sur, src, S.random_poses(6, 16))
     _log("committed weights, 16 held-out poses", res)
     assert res["beams"] > 100000

@@ -9,9 +9,9 @@ from paper_2606_06130_amd.scenes import surrogate_init_params
 
 
 def test_parameter_count():
-    # (72 neighbourhood + 69 geometry inputs) x 64, then 64 x 256, 2 x 256 x 256 and 256 x 64, with biases
-    assert SO.N_IN == 141 and SO.N_GEO == 69
-    assert SO.param_count() == 141 * 64 + 64 + 64 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 64 + 64 == 173760
+    # (72 neighbourhood + 102 geometry inputs) x 64, then 64 x 256, 2 x 256 x 256 and 256 x 64, with biases
+    assert SO.N_IN == 174 and SO.N_GEO == 102
+    assert SO.param_count() == 174 * 64 + 64 + 64 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 64 + 64 == 175872
 
 
 def _rot_z(a):
@@ -25,9 +25,15 @@ def _rot_y(a):
 
 
 def _geo_cols(f):
-    """Split geometry columns: P/10, u, S/10, sines [6, N_FREQ], cosines [6, N_FREQ]."""
+    """Split geometry columns: P/10, u, S/10, sines [9, N_FREQ], cosines [9, N_FREQ] (the mirror
+    direction m is _mirror(f))."""
     F = SO.N_FREQ
-    return f[:, 0:3], f[:, 3:6], f[:, 6:9], f[:, 9:9 + 6 * F].reshape(-1, 6, F), f[:, 9 + 6 * F:].reshape(-1, 6, F)
+    return (f[:, 0:3], f[:, 3:6], f[:, 6:9], f[:, 12:12 + 9 * F].reshape(-1, 9, F),
+            f[:, 12 + 9 * F:].reshape(-1, 9, F))
+
+
+def _mirror(f):
+    return f[:, 9:12]
 
 
 def test_geometry_axis_hit_point_and_rotation():
@@ -84,7 +90,7 @@ def test_geometry_fourier_columns():
            for _ in range(2)]
     f = SO.geometry_features(g, geo, 15.0)
     P10, u, _, sn, cs = _geo_cols(f)
-    x = np.concatenate([P10, u], axis=1)
+    x = np.concatenate([P10, u, _mirror(f)], axis=1)
     np.testing.assert_allclose(sn ** 2 + cs ** 2, 1.0, atol=1e-14)
     np.testing.assert_allclose(sn[:, :, 0], np.sin(np.pi / 2 * x), atol=1e-14)
     for k in range(1, SO.N_FREQ):
@@ -94,6 +100,43 @@ def test_geometry_fourier_columns():
     assert nohit.any()
     np.testing.assert_array_equal(sn[nohit, :3], 0.0)
     np.testing.assert_array_equal(cs[nohit, :3], 1.0)
+    np.testing.assert_array_equal(sn[nohit, 6:], 0.0)
+    np.testing.assert_array_equal(cs[nohit, 6:], 1.0)
+
+
+def test_geometry_mirror_direction():
+    """The mirror direction is the law of reflection at the mean first-hit
+    normal: a horizontal seabed (normal +z) flips the vertical component, a
+    wall facing -x flips the x component; the normal's length and sign do not
+    matter; the mirror is a unit vector at the same angle to the normal as
+    the axis, mirroring it back gives the axis, and it is zero for a beam
+    without a hit or without a normal."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    S = np.array([0.5, -1.0, -3.0])
+    geo = [SO.geometry_block(S, _rot_z(0.3) @ _rot_y(0.6), 1.0, 0.5)]
+    g = np.zeros((1, 2, 3, 8))
+    g[..., 0] = 0.3
+    g[..., 6] = 1.0
+    g[0, 0, 0, 3:6] = [0.0, 0.0, 1.0]                  # seabed
+    g[0, 0, 1, 3:6] = [-0.4, 0.0, 0.0]                 # wall facing -x, normal of length 0.4
+    g[0, 0, 2, 3:6] = [0.0, 0.0, -2.0]                 # seabed normal, opposite sign and length 2
+    g[0, 1, 0, 3:6] = rng.normal(size=3)               # any surface
+    g[0, 1, 1, 6] = 0.0                                # no hit
+    g[0, 1, 1, 3:6] = [0.0, 0.0, 1.0]
+    g[0, 1, 2, 3:6] = 0.0                              # a hit without a normal
+    f = SO.geometry_features(g, geo, 15.0)
+    _, u, _, _, _ = _geo_cols(f)
+    m = _mirror(f)
+    np.testing.assert_allclose(m[0], u[0] * [1, 1, -1], atol=1e-15)
+    np.testing.assert_allclose(m[1], u[1] * [-1, 1, 1], atol=1e-15)
+    np.testing.assert_allclose(m[2], u[2] * [1, 1, -1], atol=1e-15)
+    n = g[0, 1, 0, 3:6] / np.linalg.norm(g[0, 1, 0, 3:6])
+    assert abs(np.linalg.norm(m[3]) - 1.0) < 1e-14
+    assert abs(m[3] @ n + u[3] @ n) < 1e-14            # same angle, other side
+    np.testing.assert_allclose(m[3] - u[3], -2.0 * (u[3] @ n) * n, atol=1e-14)   # the change lies along the normal
+    np.testing.assert_allclose(m[3] - 2.0 * (m[3] @ n) * n, u[3], atol=1e-14)    # mirroring back gives the axis
+    np.testing.assert_array_equal(m[4], 0.0)
+    np.testing.assert_array_equal(m[5], 0.0)
 
 
 def test_inputs_concatenate_im2col_and_geometry():
