@@ -86,9 +86,10 @@ def geometry(src, poses):
     return src.torch.from_numpy(sonar.surrogate_geometry(src.cfg, poses)).cuda()
 
 
-def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
+def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0, stop_step=None):
     """Adam with cosine learning-rate decay over mini-batches of `batch_pings`
-    pings. Returns the per-step losses."""
+    pings, from step `start_step` up to (not including) `stop_step` (default:
+    the end of the schedule). Returns the per-step losses."""
     torch = src.torch
     B = batch_pings
     geo_all = geometry(src, poses)
@@ -107,6 +108,8 @@ def train(sur, src, poses, epochs, batch_pings, lr0, log=print, start_step=0):
             if step < start_step:
                 step += 1
                 continue
+            if stop_step is not None and step >= stop_step:
+                break
             pick = order[s * B:(s + 1) * B]
             for b in range(B):
                 _, _, im = src.run(poses[pick[b]], gbuf_slot=gb[b])
@@ -217,6 +220,8 @@ def main(argv=None):
     ap.add_argument("--stats-pings", type=int, default=64)
     ap.add_argument("--out", default="surrogate_run")
     ap.add_argument("--resume", default=None)
+    ap.add_argument("--stop-step", type=int, default=None,
+                    help="stop before this step of the schedule: write the checkpoint, skip the evaluation")
     ap.add_argument("--weights-out", default=None, help="also write the weights-only checkpoint here")
     args = ap.parse_args(argv)
     import torch
@@ -245,9 +250,13 @@ def main(argv=None):
         sur.set_state(S.surrogate_init_params(11))
     sur.set_loss_weights(loss_weights(std))
     log(f"setup {time.time() - t0:.1f}s; rows/ping {src.rows}; params {sur.n_params}")
-    losses = train(sur, src, train_poses, args.epochs, args.batch, args.lr, log, start_step=start)
+    losses = train(sur, src, train_poses, args.epochs, args.batch, args.lr, log, start_step=start,
+                   stop_step=args.stop_step)
     t_train = time.time() - t0
     save_checkpoint(os.path.join(args.out, "checkpoint.npz"), sur, mean, std)
+    if args.stop_step is not None and args.stop_step < (args.train_pings // args.batch) * args.epochs:
+        log(f"stopped before step {args.stop_step}; resume from {os.path.join(args.out, 'checkpoint.npz')}")
+        return
     meta = {"target": "level", "inputs": "gbuffer+geometry+mirror", "smooth": 32, "train_pings": args.train_pings,
             "train_pose_seed": 5,
             "epochs": args.epochs, "batch_pings": args.batch, "lr": args.lr, "stats_pings": args.stats_pings}
