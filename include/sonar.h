@@ -52,7 +52,7 @@ typedef enum {
     SONAR_E_NOMEM = -2,         /* device allocation failed (build only) */
     SONAR_E_DEVICE = -3,        /* a HIP call failed */
     SONAR_E_STACK = -4,         /* traversal stack too shallow for the scene's hierarchy */
-    SONAR_E_UNSUPPORTED = -5    /* a valid request outside what this build implements */
+    SONAR_E_UNSUPPORTED = -5    /* a valid request outside what the library implements */
 } sonar_status;
 
 /* Opaque, library-owned, immutable after build. Usable from several streams
